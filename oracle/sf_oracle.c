@@ -1,0 +1,375 @@
+/*
+ * FP64 CPU oracle of the discrete social-field pedestrian step.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, plain reference that the
+ * GPU library is checked against.  Only the tests, the smoke check and the
+ * benchmark's CPU-baseline leg load it; the product library never does, and
+ * it shares no code, header, table or helper with the HIP path.
+ *
+ * What it computes (Yu, Zhu, Wu, Zhang, "Improved OpenCL-based Implementation
+ * of Social Field Pedestrian Model"):
+ *   - the discrete model of section 2: a grid of space units (su), one centre
+ *     su per pedestrian, at most one su of movement per tick (v_max = 1), so a
+ *     pedestrian's candidates are its own su and its 8 Moore neighbours;
+ *   - the fields of section 2: a static attractive field of the openings
+ *     (destination field: 8-neighbour unit-cost BFS distance to the exit set),
+ *     a static repulsive field of the obstacles, and the recurrent repulsive
+ *     field of every pedestrian over its square window, superposed linearly
+ *     (the write-back of k-5, section 3.1 and Algorithms 2/3: only the total
+ *     of the contributions matters);
+ *   - the tick of Algorithm 1: k-2 each pedestrian picks its next su, k-3 an
+ *     election among the at most 8 pedestrians registered for an unoccupied
+ *     su picks one occupant (s-2), k-4 winners move, losers stay;
+ *   - openings remove the pedestrians that enter them (Fig. 6 caption, task 11).
+ *
+ * Readings taken where the paper is silent (listed in the design notes):
+ *   field law      phi(d) = k * |d|_2^alpha for 0 < |d|_inf <= R, phi(0) = 0
+ *                  (the paper quotes k = 1, alpha = -0.5 for the 7x7 recurrent
+ *                  repulsive field of Fig. 1 and states a 1x1 geometry has no
+ *                  fan-out, i.e. no strength at the field's own centre);
+ *   regulation     identity; no local-density term; P = w_D*D + O + Phi;
+ *   candidates     own su, plus each Moore neighbour that is inside the grid,
+ *                  not an obstacle and unoccupied at the start of the tick;
+ *   choice         minimum of u(y) = P(y) - phi(y - x) (own field removed),
+ *                  lowest direction index on exact ties; the decision is
+ *                  taken on FP32 values fl32(fl32(P) - fl32(phi)), the
+ *                  paper's field precision;
+ *   near tie       the two smallest FP64 u differ by <= 1e-5*max(|u1|,|u2|,1);
+ *   election       minimum key = philox(id, t).x * 2^32 + id, where philox is
+ *                  Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) with
+ *                  counter (id, t_lo, t_hi, 0) and key (seed_lo, seed_hi).
+ *
+ * Direction list: e0 = (0,0) stay, e1 = (1,0), e2 = (1,1), e3 = (0,1),
+ * e4 = (-1,1), e5 = (-1,0), e6 = (-1,-1), e7 = (0,-1), e8 = (1,-1); x is the
+ * column (east +), y the row (south +); linear index c = y*W + x.
+ *
+ * Parity pins: see the oracle tests (library routines, closed forms,
+ * invariants and hand-worked scenes).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+static const int DIR_X[9] = {0, 1, 1, 0, -1, -1, -1, 0, 1};
+static const int DIR_Y[9] = {0, 0, 1, 1, 1, 0, -1, -1, -1};
+
+/* ---- field law ---------------------------------------------------------- */
+
+/* phi at offset (dx, dy) for a field of half-width R (0 outside the window). */
+double orc_phi(int dx, int dy, int R, double k, double alpha)
+{
+    int adx = dx < 0 ? -dx : dx, ady = dy < 0 ? -dy : dy;
+    if (adx > R || ady > R) return 0.0;
+    if (dx == 0 && dy == 0) return 0.0;
+    double dist = sqrt((double)dx * dx + (double)dy * dy);
+    return k * pow(dist, alpha);
+}
+
+/* Full (2R+1)^2 stamp, row-major [dy+R][dx+R]. */
+void orc_phi_table(int R, double k, double alpha, double *out)
+{
+    int n = 2 * R + 1;
+    for (int dy = -R; dy <= R; ++dy)
+        for (int dx = -R; dx <= R; ++dx)
+            out[(dy + R) * n + (dx + R)] = orc_phi(dx, dy, R, k, alpha);
+}
+
+/* ---- destination field: BFS distance to the exits ----------------------- */
+
+/* D[c] = number of 8-neighbour unit steps from c to the nearest exit su over
+ * non-obstacle su; -1 on obstacles and on su that cannot reach an exit.
+ * Returns the number of non-obstacle su that cannot reach an exit. */
+int64_t orc_bfs_distance(int W, int H, const uint8_t *obst, const uint8_t *exitm,
+                         int32_t *D)
+{
+    int64_t n = (int64_t)W * H;
+    int32_t *queue = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int64_t head = 0, tail = 0;
+    for (int64_t c = 0; c < n; ++c) {
+        D[c] = -1;
+        if (exitm[c] && !obst[c]) {
+            D[c] = 0;
+            queue[tail++] = (int32_t)c;
+        }
+    }
+    while (head < tail) {
+        int32_t c = queue[head++];
+        int x = c % W, y = c / W;
+        for (int d = 1; d <= 8; ++d) {
+            int nx = x + DIR_X[d], ny = y + DIR_Y[d];
+            if (nx < 0 || ny < 0 || nx >= W || ny >= H) continue;
+            int64_t nc = (int64_t)ny * W + nx;
+            if (obst[nc] || D[nc] >= 0) continue;
+            D[nc] = D[c] + 1;
+            queue[tail++] = (int32_t)nc;
+        }
+    }
+    free(queue);
+    int64_t unreachable = 0;
+    for (int64_t c = 0; c < n; ++c)
+        if (!obst[c] && D[c] < 0) ++unreachable;
+    return unreachable;
+}
+
+/* ---- superposed source field -------------------------------------------- */
+
+/* out[c] = sum over source su s (src[s] != 0) of phi(c - s), for every su c of
+ * the grid.  Each source spreads its window; contributions outside the grid
+ * are dropped.  Plain scatter in source raster order, FP64. */
+void orc_source_field(int W, int H, const uint8_t *src, int R, double k, double alpha,
+                      double *out)
+{
+    int64_t n = (int64_t)W * H;
+    int m = 2 * R + 1;
+    double *tab = (double *)malloc(sizeof(double) * (size_t)m * m);
+    orc_phi_table(R, k, alpha, tab);
+    for (int64_t c = 0; c < n; ++c) out[c] = 0.0;
+    for (int64_t s = 0; s < n; ++s) {
+        if (!src[s]) continue;
+        int sx = (int)(s % W), sy = (int)(s / W);
+        for (int dy = -R; dy <= R; ++dy) {
+            int y = sy + dy;
+            if (y < 0 || y >= H) continue;
+            for (int dx = -R; dx <= R; ++dx) {
+                int x = sx + dx;
+                if (x < 0 || x >= W) continue;
+                out[(int64_t)y * W + x] += tab[(dy + R) * m + (dx + R)];
+            }
+        }
+    }
+    free(tab);
+}
+
+/* Occupancy mask from positions (pos < 0: evacuated). */
+void orc_occupancy(int W, int H, int32_t n_peds, const int32_t *pos, uint8_t *occ)
+{
+    memset(occ, 0, (size_t)W * H);
+    for (int32_t i = 0; i < n_peds; ++i)
+        if (pos[i] >= 0) occ[pos[i]] = 1;
+}
+
+/* P[c] = w_D*D[c] + O[c] + Phi[c] on non-obstacle su, +inf on obstacles.
+ * Phi is the superposed pedestrian field of the live pedestrians. */
+void orc_total_field(int W, int H, const uint8_t *obst, const int32_t *D, const double *O,
+                     double w_dest, int32_t n_peds, const int32_t *pos, int R, double k,
+                     double alpha, double *P)
+{
+    int64_t n = (int64_t)W * H;
+    uint8_t *occ = (uint8_t *)malloc((size_t)(n > 0 ? n : 1));
+    orc_occupancy(W, H, n_peds, pos, occ);
+    orc_source_field(W, H, occ, R, k, alpha, P);
+    for (int64_t c = 0; c < n; ++c)
+        P[c] = obst[c] ? INFINITY : w_dest * (double)D[c] + O[c] + P[c];
+    free(occ);
+}
+
+/* ---- counter-based generator --------------------------------------------- */
+
+/* Philox4x32-10 of Salmon, Moraes, Dror and Shaw ("Parallel Random Numbers: As
+ * Easy as 1, 2, 3", SC'11): ten rounds of two 32x32->64 multiplications
+ * (multipliers 0xD2511F53 and 0xCD9E8D57) mixed with the key, the key being
+ * advanced by the Weyl constants 0x9E3779B9 and 0xBB67AE85 between rounds. */
+void orc_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+    uint32_t k0 = key_in[0], k1 = key_in[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* Election key of pedestrian `id` at step t. */
+uint64_t orc_claim_key(int32_t id, int64_t t, uint64_t seed)
+{
+    uint32_t ctr[4] = {(uint32_t)id, (uint32_t)((uint64_t)t & 0xffffffffu),
+                       (uint32_t)((uint64_t)t >> 32), 0u};
+    uint32_t key[2] = {(uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32)};
+    uint32_t r[4];
+    orc_philox4x32_10(ctr, key, r);
+    return ((uint64_t)r[0] << 32) | (uint32_t)id;
+}
+
+/* ---- one tick ------------------------------------------------------------ */
+
+/* Decision of one live pedestrian at su p, given the step-start field P and
+ * occupancy.  Writes the chosen su and whether the two best candidates are a
+ * near tie.  phi1 / phi2: the pedestrian's own field at an axial / diagonal
+ * neighbour. */
+static void decide_one(int W, int H, const uint8_t *obst, const uint8_t *occ,
+                       const double *P, double phi_axial, double phi_diag, int32_t p,
+                       int32_t *target, uint8_t *tied)
+{
+    int x = p % W, y = p / W;
+    float best32 = 0.0f;
+    int best_dir = -1;
+    double u_lo = INFINITY, u_lo2 = INFINITY; /* two smallest FP64 values */
+    for (int d = 0; d <= 8; ++d) {
+        int nx = x + DIR_X[d], ny = y + DIR_Y[d];
+        if (d > 0) {
+            if (nx < 0 || ny < 0 || nx >= W || ny >= H) continue;
+            int64_t nc = (int64_t)ny * W + nx;
+            if (obst[nc] || occ[nc]) continue;
+        }
+        int64_t c = (int64_t)ny * W + nx;
+        double own = d == 0 ? 0.0 : ((d & 1) ? phi_axial : phi_diag);
+        double u64 = P[c] - own;
+        float u32 = (float)P[c] - (float)own;
+        if (best_dir < 0 || u32 < best32) {
+            best32 = u32;
+            best_dir = d;
+        }
+        if (u64 < u_lo) {
+            u_lo2 = u_lo;
+            u_lo = u64;
+        } else if (u64 < u_lo2) {
+            u_lo2 = u64;
+        }
+    }
+    *target = (int32_t)((int64_t)(y + DIR_Y[best_dir]) * W + (x + DIR_X[best_dir]));
+    double scale = fabs(u_lo);
+    if (fabs(u_lo2) > scale) scale = fabs(u_lo2);
+    if (scale < 1.0) scale = 1.0;
+    *tied = (isfinite(u_lo2) && (u_lo2 - u_lo) <= 1e-5 * scale) ? 1 : 0;
+}
+
+/* One tick from state (pos, t).
+ *   P       [W*H]  the step-start total field (orc_total_field of pos)
+ *   pos     [N]    in: step-start positions (-1 = evacuated); out: new ones
+ *   target  [N]    out: chosen su (own su when staying; -1 when evacuated)
+ *   moved   [N]    out: 1 if the pedestrian won its election and moved
+ *   tied    [N]    out: 1 if its two best candidates are a near tie
+ * Returns the number of pedestrians that left through an exit this tick. */
+int64_t orc_step(int W, int H, const uint8_t *obst, const uint8_t *exitm, const double *P,
+                 int R, double k, double alpha, uint64_t seed, int64_t t, int32_t n_peds,
+                 int32_t *pos, int32_t *target, uint8_t *moved, uint8_t *tied)
+{
+    int64_t n = (int64_t)W * H;
+    uint8_t *occ = (uint8_t *)malloc((size_t)(n > 0 ? n : 1));
+    orc_occupancy(W, H, n_peds, pos, occ);
+    double phi_axial = orc_phi(1, 0, R, k, alpha);
+    double phi_diag = orc_phi(1, 1, R, k, alpha);
+
+    /* k-2: every live pedestrian decides on the same step-start state. */
+    for (int32_t i = 0; i < n_peds; ++i) {
+        moved[i] = 0;
+        tied[i] = 0;
+        target[i] = -1;
+        if (pos[i] < 0) continue;
+        decide_one(W, H, obst, occ, P, phi_axial, phi_diag, pos[i], &target[i], &tied[i]);
+    }
+
+    /* k-3: per claimed su, the registered pedestrian with the smallest key. */
+    uint64_t *best = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(n > 0 ? n : 1));
+    for (int64_t c = 0; c < n; ++c) best[c] = UINT64_MAX;
+    for (int32_t i = 0; i < n_peds; ++i) {
+        if (pos[i] < 0 || target[i] == pos[i]) continue;
+        uint64_t key = orc_claim_key(i, t, seed);
+        if (key < best[target[i]]) best[target[i]] = key;
+    }
+
+    /* k-4: winners move (or leave through an exit); losers stay. */
+    int64_t left = 0;
+    for (int32_t i = 0; i < n_peds; ++i) {
+        if (pos[i] < 0 || target[i] == pos[i]) continue;
+        if (best[target[i]] != orc_claim_key(i, t, seed)) continue;
+        moved[i] = 1;
+        if (exitm[target[i]]) {
+            pos[i] = -1;
+            ++left;
+        } else {
+            pos[i] = target[i];
+        }
+    }
+    free(best);
+    free(occ);
+    return left;
+}
+
+/* ---- point evaluation for large grids ------------------------------------ */
+
+/* P at one su from masks (no full-grid pass): w_D*D + sum over obstacle su in
+ * the obstacle window + sum over occupied su in the pedestrian window. */
+double orc_field_at(int W, int H, const uint8_t *obst, const uint8_t *occ, const int32_t *D,
+                    double w_dest, int R, double k, double alpha, int R_obs, double k_obs,
+                    double alpha_obs, int64_t c)
+{
+    if (obst[c]) return INFINITY;
+    int x = (int)(c % W), y = (int)(c / W);
+    double o = 0.0, f = 0.0;
+    for (int dy = -R_obs; dy <= R_obs; ++dy) {
+        int sy = y - dy;
+        if (sy < 0 || sy >= H) continue;
+        for (int dx = -R_obs; dx <= R_obs; ++dx) {
+            int sx = x - dx;
+            if (sx < 0 || sx >= W) continue;
+            if (obst[(int64_t)sy * W + sx]) o += orc_phi(dx, dy, R_obs, k_obs, alpha_obs);
+        }
+    }
+    for (int dy = -R; dy <= R; ++dy) {
+        int sy = y - dy;
+        if (sy < 0 || sy >= H) continue;
+        for (int dx = -R; dx <= R; ++dx) {
+            int sx = x - dx;
+            if (sx < 0 || sx >= W) continue;
+            if (occ[(int64_t)sy * W + sx]) f += orc_phi(dx, dy, R, k, alpha);
+        }
+    }
+    return w_dest * (double)D[c] + o + f;
+}
+
+/* Decision of the pedestrian standing at su p, from point evaluations of the
+ * field on its 3x3 neighbourhood.  Same rule as the full-grid tick. */
+void orc_decide_at(int W, int H, const uint8_t *obst, const uint8_t *occ, const int32_t *D,
+                   double w_dest, int R, double k, double alpha, int R_obs, double k_obs,
+                   double alpha_obs, int32_t p, int32_t *target, uint8_t *tied,
+                   double *P9)
+{
+    double Ploc[9];
+    int x = p % W, y = p / W;
+    /* field on the 3x3 block around p, stored by direction */
+    for (int d = 0; d <= 8; ++d) {
+        int nx = x + DIR_X[d], ny = y + DIR_Y[d];
+        Ploc[d] = INFINITY;
+        if (nx < 0 || ny < 0 || nx >= W || ny >= H) continue;
+        Ploc[d] = orc_field_at(W, H, obst, occ, D, w_dest, R, k, alpha, R_obs, k_obs,
+                               alpha_obs, (int64_t)ny * W + nx);
+    }
+    if (P9)
+        for (int d = 0; d <= 8; ++d) P9[d] = Ploc[d];
+    /* reuse the full-grid rule on a 3x3 window around p */
+    uint8_t o3[9], c3[9];
+    double P3[9];
+    for (int j = 0; j < 9; ++j) {
+        o3[j] = 1;
+        c3[j] = 0;
+        P3[j] = INFINITY;
+    }
+    for (int d = 0; d <= 8; ++d) {
+        int nx = x + DIR_X[d], ny = y + DIR_Y[d];
+        if (nx < 0 || ny < 0 || nx >= W || ny >= H) continue;
+        int64_t nc = (int64_t)ny * W + nx;
+        int j = (DIR_Y[d] + 1) * 3 + (DIR_X[d] + 1);
+        o3[j] = obst[nc];
+        c3[j] = d == 0 ? 1 : occ[nc];
+        P3[j] = Ploc[d];
+    }
+    int32_t t3;
+    decide_one(3, 3, o3, c3, P3, orc_phi(1, 0, R, k, alpha), orc_phi(1, 1, R, k, alpha), 4,
+               &t3, tied);
+    int tx = t3 % 3 - 1, ty = t3 / 3 - 1;
+    *target = (int32_t)((int64_t)(y + ty) * W + (x + tx));
+}
