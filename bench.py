@@ -1,0 +1,189 @@
+"""Benchmark of the social-field tick on one MI355X.
+
+Workload: the 1024x1024 hall (5% rectangle obstacles, two 16-su exits,
+50,000 pedestrians, field radius 16, 500 ticks), synthetic and seeded.  A
+"step" is one tick of the whole hot path: bin, decide + claim, commit,
+superpose.  Inputs are resident in HBM when the timed region starts.
+
+Prints one JSON line: pedestrian-steps/s (value) and su-field updates/s, the
+roofline of the dominant kernel (field superposition) from HIP events recorded
+around its launches, and the CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "pedestrian-steps/s + su-field updates/s; batched vs plain, 0 untied mismatches"
+# Non-packed FP32 add rate of MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz.
+ALU_PEAK_TFLOPS = 256 * 64 * 2.4e9 / 1e12
+KERNEL_SRC = os.path.join(ROOT, "paper_1803_04782_amd", "csrc", "sf_kernels.hip")
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "superpose_hall1024_pmc.json")
+
+
+def kernel_source_hash() -> str:
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def window_contributions(sc) -> float:
+    """Mean number of (pedestrian, su) pairs per pedestrian with the su inside
+    the grid and the pedestrian's window, own su excluded, at the initial
+    positions."""
+    W, H, R = sc.width, sc.height, sc.radius
+    x = sc.pos % W
+    y = sc.pos // W
+    wx = np.minimum(x + R, W - 1) - np.maximum(x - R, 0) + 1
+    wy = np.minimum(y + R, H - 1) - np.maximum(y - R, 0) + 1
+    return float(np.mean(wx * wy - 1))
+
+
+def traffic_per_launch():
+    """HBM bytes per superposition launch from the committed rocprofv3 PMC
+    summary, if it was taken on the current kernel source."""
+    try:
+        d = json.load(open(PMC_SUMMARY))
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(sc, gpu_state, seconds: float = 12.0):
+    """The FP64 oracle as it stands (single thread) on a bounded sample of the
+    workload, plus the same-run accuracy gate: one lockstep tick of the GPU
+    state against the oracle."""
+    import oracle
+
+    st = oracle.statics(sc)
+    pos = sc.pos.copy()
+    live_sum = 0
+    ticks = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds and ticks < sc.steps:
+        live_sum += int((pos >= 0).sum())
+        pos = oracle.step(st, pos, sc.start_step + ticks).pos
+        ticks += 1
+    dt = time.perf_counter() - t0
+    base = {"value": live_sum / dt, "unit": "pedestrian-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {ticks} ticks of the workload from its initial state "
+                      f"(FP64 C oracle, one thread, {dt:.1f} s)"}
+    # accuracy gate on the GPU's final state
+    pos_g, P_g, t_g, tgt_g, flags_g, pos_next = gpu_state
+    r = oracle.step(st, pos_g, t_g)
+    free = sc.obstacle == 0
+    err = float(np.max(np.abs(P_g[free] - r.P[free]) / np.maximum(np.abs(r.P[free]), 1.0)))
+    live = pos_g >= 0
+    won = (flags_g & 2) != 0
+    bad = live & ((tgt_g != r.target) | (won != (r.moved == 1)) | (pos_next != r.pos))
+    tied = set(r.target[live & (r.tied == 1)].tolist()) | set(tgt_g[live & (r.tied == 1)].tolist())
+    untied = [j for j in np.flatnonzero(bad)
+              if not r.tied[j] and r.target[j] not in tied and tgt_g[j] not in tied]
+    gate = {"tick": int(t_g), "field_rel_err": err, "untied_mismatches": len(untied),
+            "tied_mismatches": int(bad.sum()) - len(untied),
+            "near_tie_decisions": int(r.tied[live].sum()), "decisions": int(live.sum())}
+    return base, gate
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="hall1024", choices=["hall1024", "room64", "plaza8192"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "path is a design, not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1803_04782_amd import scenes, sf
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    sc = scenes.WORKLOADS[args.workload]()
+    print(f"[bench] workload {sc.name}: {sc.width}x{sc.height} su, {sc.n_peds} pedestrians, "
+          f"R={sc.radius}", file=sys.stderr, flush=True)
+    free_su = int((sc.obstacle == 0).sum())
+    g = sf.GpuScene(sc, stream=stream)
+    try:
+        # warm-up ticks, then back to the initial state for the timed run
+        g.step(args.warmup)
+        g.set_state(sc.pos, sc.start_step)
+        torch.cuda.synchronize()
+
+        t0 = time.perf_counter()
+        g.step(args.steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        s = g.stats()
+        ped_steps = s["ped_steps"]
+
+        # same ticks again with HIP events around every kernel launch
+        g.set_state(sc.pos, sc.start_step)
+        g.set_timing(True)
+        g.step(args.steps)
+        torch.cuda.synchronize()
+        ktimes = {}
+        for name, kid in (("superpose", sf.SF_KERNEL_SUPERPOSE), ("decide", sf.SF_KERNEL_DECIDE),
+                          ("commit", sf.SF_KERNEL_COMMIT), ("bin", sf.SF_KERNEL_BIN)):
+            ms, n = g.kernel_time(kid)
+            ktimes[name] = {"avg_us": 1000.0 * ms / max(n, 1), "launches": n}
+        g.set_timing(False)
+        s2 = g.stats()
+
+        # final state for the accuracy gate
+        pos_g = g.positions()
+        P_g = g.field()
+        t_g = g.stats()["step"]
+        g.step(1)
+        tgt_g, flags_g = g.last_moves()
+        pos_next = g.positions()
+    finally:
+        g.close()
+
+    value = ped_steps / dt
+    su_updates = args.steps * free_su / dt
+    contrib_per_launch = (s2["ped_steps"] / max(args.steps, 1)) * window_contributions(sc)
+    sup_us = ktimes["superpose"]["avg_us"]
+    achieved = contrib_per_launch / (sup_us * 1e-6) / 1e12
+    roofline = {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved / ALU_PEAK_TFLOPS,
+                "traffic": traffic_per_launch(), "kernel": "superpose",
+                "flop_per_launch": contrib_per_launch, "avg_launch_us": sup_us}
+
+    out = {"metric": METRIC, "value": value, "unit": "pedestrian-steps/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1000.0 * dt / args.steps,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic", "config": {"workload": sc.name, "grid": [sc.width, sc.height],
+                                           "pedestrians": sc.n_peds, "radius": sc.radius,
+                                           "ticks": args.steps, "parallelism": "single-gpu"},
+           "su_field_updates_per_s": su_updates, "kernels": ktimes, "roofline": roofline,
+           "stats": s}
+    if not args.no_cpu:
+        base, gate = cpu_baseline(sc, (pos_g, P_g, t_g, tgt_g, flags_g, pos_next),
+                                  args.cpu_seconds)
+        out["cpu_baseline"] = base
+        out["accuracy_gate"] = gate
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

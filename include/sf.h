@@ -1,0 +1,171 @@
+/*
+ * libsf -- per-tick update of the discrete social-field pedestrian model on
+ * AMD MI355X (gfx950).
+ *
+ * Model: Yu, Zhu, Wu, Zhang, "Improved OpenCL-based Implementation of Social
+ * Field Pedestrian Model".  Section 2 defines the discrete model (a grid of
+ * space units, "su"; one centre su per pedestrian; v_max = 1 su per tick),
+ * section 3.1 and Algorithm 1 the tick (k-1 .. k-5: decide, register and
+ * elect, move, write the field back), Algorithms 2/3 with Eq. 1 the field
+ * write-back as a sum of per-source contributions.
+ *
+ * Readings taken where the paper is silent:
+ *   - field law phi(d) = k*|d|_2^alpha on the square window |d|_inf <= R and
+ *     phi(0) = 0 (Fig. 1 caption: k = 1, alpha = -0.5; Table I: a 1x1 field
+ *     has no fan-out);
+ *   - static destination field D = 8-neighbour unit-cost BFS distance to the
+ *     exits; static obstacle field O = the same law summed over obstacle su;
+ *   - total field P = w_dest*D + O + Phi, +inf on obstacle su, FP32;
+ *   - a pedestrian at x chooses, among x and its free in-grid non-obstacle
+ *     Moore neighbours y, the minimum of u(y) = P(y) - phi(y - x), lowest
+ *     direction index on exact ties; direction order stay, (1,0), (1,1),
+ *     (0,1), (-1,1), (-1,0), (-1,-1), (0,-1), (1,-1) (x east, y south);
+ *   - the election of k-3 among the <= 8 registrants of an su keeps the
+ *     smallest key (Philox4x32-10(counter = (id, t_lo, t_hi, 0),
+ *     key = (seed_lo, seed_hi)).word0 << 32) | id; losers stay;
+ *   - entering an exit su removes the pedestrian in the same tick.
+ *
+ * Conventions.
+ *   - Grids are row-major, x fastest; linear su index c = y*width + x.
+ *   - Every call returns SF_OK (0) or a negative SF_E* code; the message of
+ *     the last failure on the calling thread is in sf_last_error().  No C++
+ *     exception crosses this boundary.
+ *   - Host input arrays are owned by the caller and copied during the call.
+ *     Output buffers are owned by the caller.  All device state is owned by
+ *     the scene and released by sf_destroy_scene.
+ *   - Work of a scene is enqueued on the HIP stream given at creation (NULL =
+ *     the null stream) on the device that was current at creation.
+ *   - Calls on different scenes may run on different threads; calls on one
+ *     scene must not overlap.
+ */
+#ifndef SF_H
+#define SF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SF_OK 0
+#define SF_EINVAL (-1)       /* bad descriptor or argument                    */
+#define SF_ENOMEM (-2)       /* device or host allocation failed              */
+#define SF_EDEVICE (-3)      /* a HIP call failed                             */
+#define SF_EUNREACHABLE (-4) /* a non-obstacle su has no path to any exit     */
+
+/* Largest field half-width R (pedestrian and obstacle fields) accepted. */
+#define SF_MAX_RADIUS 48
+
+typedef struct sf_scene sf_scene; /* opaque, library-owned */
+
+/* Scene description (section 2 grid, pedestrians, field geometry; Algorithm 1
+ * tick counter).  All pointers are host pointers, read during
+ * sf_create_scene only. */
+typedef struct {
+    int32_t width, height;    /* grid size in su; width*height < 2^31            */
+    const uint8_t *obstacle;  /* [height*width] 1 = obstacle (walls included)    */
+    const uint8_t *exit;      /* [height*width] 1 = exit su; never an obstacle   */
+    int32_t n_peds;           /* number of pedestrians; id = index in pos        */
+    const int32_t *pos;       /* [n_peds] linear su index, distinct, on free
+                                 non-exit su                                      */
+    int32_t radius;           /* pedestrian field half-width R, 0..SF_MAX_RADIUS */
+    double k, alpha;          /* pedestrian field law (paper example: 1, -0.5)   */
+    double k_obs, alpha_obs;  /* obstacle field law                               */
+    int32_t radius_obs;       /* obstacle field half-width; -1 = same as radius  */
+    double w_dest;            /* weight of the destination field                  */
+    uint64_t seed;            /* election key of the counter-based generator      */
+    int64_t start_step;       /* tick index of the initial state (>= 0)           */
+} sf_scene_desc;
+
+/* Running totals of a scene. */
+typedef struct {
+    int64_t step;      /* index of the next tick                                  */
+    int64_t live;      /* pedestrians still in the scene                          */
+    int64_t evacuated; /* pedestrians that left through an exit, in total        */
+    int64_t ped_steps; /* sum over ticks run of the live count at the tick start */
+    int64_t movers;    /* sum of pedestrians that registered for an su            */
+    int64_t moved;     /* sum of pedestrians that won their election and moved    */
+    int64_t tied;      /* sum of decisions whose two best FP32 values were within
+                          1e-5 relative (near ties)                               */
+} sf_stats_t;
+
+/* Flags reported per pedestrian by sf_last_moves. */
+#define SF_FLAG_MOVER 1u /* registered for a neighbour su (Algorithm 1, k-2)  */
+#define SF_FLAG_WON 2u   /* won the election and moved (k-3, k-4)             */
+#define SF_FLAG_TIED 4u  /* two best candidates within 1e-5 relative (FP32)   */
+
+/* Kernels that sf_kernel_time can report. */
+#define SF_KERNEL_SUPERPOSE 0 /* field write-back (k-5 role): P from positions */
+#define SF_KERNEL_DECIDE 1    /* decide + register (k-2, k-3 claims)            */
+#define SF_KERNEL_COMMIT 2    /* move winners, evacuate (k-4)                   */
+#define SF_KERNEL_BIN 3       /* counting-sort binning (scan + scatter)         */
+#define SF_KERNEL_COUNT 4
+
+/* Create a scene: validate the descriptor, copy it to the device, build the
+ * static fields (BFS destination field and obstacle field, fused to one FP32
+ * array), bin the pedestrians and compute the field of the initial
+ * positions.  `hip_stream` is a hipStream_t (NULL for the null stream).
+ * Blocks until the scene is ready.  Errors: SF_EINVAL (bad sizes, pointers,
+ * radius, non-finite parameters, exit on an obstacle, no exit, pedestrian out
+ * of range / on an obstacle or exit / duplicated), SF_EUNREACHABLE (a free su
+ * cannot reach an exit), SF_ENOMEM, SF_EDEVICE.  On error *out is NULL. */
+int sf_create_scene(const sf_scene_desc *desc, void *hip_stream, sf_scene **out);
+
+/* Enqueue n_steps ticks (Algorithm 1 loop body, n_steps >= 0) on the scene's
+ * stream and return without waiting.  After each tick the scene's field is
+ * that of the new positions. */
+int sf_step(sf_scene *s, int32_t n_steps);
+
+/* Copy the current total field P (float32 [height*width], +inf on obstacle
+ * su).  dst_on_device = 1: dst is device memory and the copy is enqueued on
+ * the scene's stream; 0: dst is host memory and the call blocks. */
+int sf_field(const sf_scene *s, float *dst, int dst_on_device);
+
+/* Copy positions by pedestrian id (int32 [n_peds], -1 once evacuated) and,
+ * if `alive` is not NULL, alive flags (uint8 [n_peds]).  Same dst_on_device
+ * convention as sf_field. */
+int sf_positions(const sf_scene *s, int32_t *pos, uint8_t *alive, int dst_on_device);
+
+/* Outcome of the last tick by pedestrian id: target su (int32 [n_peds]; own su
+ * when staying, -1 when already evacuated before that tick) and SF_FLAG_*
+ * bits (uint8 [n_peds]).  Either pointer may be NULL.  Same dst_on_device
+ * convention as sf_field.  Before the first tick all entries are zero. */
+int sf_last_moves(const sf_scene *s, int32_t *target, uint8_t *flags, int dst_on_device);
+
+/* Copy the static fields: S = fl32(w_dest*D + O) (float32 [height*width], +inf
+ * on obstacles) and D (int32 [height*width], -1 on obstacles).  Either pointer
+ * may be NULL.  Same dst_on_device convention as sf_field. */
+int sf_static_field(const sf_scene *s, float *S, int32_t *D, int dst_on_device);
+
+/* Replace the pedestrian state (checkpoint resume): host positions by id
+ * (int32 [n_peds], -1 = evacuated; live ones distinct, on free non-exit su)
+ * and the index of the next tick.  Counters are reset as at creation with the
+ * evacuated count set to the number of -1 entries.  Blocks.  SF_EINVAL on a
+ * bad state. */
+int sf_set_state(sf_scene *s, const int32_t *pos, int64_t step);
+
+/* Copy the running totals (blocks until the scene's queued work is done). */
+int sf_stats(const sf_scene *s, sf_stats_t *out);
+
+/* Block until all work enqueued for the scene has finished. */
+int sf_sync(const sf_scene *s);
+
+/* Per-kernel timing with HIP events recorded on the scene's stream around
+ * every launch of the kernels listed above.  enable = 1 starts a fresh
+ * measurement, 0 stops recording.  sf_kernel_time blocks, then reports the
+ * summed duration in milliseconds and the number of launches measured for
+ * one SF_KERNEL_* id. */
+int sf_set_timing(sf_scene *s, int enable);
+int sf_kernel_time(const sf_scene *s, int kernel, double *total_ms, int64_t *launches);
+
+/* Release the scene (NULL is ignored).  Waits for the scene's work first. */
+void sf_destroy_scene(sf_scene *s);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char *sf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SF_H */

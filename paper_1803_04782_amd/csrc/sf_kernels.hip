@@ -1,0 +1,736 @@
+// HIP kernels (gfx950) of the social-field tick.
+//
+// One tick (Algorithm 1 of the paper) runs as
+//   bin scan -> bin scatter -> decide+claim -> commit -> superpose
+// and scene creation as
+//   phi tables -> BFS destination field -> obstacle field (FP64) -> S ->
+//   occupancy + bin counts -> superpose.
+//
+// Field superposition (the role of k-4/k-5 and Algorithms 2/3): every su
+// gathers the contributions of the live pedestrians within its R-halo.  The
+// occupancy bitmap is the bin structure: counts per su are 0 or 1, so the
+// counting sort with one-su bins degenerates to a bitmap, and scanning its
+// words row by row enumerates a tile's halo pedestrians in global row-major
+// order.  Every su therefore sums its contributions in the same order whatever
+// the tiling, which makes the FP32 field reproducible bit for bit.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "sf_internal.h"
+
+namespace sf {
+
+namespace {
+
+constexpr int kDirX[9] = {0, 1, 1, 0, -1, -1, -1, 0, 1};
+constexpr int kDirY[9] = {0, 0, 1, 1, 1, 0, -1, -1, -1};
+
+constexpr uint8_t kMover = 1u, kWon = 2u, kTied = 4u;
+
+// ---- small helpers ------------------------------------------------------------
+
+__device__ __forceinline__ unsigned lane_id() { return __lane_id(); }
+
+// Sum of `pred` over the block, added to *dst by one thread (skipped when 0).
+// Every thread of the block must call it.
+__device__ __forceinline__ void block_count_add(bool pred, unsigned long long *dst)
+{
+    __shared__ unsigned int part[16];
+    const unsigned long long b = __ballot(pred);
+    const int wv = threadIdx.x >> 6;
+    if (lane_id() == 0) part[wv] = (unsigned int)__popcll(b);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long s = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += part[w];
+        if (s) atomicAdd(dst, s);
+    }
+    __syncthreads();
+}
+
+// Wave-aggregated append: lanes with `pred` get consecutive slots of a list
+// whose length is *cnt; one atomic per wave.
+__device__ __forceinline__ unsigned int wave_append(bool pred, unsigned int *cnt)
+{
+    const unsigned long long b = __ballot(pred);
+    if (b == 0) return 0;
+    unsigned int base = 0;
+    const int leader = __ffsll((long long)b) - 1;
+    if ((int)lane_id() == leader) base = atomicAdd(cnt, (unsigned int)__popcll(b));
+    base = __shfl(base, leader);
+    const unsigned long long below = b & ((1ull << lane_id()) - 1ull);
+    return base + (unsigned int)__popcll(below);
+}
+
+// Pointer into LDS (address space 3): 32-bit byte addresses, ds_* instructions.
+template <typename T>
+using lds_ptr = const __attribute__((address_space(3))) T *;
+
+// Hides the arithmetic origin of a per-lane value from the optimiser (an empty
+// asm with a VGPR constraint), so that address expressions built on it are not
+// refactored into per-source multiplications.
+__device__ __forceinline__ int opaque_lane(int x)
+{
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
+// Philox4x32-10 block function (Salmon, Moraes, Dror, Shaw, SC'11), word 0 of
+// the output.  Round: two 32x32->64 products with 0xD2511F53 (word 0) and
+// 0xCD9E8D57 (word 2), outputs (hi1 ^ w1 ^ k0, lo1, hi0 ^ w3 ^ k1, lo0); the key
+// advances by 0x9E3779B9 / 0xBB67AE85 between rounds.
+__device__ __forceinline__ uint32_t philox_w0(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3,
+                                              uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint32_t lo0 = 0xD2511F53u * w0;
+        const uint32_t hi0 = __umulhi(0xD2511F53u, w0);
+        const uint32_t lo1 = 0xCD9E8D57u * w2;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, w2);
+        const uint32_t n0 = hi1 ^ w1 ^ k0;
+        const uint32_t n2 = hi0 ^ w3 ^ k1;
+        w0 = n0;
+        w1 = lo1;
+        w2 = n2;
+        w3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return w0;
+}
+
+// ---- fills and masks ----------------------------------------------------------
+
+__global__ void k_fill_u64(unsigned long long *p, size_t n, unsigned long long v)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_fill_i32(int32_t *p, size_t n, int32_t v)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// One thread per 64-bit word of a row-padded bitmap (wpr words per row).
+__global__ void k_mask_to_bits(const uint8_t *__restrict__ mask, unsigned long long *__restrict__ bits,
+                               int W, int H, int wpr)
+{
+    const size_t nw = (size_t)wpr * H;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nw;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const int y = (int)(i / wpr), w = (int)(i % wpr);
+        const int x0 = w * 64;
+        const int n = min(64, W - x0);
+        const uint8_t *row = mask + (size_t)y * W + x0;
+        unsigned long long b = 0;
+        for (int j = 0; j < n; ++j) b |= (unsigned long long)(row[j] != 0) << j;
+        bits[i] = b;
+    }
+}
+
+// ---- field law table ----------------------------------------------------------
+
+// Column-major, zero-padded stamp: entry (dx, dy) at (dx+padx)*stride +
+// (dy+pady) holds k*|d|^alpha inside the square window, 0 elsewhere and at
+// d = 0.  Evaluated in FP64 and rounded once to T.
+template <typename T>
+__global__ void k_phi_table(T *tab, int ncols, int nrows, int stride, int padx, int pady, int R,
+                            double k, double alpha)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ncols * stride) return;
+    const int ci = i / stride, ri = i - ci * stride;
+    const int dx = ci - padx, dy = ri - pady;
+    double v = 0.0;
+    if (ri < nrows && abs(dx) <= R && abs(dy) <= R && (dx != 0 || dy != 0))
+        v = k * pow(sqrt((double)dx * dx + (double)dy * dy), alpha);
+    tab[i] = (T)v;
+}
+
+// ---- destination field: multi-source BFS --------------------------------------
+
+__global__ void k_bfs_init(const uint8_t *__restrict__ obst, const uint8_t *__restrict__ exitm,
+                           int32_t *__restrict__ D, int32_t *__restrict__ frontier,
+                           unsigned int *cnt, int n)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    bool src = false;
+    if (c < n) {
+        src = exitm[c] && !obst[c];
+        D[c] = src ? 0 : -1;
+    }
+    const unsigned int slot = wave_append(src, &cnt[0]);
+    if (src) frontier[slot] = c;
+}
+
+// Expansion of BFS level L: frontier of level L (count cnt[L%3]) -> level L+1
+// (count cnt[(L+1)%3]); cnt[(L+2)%3] is cleared for the next launch.
+__global__ void k_bfs_expand(const uint8_t *__restrict__ obst, int32_t *D,
+                             const int32_t *__restrict__ fin, int32_t *__restrict__ fout,
+                             unsigned int *cnt, int W, int H, int L)
+{
+    const unsigned int n_in = cnt[L % 3];
+    const unsigned int nthreads = gridDim.x * blockDim.x;
+    const unsigned int tid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid == 0) cnt[(L + 2) % 3] = 0u;
+    // every lane of a wave runs the same number of iterations (wave_append
+    // needs the whole wave)
+    const unsigned int rounds = (n_in + nthreads - 1) / nthreads;
+    for (unsigned int r = 0; r < rounds; ++r) {
+        const unsigned int i = r * nthreads + tid;
+        const bool act = i < n_in;
+        int x = 0, y = 0;
+        if (act) {
+            const int c = fin[i];
+            x = c % W;
+            y = c / W;
+        }
+#pragma unroll
+        for (int d = 1; d <= 8; ++d) {
+            const int nx = x + kDirX[d], ny = y + kDirY[d];
+            bool found = false;
+            int nc = 0;
+            if (act && nx >= 0 && ny >= 0 && nx < W && ny < H) {
+                nc = ny * W + nx;
+                if (!obst[nc] && D[nc] < 0) found = atomicCAS(&D[nc], -1, L + 1) == -1;
+            }
+            const unsigned int slot = wave_append(found, &cnt[(L + 1) % 3]);
+            if (found) fout[slot] = nc;
+        }
+    }
+}
+
+__global__ void k_count_unreachable(const uint8_t *__restrict__ obst, const int32_t *__restrict__ D,
+                                    int n, unsigned long long *out)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool bad = c < n && !obst[c] && D[c] < 0;
+    block_count_add(bad, out);
+}
+
+__global__ void k_static_S(const int32_t *__restrict__ D, const double *__restrict__ O,
+                           const uint8_t *__restrict__ obst, double w_dest, float *__restrict__ S,
+                           int n)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    S[c] = obst[c] ? INFINITY : (float)(w_dest * (double)D[c] + O[c]);
+}
+
+// ---- field superposition --------------------------------------------------------
+
+// Persistent kernel: each wave takes TW x TH output tiles.  For every live
+// source in the tile's R-halo (bitmap words scanned in row-major order; the
+// source coordinates are wave-uniform) each lane adds HL table entries, one
+// per owned row, at immediate offsets G*r from a single per-source address.
+constexpr int kSupThreads = 256;
+
+template <typename T, int TW, int HL, bool ADD_S>
+__global__ __launch_bounds__(kSupThreads) void k_superpose(
+    const unsigned long long *__restrict__ bits, int wpr, const T *__restrict__ tab_g,
+    int tab_elems, int stride, int padx, int pady, int R, const float *__restrict__ S,
+    T *__restrict__ outT, float *__restrict__ outP, int W, int H, int tiles_x, int n_tiles)
+{
+    constexpr int G = 64 / TW;
+    constexpr int TH = G * HL;
+    constexpr int NW = kSupThreads / 64;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    T *tab = reinterpret_cast<T *>(lds_raw);
+    for (int i = threadIdx.x; i < tab_elems; i += kSupThreads) tab[i] = tab_g[i];
+    __syncthreads();
+
+    const int lane = (int)lane_id();
+    // wave index and everything derived from it is wave-uniform: the source
+    // scan below runs on the scalar unit
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int col = lane / G, rg = lane % G;
+    const int t0 = __builtin_amdgcn_readfirstlane((int)blockIdx.x * NW + wv);
+    const int tstep = __builtin_amdgcn_readfirstlane((int)gridDim.x * NW);
+
+    for (int t = t0; t < n_tiles; t += tstep) {
+        const int ty = t / tiles_x, tx = t - ty * tiles_x;
+        const int x0 = tx * TW, y0 = ty * TH;
+        // byte address in LDS of table entry (this lane's su - source at the
+        // origin); a source at (px, py) then reads at base - (px*stride + py)*E
+        constexpr int E = (int)sizeof(T);
+        const int base = opaque_lane((int)(uint32_t)(uintptr_t)((lds_ptr<T>)tab) +
+                                     ((x0 + col + padx) * stride + (y0 + rg + pady)) * E);
+        T acc[HL];
+#pragma unroll
+        for (int r = 0; r < HL; ++r) acc[r] = T(0);
+        const int ya = max(y0 - R, 0), yb = min(y0 + TH - 1 + R, H - 1);
+        const int xa = max(x0 - R, 0), xb = min(x0 + TW - 1 + R, W - 1);
+        const int wa = xa >> 6, nwd = (xb >> 6) - wa + 1;  // 1..3 words per halo row
+        const unsigned long long ma = ~0ull << (xa & 63);
+        const unsigned long long mb = ~0ull >> (63 - (xb & 63));
+        // 64 halo rows at a time: lane i holds the masked words of row ya+r0+i
+        for (int r0 = ya; r0 <= yb; r0 += 64) {
+            const int y = r0 + lane;
+            unsigned long long m0 = 0, m1 = 0, m2 = 0;
+            if (y <= yb) {
+                const unsigned long long *row = bits + (size_t)y * wpr + wa;
+                m0 = row[0];
+                if (nwd > 1) m1 = row[1];
+                if (nwd > 2) m2 = row[2];
+            }
+            m0 &= ma;
+            if (nwd == 1) m0 &= mb;
+            if (nwd == 2) m1 &= mb;
+            if (nwd == 3) m2 &= mb;
+            unsigned long long nz = __ballot((m0 | m1 | m2) != 0ull);
+            while (nz) {  // non-empty halo rows, ascending
+                const int li = __builtin_ctzll(nz);
+                nz &= nz - 1ull;
+                const int py = r0 + li;
+                const int rbase = base - py * E;
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    if (j >= nwd) break;
+                    const unsigned long long mj = j == 0 ? m0 : (j == 1 ? m1 : m2);
+                    unsigned long long mw =
+                        ((unsigned long long)(uint32_t)__builtin_amdgcn_readlane((int)(mj >> 32), li)
+                         << 32) |
+                        (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)mj, li);
+                    const int cbase = ((wa + j) << 6) * stride * E;
+                    while (mw) {  // sources of the word, ascending x
+                        const int b = __builtin_ctzll(mw);
+                        mw &= mw - 1ull;
+                        const lds_ptr<T> src = reinterpret_cast<lds_ptr<T>>(
+                            (uint32_t)(rbase - (cbase + b * stride * E)));
+#pragma unroll
+                        for (int r = 0; r < HL; ++r) acc[r] += src[G * r];
+                    }
+                }
+            }
+        }
+        const int x = x0 + col;
+#pragma unroll
+        for (int r = 0; r < HL; ++r) {
+            const int y = y0 + rg + G * r;
+            if (x < W && y < H) {
+                const size_t c = (size_t)y * W + x;
+                if constexpr (ADD_S)
+                    outP[c] = S[c] + (float)acc[r];
+                else
+                    outT[c] = acc[r];
+            }
+        }
+    }
+}
+
+// ---- occupancy and binning ------------------------------------------------------
+
+__device__ __forceinline__ int bin_of(int p, int W, int bins_x)
+{
+    const int y = p / W, x = p - y * W;
+    return (y >> 6) * bins_x + (x >> 6);
+}
+
+__global__ void k_occ_init(const int32_t *__restrict__ pos, int N, unsigned long long *occ, int wpr,
+                           int W, int32_t *bin_count, int bins_x, DevCounters *ctr)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int p = i < N ? pos[i] : -1;
+    if (p >= 0) {
+        const int y = p / W, x = p - y * W;
+        atomicOr(&occ[(size_t)y * wpr + (x >> 6)], 1ull << (x & 63));
+        atomicAdd(&bin_count[(y >> 6) * bins_x + (x >> 6)], 1);
+    }
+    block_count_add(p >= 0, &ctr->live);
+}
+
+// Exclusive scan of the bin counts by one workgroup of 1024 threads; the counts
+// are cleared for the next tick (commit refills them).
+__global__ __launch_bounds__(1024) void k_bin_scan(int32_t *count, int32_t *start, int32_t *cursor,
+                                                    int nb)
+{
+    __shared__ int part[1024];
+    const int tid = threadIdx.x;
+    const int per = (nb + 1023) / 1024;
+    const int lo = min(tid * per, nb), hi = min(lo + per, nb);
+    int s = 0;
+    for (int i = lo; i < hi; ++i) s += count[i];
+    part[tid] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int v = tid >= off ? part[tid - off] : 0;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    int run = part[tid] - s;
+    for (int i = lo; i < hi; ++i) {
+        const int c = count[i];
+        start[i] = run;
+        cursor[i] = run;
+        run += c;
+        count[i] = 0;
+    }
+    if (tid == 1023) start[nb] = part[1023];
+}
+
+__global__ void k_bin_scatter(const int32_t *__restrict__ pos, int N, int W, int bins_x,
+                              int32_t *cursor, int32_t *__restrict__ sorted)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int p = pos[i];
+    if (p < 0) return;
+    const int slot = atomicAdd(&cursor[bin_of(p, W, bins_x)], 1);
+    sorted[slot] = i;
+}
+
+// ---- decide + claim (k-2, k-3 registration) --------------------------------------
+
+__global__ __launch_bounds__(256) void k_decide_claim(
+    const int32_t *__restrict__ sorted, const int32_t *__restrict__ bin_start, int nb,
+    const int32_t *__restrict__ pos, const float *__restrict__ P,
+    const unsigned long long *__restrict__ occ, int wpr, int W, int H, float phi_axial,
+    float phi_diag, unsigned long long seed, int32_t *__restrict__ target,
+    unsigned long long *__restrict__ key, uint8_t *__restrict__ flags, unsigned long long *claim,
+    DevCounters *ctr)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int live = bin_start[nb];
+    const unsigned long long t = ctr->step;
+    bool mover = false, tied = false;
+    if (j < live) {
+        const int i = sorted[j];
+        const int p = pos[i];
+        const int y = p / W, x = p - y * W;
+        float lo = P[p], lo2 = INFINITY;
+        int best = 0;
+#pragma unroll
+        for (int d = 1; d <= 8; ++d) {
+            const int nx = x + kDirX[d], ny = y + kDirY[d];
+            if (nx >= 0 && ny >= 0 && nx < W && ny < H) {
+                const unsigned long long wbits = occ[(size_t)ny * wpr + (nx >> 6)];
+                const float pc = P[(size_t)ny * W + nx];
+                // P is +inf on obstacle su
+                if (!((wbits >> (nx & 63)) & 1ull) && pc < INFINITY) {
+                    const float u = pc - ((d & 1) ? phi_axial : phi_diag);
+                    if (u < lo) {
+                        lo2 = lo;
+                        lo = u;
+                        best = d;
+                    } else if (u < lo2) {
+                        lo2 = u;
+                    }
+                }
+            }
+        }
+        const float scale = fmaxf(fmaxf(fabsf(lo), fabsf(lo2)), 1.0f);
+        tied = lo2 < INFINITY && (lo2 - lo) <= 1e-5f * scale;
+        int tgt = p;
+        if (best != 0) {
+            tgt = (y + kDirY[best]) * W + (x + kDirX[best]);
+            const uint32_t r = philox_w0((uint32_t)i, (uint32_t)t, (uint32_t)(t >> 32), 0u,
+                                         (uint32_t)seed, (uint32_t)(seed >> 32));
+            const unsigned long long kk = ((unsigned long long)r << 32) | (uint32_t)i;
+            atomicMin(&claim[tgt], kk);
+            key[i] = kk;
+            mover = true;
+        }
+        target[i] = tgt;
+        flags[i] = (uint8_t)((mover ? kMover : 0u) | (tied ? kTied : 0u));
+    }
+    block_count_add(mover, &ctr->movers);
+    block_count_add(tied, &ctr->tied);
+}
+
+// ---- commit (k-4 moves, exits) -------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_commit(int N, int W, int bins_x, int32_t *__restrict__ pos,
+                                                int32_t *__restrict__ target,
+                                                const unsigned long long *__restrict__ key,
+                                                uint8_t *__restrict__ flags,
+                                                unsigned long long *claim, unsigned long long *occ,
+                                                int wpr, const uint8_t *__restrict__ exitm,
+                                                int32_t *bin_count, DevCounters *ctr)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    bool was_live = false, won = false, left = false;
+    if (i < N) {
+        const int p = pos[i];
+        if (p < 0) {
+            target[i] = -1;
+            flags[i] = 0;
+        } else {
+            was_live = true;
+            int np = p;
+            const uint8_t f = flags[i];
+            if (f & kMover) {
+                const int tgt = target[i];
+                const unsigned long long kk = key[i];
+                if (claim[tgt] == kk) {
+                    won = true;
+                    claim[tgt] = ~0ull;
+                    const int y = p / W, x = p - y * W;
+                    atomicAnd(&occ[(size_t)y * wpr + (x >> 6)], ~(1ull << (x & 63)));
+                    if (exitm[tgt]) {
+                        left = true;
+                        np = -1;
+                    } else {
+                        const int ty = tgt / W, tx = tgt - ty * W;
+                        atomicOr(&occ[(size_t)ty * wpr + (tx >> 6)], 1ull << (tx & 63));
+                        np = tgt;
+                    }
+                    pos[i] = np;
+                    flags[i] = f | kWon;
+                }
+            }
+            if (np >= 0) atomicAdd(&bin_count[bin_of(np, W, bins_x)], 1);
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&ctr->step, 1ull);
+    block_count_add(was_live, &ctr->ped_steps);
+    block_count_add(won, &ctr->moved);
+    block_count_add(left, &ctr->evacuated);
+    // live -= left, as a two's-complement add of the negated count
+    {
+        __shared__ unsigned int lp[16];
+        const unsigned long long b = __ballot(left);
+        if (lane_id() == 0) lp[threadIdx.x >> 6] = (unsigned int)__popcll(b);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long s = 0;
+            for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += lp[w];
+            if (s) atomicAdd(&ctr->live, (unsigned long long)(-(long long)s));
+        }
+    }
+}
+
+inline unsigned int blocks_for(size_t n, unsigned int bs, unsigned int cap = 65535u * 16u)
+{
+    size_t b = (n + bs - 1) / bs;
+    if (b == 0) b = 1;
+    return (unsigned int)(b > cap ? cap : b);
+}
+
+template <typename T, int TW, int HL, bool ADD_S>
+hipError_t sup_launch(const SupCfg &c, const unsigned long long *bits, int wpr, const T *tab,
+                      const float *S, T *outT, float *outP, int W, int H, hipStream_t st)
+{
+    constexpr int TH = (64 / TW) * HL;
+    const int tiles_x = (W + TW - 1) / TW, tiles_y = (H + TH - 1) / TH;
+    const int n_tiles = tiles_x * tiles_y;
+    const int want = (n_tiles + kSupThreads / 64 - 1) / (kSupThreads / 64);
+    const int grid = want < c.grid ? want : c.grid;
+    hipLaunchKernelGGL((k_superpose<T, TW, HL, ADD_S>), dim3(grid > 0 ? grid : 1), dim3(kSupThreads),
+                       c.lds_bytes, st, bits, wpr, tab, c.ncols * c.stride, c.stride, c.padx,
+                       c.pady, c.radius, S, outT, outP, W, H, tiles_x, n_tiles);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+// ---- launch configuration -------------------------------------------------------------
+
+void pick_sup_shape(int radius, int *tw, int *hl)
+{
+    if (radius <= 8) {
+        *tw = 8;
+        *hl = 1;
+    } else if (radius <= 24) {
+        *tw = 16;
+        *hl = 2;
+    } else {
+        *tw = 16;
+        *hl = 4;
+    }
+}
+
+SupCfg make_sup_cfg(int radius, int tw, int hl, size_t elem)
+{
+    SupCfg c;
+    c.tw = tw;
+    c.hl = hl;
+    c.g = 64 / tw;
+    c.th = c.g * hl;
+    c.radius = radius;
+    c.padx = radius + tw - 1;
+    c.pady = radius + c.th - 1;
+    c.ncols = 2 * c.padx + 1;
+    c.nrows = 2 * c.pady + 1;
+    // stride = G * odd: lane l = col*G + rg reads word col*stride + rg (+ const),
+    // and col*stride mod 64 = G * (col*odd mod TW) is a permutation of the
+    // multiples of G, so the 64 lanes of a read hit 64 distinct banks (and the
+    // two 32-lane halves 32 distinct banks each).
+    int s = c.nrows;
+    while (s % c.g != 0 || ((s / c.g) & 1) == 0) ++s;
+    c.stride = s;
+    c.elem = elem;
+    c.lds_bytes = (size_t)c.ncols * c.stride * elem;
+    return c;
+}
+
+// ---- launchers ----------------------------------------------------------------------
+
+hipError_t launch_fill_u64(unsigned long long *p, size_t n, unsigned long long v, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fill_u64, dim3(blocks_for(n, 256, 8192)), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t *p, size_t n, int32_t v, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(n, 256, 8192)), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_mask_to_bits(const uint8_t *mask, unsigned long long *bits, int W, int H, int wpr,
+                               hipStream_t st)
+{
+    hipLaunchKernelGGL(k_mask_to_bits, dim3(blocks_for((size_t)wpr * H, 256, 8192)), dim3(256), 0,
+                       st, mask, bits, W, H, wpr);
+    return hipGetLastError();
+}
+
+hipError_t launch_phi_table_f32(float *tab, const SupCfg &c, double k, double alpha, hipStream_t st)
+{
+    const int n = c.ncols * c.stride;
+    hipLaunchKernelGGL(k_phi_table<float>, dim3(blocks_for(n, 256)), dim3(256), 0, st, tab, c.ncols,
+                       c.nrows, c.stride, c.padx, c.pady, c.radius, k, alpha);
+    return hipGetLastError();
+}
+
+hipError_t launch_phi_table_f64(double *tab, const SupCfg &c, double k, double alpha,
+                                hipStream_t st)
+{
+    const int n = c.ncols * c.stride;
+    hipLaunchKernelGGL(k_phi_table<double>, dim3(blocks_for(n, 256)), dim3(256), 0, st, tab,
+                       c.ncols, c.nrows, c.stride, c.padx, c.pady, c.radius, k, alpha);
+    return hipGetLastError();
+}
+
+hipError_t launch_bfs_init(const uint8_t *obst, const uint8_t *exitm, int32_t *D, int32_t *frontier,
+                           unsigned int *cnt, int n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_bfs_init, dim3(blocks_for(n, 256)), dim3(256), 0, st, obst, exitm, D,
+                       frontier, cnt, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_bfs_levels(const uint8_t *obst, int32_t *D, int32_t *fa, int32_t *fb,
+                             unsigned int *cnt, int W, int H, int level0, int levels, int grid,
+                             hipStream_t st)
+{
+    for (int L = level0; L < level0 + levels; ++L) {
+        const int32_t *fin = (L & 1) ? fb : fa;
+        int32_t *fout = (L & 1) ? fa : fb;
+        hipLaunchKernelGGL(k_bfs_expand, dim3(grid), dim3(256), 0, st, obst, D, fin, fout, cnt, W,
+                           H, L);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_count_unreachable(const uint8_t *obst, const int32_t *D, int n,
+                                    unsigned long long *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_count_unreachable, dim3(blocks_for(n, 256)), dim3(256), 0, st, obst, D, n,
+                       out);
+    return hipGetLastError();
+}
+
+hipError_t set_superpose_lds_limits(size_t f32_bytes, size_t f64_bytes)
+{
+    hipError_t e = hipSuccess;
+    const void *f32s[] = {
+        reinterpret_cast<const void *>(&k_superpose<float, 8, 1, true>),
+        reinterpret_cast<const void *>(&k_superpose<float, 16, 2, true>),
+        reinterpret_cast<const void *>(&k_superpose<float, 16, 4, true>)};
+    for (const void *f : f32s) {
+        e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)f32_bytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_superpose<double, 8, 1, false>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)f64_bytes);
+}
+
+hipError_t launch_superpose_f32(const SupCfg &c, const unsigned long long *bits, int wpr,
+                                const float *tab, const float *S, float *P, int W, int H,
+                                hipStream_t st)
+{
+    if (c.tw == 8 && c.hl == 1)
+        return sup_launch<float, 8, 1, true>(c, bits, wpr, tab, S, nullptr, P, W, H, st);
+    if (c.tw == 16 && c.hl == 2)
+        return sup_launch<float, 16, 2, true>(c, bits, wpr, tab, S, nullptr, P, W, H, st);
+    if (c.tw == 16 && c.hl == 4)
+        return sup_launch<float, 16, 4, true>(c, bits, wpr, tab, S, nullptr, P, W, H, st);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_superpose_f64(const SupCfg &c, const unsigned long long *bits, int wpr,
+                                const double *tab, double *out, int W, int H, hipStream_t st)
+{
+    if (c.tw == 8 && c.hl == 1)
+        return sup_launch<double, 8, 1, false>(c, bits, wpr, tab, nullptr, out, nullptr, W, H, st);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_static_S(const int32_t *D, const double *O, const uint8_t *obst, double w_dest,
+                           float *S, int n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_static_S, dim3(blocks_for(n, 256)), dim3(256), 0, st, D, O, obst, w_dest,
+                       S, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_occ_init(const int32_t *pos, int N, unsigned long long *occ, int wpr, int W,
+                           int32_t *bin_count, int bins_x, DevCounters *ctr, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_occ_init, dim3(blocks_for(N, 256)), dim3(256), 0, st, pos, N, occ, wpr, W,
+                       bin_count, bins_x, ctr);
+    return hipGetLastError();
+}
+
+hipError_t launch_bin_scan(int32_t *bin_count, int32_t *bin_start, int32_t *bin_cursor, int nb,
+                           hipStream_t st)
+{
+    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, st, bin_count, bin_start, bin_cursor,
+                       nb);
+    return hipGetLastError();
+}
+
+hipError_t launch_bin_scatter(const int32_t *pos, int N, int W, int bins_x, int32_t *bin_cursor,
+                              int32_t *sorted, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_bin_scatter, dim3(blocks_for(N, 256)), dim3(256), 0, st, pos, N, W,
+                       bins_x, bin_cursor, sorted);
+    return hipGetLastError();
+}
+
+hipError_t launch_decide_claim(const int32_t *sorted, const int32_t *bin_start, int nb, int N,
+                               const int32_t *pos, const float *P, const unsigned long long *occ,
+                               int wpr, int W, int H, float phi_axial, float phi_diag,
+                               unsigned long long seed, int32_t *target, unsigned long long *key,
+                               uint8_t *flags, unsigned long long *claim, DevCounters *ctr,
+                               hipStream_t st)
+{
+    hipLaunchKernelGGL(k_decide_claim, dim3(blocks_for(N, 256)), dim3(256), 0, st, sorted,
+                       bin_start, nb, pos, P, occ, wpr, W, H, phi_axial, phi_diag, seed, target,
+                       key, flags, claim, ctr);
+    return hipGetLastError();
+}
+
+hipError_t launch_commit(int N, int W, int bins_x, int32_t *pos, const int32_t *target,
+                         const unsigned long long *key, uint8_t *flags, unsigned long long *claim,
+                         unsigned long long *occ, int wpr, const uint8_t *exitm,
+                         int32_t *bin_count, DevCounters *ctr, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_commit, dim3(blocks_for(N, 256)), dim3(256), 0, st, N, W, bins_x, pos,
+                       const_cast<int32_t *>(target), key, flags, claim, occ, wpr, exitm,
+                       bin_count, ctr);
+    return hipGetLastError();
+}
+
+}  // namespace sf

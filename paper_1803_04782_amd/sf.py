@@ -1,0 +1,229 @@
+"""Python binding of libsf (include/sf.h): argument marshalling only.
+
+Every computation runs in the HIP library; this module converts numpy arrays
+and torch device tensors into the pointers and sizes the C ABI takes.  It
+raises if the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsf.so")
+
+SF_OK = 0
+SF_EINVAL = -1
+SF_ENOMEM = -2
+SF_EDEVICE = -3
+SF_EUNREACHABLE = -4
+SF_MAX_RADIUS = 48
+
+SF_FLAG_MOVER = 1
+SF_FLAG_WON = 2
+SF_FLAG_TIED = 4
+
+SF_KERNEL_SUPERPOSE = 0
+SF_KERNEL_DECIDE = 1
+SF_KERNEL_COMMIT = 2
+SF_KERNEL_BIN = 3
+
+# every symbol include/sf.h declares
+EXPORTS = ("sf_create_scene", "sf_step", "sf_field", "sf_positions", "sf_last_moves",
+           "sf_static_field", "sf_set_state", "sf_stats", "sf_sync", "sf_set_timing",
+           "sf_kernel_time", "sf_destroy_scene", "sf_last_error")
+
+
+class SceneDesc(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("obstacle", ctypes.c_void_p), ("exit", ctypes.c_void_p),
+                ("n_peds", ctypes.c_int32), ("pos", ctypes.c_void_p),
+                ("radius", ctypes.c_int32), ("k", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("k_obs", ctypes.c_double), ("alpha_obs", ctypes.c_double),
+                ("radius_obs", ctypes.c_int32), ("w_dest", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("start_step", ctypes.c_int64)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("step", ctypes.c_int64), ("live", ctypes.c_int64), ("evacuated", ctypes.c_int64),
+                ("ped_steps", ctypes.c_int64), ("movers", ctypes.c_int64),
+                ("moved", ctypes.c_int64), ("tied", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+class SfError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libsf error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load():
+    """Load libsf.so (raises if it is missing: there is no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    lib.sf_create_scene.argtypes = [ctypes.POINTER(SceneDesc), P, ctypes.POINTER(P)]
+    lib.sf_step.argtypes = [P, i32]
+    lib.sf_field.argtypes = [P, P, ctypes.c_int]
+    lib.sf_positions.argtypes = [P, P, P, ctypes.c_int]
+    lib.sf_last_moves.argtypes = [P, P, P, ctypes.c_int]
+    lib.sf_static_field.argtypes = [P, P, P, ctypes.c_int]
+    lib.sf_set_state.argtypes = [P, P, i64]
+    lib.sf_stats.argtypes = [P, ctypes.POINTER(Stats)]
+    lib.sf_sync.argtypes = [P]
+    lib.sf_set_timing.argtypes = [P, ctypes.c_int]
+    lib.sf_kernel_time.argtypes = [P, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                   ctypes.POINTER(i64)]
+    lib.sf_destroy_scene.argtypes = [P]
+    lib.sf_destroy_scene.restype = None
+    lib.sf_last_error.restype = ctypes.c_char_p
+    lib.sf_last_error.argtypes = []
+    for name in EXPORTS:
+        if name not in ("sf_destroy_scene", "sf_last_error"):
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != SF_OK:
+        raise SfError(rc, load().sf_last_error().decode())
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def make_desc(scene, start_step: Optional[int] = None):
+    """Descriptor plus the numpy arrays it points to (keep both alive)."""
+    ob = np.ascontiguousarray(scene.obstacle, dtype=np.uint8)
+    ex = np.ascontiguousarray(scene.exit, dtype=np.uint8)
+    pos = np.ascontiguousarray(scene.pos, dtype=np.int32)
+    d = SceneDesc(width=int(scene.width), height=int(scene.height), obstacle=_ptr(ob).value,
+                  exit=_ptr(ex).value, n_peds=int(pos.shape[0]),
+                  pos=_ptr(pos).value if pos.size else None, radius=int(scene.radius),
+                  k=float(scene.k), alpha=float(scene.alpha), k_obs=float(scene.k_obs),
+                  alpha_obs=float(scene.alpha_obs), radius_obs=int(scene.radius_obs),
+                  w_dest=float(scene.w_dest), seed=int(scene.seed) & (2**64 - 1),
+                  start_step=int(scene.start_step if start_step is None else start_step))
+    return d, (ob, ex, pos)
+
+
+def _stream_handle(stream):
+    if stream is None:
+        return None
+    if hasattr(stream, "cuda_stream"):
+        return int(stream.cuda_stream) or None
+    return int(stream) or None
+
+
+class GpuScene:
+    """One scene resident on the current HIP device."""
+
+    def __init__(self, scene, stream=None):
+        lib = load()
+        self.width, self.height = int(scene.width), int(scene.height)
+        self.n_peds = int(np.asarray(scene.pos).shape[0])
+        desc, keep = make_desc(scene)
+        h = ctypes.c_void_p()
+        _check(lib.sf_create_scene(ctypes.byref(desc), _stream_handle(stream), ctypes.byref(h)))
+        self._h = h
+        del keep
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            load().sf_destroy_scene(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def step(self, n: int = 1):
+        _check(load().sf_step(self._h, int(n)))
+
+    def sync(self):
+        _check(load().sf_sync(self._h))
+
+    def field(self, out=None):
+        """Host copy (numpy float32 [H*W]) or, with a torch tensor `out`, a
+        device-to-device copy enqueued on the scene stream."""
+        if out is not None:
+            _check(load().sf_field(self._h, ctypes.c_void_p(out.data_ptr()), 1))
+            return out
+        a = np.empty(self.width * self.height, dtype=np.float32)
+        _check(load().sf_field(self._h, _ptr(a), 0))
+        return a
+
+    def static_field(self):
+        S = np.empty(self.width * self.height, dtype=np.float32)
+        D = np.empty(self.width * self.height, dtype=np.int32)
+        _check(load().sf_static_field(self._h, _ptr(S), _ptr(D), 0))
+        return S, D
+
+    def positions(self):
+        pos = np.empty(self.n_peds, dtype=np.int32)
+        _check(load().sf_positions(self._h, _ptr(pos), None, 0))
+        return pos
+
+    def last_moves(self):
+        t = np.empty(self.n_peds, dtype=np.int32)
+        f = np.empty(self.n_peds, dtype=np.uint8)
+        _check(load().sf_last_moves(self._h, _ptr(t), _ptr(f), 0))
+        return t, f
+
+    def set_state(self, pos, step: int):
+        p = np.ascontiguousarray(pos, dtype=np.int32)
+        _check(load().sf_set_state(self._h, _ptr(p) if p.size else None, int(step)))
+
+    def stats(self) -> dict:
+        st = Stats()
+        _check(load().sf_stats(self._h, ctypes.byref(st)))
+        return st.as_dict()
+
+    def set_timing(self, on: bool):
+        _check(load().sf_set_timing(self._h, 1 if on else 0))
+
+    def kernel_time(self, kernel: int):
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        _check(load().sf_kernel_time(self._h, int(kernel), ctypes.byref(ms), ctypes.byref(n)))
+        return float(ms.value), int(n.value)
+
+
+def create_error(scene) -> tuple:
+    """(code, message) of sf_create_scene for a descriptor; destroys the scene
+    if creation succeeded.  Used to exercise validation."""
+    lib = load()
+    desc, keep = make_desc(scene)
+    h = ctypes.c_void_p()
+    rc = lib.sf_create_scene(ctypes.byref(desc), None, ctypes.byref(h))
+    msg = lib.sf_last_error().decode()
+    if rc == SF_OK:
+        lib.sf_destroy_scene(h)
+    del keep
+    return rc, msg

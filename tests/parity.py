@@ -1,0 +1,107 @@
+"""Lockstep comparison of the HIP library with the FP64 oracle.
+
+Protocol: at each compared tick the oracle takes the GPU's state (positions,
+tick index), computes the FP64 field P_t and the tick's outcome, and the two
+are compared:
+  * field: max |P_gpu - P_oracle| / max(|P_oracle|, 1) over non-obstacle su,
+    bound 1e-5;
+  * per pedestrian: chosen su, election result and new position must match
+    bit for bit, except where the oracle flags a near tie (its two best FP64
+    candidate values within 1e-5 relative) or where the mismatch is caused by
+    one: a near-tied pedestrian whose oracle or GPU target equals this
+    pedestrian's target (either side's) or its position.  Everything else is
+    an "untied" mismatch and must not occur.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle
+
+FIELD_RTOL = 1e-5
+
+
+def field_rel_err(P_gpu: np.ndarray, P_orc: np.ndarray, obstacle: np.ndarray) -> float:
+    free = obstacle == 0
+    a = P_gpu[free].astype(np.float64)
+    b = P_orc[free]
+    if a.size == 0:
+        return 0.0
+    return float(np.max(np.abs(a - b) / np.maximum(np.abs(b), 1.0)))
+
+
+def classify(pos_before, r: "oracle.StepResult", tgt_g, flags_g, pos_g):
+    """(untied mismatch ids, tied mismatch ids)."""
+    from paper_1803_04782_amd.sf import SF_FLAG_WON
+
+    live = pos_before >= 0
+    won_g = (flags_g & SF_FLAG_WON) != 0
+    tgt_o = np.where(live, r.target, -1)
+    tgt_gg = np.where(live, tgt_g, -1)
+    bad = live & ((tgt_o != tgt_gg) | (won_g != (r.moved == 1)) | (pos_g != r.pos))
+    if not bad.any():
+        return np.array([], np.int64), np.array([], np.int64)
+    tied = np.flatnonzero(live & (r.tied == 1))
+    hot = set(np.concatenate([r.target[tied], tgt_g[tied]]).tolist())
+    untied, tie = [], []
+    for j in np.flatnonzero(bad):
+        if r.tied[j] or tgt_o[j] in hot or tgt_gg[j] in hot or pos_before[j] in hot:
+            tie.append(j)
+        else:
+            untied.append(j)
+    return np.array(untied, np.int64), np.array(tie, np.int64)
+
+
+class Report:
+    def __init__(self):
+        self.steps = 0
+        self.max_field_err = 0.0
+        self.untied = 0
+        self.tied_mismatch = 0
+        self.tied_flags = 0
+        self.decisions = 0
+        self.first_untied = None
+
+    def __repr__(self):
+        return (f"Report(steps={self.steps}, max_field_err={self.max_field_err:.3g}, "
+                f"untied={self.untied}, tied_mismatch={self.tied_mismatch}, "
+                f"tied_flags={self.tied_flags}, decisions={self.decisions})")
+
+
+def compare_tick(g, st, report: Report, t: int):
+    """Compare one tick of GPU scene `g` (about to run tick t) with the oracle."""
+    pos = g.positions()
+    P_gpu = g.field()
+    r = oracle.step(st, pos, t)
+    err = field_rel_err(P_gpu, r.P, st.obstacle)
+    g.step(1)
+    tgt_g, flags_g = g.last_moves()
+    pos_g = g.positions()
+    untied, tied = classify(pos, r, tgt_g, flags_g, pos_g)
+    report.steps += 1
+    report.max_field_err = max(report.max_field_err, err)
+    report.untied += len(untied)
+    report.tied_mismatch += len(tied)
+    report.tied_flags += int(r.tied[pos >= 0].sum())
+    report.decisions += int((pos >= 0).sum())
+    if len(untied) and report.first_untied is None:
+        j = int(untied[0])
+        report.first_untied = dict(t=t, id=j, pos=int(pos[j]), tgt_orc=int(r.target[j]),
+                                   tgt_gpu=int(tgt_g[j]), moved_orc=int(r.moved[j]),
+                                   flags_gpu=int(flags_g[j]), pos_orc=int(r.pos[j]),
+                                   pos_gpu=int(pos_g[j]))
+    return r
+
+
+def lockstep(g, st, t0: int, n_steps: int, every: int = 1) -> Report:
+    rep = Report()
+    t = t0
+    done = 0
+    while done < n_steps:
+        if done % every == 0:
+            compare_tick(g, st, rep, t)
+        else:
+            g.step(1)
+        t += 1
+        done += 1
+    return rep
