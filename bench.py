@@ -141,7 +141,7 @@ def main():
         torch.cuda.synchronize()
         ktimes = {}
         for name, kid in (("superpose", sf.SF_KERNEL_SUPERPOSE), ("decide", sf.SF_KERNEL_DECIDE),
-                          ("commit", sf.SF_KERNEL_COMMIT), ("bin", sf.SF_KERNEL_BIN)):
+                          ("commit", sf.SF_KERNEL_COMMIT)):
             ms, n = g.kernel_time(kid)
             ktimes[name] = {"avg_us": 1000.0 * ms / max(n, 1), "launches": n}
         g.set_timing(False)

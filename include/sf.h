@@ -95,11 +95,11 @@ typedef struct {
 #define SF_FLAG_TIED 4u  /* two best candidates within 1e-5 relative (FP32)   */
 
 /* Kernels that sf_kernel_time can report. */
-#define SF_KERNEL_SUPERPOSE 0 /* field write-back (k-5 role): P from positions */
-#define SF_KERNEL_DECIDE 1    /* decide + register (k-2, k-3 claims)            */
-#define SF_KERNEL_COMMIT 2    /* move winners, evacuate (k-4)                   */
-#define SF_KERNEL_BIN 3       /* counting-sort binning (scan + scatter)         */
-#define SF_KERNEL_COUNT 4
+#define SF_KERNEL_SUPERPOSE 0 /* field write-back (k-5 role): P from positions  */
+#define SF_KERNEL_DECIDE 1    /* counting-sort binning + decide + register
+                                 (k-1 .. k-3 roles)                              */
+#define SF_KERNEL_COMMIT 2    /* move winners, evacuate (k-4)                    */
+#define SF_KERNEL_COUNT 3
 
 /* Create a scene: validate the descriptor, copy it to the device, build the
  * static fields (BFS destination field and obstacle field, fused to one FP32

@@ -15,7 +15,6 @@
 #include "sf.h"
 #include "sf_internal.h"
 
-using sf::DevCounters;
 using sf::SupCfg;
 
 namespace {
@@ -62,7 +61,7 @@ struct sf_scene {
     int ncu = 0;
     // layout
     int wpr = 0;          // 64-bit words per bitmap row
-    int bins_x = 0, nb = 0;
+    int chunk = 4;        // bitmap words per wave in the decide kernel
     SupCfg sup;           // pedestrian field launch shape
     float phi_axial = 0.f, phi_diag = 0.f;
     // device state
@@ -70,15 +69,14 @@ struct sf_scene {
     int32_t *D = nullptr;
     uint8_t *exitm = nullptr;
     unsigned long long *occ = nullptr, *claim = nullptr, *key = nullptr;
-    int32_t *pos = nullptr, *target = nullptr, *sorted = nullptr;
+    int32_t *pos = nullptr, *target = nullptr, *owner = nullptr;
     uint8_t *flags = nullptr;
-    int32_t *bin_count = nullptr, *bin_start = nullptr, *bin_cursor = nullptr;
-    DevCounters *ctr = nullptr;
+    unsigned long long *ctr = nullptr;  // see sf::ctr_index
     std::vector<void *> owned;
     // timing
     bool timing = false;
     std::vector<EventPair> ev[SF_KERNEL_COUNT];
-    size_t ev_used[SF_KERNEL_COUNT] = {0, 0, 0, 0};
+    size_t ev_used[SF_KERNEL_COUNT] = {};
 };
 
 namespace {
@@ -200,21 +198,37 @@ int record_end(sf_scene *s, int k)
     return SF_OK;
 }
 
-// Occupancy, bin counts and live count from the current positions, then the
-// field of those positions.  Counters other than `live` are left as they are.
+// Occupancy, owner map and live count from the current positions, then the
+// field of those positions.  Other counters are left as they are.
 int rebuild_dynamic(sf_scene *s)
 {
     const size_t nwords = (size_t)s->wpr * s->H;
     SF_HIP(sf::launch_fill_u64(s->occ, nwords, 0ull, s->stream), "clear occupancy");
-    SF_HIP(sf::launch_fill_i32(s->bin_count, (size_t)s->nb, 0, s->stream), "clear bins");
-    SF_HIP(sf::launch_fill_u64(&s->ctr->live, 1, 0ull, s->stream), "clear live");
-    SF_HIP(sf::launch_occ_init(s->pos, s->N, s->occ, s->wpr, s->W, s->bin_count, s->bins_x,
-                               s->ctr, s->stream),
+    SF_HIP(sf::launch_fill_i32(s->owner, (size_t)s->W * s->H, -1, s->stream), "clear owners");
+    SF_HIP(sf::launch_occ_init(s->pos, s->N, s->occ, s->wpr, s->W, s->owner, s->ctr, s->stream),
            "occupancy");
     SF_HIP(sf::launch_superpose_f32(s->sup, s->occ, s->wpr, s->tab, s->S, s->P, s->W, s->H,
                                     s->stream),
            "superpose");
     return SF_OK;
+}
+
+// Zero all running totals and set the tick index.
+int reset_counters(sf_scene *s, int64_t step, int64_t evacuated)
+{
+    SF_HIP(sf::launch_fill_u64(s->ctr, sf::kCtrWords, 0ull, s->stream), "clear counters");
+    SF_HIP(sf::launch_fill_u64(s->ctr, 1, (unsigned long long)step, s->stream), "step");
+    SF_HIP(sf::launch_fill_u64(s->ctr + sf::ctr_index(sf::kEvacuated, 0), 1,
+                               (unsigned long long)evacuated, s->stream),
+           "evacuated");
+    return SF_OK;
+}
+
+int64_t counter_sum(const unsigned long long *h, int id)
+{
+    unsigned long long v = 0;
+    for (int k = 0; k < sf::kSlots; ++k) v += h[sf::ctr_index(id, k)];
+    return (int64_t)v;
 }
 
 int build_statics(sf_scene *s, const uint8_t *h_obst, const uint8_t *h_exit)
@@ -254,15 +268,15 @@ int build_statics(sf_scene *s, const uint8_t *h_obst, const uint8_t *h_exit)
         if (left == 0) break;
         if (level > n) return fail(SF_EDEVICE, "BFS did not terminate");
     }
-    SF_HIP(sf::launch_fill_u64(&s->ctr->scratch, 1, 0ull, st), "clear scratch");
-    SF_HIP(sf::launch_count_unreachable(obst, s->D, n, &s->ctr->scratch, st), "reachability");
-    unsigned long long unreachable = 0;
-    SF_HIP(hipMemcpyAsync(&unreachable, &s->ctr->scratch, sizeof unreachable,
-                          hipMemcpyDeviceToHost, st),
+    SF_HIP(sf::launch_fill_u64(s->ctr, sf::kCtrWords, 0ull, st), "clear counters");
+    SF_HIP(sf::launch_count_unreachable(obst, s->D, n, s->ctr, st), "reachability");
+    std::vector<unsigned long long> hc(sf::kCtrWords);
+    SF_HIP(hipMemcpyAsync(hc.data(), s->ctr, sf::kCtrWords * 8, hipMemcpyDeviceToHost, st),
            "reachability copy");
     SF_HIP(hipStreamSynchronize(st), "reachability sync");
+    const long long unreachable = counter_sum(hc.data(), sf::kScratch);
     if (unreachable)
-        return fail(SF_EUNREACHABLE, "%llu free su cannot reach any exit", unreachable);
+        return fail(SF_EUNREACHABLE, "%lld free su cannot reach any exit", unreachable);
 
     // obstacle field in FP64, fused with the destination field into S
     const SupCfg oc = sf::make_sup_cfg(s->R_obs, 8, 1, sizeof(double));
@@ -327,8 +341,7 @@ int create(const sf_scene_desc *d, void *hip_stream, sf_scene **out)
     SF_HIP(hipDeviceGetAttribute(&s->ncu, hipDeviceAttributeMultiprocessorCount, s->device),
            "CU count");
     s->wpr = (s->W + 63) / 64;
-    s->bins_x = (s->W + 63) / 64;
-    s->nb = s->bins_x * ((s->H + 63) / 64);
+    s->chunk = sf::pick_decide_chunk(s->W, s->H, s->N);
 
     int tw = 0, hl = 0;
     sf::pick_sup_shape(s->R, &tw, &hl);
@@ -375,19 +388,12 @@ int create(const sf_scene_desc *d, void *hip_stream, sf_scene **out)
         (rc = dalloc(s, &s->occ, (size_t)s->wpr * s->H, "occupancy")) ||
         (rc = dalloc(s, &s->claim, n, "claims")) || (rc = dalloc(s, &s->key, N, "keys")) ||
         (rc = dalloc(s, &s->pos, N, "positions")) || (rc = dalloc(s, &s->target, N, "targets")) ||
-        (rc = dalloc(s, &s->sorted, N, "sorted ids")) || (rc = dalloc(s, &s->flags, (N + 3) & ~(size_t)3, "flags")) ||
-        (rc = dalloc(s, &s->bin_count, (size_t)s->nb, "bin counts")) ||
-        (rc = dalloc(s, &s->bin_start, (size_t)s->nb + 1, "bin starts")) ||
-        (rc = dalloc(s, &s->bin_cursor, (size_t)s->nb, "bin cursors")) ||
-        (rc = dalloc(s, &s->ctr, 1, "counters")))
+        (rc = dalloc(s, &s->owner, n, "owners")) ||
+        (rc = dalloc(s, &s->flags, (N + 3) & ~(size_t)3, "flags")) ||
+        (rc = dalloc(s, &s->ctr, sf::kCtrWords, "counters")))
         return rc;
 
     hipStream_t st = s->stream;
-    SF_HIP(sf::launch_fill_u64(reinterpret_cast<unsigned long long *>(s->ctr),
-                               sizeof(DevCounters) / 8, 0ull, st),
-           "clear counters");
-    SF_HIP(sf::launch_fill_u64(&s->ctr->step, 1, (unsigned long long)s->start_step, st),
-           "start step");
     SF_HIP(sf::launch_fill_u64(s->claim, n, ~0ull, st), "clear claims");
     SF_HIP(sf::launch_fill_i32(s->target, N, 0, st), "clear targets");
     SF_HIP(sf::launch_fill_i32(reinterpret_cast<int32_t *>(s->flags), (N + 3) / 4, 0, st),
@@ -406,6 +412,7 @@ int create(const sf_scene_desc *d, void *hip_stream, sf_scene **out)
         SF_HIP(hipMemcpyAsync(&s->phi_diag, s->tab + id, sizeof(float), hipMemcpyDeviceToHost, st),
                "phi copy");
     }
+    if ((rc = reset_counters(s, s->start_step, 0))) return rc;
     if ((rc = rebuild_dynamic(s))) return rc;
     SF_HIP(hipStreamSynchronize(st), "create sync");
     *out = s;
@@ -417,20 +424,15 @@ int enqueue_tick(sf_scene *s)
 {
     hipStream_t st = s->stream;
     int rc;
-    if ((rc = record_begin(s, SF_KERNEL_BIN))) return rc;
-    SF_HIP(sf::launch_bin_scan(s->bin_count, s->bin_start, s->bin_cursor, s->nb, st), "bin scan");
-    SF_HIP(sf::launch_bin_scatter(s->pos, s->N, s->W, s->bins_x, s->bin_cursor, s->sorted, st),
-           "bin scatter");
-    if ((rc = record_end(s, SF_KERNEL_BIN))) return rc;
     if ((rc = record_begin(s, SF_KERNEL_DECIDE))) return rc;
-    SF_HIP(sf::launch_decide_claim(s->sorted, s->bin_start, s->nb, s->N, s->pos, s->P, s->occ,
-                                   s->wpr, s->W, s->H, s->phi_axial, s->phi_diag, s->seed,
-                                   s->target, s->key, s->flags, s->claim, s->ctr, st),
+    SF_HIP(sf::launch_decide_claim(s->chunk, s->occ, s->wpr, s->W, s->H, s->owner, s->P,
+                                   s->phi_axial, s->phi_diag, s->seed, s->target, s->key, s->flags,
+                                   s->claim, s->ctr, st),
            "decide");
     if ((rc = record_end(s, SF_KERNEL_DECIDE))) return rc;
     if ((rc = record_begin(s, SF_KERNEL_COMMIT))) return rc;
-    SF_HIP(sf::launch_commit(s->N, s->W, s->bins_x, s->pos, s->target, s->key, s->flags, s->claim,
-                             s->occ, s->wpr, s->exitm, s->bin_count, s->ctr, st),
+    SF_HIP(sf::launch_commit(s->N, s->W, s->pos, s->target, s->key, s->flags, s->claim, s->occ,
+                             s->wpr, s->owner, s->exitm, s->ctr, st),
            "commit");
     if ((rc = record_end(s, SF_KERNEL_COMMIT))) return rc;
     if ((rc = record_begin(s, SF_KERNEL_SUPERPOSE))) return rc;
@@ -548,12 +550,7 @@ int sf_set_state(sf_scene *s, const int32_t *pos, int64_t step)
             SF_HIP(hipMemcpyAsync(s->pos, pos, (size_t)s->N * sizeof(int32_t),
                                   hipMemcpyHostToDevice, st),
                    "copy positions");
-        SF_HIP(sf::launch_fill_u64(reinterpret_cast<unsigned long long *>(s->ctr),
-                                   sizeof(DevCounters) / 8, 0ull, st),
-               "clear counters");
-        SF_HIP(sf::launch_fill_u64(&s->ctr->step, 1, (unsigned long long)step, st), "step");
-        SF_HIP(sf::launch_fill_u64(&s->ctr->evacuated, 1, (unsigned long long)gone, st),
-               "evacuated");
+        if ((rc = reset_counters(s, step, gone))) return rc;
         SF_HIP(sf::launch_fill_u64(s->claim, n, ~0ull, st), "clear claims");
         SF_HIP(sf::launch_fill_i32(s->target, (size_t)s->N, 0, st), "clear targets");
         SF_HIP(sf::launch_fill_i32(reinterpret_cast<int32_t *>(s->flags), ((size_t)s->N + 3) / 4,
@@ -571,16 +568,17 @@ int sf_stats(const sf_scene *s, sf_stats_t *out)
 {
     if (!s || !out) return fail(SF_EINVAL, "scene or out is NULL");
     DeviceGuard g(s->device);
-    DevCounters c;
-    SF_HIP(hipMemcpyAsync(&c, s->ctr, sizeof c, hipMemcpyDeviceToHost, s->stream), "stats copy");
+    std::vector<unsigned long long> h(sf::kCtrWords);
+    SF_HIP(hipMemcpyAsync(h.data(), s->ctr, sf::kCtrWords * 8, hipMemcpyDeviceToHost, s->stream),
+           "stats copy");
     SF_HIP(hipStreamSynchronize(s->stream), "stats sync");
-    out->step = (int64_t)c.step;
-    out->live = (int64_t)c.live;
-    out->evacuated = (int64_t)c.evacuated;
-    out->ped_steps = (int64_t)c.ped_steps;
-    out->movers = (int64_t)c.movers;
-    out->moved = (int64_t)c.moved;
-    out->tied = (int64_t)c.tied;
+    out->step = (int64_t)h[0];
+    out->live = counter_sum(h.data(), sf::kLive);
+    out->evacuated = counter_sum(h.data(), sf::kEvacuated);
+    out->ped_steps = counter_sum(h.data(), sf::kPedSteps);
+    out->movers = counter_sum(h.data(), sf::kMovers);
+    out->moved = counter_sum(h.data(), sf::kMoved);
+    out->tied = counter_sum(h.data(), sf::kTied);
     return SF_OK;
 }
 

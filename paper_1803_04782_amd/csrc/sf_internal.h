@@ -9,18 +9,27 @@
 
 namespace sf {
 
-// Running totals kept on the device (all 64-bit so they can be updated with
-// 64-bit atomics).
-struct DevCounters {
-    unsigned long long step;       // index of the next tick
-    unsigned long long live;       // pedestrians still in the scene
-    unsigned long long evacuated;  // left through an exit, in total
-    unsigned long long ped_steps;  // sum of live counts at tick starts
-    unsigned long long movers;     // sum of registrations
-    unsigned long long moved;      // sum of election winners
-    unsigned long long tied;       // sum of FP32 near-tie decisions
-    unsigned long long scratch;    // set-up counters (BFS, validation)
+// Running totals kept on the device.  Word 0 holds the index of the next
+// tick.  Every other total has kSlots copies, each on its own 128-byte line;
+// block b adds to copy b % kSlots, so that blocks do not serialise on one
+// address, and the host sums the copies.
+enum CounterId {
+    kLive = 0,    // pedestrians still in the scene (live count at reset + deltas)
+    kEvacuated,   // left through an exit
+    kPedSteps,    // sum of live counts at tick starts
+    kMovers,      // registrations
+    kMoved,       // election winners
+    kTied,        // FP32 near-tie decisions
+    kScratch,     // set-up counts (reachability)
+    kNumCounters
 };
+constexpr int kCtrStride = 16;  // 64-bit words per 128-byte line
+constexpr int kSlots = 64;
+constexpr size_t kCtrWords = (size_t)(1 + kNumCounters * kSlots) * kCtrStride;
+__host__ __device__ inline size_t ctr_index(int id, int slot)
+{
+    return (size_t)(1 + id * kSlots + slot) * kCtrStride;
+}
 
 // Geometry of one launch configuration of the superposition kernel.
 // Lane l of a wave owns output column col = l / G and rows rg + G*r
@@ -61,7 +70,7 @@ hipError_t launch_bfs_levels(const uint8_t *obst, int32_t *D, int32_t *fa, int32
                              unsigned int *cnt, int W, int H, int level0, int levels,
                              int grid, hipStream_t st);
 hipError_t launch_count_unreachable(const uint8_t *obst, const int32_t *D, int n,
-                                    unsigned long long *out, hipStream_t st);
+                                    unsigned long long *ctr, hipStream_t st);
 hipError_t launch_superpose_f32(const SupCfg &c, const unsigned long long *bits, int wpr,
                                 const float *tab, const float *S, float *P, int W, int H,
                                 hipStream_t st);
@@ -71,21 +80,19 @@ hipError_t set_superpose_lds_limits(size_t f32_bytes, size_t f64_bytes);
 hipError_t launch_static_S(const int32_t *D, const double *O, const uint8_t *obst,
                            double w_dest, float *S, int n, hipStream_t st);
 hipError_t launch_occ_init(const int32_t *pos, int N, unsigned long long *occ, int wpr, int W,
-                           int32_t *bin_count, int bins_x, DevCounters *ctr, hipStream_t st);
-hipError_t launch_bin_scan(int32_t *bin_count, int32_t *bin_start, int32_t *bin_cursor,
-                           int nb, hipStream_t st);
-hipError_t launch_bin_scatter(const int32_t *pos, int N, int W, int bins_x,
-                              int32_t *bin_cursor, int32_t *sorted, hipStream_t st);
-hipError_t launch_decide_claim(const int32_t *sorted, const int32_t *bin_start, int nb, int N,
-                               const int32_t *pos, const float *P,
-                               const unsigned long long *occ, int wpr, int W, int H,
-                               float phi_axial, float phi_diag, unsigned long long seed,
-                               int32_t *target, unsigned long long *key, uint8_t *flags,
-                               unsigned long long *claim, DevCounters *ctr, hipStream_t st);
-hipError_t launch_commit(int N, int W, int bins_x, int32_t *pos, const int32_t *target,
+                           int32_t *owner, unsigned long long *ctr, hipStream_t st);
+// Words of the occupancy bitmap handled per wave by the decide kernel.
+int pick_decide_chunk(int W, int H, int N);
+hipError_t launch_decide_claim(int chunk, const unsigned long long *occ, int wpr, int W, int H,
+                               const int32_t *owner, const float *P, float phi_axial,
+                               float phi_diag, unsigned long long seed, int32_t *target,
+                               unsigned long long *key, uint8_t *flags,
+                               unsigned long long *claim, unsigned long long *ctr,
+                               hipStream_t st);
+hipError_t launch_commit(int N, int W, int32_t *pos, int32_t *target,
                          const unsigned long long *key, uint8_t *flags,
                          unsigned long long *claim, unsigned long long *occ, int wpr,
-                         const uint8_t *exitm, int32_t *bin_count, DevCounters *ctr,
+                         int32_t *owner, const uint8_t *exitm, unsigned long long *ctr,
                          hipStream_t st);
 
 }  // namespace sf

@@ -1,10 +1,10 @@
 // HIP kernels (gfx950) of the social-field tick.
 //
 // One tick (Algorithm 1 of the paper) runs as
-//   bin scan -> bin scatter -> decide+claim -> commit -> superpose
+//   bin + decide + claim -> commit -> superpose
 // and scene creation as
 //   phi tables -> BFS destination field -> obstacle field (FP64) -> S ->
-//   occupancy + bin counts -> superpose.
+//   occupancy -> superpose.
 //
 // Field superposition (the role of k-4/k-5 and Algorithms 2/3): every su
 // gathers the contributions of the live pedestrians within its R-halo.  The
@@ -33,19 +33,37 @@ constexpr uint8_t kMover = 1u, kWon = 2u, kTied = 4u;
 
 __device__ __forceinline__ unsigned lane_id() { return __lane_id(); }
 
-// Sum of `pred` over the block, added to *dst by one thread (skipped when 0).
-// Every thread of the block must call it.
-__device__ __forceinline__ void block_count_add(bool pred, unsigned long long *dst)
+// Sum of `v` over the block, added by one thread to copy (block % kSlots) of
+// running total `id` (skipped when 0).  Every thread of the block must call
+// it; it synchronises the block.
+__device__ __forceinline__ void block_sum_add(unsigned int v, unsigned long long *ctr, int id)
 {
     __shared__ unsigned int part[16];
-    const unsigned long long b = __ballot(pred);
+    // wave sum by butterfly shuffles
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
     const int wv = threadIdx.x >> 6;
-    if (lane_id() == 0) part[wv] = (unsigned int)__popcll(b);
+    if (lane_id() == 0) part[wv] = v;
     __syncthreads();
     if (threadIdx.x == 0) {
         unsigned long long s = 0;
         for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += part[w];
-        if (s) atomicAdd(dst, s);
+        if (s) atomicAdd(&ctr[ctr_index(id, blockIdx.x % kSlots)], s);
+    }
+    __syncthreads();
+}
+
+// Same for a signed delta (two's-complement add).
+__device__ __forceinline__ void block_delta_add(int v, unsigned long long *ctr, int id)
+{
+    __shared__ int part[16];
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
+    const int wv = threadIdx.x >> 6;
+    if (lane_id() == 0) part[wv] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        long long s = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += part[w];
+        if (s) atomicAdd(&ctr[ctr_index(id, blockIdx.x % kSlots)], (unsigned long long)s);
     }
     __syncthreads();
 }
@@ -208,11 +226,11 @@ __global__ void k_bfs_expand(const uint8_t *__restrict__ obst, int32_t *D,
 }
 
 __global__ void k_count_unreachable(const uint8_t *__restrict__ obst, const int32_t *__restrict__ D,
-                                    int n, unsigned long long *out)
+                                    int n, unsigned long long *ctr)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     const bool bad = c < n && !obst[c] && D[c] < 0;
-    block_count_add(bad, out);
+    block_sum_add(bad ? 1u : 0u, ctr, kScratch);
 }
 
 __global__ void k_static_S(const int32_t *__restrict__ D, const double *__restrict__ O,
@@ -325,85 +343,72 @@ __global__ __launch_bounds__(kSupThreads) void k_superpose(
     }
 }
 
-// ---- occupancy and binning ------------------------------------------------------
-
-__device__ __forceinline__ int bin_of(int p, int W, int bins_x)
-{
-    const int y = p / W, x = p - y * W;
-    return (y >> 6) * bins_x + (x >> 6);
-}
+// ---- occupancy ----------------------------------------------------------------------
 
 __global__ void k_occ_init(const int32_t *__restrict__ pos, int N, unsigned long long *occ, int wpr,
-                           int W, int32_t *bin_count, int bins_x, DevCounters *ctr)
+                           int W, int32_t *__restrict__ owner, unsigned long long *ctr)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int p = i < N ? pos[i] : -1;
     if (p >= 0) {
         const int y = p / W, x = p - y * W;
         atomicOr(&occ[(size_t)y * wpr + (x >> 6)], 1ull << (x & 63));
-        atomicAdd(&bin_count[(y >> 6) * bins_x + (x >> 6)], 1);
+        owner[p] = i;
     }
-    block_count_add(p >= 0, &ctr->live);
+    block_sum_add(p >= 0 ? 1u : 0u, ctr, kLive);
 }
 
-// Exclusive scan of the bin counts by one workgroup of 1024 threads; the counts
-// are cleared for the next tick (commit refills them).
-__global__ __launch_bounds__(1024) void k_bin_scan(int32_t *count, int32_t *start, int32_t *cursor,
-                                                    int nb)
-{
-    __shared__ int part[1024];
-    const int tid = threadIdx.x;
-    const int per = (nb + 1023) / 1024;
-    const int lo = min(tid * per, nb), hi = min(lo + per, nb);
-    int s = 0;
-    for (int i = lo; i < hi; ++i) s += count[i];
-    part[tid] = s;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        const int v = tid >= off ? part[tid - off] : 0;
-        __syncthreads();
-        part[tid] += v;
-        __syncthreads();
-    }
-    int run = part[tid] - s;
-    for (int i = lo; i < hi; ++i) {
-        const int c = count[i];
-        start[i] = run;
-        cursor[i] = run;
-        run += c;
-        count[i] = 0;
-    }
-    if (tid == 1023) start[nb] = part[1023];
-}
+// ---- bin + decide + claim (k-2, k-3 registration) --------------------------------------
+//
+// Binning is a counting sort whose bins are the 64-su row words of the
+// occupancy bitmap: each wave takes `chunk` consecutive words, the per-word
+// counts are popcounts, a wave prefix sum gives each word's first slot, and
+// every lane scatters its word's su indices (ascending x) into a wave-private
+// LDS list.  The wave then decides for the listed pedestrians 64 at a time,
+// so neighbouring lanes work on neighbouring su.
 
-__global__ void k_bin_scatter(const int32_t *__restrict__ pos, int N, int W, int bins_x,
-                              int32_t *cursor, int32_t *__restrict__ sorted)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    const int p = pos[i];
-    if (p < 0) return;
-    const int slot = atomicAdd(&cursor[bin_of(p, W, bins_x)], 1);
-    sorted[slot] = i;
-}
+constexpr int kDecideThreads = 256;
 
-// ---- decide + claim (k-2, k-3 registration) --------------------------------------
-
-__global__ __launch_bounds__(256) void k_decide_claim(
-    const int32_t *__restrict__ sorted, const int32_t *__restrict__ bin_start, int nb,
-    const int32_t *__restrict__ pos, const float *__restrict__ P,
-    const unsigned long long *__restrict__ occ, int wpr, int W, int H, float phi_axial,
+__global__ __launch_bounds__(kDecideThreads) void k_decide_claim(
+    int chunk, const unsigned long long *__restrict__ occ, int wpr, int W, int H,
+    const int32_t *__restrict__ owner, const float *__restrict__ P, float phi_axial,
     float phi_diag, unsigned long long seed, int32_t *__restrict__ target,
     unsigned long long *__restrict__ key, uint8_t *__restrict__ flags, unsigned long long *claim,
-    DevCounters *ctr)
+    unsigned long long *ctr)
 {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    const int live = bin_start[nb];
-    const unsigned long long t = ctr->step;
-    bool mover = false, tied = false;
-    if (j < live) {
-        const int i = sorted[j];
-        const int p = pos[i];
+    extern __shared__ int32_t list_raw[];
+    const int lane = (int)lane_id();
+    const int wv = threadIdx.x >> 6;
+    int32_t *list = list_raw + (size_t)wv * chunk * 64;
+    const size_t nwords = (size_t)wpr * H;
+    const size_t w = ((size_t)blockIdx.x * (kDecideThreads / 64) + wv) * chunk + lane;
+    unsigned long long m = 0;
+    if (lane < chunk && w < nwords) m = occ[w];
+    const int cntl = __popcll(m);
+    int incl = cntl;
+    for (int d = 1; d < 64; d <<= 1) {
+        const int v = __shfl_up(incl, d);
+        if (lane >= d) incl += v;
+    }
+    const int total = __shfl(incl, 63);
+    if (m) {
+        const int y = (int)(w / wpr);
+        const int xb = (int)(w % wpr) * 64;
+        int o = incl - cntl;
+        while (m) {
+            const int b = __builtin_ctzll(m);
+            m &= m - 1ull;
+            list[o++] = y * W + xb + b;
+        }
+    }
+    __syncthreads();
+    const unsigned long long t = ctr[0];
+    unsigned int movers = 0, ties = 0;
+    for (int base = 0; base < total; base += 64) {
+        const int k = base + lane;
+        if (k >= total) break;
+        const int p = list[k];
+        const int i = owner[p];
         const int y = p / W, x = p - y * W;
         float lo = P[p], lo2 = INFINITY;
         int best = 0;
@@ -427,8 +432,9 @@ __global__ __launch_bounds__(256) void k_decide_claim(
             }
         }
         const float scale = fmaxf(fmaxf(fabsf(lo), fabsf(lo2)), 1.0f);
-        tied = lo2 < INFINITY && (lo2 - lo) <= 1e-5f * scale;
+        const bool tied = lo2 < INFINITY && (lo2 - lo) <= 1e-5f * scale;
         int tgt = p;
+        bool mover = false;
         if (best != 0) {
             tgt = (y + kDirY[best]) * W + (x + kDirX[best]);
             const uint32_t r = philox_w0((uint32_t)i, (uint32_t)t, (uint32_t)(t >> 32), 0u,
@@ -440,20 +446,23 @@ __global__ __launch_bounds__(256) void k_decide_claim(
         }
         target[i] = tgt;
         flags[i] = (uint8_t)((mover ? kMover : 0u) | (tied ? kTied : 0u));
+        movers += mover;
+        ties += tied;
     }
-    block_count_add(mover, &ctr->movers);
-    block_count_add(tied, &ctr->tied);
+    block_sum_add(movers, ctr, kMovers);
+    block_sum_add(ties, ctr, kTied);
 }
 
 // ---- commit (k-4 moves, exits) -------------------------------------------------------
 
-__global__ __launch_bounds__(256) void k_commit(int N, int W, int bins_x, int32_t *__restrict__ pos,
+__global__ __launch_bounds__(256) void k_commit(int N, int W, int32_t *__restrict__ pos,
                                                 int32_t *__restrict__ target,
                                                 const unsigned long long *__restrict__ key,
                                                 uint8_t *__restrict__ flags,
                                                 unsigned long long *claim, unsigned long long *occ,
-                                                int wpr, const uint8_t *__restrict__ exitm,
-                                                int32_t *bin_count, DevCounters *ctr)
+                                                int wpr, int32_t *owner,
+                                                const uint8_t *__restrict__ exitm,
+                                                unsigned long long *ctr)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     bool was_live = false, won = false, left = false;
@@ -464,47 +473,37 @@ __global__ __launch_bounds__(256) void k_commit(int N, int W, int bins_x, int32_
             flags[i] = 0;
         } else {
             was_live = true;
-            int np = p;
             const uint8_t f = flags[i];
             if (f & kMover) {
                 const int tgt = target[i];
                 const unsigned long long kk = key[i];
+                // the winner is the only registrant that finds its own key; it
+                // also resets the word, which losers then read as "not mine"
                 if (claim[tgt] == kk) {
                     won = true;
                     claim[tgt] = ~0ull;
                     const int y = p / W, x = p - y * W;
                     atomicAnd(&occ[(size_t)y * wpr + (x >> 6)], ~(1ull << (x & 63)));
+                    owner[p] = -1;
                     if (exitm[tgt]) {
                         left = true;
-                        np = -1;
+                        pos[i] = -1;
                     } else {
                         const int ty = tgt / W, tx = tgt - ty * W;
                         atomicOr(&occ[(size_t)ty * wpr + (tx >> 6)], 1ull << (tx & 63));
-                        np = tgt;
+                        owner[tgt] = i;
+                        pos[i] = tgt;
                     }
-                    pos[i] = np;
                     flags[i] = f | kWon;
                 }
             }
-            if (np >= 0) atomicAdd(&bin_count[bin_of(np, W, bins_x)], 1);
         }
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&ctr->step, 1ull);
-    block_count_add(was_live, &ctr->ped_steps);
-    block_count_add(won, &ctr->moved);
-    block_count_add(left, &ctr->evacuated);
-    // live -= left, as a two's-complement add of the negated count
-    {
-        __shared__ unsigned int lp[16];
-        const unsigned long long b = __ballot(left);
-        if (lane_id() == 0) lp[threadIdx.x >> 6] = (unsigned int)__popcll(b);
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            unsigned long long s = 0;
-            for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += lp[w];
-            if (s) atomicAdd(&ctr->live, (unsigned long long)(-(long long)s));
-        }
-    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&ctr[0], 1ull);
+    block_sum_add(was_live ? 1u : 0u, ctr, kPedSteps);
+    block_sum_add(won ? 1u : 0u, ctr, kMoved);
+    block_sum_add(left ? 1u : 0u, ctr, kEvacuated);
+    block_delta_add(left ? -1 : 0, ctr, kLive);
 }
 
 inline unsigned int blocks_for(size_t n, unsigned int bs, unsigned int cap = 65535u * 16u)
@@ -686,50 +685,45 @@ hipError_t launch_static_S(const int32_t *D, const double *O, const uint8_t *obs
 }
 
 hipError_t launch_occ_init(const int32_t *pos, int N, unsigned long long *occ, int wpr, int W,
-                           int32_t *bin_count, int bins_x, DevCounters *ctr, hipStream_t st)
+                           int32_t *owner, unsigned long long *ctr, hipStream_t st)
 {
     hipLaunchKernelGGL(k_occ_init, dim3(blocks_for(N, 256)), dim3(256), 0, st, pos, N, occ, wpr, W,
-                       bin_count, bins_x, ctr);
+                       owner, ctr);
     return hipGetLastError();
 }
 
-hipError_t launch_bin_scan(int32_t *bin_count, int32_t *bin_start, int32_t *bin_cursor, int nb,
-                           hipStream_t st)
+int pick_decide_chunk(int W, int H, int N)
 {
-    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, st, bin_count, bin_start, bin_cursor,
-                       nb);
+    // a wave of `chunk` words holds chunk * 64 * N / (W*H) pedestrians on
+    // average: aim at about one per lane
+    const double su_per_ped = (double)W * H / (N > 0 ? N : 1);
+    int c = 4;
+    while (c < 64 && c * 2 <= su_per_ped) c *= 2;
+    return c;
+}
+
+hipError_t launch_decide_claim(int chunk, const unsigned long long *occ, int wpr, int W, int H,
+                               const int32_t *owner, const float *P, float phi_axial,
+                               float phi_diag, unsigned long long seed, int32_t *target,
+                               unsigned long long *key, uint8_t *flags, unsigned long long *claim,
+                               unsigned long long *ctr, hipStream_t st)
+{
+    const size_t nwords = (size_t)wpr * H;
+    const size_t per_block = (size_t)(kDecideThreads / 64) * chunk;
+    const size_t lds = (size_t)(kDecideThreads / 64) * chunk * 64 * sizeof(int32_t);
+    hipLaunchKernelGGL(k_decide_claim, dim3(blocks_for(nwords, (unsigned)per_block)),
+                       dim3(kDecideThreads), lds, st, chunk, occ, wpr, W, H, owner, P, phi_axial,
+                       phi_diag, seed, target, key, flags, claim, ctr);
     return hipGetLastError();
 }
 
-hipError_t launch_bin_scatter(const int32_t *pos, int N, int W, int bins_x, int32_t *bin_cursor,
-                              int32_t *sorted, hipStream_t st)
+hipError_t launch_commit(int N, int W, int32_t *pos, int32_t *target, const unsigned long long *key,
+                         uint8_t *flags, unsigned long long *claim, unsigned long long *occ,
+                         int wpr, int32_t *owner, const uint8_t *exitm, unsigned long long *ctr,
+                         hipStream_t st)
 {
-    hipLaunchKernelGGL(k_bin_scatter, dim3(blocks_for(N, 256)), dim3(256), 0, st, pos, N, W,
-                       bins_x, bin_cursor, sorted);
-    return hipGetLastError();
-}
-
-hipError_t launch_decide_claim(const int32_t *sorted, const int32_t *bin_start, int nb, int N,
-                               const int32_t *pos, const float *P, const unsigned long long *occ,
-                               int wpr, int W, int H, float phi_axial, float phi_diag,
-                               unsigned long long seed, int32_t *target, unsigned long long *key,
-                               uint8_t *flags, unsigned long long *claim, DevCounters *ctr,
-                               hipStream_t st)
-{
-    hipLaunchKernelGGL(k_decide_claim, dim3(blocks_for(N, 256)), dim3(256), 0, st, sorted,
-                       bin_start, nb, pos, P, occ, wpr, W, H, phi_axial, phi_diag, seed, target,
-                       key, flags, claim, ctr);
-    return hipGetLastError();
-}
-
-hipError_t launch_commit(int N, int W, int bins_x, int32_t *pos, const int32_t *target,
-                         const unsigned long long *key, uint8_t *flags, unsigned long long *claim,
-                         unsigned long long *occ, int wpr, const uint8_t *exitm,
-                         int32_t *bin_count, DevCounters *ctr, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_commit, dim3(blocks_for(N, 256)), dim3(256), 0, st, N, W, bins_x, pos,
-                       const_cast<int32_t *>(target), key, flags, claim, occ, wpr, exitm,
-                       bin_count, ctr);
+    hipLaunchKernelGGL(k_commit, dim3(blocks_for(N, 256)), dim3(256), 0, st, N, W, pos, target, key,
+                       flags, claim, occ, wpr, owner, exitm, ctr);
     return hipGetLastError();
 }
 

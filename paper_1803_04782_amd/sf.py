@@ -29,7 +29,6 @@ SF_FLAG_TIED = 4
 SF_KERNEL_SUPERPOSE = 0
 SF_KERNEL_DECIDE = 1
 SF_KERNEL_COMMIT = 2
-SF_KERNEL_BIN = 3
 
 # every symbol include/sf.h declares
 EXPORTS = ("sf_create_scene", "sf_step", "sf_field", "sf_positions", "sf_last_moves",
