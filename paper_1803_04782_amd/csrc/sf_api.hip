@@ -15,6 +15,7 @@
 #include "sf.h"
 #include "sf_internal.h"
 
+using sf::ListCfg;
 using sf::SupCfg;
 
 namespace {
@@ -62,7 +63,7 @@ struct sf_scene {
     // layout
     int wpr = 0;          // 64-bit words per bitmap row
     int chunk = 4;        // bitmap words per wave in the decide kernel
-    SupCfg sup;           // pedestrian field launch shape
+    ListCfg lc;           // pedestrian field launch shape
     float phi_axial = 0.f, phi_diag = 0.f;
     // device state
     float *S = nullptr, *P = nullptr, *tab = nullptr;
@@ -207,8 +208,7 @@ int rebuild_dynamic(sf_scene *s)
     SF_HIP(sf::launch_fill_i32(s->owner, (size_t)s->W * s->H, -1, s->stream), "clear owners");
     SF_HIP(sf::launch_occ_init(s->pos, s->N, s->occ, s->wpr, s->W, s->owner, s->ctr, s->stream),
            "occupancy");
-    SF_HIP(sf::launch_superpose_f32(s->sup, s->occ, s->wpr, s->tab, s->S, s->P, s->W, s->H,
-                                    s->stream),
+    SF_HIP(sf::launch_field_list(s->lc, s->occ, s->wpr, s->tab, s->S, s->P, s->W, s->H, s->stream),
            "superpose");
     return SF_OK;
 }
@@ -281,20 +281,18 @@ int build_statics(sf_scene *s, const uint8_t *h_obst, const uint8_t *h_exit)
     // obstacle field in FP64, fused with the destination field into S
     const SupCfg oc = sf::make_sup_cfg(s->R_obs, 8, 1, sizeof(double));
     SupCfg ocg = oc;
-    ocg.grid = s->sup.grid;
     if ((rc = dalloc(s, &tab64, (size_t)oc.ncols * oc.stride, "obstacle table")) ||
         (rc = dalloc(s, &O, (size_t)n, "obstacle field")))
         return rc;
     {
-        // the largest table any scene can need fits the 160 KB LDS of a CU
         int max_lds = 0;
         SF_HIP(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock,
                                      s->device),
                "LDS size");
-        if ((size_t)max_lds < oc.lds_bytes || (size_t)max_lds < s->sup.lds_bytes)
-            return fail(SF_EINVAL, "field table needs %zu B of LDS, device has %d B",
-                        std::max(oc.lds_bytes, s->sup.lds_bytes), max_lds);
-        SF_HIP(sf::set_superpose_lds_limits((size_t)max_lds, (size_t)max_lds), "LDS limits");
+        if ((size_t)max_lds < oc.lds_bytes)
+            return fail(SF_EINVAL, "obstacle table needs %zu B of LDS, device has %d B",
+                        oc.lds_bytes, max_lds);
+        SF_HIP(sf::set_superpose_lds_limit((size_t)max_lds), "LDS limit");
         ocg.grid = std::max(1, s->ncu * (int)std::max<size_t>(1, (size_t)max_lds / oc.lds_bytes));
     }
     SF_HIP(sf::launch_phi_table_f64(tab64, oc, s->k_obs, s->alpha_obs, st), "obstacle table");
@@ -343,48 +341,38 @@ int create(const sf_scene_desc *d, void *hip_stream, sf_scene **out)
     s->wpr = (s->W + 63) / 64;
     s->chunk = sf::pick_decide_chunk(s->W, s->H, s->N);
 
-    int tw = 0, hl = 0;
-    sf::pick_sup_shape(s->R, &tw, &hl);
-    if (const char *e = std::getenv("SF_TILE")) {
-        // wave-tile override "TWxHL" (8x1, 16x2 or 16x4); the field does not
-        // depend on it bit for bit, the speed does
-        int a = 0, b = 0;
-        if (std::sscanf(e, "%dx%d", &a, &b) == 2 &&
-            ((a == 8 && b == 1) || (a == 16 && b == 2) || (a == 16 && b == 4))) {
-            tw = a;
-            hl = b;
-        } else {
-            return fail(SF_EINVAL, "SF_TILE=%s is not one of 8x1, 16x2, 16x4", e);
-        }
-    }
     int max_lds = 0;
     SF_HIP(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, s->device),
            "LDS size");
-    s->sup = sf::make_sup_cfg(s->R, tw, hl, sizeof(float));
-    if (s->sup.lds_bytes > (size_t)max_lds && !std::getenv("SF_TILE")) {
-        // a smaller wave tile needs a smaller padded table
-        const int shapes[2][2] = {{16, 2}, {8, 1}};
-        for (const auto &sh : shapes) {
-            s->sup = sf::make_sup_cfg(s->R, sh[0], sh[1], sizeof(float));
-            if (s->sup.lds_bytes <= (size_t)max_lds) break;
-        }
+    s->lc = sf::pick_list_cfg(s->R, (size_t)max_lds - 1024);
+    if (const char *e = std::getenv("SF_TILE")) {
+        // launch-shape override "TWxHLxVECxNW"; the field does not depend on it
+        // bit for bit, the speed does
+        int a = 0, b = 0, v = 0, w = 0;
+        if (std::sscanf(e, "%dx%dx%dx%d", &a, &b, &v, &w) != 4)
+            return fail(SF_EINVAL, "SF_TILE=%s is not of the form TWxHLxVECxNW", e);
+        s->lc = sf::make_list_cfg(s->R, a, b, v, w, 2048);
+        const bool known = (a == 16 && b == 2 && v == 2 && (w == 4 || w == 8)) ||
+                           (a == 16 && b == 4 && (v == 2 || v == 4) && (w == 4 || w == 8));
+        if (!known || s->lc.halo_rows > 64 * w)
+            return fail(SF_EINVAL, "SF_TILE=%s is not a compiled shape for radius %d", e, s->R);
     }
-    if (s->sup.lds_bytes > (size_t)max_lds)
-        return fail(SF_EINVAL, "field table of radius %d needs %zu B of LDS, device has %d B", s->R,
-                    s->sup.lds_bytes, max_lds);
+    if (s->lc.lds_bytes == 0 || s->lc.lds_bytes > (size_t)max_lds - 1024 ||
+        s->lc.list_cap < 2 * s->lc.max_row)
+        return fail(SF_EINVAL, "field of radius %d does not fit %d B of LDS", s->R, max_lds);
+    // the kernel also holds a few bytes of static LDS
+    SF_HIP(sf::set_field_list_lds_limit((size_t)max_lds - 1024), "LDS limit");
     {
-        // persistent workgroups: as many as fit per CU by LDS, at most 8
-        const size_t lds_per_cu = 160 * 1024;
-        int per_cu = (int)std::min<size_t>(8, lds_per_cu / std::max<size_t>(s->sup.lds_bytes, 1));
-        if (per_cu < 1) per_cu = 1;
-        s->sup.grid = s->ncu * per_cu;
+        int per_cu = (int)std::max<size_t>(1, (size_t)(160 * 1024) / s->lc.lds_bytes);
+        per_cu = std::min(per_cu, std::max(1, 32 / (s->lc.nw)));
+        s->lc.grid = s->ncu * per_cu;
     }
 
     const size_t n = (size_t)s->W * s->H;
     const size_t N = (size_t)s->N;
     if ((rc = dalloc(s, &s->S, n, "S")) || (rc = dalloc(s, &s->P, n, "P")) ||
         (rc = dalloc(s, &s->D, n, "D")) || (rc = dalloc(s, &s->exitm, n, "exit mask")) ||
-        (rc = dalloc(s, &s->tab, (size_t)s->sup.ncols * s->sup.stride, "phi table")) ||
+        (rc = dalloc(s, &s->tab, (size_t)s->lc.vec * s->lc.copy_elems, "phi table")) ||
         (rc = dalloc(s, &s->occ, (size_t)s->wpr * s->H, "occupancy")) ||
         (rc = dalloc(s, &s->claim, n, "claims")) || (rc = dalloc(s, &s->key, N, "keys")) ||
         (rc = dalloc(s, &s->pos, N, "positions")) || (rc = dalloc(s, &s->target, N, "targets")) ||
@@ -398,15 +386,15 @@ int create(const sf_scene_desc *d, void *hip_stream, sf_scene **out)
     SF_HIP(sf::launch_fill_i32(s->target, N, 0, st), "clear targets");
     SF_HIP(sf::launch_fill_i32(reinterpret_cast<int32_t *>(s->flags), (N + 3) / 4, 0, st),
            "clear flags");
-    SF_HIP(sf::launch_phi_table_f32(s->tab, s->sup, s->k, s->alpha, st), "phi table");
+    SF_HIP(sf::launch_phi_copies(s->tab, s->lc, s->k, s->alpha, st), "phi table");
     if (N)
         SF_HIP(hipMemcpyAsync(s->pos, d->pos, N * sizeof(int32_t), hipMemcpyHostToDevice, st),
                "copy positions");
     if ((rc = build_statics(s, d->obstacle, d->exit))) return rc;
     {
         // own-field values at axial and diagonal neighbours, as the kernels see them
-        const size_t ia = (size_t)(s->sup.padx + 1) * s->sup.stride + s->sup.pady;
-        const size_t id = (size_t)(s->sup.padx + 1) * s->sup.stride + s->sup.pady + 1;
+        const size_t ia = (size_t)(s->lc.padx + 1) * s->lc.stride + s->lc.pady;
+        const size_t id = ia + 1;
         SF_HIP(hipMemcpyAsync(&s->phi_axial, s->tab + ia, sizeof(float), hipMemcpyDeviceToHost, st),
                "phi copy");
         SF_HIP(hipMemcpyAsync(&s->phi_diag, s->tab + id, sizeof(float), hipMemcpyDeviceToHost, st),
@@ -436,7 +424,7 @@ int enqueue_tick(sf_scene *s)
            "commit");
     if ((rc = record_end(s, SF_KERNEL_COMMIT))) return rc;
     if ((rc = record_begin(s, SF_KERNEL_SUPERPOSE))) return rc;
-    SF_HIP(sf::launch_superpose_f32(s->sup, s->occ, s->wpr, s->tab, s->S, s->P, s->W, s->H, st),
+    SF_HIP(sf::launch_field_list(s->lc, s->occ, s->wpr, s->tab, s->S, s->P, s->W, s->H, st),
            "superpose");
     if ((rc = record_end(s, SF_KERNEL_SUPERPOSE))) return rc;
     return SF_OK;

@@ -50,8 +50,40 @@ struct SupCfg {
 };
 
 SupCfg make_sup_cfg(int radius, int tw, int hl, size_t elem);
-// Picks the wave-tile shape used for the FP32 pedestrian field at radius R.
-void pick_sup_shape(int radius, int *tw, int *hl);
+
+// Launch shape of the per-tick FP32 field kernel (source-list gather).
+// A workgroup of NW waves covers a TW-column strip of NW*TH rows; wave w owns
+// rows [w*TH, (w+1)*TH).  Lane l owns column l % TW and, with rg = l / TW and
+// G = 64 / TW, the rows (q*G + rg)*VEC + j for q < HL/VEC, j < VEC, so each of
+// its HL/VEC table reads is one aligned VEC-wide LDS load.  The stamp is kept
+// in VEC copies, copy c shifted down by c rows, so that a source at row py
+// reads copy (py - pady) mod VEC aligned:
+//   copy c, entry (dx, dy) at c*ncols*stride + (dx + padx)*stride + dy + pady + c
+//   padx = R + TW (one zero column beyond the halo for padding entries),
+//   pady = R + TH - 1, stride >= 2*pady + VEC, stride = VEC * odd (banks).
+// The strip's halo sources are listed in LDS in row-major order; the list
+// holds `list_cap` entries and longer halos are processed in several passes.
+struct ListCfg {
+    int tw = 0, hl = 0, vec = 0, nw = 0;
+    int g = 0, th = 0, wt = 0;
+    int radius = 0;
+    int padx = 0, pady = 0, ncols = 0, nrows = 0, stride = 0;
+    int copy_elems = 0;  // ncols * stride
+    int list_cap = 0;
+    int max_row = 0;     // most sources one halo row can hold
+    int halo_rows = 0;   // most halo rows of one strip
+    size_t lds_bytes = 0;
+    int grid = 0;
+};
+ListCfg make_list_cfg(int radius, int tw, int hl, int vec, int nw, int list_cap);
+// Picks the launch shape for radius R that fits `max_lds` bytes of LDS.
+ListCfg pick_list_cfg(int radius, size_t max_lds);
+hipError_t launch_phi_copies(float *tab, const ListCfg &c, double k, double alpha,
+                             hipStream_t st);
+hipError_t launch_field_list(const ListCfg &c, const unsigned long long *bits, int wpr,
+                             const float *tab, const float *S, float *P, int W, int H,
+                             hipStream_t st);
+hipError_t set_field_list_lds_limit(size_t bytes);
 
 // Launchers: all enqueue on `st` and return the launch status.
 hipError_t launch_fill_u64(unsigned long long *p, size_t n, unsigned long long v, hipStream_t st);
@@ -71,12 +103,9 @@ hipError_t launch_bfs_levels(const uint8_t *obst, int32_t *D, int32_t *fa, int32
                              int grid, hipStream_t st);
 hipError_t launch_count_unreachable(const uint8_t *obst, const int32_t *D, int n,
                                     unsigned long long *ctr, hipStream_t st);
-hipError_t launch_superpose_f32(const SupCfg &c, const unsigned long long *bits, int wpr,
-                                const float *tab, const float *S, float *P, int W, int H,
-                                hipStream_t st);
 hipError_t launch_superpose_f64(const SupCfg &c, const unsigned long long *bits, int wpr,
                                 const double *tab, double *out, int W, int H, hipStream_t st);
-hipError_t set_superpose_lds_limits(size_t f32_bytes, size_t f64_bytes);
+hipError_t set_superpose_lds_limit(size_t f64_bytes);
 hipError_t launch_static_S(const int32_t *D, const double *O, const uint8_t *obst,
                            double w_dest, float *S, int n, hipStream_t st);
 hipError_t launch_occ_init(const int32_t *pos, int N, unsigned long long *occ, int wpr, int W,

@@ -343,6 +343,252 @@ __global__ __launch_bounds__(kSupThreads) void k_superpose(
     }
 }
 
+// ---- per-tick field: source-list gather ---------------------------------------------
+//
+// One workgroup per TW-column strip of NW*TH rows (persistent over strips).
+//  1. thread t loads the bitmap words of halo row ya + t and counts its sources;
+//  2. a block-wide exclusive scan turns the counts into list offsets, so the
+//     list holds the strip's halo sources in global row-major order;
+//  3. each thread writes its row's entries: an entry is the byte offset that
+//     turns a lane's base address into the address of table entry
+//     (lane su - source) in the aligned copy for the source's row;
+//  4. each wave walks the contiguous part of the list that lies within R rows
+//     of its own rows: per source one address add, HL/VEC aligned LDS vector
+//     loads and HL adds per lane.
+// A halo with more than list_cap - max_row sources is processed in several
+// passes over consecutive row ranges, which keeps the row-major order.
+
+template <int VEC>
+struct VecOf;
+template <>
+struct VecOf<2> {
+    typedef float type __attribute__((ext_vector_type(2)));
+};
+template <>
+struct VecOf<4> {
+    typedef float type __attribute__((ext_vector_type(4)));
+};
+
+__device__ __forceinline__ int wave_incl_scan(int v)
+{
+    const int lane = (int)lane_id();
+    for (int d = 1; d < 64; d <<= 1) {
+        const int t = __shfl_up(v, d);
+        if (lane >= d) v += t;
+    }
+    return v;
+}
+
+// smallest r in [0, n] with a[r] >= v (a non-decreasing, a[n] >= v)
+__device__ __forceinline__ int lower_bound_lds(const int *a, int n, int v)
+{
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (a[mid] < v)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// acc[q] += table vector at LDS byte address a + q*G*sizeof(vec)
+template <int NQ, int G, typename V>
+__device__ __forceinline__ void gather_one(V *acc, int a)
+{
+    typedef const __attribute__((address_space(3))) V *ptr;
+    const ptr s = reinterpret_cast<ptr>((uint32_t)a);
+    V v[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) v[q] = s[q * G];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[q] += v[q];
+}
+
+template <int TW, int HL, int VEC, int NW>
+__global__ __launch_bounds__(NW * 64) void k_field_list(
+    const unsigned long long *__restrict__ bits, int wpr, const float *__restrict__ tab_g,
+    int copy_elems, int stride, int padx, int pady, int R, int list_cap, int max_row,
+    const float *__restrict__ S, float *__restrict__ P, int W, int H, int tiles_x, int n_tiles)
+{
+    constexpr int G = 64 / TW, TH = G * HL, WT = NW * TH, NT = NW * 64, NQ = HL / VEC;
+    typedef typename VecOf<VEC>::type vec_t;
+    typedef const __attribute__((address_space(3))) vec_t *lds_vec;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    __shared__ int wave_tot[NW];
+    float *tab = reinterpret_cast<float *>(lds_raw);
+    const int tab_elems = VEC * copy_elems;  // a multiple of 4
+    int *list = reinterpret_cast<int *>(tab + tab_elems);
+    int *row_excl = list + list_cap;
+    for (int i = threadIdx.x; i < tab_elems / 4; i += NT)
+        reinterpret_cast<float4 *>(tab)[i] = reinterpret_cast<const float4 *>(tab_g)[i];
+    __syncthreads();
+
+    const int tid = (int)threadIdx.x, lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int col = lane % TW, rg = lane / TW;
+    const int tbase = (int)(uint32_t)(uintptr_t)((lds_ptr<float>)tab);
+    const int cap = list_cap - max_row;
+
+    for (int t = (int)blockIdx.x; t < n_tiles; t += (int)gridDim.x) {
+        const int ty = t / tiles_x, tx = t - ty * tiles_x;
+        const int X0 = tx * TW, Y0 = ty * WT, y0w = Y0 + wv * TH;
+        const int ya = max(Y0 - R, 0), yb = min(Y0 + WT - 1 + R, H - 1);
+        const int nr = yb - ya + 1;
+        const int xa = max(X0 - R, 0), xb = min(X0 + TW - 1 + R, W - 1);
+        const int wa = xa >> 6, nwd = (xb >> 6) - wa + 1;
+        const unsigned long long ma = ~0ull << (xa & 63), mb = ~0ull >> (63 - (xb & 63));
+
+        // 1. this thread's halo row
+        unsigned long long m0 = 0, m1 = 0, m2 = 0;
+        if (tid < nr) {
+            const unsigned long long *row = bits + (size_t)(ya + tid) * wpr + wa;
+            m0 = row[0];
+            if (nwd > 1) m1 = row[1];
+            if (nwd > 2) m2 = row[2];
+        }
+        m0 &= ma;
+        if (nwd == 1) m0 &= mb;
+        if (nwd == 2) m1 &= mb;
+        if (nwd == 3) m2 &= mb;
+        const int cnt = __popcll(m0) + __popcll(m1) + __popcll(m2);
+
+        // 2. block exclusive scan of the row counts
+        const int incl = wave_incl_scan(cnt);
+        if (lane == 63) wave_tot[wv] = incl;
+        __syncthreads();
+        int before = 0, total = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            const int v = wave_tot[w];
+            before += w < wv ? v : 0;
+            total += v;
+        }
+        const int excl = before + incl - cnt;
+        if (tid < nr) row_excl[tid] = excl;
+        if (tid == 0) row_excl[nr] = total;
+        __syncthreads();
+
+        // this wave's halo rows (relative to ya) and per-lane base address
+        const int ra = max(y0w - R, ya) - ya;
+        const int rb = min(y0w + TH - 1 + R, yb) - ya;
+        const int lb = opaque_lane(tbase + ((X0 + col + padx) * stride + (y0w + rg * VEC + pady)) * 4);
+        vec_t acc[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) acc[q] = (vec_t)(0.0f);
+
+        const int npass = (total + cap - 1) / cap;
+        for (int k = 0; k < npass; ++k) {
+            int start = 0, end = total;
+            if (npass > 1) {
+                start = row_excl[lower_bound_lds(row_excl, nr, k * cap)];
+                if (k + 1 < npass) end = row_excl[lower_bound_lds(row_excl, nr, (k + 1) * cap)];
+            }
+            // 3. entries of the rows in this pass
+            if (tid < nr && cnt > 0 && excl >= start && excl < end) {
+                const int py = ya + tid;
+                const int c = (py - pady) & (VEC - 1);
+                const int rowterm = c * copy_elems * 4 - (py - c) * 4;
+                int o = excl - start;
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    unsigned long long mj = j == 0 ? m0 : (j == 1 ? m1 : m2);
+                    const int xw = (wa + j) * 64;
+                    while (mj) {
+                        const int b = __builtin_ctzll(mj);
+                        mj &= mj - 1ull;
+                        list[o++] = rowterm - (xw + b) * stride * 4;
+                    }
+                }
+            }
+            __syncthreads();
+            // 4. gather: list entries are read four at a time (one broadcast
+            // LDS load), each source costs one address add per lane
+            if (ra <= rb) {
+                const int lo = __builtin_amdgcn_readfirstlane(max(row_excl[ra], start) - start);
+                const int hi = __builtin_amdgcn_readfirstlane(min(row_excl[rb + 1], end) - start);
+                int i = lo;
+                for (; i < hi && (i & 3); ++i) gather_one<NQ, G>(acc, lb + list[i]);
+                const int4 *list4 = reinterpret_cast<const int4 *>(list);
+                // eight sources per round: both entry groups are read first, then
+                // eight table reads are in flight before the adds
+                for (; i + 8 <= hi; i += 8) {
+                    const int4 ea = list4[i >> 2];
+                    const int4 eb = list4[(i >> 2) + 1];
+                    const int a[8] = {ea.x, ea.y, ea.z, ea.w, eb.x, eb.y, eb.z, eb.w};
+                    vec_t v[8][NQ];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const lds_vec sp = reinterpret_cast<lds_vec>((uint32_t)(lb + a[u]));
+#pragma unroll
+                        for (int q = 0; q < NQ; ++q) v[u][q] = sp[q * G];
+                    }
+                    // row-major source order per accumulator
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+#pragma unroll
+                        for (int q = 0; q < NQ; ++q) acc[q] += v[u][q];
+                    }
+                }
+                if (i + 4 <= hi) {
+                    const int4 ea = list4[i >> 2];
+                    const int a[4] = {ea.x, ea.y, ea.z, ea.w};
+                    vec_t v[4][NQ];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const lds_vec sp = reinterpret_cast<lds_vec>((uint32_t)(lb + a[u]));
+#pragma unroll
+                        for (int q = 0; q < NQ; ++q) v[u][q] = sp[q * G];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+#pragma unroll
+                        for (int q = 0; q < NQ; ++q) acc[q] += v[u][q];
+                    }
+                    i += 4;
+                }
+                for (; i < hi; ++i) gather_one<NQ, G>(acc, lb + list[i]);
+            }
+            __syncthreads();
+        }
+
+        // 5. P = S + Phi for this lane's su
+        const int x = X0 + col;
+        if (x < W) {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+#pragma unroll
+                for (int j = 0; j < VEC; ++j) {
+                    const int y = y0w + (q * G + rg) * VEC + j;
+                    if (y < H) {
+                        const size_t c = (size_t)y * W + x;
+                        P[c] = S[c] + acc[q][j];
+                    }
+                }
+            }
+        }
+        __syncthreads();  // wave_tot and row_excl are rewritten by the next strip
+    }
+}
+
+// Stamp copies for the source-list gather (see ListCfg): copy c holds
+// phi(dx, dy) at (dx + padx)*stride + (dy + pady + c); FP64 value rounded once.
+__global__ void k_phi_copies(float *tab, int vec, int ncols, int stride, int padx, int pady,
+                             int R, double k, double alpha)
+{
+    const int copy = ncols * stride;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= vec * copy) return;
+    const int c = i / copy, rem = i - c * copy;
+    const int ci = rem / stride, ri = rem - ci * stride;
+    const int dx = ci - padx, dy = ri - c - pady;
+    double v = 0.0;
+    if (abs(dx) <= R && abs(dy) <= R && (dx != 0 || dy != 0))
+        v = k * pow(sqrt((double)dx * dx + (double)dy * dy), alpha);
+    tab[i] = (float)v;
+}
+
 // ---- occupancy ----------------------------------------------------------------------
 
 __global__ void k_occ_init(const int32_t *__restrict__ pos, int N, unsigned long long *occ, int wpr,
@@ -532,20 +778,6 @@ hipError_t sup_launch(const SupCfg &c, const unsigned long long *bits, int wpr, 
 
 // ---- launch configuration -------------------------------------------------------------
 
-void pick_sup_shape(int radius, int *tw, int *hl)
-{
-    if (radius <= 8) {
-        *tw = 8;
-        *hl = 1;
-    } else if (radius <= 24) {
-        *tw = 16;
-        *hl = 2;
-    } else {
-        *tw = 16;
-        *hl = 4;
-    }
-}
-
 SupCfg make_sup_cfg(int radius, int tw, int hl, size_t elem)
 {
     SupCfg c;
@@ -640,31 +872,142 @@ hipError_t launch_count_unreachable(const uint8_t *obst, const int32_t *D, int n
     return hipGetLastError();
 }
 
-hipError_t set_superpose_lds_limits(size_t f32_bytes, size_t f64_bytes)
+hipError_t set_superpose_lds_limit(size_t f64_bytes)
 {
-    hipError_t e = hipSuccess;
-    const void *f32s[] = {
-        reinterpret_cast<const void *>(&k_superpose<float, 8, 1, true>),
-        reinterpret_cast<const void *>(&k_superpose<float, 16, 2, true>),
-        reinterpret_cast<const void *>(&k_superpose<float, 16, 4, true>)};
-    for (const void *f : f32s) {
-        e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)f32_bytes);
-        if (e != hipSuccess) return e;
-    }
     return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_superpose<double, 8, 1, false>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)f64_bytes);
 }
 
-hipError_t launch_superpose_f32(const SupCfg &c, const unsigned long long *bits, int wpr,
-                                const float *tab, const float *S, float *P, int W, int H,
-                                hipStream_t st)
+// ---- source-list gather: configuration and launch ------------------------------------
+
+namespace {
+
+// Most lanes of one LDS vector read that share a bank, for lane l at column
+// l % tw, row group l / tw, dword address col*stride + rg*vec (+ the vec dwords).
+// The LDS serves 256 bytes per clock: 256 / (4*vec) lanes per pass.
+int bank_degree(int tw, int vec, int stride)
 {
-    if (c.tw == 8 && c.hl == 1)
-        return sup_launch<float, 8, 1, true>(c, bits, wpr, tab, S, nullptr, P, W, H, st);
-    if (c.tw == 16 && c.hl == 2)
-        return sup_launch<float, 16, 2, true>(c, bits, wpr, tab, S, nullptr, P, W, H, st);
-    if (c.tw == 16 && c.hl == 4)
-        return sup_launch<float, 16, 4, true>(c, bits, wpr, tab, S, nullptr, P, W, H, st);
+    const int lanes = 256 / (4 * vec);
+    int worst = 0;
+    for (int p = 0; p < 64; p += lanes) {
+        int hits[64] = {0};
+        for (int l = p; l < p + lanes && l < 64; ++l) {
+            const int col = l % tw, rg = l / tw;
+            const int a = col * stride + rg * vec;
+            for (int j = 0; j < vec; ++j) ++hits[(a + j) % 64];
+        }
+        for (int b = 0; b < 64; ++b) worst = hits[b] > worst ? hits[b] : worst;
+    }
+    return worst;
+}
+
+}  // namespace
+
+ListCfg make_list_cfg(int radius, int tw, int hl, int vec, int nw, int list_cap)
+{
+    ListCfg c;
+    c.tw = tw;
+    c.hl = hl;
+    c.vec = vec;
+    c.nw = nw;
+    c.g = 64 / tw;
+    c.th = c.g * hl;
+    c.wt = nw * c.th;
+    c.radius = radius;
+    c.padx = radius + tw;
+    c.pady = radius + c.th - 1;
+    c.ncols = 2 * c.padx + 1;
+    c.nrows = 2 * c.pady + 1;
+    const int min_s = c.nrows + vec - 1;
+    int best = -1, best_deg = 1 << 30;
+    for (int s = min_s; s < min_s + 64; ++s) {
+        if (s % 4 != 0) continue;  // copies stay 16-byte aligned
+        const int d = bank_degree(tw, vec, s);
+        if (d < best_deg) {
+            best_deg = d;
+            best = s;
+        }
+        if (d == 1) break;
+    }
+    c.stride = best;
+    c.copy_elems = c.ncols * c.stride;
+    c.max_row = tw + 2 * radius;
+    c.halo_rows = c.wt + 2 * radius;
+    c.list_cap = list_cap;
+    c.lds_bytes = (size_t)vec * c.copy_elems * 4 + (size_t)list_cap * 4 + (size_t)(c.halo_rows + 1) * 4;
+    return c;
+}
+
+ListCfg pick_list_cfg(int radius, size_t max_lds)
+{
+    // (TW, HL, VEC, NW) by radius, then smaller variants if LDS is short
+    const int shapes[][4] = {{16, 2, 2, 4}, {16, 4, 4, 4}, {16, 4, 2, 8}, {16, 4, 2, 4}, {16, 2, 2, 4}};
+    int first = radius <= 8 ? 0 : (radius <= 24 ? 1 : 2);
+    ListCfg c;
+    for (int i = first; i < 5; ++i) {
+        const int *sh = shapes[i];
+        for (int cap = 4096; cap >= 512; cap /= 2) {
+            ListCfg t = make_list_cfg(radius, sh[0], sh[1], sh[2], sh[3], cap);
+            if (cap < 2 * t.max_row || t.halo_rows > 64 * sh[3]) break;
+            // prefer two workgroups per CU when the shape allows it
+            if (t.lds_bytes <= max_lds / 2 || (sh[3] == 8 && t.lds_bytes <= max_lds)) return t;
+            c = t;
+        }
+        if (c.lds_bytes && c.lds_bytes <= max_lds && c.list_cap >= 2 * c.max_row) return c;
+    }
+    return c;
+}
+
+hipError_t launch_phi_copies(float *tab, const ListCfg &c, double k, double alpha, hipStream_t st)
+{
+    const int n = c.vec * c.copy_elems;
+    hipLaunchKernelGGL(k_phi_copies, dim3(blocks_for(n, 256)), dim3(256), 0, st, tab, c.vec, c.ncols,
+                       c.stride, c.padx, c.pady, c.radius, k, alpha);
+    return hipGetLastError();
+}
+
+namespace {
+
+template <int TW, int HL, int VEC, int NW>
+hipError_t field_list_launch(const ListCfg &c, const unsigned long long *bits, int wpr,
+                             const float *tab, const float *S, float *P, int W, int H,
+                             hipStream_t st)
+{
+    constexpr int WT = NW * (64 / TW) * HL;
+    const int tiles_x = (W + TW - 1) / TW, tiles_y = (H + WT - 1) / WT;
+    const int n_tiles = tiles_x * tiles_y;
+    const int grid = n_tiles < c.grid ? n_tiles : c.grid;
+    hipLaunchKernelGGL((k_field_list<TW, HL, VEC, NW>), dim3(grid > 0 ? grid : 1), dim3(NW * 64),
+                       c.lds_bytes, st, bits, wpr, tab, c.copy_elems, c.stride, c.padx, c.pady,
+                       c.radius, c.list_cap, c.max_row, S, P, W, H, tiles_x, n_tiles);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+#define SF_LIST_SHAPES(X) X(16, 2, 2, 4) X(16, 4, 4, 4) X(16, 4, 2, 8) X(16, 4, 2, 4) X(16, 4, 4, 8) X(16, 2, 2, 8)
+
+hipError_t set_field_list_lds_limit(size_t bytes)
+{
+    hipError_t e = hipSuccess;
+#define SF_SET(a, b, v, n)                                                                        \
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_field_list<a, b, v, n>),         \
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);          \
+    if (e != hipSuccess) return e;
+    SF_LIST_SHAPES(SF_SET)
+#undef SF_SET
+    return e;
+}
+
+hipError_t launch_field_list(const ListCfg &c, const unsigned long long *bits, int wpr,
+                             const float *tab, const float *S, float *P, int W, int H,
+                             hipStream_t st)
+{
+#define SF_DISPATCH(a, b, v, n)                                                                   \
+    if (c.tw == a && c.hl == b && c.vec == v && c.nw == n)                                      \
+        return field_list_launch<a, b, v, n>(c, bits, wpr, tab, S, P, W, H, st);
+    SF_LIST_SHAPES(SF_DISPATCH)
+#undef SF_DISPATCH
     return hipErrorInvalidValue;
 }
 

@@ -107,6 +107,14 @@ def test_small_scenes_lockstep(sf, W, H, N, R, seed, extra):
     _run_lockstep(sf, sc, 25)
 
 
+def test_dense_crowd_multipass_lockstep(sf):
+    # 60% of the free su occupied with R = 32: a strip's halo holds more sources
+    # than one list pass, so the gather runs several passes per strip
+    sc = scenes.random_scene(150, 140, n_peds=0, radius=32, seed=12, bernoulli=0.02,
+                             exits=("E", "W"), exit_width=6, occupancy=0.6)
+    _run_lockstep(sf, sc, 12)
+
+
 def test_hall1024_lockstep_sampled(sf):
     # the benchmark workload at full size, same launch configuration
     sc = scenes.hall1024()
@@ -178,7 +186,7 @@ def test_tile_shape_invariance(sf, monkeypatch):
     # wave-tile shape bit for bit (Eq. 1: any partition of the sum)
     sc = scenes.random_scene(130, 90, n_peds=1500, radius=7, seed=33, bernoulli=0.03)
     fields = []
-    for shape in ("8x1", "16x2", "16x4"):
+    for shape in ("16x2x2x4", "16x4x4x4", "16x4x2x8", "16x4x2x4", "16x2x2x8"):
         monkeypatch.setenv("SF_TILE", shape)
         with sf.GpuScene(sc) as g:
             g.step(5)
