@@ -103,7 +103,21 @@ def main():
     ap.add_argument("--workload", default="hall1024", choices=["hall1024", "room64", "plaza8192"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only run a plain device-to-device copy of this many MiB (HBM "
+                         "counter calibration under rocprofv3) and exit")
     args = ap.parse_args()
+    if args.copy_probe_mib:
+        import torch
+
+        n = args.copy_probe_mib * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": n * 4, "launches": 3}))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
               "path is a design, not part of this build", file=sys.stderr)

@@ -348,13 +348,13 @@ int create(const sf_scene_desc *d, void *hip_stream, sf_scene **out)
     if (const char *e = std::getenv("SF_TILE")) {
         // launch-shape override "TWxHLxVECxNW"; the field does not depend on it
         // bit for bit, the speed does
-        int a = 0, b = 0, v = 0, w = 0;
-        if (std::sscanf(e, "%dx%dx%dx%d", &a, &b, &v, &w) != 4)
-            return fail(SF_EINVAL, "SF_TILE=%s is not of the form TWxHLxVECxNW", e);
-        s->lc = sf::make_list_cfg(s->R, a, b, v, w, 2048);
-        const bool known = (a == 16 && b == 2 && v == 2 && (w == 4 || w == 8)) ||
-                           (a == 16 && b == 4 && (v == 2 || v == 4) && (w == 4 || w == 8));
-        if (!known || s->lc.halo_rows > 64 * w)
+        int a = 0, b = 0, v = 0, w = 0, mode = 1;
+        const int got = std::sscanf(e, "%dx%dx%dx%dx%d", &a, &b, &v, &w, &mode);
+        if (got != 4 && got != 5)
+            return fail(SF_EINVAL, "SF_TILE=%s is not of the form TWxHLxVECxNW[xMODE]", e);
+        s->lc = sf::make_list_cfg(s->R, a, b, v, w, mode ? 512 : 2048, mode != 0);
+        const bool known = sf::list_shape_compiled(a, b, v, w);
+        if (!known || s->lc.halo_rows > (mode ? 3 * 64 : 64 * w))
             return fail(SF_EINVAL, "SF_TILE=%s is not a compiled shape for radius %d", e, s->R);
     }
     if (s->lc.lds_bytes == 0 || s->lc.lds_bytes > (size_t)max_lds - 1024 ||

@@ -54,8 +54,9 @@ SupCfg make_sup_cfg(int radius, int tw, int hl, size_t elem);
 // Launch shape of the per-tick FP32 field kernel (source-list gather).
 // A workgroup of NW waves covers a TW-column strip of NW*TH rows; wave w owns
 // rows [w*TH, (w+1)*TH).  Lane l owns column l % TW and, with rg = l / TW and
-// G = 64 / TW, the rows (q*G + rg)*VEC + j for q < HL/VEC, j < VEC, so each of
-// its HL/VEC table reads is one aligned VEC-wide LDS load.  The stamp is kept
+// G = 64 / TW, the HL consecutive rows rg*HL .. rg*HL + HL-1, so its slice of
+// a source's stamp column is HL contiguous floats read as HL/VEC aligned
+// VEC-wide LDS loads (one contiguous access per lane).  The stamp is kept
 // in VEC copies, copy c shifted down by c rows, so that a source at row py
 // reads copy (py - pady) mod VEC aligned:
 //   copy c, entry (dx, dy) at c*ncols*stride + (dx + padx)*stride + dy + pady + c
@@ -71,11 +72,13 @@ struct ListCfg {
     int copy_elems = 0;  // ncols * stride
     int list_cap = 0;
     int max_row = 0;     // most sources one halo row can hold
-    int halo_rows = 0;   // most halo rows of one strip
+    int halo_rows = 0;   // most halo rows of one strip (one wave tile in wave mode)
+    bool wave_lists = false;  // wave-private lists (k_field_wave) instead of one per strip
     size_t lds_bytes = 0;
     int grid = 0;
 };
-ListCfg make_list_cfg(int radius, int tw, int hl, int vec, int nw, int list_cap);
+ListCfg make_list_cfg(int radius, int tw, int hl, int vec, int nw, int list_cap,
+                      bool wave_lists);
 // Picks the launch shape for radius R that fits `max_lds` bytes of LDS.
 ListCfg pick_list_cfg(int radius, size_t max_lds);
 hipError_t launch_phi_copies(float *tab, const ListCfg &c, double k, double alpha,
@@ -84,6 +87,7 @@ hipError_t launch_field_list(const ListCfg &c, const unsigned long long *bits, i
                              const float *tab, const float *S, float *P, int W, int H,
                              hipStream_t st);
 hipError_t set_field_list_lds_limit(size_t bytes);
+bool list_shape_compiled(int tw, int hl, int vec, int nw);
 
 // Launchers: all enqueue on `st` and return the launch status.
 hipError_t launch_fill_u64(unsigned long long *p, size_t n, unsigned long long v, hipStream_t st);

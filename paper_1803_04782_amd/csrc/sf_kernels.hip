@@ -393,15 +393,15 @@ __device__ __forceinline__ int lower_bound_lds(const int *a, int n, int v)
     return lo;
 }
 
-// acc[q] += table vector at LDS byte address a + q*G*sizeof(vec)
-template <int NQ, int G, typename V>
+// acc[q] += table vector at LDS byte address a + q*sizeof(vec)
+template <int NQ, typename V>
 __device__ __forceinline__ void gather_one(V *acc, int a)
 {
     typedef const __attribute__((address_space(3))) V *ptr;
     const ptr s = reinterpret_cast<ptr>((uint32_t)a);
     V v[NQ];
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) v[q] = s[q * G];
+    for (int q = 0; q < NQ; ++q) v[q] = s[q];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) acc[q] += v[q];
 }
@@ -431,28 +431,69 @@ __global__ __launch_bounds__(NW * 64) void k_field_list(
     const int tbase = (int)(uint32_t)(uintptr_t)((lds_ptr<float>)tab);
     const int cap = list_cap - max_row;
 
-    for (int t = (int)blockIdx.x; t < n_tiles; t += (int)gridDim.x) {
+    // Strip geometry: halo rows [ya, ya + nr), halo bitmap words [wa, wa + nwd).
+    struct Strip {
+        int X0, Y0, ya, nr, xa, xb, wa, nwd;
+    };
+    auto strip = [&](int t) {
+        Strip g;
         const int ty = t / tiles_x, tx = t - ty * tiles_x;
-        const int X0 = tx * TW, Y0 = ty * WT, y0w = Y0 + wv * TH;
-        const int ya = max(Y0 - R, 0), yb = min(Y0 + WT - 1 + R, H - 1);
-        const int nr = yb - ya + 1;
-        const int xa = max(X0 - R, 0), xb = min(X0 + TW - 1 + R, W - 1);
-        const int wa = xa >> 6, nwd = (xb >> 6) - wa + 1;
+        g.X0 = tx * TW;
+        g.Y0 = ty * WT;
+        g.ya = max(g.Y0 - R, 0);
+        g.nr = min(g.Y0 + WT - 1 + R, H - 1) - g.ya + 1;
+        g.xa = max(g.X0 - R, 0);
+        g.xb = min(g.X0 + TW - 1 + R, W - 1);
+        g.wa = g.xa >> 6;
+        g.nwd = (g.xb >> 6) - g.wa + 1;
+        return g;
+    };
+    // bitmap words of this thread's halo row of strip t (issued early: the
+    // loads stay in flight across the previous strip's work)
+    unsigned long long n0 = 0, n1 = 0, n2 = 0;
+    auto fetch_rows = [&](int t) {
+        n0 = n1 = n2 = 0;
+        if (t >= n_tiles) return;
+        const Strip g = strip(t);
+        if (tid < g.nr) {
+            const unsigned long long *row = bits + (size_t)(g.ya + tid) * wpr + g.wa;
+            n0 = row[0];
+            if (g.nwd > 1) n1 = row[1];
+            if (g.nwd > 2) n2 = row[2];
+        }
+    };
+    fetch_rows((int)blockIdx.x);
+
+    for (int t = (int)blockIdx.x; t < n_tiles; t += (int)gridDim.x) {
+        const Strip g = strip(t);
+        const int X0 = g.X0, Y0 = g.Y0, y0w = Y0 + wv * TH;
+        const int ya = g.ya, nr = g.nr, xa = g.xa, xb = g.xb, wa = g.wa, nwd = g.nwd;
+        const int yb = ya + nr - 1;
         const unsigned long long ma = ~0ull << (xa & 63), mb = ~0ull >> (63 - (xb & 63));
 
         // 1. this thread's halo row
-        unsigned long long m0 = 0, m1 = 0, m2 = 0;
-        if (tid < nr) {
-            const unsigned long long *row = bits + (size_t)(ya + tid) * wpr + wa;
-            m0 = row[0];
-            if (nwd > 1) m1 = row[1];
-            if (nwd > 2) m2 = row[2];
-        }
+        unsigned long long m0 = n0, m1 = n1, m2 = n2;
         m0 &= ma;
         if (nwd == 1) m0 &= mb;
         if (nwd == 2) m1 &= mb;
         if (nwd == 3) m2 &= mb;
         const int cnt = __popcll(m0) + __popcll(m1) + __popcll(m2);
+        // keep the loads below after the use of the prefetched words, so that
+        // the wait for those does not also wait for the new requests
+        asm volatile("" ::"v"(cnt) : "memory");
+        // S of this lane's su and the next strip's halo rows are requested now
+        // and arrive while this strip is gathered
+        const int x = X0 + col;
+        float sv[HL];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+#pragma unroll
+            for (int j = 0; j < VEC; ++j) {
+                const int y = y0w + rg * HL + q * VEC + j;
+                sv[q * VEC + j] = (x < W && y < H) ? S[(size_t)y * W + x] : 0.0f;
+            }
+        }
+        fetch_rows(t + (int)gridDim.x);
 
         // 2. block exclusive scan of the row counts
         const int incl = wave_incl_scan(cnt);
@@ -473,7 +514,7 @@ __global__ __launch_bounds__(NW * 64) void k_field_list(
         // this wave's halo rows (relative to ya) and per-lane base address
         const int ra = max(y0w - R, ya) - ya;
         const int rb = min(y0w + TH - 1 + R, yb) - ya;
-        const int lb = opaque_lane(tbase + ((X0 + col + padx) * stride + (y0w + rg * VEC + pady)) * 4);
+        const int lb = opaque_lane(tbase + ((X0 + col + padx) * stride + (y0w + rg * HL + pady)) * 4);
         vec_t acc[NQ];
 #pragma unroll
         for (int q = 0; q < NQ; ++q) acc[q] = (vec_t)(0.0f);
@@ -509,7 +550,7 @@ __global__ __launch_bounds__(NW * 64) void k_field_list(
                 const int lo = __builtin_amdgcn_readfirstlane(max(row_excl[ra], start) - start);
                 const int hi = __builtin_amdgcn_readfirstlane(min(row_excl[rb + 1], end) - start);
                 int i = lo;
-                for (; i < hi && (i & 3); ++i) gather_one<NQ, G>(acc, lb + list[i]);
+                for (; i < hi && (i & 3); ++i) gather_one<NQ>(acc, lb + list[i]);
                 const int4 *list4 = reinterpret_cast<const int4 *>(list);
                 // eight sources per round: both entry groups are read first, then
                 // eight table reads are in flight before the adds
@@ -522,7 +563,7 @@ __global__ __launch_bounds__(NW * 64) void k_field_list(
                     for (int u = 0; u < 8; ++u) {
                         const lds_vec sp = reinterpret_cast<lds_vec>((uint32_t)(lb + a[u]));
 #pragma unroll
-                        for (int q = 0; q < NQ; ++q) v[u][q] = sp[q * G];
+                        for (int q = 0; q < NQ; ++q) v[u][q] = sp[q];
                     }
                     // row-major source order per accumulator
 #pragma unroll
@@ -539,7 +580,7 @@ __global__ __launch_bounds__(NW * 64) void k_field_list(
                     for (int u = 0; u < 4; ++u) {
                         const lds_vec sp = reinterpret_cast<lds_vec>((uint32_t)(lb + a[u]));
 #pragma unroll
-                        for (int q = 0; q < NQ; ++q) v[u][q] = sp[q * G];
+                        for (int q = 0; q < NQ; ++q) v[u][q] = sp[q];
                     }
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
@@ -548,23 +589,19 @@ __global__ __launch_bounds__(NW * 64) void k_field_list(
                     }
                     i += 4;
                 }
-                for (; i < hi; ++i) gather_one<NQ, G>(acc, lb + list[i]);
+                for (; i < hi; ++i) gather_one<NQ>(acc, lb + list[i]);
             }
             __syncthreads();
         }
 
         // 5. P = S + Phi for this lane's su
-        const int x = X0 + col;
         if (x < W) {
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
 #pragma unroll
                 for (int j = 0; j < VEC; ++j) {
-                    const int y = y0w + (q * G + rg) * VEC + j;
-                    if (y < H) {
-                        const size_t c = (size_t)y * W + x;
-                        P[c] = S[c] + acc[q][j];
-                    }
+                    const int y = y0w + rg * HL + q * VEC + j;
+                    if (y < H) P[(size_t)y * W + x] = sv[q * VEC + j] + acc[q][j];
                 }
             }
         }
@@ -572,20 +609,224 @@ __global__ __launch_bounds__(NW * 64) void k_field_list(
     }
 }
 
+// ---- per-tick field, wave-private source lists ----------------------------------------
+//
+// Same table, entries and gather as k_field_list, but every wave lists the
+// sources of its own TW x TH tile's halo, so waves never wait for each other:
+// lane i holds halo rows i, 64 + i and 128 + i; the row counts are prefix-summed
+// with ballots (no LDS traffic); entries go to a wave-private LDS list of `cap`
+// entries (several passes when a dense halo overflows it).
+
+// Exclusive prefix sum over the lanes of a wave of counts in [0, 255], and the
+// wave total, from eight ballots.
+__device__ __forceinline__ int wave_excl_small(int cnt, int &total)
+{
+    int excl = 0, tot = 0;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        const unsigned long long m = __ballot((cnt >> b) & 1);
+        const int below = (int)__builtin_amdgcn_mbcnt_hi(
+            (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+        excl += below << b;
+        tot += __popcll(m) << b;
+    }
+    total = tot;
+    return excl;
+}
+
+template <int TW, int HL, int VEC, int NW>
+__global__ __launch_bounds__(NW * 64) void k_field_wave(
+    const unsigned long long *__restrict__ bits, int wpr, const float *__restrict__ tab_g,
+    int copy_elems, int stride, int padx, int pady, int R, int cap, int max_row,
+    const float *__restrict__ S, float *__restrict__ P, int W, int H, int tiles_x, int n_tiles)
+{
+    constexpr int G = 64 / TW, TH = G * HL, NQ = HL / VEC, NS = 3;
+    typedef typename VecOf<VEC>::type vec_t;
+    typedef const __attribute__((address_space(3))) vec_t *lds_vec;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    float *tab = reinterpret_cast<float *>(lds_raw);
+    const int tab_elems = VEC * copy_elems;  // a multiple of 4
+    for (int i = threadIdx.x; i < tab_elems / 4; i += NW * 64)
+        reinterpret_cast<float4 *>(tab)[i] = reinterpret_cast<const float4 *>(tab_g)[i];
+    __syncthreads();
+
+    const int tid = (int)threadIdx.x, lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    int *list = reinterpret_cast<int *>(tab + tab_elems) + wv * cap;  // cap: a multiple of 4
+    const int col = lane % TW, rg = lane / TW;
+    const int tbase = (int)(uint32_t)(uintptr_t)((lds_ptr<float>)tab);
+    const int capp = cap - max_row;
+    const int t0 = __builtin_amdgcn_readfirstlane((int)blockIdx.x * NW + wv);
+    const int tstep = __builtin_amdgcn_readfirstlane((int)gridDim.x * NW);
+
+    struct Tile {
+        int X0, Y0, ya, nr, xa, xb, wa, nwd;
+    };
+    auto tile = [&](int t) {
+        Tile g;
+        const int ty = t / tiles_x, tx = t - ty * tiles_x;
+        g.X0 = tx * TW;
+        g.Y0 = ty * TH;
+        g.ya = max(g.Y0 - R, 0);
+        g.nr = min(g.Y0 + TH - 1 + R, H - 1) - g.ya + 1;
+        g.xa = max(g.X0 - R, 0);
+        g.xb = min(g.X0 + TW - 1 + R, W - 1);
+        g.wa = g.xa >> 6;
+        g.nwd = (g.xb >> 6) - g.wa + 1;
+        return g;
+    };
+    unsigned long long n[NS][3];
+    auto fetch = [&](int t) {
+#pragma unroll
+        for (int sl = 0; sl < NS; ++sl) n[sl][0] = n[sl][1] = n[sl][2] = 0;
+        if (t >= n_tiles) return;
+        const Tile g = tile(t);
+#pragma unroll
+        for (int sl = 0; sl < NS; ++sl) {
+            const int r = 64 * sl + lane;
+            if (r < g.nr) {
+                const unsigned long long *row = bits + (size_t)(g.ya + r) * wpr + g.wa;
+                n[sl][0] = row[0];
+                if (g.nwd > 1) n[sl][1] = row[1];
+                if (g.nwd > 2) n[sl][2] = row[2];
+            }
+        }
+    };
+    fetch(t0);
+
+    for (int t = t0; t < n_tiles; t += tstep) {
+        const Tile g = tile(t);
+        const int X0 = g.X0, y0 = g.Y0, ya = g.ya, wa = g.wa, nwd = g.nwd;
+        const unsigned long long ma = ~0ull << (g.xa & 63), mb = ~0ull >> (63 - (g.xb & 63));
+        unsigned long long m[NS][3];
+        int cnt[NS];
+#pragma unroll
+        for (int sl = 0; sl < NS; ++sl) {
+            m[sl][0] = n[sl][0] & ma;
+            m[sl][1] = n[sl][1];
+            m[sl][2] = n[sl][2];
+            if (nwd == 1) m[sl][0] &= mb;
+            if (nwd == 2) m[sl][1] &= mb;
+            if (nwd == 3) m[sl][2] &= mb;
+            cnt[sl] = __popcll(m[sl][0]) + __popcll(m[sl][1]) + __popcll(m[sl][2]);
+        }
+        // the prefetched words are consumed before new loads are issued
+        asm volatile("" ::"v"(cnt[0]), "v"(cnt[1]), "v"(cnt[2]) : "memory");
+        const int x = X0 + col;
+        float sv[HL];
+#pragma unroll
+        for (int r = 0; r < HL; ++r) {
+            const int y = y0 + rg * HL + r;
+            sv[r] = (x < W && y < H) ? S[(size_t)y * W + x] : 0.0f;
+        }
+        fetch(t + tstep);
+
+        // row-major prefix of the halo row counts
+        int excl[NS], total = 0;
+#pragma unroll
+        for (int sl = 0; sl < NS; ++sl) {
+            int tot;
+            const int e = wave_excl_small(cnt[sl], tot);
+            excl[sl] = total + e;
+            total += tot;
+        }
+        // first row start at or after v (row order: slot-major, then lane)
+        auto first_at_least = [&](int v) {
+#pragma unroll
+            for (int sl = 0; sl < NS; ++sl) {
+                const unsigned long long b = __ballot(excl[sl] >= v);
+                if (b) return __builtin_amdgcn_readlane(excl[sl], __builtin_ctzll(b));
+            }
+            return total;
+        };
+
+        const int lb = opaque_lane(tbase + ((X0 + col + padx) * stride + (y0 + rg * HL + pady)) * 4);
+        vec_t acc[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) acc[q] = (vec_t)(0.0f);
+        const int npass = (total + capp - 1) / capp;
+        for (int pass = 0; pass < npass; ++pass) {
+            int sp = 0, ep = total;
+            if (npass > 1) {
+                sp = first_at_least(pass * capp);
+                if (pass + 1 < npass) ep = first_at_least((pass + 1) * capp);
+            }
+#pragma unroll
+            for (int sl = 0; sl < NS; ++sl) {
+                if (cnt[sl] > 0 && excl[sl] >= sp && excl[sl] < ep) {
+                    const int py = ya + 64 * sl + lane;
+                    const int c = (py - pady) & (VEC - 1);
+                    const int rowterm = c * copy_elems * 4 - (py - c) * 4;
+                    int o = excl[sl] - sp;
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) {
+                        unsigned long long mj = m[sl][j];
+                        const int xw = (wa + j) * 64;
+                        while (mj) {
+                            const int b = __builtin_ctzll(mj);
+                            mj &= mj - 1ull;
+                            list[o++] = rowterm - (xw + b) * stride * 4;
+                        }
+                    }
+                }
+            }
+            // the list writes of all lanes complete before the wave reads them
+            __builtin_amdgcn_s_waitcnt(0xC07F);
+            asm volatile("" ::: "memory");
+            const int hi = ep - sp;
+            int i = 0;
+            const int4 *list4 = reinterpret_cast<const int4 *>(list);
+            for (; i + 8 <= hi; i += 8) {
+                const int4 ea = list4[i >> 2];
+                const int4 eb = list4[(i >> 2) + 1];
+                const int a[8] = {ea.x, ea.y, ea.z, ea.w, eb.x, eb.y, eb.z, eb.w};
+                vec_t v[8][NQ];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const lds_vec sp8 = reinterpret_cast<lds_vec>((uint32_t)(lb + a[u]));
+#pragma unroll
+                    for (int q = 0; q < NQ; ++q) v[u][q] = sp8[q];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+#pragma unroll
+                    for (int q = 0; q < NQ; ++q) acc[q] += v[u][q];
+                }
+            }
+            for (; i < hi; ++i) gather_one<NQ>(acc, lb + list[i]);
+            // this pass's reads precede the next pass's writes
+            asm volatile("" ::: "memory");
+        }
+
+        if (x < W) {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+#pragma unroll
+                for (int j = 0; j < VEC; ++j) {
+                    const int y = y0 + rg * HL + q * VEC + j;
+                    if (y < H) P[(size_t)y * W + x] = sv[q * VEC + j] + acc[q][j];
+                }
+            }
+        }
+    }
+}
+
 // Stamp copies for the source-list gather (see ListCfg): copy c holds
 // phi(dx, dy) at (dx + padx)*stride + (dy + pady + c); FP64 value rounded once.
-__global__ void k_phi_copies(float *tab, int vec, int ncols, int stride, int padx, int pady,
-                             int R, double k, double alpha)
+// (each copy occupies copy_elems >= ncols*stride floats; the tail is zero)
+__global__ void k_phi_copies(float *tab, int vec, int copy_elems, int ncols, int stride, int padx,
+                             int pady, int R, double k, double alpha)
 {
-    const int copy = ncols * stride;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= vec * copy) return;
-    const int c = i / copy, rem = i - c * copy;
-    const int ci = rem / stride, ri = rem - ci * stride;
-    const int dx = ci - padx, dy = ri - c - pady;
+    if (i >= vec * copy_elems) return;
+    const int c = i / copy_elems, rem = i - c * copy_elems;
     double v = 0.0;
-    if (abs(dx) <= R && abs(dy) <= R && (dx != 0 || dy != 0))
-        v = k * pow(sqrt((double)dx * dx + (double)dy * dy), alpha);
+    if (rem < ncols * stride) {
+        const int ci = rem / stride, ri = rem - ci * stride;
+        const int dx = ci - padx, dy = ri - c - pady;
+        if (abs(dx) <= R && abs(dy) <= R && (dx != 0 || dy != 0))
+            v = k * pow(sqrt((double)dx * dx + (double)dy * dy), alpha);
+    }
     tab[i] = (float)v;
 }
 
@@ -882,19 +1123,20 @@ hipError_t set_superpose_lds_limit(size_t f64_bytes)
 
 namespace {
 
-// Most lanes of one LDS vector read that share a bank, for lane l at column
-// l % tw, row group l / tw, dword address col*stride + rg*vec (+ the vec dwords).
-// The LDS serves 256 bytes per clock: 256 / (4*vec) lanes per pass.
-int bank_degree(int tw, int vec, int stride)
+// Most lanes of one LDS read of a source's column slice that share a bank:
+// lane l (column l % tw, row group l / tw) reads the hl contiguous dwords at
+// col*stride + rg*hl.  The LDS serves 256 bytes per clock, so 64 / hl lanes
+// form one pass.
+int bank_degree(int tw, int hl, int stride)
 {
-    const int lanes = 256 / (4 * vec);
+    const int lanes = 64 / hl;
     int worst = 0;
     for (int p = 0; p < 64; p += lanes) {
         int hits[64] = {0};
         for (int l = p; l < p + lanes && l < 64; ++l) {
             const int col = l % tw, rg = l / tw;
-            const int a = col * stride + rg * vec;
-            for (int j = 0; j < vec; ++j) ++hits[(a + j) % 64];
+            const int a = col * stride + rg * hl;
+            for (int j = 0; j < hl; ++j) ++hits[(a + j) % 64];
         }
         for (int b = 0; b < 64; ++b) worst = hits[b] > worst ? hits[b] : worst;
     }
@@ -903,9 +1145,10 @@ int bank_degree(int tw, int vec, int stride)
 
 }  // namespace
 
-ListCfg make_list_cfg(int radius, int tw, int hl, int vec, int nw, int list_cap)
+ListCfg make_list_cfg(int radius, int tw, int hl, int vec, int nw, int list_cap, bool wave_lists)
 {
     ListCfg c;
+    c.wave_lists = wave_lists;
     c.tw = tw;
     c.hl = hl;
     c.vec = vec;
@@ -921,8 +1164,8 @@ ListCfg make_list_cfg(int radius, int tw, int hl, int vec, int nw, int list_cap)
     const int min_s = c.nrows + vec - 1;
     int best = -1, best_deg = 1 << 30;
     for (int s = min_s; s < min_s + 64; ++s) {
-        if (s % 4 != 0) continue;  // copies stay 16-byte aligned
-        const int d = bank_degree(tw, vec, s);
+        if (s % vec != 0) continue;  // aligned VEC-wide reads
+        const int d = bank_degree(tw, hl, s);
         if (d < best_deg) {
             best_deg = d;
             best = s;
@@ -930,49 +1173,72 @@ ListCfg make_list_cfg(int radius, int tw, int hl, int vec, int nw, int list_cap)
         if (d == 1) break;
     }
     c.stride = best;
-    c.copy_elems = c.ncols * c.stride;
+    c.copy_elems = (c.ncols * c.stride + 3) & ~3;  // copies start 16-byte aligned
     c.max_row = tw + 2 * radius;
-    c.halo_rows = c.wt + 2 * radius;
     c.list_cap = list_cap;
-    c.lds_bytes = (size_t)vec * c.copy_elems * 4 + (size_t)list_cap * 4 + (size_t)(c.halo_rows + 1) * 4;
+    if (wave_lists) {
+        // per wave: halo of TH + 2R rows (at most 3 x 64 lanes), list of list_cap
+        c.halo_rows = c.th + 2 * radius;
+        c.lds_bytes = (size_t)vec * c.copy_elems * 4 + (size_t)nw * list_cap * 4;
+    } else {
+        c.halo_rows = c.wt + 2 * radius;
+        c.lds_bytes = (size_t)vec * c.copy_elems * 4 + (size_t)list_cap * 4 +
+                      (size_t)(c.halo_rows + 1) * 4;
+    }
     return c;
 }
 
 ListCfg pick_list_cfg(int radius, size_t max_lds)
 {
-    // (TW, HL, VEC, NW) by radius, then smaller variants if LDS is short
-    const int shapes[][4] = {{16, 2, 2, 4}, {16, 4, 4, 4}, {16, 4, 2, 8}, {16, 4, 2, 4}, {16, 2, 2, 4}};
-    int first = radius <= 8 ? 0 : (radius <= 24 ? 1 : 2);
-    ListCfg c;
-    for (int i = first; i < 5; ++i) {
+    // one list per workgroup strip, 16-column strips, one aligned 8-byte read
+    // per source and lane (conflict-free banks); two workgroups per CU are
+    // preferred, smaller lists and workgroups if LDS is short
+    const int shapes[][4] = {{16, 2, 2, 8}, {16, 2, 2, 4}};
+    ListCfg best;
+    for (int i = 0; i < 2; ++i) {
         const int *sh = shapes[i];
         for (int cap = 4096; cap >= 512; cap /= 2) {
-            ListCfg t = make_list_cfg(radius, sh[0], sh[1], sh[2], sh[3], cap);
+            ListCfg t = make_list_cfg(radius, sh[0], sh[1], sh[2], sh[3], cap, false);
             if (cap < 2 * t.max_row || t.halo_rows > 64 * sh[3]) break;
-            // prefer two workgroups per CU when the shape allows it
-            if (t.lds_bytes <= max_lds / 2 || (sh[3] == 8 && t.lds_bytes <= max_lds)) return t;
-            c = t;
+            if (t.lds_bytes <= max_lds / 2) return t;
+            if (t.lds_bytes <= max_lds && best.lds_bytes == 0) best = t;
         }
-        if (c.lds_bytes && c.lds_bytes <= max_lds && c.list_cap >= 2 * c.max_row) return c;
     }
-    return c;
+    return best;
 }
 
 hipError_t launch_phi_copies(float *tab, const ListCfg &c, double k, double alpha, hipStream_t st)
 {
     const int n = c.vec * c.copy_elems;
-    hipLaunchKernelGGL(k_phi_copies, dim3(blocks_for(n, 256)), dim3(256), 0, st, tab, c.vec, c.ncols,
-                       c.stride, c.padx, c.pady, c.radius, k, alpha);
+    hipLaunchKernelGGL(k_phi_copies, dim3(blocks_for(n, 256)), dim3(256), 0, st, tab, c.vec,
+                       c.copy_elems, c.ncols, c.stride, c.padx, c.pady, c.radius, k, alpha);
     return hipGetLastError();
 }
 
 namespace {
 
 template <int TW, int HL, int VEC, int NW>
+hipError_t field_wave_launch(const ListCfg &c, const unsigned long long *bits, int wpr,
+                             const float *tab, const float *S, float *P, int W, int H,
+                             hipStream_t st)
+{
+    constexpr int TH = (64 / TW) * HL;
+    const int tiles_x = (W + TW - 1) / TW, tiles_y = (H + TH - 1) / TH;
+    const int n_tiles = tiles_x * tiles_y;
+    const int want = (n_tiles + NW - 1) / NW;
+    const int grid = want < c.grid ? want : c.grid;
+    hipLaunchKernelGGL((k_field_wave<TW, HL, VEC, NW>), dim3(grid > 0 ? grid : 1), dim3(NW * 64),
+                       c.lds_bytes, st, bits, wpr, tab, c.copy_elems, c.stride, c.padx, c.pady,
+                       c.radius, c.list_cap, c.max_row, S, P, W, H, tiles_x, n_tiles);
+    return hipGetLastError();
+}
+
+template <int TW, int HL, int VEC, int NW>
 hipError_t field_list_launch(const ListCfg &c, const unsigned long long *bits, int wpr,
                              const float *tab, const float *S, float *P, int W, int H,
                              hipStream_t st)
 {
+    if (c.wave_lists) return field_wave_launch<TW, HL, VEC, NW>(c, bits, wpr, tab, S, P, W, H, st);
     constexpr int WT = NW * (64 / TW) * HL;
     const int tiles_x = (W + TW - 1) / TW, tiles_y = (H + WT - 1) / WT;
     const int n_tiles = tiles_x * tiles_y;
@@ -985,13 +1251,27 @@ hipError_t field_list_launch(const ListCfg &c, const unsigned long long *bits, i
 
 }  // namespace
 
-#define SF_LIST_SHAPES(X) X(16, 2, 2, 4) X(16, 4, 4, 4) X(16, 4, 2, 8) X(16, 4, 2, 4) X(16, 4, 4, 8) X(16, 2, 2, 8)
+#define SF_LIST_SHAPES(X)                                                                     \
+    X(16, 2, 2, 4) X(16, 2, 2, 8) X(16, 4, 2, 4) X(16, 4, 2, 8) X(16, 4, 4, 4) X(16, 4, 4, 8)    \
+    X(32, 2, 2, 4) X(32, 2, 2, 8) X(32, 4, 2, 4) X(32, 4, 4, 4) X(8, 4, 4, 4) X(8, 2, 2, 4)
+
+bool list_shape_compiled(int tw, int hl, int vec, int nw)
+{
+#define SF_KNOWN(a, b, v, n) \
+    if (tw == a && hl == b && vec == v && nw == n) return true;
+    SF_LIST_SHAPES(SF_KNOWN)
+#undef SF_KNOWN
+    return false;
+}
 
 hipError_t set_field_list_lds_limit(size_t bytes)
 {
     hipError_t e = hipSuccess;
 #define SF_SET(a, b, v, n)                                                                        \
     e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_field_list<a, b, v, n>),         \
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);          \
+    if (e != hipSuccess) return e;                                                            \
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_field_wave<a, b, v, n>),         \
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);          \
     if (e != hipSuccess) return e;
     SF_LIST_SHAPES(SF_SET)

@@ -186,7 +186,10 @@ def test_tile_shape_invariance(sf, monkeypatch):
     # wave-tile shape bit for bit (Eq. 1: any partition of the sum)
     sc = scenes.random_scene(130, 90, n_peds=1500, radius=7, seed=33, bernoulli=0.03)
     fields = []
-    for shape in ("16x2x2x4", "16x4x4x4", "16x4x2x8", "16x4x2x4", "16x2x2x8"):
+    base = ("16x2x2x4", "16x2x2x8", "16x4x2x4", "16x4x2x8", "16x4x4x4", "16x4x4x8",
+            "32x2x2x4", "32x2x2x8", "32x4x2x4", "32x4x4x4", "8x4x4x4", "8x2x2x4")
+    # mode 1: wave-private source lists, mode 0: one list per workgroup strip
+    for shape in [f"{b}x{m}" for m in (1, 0) for b in base]:
         monkeypatch.setenv("SF_TILE", shape)
         with sf.GpuScene(sc) as g:
             g.step(5)
