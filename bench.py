@@ -176,10 +176,15 @@ def main():
     contrib_per_launch = (s2["ped_steps"] / max(args.steps, 1)) * window_contributions(sc)
     sup_us = ktimes["superpose"]["avg_us"]
     achieved = contrib_per_launch / (sup_us * 1e-6) / 1e12
+    # algorithmic bytes of one superposition launch: S read and P written once
+    # per su, the occupancy bitmap read once
+    alg_bytes = 8.0 * sc.width * sc.height + 8.0 * ((sc.width + 63) // 64) * sc.height
     roofline = {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / ALU_PEAK_TFLOPS,
                 "traffic": traffic_per_launch(), "kernel": "superpose",
-                "flop_per_launch": contrib_per_launch, "avg_launch_us": sup_us}
+                "flop_per_launch": contrib_per_launch, "avg_launch_us": sup_us,
+                "algorithmic_bytes_per_launch": alg_bytes,
+                "hbm_frac": alg_bytes / (sup_us * 1e-6) / 8.0e12}
 
     out = {"metric": METRIC, "value": value, "unit": "pedestrian-steps/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1000.0 * dt / args.steps,

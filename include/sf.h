@@ -150,8 +150,9 @@ int sf_stats(const sf_scene *s, sf_stats_t *out);
 /* Block until all work enqueued for the scene has finished. */
 int sf_sync(const sf_scene *s);
 
-/* Per-kernel timing with HIP events recorded on the scene's stream around
- * every launch of the kernels listed above.  enable = 1 starts a fresh
+/* Per-kernel timing: while enabled, every launch of the kernels listed above
+ * records a start/stop HIP event pair as part of its own dispatch (the
+ * kernel's execution interval, no extra stream packets).  enable = 1 starts a fresh
  * measurement, 0 stops recording.  sf_kernel_time blocks, then reports the
  * summed duration in milliseconds and the number of launches measured for
  * one SF_KERNEL_* id. */

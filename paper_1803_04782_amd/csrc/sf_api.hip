@@ -178,23 +178,20 @@ int validate_positions(int W, int H, const uint8_t *obst, const uint8_t *exitm, 
     return SF_OK;
 }
 
-int record_begin(sf_scene *s, int k)
+// Event pair that the next launch of kernel k records (nullptr when not timing).
+int timing_events(sf_scene *s, int k, sf::LaunchEvents *ev)
 {
+    ev->start = ev->stop = nullptr;
     if (!s->timing) return SF_OK;
     if (s->ev_used[k] == s->ev[k].size()) {
         EventPair e;
-        SF_HIP(hipEventCreate(&e.a), "hipEventCreate");
-        SF_HIP(hipEventCreate(&e.b), "hipEventCreate");
+        // no system-scope fence: the timestamps are only read back by this library
+        SF_HIP(hipEventCreateWithFlags(&e.a, hipEventDisableSystemFence), "hipEventCreate");
+        SF_HIP(hipEventCreateWithFlags(&e.b, hipEventDisableSystemFence), "hipEventCreate");
         s->ev[k].push_back(e);
     }
-    SF_HIP(hipEventRecord(s->ev[k][s->ev_used[k]].a, s->stream), "hipEventRecord");
-    return SF_OK;
-}
-
-int record_end(sf_scene *s, int k)
-{
-    if (!s->timing) return SF_OK;
-    SF_HIP(hipEventRecord(s->ev[k][s->ev_used[k]].b, s->stream), "hipEventRecord");
+    ev->start = s->ev[k][s->ev_used[k]].a;
+    ev->stop = s->ev[k][s->ev_used[k]].b;
     ++s->ev_used[k];
     return SF_OK;
 }
@@ -411,22 +408,20 @@ int create(const sf_scene_desc *d, void *hip_stream, sf_scene **out)
 int enqueue_tick(sf_scene *s)
 {
     hipStream_t st = s->stream;
+    sf::LaunchEvents ev;
     int rc;
-    if ((rc = record_begin(s, SF_KERNEL_DECIDE))) return rc;
+    if ((rc = timing_events(s, SF_KERNEL_DECIDE, &ev))) return rc;
     SF_HIP(sf::launch_decide_claim(s->chunk, s->occ, s->wpr, s->W, s->H, s->owner, s->P,
                                    s->phi_axial, s->phi_diag, s->seed, s->target, s->key, s->flags,
-                                   s->claim, s->ctr, st),
+                                   s->claim, s->ctr, st, &ev),
            "decide");
-    if ((rc = record_end(s, SF_KERNEL_DECIDE))) return rc;
-    if ((rc = record_begin(s, SF_KERNEL_COMMIT))) return rc;
+    if ((rc = timing_events(s, SF_KERNEL_COMMIT, &ev))) return rc;
     SF_HIP(sf::launch_commit(s->N, s->W, s->pos, s->target, s->key, s->flags, s->claim, s->occ,
-                             s->wpr, s->owner, s->exitm, s->ctr, st),
+                             s->wpr, s->owner, s->exitm, s->ctr, st, &ev),
            "commit");
-    if ((rc = record_end(s, SF_KERNEL_COMMIT))) return rc;
-    if ((rc = record_begin(s, SF_KERNEL_SUPERPOSE))) return rc;
-    SF_HIP(sf::launch_field_list(s->lc, s->occ, s->wpr, s->tab, s->S, s->P, s->W, s->H, st),
+    if ((rc = timing_events(s, SF_KERNEL_SUPERPOSE, &ev))) return rc;
+    SF_HIP(sf::launch_field_list(s->lc, s->occ, s->wpr, s->tab, s->S, s->P, s->W, s->H, st, &ev),
            "superpose");
-    if ((rc = record_end(s, SF_KERNEL_SUPERPOSE))) return rc;
     return SF_OK;
 }
 

@@ -9,6 +9,12 @@
 
 namespace sf {
 
+// Optional start/stop events recorded by the dispatch itself (profiling
+// timestamps of the kernel), for per-kernel timing.
+struct LaunchEvents {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+
 // Running totals kept on the device.  Word 0 holds the index of the next
 // tick.  Every other total has kSlots copies, each on its own 128-byte line;
 // block b adds to copy b % kSlots, so that blocks do not serialise on one
@@ -85,7 +91,7 @@ hipError_t launch_phi_copies(float *tab, const ListCfg &c, double k, double alph
                              hipStream_t st);
 hipError_t launch_field_list(const ListCfg &c, const unsigned long long *bits, int wpr,
                              const float *tab, const float *S, float *P, int W, int H,
-                             hipStream_t st);
+                             hipStream_t st, const LaunchEvents *ev = nullptr);
 hipError_t set_field_list_lds_limit(size_t bytes);
 bool list_shape_compiled(int tw, int hl, int vec, int nw);
 
@@ -121,11 +127,11 @@ hipError_t launch_decide_claim(int chunk, const unsigned long long *occ, int wpr
                                float phi_diag, unsigned long long seed, int32_t *target,
                                unsigned long long *key, uint8_t *flags,
                                unsigned long long *claim, unsigned long long *ctr,
-                               hipStream_t st);
+                               hipStream_t st, const LaunchEvents *ev = nullptr);
 hipError_t launch_commit(int N, int W, int32_t *pos, int32_t *target,
                          const unsigned long long *key, uint8_t *flags,
                          unsigned long long *claim, unsigned long long *occ, int wpr,
                          int32_t *owner, const uint8_t *exitm, unsigned long long *ctr,
-                         hipStream_t st);
+                         hipStream_t st, const LaunchEvents *ev = nullptr);
 
 }  // namespace sf

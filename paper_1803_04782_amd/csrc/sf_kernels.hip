@@ -13,6 +13,7 @@
 // words row by row enumerates a tile's halo pedestrians in global row-major
 // order.  Every su therefore sums its contributions in the same order whatever
 // the tiling, which makes the FP32 field reproducible bit for bit.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -993,6 +994,19 @@ __global__ __launch_bounds__(256) void k_commit(int N, int W, int32_t *__restric
     block_delta_add(left ? -1 : 0, ctr, kLive);
 }
 
+// Plain launch, or a launch whose dispatch records `ev` (kernel timing).
+template <typename K, typename... A>
+hipError_t launch(K kernel, dim3 grid, dim3 block, size_t lds, hipStream_t st,
+                  const LaunchEvents *ev, A... args)
+{
+    if (ev && ev->start)
+        hipExtLaunchKernelGGL(kernel, grid, block, (uint32_t)lds, st, ev->start, ev->stop, 0u,
+                              args...);
+    else
+        hipLaunchKernelGGL(kernel, grid, block, lds, st, args...);
+    return hipGetLastError();
+}
+
 inline unsigned int blocks_for(size_t n, unsigned int bs, unsigned int cap = 65535u * 16u)
 {
     size_t b = (n + bs - 1) / bs;
@@ -1220,33 +1234,32 @@ namespace {
 template <int TW, int HL, int VEC, int NW>
 hipError_t field_wave_launch(const ListCfg &c, const unsigned long long *bits, int wpr,
                              const float *tab, const float *S, float *P, int W, int H,
-                             hipStream_t st)
+                             hipStream_t st, const LaunchEvents *ev)
 {
     constexpr int TH = (64 / TW) * HL;
     const int tiles_x = (W + TW - 1) / TW, tiles_y = (H + TH - 1) / TH;
     const int n_tiles = tiles_x * tiles_y;
     const int want = (n_tiles + NW - 1) / NW;
     const int grid = want < c.grid ? want : c.grid;
-    hipLaunchKernelGGL((k_field_wave<TW, HL, VEC, NW>), dim3(grid > 0 ? grid : 1), dim3(NW * 64),
-                       c.lds_bytes, st, bits, wpr, tab, c.copy_elems, c.stride, c.padx, c.pady,
-                       c.radius, c.list_cap, c.max_row, S, P, W, H, tiles_x, n_tiles);
-    return hipGetLastError();
+    return launch(k_field_wave<TW, HL, VEC, NW>, dim3(grid > 0 ? grid : 1), dim3(NW * 64),
+                  c.lds_bytes, st, ev, bits, wpr, tab, c.copy_elems, c.stride, c.padx, c.pady,
+                  c.radius, c.list_cap, c.max_row, S, P, W, H, tiles_x, n_tiles);
 }
 
 template <int TW, int HL, int VEC, int NW>
 hipError_t field_list_launch(const ListCfg &c, const unsigned long long *bits, int wpr,
                              const float *tab, const float *S, float *P, int W, int H,
-                             hipStream_t st)
+                             hipStream_t st, const LaunchEvents *ev)
 {
-    if (c.wave_lists) return field_wave_launch<TW, HL, VEC, NW>(c, bits, wpr, tab, S, P, W, H, st);
+    if (c.wave_lists)
+        return field_wave_launch<TW, HL, VEC, NW>(c, bits, wpr, tab, S, P, W, H, st, ev);
     constexpr int WT = NW * (64 / TW) * HL;
     const int tiles_x = (W + TW - 1) / TW, tiles_y = (H + WT - 1) / WT;
     const int n_tiles = tiles_x * tiles_y;
     const int grid = n_tiles < c.grid ? n_tiles : c.grid;
-    hipLaunchKernelGGL((k_field_list<TW, HL, VEC, NW>), dim3(grid > 0 ? grid : 1), dim3(NW * 64),
-                       c.lds_bytes, st, bits, wpr, tab, c.copy_elems, c.stride, c.padx, c.pady,
-                       c.radius, c.list_cap, c.max_row, S, P, W, H, tiles_x, n_tiles);
-    return hipGetLastError();
+    return launch(k_field_list<TW, HL, VEC, NW>, dim3(grid > 0 ? grid : 1), dim3(NW * 64),
+                  c.lds_bytes, st, ev, bits, wpr, tab, c.copy_elems, c.stride, c.padx, c.pady,
+                  c.radius, c.list_cap, c.max_row, S, P, W, H, tiles_x, n_tiles);
 }
 
 }  // namespace
@@ -1281,11 +1294,11 @@ hipError_t set_field_list_lds_limit(size_t bytes)
 
 hipError_t launch_field_list(const ListCfg &c, const unsigned long long *bits, int wpr,
                              const float *tab, const float *S, float *P, int W, int H,
-                             hipStream_t st)
+                             hipStream_t st, const LaunchEvents *ev)
 {
 #define SF_DISPATCH(a, b, v, n)                                                                   \
     if (c.tw == a && c.hl == b && c.vec == v && c.nw == n)                                      \
-        return field_list_launch<a, b, v, n>(c, bits, wpr, tab, S, P, W, H, st);
+        return field_list_launch<a, b, v, n>(c, bits, wpr, tab, S, P, W, H, st, ev);
     SF_LIST_SHAPES(SF_DISPATCH)
 #undef SF_DISPATCH
     return hipErrorInvalidValue;
@@ -1329,25 +1342,23 @@ hipError_t launch_decide_claim(int chunk, const unsigned long long *occ, int wpr
                                const int32_t *owner, const float *P, float phi_axial,
                                float phi_diag, unsigned long long seed, int32_t *target,
                                unsigned long long *key, uint8_t *flags, unsigned long long *claim,
-                               unsigned long long *ctr, hipStream_t st)
+                               unsigned long long *ctr, hipStream_t st, const LaunchEvents *ev)
 {
     const size_t nwords = (size_t)wpr * H;
     const size_t per_block = (size_t)(kDecideThreads / 64) * chunk;
     const size_t lds = (size_t)(kDecideThreads / 64) * chunk * 64 * sizeof(int32_t);
-    hipLaunchKernelGGL(k_decide_claim, dim3(blocks_for(nwords, (unsigned)per_block)),
-                       dim3(kDecideThreads), lds, st, chunk, occ, wpr, W, H, owner, P, phi_axial,
-                       phi_diag, seed, target, key, flags, claim, ctr);
-    return hipGetLastError();
+    return launch(k_decide_claim, dim3(blocks_for(nwords, (unsigned)per_block)),
+                  dim3(kDecideThreads), lds, st, ev, chunk, occ, wpr, W, H, owner, P, phi_axial,
+                  phi_diag, seed, target, key, flags, claim, ctr);
 }
 
 hipError_t launch_commit(int N, int W, int32_t *pos, int32_t *target, const unsigned long long *key,
                          uint8_t *flags, unsigned long long *claim, unsigned long long *occ,
                          int wpr, int32_t *owner, const uint8_t *exitm, unsigned long long *ctr,
-                         hipStream_t st)
+                         hipStream_t st, const LaunchEvents *ev)
 {
-    hipLaunchKernelGGL(k_commit, dim3(blocks_for(N, 256)), dim3(256), 0, st, N, W, pos, target, key,
-                       flags, claim, occ, wpr, owner, exitm, ctr);
-    return hipGetLastError();
+    return launch(k_commit, dim3(blocks_for(N, 256)), dim3(256), 0, st, ev, N, W, pos, target, key,
+                  flags, claim, occ, wpr, owner, exitm, ctr);
 }
 
 }  // namespace sf
