@@ -370,14 +370,21 @@ struct VecOf<4> {
     typedef float type __attribute__((ext_vector_type(4)));
 };
 
-__device__ __forceinline__ int wave_incl_scan(int v)
+// Exclusive prefix sum over the lanes of a wave of counts in [0, 255], and the
+// wave total, from eight ballots.
+__device__ __forceinline__ int wave_excl_small(int cnt, int &total)
 {
-    const int lane = (int)lane_id();
-    for (int d = 1; d < 64; d <<= 1) {
-        const int t = __shfl_up(v, d);
-        if (lane >= d) v += t;
+    int excl = 0, tot = 0;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        const unsigned long long m = __ballot((cnt >> b) & 1);
+        const int below = (int)__builtin_amdgcn_mbcnt_hi(
+            (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+        excl += below << b;
+        tot += __popcll(m) << b;
     }
-    return v;
+    total = tot;
+    return excl;
 }
 
 // smallest r in [0, n] with a[r] >= v (a non-decreasing, a[n] >= v)
@@ -496,9 +503,10 @@ __global__ __launch_bounds__(NW * 64) void k_field_list(
         }
         fetch_rows(t + (int)gridDim.x);
 
-        // 2. block exclusive scan of the row counts
-        const int incl = wave_incl_scan(cnt);
-        if (lane == 63) wave_tot[wv] = incl;
+        // 2. block exclusive scan of the row counts (ballots within a wave)
+        int wtot;
+        const int wexcl = wave_excl_small(cnt, wtot);
+        if (lane == 0) wave_tot[wv] = wtot;
         __syncthreads();
         int before = 0, total = 0;
 #pragma unroll
@@ -507,7 +515,7 @@ __global__ __launch_bounds__(NW * 64) void k_field_list(
             before += w < wv ? v : 0;
             total += v;
         }
-        const int excl = before + incl - cnt;
+        const int excl = before + wexcl;
         if (tid < nr) row_excl[tid] = excl;
         if (tid == 0) row_excl[nr] = total;
         __syncthreads();
@@ -617,23 +625,6 @@ __global__ __launch_bounds__(NW * 64) void k_field_list(
 // lane i holds halo rows i, 64 + i and 128 + i; the row counts are prefix-summed
 // with ballots (no LDS traffic); entries go to a wave-private LDS list of `cap`
 // entries (several passes when a dense halo overflows it).
-
-// Exclusive prefix sum over the lanes of a wave of counts in [0, 255], and the
-// wave total, from eight ballots.
-__device__ __forceinline__ int wave_excl_small(int cnt, int &total)
-{
-    int excl = 0, tot = 0;
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-        const unsigned long long m = __ballot((cnt >> b) & 1);
-        const int below = (int)__builtin_amdgcn_mbcnt_hi(
-            (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-        excl += below << b;
-        tot += __popcll(m) << b;
-    }
-    total = tot;
-    return excl;
-}
 
 template <int TW, int HL, int VEC, int NW>
 __global__ __launch_bounds__(NW * 64) void k_field_wave(
@@ -873,23 +864,20 @@ __global__ __launch_bounds__(kDecideThreads) void k_decide_claim(
     unsigned long long m = 0;
     if (lane < chunk && w < nwords) m = occ[w];
     const int cntl = __popcll(m);
-    int incl = cntl;
-    for (int d = 1; d < 64; d <<= 1) {
-        const int v = __shfl_up(incl, d);
-        if (lane >= d) incl += v;
-    }
-    const int total = __shfl(incl, 63);
+    int total;
+    int o = wave_excl_small(cntl, total);
     if (m) {
         const int y = (int)(w / wpr);
         const int xb = (int)(w % wpr) * 64;
-        int o = incl - cntl;
         while (m) {
             const int b = __builtin_ctzll(m);
             m &= m - 1ull;
             list[o++] = y * W + xb + b;
         }
     }
-    __syncthreads();
+    // the list is private to the wave: its writes complete before it is read
+    __builtin_amdgcn_s_waitcnt(0xC07F);
+    asm volatile("" ::: "memory");
     const unsigned long long t = ctr[0];
     unsigned int movers = 0, ties = 0;
     for (int base = 0; base < total; base += 64) {
