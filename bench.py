@@ -8,6 +8,18 @@ superpose.  Inputs are resident in HBM when the timed region starts.
 Prints one JSON line: pedestrian-steps/s (value) and su-field updates/s, the
 roofline of the dominant kernel (field superposition) from HIP events recorded
 around its launches, and the CPU oracle timed on a bounded sample.
+
+--workload serving runs the serving loop (Poisson arrivals at 50, 200 and 800
+scenes/s, sizes from the same distribution, each scene to evacuation or 2000
+ticks, admission by device footprint) and reports per-tick latency p50/p99
+and scenes/s per rate.
+
+--workload ensemble256 measures batching instead: 256 scenes of uneven size,
+crowd and radius (sides 128..2048 su, 300 ticks), stepped once as a plain
+loop of per-scene ticks and once as a batch (one decide, commit and field
+launch per tick for all scenes, graph replays, autotuned tiling), with both
+results checked to be identical and a lockstep tick of the smallest scenes
+against the oracle.
 """
 from __future__ import annotations
 
@@ -95,12 +107,173 @@ def cpu_baseline(sc, gpu_state, seconds: float = 12.0):
     return base, gate
 
 
+def bench_ensemble(args, stream):
+    """Batched vs plain on the uneven 256-scene ensemble."""
+    import torch
+
+    import oracle
+    from paper_1803_04782_amd import scenes, sf
+
+    def say(*a):
+        print("[bench]", *a, file=sys.stderr, flush=True)
+
+    t0 = time.perf_counter()
+    scs = scenes.ensemble(n_scenes=args.scenes, seed=3)
+    steps = args.steps if args.steps is not None else scs[0].steps
+    su_total = sum(s.width * s.height for s in scs)
+    free_total = sum(int((s.obstacle == 0).sum()) for s in scs)
+    peds_total = sum(s.n_peds for s in scs)
+    say(f"ensemble of {len(scs)} scenes: {su_total:.3g} su, {peds_total} pedestrians "
+        f"(generated in {time.perf_counter() - t0:.1f} s)")
+    t0 = time.perf_counter()
+    plain = [sf.GpuScene(s, stream=stream) for s in scs]
+    member = [sf.GpuScene(s, stream=stream) for s in scs]
+    say(f"created {2 * len(scs)} scenes in {time.perf_counter() - t0:.1f} s")
+    b = sf.Batch(member, stream=stream)
+    try:
+        t0 = time.perf_counter()
+        tiling = b.tune(reps=3)
+        say(f"autotuned tiling {tiling} in {time.perf_counter() - t0:.1f} s")
+        for _ in range(args.warmup):
+            for g in plain:
+                g.step(1)
+        b.step(args.warmup)
+        torch.cuda.synchronize()
+        ps_plain0 = sum(g.stats()["ped_steps"] for g in plain)
+        ps_batch0 = sum(x["ped_steps"] for x in b.stats())
+
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            for g in plain:
+                g.step(1)
+        torch.cuda.synchronize()
+        dt_plain = time.perf_counter() - t0
+        say(f"plain loop: {steps} ticks in {dt_plain:.2f} s")
+        t0 = time.perf_counter()
+        b.step(steps)
+        torch.cuda.synchronize()
+        dt_batch = time.perf_counter() - t0
+        say(f"batched: {steps} ticks in {dt_batch:.2f} s")
+        ps_plain = sum(g.stats()["ped_steps"] for g in plain) - ps_plain0
+        totals = b.stats()
+        ps_batch = sum(x["ped_steps"] for x in totals) - ps_batch0
+
+        # the two runs must agree bit for bit (positions of every scene, fields
+        # of the 16 smallest)
+        order = np.argsort([s.width * s.height for s in scs])
+        same_pos = all(np.array_equal(a.positions(), m.positions()) for a, m in zip(plain, member))
+        same_field = all(np.array_equal(plain[j].field(), member[j].field()) for j in order[:16])
+        # one lockstep tick of the 8 smallest scenes against the oracle
+        small = [int(j) for j in order[:8]]
+        before = []
+        for j in small:
+            st = oracle.statics(scs[j])
+            pos = member[j].positions()
+            before.append((j, st, pos, member[j].field(),
+                           oracle.step(st, pos, totals[j]["step"])))
+        b.step(1)
+        err, untied, tied = 0.0, 0, 0
+        for j, st, pos, P_g, r in before:
+            free = st.obstacle == 0
+            if free.any():
+                err = max(err, float(np.max(np.abs(P_g[free] - r.P[free]) /
+                                            np.maximum(np.abs(r.P[free]), 1.0))))
+            tgt_g, flags_g = member[j].last_moves()
+            pos_g = member[j].positions()
+            live = pos >= 0
+            won = (flags_g & 2) != 0
+            bad = live & ((tgt_g != r.target) | (won != (r.moved == 1)) | (pos_g != r.pos))
+            hot = set(r.target[live & (r.tied == 1)].tolist()) | \
+                set(tgt_g[live & (r.tied == 1)].tolist())
+            u = [k for k in np.flatnonzero(bad)
+                 if not r.tied[k] and r.target[k] not in hot and tgt_g[k] not in hot
+                 and pos[k] not in hot]
+            untied += len(u)
+            tied += int(bad.sum()) - len(u)
+    finally:
+        b.close()
+        for g in plain + member:
+            g.close()
+
+    value = ps_batch / dt_batch
+    out = {"metric": METRIC, "value": value, "unit": "pedestrian-steps/s", "n_gpus": 1,
+           "steps": steps, "warmup": args.warmup, "ms_per_step": 1000.0 * dt_batch / steps,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": f"ensemble{len(scs)}", "scenes": len(scs), "su": su_total,
+                      "pedestrians": peds_total, "ticks": steps, "sides": [128, 2048],
+                      "radii": [4, 8, 16, 32], "parallelism": "single-gpu"},
+           "su_field_updates_per_s": steps * free_total / dt_batch,
+           "plain": {"value": ps_plain / dt_plain, "ms_per_step": 1000.0 * dt_plain / steps},
+           "batched_vs_plain": (ps_batch / dt_batch) / (ps_plain / dt_plain),
+           "tiling": tiling,
+           "identical_to_plain": {"positions_all_scenes": bool(same_pos),
+                                  "fields_16_smallest": bool(same_field)},
+           "accuracy_gate": {"scenes": len(small), "field_rel_err": err,
+                             "untied_mismatches": untied, "tied_mismatches": tied},
+           "roofline": None, "cpu_baseline": None}
+    print(json.dumps(out), flush=True)
+
+
+def bench_serving(args, stream):
+    """Serving loop under Poisson arrivals at several rates."""
+    import torch
+
+    from paper_1803_04782_amd import scenes, serve
+
+    def say(*a):
+        print("[bench]", *a, file=sys.stderr, flush=True)
+
+    # request sizes: a pool of scenes drawn from the uneven-ensemble
+    # distribution (request i uses pool entry i mod pool size)
+    t0 = time.perf_counter()
+    pool = scenes.ensemble(n_scenes=args.pool, seed=4, steps=2000)
+    say(f"request pool of {len(pool)} scenes generated in {time.perf_counter() - t0:.1f} s")
+    rates = [float(r) for r in args.rates.split(",")]
+    runs = []
+    for lam in rates:
+        arrivals = serve.poisson_arrivals(lam, args.serve_seconds, seed=4)
+        reqs = [serve.Request(i, float(a), (lambda s=pool[i % len(pool)]: s), max_steps=2000)
+                for i, a in enumerate(arrivals)]
+        srv = serve.Server(int(args.budget_gib * (1 << 30)), max_scenes=args.max_scenes,
+                           stream=stream)
+        say(f"rate {lam:g}/s: {len(reqs)} requests over {args.serve_seconds:g} s")
+        out = srv.run(reqs, stop_admitting_at=args.serve_seconds, drain=False,
+                      deadline=args.serve_seconds)
+        torch.cuda.synchronize()
+        out.pop("results")
+        out["rate_per_s"] = lam
+        say(f"   {json.dumps(out)}")
+        runs.append(out)
+    best = max(runs, key=lambda r: r["ped_steps_per_s"])
+    out = {"metric": METRIC, "value": best["ped_steps_per_s"], "unit": "pedestrian-steps/s",
+           "n_gpus": 1, "steps": None, "warmup": 0, "ms_per_step": best["step_latency_ms_p50"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": "serving", "rates_per_s": rates,
+                      "window_s": args.serve_seconds, "max_steps": 2000,
+                      "budget_gib": args.budget_gib, "max_scenes": args.max_scenes,
+                      "request_pool": len(pool), "parallelism": "single-gpu"},
+           "runs": runs, "roofline": None, "cpu_baseline": None}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed ticks (default: the workload's own tick count)")
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="hall1024", choices=["hall1024", "room64", "plaza8192"])
+    ap.add_argument("--workload", default="hall1024",
+                    choices=["hall1024", "room64", "plaza8192", "ensemble256", "serving"])
+    ap.add_argument("--scenes", type=int, default=256, help="ensemble size (ensemble256)")
+    ap.add_argument("--rates", default="50,200,800", help="arrival rates per s (serving)")
+    ap.add_argument("--serve-seconds", type=float, default=30.0,
+                    help="arrival window per rate (serving)")
+    ap.add_argument("--budget-gib", type=float, default=64.0,
+                    help="device memory admitted scenes may hold (serving)")
+    ap.add_argument("--max-scenes", type=int, default=256, help="resident slots (serving)")
+    ap.add_argument("--pool", type=int, default=64, help="request pool size (serving)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -130,7 +303,15 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    if args.workload == "ensemble256":
+        bench_ensemble(args, stream)
+        return
+    if args.workload == "serving":
+        bench_serving(args, stream)
+        return
     sc = scenes.WORKLOADS[args.workload]()
+    if args.steps is None:
+        args.steps = sc.steps
     print(f"[bench] workload {sc.name}: {sc.width}x{sc.height} su, {sc.n_peds} pedestrians, "
           f"R={sc.radius}", file=sys.stderr, flush=True)
     free_su = int((sc.obstacle == 0).sum())

@@ -162,6 +162,69 @@ int sf_kernel_time(const sf_scene *s, int kernel, double *total_ms, int64_t *lau
 /* Release the scene (NULL is ignored).  Waits for the scene's work first. */
 void sf_destroy_scene(sf_scene *s);
 
+/* ---- batches ---------------------------------------------------------------
+ * Not in the paper, whose tick runs one scene at a time: a batch advances many
+ * scenes of different grid size, crowd and radius together.  Each tick is one
+ * decide, one commit and one field launch that together cover every member
+ * scene, and runs of ticks are replayed from captured HIP graphs.  Every
+ * member evolves exactly as under sf_step alone: the kernels are the same,
+ * per scene, and the field's summation order does not depend on the launch.
+ *
+ * While a scene belongs to a batch its work runs on the batch's stream:
+ * sf_field, sf_positions, sf_last_moves, sf_static_field, sf_stats and sf_sync
+ * on the scene are ordered after the batch's enqueued ticks, while sf_step and
+ * sf_set_state on it fail with SF_EINVAL.  A scene belongs to at most one batch
+ * at a time.  Destroy a batch before its scenes; if a member scene is destroyed
+ * first, later sf_batch_step calls on that batch fail with SF_EINVAL. */
+typedef struct sf_batch sf_batch; /* opaque, library-owned */
+
+/* Launch shape and schedule of a batch (a zero field = library default). */
+typedef struct {
+    int32_t tw, hl, vec, nw;   /* field kernel: strip width in su, rows per lane,
+                                  LDS vector width, waves per workgroup; one of
+                                  the compiled shapes, or all four zero        */
+    int32_t list_cap;          /* field kernel: source-list entries in LDS      */
+    int32_t blocks_per_cu;     /* field kernel: workgroups per compute unit     */
+    int32_t items_per_block;   /* field kernel: work items (runs of strips of
+                                  one scene) dealt to each workgroup per tick  */
+    int32_t max_chunk;         /* decide kernel: most bitmap words per wave     */
+} sf_batch_tiling;
+
+/* Group n_scenes (>= 1, distinct, none in another batch, all on the current
+ * device) into a batch whose ticks are enqueued on `hip_stream`.  `tiling`
+ * may be NULL (defaults).  Waits for the scenes' queued work.  The scenes
+ * stay owned by the caller.  Errors: SF_EINVAL (bad list or tiling that does
+ * not fit the largest radius), SF_ENOMEM, SF_EDEVICE. */
+int sf_batch_create(sf_scene *const *scenes, int32_t n_scenes, const sf_batch_tiling *tiling,
+                    void *hip_stream, sf_batch **out);
+
+/* Autotuner: times the field launch of every compiled shape and a few
+ * schedules on the batch's current state (`reps` launches each, median
+ * kept), adopts the fastest and, if `chosen` is not NULL, reports it.  The
+ * scenes' state is unchanged (the field is recomputed, bit for bit).
+ * Blocks. */
+int sf_batch_tune(sf_batch *b, int32_t reps, sf_batch_tiling *chosen);
+
+/* The tiling in use (defaults filled in). */
+int sf_batch_get_tiling(const sf_batch *b, sf_batch_tiling *out);
+
+/* Enqueue n_steps (>= 0) ticks of every member scene and return without
+ * waiting.  Runs of two or more ticks replay graphs of up to 8 ticks,
+ * captured on first use; a single tick is launched directly. */
+int sf_batch_step(sf_batch *b, int32_t n_steps);
+
+/* Running totals of every member scene (out[n_scenes], in the order given to
+ * sf_batch_create), read with one launch and one copy.  Blocks until the
+ * batch's queued work is done. */
+int sf_batch_stats(const sf_batch *b, sf_stats_t *out);
+
+/* Block until all work enqueued on the batch has finished. */
+int sf_batch_sync(const sf_batch *b);
+
+/* Release the batch (NULL is ignored) after its work; the member scenes go
+ * back to their own streams. */
+void sf_batch_destroy(sf_batch *b);
+
 /* Message of the last failure on the calling thread ("" if none). */
 const char *sf_last_error(void);
 

@@ -8,14 +8,18 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <new>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "sf.h"
 #include "sf_internal.h"
 
+using sf::FieldLaunch;
 using sf::ListCfg;
+using sf::SceneView;
 using sf::SupCfg;
 
 namespace {
@@ -70,14 +74,60 @@ struct sf_scene {
     int32_t *D = nullptr;
     uint8_t *exitm = nullptr;
     unsigned long long *occ = nullptr, *claim = nullptr, *key = nullptr;
-    int32_t *pos = nullptr, *target = nullptr, *owner = nullptr;
+    int32_t *pos = nullptr, *target = nullptr;
+    unsigned long long *owner = nullptr;  // see SceneView::owner
+    // Per-pedestrian arrays use internal ids: live pedestrians in row-major
+    // order of their positions when the state was set, then the evacuated
+    // ones, so that neighbouring su hold neighbouring ids.  ext (device) and
+    // h_ext (host) map an internal id to the caller's id.
+    int32_t *ext = nullptr;
+    std::vector<int32_t> h_ext;
     uint8_t *flags = nullptr;
     unsigned long long *ctr = nullptr;  // see sf::ctr_index
+    // what the per-tick kernels read: the view (host copy and device copy),
+    // the field work items and the launch sizes
+    SceneView view = {};
+    int strips_per_block = 1;  // field: strips per work item (items dealt round robin)
+    FieldLaunch fl;
+    // batch membership: while a batch holds the scene, `stream` is the
+    // batch's stream and `own_stream` the one given at create
+    sf_batch *batch = nullptr;
+    hipStream_t own_stream = nullptr;
     std::vector<void *> owned;
     // timing
     bool timing = false;
     std::vector<EventPair> ev[SF_KERNEL_COUNT];
     size_t ev_used[SF_KERNEL_COUNT] = {};
+};
+
+namespace {
+
+// Device-side layout of a batch for one tiling: the member views, the
+// workgroup -> scene maps of the decide and commit launches, the field work
+// items and the stamp tables (one per distinct radius and field law).
+struct BatchLayout {
+    sf_batch_tiling t = {};
+    FieldLaunch fl;
+    int n_items = 0, dec_blocks = 0, com_blocks = 0, max_chunk = 4;
+    SceneView *d_views = nullptr;
+    int32_t *d_dec_scene = nullptr, *d_com_scene = nullptr, *d_items = nullptr;
+    unsigned long long *d_totals = nullptr;  // 8 words per scene (sf_batch_stats)
+    std::vector<void *> bufs;
+};
+
+}  // namespace
+
+struct sf_batch {
+    int device = 0;
+    hipStream_t stream = nullptr;   // where ticks run (caller's stream)
+    hipStream_t capture = nullptr;  // private stream on which graphs are captured
+    int ncu = 0;
+    size_t max_lds = 0;
+    std::vector<sf_scene *> scenes;
+    bool broken = false;  // a member scene was destroyed
+    BatchLayout cur;
+    // captured graphs by ticks per replay
+    std::map<int, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
 };
 
 namespace {
@@ -101,6 +151,11 @@ void release(sf_scene *s)
     (void)hipGetDevice(&cur);
     (void)hipSetDevice(s->device);
     (void)hipStreamSynchronize(s->stream);
+    if (sf_batch *b = s->batch) {
+        // the batch can no longer run: its views name this scene's memory
+        b->broken = true;
+        b->scenes.erase(std::remove(b->scenes.begin(), b->scenes.end(), s), b->scenes.end());
+    }
     for (void *p : s->owned) (void)hipFree(p);
     for (int k = 0; k < SF_KERNEL_COUNT; ++k)
         for (EventPair &e : s->ev[k]) {
@@ -202,11 +257,11 @@ int rebuild_dynamic(sf_scene *s)
 {
     const size_t nwords = (size_t)s->wpr * s->H;
     SF_HIP(sf::launch_fill_u64(s->occ, nwords, 0ull, s->stream), "clear occupancy");
-    SF_HIP(sf::launch_fill_i32(s->owner, (size_t)s->W * s->H, -1, s->stream), "clear owners");
-    SF_HIP(sf::launch_occ_init(s->pos, s->N, s->occ, s->wpr, s->W, s->owner, s->ctr, s->stream),
+    SF_HIP(sf::launch_fill_u64(s->owner, (size_t)s->W * s->H, ~0ull, s->stream), "clear owners");
+    SF_HIP(sf::launch_occ_init(s->pos, s->N, s->occ, s->wpr, s->W, s->ext, s->owner, s->ctr,
+                               s->stream),
            "occupancy");
-    SF_HIP(sf::launch_field_list(s->lc, s->occ, s->wpr, s->tab, s->S, s->P, s->W, s->H, s->stream),
-           "superpose");
+    SF_HIP(sf::launch_field_one(s->fl, s->view, s->strips_per_block, s->stream), "superpose");
     return SF_OK;
 }
 
@@ -302,6 +357,57 @@ int build_statics(sf_scene *s, const uint8_t *h_obst, const uint8_t *h_exit)
     return SF_OK;
 }
 
+int setup_launches(sf_scene *s);
+
+// Positions by caller id -> internal order (see sf_scene::ext), uploaded with
+// the id map.  Blocks until the copies are done.
+int upload_positions(sf_scene *s, const int32_t *pos)
+{
+    const int N = s->N;
+    std::vector<int32_t> order((size_t)N), pint((size_t)N);
+    for (int i = 0; i < N; ++i) order[(size_t)i] = i;
+    // evacuated (-1) compare as the largest unsigned value: they go last
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return (uint32_t)pos[a] < (uint32_t)pos[b]; });
+    for (int i = 0; i < N; ++i) pint[(size_t)i] = pos[order[(size_t)i]];
+    s->h_ext = order;
+    if (N) {
+        SF_HIP(hipMemcpyAsync(s->pos, pint.data(), (size_t)N * sizeof(int32_t),
+                              hipMemcpyHostToDevice, s->stream),
+               "copy positions");
+        SF_HIP(hipMemcpyAsync(s->ext, order.data(), (size_t)N * sizeof(int32_t),
+                              hipMemcpyHostToDevice, s->stream),
+               "copy id map");
+    }
+    SF_HIP(hipStreamSynchronize(s->stream), "positions sync");
+    return SF_OK;
+}
+
+// Copy a per-pedestrian array to caller order: dst[ext[i]] = src[i].
+template <typename T>
+int copy_by_caller_id(const sf_scene *s, T *dst, const T *src, int dst_on_device)
+{
+    const int N = s->N;
+    if (!dst || N == 0) return SF_OK;
+    if (dst_on_device) {
+        hipError_t e;
+        if constexpr (sizeof(T) == 4)
+            e = sf::launch_scatter_i32(reinterpret_cast<const int32_t *>(src), s->ext,
+                                       reinterpret_cast<int32_t *>(dst), N, s->stream);
+        else
+            e = sf::launch_scatter_u8(reinterpret_cast<const uint8_t *>(src), s->ext,
+                                      reinterpret_cast<uint8_t *>(dst), N, s->stream);
+        SF_HIP(e, "scatter by id");
+        return SF_OK;
+    }
+    std::vector<T> tmp((size_t)N);
+    SF_HIP(hipMemcpyAsync(tmp.data(), src, (size_t)N * sizeof(T), hipMemcpyDeviceToHost, s->stream),
+           "copy out");
+    SF_HIP(hipStreamSynchronize(s->stream), "copy out sync");
+    for (int i = 0; i < N; ++i) dst[s->h_ext[(size_t)i]] = tmp[(size_t)i];
+    return SF_OK;
+}
+
 int create(const sf_scene_desc *d, void *hip_stream, sf_scene **out)
 {
     int rc = validate(d);
@@ -332,6 +438,7 @@ int create(const sf_scene_desc *d, void *hip_stream, sf_scene **out)
     s->seed = d->seed;
     s->start_step = d->start_step;
     s->stream = static_cast<hipStream_t>(hip_stream);
+    s->own_stream = s->stream;
     SF_HIP(hipGetDevice(&s->device), "hipGetDevice");
     SF_HIP(hipDeviceGetAttribute(&s->ncu, hipDeviceAttributeMultiprocessorCount, s->device),
            "CU count");
@@ -343,22 +450,23 @@ int create(const sf_scene_desc *d, void *hip_stream, sf_scene **out)
            "LDS size");
     s->lc = sf::pick_list_cfg(s->R, (size_t)max_lds - 1024);
     if (const char *e = std::getenv("SF_TILE")) {
-        // launch-shape override "TWxHLxVECxNW"; the field does not depend on it
-        // bit for bit, the speed does
-        int a = 0, b = 0, v = 0, w = 0, mode = 1;
-        const int got = std::sscanf(e, "%dx%dx%dx%dx%d", &a, &b, &v, &w, &mode);
+        // launch-shape override "TWxHLxVECxNW[xCAP]"; the field does not
+        // depend on it bit for bit, the speed does
+        int a = 0, b = 0, v = 0, w = 0, cap = 2048;
+        const int got = std::sscanf(e, "%dx%dx%dx%dx%d", &a, &b, &v, &w, &cap);
         if (got != 4 && got != 5)
-            return fail(SF_EINVAL, "SF_TILE=%s is not of the form TWxHLxVECxNW[xMODE]", e);
-        s->lc = sf::make_list_cfg(s->R, a, b, v, w, mode ? 512 : 2048, mode != 0);
-        const bool known = sf::list_shape_compiled(a, b, v, w);
-        if (!known || s->lc.halo_rows > (mode ? 3 * 64 : 64 * w))
-            return fail(SF_EINVAL, "SF_TILE=%s is not a compiled shape for radius %d", e, s->R);
+            return fail(SF_EINVAL, "SF_TILE=%s is not of the form TWxHLxVECxNW[xCAP]", e);
+        if (!sf::list_shape_compiled(a, b, v, w) || cap < 1 || cap > (1 << 16))
+            return fail(SF_EINVAL, "SF_TILE=%s is not a compiled shape", e);
+        s->lc = sf::make_list_cfg(s->R, a, b, v, w, cap);
+        if (s->lc.halo_rows > 64 * w)
+            return fail(SF_EINVAL, "SF_TILE=%s does not fit radius %d", e, s->R);
     }
     if (s->lc.lds_bytes == 0 || s->lc.lds_bytes > (size_t)max_lds - 1024 ||
         s->lc.list_cap < 2 * s->lc.max_row)
         return fail(SF_EINVAL, "field of radius %d does not fit %d B of LDS", s->R, max_lds);
     // the kernel also holds a few bytes of static LDS
-    SF_HIP(sf::set_field_list_lds_limit((size_t)max_lds - 1024), "LDS limit");
+    SF_HIP(sf::set_field_lds_limit((size_t)max_lds - 1024), "LDS limit");
     {
         int per_cu = (int)std::max<size_t>(1, (size_t)(160 * 1024) / s->lc.lds_bytes);
         per_cu = std::min(per_cu, std::max(1, 32 / (s->lc.nw)));
@@ -373,6 +481,7 @@ int create(const sf_scene_desc *d, void *hip_stream, sf_scene **out)
         (rc = dalloc(s, &s->occ, (size_t)s->wpr * s->H, "occupancy")) ||
         (rc = dalloc(s, &s->claim, n, "claims")) || (rc = dalloc(s, &s->key, N, "keys")) ||
         (rc = dalloc(s, &s->pos, N, "positions")) || (rc = dalloc(s, &s->target, N, "targets")) ||
+        (rc = dalloc(s, &s->ext, N, "id map")) ||
         (rc = dalloc(s, &s->owner, n, "owners")) ||
         (rc = dalloc(s, &s->flags, (N + 3) & ~(size_t)3, "flags")) ||
         (rc = dalloc(s, &s->ctr, sf::kCtrWords, "counters")))
@@ -384,9 +493,7 @@ int create(const sf_scene_desc *d, void *hip_stream, sf_scene **out)
     SF_HIP(sf::launch_fill_i32(reinterpret_cast<int32_t *>(s->flags), (N + 3) / 4, 0, st),
            "clear flags");
     SF_HIP(sf::launch_phi_copies(s->tab, s->lc, s->k, s->alpha, st), "phi table");
-    if (N)
-        SF_HIP(hipMemcpyAsync(s->pos, d->pos, N * sizeof(int32_t), hipMemcpyHostToDevice, st),
-               "copy positions");
+    if ((rc = upload_positions(s, d->pos))) return rc;
     if ((rc = build_statics(s, d->obstacle, d->exit))) return rc;
     {
         // own-field values at axial and diagonal neighbours, as the kernels see them
@@ -396,12 +503,50 @@ int create(const sf_scene_desc *d, void *hip_stream, sf_scene **out)
                "phi copy");
         SF_HIP(hipMemcpyAsync(&s->phi_diag, s->tab + id, sizeof(float), hipMemcpyDeviceToHost, st),
                "phi copy");
+        SF_HIP(hipStreamSynchronize(st), "phi sync");
     }
+    if ((rc = setup_launches(s))) return rc;
     if ((rc = reset_counters(s, s->start_step, 0))) return rc;
     if ((rc = rebuild_dynamic(s))) return rc;
     SF_HIP(hipStreamSynchronize(st), "create sync");
     *out = s;
     s = nullptr;  // ownership passes to the caller
+    return SF_OK;
+}
+
+// The scene's view (passed by value to its per-tick kernels) and the field's
+// work items.
+int setup_launches(sf_scene *s)
+{
+    SceneView &v = s->view;
+    v = SceneView{};
+    v.W = s->W;
+    v.H = s->H;
+    v.wpr = s->wpr;
+    v.N = s->N;
+    v.R = s->R;
+    v.chunk = s->chunk;
+    v.dec_block0 = 0;
+    v.com_block0 = 0;
+    v.phi_axial = s->phi_axial;
+    v.phi_diag = s->phi_diag;
+    v.seed = s->seed;
+    v.S = s->S;
+    v.P = s->P;
+    v.occ = s->occ;
+    v.claim = s->claim;
+    v.key = s->key;
+    v.ctr = s->ctr;
+    v.owner = s->owner;
+    v.pos = s->pos;
+    v.target = s->target;
+    v.flags = s->flags;
+    v.exitm = s->exitm;
+    v.ext = s->ext;
+    sf::set_view_layout(v, s->lc, s->tab);
+    s->fl = sf::field_launch_for(s->lc);
+    // one strip per item: workgroup b takes strips b, b + grid, ...
+    s->strips_per_block = 1;
     return SF_OK;
 }
 
@@ -411,17 +556,11 @@ int enqueue_tick(sf_scene *s)
     sf::LaunchEvents ev;
     int rc;
     if ((rc = timing_events(s, SF_KERNEL_DECIDE, &ev))) return rc;
-    SF_HIP(sf::launch_decide_claim(s->chunk, s->occ, s->wpr, s->W, s->H, s->owner, s->P,
-                                   s->phi_axial, s->phi_diag, s->seed, s->target, s->key, s->flags,
-                                   s->claim, s->ctr, st, &ev),
-           "decide");
+    SF_HIP(sf::launch_decide_one(s->view, st, &ev), "decide");
     if ((rc = timing_events(s, SF_KERNEL_COMMIT, &ev))) return rc;
-    SF_HIP(sf::launch_commit(s->N, s->W, s->pos, s->target, s->key, s->flags, s->claim, s->occ,
-                             s->wpr, s->owner, s->exitm, s->ctr, st, &ev),
-           "commit");
+    SF_HIP(sf::launch_commit_one(s->view, st, &ev), "commit");
     if ((rc = timing_events(s, SF_KERNEL_SUPERPOSE, &ev))) return rc;
-    SF_HIP(sf::launch_field_list(s->lc, s->occ, s->wpr, s->tab, s->S, s->P, s->W, s->H, st, &ev),
-           "superpose");
+    SF_HIP(sf::launch_field_one(s->fl, s->view, s->strips_per_block, st, &ev), "superpose");
     return SF_OK;
 }
 
@@ -434,6 +573,369 @@ int copy_out(const sf_scene *s, void *dst, const void *src, size_t bytes, int on
         SF_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s->stream), "copy out");
         SF_HIP(hipStreamSynchronize(s->stream), "copy out sync");
     }
+    return SF_OK;
+}
+
+// ---- batches ---------------------------------------------------------------------
+
+template <typename T>
+int balloc(std::vector<void *> &owned, T **p, size_t n, const char *what)
+{
+    void *q = nullptr;
+    const hipError_t e = hipMalloc(&q, (n ? n : 1) * sizeof(T));
+    if (e != hipSuccess) return hip_fail(e, what);
+    owned.push_back(q);
+    *p = static_cast<T *>(q);
+    return SF_OK;
+}
+
+void free_layout(BatchLayout &L)
+{
+    for (void *p : L.bufs) (void)hipFree(p);
+    L = BatchLayout{};
+}
+
+void drop_graphs(sf_batch *b)
+{
+    for (auto &g : b->graphs) {
+        (void)hipGraphExecDestroy(g.second.second);
+        (void)hipGraphDestroy(g.second.first);
+    }
+    b->graphs.clear();
+}
+
+int max_radius(const sf_batch *b)
+{
+    int r = 0;
+    for (const sf_scene *s : b->scenes) r = std::max(r, s->R);
+    return r;
+}
+
+// Fill in the defaults of `in` and check it against the batch's largest
+// radius; `lc` receives the launch shape at that radius.
+int resolve_tiling(const sf_batch *b, const sf_batch_tiling *in, sf_batch_tiling *out,
+                   ListCfg *lc)
+{
+    sf_batch_tiling t = in ? *in : sf_batch_tiling{};
+    const int R = max_radius(b);
+    const size_t lds_cap = b->max_lds - 1024;
+    if (t.tw == 0 && t.hl == 0 && t.vec == 0 && t.nw == 0) {
+        const ListCfg d = sf::pick_list_cfg(R, lds_cap);
+        t.tw = d.tw;
+        t.hl = d.hl;
+        t.vec = d.vec;
+        t.nw = d.nw;
+        if (t.list_cap == 0) t.list_cap = d.list_cap;
+    }
+    if (!sf::list_shape_compiled(t.tw, t.hl, t.vec, t.nw))
+        return fail(SF_EINVAL, "tiling %dx%dx%dx%d is not a compiled shape", t.tw, t.hl, t.vec,
+                    t.nw);
+    if (t.list_cap == 0) {
+        for (int cap = 4096; cap >= 512; cap /= 2) {
+            const ListCfg c = sf::make_list_cfg(R, t.tw, t.hl, t.vec, t.nw, cap);
+            if (c.lds_bytes <= lds_cap) {
+                t.list_cap = cap;
+                break;
+            }
+        }
+    }
+    if (t.list_cap < 0 || t.list_cap > (1 << 16))
+        return fail(SF_EINVAL, "list_cap %d outside 0..65536", t.list_cap);
+    const ListCfg c = sf::make_list_cfg(R, t.tw, t.hl, t.vec, t.nw, t.list_cap);
+    if (c.list_cap < 2 * c.max_row || c.halo_rows > 64 * t.nw || c.lds_bytes > lds_cap)
+        return fail(SF_EINVAL, "tiling %dx%dx%dx%d with list_cap %d does not fit radius %d",
+                    t.tw, t.hl, t.vec, t.nw, t.list_cap, R);
+    const int bpc_max = std::max(1, std::min((int)((160 * 1024) / c.lds_bytes), 32 / t.nw));
+    if (t.blocks_per_cu == 0) t.blocks_per_cu = bpc_max;
+    if (t.blocks_per_cu < 1 || t.blocks_per_cu > 64)
+        return fail(SF_EINVAL, "blocks_per_cu %d outside 1..64", t.blocks_per_cu);
+    if (t.items_per_block == 0) t.items_per_block = 8;
+    if (t.items_per_block < 1 || t.items_per_block > 4096)
+        return fail(SF_EINVAL, "items_per_block %d outside 1..4096", t.items_per_block);
+    if (t.max_chunk == 0) t.max_chunk = 32;
+    if (t.max_chunk < 4 || t.max_chunk > 64 || (t.max_chunk & (t.max_chunk - 1)))
+        return fail(SF_EINVAL, "max_chunk %d is not a power of two in 4..64", t.max_chunk);
+    *out = t;
+    *lc = c;
+    return SF_OK;
+}
+
+int build_layout(sf_batch *b, const sf_batch_tiling *req, BatchLayout *out)
+{
+    BatchLayout L;
+    struct Guard {
+        BatchLayout *L;
+        ~Guard()
+        {
+            if (L) free_layout(*L);
+        }
+    } guard{&L};
+    ListCfg lmax;
+    int rc = resolve_tiling(b, req, &L.t, &lmax);
+    if (rc) return rc;
+    const sf_batch_tiling &t = L.t;
+    L.fl = sf::field_launch_for(lmax);
+    L.fl.grid = b->ncu * t.blocks_per_cu;
+    hipStream_t st = b->stream;
+
+    const int n = (int)b->scenes.size();
+    std::vector<SceneView> views((size_t)n);
+    std::vector<double> strip_cost((size_t)n);
+    std::map<std::tuple<int, double, double>, float *> tables;
+    int64_t dec_total = 0, com_total = 0;
+    for (int j = 0; j < n; ++j) {
+        const sf_scene *s = b->scenes[(size_t)j];
+        const ListCfg lc = sf::make_list_cfg(s->R, t.tw, t.hl, t.vec, t.nw, t.list_cap);
+        const auto key = std::make_tuple(s->R, s->k, s->alpha);
+        float *&tab = tables[key];
+        if (!tab) {
+            if ((rc = balloc(L.bufs, &tab, (size_t)lc.vec * lc.copy_elems, "batch phi table")))
+                return rc;
+            SF_HIP(sf::launch_phi_copies(tab, lc, s->k, s->alpha, st), "batch phi table");
+        }
+        SceneView v = s->view;
+        sf::set_view_layout(v, lc, tab);
+        v.chunk = std::min(s->chunk, t.max_chunk);
+        v.dec_block0 = (int32_t)dec_total;
+        v.com_block0 = (int32_t)com_total;
+        dec_total += sf::decide_blocks(s->wpr, s->H, v.chunk);
+        com_total += sf::commit_blocks(s->N);
+        if (dec_total >= INT32_MAX / 2 || com_total >= INT32_MAX / 2)
+            return fail(SF_EINVAL, "batch too large for one launch");
+        L.max_chunk = std::max(L.max_chunk, v.chunk);
+        views[(size_t)j] = v;
+        // relative cost of one strip: its su, plus the sources each wave
+        // gathers (density times the wave tile's halo window)
+        const double rho = (double)s->N / ((double)s->W * s->H);
+        strip_cost[(size_t)j] = (double)lc.tw * lc.wt +
+                                4.0 * lc.nw * rho * (lc.tw + 2.0 * s->R) * (lc.th + 2.0 * s->R);
+    }
+    L.dec_blocks = (int)dec_total;
+    L.com_blocks = (int)com_total;
+    std::vector<int32_t> dec_scene((size_t)dec_total), com_scene((size_t)com_total);
+    for (int j = 0; j < n; ++j) {
+        const SceneView &v = views[(size_t)j];
+        const int64_t d1 = j + 1 < n ? views[(size_t)j + 1].dec_block0 : dec_total;
+        const int64_t c1 = j + 1 < n ? views[(size_t)j + 1].com_block0 : com_total;
+        std::fill(dec_scene.begin() + v.dec_block0, dec_scene.begin() + d1, j);
+        std::fill(com_scene.begin() + v.com_block0, com_scene.begin() + c1, j);
+    }
+
+    // field items: runs of strips of about equal estimated cost, scenes that
+    // share a table adjacent (largest radius first), so that a workgroup's
+    // successive items rarely reload the table
+    double total = 0.0;
+    for (int j = 0; j < n; ++j) total += strip_cost[(size_t)j] * views[(size_t)j].n_strips;
+    const double per_item = total / std::max(1.0, (double)L.fl.grid * t.items_per_block);
+    std::vector<int> order((size_t)n);
+    for (int j = 0; j < n; ++j) order[(size_t)j] = j;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
+        const sf_scene *x = b->scenes[(size_t)a], *y = b->scenes[(size_t)c];
+        return std::make_tuple(-x->R, x->k, x->alpha, -strip_cost[(size_t)a]) <
+               std::make_tuple(-y->R, y->k, y->alpha, -strip_cost[(size_t)c]);
+    });
+    std::vector<int32_t> items;
+    for (int j : order) {
+        const int ns = views[(size_t)j].n_strips;
+        const int per = (int)std::max(1.0, std::min((double)ns,
+                                                    std::floor(per_item / strip_cost[(size_t)j] + 0.5)));
+        for (int a = 0; a < ns; a += per) {
+            items.push_back(j);
+            items.push_back(a);
+            items.push_back(std::min(ns, a + per));
+            items.push_back(0);
+        }
+    }
+    L.n_items = (int)(items.size() / 4);
+
+    if ((rc = balloc(L.bufs, &L.d_views, views.size(), "batch views")) ||
+        (rc = balloc(L.bufs, &L.d_dec_scene, dec_scene.size(), "batch decide map")) ||
+        (rc = balloc(L.bufs, &L.d_com_scene, com_scene.size(), "batch commit map")) ||
+        (rc = balloc(L.bufs, &L.d_items, items.size(), "batch items")) ||
+        (rc = balloc(L.bufs, &L.d_totals, views.size() * 8, "batch totals")))
+        return rc;
+    SF_HIP(hipMemcpyAsync(L.d_views, views.data(), views.size() * sizeof(SceneView),
+                          hipMemcpyHostToDevice, st),
+           "batch views");
+    SF_HIP(hipMemcpyAsync(L.d_dec_scene, dec_scene.data(), dec_scene.size() * 4,
+                          hipMemcpyHostToDevice, st),
+           "batch decide map");
+    SF_HIP(hipMemcpyAsync(L.d_com_scene, com_scene.data(), com_scene.size() * 4,
+                          hipMemcpyHostToDevice, st),
+           "batch commit map");
+    SF_HIP(hipMemcpyAsync(L.d_items, items.data(), items.size() * 4, hipMemcpyHostToDevice, st),
+           "batch items");
+    SF_HIP(hipStreamSynchronize(st), "batch layout sync");
+    *out = L;
+    guard.L = nullptr;
+    return SF_OK;
+}
+
+int batch_field(const sf_batch *b, const BatchLayout &L, hipStream_t st,
+                const sf::LaunchEvents *ev = nullptr)
+{
+    SF_HIP(sf::launch_field(L.fl, L.d_views, L.d_items, L.n_items, st, ev), "batch field");
+    return SF_OK;
+}
+
+int batch_tick(const sf_batch *b, hipStream_t st)
+{
+    const BatchLayout &L = b->cur;
+    SF_HIP(sf::launch_decide_claim(L.d_views, L.d_dec_scene, L.dec_blocks, L.max_chunk, st),
+           "batch decide");
+    SF_HIP(sf::launch_commit(L.d_views, L.d_com_scene, L.com_blocks, st), "batch commit");
+    return batch_field(b, L, st);
+}
+
+// Executable graph of `k` ticks, captured on first use.
+int batch_graph(sf_batch *b, int k, hipGraphExec_t *out)
+{
+    auto it = b->graphs.find(k);
+    if (it != b->graphs.end()) {
+        *out = it->second.second;
+        return SF_OK;
+    }
+    SF_HIP(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal), "begin capture");
+    int rc = SF_OK;
+    for (int i = 0; i < k && rc == SF_OK; ++i) rc = batch_tick(b, b->capture);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(b->capture, &g);
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return hip_fail(e, "end capture");
+    hipGraphExec_t x = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (ei != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return hip_fail(ei, "graph instantiate");
+    }
+    b->graphs[k] = std::make_pair(g, x);
+    *out = x;
+    return SF_OK;
+}
+
+constexpr int kGraphTicks = 8;
+
+int batch_create(sf_scene *const *scenes, int32_t n, const sf_batch_tiling *tiling,
+                 void *hip_stream, sf_batch **out)
+{
+    if (!scenes || n <= 0) return fail(SF_EINVAL, "a batch needs at least one scene");
+    int dev = 0;
+    SF_HIP(hipGetDevice(&dev), "hipGetDevice");
+    for (int32_t i = 0; i < n; ++i) {
+        const sf_scene *s = scenes[i];
+        if (!s) return fail(SF_EINVAL, "scene %d is NULL", i);
+        if (s->batch) return fail(SF_EINVAL, "scene %d already belongs to a batch", i);
+        if (s->device != dev) return fail(SF_EINVAL, "scene %d is on device %d, not %d", i, s->device, dev);
+        for (int32_t j = 0; j < i; ++j)
+            if (scenes[j] == s) return fail(SF_EINVAL, "scene %d is listed twice", i);
+    }
+    sf_batch *b = new (std::nothrow) sf_batch;
+    if (!b) return fail(SF_ENOMEM, "host allocation failed");
+    struct Cleanup {
+        sf_batch **b;
+        ~Cleanup()
+        {
+            if (*b) {
+                free_layout((*b)->cur);
+                if ((*b)->capture) (void)hipStreamDestroy((*b)->capture);
+                delete *b;
+            }
+        }
+    } cleanup{&b};
+    b->device = dev;
+    b->stream = static_cast<hipStream_t>(hip_stream);
+    b->scenes.assign(scenes, scenes + n);
+    SF_HIP(hipDeviceGetAttribute(&b->ncu, hipDeviceAttributeMultiprocessorCount, dev), "CU count");
+    int max_lds = 0;
+    SF_HIP(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev),
+           "LDS size");
+    b->max_lds = (size_t)max_lds;
+    SF_HIP(sf::set_field_lds_limit(b->max_lds - 1024), "LDS limit");
+    SF_HIP(hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking), "capture stream");
+    for (sf_scene *s : b->scenes) SF_HIP(hipStreamSynchronize(s->stream), "scene sync");
+    int rc = build_layout(b, tiling, &b->cur);
+    if (rc) return rc;
+    for (sf_scene *s : b->scenes) {
+        s->batch = b;
+        s->stream = b->stream;
+    }
+    *out = b;
+    b = nullptr;
+    return SF_OK;
+}
+
+int batch_tune(sf_batch *b, int32_t reps, sf_batch_tiling *chosen)
+{
+    if (reps < 1 || reps > 1000) return fail(SF_EINVAL, "reps %d outside 1..1000", reps);
+    SF_HIP(hipStreamSynchronize(b->stream), "tune sync");
+    EventPair ep;
+    SF_HIP(hipEventCreateWithFlags(&ep.a, hipEventDisableSystemFence), "hipEventCreate");
+    const hipError_t eb = hipEventCreateWithFlags(&ep.b, hipEventDisableSystemFence);
+    struct Ev {
+        EventPair *p;
+        ~Ev()
+        {
+            if (p->a) (void)hipEventDestroy(p->a);
+            if (p->b) (void)hipEventDestroy(p->b);
+        }
+    } ev_guard{&ep};
+    if (eb != hipSuccess) return hip_fail(eb, "hipEventCreate");
+
+    static const int shapes[][4] = {{16, 2, 2, 4}, {16, 2, 2, 8}, {16, 4, 2, 4}, {16, 4, 2, 8},
+                                    {16, 4, 4, 4}, {16, 4, 4, 8}, {32, 2, 2, 4}, {32, 2, 2, 8},
+                                    {32, 4, 2, 4}, {32, 4, 4, 4}, {8, 4, 4, 4},  {8, 2, 2, 4}};
+    const int caps[] = {1024, 2048, 4096};
+    const int ipbs[] = {2, 8};
+    double best_ms = 1e30;
+    sf_batch_tiling best = b->cur.t;
+    std::vector<float> ms((size_t)reps);
+    for (const auto &sh : shapes) {
+        for (int cap : caps) {
+            for (int ipb : ipbs) {
+                sf_batch_tiling t = b->cur.t;
+                t.tw = sh[0];
+                t.hl = sh[1];
+                t.vec = sh[2];
+                t.nw = sh[3];
+                t.list_cap = cap;
+                t.blocks_per_cu = 0;
+                t.items_per_block = ipb;
+                BatchLayout L;
+                if (build_layout(b, &t, &L) != SF_OK) continue;  // shape does not fit
+                int rc = SF_OK;
+                const sf::LaunchEvents lev{ep.a, ep.b};
+                for (int r = 0; r < reps && rc == SF_OK; ++r) {
+                    rc = batch_field(b, L, b->stream, &lev);
+                    if (rc == SF_OK) {
+                        const hipError_t e1 = hipEventSynchronize(ep.b);
+                        const hipError_t e2 = e1 == hipSuccess
+                                                  ? hipEventElapsedTime(&ms[(size_t)r], ep.a, ep.b)
+                                                  : e1;
+                        if (e2 != hipSuccess) rc = hip_fail(e2, "tune timing");
+                    }
+                }
+                free_layout(L);
+                if (rc) return rc;
+                std::vector<float> sorted = ms;
+                std::sort(sorted.begin(), sorted.end());
+                const double med = sorted[sorted.size() / 2];
+                if (med < best_ms) {
+                    best_ms = med;
+                    best = t;
+                }
+            }
+        }
+    }
+    BatchLayout L;
+    int rc = build_layout(b, &best, &L);
+    if (rc) return rc;
+    drop_graphs(b);
+    free_layout(b->cur);
+    b->cur = L;
+    if (chosen) *chosen = b->cur.t;
     return SF_OK;
 }
 
@@ -459,6 +961,7 @@ int sf_step(sf_scene *s, int32_t n_steps)
 {
     if (!s) return fail(SF_EINVAL, "scene is NULL");
     if (n_steps < 0) return fail(SF_EINVAL, "n_steps %d is negative", n_steps);
+    if (s->batch) return fail(SF_EINVAL, "the scene belongs to a batch: step the batch");
     DeviceGuard g(s->device);
     try {
         for (int32_t i = 0; i < n_steps; ++i) {
@@ -482,7 +985,12 @@ int sf_positions(const sf_scene *s, int32_t *pos, uint8_t *alive, int dst_on_dev
 {
     if (!s || !pos) return fail(SF_EINVAL, "scene or pos is NULL");
     DeviceGuard g(s->device);
-    int rc = copy_out(s, pos, s->pos, (size_t)s->N * sizeof(int32_t), dst_on_device);
+    int rc;
+    try {
+        rc = copy_by_caller_id(s, pos, (const int32_t *)s->pos, dst_on_device);
+    } catch (const std::bad_alloc &) {
+        return fail(SF_ENOMEM, "host allocation failed");
+    }
     if (rc || !alive) return rc;
     if (dst_on_device) return fail(SF_EINVAL, "alive flags are only produced in host memory");
     for (int i = 0; i < s->N; ++i) alive[i] = pos[i] >= 0;
@@ -493,9 +1001,13 @@ int sf_last_moves(const sf_scene *s, int32_t *target, uint8_t *flags, int dst_on
 {
     if (!s) return fail(SF_EINVAL, "scene is NULL");
     DeviceGuard g(s->device);
-    int rc = copy_out(s, target, s->target, (size_t)s->N * sizeof(int32_t), dst_on_device);
-    if (rc) return rc;
-    return copy_out(s, flags, s->flags, (size_t)s->N, dst_on_device);
+    try {
+        int rc = copy_by_caller_id(s, target, (const int32_t *)s->target, dst_on_device);
+        if (rc) return rc;
+        return copy_by_caller_id(s, flags, (const uint8_t *)s->flags, dst_on_device);
+    } catch (const std::bad_alloc &) {
+        return fail(SF_ENOMEM, "host allocation failed");
+    }
 }
 
 int sf_static_field(const sf_scene *s, float *S, int32_t *D, int dst_on_device)
@@ -513,6 +1025,7 @@ int sf_set_state(sf_scene *s, const int32_t *pos, int64_t step)
     if (!s) return fail(SF_EINVAL, "scene is NULL");
     if (step < 0) return fail(SF_EINVAL, "step %lld is negative", (long long)step);
     if (s->N > 0 && !pos) return fail(SF_EINVAL, "pos is NULL");
+    if (s->batch) return fail(SF_EINVAL, "the scene belongs to a batch");
     DeviceGuard g(s->device);
     try {
         const size_t n = (size_t)s->W * s->H;
@@ -529,10 +1042,7 @@ int sf_set_state(sf_scene *s, const int32_t *pos, int64_t step)
         int64_t gone = 0;
         for (int i = 0; i < s->N; ++i) gone += pos[i] < 0;
         hipStream_t st = s->stream;
-        if (s->N)
-            SF_HIP(hipMemcpyAsync(s->pos, pos, (size_t)s->N * sizeof(int32_t),
-                                  hipMemcpyHostToDevice, st),
-                   "copy positions");
+        if ((rc = upload_positions(s, pos))) return rc;
         if ((rc = reset_counters(s, step, gone))) return rc;
         SF_HIP(sf::launch_fill_u64(s->claim, n, ~0ull, st), "clear claims");
         SF_HIP(sf::launch_fill_i32(s->target, (size_t)s->N, 0, st), "clear targets");
@@ -600,6 +1110,119 @@ int sf_kernel_time(const sf_scene *s, int kernel, double *total_ms, int64_t *lau
 }
 
 void sf_destroy_scene(sf_scene *s) { release(s); }
+
+int sf_batch_create(sf_scene *const *scenes, int32_t n_scenes, const sf_batch_tiling *tiling,
+                    void *hip_stream, sf_batch **out)
+{
+    g_last_error.clear();
+    if (!out) return fail(SF_EINVAL, "out is NULL");
+    *out = nullptr;
+    try {
+        return batch_create(scenes, n_scenes, tiling, hip_stream, out);
+    } catch (const std::bad_alloc &) {
+        return fail(SF_ENOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(SF_EDEVICE, "unexpected failure in sf_batch_create");
+    }
+}
+
+int sf_batch_tune(sf_batch *b, int32_t reps, sf_batch_tiling *chosen)
+{
+    if (!b) return fail(SF_EINVAL, "batch is NULL");
+    if (b->broken) return fail(SF_EINVAL, "a member scene of the batch was destroyed");
+    DeviceGuard g(b->device);
+    try {
+        return batch_tune(b, reps, chosen);
+    } catch (const std::bad_alloc &) {
+        return fail(SF_ENOMEM, "host allocation failed");
+    }
+}
+
+int sf_batch_get_tiling(const sf_batch *b, sf_batch_tiling *out)
+{
+    if (!b || !out) return fail(SF_EINVAL, "batch or out is NULL");
+    *out = b->cur.t;
+    return SF_OK;
+}
+
+int sf_batch_step(sf_batch *b, int32_t n_steps)
+{
+    if (!b) return fail(SF_EINVAL, "batch is NULL");
+    if (n_steps < 0) return fail(SF_EINVAL, "n_steps %d is negative", n_steps);
+    if (b->broken) return fail(SF_EINVAL, "a member scene of the batch was destroyed");
+    DeviceGuard g(b->device);
+    try {
+        if (n_steps == 1) {
+            // a single tick is launched directly (a batch whose membership
+            // changes every tick would not reuse a captured graph)
+            return batch_tick(b, b->stream);
+        }
+        while (n_steps > 0) {
+            const int k = std::min(n_steps, kGraphTicks);
+            hipGraphExec_t x = nullptr;
+            const int rc = batch_graph(b, k, &x);
+            if (rc) return rc;
+            SF_HIP(hipGraphLaunch(x, b->stream), "graph launch");
+            n_steps -= k;
+        }
+    } catch (const std::bad_alloc &) {
+        return fail(SF_ENOMEM, "host allocation failed");
+    }
+    return SF_OK;
+}
+
+int sf_batch_stats(const sf_batch *b, sf_stats_t *out)
+{
+    if (!b || !out) return fail(SF_EINVAL, "batch or out is NULL");
+    if (b->broken) return fail(SF_EINVAL, "a member scene of the batch was destroyed");
+    DeviceGuard g(b->device);
+    try {
+        const size_t n = b->scenes.size();
+        std::vector<unsigned long long> h(n * 8);
+        SF_HIP(sf::launch_sum_counters(b->cur.d_views, (int)n, b->cur.d_totals, b->stream),
+               "batch totals");
+        SF_HIP(hipMemcpyAsync(h.data(), b->cur.d_totals, h.size() * 8, hipMemcpyDeviceToHost,
+                              b->stream),
+               "batch totals copy");
+        SF_HIP(hipStreamSynchronize(b->stream), "batch totals sync");
+        for (size_t j = 0; j < n; ++j) {
+            const unsigned long long *w = &h[j * 8];
+            out[j].step = (int64_t)w[0];
+            out[j].live = (int64_t)w[1 + sf::kLive];
+            out[j].evacuated = (int64_t)w[1 + sf::kEvacuated];
+            out[j].ped_steps = (int64_t)w[1 + sf::kPedSteps];
+            out[j].movers = (int64_t)w[1 + sf::kMovers];
+            out[j].moved = (int64_t)w[1 + sf::kMoved];
+            out[j].tied = (int64_t)w[1 + sf::kTied];
+        }
+    } catch (const std::bad_alloc &) {
+        return fail(SF_ENOMEM, "host allocation failed");
+    }
+    return SF_OK;
+}
+
+int sf_batch_sync(const sf_batch *b)
+{
+    if (!b) return fail(SF_EINVAL, "batch is NULL");
+    DeviceGuard g(b->device);
+    SF_HIP(hipStreamSynchronize(b->stream), "batch sync");
+    return SF_OK;
+}
+
+void sf_batch_destroy(sf_batch *b)
+{
+    if (!b) return;
+    DeviceGuard g(b->device);
+    (void)hipStreamSynchronize(b->stream);
+    for (sf_scene *s : b->scenes) {
+        s->batch = nullptr;
+        s->stream = s->own_stream;
+    }
+    drop_graphs(b);
+    free_layout(b->cur);
+    if (b->capture) (void)hipStreamDestroy(b->capture);
+    delete b;
+}
 
 const char *sf_last_error(void) { return g_last_error.c_str(); }
 

@@ -65,7 +65,7 @@ SupCfg make_sup_cfg(int radius, int tw, int hl, size_t elem);
 // VEC-wide LDS loads (one contiguous access per lane).  The stamp is kept
 // in VEC copies, copy c shifted down by c rows, so that a source at row py
 // reads copy (py - pady) mod VEC aligned:
-//   copy c, entry (dx, dy) at c*ncols*stride + (dx + padx)*stride + dy + pady + c
+//   copy c, entry (dx, dy) at c*copy_elems + (dx + padx)*stride + dy + pady + c
 //   padx = R + TW (one zero column beyond the halo for padding entries),
 //   pady = R + TH - 1, stride >= 2*pady + VEC, stride = VEC * odd (banks).
 // The strip's halo sources are listed in LDS in row-major order; the list
@@ -75,25 +75,80 @@ struct ListCfg {
     int g = 0, th = 0, wt = 0;
     int radius = 0;
     int padx = 0, pady = 0, ncols = 0, nrows = 0, stride = 0;
-    int copy_elems = 0;  // ncols * stride
+    int copy_elems = 0;  // ncols * stride rounded up to a multiple of 4
     int list_cap = 0;
     int max_row = 0;     // most sources one halo row can hold
-    int halo_rows = 0;   // most halo rows of one strip (one wave tile in wave mode)
-    bool wave_lists = false;  // wave-private lists (k_field_wave) instead of one per strip
+    int halo_rows = 0;   // most halo rows of one strip
     size_t lds_bytes = 0;
     int grid = 0;
 };
-ListCfg make_list_cfg(int radius, int tw, int hl, int vec, int nw, int list_cap,
-                      bool wave_lists);
+ListCfg make_list_cfg(int radius, int tw, int hl, int vec, int nw, int list_cap);
 // Picks the launch shape for radius R that fits `max_lds` bytes of LDS.
 ListCfg pick_list_cfg(int radius, size_t max_lds);
+bool list_shape_compiled(int tw, int hl, int vec, int nw);
 hipError_t launch_phi_copies(float *tab, const ListCfg &c, double k, double alpha,
                              hipStream_t st);
-hipError_t launch_field_list(const ListCfg &c, const unsigned long long *bits, int wpr,
-                             const float *tab, const float *S, float *P, int W, int H,
-                             hipStream_t st, const LaunchEvents *ev = nullptr);
-hipError_t set_field_list_lds_limit(size_t bytes);
-bool list_shape_compiled(int tw, int hl, int vec, int nw);
+// Dynamic LDS limit of the field and decide kernels.
+hipError_t set_field_lds_limit(size_t bytes);
+
+// What the per-tick kernels read of one scene.  A launch covers one or more
+// scenes; every scene of a launch has its own view.
+struct SceneView {
+    int32_t W, H, wpr, N;
+    int32_t R;
+    int32_t chunk;       // decide: bitmap words per wave
+    int32_t dec_block0;  // first workgroup of this scene in the decide launch
+    int32_t com_block0;  // first workgroup of this scene in the commit launch
+    // field gather layout of this scene's radius under the launch's tile shape
+    int32_t tiles_x, n_strips, copy_elems, stride;
+    int32_t padx, pady, max_row, tab_elems;
+    float phi_axial, phi_diag;  // own-field values at axial / diagonal neighbours
+    unsigned long long seed;
+    const float *tab;           // tab_elems floats: the VEC stamp copies
+    const float *S;
+    float *P;
+    unsigned long long *occ, *claim, *key, *ctr;
+    // per-pedestrian arrays are indexed by an internal id (pedestrians in
+    // row-major order of their positions when the state was set); ext maps
+    // it to the caller's id, which keys the election.  owner[su] holds
+    // (caller id << 32) | internal id of the pedestrian there, ~0 if none.
+    unsigned long long *owner;
+    int32_t *pos, *target;
+    uint8_t *flags;
+    const uint8_t *exitm;
+    const int32_t *ext;
+};
+
+// Field layout fields of `v` for shape `c` (built for the scene's radius).
+void set_view_layout(SceneView &v, const ListCfg &c, const float *tab);
+
+// Workgroups of a scene in the decide and commit launches.
+int decide_blocks(int wpr, int H, int chunk);
+int commit_blocks(int N);
+
+// One field launch over `n_items` work items (int4: scene, first strip,
+// end strip, unused).  Workgroup b takes items b, b + grid, b + 2*grid, ...
+// `tab_max` is the largest tab_elems of the launch's scenes and `halo_max`
+// the largest halo row count; both size the dynamic LDS.
+struct FieldLaunch {
+    int tw = 0, hl = 0, vec = 0, nw = 0;
+    int list_cap = 0, tab_max = 0, halo_max = 0;
+    int grid = 0;
+    size_t lds_bytes = 0;
+};
+FieldLaunch field_launch_for(const ListCfg &c);  // tab_max/halo_max of c, grid = c.grid
+size_t field_lds_bytes(const FieldLaunch &f);
+hipError_t launch_field(const FieldLaunch &f, const SceneView *views, const int32_t *items,
+                        int n_items, hipStream_t st, const LaunchEvents *ev = nullptr);
+// Single-scene forms: the view is passed by value.  Field item i is strips
+// [i*per, (i+1)*per) and workgroup b takes items b, b + grid, ... (grid =
+// min(f.grid, items)); decide and commit launch the scene's own blocks.
+hipError_t launch_field_one(const FieldLaunch &f, const SceneView &view, int per,
+                            hipStream_t st, const LaunchEvents *ev = nullptr);
+hipError_t launch_decide_one(const SceneView &view, hipStream_t st,
+                             const LaunchEvents *ev = nullptr);
+hipError_t launch_commit_one(const SceneView &view, hipStream_t st,
+                             const LaunchEvents *ev = nullptr);
 
 // Launchers: all enqueue on `st` and return the launch status.
 hipError_t launch_fill_u64(unsigned long long *p, size_t n, unsigned long long v, hipStream_t st);
@@ -119,19 +174,24 @@ hipError_t set_superpose_lds_limit(size_t f64_bytes);
 hipError_t launch_static_S(const int32_t *D, const double *O, const uint8_t *obst,
                            double w_dest, float *S, int n, hipStream_t st);
 hipError_t launch_occ_init(const int32_t *pos, int N, unsigned long long *occ, int wpr, int W,
-                           int32_t *owner, unsigned long long *ctr, hipStream_t st);
+                           const int32_t *ext, unsigned long long *owner,
+                           unsigned long long *ctr, hipStream_t st);
 // Words of the occupancy bitmap handled per wave by the decide kernel.
 int pick_decide_chunk(int W, int H, int N);
-hipError_t launch_decide_claim(int chunk, const unsigned long long *occ, int wpr, int W, int H,
-                               const int32_t *owner, const float *P, float phi_axial,
-                               float phi_diag, unsigned long long seed, int32_t *target,
-                               unsigned long long *key, uint8_t *flags,
-                               unsigned long long *claim, unsigned long long *ctr,
-                               hipStream_t st, const LaunchEvents *ev = nullptr);
-hipError_t launch_commit(int N, int W, int32_t *pos, int32_t *target,
-                         const unsigned long long *key, uint8_t *flags,
-                         unsigned long long *claim, unsigned long long *occ, int wpr,
-                         int32_t *owner, const uint8_t *exitm, unsigned long long *ctr,
+// Decide + claim over `n_blocks` workgroups.  `block_scene[b]` names the
+// scene of workgroup b (NULL: every workgroup belongs to views[0]);
+// `max_chunk` is the largest chunk of the launch's scenes (sizes the LDS).
+hipError_t launch_decide_claim(const SceneView *views, const int32_t *block_scene, int n_blocks,
+                               int max_chunk, hipStream_t st, const LaunchEvents *ev = nullptr);
+hipError_t launch_commit(const SceneView *views, const int32_t *block_scene, int n_blocks,
                          hipStream_t st, const LaunchEvents *ev = nullptr);
+// dst[ext[i]] = src[i] for i < n (internal to caller order).
+hipError_t launch_scatter_i32(const int32_t *src, const int32_t *ext, int32_t *dst, int n,
+                              hipStream_t st);
+hipError_t launch_scatter_u8(const uint8_t *src, const int32_t *ext, uint8_t *dst, int n,
+                             hipStream_t st);
+// out[j*8 + 0] = step of scene j, out[j*8 + 1 + id] = running total id.
+hipError_t launch_sum_counters(const SceneView *views, int n_scenes, unsigned long long *out,
+                               hipStream_t st);
 
 }  // namespace sf

@@ -16,6 +16,7 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 
@@ -37,7 +38,8 @@ __device__ __forceinline__ unsigned lane_id() { return __lane_id(); }
 // Sum of `v` over the block, added by one thread to copy (block % kSlots) of
 // running total `id` (skipped when 0).  Every thread of the block must call
 // it; it synchronises the block.
-__device__ __forceinline__ void block_sum_add(unsigned int v, unsigned long long *ctr, int id)
+template <typename Ctr>
+__device__ __forceinline__ void block_sum_add(unsigned int v, Ctr ctr, int id)
 {
     __shared__ unsigned int part[16];
     // wave sum by butterfly shuffles
@@ -48,13 +50,16 @@ __device__ __forceinline__ void block_sum_add(unsigned int v, unsigned long long
     if (threadIdx.x == 0) {
         unsigned long long s = 0;
         for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += part[w];
-        if (s) atomicAdd(&ctr[ctr_index(id, blockIdx.x % kSlots)], s);
+        if (s)
+            __hip_atomic_fetch_add(&ctr[ctr_index(id, blockIdx.x % kSlots)], s, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
     }
     __syncthreads();
 }
 
 // Same for a signed delta (two's-complement add).
-__device__ __forceinline__ void block_delta_add(int v, unsigned long long *ctr, int id)
+template <typename Ctr>
+__device__ __forceinline__ void block_delta_add(int v, Ctr ctr, int id)
 {
     __shared__ int part[16];
     for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
@@ -64,7 +69,9 @@ __device__ __forceinline__ void block_delta_add(int v, unsigned long long *ctr, 
     if (threadIdx.x == 0) {
         long long s = 0;
         for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += part[w];
-        if (s) atomicAdd(&ctr[ctr_index(id, blockIdx.x % kSlots)], (unsigned long long)s);
+        if (s)
+            __hip_atomic_fetch_add(&ctr[ctr_index(id, blockIdx.x % kSlots)], (unsigned long long)s,
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     __syncthreads();
 }
@@ -86,6 +93,18 @@ __device__ __forceinline__ unsigned int wave_append(bool pred, unsigned int *cnt
 // Pointer into LDS (address space 3): 32-bit byte addresses, ds_* instructions.
 template <typename T>
 using lds_ptr = const __attribute__((address_space(3))) T *;
+
+// Pointer into device global memory (address space 1).  A pointer read from
+// memory (a scene view) is generic to the compiler, and generic accesses
+// become flat_* instructions, which also occupy the LDS wait counter; held as
+// gptr, its accesses are global_* instructions.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T *;
+template <typename T>
+__device__ __forceinline__ gptr<T> to_global(T *p)
+{
+    return (gptr<T>)p;
+}
 
 // Hides the arithmetic origin of a per-lane value from the optimiser (an empty
 // asm with a VGPR constraint), so that address expressions built on it are not
@@ -346,7 +365,8 @@ __global__ __launch_bounds__(kSupThreads) void k_superpose(
 
 // ---- per-tick field: source-list gather ---------------------------------------------
 //
-// One workgroup per TW-column strip of NW*TH rows (persistent over strips).
+// A workgroup takes work items (runs of TW-column strips of NW*TH rows, each
+// run inside one scene) and for every strip:
 //  1. thread t loads the bitmap words of halo row ya + t and counts its sources;
 //  2. a block-wide exclusive scan turns the counts into list offsets, so the
 //     list holds the strip's halo sources in global row-major order;
@@ -357,7 +377,11 @@ __global__ __launch_bounds__(kSupThreads) void k_superpose(
 //     of its own rows: per source one address add, HL/VEC aligned LDS vector
 //     loads and HL adds per lane.
 // A halo with more than list_cap - max_row sources is processed in several
-// passes over consecutive row ranges, which keeps the row-major order.
+// passes over consecutive row ranges, which keeps the row-major order.  The
+// bitmap rows of the next strip (possibly of the next item and scene) are
+// requested before the current strip is gathered.  The stamp copies are
+// reloaded into LDS when consecutive items belong to scenes with different
+// tables.
 
 template <int VEC>
 struct VecOf;
@@ -414,66 +438,138 @@ __device__ __forceinline__ void gather_one(V *acc, int a)
     for (int q = 0; q < NQ; ++q) acc[q] += v[q];
 }
 
-template <int TW, int HL, int VEC, int NW>
-__global__ __launch_bounds__(NW * 64) void k_field_list(
-    const unsigned long long *__restrict__ bits, int wpr, const float *__restrict__ tab_g,
-    int copy_elems, int stride, int padx, int pady, int R, int list_cap, int max_row,
-    const float *__restrict__ S, float *__restrict__ P, int W, int H, int tiles_x, int n_tiles)
+// The part of a scene's view that the field kernel reads, kept in scalar
+// registers (a whole SceneView copy would be placed in private memory).
+struct FieldScene {
+    int W, H, wpr, R, tiles_x, copy_elems, stride, padx, pady, max_row, tab_elems;
+    gptr<const VecOf<4>::type> tab;
+    gptr<const float> S;
+    gptr<float> P;
+    gptr<const unsigned long long> occ;
+};
+
+__device__ __forceinline__ FieldScene field_scene(const SceneView &v)
 {
+    FieldScene f;
+    f.W = v.W;
+    f.H = v.H;
+    f.wpr = v.wpr;
+    f.R = v.R;
+    f.tiles_x = v.tiles_x;
+    f.copy_elems = v.copy_elems;
+    f.stride = v.stride;
+    f.padx = v.padx;
+    f.pady = v.pady;
+    f.max_row = v.max_row;
+    f.tab_elems = v.tab_elems;
+    f.tab = to_global(reinterpret_cast<const VecOf<4>::type *>(v.tab));
+    f.S = to_global(v.S);
+    f.P = to_global(v.P);
+    f.occ = to_global(v.occ);
+    return f;
+}
+
+// Work items of a field launch.  MULTI: items[i] from the table and the
+// scene views from `views`; otherwise the single scene `one` (a kernel
+// argument, no dependent load) and item i = strips [i*per, (i+1)*per).
+template <bool MULTI>
+struct FieldWork {
+    const SceneView &one;
+    const SceneView *__restrict__ views;
+    const int4 *__restrict__ items;
+    int per;
+    __device__ __forceinline__ int4 item(int i) const
+    {
+        if constexpr (MULTI) return items[i];
+        return make_int4(0, i * per, min(i * per + per, one.n_strips), 0);
+    }
+    __device__ __forceinline__ FieldScene scene(int j) const
+    {
+        if constexpr (MULTI) return field_scene(views[j]);
+        return field_scene(one);
+    }
+};
+
+template <int TW, int HL, int VEC, int NW, bool MULTI>
+__global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
+                                                   const SceneView *__restrict__ views,
+                                                   const int4 *__restrict__ items, int n_items,
+                                                   int per, int tab_max, int list_cap)
+{
+    const FieldWork<MULTI> work{one, views, items, per};
     constexpr int G = 64 / TW, TH = G * HL, WT = NW * TH, NT = NW * 64, NQ = HL / VEC;
     typedef typename VecOf<VEC>::type vec_t;
     typedef const __attribute__((address_space(3))) vec_t *lds_vec;
     extern __shared__ __align__(16) unsigned char lds_raw[];
     __shared__ int wave_tot[NW];
     float *tab = reinterpret_cast<float *>(lds_raw);
-    const int tab_elems = VEC * copy_elems;  // a multiple of 4
-    int *list = reinterpret_cast<int *>(tab + tab_elems);
+    int *list = reinterpret_cast<int *>(tab + tab_max);
     int *row_excl = list + list_cap;
-    for (int i = threadIdx.x; i < tab_elems / 4; i += NT)
-        reinterpret_cast<float4 *>(tab)[i] = reinterpret_cast<const float4 *>(tab_g)[i];
-    __syncthreads();
 
     const int tid = (int)threadIdx.x, lane = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int col = lane % TW, rg = lane / TW;
     const int tbase = (int)(uint32_t)(uintptr_t)((lds_ptr<float>)tab);
-    const int cap = list_cap - max_row;
+
+    int item = (int)blockIdx.x;
+    if (item >= n_items) return;
+    int4 it = work.item(item);
+    FieldScene v = work.scene(it.x);
+    int t = it.y;
+    typedef VecOf<4>::type f4;
+    for (int i = tid; i < v.tab_elems / 4; i += NT) reinterpret_cast<f4 *>(tab)[i] = v.tab[i];
 
     // Strip geometry: halo rows [ya, ya + nr), halo bitmap words [wa, wa + nwd).
     struct Strip {
         int X0, Y0, ya, nr, xa, xb, wa, nwd;
     };
-    auto strip = [&](int t) {
+    auto strip = [&](const FieldScene &s, int ts) {
         Strip g;
-        const int ty = t / tiles_x, tx = t - ty * tiles_x;
+        const int ty = ts / s.tiles_x, tx = ts - ty * s.tiles_x;
         g.X0 = tx * TW;
         g.Y0 = ty * WT;
-        g.ya = max(g.Y0 - R, 0);
-        g.nr = min(g.Y0 + WT - 1 + R, H - 1) - g.ya + 1;
-        g.xa = max(g.X0 - R, 0);
-        g.xb = min(g.X0 + TW - 1 + R, W - 1);
+        g.ya = max(g.Y0 - s.R, 0);
+        g.nr = min(g.Y0 + WT - 1 + s.R, s.H - 1) - g.ya + 1;
+        g.xa = max(g.X0 - s.R, 0);
+        g.xb = min(g.X0 + TW - 1 + s.R, s.W - 1);
         g.wa = g.xa >> 6;
         g.nwd = (g.xb >> 6) - g.wa + 1;
         return g;
     };
-    // bitmap words of this thread's halo row of strip t (issued early: the
+    // bitmap words of this thread's halo row of a strip (issued early: the
     // loads stay in flight across the previous strip's work)
     unsigned long long n0 = 0, n1 = 0, n2 = 0;
-    auto fetch_rows = [&](int t) {
+    auto fetch_rows = [&](const FieldScene &s, int ts) {
         n0 = n1 = n2 = 0;
-        if (t >= n_tiles) return;
-        const Strip g = strip(t);
+        const Strip g = strip(s, ts);
         if (tid < g.nr) {
-            const unsigned long long *row = bits + (size_t)(g.ya + tid) * wpr + g.wa;
+            const gptr<const unsigned long long> row = s.occ + (size_t)(g.ya + tid) * s.wpr + g.wa;
             n0 = row[0];
             if (g.nwd > 1) n1 = row[1];
             if (g.nwd > 2) n2 = row[2];
         }
     };
-    fetch_rows((int)blockIdx.x);
+    fetch_rows(v, t);
+    __syncthreads();
 
-    for (int t = (int)blockIdx.x; t < n_tiles; t += (int)gridDim.x) {
-        const Strip g = strip(t);
+    for (;;) {
+        // the strip after this one: the next of this item, else the first of
+        // this workgroup's next item
+        int nitem = item, nt = t + 1;
+        int4 nit = it;
+        FieldScene nv = v;
+        if (nt >= it.z) {
+            nitem = item + (int)gridDim.x;
+            if (nitem < n_items) {
+                nit = work.item(nitem);
+                nt = nit.y;
+                if (nit.x != it.x) nv = work.scene(nit.x);
+            }
+        }
+        const bool more = nitem < n_items;
+
+        const Strip g = strip(v, t);
+        const int W = v.W, H = v.H, R = v.R, stride = v.stride, padx = v.padx, pady = v.pady;
         const int X0 = g.X0, Y0 = g.Y0, y0w = Y0 + wv * TH;
         const int ya = g.ya, nr = g.nr, xa = g.xa, xb = g.xb, wa = g.wa, nwd = g.nwd;
         const int yb = ya + nr - 1;
@@ -498,10 +594,10 @@ __global__ __launch_bounds__(NW * 64) void k_field_list(
 #pragma unroll
             for (int j = 0; j < VEC; ++j) {
                 const int y = y0w + rg * HL + q * VEC + j;
-                sv[q * VEC + j] = (x < W && y < H) ? S[(size_t)y * W + x] : 0.0f;
+                sv[q * VEC + j] = (x < W && y < H) ? v.S[(size_t)y * W + x] : 0.0f;
             }
         }
-        fetch_rows(t + (int)gridDim.x);
+        if (more) fetch_rows(nv, nt);
 
         // 2. block exclusive scan of the row counts (ballots within a wave)
         int wtot;
@@ -511,9 +607,9 @@ __global__ __launch_bounds__(NW * 64) void k_field_list(
         int before = 0, total = 0;
 #pragma unroll
         for (int w = 0; w < NW; ++w) {
-            const int v = wave_tot[w];
-            before += w < wv ? v : 0;
-            total += v;
+            const int u = wave_tot[w];
+            before += w < wv ? u : 0;
+            total += u;
         }
         const int excl = before + wexcl;
         if (tid < nr) row_excl[tid] = excl;
@@ -528,6 +624,7 @@ __global__ __launch_bounds__(NW * 64) void k_field_list(
 #pragma unroll
         for (int q = 0; q < NQ; ++q) acc[q] = (vec_t)(0.0f);
 
+        const int cap = list_cap - v.max_row;
         const int npass = (total + cap - 1) / cap;
         for (int k = 0; k < npass; ++k) {
             int start = 0, end = total;
@@ -539,7 +636,7 @@ __global__ __launch_bounds__(NW * 64) void k_field_list(
             if (tid < nr && cnt > 0 && excl >= start && excl < end) {
                 const int py = ya + tid;
                 const int c = (py - pady) & (VEC - 1);
-                const int rowterm = c * copy_elems * 4 - (py - c) * 4;
+                const int rowterm = c * v.copy_elems * 4 - (py - c) * 4;
                 int o = excl - start;
 #pragma unroll
                 for (int j = 0; j < 3; ++j) {
@@ -561,40 +658,50 @@ __global__ __launch_bounds__(NW * 64) void k_field_list(
                 int i = lo;
                 for (; i < hi && (i & 3); ++i) gather_one<NQ>(acc, lb + list[i]);
                 const int4 *list4 = reinterpret_cast<const int4 *>(list);
-                // eight sources per round: both entry groups are read first, then
-                // eight table reads are in flight before the adds
-                for (; i + 8 <= hi; i += 8) {
-                    const int4 ea = list4[i >> 2];
-                    const int4 eb = list4[(i >> 2) + 1];
-                    const int a[8] = {ea.x, ea.y, ea.z, ea.w, eb.x, eb.y, eb.z, eb.w};
-                    vec_t v[8][NQ];
+                // eight sources per round: eight table reads are in flight
+                // before the adds, and the next round's entries are read
+                // behind them (reading up to eight entries past the pass stays
+                // inside the allocation: row_excl follows the list)
+                if (i + 8 <= hi) {
+                    int4 ea = list4[i >> 2];
+                    int4 eb = list4[(i >> 2) + 1];
+                    for (; i + 8 <= hi; i += 8) {
+                        const int a[8] = {ea.x, ea.y, ea.z, ea.w, eb.x, eb.y, eb.z, eb.w};
+                        ea = list4[(i >> 2) + 2];
+                        eb = list4[(i >> 2) + 3];
+                        // the compiler keeps this order: next entries, table
+                        // reads, adds (no wait is implied by the barriers)
+                        asm volatile("" ::: "memory");
+                        vec_t u8[8][NQ];
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) {
-                        const lds_vec sp = reinterpret_cast<lds_vec>((uint32_t)(lb + a[u]));
+                        for (int u = 0; u < 8; ++u) {
+                            const lds_vec sp = reinterpret_cast<lds_vec>((uint32_t)(lb + a[u]));
 #pragma unroll
-                        for (int q = 0; q < NQ; ++q) v[u][q] = sp[q];
-                    }
-                    // row-major source order per accumulator
+                            for (int q = 0; q < NQ; ++q) u8[u][q] = sp[q];
+                        }
+                        asm volatile("" ::: "memory");
+                        // row-major source order per accumulator
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) {
+                        for (int u = 0; u < 8; ++u) {
 #pragma unroll
-                        for (int q = 0; q < NQ; ++q) acc[q] += v[u][q];
+                            for (int q = 0; q < NQ; ++q) acc[q] += u8[u][q];
+                        }
                     }
                 }
                 if (i + 4 <= hi) {
                     const int4 ea = list4[i >> 2];
                     const int a[4] = {ea.x, ea.y, ea.z, ea.w};
-                    vec_t v[4][NQ];
+                    vec_t u4[4][NQ];
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
                         const lds_vec sp = reinterpret_cast<lds_vec>((uint32_t)(lb + a[u]));
 #pragma unroll
-                        for (int q = 0; q < NQ; ++q) v[u][q] = sp[q];
+                        for (int q = 0; q < NQ; ++q) u4[u][q] = sp[q];
                     }
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
 #pragma unroll
-                        for (int q = 0; q < NQ; ++q) acc[q] += v[u][q];
+                        for (int q = 0; q < NQ; ++q) acc[q] += u4[u][q];
                     }
                     i += 4;
                 }
@@ -610,196 +717,25 @@ __global__ __launch_bounds__(NW * 64) void k_field_list(
 #pragma unroll
                 for (int j = 0; j < VEC; ++j) {
                     const int y = y0w + rg * HL + q * VEC + j;
-                    if (y < H) P[(size_t)y * W + x] = sv[q * VEC + j] + acc[q][j];
+                    if (y < H) v.P[(size_t)y * W + x] = sv[q * VEC + j] + acc[q][j];
                 }
             }
         }
-        __syncthreads();  // wave_tot and row_excl are rewritten by the next strip
-    }
-}
-
-// ---- per-tick field, wave-private source lists ----------------------------------------
-//
-// Same table, entries and gather as k_field_list, but every wave lists the
-// sources of its own TW x TH tile's halo, so waves never wait for each other:
-// lane i holds halo rows i, 64 + i and 128 + i; the row counts are prefix-summed
-// with ballots (no LDS traffic); entries go to a wave-private LDS list of `cap`
-// entries (several passes when a dense halo overflows it).
-
-template <int TW, int HL, int VEC, int NW>
-__global__ __launch_bounds__(NW * 64) void k_field_wave(
-    const unsigned long long *__restrict__ bits, int wpr, const float *__restrict__ tab_g,
-    int copy_elems, int stride, int padx, int pady, int R, int cap, int max_row,
-    const float *__restrict__ S, float *__restrict__ P, int W, int H, int tiles_x, int n_tiles)
-{
-    constexpr int G = 64 / TW, TH = G * HL, NQ = HL / VEC, NS = 3;
-    typedef typename VecOf<VEC>::type vec_t;
-    typedef const __attribute__((address_space(3))) vec_t *lds_vec;
-    extern __shared__ __align__(16) unsigned char lds_raw[];
-    float *tab = reinterpret_cast<float *>(lds_raw);
-    const int tab_elems = VEC * copy_elems;  // a multiple of 4
-    for (int i = threadIdx.x; i < tab_elems / 4; i += NW * 64)
-        reinterpret_cast<float4 *>(tab)[i] = reinterpret_cast<const float4 *>(tab_g)[i];
-    __syncthreads();
-
-    const int tid = (int)threadIdx.x, lane = tid & 63;
-    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-    int *list = reinterpret_cast<int *>(tab + tab_elems) + wv * cap;  // cap: a multiple of 4
-    const int col = lane % TW, rg = lane / TW;
-    const int tbase = (int)(uint32_t)(uintptr_t)((lds_ptr<float>)tab);
-    const int capp = cap - max_row;
-    const int t0 = __builtin_amdgcn_readfirstlane((int)blockIdx.x * NW + wv);
-    const int tstep = __builtin_amdgcn_readfirstlane((int)gridDim.x * NW);
-
-    struct Tile {
-        int X0, Y0, ya, nr, xa, xb, wa, nwd;
-    };
-    auto tile = [&](int t) {
-        Tile g;
-        const int ty = t / tiles_x, tx = t - ty * tiles_x;
-        g.X0 = tx * TW;
-        g.Y0 = ty * TH;
-        g.ya = max(g.Y0 - R, 0);
-        g.nr = min(g.Y0 + TH - 1 + R, H - 1) - g.ya + 1;
-        g.xa = max(g.X0 - R, 0);
-        g.xb = min(g.X0 + TW - 1 + R, W - 1);
-        g.wa = g.xa >> 6;
-        g.nwd = (g.xb >> 6) - g.wa + 1;
-        return g;
-    };
-    unsigned long long n[NS][3];
-    auto fetch = [&](int t) {
-#pragma unroll
-        for (int sl = 0; sl < NS; ++sl) n[sl][0] = n[sl][1] = n[sl][2] = 0;
-        if (t >= n_tiles) return;
-        const Tile g = tile(t);
-#pragma unroll
-        for (int sl = 0; sl < NS; ++sl) {
-            const int r = 64 * sl + lane;
-            if (r < g.nr) {
-                const unsigned long long *row = bits + (size_t)(g.ya + r) * wpr + g.wa;
-                n[sl][0] = row[0];
-                if (g.nwd > 1) n[sl][1] = row[1];
-                if (g.nwd > 2) n[sl][2] = row[2];
+        if (!more) break;
+        // No barrier here: every read of wave_tot, row_excl, the list and the
+        // table for this strip happened before this strip's last barrier (the
+        // one after the gather, or after the scan when there is no source).
+        if (nitem != item) {
+            if (nv.tab != v.tab) {
+                for (int i = tid; i < nv.tab_elems / 4; i += NT)
+                    reinterpret_cast<f4 *>(tab)[i] = nv.tab[i];
+                __syncthreads();
             }
+            item = nitem;
+            it = nit;
         }
-    };
-    fetch(t0);
-
-    for (int t = t0; t < n_tiles; t += tstep) {
-        const Tile g = tile(t);
-        const int X0 = g.X0, y0 = g.Y0, ya = g.ya, wa = g.wa, nwd = g.nwd;
-        const unsigned long long ma = ~0ull << (g.xa & 63), mb = ~0ull >> (63 - (g.xb & 63));
-        unsigned long long m[NS][3];
-        int cnt[NS];
-#pragma unroll
-        for (int sl = 0; sl < NS; ++sl) {
-            m[sl][0] = n[sl][0] & ma;
-            m[sl][1] = n[sl][1];
-            m[sl][2] = n[sl][2];
-            if (nwd == 1) m[sl][0] &= mb;
-            if (nwd == 2) m[sl][1] &= mb;
-            if (nwd == 3) m[sl][2] &= mb;
-            cnt[sl] = __popcll(m[sl][0]) + __popcll(m[sl][1]) + __popcll(m[sl][2]);
-        }
-        // the prefetched words are consumed before new loads are issued
-        asm volatile("" ::"v"(cnt[0]), "v"(cnt[1]), "v"(cnt[2]) : "memory");
-        const int x = X0 + col;
-        float sv[HL];
-#pragma unroll
-        for (int r = 0; r < HL; ++r) {
-            const int y = y0 + rg * HL + r;
-            sv[r] = (x < W && y < H) ? S[(size_t)y * W + x] : 0.0f;
-        }
-        fetch(t + tstep);
-
-        // row-major prefix of the halo row counts
-        int excl[NS], total = 0;
-#pragma unroll
-        for (int sl = 0; sl < NS; ++sl) {
-            int tot;
-            const int e = wave_excl_small(cnt[sl], tot);
-            excl[sl] = total + e;
-            total += tot;
-        }
-        // first row start at or after v (row order: slot-major, then lane)
-        auto first_at_least = [&](int v) {
-#pragma unroll
-            for (int sl = 0; sl < NS; ++sl) {
-                const unsigned long long b = __ballot(excl[sl] >= v);
-                if (b) return __builtin_amdgcn_readlane(excl[sl], __builtin_ctzll(b));
-            }
-            return total;
-        };
-
-        const int lb = opaque_lane(tbase + ((X0 + col + padx) * stride + (y0 + rg * HL + pady)) * 4);
-        vec_t acc[NQ];
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) acc[q] = (vec_t)(0.0f);
-        const int npass = (total + capp - 1) / capp;
-        for (int pass = 0; pass < npass; ++pass) {
-            int sp = 0, ep = total;
-            if (npass > 1) {
-                sp = first_at_least(pass * capp);
-                if (pass + 1 < npass) ep = first_at_least((pass + 1) * capp);
-            }
-#pragma unroll
-            for (int sl = 0; sl < NS; ++sl) {
-                if (cnt[sl] > 0 && excl[sl] >= sp && excl[sl] < ep) {
-                    const int py = ya + 64 * sl + lane;
-                    const int c = (py - pady) & (VEC - 1);
-                    const int rowterm = c * copy_elems * 4 - (py - c) * 4;
-                    int o = excl[sl] - sp;
-#pragma unroll
-                    for (int j = 0; j < 3; ++j) {
-                        unsigned long long mj = m[sl][j];
-                        const int xw = (wa + j) * 64;
-                        while (mj) {
-                            const int b = __builtin_ctzll(mj);
-                            mj &= mj - 1ull;
-                            list[o++] = rowterm - (xw + b) * stride * 4;
-                        }
-                    }
-                }
-            }
-            // the list writes of all lanes complete before the wave reads them
-            __builtin_amdgcn_s_waitcnt(0xC07F);
-            asm volatile("" ::: "memory");
-            const int hi = ep - sp;
-            int i = 0;
-            const int4 *list4 = reinterpret_cast<const int4 *>(list);
-            for (; i + 8 <= hi; i += 8) {
-                const int4 ea = list4[i >> 2];
-                const int4 eb = list4[(i >> 2) + 1];
-                const int a[8] = {ea.x, ea.y, ea.z, ea.w, eb.x, eb.y, eb.z, eb.w};
-                vec_t v[8][NQ];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const lds_vec sp8 = reinterpret_cast<lds_vec>((uint32_t)(lb + a[u]));
-#pragma unroll
-                    for (int q = 0; q < NQ; ++q) v[u][q] = sp8[q];
-                }
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-#pragma unroll
-                    for (int q = 0; q < NQ; ++q) acc[q] += v[u][q];
-                }
-            }
-            for (; i < hi; ++i) gather_one<NQ>(acc, lb + list[i]);
-            // this pass's reads precede the next pass's writes
-            asm volatile("" ::: "memory");
-        }
-
-        if (x < W) {
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) {
-#pragma unroll
-                for (int j = 0; j < VEC; ++j) {
-                    const int y = y0 + rg * HL + q * VEC + j;
-                    if (y < H) P[(size_t)y * W + x] = sv[q * VEC + j] + acc[q][j];
-                }
-            }
-        }
+        v = nv;
+        t = nt;
     }
 }
 
@@ -825,14 +761,15 @@ __global__ void k_phi_copies(float *tab, int vec, int copy_elems, int ncols, int
 // ---- occupancy ----------------------------------------------------------------------
 
 __global__ void k_occ_init(const int32_t *__restrict__ pos, int N, unsigned long long *occ, int wpr,
-                           int W, int32_t *__restrict__ owner, unsigned long long *ctr)
+                           int W, const int32_t *__restrict__ ext,
+                           unsigned long long *__restrict__ owner, unsigned long long *ctr)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int p = i < N ? pos[i] : -1;
     if (p >= 0) {
         const int y = p / W, x = p - y * W;
         atomicOr(&occ[(size_t)y * wpr + (x >> 6)], 1ull << (x & 63));
-        owner[p] = i;
+        owner[p] = ((unsigned long long)(uint32_t)ext[i] << 32) | (uint32_t)i;
     }
     block_sum_add(p >= 0 ? 1u : 0u, ctr, kLive);
 }
@@ -847,20 +784,40 @@ __global__ void k_occ_init(const int32_t *__restrict__ pos, int N, unsigned long
 // so neighbouring lanes work on neighbouring su.
 
 constexpr int kDecideThreads = 256;
+constexpr int kCommitThreads = 256;
 
+// The view of this workgroup's scene: views[block_scene[block]] (MULTI) or
+// the kernel argument `one`.
+template <bool MULTI>
+__device__ __forceinline__ const SceneView &block_view(const SceneView &one,
+                                                       const SceneView *__restrict__ views,
+                                                       const int32_t *__restrict__ block_scene)
+{
+    if constexpr (MULTI) return views[block_scene[blockIdx.x]];
+    return one;
+}
+
+template <bool MULTI>
 __global__ __launch_bounds__(kDecideThreads) void k_decide_claim(
-    int chunk, const unsigned long long *__restrict__ occ, int wpr, int W, int H,
-    const int32_t *__restrict__ owner, const float *__restrict__ P, float phi_axial,
-    float phi_diag, unsigned long long seed, int32_t *__restrict__ target,
-    unsigned long long *__restrict__ key, uint8_t *__restrict__ flags, unsigned long long *claim,
-    unsigned long long *ctr)
+    SceneView one, const SceneView *__restrict__ views, const int32_t *__restrict__ block_scene,
+    int max_chunk)
 {
     extern __shared__ int32_t list_raw[];
     const int lane = (int)lane_id();
     const int wv = threadIdx.x >> 6;
-    int32_t *list = list_raw + (size_t)wv * chunk * 64;
+    const SceneView &v = block_view<MULTI>(one, views, block_scene);
+    const int W = v.W, H = v.H, wpr = v.wpr, chunk = v.chunk;
+    const gptr<const unsigned long long> occ = to_global((const unsigned long long *)v.occ);
+    const gptr<const float> P = to_global((const float *)v.P);
+    const gptr<const unsigned long long> owner = to_global((const unsigned long long *)v.owner);
+    const gptr<unsigned long long> claim = to_global(v.claim), key = to_global(v.key),
+                                   ctr = to_global(v.ctr);
+    const gptr<int32_t> target = to_global(v.target);
+    const gptr<uint8_t> flags = to_global(v.flags);
+    int32_t *list = list_raw + (size_t)wv * max_chunk * 64;
     const size_t nwords = (size_t)wpr * H;
-    const size_t w = ((size_t)blockIdx.x * (kDecideThreads / 64) + wv) * chunk + lane;
+    const size_t w =
+        ((size_t)(blockIdx.x - v.dec_block0) * (kDecideThreads / 64) + wv) * chunk + lane;
     unsigned long long m = 0;
     if (lane < chunk && w < nwords) m = occ[w];
     const int cntl = __popcll(m);
@@ -879,12 +836,16 @@ __global__ __launch_bounds__(kDecideThreads) void k_decide_claim(
     __builtin_amdgcn_s_waitcnt(0xC07F);
     asm volatile("" ::: "memory");
     const unsigned long long t = ctr[0];
+    const unsigned long long seed = v.seed;
+    const float phi_axial = v.phi_axial, phi_diag = v.phi_diag;
     unsigned int movers = 0, ties = 0;
     for (int base = 0; base < total; base += 64) {
         const int k = base + lane;
         if (k >= total) break;
         const int p = list[k];
-        const int i = owner[p];
+        const unsigned long long who = owner[p];
+        const int i = (int)(uint32_t)who;
+        const uint32_t eid = (uint32_t)(who >> 32);
         const int y = p / W, x = p - y * W;
         float lo = P[p], lo2 = INFINITY;
         int best = 0;
@@ -913,10 +874,10 @@ __global__ __launch_bounds__(kDecideThreads) void k_decide_claim(
         bool mover = false;
         if (best != 0) {
             tgt = (y + kDirY[best]) * W + (x + kDirX[best]);
-            const uint32_t r = philox_w0((uint32_t)i, (uint32_t)t, (uint32_t)(t >> 32), 0u,
+            const uint32_t r = philox_w0(eid, (uint32_t)t, (uint32_t)(t >> 32), 0u,
                                          (uint32_t)seed, (uint32_t)(seed >> 32));
-            const unsigned long long kk = ((unsigned long long)r << 32) | (uint32_t)i;
-            atomicMin(&claim[tgt], kk);
+            const unsigned long long kk = ((unsigned long long)r << 32) | eid;
+            __hip_atomic_fetch_min(&claim[tgt], kk, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             key[i] = kk;
             mover = true;
         }
@@ -931,18 +892,25 @@ __global__ __launch_bounds__(kDecideThreads) void k_decide_claim(
 
 // ---- commit (k-4 moves, exits) -------------------------------------------------------
 
-__global__ __launch_bounds__(256) void k_commit(int N, int W, int32_t *__restrict__ pos,
-                                                int32_t *__restrict__ target,
-                                                const unsigned long long *__restrict__ key,
-                                                uint8_t *__restrict__ flags,
-                                                unsigned long long *claim, unsigned long long *occ,
-                                                int wpr, int32_t *owner,
-                                                const uint8_t *__restrict__ exitm,
-                                                unsigned long long *ctr)
+template <bool MULTI>
+__global__ __launch_bounds__(kCommitThreads) void k_commit(SceneView one,
+                                                           const SceneView *__restrict__ views,
+                                                           const int32_t *__restrict__ block_scene)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const SceneView &v = block_view<MULTI>(one, views, block_scene);
+    const int lb = (int)blockIdx.x - v.com_block0;
+    const int i = lb * kCommitThreads + (int)threadIdx.x;
+    const int W = v.W, wpr = v.wpr;
+    const gptr<int32_t> pos = to_global(v.pos), target = to_global(v.target);
+    const gptr<unsigned long long> owner = to_global(v.owner);
+    const gptr<const int32_t> ext = to_global(v.ext);
+    const gptr<uint8_t> flags = to_global(v.flags);
+    const gptr<const uint8_t> exitm = to_global(v.exitm);
+    const gptr<const unsigned long long> key = to_global((const unsigned long long *)v.key);
+    const gptr<unsigned long long> claim = to_global(v.claim), occ = to_global(v.occ),
+                                   ctr = to_global(v.ctr);
     bool was_live = false, won = false, left = false;
-    if (i < N) {
+    if (i < v.N) {
         const int p = pos[i];
         if (p < 0) {
             target[i] = -1;
@@ -959,15 +927,17 @@ __global__ __launch_bounds__(256) void k_commit(int N, int W, int32_t *__restric
                     won = true;
                     claim[tgt] = ~0ull;
                     const int y = p / W, x = p - y * W;
-                    atomicAnd(&occ[(size_t)y * wpr + (x >> 6)], ~(1ull << (x & 63)));
-                    owner[p] = -1;
+                    __hip_atomic_fetch_and(&occ[(size_t)y * wpr + (x >> 6)], ~(1ull << (x & 63)),
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    owner[p] = ~0ull;
                     if (exitm[tgt]) {
                         left = true;
                         pos[i] = -1;
                     } else {
                         const int ty = tgt / W, tx = tgt - ty * W;
-                        atomicOr(&occ[(size_t)ty * wpr + (tx >> 6)], 1ull << (tx & 63));
-                        owner[tgt] = i;
+                        __hip_atomic_fetch_or(&occ[(size_t)ty * wpr + (tx >> 6)], 1ull << (tx & 63),
+                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        owner[tgt] = ((unsigned long long)(uint32_t)ext[i] << 32) | (uint32_t)i;
                         pos[i] = tgt;
                     }
                     flags[i] = f | kWon;
@@ -975,11 +945,43 @@ __global__ __launch_bounds__(256) void k_commit(int N, int W, int32_t *__restric
             }
         }
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&ctr[0], 1ull);
+    if (lb == 0 && threadIdx.x == 0)
+        __hip_atomic_fetch_add(&ctr[0], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     block_sum_add(was_live ? 1u : 0u, ctr, kPedSteps);
     block_sum_add(won ? 1u : 0u, ctr, kMoved);
     block_sum_add(left ? 1u : 0u, ctr, kEvacuated);
     block_delta_add(left ? -1 : 0, ctr, kLive);
+}
+
+// ---- caller-order output ---------------------------------------------------------------
+
+template <typename T>
+__global__ void k_scatter(const T *__restrict__ src, const int32_t *__restrict__ ext,
+                          T *__restrict__ dst, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[ext[i]] = src[i];
+}
+
+// ---- batched counter read-out --------------------------------------------------------
+//
+// Workgroup j sums the slot copies of every running total of scene j into
+// out[j * 8 + (0: step, 1 + id: total id)].
+
+__global__ __launch_bounds__(64) void k_sum_counters(const SceneView *__restrict__ views,
+                                                     unsigned long long *__restrict__ out)
+{
+    const gptr<const unsigned long long> ctr =
+        to_global((const unsigned long long *)views[blockIdx.x].ctr);
+    const int lane = (int)threadIdx.x;
+    unsigned long long mine = 0;
+    for (int id = 0; id < kNumCounters; ++id) {
+        unsigned long long v = ctr[ctr_index(id, lane)];
+        for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
+        if (lane == 1 + id) mine = v;
+    }
+    if (lane == 0) mine = ctr[0];
+    if (lane < 8) out[(size_t)blockIdx.x * 8 + lane] = mine;
 }
 
 // Plain launch, or a launch whose dispatch records `ev` (kernel timing).
@@ -1147,10 +1149,9 @@ int bank_degree(int tw, int hl, int stride)
 
 }  // namespace
 
-ListCfg make_list_cfg(int radius, int tw, int hl, int vec, int nw, int list_cap, bool wave_lists)
+ListCfg make_list_cfg(int radius, int tw, int hl, int vec, int nw, int list_cap)
 {
     ListCfg c;
-    c.wave_lists = wave_lists;
     c.tw = tw;
     c.hl = hl;
     c.vec = vec;
@@ -1178,15 +1179,9 @@ ListCfg make_list_cfg(int radius, int tw, int hl, int vec, int nw, int list_cap,
     c.copy_elems = (c.ncols * c.stride + 3) & ~3;  // copies start 16-byte aligned
     c.max_row = tw + 2 * radius;
     c.list_cap = list_cap;
-    if (wave_lists) {
-        // per wave: halo of TH + 2R rows (at most 3 x 64 lanes), list of list_cap
-        c.halo_rows = c.th + 2 * radius;
-        c.lds_bytes = (size_t)vec * c.copy_elems * 4 + (size_t)nw * list_cap * 4;
-    } else {
-        c.halo_rows = c.wt + 2 * radius;
-        c.lds_bytes = (size_t)vec * c.copy_elems * 4 + (size_t)list_cap * 4 +
-                      (size_t)(c.halo_rows + 1) * 4;
-    }
+    c.halo_rows = c.wt + 2 * radius;
+    c.lds_bytes = (size_t)vec * c.copy_elems * 4 + (size_t)list_cap * 4 +
+                  (size_t)(c.halo_rows + 1) * 4;
     return c;
 }
 
@@ -1200,7 +1195,7 @@ ListCfg pick_list_cfg(int radius, size_t max_lds)
     for (int i = 0; i < 2; ++i) {
         const int *sh = shapes[i];
         for (int cap = 4096; cap >= 512; cap /= 2) {
-            ListCfg t = make_list_cfg(radius, sh[0], sh[1], sh[2], sh[3], cap, false);
+            ListCfg t = make_list_cfg(radius, sh[0], sh[1], sh[2], sh[3], cap);
             if (cap < 2 * t.max_row || t.halo_rows > 64 * sh[3]) break;
             if (t.lds_bytes <= max_lds / 2) return t;
             if (t.lds_bytes <= max_lds && best.lds_bytes == 0) best = t;
@@ -1217,40 +1212,38 @@ hipError_t launch_phi_copies(float *tab, const ListCfg &c, double k, double alph
     return hipGetLastError();
 }
 
-namespace {
-
-template <int TW, int HL, int VEC, int NW>
-hipError_t field_wave_launch(const ListCfg &c, const unsigned long long *bits, int wpr,
-                             const float *tab, const float *S, float *P, int W, int H,
-                             hipStream_t st, const LaunchEvents *ev)
+void set_view_layout(SceneView &v, const ListCfg &c, const float *tab)
 {
-    constexpr int TH = (64 / TW) * HL;
-    const int tiles_x = (W + TW - 1) / TW, tiles_y = (H + TH - 1) / TH;
-    const int n_tiles = tiles_x * tiles_y;
-    const int want = (n_tiles + NW - 1) / NW;
-    const int grid = want < c.grid ? want : c.grid;
-    return launch(k_field_wave<TW, HL, VEC, NW>, dim3(grid > 0 ? grid : 1), dim3(NW * 64),
-                  c.lds_bytes, st, ev, bits, wpr, tab, c.copy_elems, c.stride, c.padx, c.pady,
-                  c.radius, c.list_cap, c.max_row, S, P, W, H, tiles_x, n_tiles);
+    v.tiles_x = (v.W + c.tw - 1) / c.tw;
+    v.n_strips = v.tiles_x * ((v.H + c.wt - 1) / c.wt);
+    v.copy_elems = c.copy_elems;
+    v.stride = c.stride;
+    v.padx = c.padx;
+    v.pady = c.pady;
+    v.max_row = c.max_row;
+    v.tab_elems = c.vec * c.copy_elems;
+    v.tab = tab;
 }
 
-template <int TW, int HL, int VEC, int NW>
-hipError_t field_list_launch(const ListCfg &c, const unsigned long long *bits, int wpr,
-                             const float *tab, const float *S, float *P, int W, int H,
-                             hipStream_t st, const LaunchEvents *ev)
+FieldLaunch field_launch_for(const ListCfg &c)
 {
-    if (c.wave_lists)
-        return field_wave_launch<TW, HL, VEC, NW>(c, bits, wpr, tab, S, P, W, H, st, ev);
-    constexpr int WT = NW * (64 / TW) * HL;
-    const int tiles_x = (W + TW - 1) / TW, tiles_y = (H + WT - 1) / WT;
-    const int n_tiles = tiles_x * tiles_y;
-    const int grid = n_tiles < c.grid ? n_tiles : c.grid;
-    return launch(k_field_list<TW, HL, VEC, NW>, dim3(grid > 0 ? grid : 1), dim3(NW * 64),
-                  c.lds_bytes, st, ev, bits, wpr, tab, c.copy_elems, c.stride, c.padx, c.pady,
-                  c.radius, c.list_cap, c.max_row, S, P, W, H, tiles_x, n_tiles);
+    FieldLaunch f;
+    f.tw = c.tw;
+    f.hl = c.hl;
+    f.vec = c.vec;
+    f.nw = c.nw;
+    f.list_cap = c.list_cap;
+    f.tab_max = c.vec * c.copy_elems;
+    f.halo_max = c.halo_rows;
+    f.grid = c.grid;
+    f.lds_bytes = field_lds_bytes(f);
+    return f;
 }
 
-}  // namespace
+size_t field_lds_bytes(const FieldLaunch &f)
+{
+    return (size_t)f.tab_max * 4 + (size_t)f.list_cap * 4 + (size_t)(f.halo_max + 1) * 4;
+}
 
 #define SF_LIST_SHAPES(X)                                                                     \
     X(16, 2, 2, 4) X(16, 2, 2, 8) X(16, 4, 2, 4) X(16, 4, 2, 8) X(16, 4, 4, 4) X(16, 4, 4, 8)    \
@@ -1265,28 +1258,50 @@ bool list_shape_compiled(int tw, int hl, int vec, int nw)
     return false;
 }
 
-hipError_t set_field_list_lds_limit(size_t bytes)
+hipError_t set_field_lds_limit(size_t bytes)
 {
     hipError_t e = hipSuccess;
 #define SF_SET(a, b, v, n)                                                                        \
-    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_field_list<a, b, v, n>),         \
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_field<a, b, v, n, false>),       \
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);          \
     if (e != hipSuccess) return e;                                                            \
-    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_field_wave<a, b, v, n>),         \
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_field<a, b, v, n, true>),        \
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);          \
     if (e != hipSuccess) return e;
     SF_LIST_SHAPES(SF_SET)
 #undef SF_SET
-    return e;
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_decide_claim<false>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_decide_claim<true>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-hipError_t launch_field_list(const ListCfg &c, const unsigned long long *bits, int wpr,
-                             const float *tab, const float *S, float *P, int W, int H,
-                             hipStream_t st, const LaunchEvents *ev)
+hipError_t launch_field(const FieldLaunch &f, const SceneView *views, const int32_t *items,
+                        int n_items, hipStream_t st, const LaunchEvents *ev)
 {
+    const int grid = std::max(1, std::min(f.grid, n_items));
+    const int4 *it = reinterpret_cast<const int4 *>(items);
+    const SceneView none = {};
 #define SF_DISPATCH(a, b, v, n)                                                                   \
-    if (c.tw == a && c.hl == b && c.vec == v && c.nw == n)                                      \
-        return field_list_launch<a, b, v, n>(c, bits, wpr, tab, S, P, W, H, st, ev);
+    if (f.tw == a && f.hl == b && f.vec == v && f.nw == n)                                      \
+        return launch(k_field<a, b, v, n, true>, dim3(grid), dim3(n * 64), f.lds_bytes, st, ev,  \
+                      none, views, it, n_items, 0, f.tab_max, f.list_cap);
+    SF_LIST_SHAPES(SF_DISPATCH)
+#undef SF_DISPATCH
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_field_one(const FieldLaunch &f, const SceneView &view, int per,
+                            hipStream_t st, const LaunchEvents *ev)
+{
+    const int n_items = std::max(1, (view.n_strips + per - 1) / per);
+    const int grid = std::max(1, std::min(f.grid, n_items));
+#define SF_DISPATCH(a, b, v, n)                                                                   \
+    if (f.tw == a && f.hl == b && f.vec == v && f.nw == n)                                      \
+        return launch(k_field<a, b, v, n, false>, dim3(grid), dim3(n * 64), f.lds_bytes, st,     \
+                      ev, view, (const SceneView *)nullptr, (const int4 *)nullptr, n_items, per, \
+                      f.tab_max, f.list_cap);
     SF_LIST_SHAPES(SF_DISPATCH)
 #undef SF_DISPATCH
     return hipErrorInvalidValue;
@@ -1309,10 +1324,11 @@ hipError_t launch_static_S(const int32_t *D, const double *O, const uint8_t *obs
 }
 
 hipError_t launch_occ_init(const int32_t *pos, int N, unsigned long long *occ, int wpr, int W,
-                           int32_t *owner, unsigned long long *ctr, hipStream_t st)
+                           const int32_t *ext, unsigned long long *owner, unsigned long long *ctr,
+                           hipStream_t st)
 {
     hipLaunchKernelGGL(k_occ_init, dim3(blocks_for(N, 256)), dim3(256), 0, st, pos, N, occ, wpr, W,
-                       owner, ctr);
+                       ext, owner, ctr);
     return hipGetLastError();
 }
 
@@ -1326,27 +1342,67 @@ int pick_decide_chunk(int W, int H, int N)
     return c;
 }
 
-hipError_t launch_decide_claim(int chunk, const unsigned long long *occ, int wpr, int W, int H,
-                               const int32_t *owner, const float *P, float phi_axial,
-                               float phi_diag, unsigned long long seed, int32_t *target,
-                               unsigned long long *key, uint8_t *flags, unsigned long long *claim,
-                               unsigned long long *ctr, hipStream_t st, const LaunchEvents *ev)
+int decide_blocks(int wpr, int H, int chunk)
 {
-    const size_t nwords = (size_t)wpr * H;
     const size_t per_block = (size_t)(kDecideThreads / 64) * chunk;
-    const size_t lds = (size_t)(kDecideThreads / 64) * chunk * 64 * sizeof(int32_t);
-    return launch(k_decide_claim, dim3(blocks_for(nwords, (unsigned)per_block)),
-                  dim3(kDecideThreads), lds, st, ev, chunk, occ, wpr, W, H, owner, P, phi_axial,
-                  phi_diag, seed, target, key, flags, claim, ctr);
+    return (int)blocks_for((size_t)wpr * H, (unsigned)per_block, 1u << 30);
 }
 
-hipError_t launch_commit(int N, int W, int32_t *pos, int32_t *target, const unsigned long long *key,
-                         uint8_t *flags, unsigned long long *claim, unsigned long long *occ,
-                         int wpr, int32_t *owner, const uint8_t *exitm, unsigned long long *ctr,
+int commit_blocks(int N) { return (int)blocks_for((size_t)N, kCommitThreads, 1u << 30); }
+
+hipError_t launch_decide_claim(const SceneView *views, const int32_t *block_scene, int n_blocks,
+                               int max_chunk, hipStream_t st, const LaunchEvents *ev)
+{
+    const size_t lds = (size_t)(kDecideThreads / 64) * max_chunk * 64 * sizeof(int32_t);
+    const SceneView none = {};
+    return launch(k_decide_claim<true>, dim3(n_blocks), dim3(kDecideThreads), lds, st, ev, none,
+                  views, block_scene, max_chunk);
+}
+
+hipError_t launch_decide_one(const SceneView &view, hipStream_t st, const LaunchEvents *ev)
+{
+    const size_t lds = (size_t)(kDecideThreads / 64) * view.chunk * 64 * sizeof(int32_t);
+    return launch(k_decide_claim<false>, dim3(decide_blocks(view.wpr, view.H, view.chunk)),
+                  dim3(kDecideThreads), lds, st, ev, view, (const SceneView *)nullptr,
+                  (const int32_t *)nullptr, view.chunk);
+}
+
+hipError_t launch_scatter_i32(const int32_t *src, const int32_t *ext, int32_t *dst, int n,
+                              hipStream_t st)
+{
+    hipLaunchKernelGGL(k_scatter<int32_t>, dim3(blocks_for((size_t)n, 256)), dim3(256), 0, st,
+                       src, ext, dst, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_u8(const uint8_t *src, const int32_t *ext, uint8_t *dst, int n,
+                             hipStream_t st)
+{
+    hipLaunchKernelGGL(k_scatter<uint8_t>, dim3(blocks_for((size_t)n, 256)), dim3(256), 0, st,
+                       src, ext, dst, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum_counters(const SceneView *views, int n_scenes, unsigned long long *out,
+                               hipStream_t st)
+{
+    static_assert(kSlots == 64 && kNumCounters <= 7, "one lane per slot, eight words per scene");
+    hipLaunchKernelGGL(k_sum_counters, dim3(n_scenes), dim3(64), 0, st, views, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_commit(const SceneView *views, const int32_t *block_scene, int n_blocks,
                          hipStream_t st, const LaunchEvents *ev)
 {
-    return launch(k_commit, dim3(blocks_for(N, 256)), dim3(256), 0, st, ev, N, W, pos, target, key,
-                  flags, claim, occ, wpr, owner, exitm, ctr);
+    const SceneView none = {};
+    return launch(k_commit<true>, dim3(n_blocks), dim3(kCommitThreads), 0, st, ev, none, views,
+                  block_scene);
+}
+
+hipError_t launch_commit_one(const SceneView &view, hipStream_t st, const LaunchEvents *ev)
+{
+    return launch(k_commit<false>, dim3(commit_blocks(view.N)), dim3(kCommitThreads), 0, st, ev,
+                  view, (const SceneView *)nullptr, (const int32_t *)nullptr);
 }
 
 }  // namespace sf

@@ -1,0 +1,229 @@
+"""Serving loop over libsf: scenes arrive as requests, are admitted while their
+device footprint fits a budget, advance together, and leave when evacuated
+or after a tick limit.
+
+Continuous batching: every iteration runs one batched tick (sf_batch_step)
+over all resident scenes; requests that arrived meanwhile are admitted
+between iterations as memory and slots free up, and a changed membership
+builds a new batch (the scenes' device state stays where it is).  Scene
+state never leaves the device between ticks.  All arithmetic runs in the HIP
+library; this module only schedules.
+
+The per-tick latency a resident scene sees is the wall time of one iteration
+(admissions and retirements included).
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import time
+from typing import Callable, List, Optional
+
+import numpy as np
+
+from . import sf
+
+# Device bytes a resident scene holds (the library's per-scene arrays):
+# per su  S, P, D (4 B each), exit mask (1), claims (8), owners (8), occupancy
+# bits (1/8); per pedestrian  keys (8), positions, targets, id map (4 each),
+# flags (1); plus counters and the stamp copies (< 1 MiB).
+BYTES_PER_SU = 4 + 4 + 4 + 1 + 8 + 8 + 0.125
+BYTES_PER_PED = 8 + 4 + 4 + 4 + 1
+FIXED_BYTES = 1 << 20
+
+
+def footprint_bytes(scene) -> int:
+    su = int(scene.width) * int(scene.height)
+    return int(su * BYTES_PER_SU + int(np.asarray(scene.pos).shape[0]) * BYTES_PER_PED
+               + FIXED_BYTES)
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    arrival: float  # seconds after the start of the run
+    make_scene: Callable[[], object]  # materialised when first considered for admission
+    max_steps: int = 2000
+    _scene: object = None
+
+    def scene(self):
+        if self._scene is None:
+            self._scene = self.make_scene()
+        return self._scene
+
+
+@dataclasses.dataclass
+class Finished:
+    rid: int
+    arrival: float
+    admitted: float
+    finished: float
+    steps: int
+    stats: dict
+    positions: Optional[np.ndarray] = None
+
+
+@dataclasses.dataclass
+class _Resident:
+    req: Request
+    scene: object
+    gpu: object
+    admitted: float
+    bytes: int
+    steps: int = 0
+    last: Optional[dict] = None
+
+
+def poisson_arrivals(rate: float, duration: float, seed: int) -> np.ndarray:
+    """Arrival times of a Poisson stream of `rate` per second over [0, duration)."""
+    rng = np.random.Generator(np.random.PCG64([seed, int(rate * 1000)]))
+    n = int(rate * duration * 2 + 64)
+    t = np.cumsum(rng.exponential(1.0 / rate, size=n))
+    while t[-1] < duration:
+        t = np.concatenate([t, t[-1] + np.cumsum(rng.exponential(1.0 / rate, size=n))])
+    return t[t < duration]
+
+
+class Server:
+    """Admits, batches and retires scenes; see the module docstring."""
+
+    def __init__(self, budget_bytes: int, max_scenes: int = 512, stream=None,
+                 tiling: Optional[dict] = None, keep_positions: bool = False,
+                 clock=time.perf_counter):
+        self.budget = int(budget_bytes)
+        self.max_scenes = int(max_scenes)
+        self.stream = stream
+        self.tiling = tiling
+        self.keep_positions = keep_positions
+        self.clock = clock
+
+    def run(self, requests: List[Request], stop_admitting_at: Optional[float] = None,
+            drain: bool = True, deadline: Optional[float] = None) -> dict:
+        """Serve `requests` (sorted by arrival).  Admission stops at
+        `stop_admitting_at` seconds (None: never); with `drain`, resident
+        scenes then run to completion; `deadline` ends the run regardless."""
+        pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
+        queue: collections.deque = collections.deque()
+        resident: List[_Resident] = []
+        finished: List[Finished] = []
+        used = 0
+        batch = None
+        tick_ms: List[float] = []  # one batched tick (launch to completion)
+        step_ms: List[float] = []  # between consecutive ticks (the latency a scene sees)
+        last_end = None
+        resident_count: List[int] = []
+        admitted_n = 0
+        max_used = 0
+        max_resident = 0
+        t0 = self.clock()
+
+        def now():
+            return self.clock() - t0
+
+        try:
+            while True:
+                t = now()
+                if deadline is not None and t >= deadline:
+                    break
+                admitting = stop_admitting_at is None or t < stop_admitting_at
+                while pending and pending[0].arrival <= t:
+                    queue.append(pending.popleft())
+                changed = False
+                # admission in arrival order while the head of the queue fits
+                while admitting and queue and len(resident) < self.max_scenes:
+                    req = queue[0]
+                    scene = req.scene()
+                    need = footprint_bytes(scene)
+                    if used + need > self.budget:
+                        if not resident:
+                            raise ValueError(f"request {req.rid} needs {need} B, more than "
+                                             f"the whole budget of {self.budget} B")
+                        break
+                    queue.popleft()
+                    req._scene = None  # the device copy is the state from here on
+                    if batch is not None:
+                        batch.close()
+                        batch = None
+                    g = sf.GpuScene(scene, stream=self.stream)
+                    resident.append(_Resident(req, scene, g, now(), need))
+                    used += need
+                    admitted_n += 1
+                    max_used = max(max_used, used)
+                    max_resident = max(max_resident, len(resident))
+                    changed = True
+                if not resident:
+                    last_end = None
+                    if not admitting or (not pending and not queue):
+                        break
+                    if pending and not queue:
+                        wait = pending[0].arrival - now()
+                        if wait > 0:
+                            time.sleep(min(wait, 0.05))
+                    continue
+                if not admitting and not drain:
+                    break
+                if batch is None or changed:
+                    if batch is not None:
+                        batch.close()
+                    batch = sf.Batch([r.gpu for r in resident], tiling=self.tiling,
+                                     stream=self.stream)
+                ts = self.clock()
+                batch.step(1)
+                totals = batch.stats()  # waits for the tick
+                te = self.clock()
+                tick_ms.append(1000.0 * (te - ts))
+                if last_end is not None:
+                    step_ms.append(1000.0 * (te - last_end))
+                last_end = te
+                resident_count.append(len(resident))
+                done = []
+                for r, s in zip(resident, totals):
+                    r.steps += 1
+                    r.last = s
+                    if s["live"] == 0 or r.steps >= r.req.max_steps:
+                        done.append((r, s))
+                if done:
+                    batch.close()
+                    batch = None
+                    for r, s in done:
+                        pos = r.gpu.positions() if self.keep_positions else None
+                        finished.append(Finished(r.req.rid, r.req.arrival, r.admitted, now(),
+                                                 r.steps, s, pos))
+                        r.gpu.close()
+                        used -= r.bytes
+                    ids = {id(r) for r, _ in done}
+                    resident = [r for r in resident if id(r) not in ids]
+        finally:
+            if batch is not None:
+                batch.close()
+            for r in resident:
+                r.gpu.close()
+        wall = now()
+        ped_steps = sum(f.stats["ped_steps"] for f in finished) + \
+            sum(r.last["ped_steps"] for r in resident if r.last is not None)
+        lat = np.array(tick_ms) if tick_ms else np.zeros(1)
+        stp = np.array(step_ms) if step_ms else lat
+        waits = np.array([f.admitted - f.arrival for f in finished]) if finished else np.zeros(1)
+        return {
+            "wall_s": wall,
+            "requests": len(requests),
+            "admitted": admitted_n,
+            "finished": len(finished),
+            "unfinished_resident": len(resident),
+            "still_queued": len(queue) + len(pending),
+            "scenes_per_s": len(finished) / wall if wall > 0 else 0.0,
+            "ticks": len(tick_ms),
+            "step_latency_ms_p50": float(np.percentile(stp, 50)),
+            "step_latency_ms_p99": float(np.percentile(stp, 99)),
+            "tick_ms_p50": float(np.percentile(lat, 50)),
+            "tick_ms_p99": float(np.percentile(lat, 99)),
+            "tick_ms_mean": float(lat.mean()),
+            "resident_mean": float(np.mean(resident_count)) if resident_count else 0.0,
+            "admission_wait_s_p50": float(np.percentile(waits, 50)),
+            "admission_wait_s_p99": float(np.percentile(waits, 99)),
+            "ped_steps": int(ped_steps),
+            "ped_steps_per_s": ped_steps / wall if wall > 0 else 0.0,
+            "max_used_bytes": int(max_used),
+            "max_resident": int(max_resident),
+            "results": finished,
+        }

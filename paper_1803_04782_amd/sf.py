@@ -33,7 +33,11 @@ SF_KERNEL_COMMIT = 2
 # every symbol include/sf.h declares
 EXPORTS = ("sf_create_scene", "sf_step", "sf_field", "sf_positions", "sf_last_moves",
            "sf_static_field", "sf_set_state", "sf_stats", "sf_sync", "sf_set_timing",
-           "sf_kernel_time", "sf_destroy_scene", "sf_last_error")
+           "sf_kernel_time", "sf_destroy_scene", "sf_batch_create", "sf_batch_tune",
+           "sf_batch_get_tiling", "sf_batch_step", "sf_batch_stats", "sf_batch_sync",
+           "sf_batch_destroy",
+           "sf_last_error")
+_VOID = ("sf_destroy_scene", "sf_batch_destroy", "sf_last_error")
 
 
 class SceneDesc(ctypes.Structure):
@@ -50,6 +54,17 @@ class Stats(ctypes.Structure):
     _fields_ = [("step", ctypes.c_int64), ("live", ctypes.c_int64), ("evacuated", ctypes.c_int64),
                 ("ped_steps", ctypes.c_int64), ("movers", ctypes.c_int64),
                 ("moved", ctypes.c_int64), ("tied", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+class Tiling(ctypes.Structure):
+    """sf_batch_tiling: field tile shape and schedule of a batch (0 = default)."""
+    _fields_ = [("tw", ctypes.c_int32), ("hl", ctypes.c_int32), ("vec", ctypes.c_int32),
+                ("nw", ctypes.c_int32), ("list_cap", ctypes.c_int32),
+                ("blocks_per_cu", ctypes.c_int32), ("items_per_block", ctypes.c_int32),
+                ("max_chunk", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -87,10 +102,19 @@ def load():
                                    ctypes.POINTER(i64)]
     lib.sf_destroy_scene.argtypes = [P]
     lib.sf_destroy_scene.restype = None
+    lib.sf_batch_create.argtypes = [ctypes.POINTER(P), i32, ctypes.POINTER(Tiling), P,
+                                    ctypes.POINTER(P)]
+    lib.sf_batch_tune.argtypes = [P, i32, ctypes.POINTER(Tiling)]
+    lib.sf_batch_get_tiling.argtypes = [P, ctypes.POINTER(Tiling)]
+    lib.sf_batch_step.argtypes = [P, i32]
+    lib.sf_batch_stats.argtypes = [P, ctypes.POINTER(Stats)]
+    lib.sf_batch_sync.argtypes = [P]
+    lib.sf_batch_destroy.argtypes = [P]
+    lib.sf_batch_destroy.restype = None
     lib.sf_last_error.restype = ctypes.c_char_p
     lib.sf_last_error.argtypes = []
     for name in EXPORTS:
-        if name not in ("sf_destroy_scene", "sf_last_error"):
+        if name not in _VOID:
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -212,6 +236,60 @@ class GpuScene:
         n = ctypes.c_int64()
         _check(load().sf_kernel_time(self._h, int(kernel), ctypes.byref(ms), ctypes.byref(n)))
         return float(ms.value), int(n.value)
+
+
+class Batch:
+    """Scenes advanced together: one decide, commit and field launch per tick
+    for all members, replayed from captured HIP graphs (sf_batch_*)."""
+
+    def __init__(self, scenes, tiling: Optional[dict] = None, stream=None):
+        lib = load()
+        self.scenes = list(scenes)
+        arr = (ctypes.c_void_p * len(self.scenes))(*[s.handle.value for s in self.scenes])
+        t = Tiling(**tiling) if tiling else None
+        h = ctypes.c_void_p()
+        _check(lib.sf_batch_create(arr, len(self.scenes), ctypes.byref(t) if t else None,
+                                   _stream_handle(stream), ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            load().sf_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def step(self, n: int = 1):
+        _check(load().sf_batch_step(self._h, int(n)))
+
+    def sync(self):
+        _check(load().sf_batch_sync(self._h))
+
+    def stats(self) -> list:
+        """Running totals of every member (one launch, one copy)."""
+        arr = (Stats * len(self.scenes))()
+        _check(load().sf_batch_stats(self._h, arr))
+        return [a.as_dict() for a in arr]
+
+    def tune(self, reps: int = 3) -> dict:
+        t = Tiling()
+        _check(load().sf_batch_tune(self._h, int(reps), ctypes.byref(t)))
+        return t.as_dict()
+
+    def tiling(self) -> dict:
+        t = Tiling()
+        _check(load().sf_batch_get_tiling(self._h, ctypes.byref(t)))
+        return t.as_dict()
 
 
 def create_error(scene) -> tuple:

@@ -188,8 +188,7 @@ def test_tile_shape_invariance(sf, monkeypatch):
     fields = []
     base = ("16x2x2x4", "16x2x2x8", "16x4x2x4", "16x4x2x8", "16x4x4x4", "16x4x4x8",
             "32x2x2x4", "32x2x2x8", "32x4x2x4", "32x4x4x4", "8x4x4x4", "8x2x2x4")
-    # mode 1: wave-private source lists, mode 0: one list per workgroup strip
-    for shape in [f"{b}x{m}" for m in (1, 0) for b in base]:
+    for shape in base:
         monkeypatch.setenv("SF_TILE", shape)
         with sf.GpuScene(sc) as g:
             g.step(5)

@@ -1,0 +1,52 @@
+"""GPU test of the serving loop: requests arrive while others run, are admitted
+as memory and slots free up, and share batched ticks; every result must be
+the same as the scene run alone with sf_step for the same number of ticks."""
+import numpy as np
+import pytest
+
+from paper_1803_04782_amd import scenes, serve
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sf():
+    from paper_1803_04782_amd import sf as _sf
+
+    _sf.load()
+    return _sf
+
+
+def _request_scene(i):
+    rng = np.random.default_rng([7, i])
+    W = int(rng.integers(40, 140))
+    H = int(rng.integers(40, 140))
+    R = int(rng.choice([0, 2, 4, 8, 16]))
+    walls = tuple(rng.permutation(["W", "E", "N", "S"])[: int(rng.integers(1, 3))])
+    occ = float(rng.uniform(0.02, 0.12))
+    return scenes.build_scene(W, H, exits=walls, exit_width=6, n_peds=0, radius=R,
+                              seed=int(rng.integers(0, 2**31 - 1)), bernoulli=0.03,
+                              occupancy=occ, name=f"req{i}")
+
+
+def test_serving_results_match_scenes_alone(sf):
+    n = 24
+    arrivals = serve.poisson_arrivals(400.0, 0.5, seed=4)[:n]
+    reqs = [serve.Request(i, float(a), (lambda i=i: _request_scene(i)), max_steps=120)
+            for i, a in enumerate(arrivals)]
+    # a budget of about five mid-sized scenes forces queueing and turnover
+    budget = 5 * serve.footprint_bytes(_request_scene(0))
+    srv = serve.Server(budget, max_scenes=6, keep_positions=True)
+    out = srv.run(reqs)
+    print({k: v for k, v in out.items() if k != "results"}, flush=True)
+    assert out["finished"] == len(reqs)
+    assert out["max_used_bytes"] <= budget and out["max_resident"] <= 6
+    for f in out["results"]:
+        sc = _request_scene(f.rid)
+        with sf.GpuScene(sc) as g:
+            g.step(f.steps)
+            assert np.array_equal(g.positions(), f.positions), f.rid
+            alone = g.stats()
+        for k in ("step", "live", "evacuated", "ped_steps", "movers", "moved", "tied"):
+            assert alone[k] == f.stats[k], (f.rid, k, alone[k], f.stats[k])
+        assert f.stats["live"] == 0 or f.steps == 120
