@@ -169,6 +169,8 @@ void sf_destroy_scene(sf_scene *s);
  * scene, and runs of ticks are replayed from captured HIP graphs.  Every
  * member evolves exactly as under sf_step alone: the kernels are the same,
  * per scene, and the field's summation order does not depend on the launch.
+ * (Scenes are split into at most two groups, each with its own three launches
+ * per tick; see sf_batch_tiling.)
  *
  * While a scene belongs to a batch its work runs on the batch's stream:
  * sf_field, sf_positions, sf_last_moves, sf_static_field, sf_stats and sf_sync
@@ -178,7 +180,8 @@ void sf_destroy_scene(sf_scene *s);
  * first, later sf_batch_step calls on that batch fail with SF_EINVAL. */
 typedef struct sf_batch sf_batch; /* opaque, library-owned */
 
-/* Launch shape and schedule of a batch (a zero field = library default). */
+/* Launch shape and schedule of one group of a batch (a zero field = library
+ * default). */
 typedef struct {
     int32_t tw, hl, vec, nw;   /* field kernel: strip width in su, rows per lane,
                                   LDS vector width, waves per workgroup; one of
@@ -187,7 +190,19 @@ typedef struct {
     int32_t blocks_per_cu;     /* field kernel: workgroups per compute unit     */
     int32_t items_per_block;   /* field kernel: work items (runs of strips of
                                   one scene) dealt to each workgroup per tick  */
-    int32_t max_chunk;         /* decide kernel: most bitmap words per wave     */
+    int32_t decide_rows;       /* decide kernel: rows of a 64-su-wide tile      */
+} sf_group_tiling;
+
+/* A batch splits its scenes into up to two groups by field radius: group 0
+ * holds the scenes with radius <= split_radius, group 1 the others.  Each
+ * group has its own launches and tiling (small and large stamps favour
+ * different tile shapes and LDS budgets), and the two groups' ticks run as
+ * independent streams of work. */
+typedef struct {
+    int32_t groups;            /* 0 = two groups when both are non-empty, 1 = one
+                                  group (group[0]), 2 = two groups              */
+    int32_t split_radius;      /* 0 = default (8)                               */
+    sf_group_tiling group[2];
 } sf_batch_tiling;
 
 /* Group n_scenes (>= 1, distinct, none in another batch, all on the current
@@ -198,9 +213,9 @@ typedef struct {
 int sf_batch_create(sf_scene *const *scenes, int32_t n_scenes, const sf_batch_tiling *tiling,
                     void *hip_stream, sf_batch **out);
 
-/* Autotuner: times the field launch of every compiled shape and a few
- * schedules on the batch's current state (`reps` launches each, median
- * kept), adopts the fastest and, if `chosen` is not NULL, reports it.  The
+/* Autotuner: for each group, times the field launch of every compiled shape
+ * and a few schedules on the batch's current state (`reps` launches each,
+ * median kept), adopts the fastest and, if `chosen` is not NULL, reports it.  The
  * scenes' state is unchanged (the field is recomputed, bit for bit).
  * Blocks. */
 int sf_batch_tune(sf_batch *b, int32_t reps, sf_batch_tiling *chosen);

@@ -66,7 +66,7 @@ struct sf_scene {
     int ncu = 0;
     // layout
     int wpr = 0;          // 64-bit words per bitmap row
-    int chunk = 4;        // bitmap words per wave in the decide kernel
+    int dec_rows = 8;     // rows of a decide tile
     ListCfg lc;           // pedestrian field launch shape
     float phi_axial = 0.f, phi_diag = 0.f;
     // device state
@@ -102,16 +102,25 @@ struct sf_scene {
 
 namespace {
 
-// Device-side layout of a batch for one tiling: the member views, the
-// workgroup -> scene maps of the decide and commit launches, the field work
-// items and the stamp tables (one per distinct radius and field law).
-struct BatchLayout {
-    sf_batch_tiling t = {};
+// Device-side layout of one group of a batch for one tiling: the member
+// views, the workgroup -> scene maps of the decide and commit launches, the
+// field work items and the stamp tables (one per distinct radius and law).
+struct GroupLayout {
+    sf_group_tiling t = {};
+    std::vector<int> members;  // indices into sf_batch::scenes
     FieldLaunch fl;
-    int n_items = 0, dec_blocks = 0, com_blocks = 0, max_chunk = 4;
+    int n_items = 0, dec_blocks = 0, com_blocks = 0, max_rows = 4;
     SceneView *d_views = nullptr;
     int32_t *d_dec_scene = nullptr, *d_com_scene = nullptr, *d_items = nullptr;
-    unsigned long long *d_totals = nullptr;  // 8 words per scene (sf_batch_stats)
+    std::vector<void *> bufs;
+};
+
+struct BatchLayout {
+    sf_batch_tiling t = {};
+    int n_groups = 0;
+    GroupLayout g[2];
+    SceneView *d_all = nullptr;               // every member, batch order (totals)
+    unsigned long long *d_totals = nullptr;   // 8 words per scene (sf_batch_stats)
     std::vector<void *> bufs;
 };
 
@@ -120,7 +129,10 @@ struct BatchLayout {
 struct sf_batch {
     int device = 0;
     hipStream_t stream = nullptr;   // where ticks run (caller's stream)
-    hipStream_t capture = nullptr;  // private stream on which graphs are captured
+    hipStream_t aux = nullptr;      // second group's ticks (joined back to `stream`)
+    hipStream_t capture = nullptr;  // private streams on which graphs are captured
+    hipStream_t capture_aux = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
     int ncu = 0;
     size_t max_lds = 0;
     std::vector<sf_scene *> scenes;
@@ -443,7 +455,13 @@ int create(const sf_scene_desc *d, void *hip_stream, sf_scene **out)
     SF_HIP(hipDeviceGetAttribute(&s->ncu, hipDeviceAttributeMultiprocessorCount, s->device),
            "CU count");
     s->wpr = (s->W + 63) / 64;
-    s->chunk = sf::pick_decide_chunk(s->W, s->H, s->N);
+    s->dec_rows = sf::decide_rows(s->W, s->H, s->N, s->ncu);
+    if (const char *e = std::getenv("SF_DECIDE_ROWS")) {
+        // override of the decide kernel's tile rows (speed only)
+        const int r = std::atoi(e);
+        if (r < 1 || r > 64) return fail(SF_EINVAL, "SF_DECIDE_ROWS=%s outside 1..64", e);
+        s->dec_rows = r;
+    }
 
     int max_lds = 0;
     SF_HIP(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, s->device),
@@ -525,7 +543,7 @@ int setup_launches(sf_scene *s)
     v.wpr = s->wpr;
     v.N = s->N;
     v.R = s->R;
-    v.chunk = s->chunk;
+    v.dec_rows = s->dec_rows;
     v.dec_block0 = 0;
     v.com_block0 = 0;
     v.phi_axial = s->phi_axial;
@@ -589,8 +607,15 @@ int balloc(std::vector<void *> &owned, T **p, size_t n, const char *what)
     return SF_OK;
 }
 
+void free_group(GroupLayout &G)
+{
+    for (void *p : G.bufs) (void)hipFree(p);
+    G = GroupLayout{};
+}
+
 void free_layout(BatchLayout &L)
 {
+    for (GroupLayout &G : L.g) free_group(G);
     for (void *p : L.bufs) (void)hipFree(p);
     L = BatchLayout{};
 }
@@ -604,59 +629,191 @@ void drop_graphs(sf_batch *b)
     b->graphs.clear();
 }
 
-int max_radius(const sf_batch *b)
+constexpr int kDefaultSplitRadius = 8;
+
+// Member indices of each group for tiling `t` (groups and split filled in).
+int split_members(const sf_batch *b, sf_batch_tiling *t, std::vector<int> (&members)[2])
 {
-    int r = 0;
-    for (const sf_scene *s : b->scenes) r = std::max(r, s->R);
-    return r;
+    if (t->groups < 0 || t->groups > 2) return fail(SF_EINVAL, "groups %d outside 0..2", t->groups);
+    if (t->split_radius < 0 || t->split_radius > SF_MAX_RADIUS)
+        return fail(SF_EINVAL, "split_radius %d outside 0..%d", t->split_radius, SF_MAX_RADIUS);
+    if (t->split_radius == 0) t->split_radius = kDefaultSplitRadius;
+    members[0].clear();
+    members[1].clear();
+    for (int j = 0; j < (int)b->scenes.size(); ++j)
+        members[b->scenes[(size_t)j]->R <= t->split_radius ? 0 : 1].push_back(j);
+    if (t->groups == 0) t->groups = (!members[0].empty() && !members[1].empty()) ? 2 : 1;
+    if (t->groups == 1) {
+        for (int j : members[1]) members[0].push_back(j);
+        std::sort(members[0].begin(), members[0].end());
+        members[1].clear();
+    } else if (members[0].empty() || members[1].empty()) {
+        return fail(SF_EINVAL, "split at radius %d leaves a group empty", t->split_radius);
+    }
+    return SF_OK;
 }
 
-// Fill in the defaults of `in` and check it against the batch's largest
-// radius; `lc` receives the launch shape at that radius.
-int resolve_tiling(const sf_batch *b, const sf_batch_tiling *in, sf_batch_tiling *out,
-                   ListCfg *lc)
+// Fill in the defaults of group tiling `t` and check it against the group's
+// largest radius R; `lc` receives the launch shape at that radius.
+int resolve_group_tiling(const sf_batch *b, int R, sf_group_tiling *t, ListCfg *lc)
 {
-    sf_batch_tiling t = in ? *in : sf_batch_tiling{};
-    const int R = max_radius(b);
     const size_t lds_cap = b->max_lds - 1024;
-    if (t.tw == 0 && t.hl == 0 && t.vec == 0 && t.nw == 0) {
+    if (t->tw == 0 && t->hl == 0 && t->vec == 0 && t->nw == 0) {
         const ListCfg d = sf::pick_list_cfg(R, lds_cap);
-        t.tw = d.tw;
-        t.hl = d.hl;
-        t.vec = d.vec;
-        t.nw = d.nw;
-        if (t.list_cap == 0) t.list_cap = d.list_cap;
+        t->tw = d.tw;
+        t->hl = d.hl;
+        t->vec = d.vec;
+        t->nw = d.nw;
+        if (t->list_cap == 0) t->list_cap = d.list_cap;
     }
-    if (!sf::list_shape_compiled(t.tw, t.hl, t.vec, t.nw))
-        return fail(SF_EINVAL, "tiling %dx%dx%dx%d is not a compiled shape", t.tw, t.hl, t.vec,
-                    t.nw);
-    if (t.list_cap == 0) {
+    if (!sf::list_shape_compiled(t->tw, t->hl, t->vec, t->nw))
+        return fail(SF_EINVAL, "tiling %dx%dx%dx%d is not a compiled shape", t->tw, t->hl, t->vec,
+                    t->nw);
+    if (t->list_cap == 0) {
         for (int cap = 4096; cap >= 512; cap /= 2) {
-            const ListCfg c = sf::make_list_cfg(R, t.tw, t.hl, t.vec, t.nw, cap);
+            const ListCfg c = sf::make_list_cfg(R, t->tw, t->hl, t->vec, t->nw, cap);
             if (c.lds_bytes <= lds_cap) {
-                t.list_cap = cap;
+                t->list_cap = cap;
                 break;
             }
         }
     }
-    if (t.list_cap < 0 || t.list_cap > (1 << 16))
-        return fail(SF_EINVAL, "list_cap %d outside 0..65536", t.list_cap);
-    const ListCfg c = sf::make_list_cfg(R, t.tw, t.hl, t.vec, t.nw, t.list_cap);
-    if (c.list_cap < 2 * c.max_row || c.halo_rows > 64 * t.nw || c.lds_bytes > lds_cap)
+    if (t->list_cap < 0 || t->list_cap > (1 << 16))
+        return fail(SF_EINVAL, "list_cap %d outside 0..65536", t->list_cap);
+    const ListCfg c = sf::make_list_cfg(R, t->tw, t->hl, t->vec, t->nw, t->list_cap);
+    if (c.list_cap < 2 * c.max_row || c.halo_rows > 64 * t->nw || c.lds_bytes > lds_cap)
         return fail(SF_EINVAL, "tiling %dx%dx%dx%d with list_cap %d does not fit radius %d",
-                    t.tw, t.hl, t.vec, t.nw, t.list_cap, R);
-    const int bpc_max = std::max(1, std::min((int)((160 * 1024) / c.lds_bytes), 32 / t.nw));
-    if (t.blocks_per_cu == 0) t.blocks_per_cu = bpc_max;
-    if (t.blocks_per_cu < 1 || t.blocks_per_cu > 64)
-        return fail(SF_EINVAL, "blocks_per_cu %d outside 1..64", t.blocks_per_cu);
-    if (t.items_per_block == 0) t.items_per_block = 8;
-    if (t.items_per_block < 1 || t.items_per_block > 4096)
-        return fail(SF_EINVAL, "items_per_block %d outside 1..4096", t.items_per_block);
-    if (t.max_chunk == 0) t.max_chunk = 32;
-    if (t.max_chunk < 4 || t.max_chunk > 64 || (t.max_chunk & (t.max_chunk - 1)))
-        return fail(SF_EINVAL, "max_chunk %d is not a power of two in 4..64", t.max_chunk);
-    *out = t;
+                    t->tw, t->hl, t->vec, t->nw, t->list_cap, R);
+    const int bpc_max = std::max(1, std::min((int)((160 * 1024) / c.lds_bytes), 32 / t->nw));
+    if (t->blocks_per_cu == 0) t->blocks_per_cu = bpc_max;
+    if (t->blocks_per_cu < 1 || t->blocks_per_cu > 64)
+        return fail(SF_EINVAL, "blocks_per_cu %d outside 1..64", t->blocks_per_cu);
+    if (t->items_per_block == 0) t->items_per_block = 8;
+    if (t->items_per_block < 1 || t->items_per_block > 4096)
+        return fail(SF_EINVAL, "items_per_block %d outside 1..4096", t->items_per_block);
+    if (t->decide_rows == 0) t->decide_rows = 32;
+    if (t->decide_rows < 1 || t->decide_rows > 64)
+        return fail(SF_EINVAL, "decide_rows %d outside 1..64", t->decide_rows);
     *lc = c;
+    return SF_OK;
+}
+
+// Device layout of one group.  `views` (indexed like sf_batch::scenes)
+// receives the members' views.
+int build_group(sf_batch *b, const std::vector<int> &members, const sf_group_tiling &req,
+                GroupLayout *out, std::vector<SceneView> &views)
+{
+    GroupLayout G;
+    struct Guard {
+        GroupLayout *G;
+        ~Guard()
+        {
+            if (G) free_group(*G);
+        }
+    } guard{&G};
+    int R = 0;
+    for (int j : members) R = std::max(R, b->scenes[(size_t)j]->R);
+    G.t = req;
+    G.members = members;
+    ListCfg lmax;
+    int rc = resolve_group_tiling(b, R, &G.t, &lmax);
+    if (rc) return rc;
+    const sf_group_tiling &t = G.t;
+    G.fl = sf::field_launch_for(lmax);
+    G.fl.grid = b->ncu * t.blocks_per_cu;
+    hipStream_t st = b->stream;
+
+    const int n = (int)members.size();
+    std::vector<SceneView> gv((size_t)n);
+    std::vector<double> strip_cost((size_t)n);
+    std::map<std::tuple<int, double, double>, float *> tables;
+    int64_t dec_total = 0, com_total = 0;
+    for (int q = 0; q < n; ++q) {
+        const sf_scene *s = b->scenes[(size_t)members[(size_t)q]];
+        const ListCfg lc = sf::make_list_cfg(s->R, t.tw, t.hl, t.vec, t.nw, t.list_cap);
+        const auto key = std::make_tuple(s->R, s->k, s->alpha);
+        float *&tab = tables[key];
+        if (!tab) {
+            if ((rc = balloc(G.bufs, &tab, (size_t)lc.vec * lc.copy_elems, "batch phi table")))
+                return rc;
+            SF_HIP(sf::launch_phi_copies(tab, lc, s->k, s->alpha, st), "batch phi table");
+        }
+        SceneView v = s->view;
+        sf::set_view_layout(v, lc, tab);
+        v.dec_rows = t.decide_rows;
+        v.dec_block0 = (int32_t)dec_total;
+        v.com_block0 = (int32_t)com_total;
+        dec_total += sf::decide_blocks(s->wpr, s->H, v.dec_rows);
+        com_total += sf::commit_blocks(s->N);
+        if (dec_total >= INT32_MAX / 2 || com_total >= INT32_MAX / 2)
+            return fail(SF_EINVAL, "batch too large for one launch");
+        G.max_rows = std::max(G.max_rows, v.dec_rows);
+        gv[(size_t)q] = v;
+        views[(size_t)members[(size_t)q]] = v;
+        // relative cost of one strip: its su, plus the sources each wave
+        // gathers (density times the wave tile's halo window)
+        const double rho = (double)s->N / ((double)s->W * s->H);
+        strip_cost[(size_t)q] = (double)lc.tw * lc.wt +
+                                4.0 * lc.nw * rho * (lc.tw + 2.0 * s->R) * (lc.th + 2.0 * s->R);
+    }
+    G.dec_blocks = (int)dec_total;
+    G.com_blocks = (int)com_total;
+    std::vector<int32_t> dec_scene((size_t)dec_total), com_scene((size_t)com_total);
+    for (int q = 0; q < n; ++q) {
+        const SceneView &v = gv[(size_t)q];
+        const int64_t d1 = q + 1 < n ? gv[(size_t)q + 1].dec_block0 : dec_total;
+        const int64_t c1 = q + 1 < n ? gv[(size_t)q + 1].com_block0 : com_total;
+        std::fill(dec_scene.begin() + v.dec_block0, dec_scene.begin() + d1, q);
+        std::fill(com_scene.begin() + v.com_block0, com_scene.begin() + c1, q);
+    }
+
+    // field items: runs of strips of about equal estimated cost, scenes that
+    // share a table adjacent (largest radius first), so that a workgroup's
+    // successive items rarely reload the table
+    double total = 0.0;
+    for (int q = 0; q < n; ++q) total += strip_cost[(size_t)q] * gv[(size_t)q].n_strips;
+    const double per_item = total / std::max(1.0, (double)G.fl.grid * t.items_per_block);
+    std::vector<int> order((size_t)n);
+    for (int q = 0; q < n; ++q) order[(size_t)q] = q;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
+        const sf_scene *x = b->scenes[(size_t)members[(size_t)a]];
+        const sf_scene *y = b->scenes[(size_t)members[(size_t)c]];
+        return std::make_tuple(-x->R, x->k, x->alpha, -strip_cost[(size_t)a]) <
+               std::make_tuple(-y->R, y->k, y->alpha, -strip_cost[(size_t)c]);
+    });
+    std::vector<int32_t> items;
+    for (int q : order) {
+        const int ns = gv[(size_t)q].n_strips;
+        const int per = (int)std::max(
+            1.0, std::min((double)ns, std::floor(per_item / strip_cost[(size_t)q] + 0.5)));
+        for (int a = 0; a < ns; a += per) {
+            items.push_back(q);
+            items.push_back(a);
+            items.push_back(std::min(ns, a + per));
+            items.push_back(0);
+        }
+    }
+    G.n_items = (int)(items.size() / 4);
+
+    if ((rc = balloc(G.bufs, &G.d_views, gv.size(), "batch views")) ||
+        (rc = balloc(G.bufs, &G.d_dec_scene, dec_scene.size(), "batch decide map")) ||
+        (rc = balloc(G.bufs, &G.d_com_scene, com_scene.size(), "batch commit map")) ||
+        (rc = balloc(G.bufs, &G.d_items, items.size(), "batch items")))
+        return rc;
+    SF_HIP(hipMemcpyAsync(G.d_views, gv.data(), gv.size() * sizeof(SceneView),
+                          hipMemcpyHostToDevice, st),
+           "batch views");
+    SF_HIP(hipMemcpyAsync(G.d_dec_scene, dec_scene.data(), dec_scene.size() * 4,
+                          hipMemcpyHostToDevice, st),
+           "batch decide map");
+    SF_HIP(hipMemcpyAsync(G.d_com_scene, com_scene.data(), com_scene.size() * 4,
+                          hipMemcpyHostToDevice, st),
+           "batch commit map");
+    SF_HIP(hipMemcpyAsync(G.d_items, items.data(), items.size() * 4, hipMemcpyHostToDevice, st),
+           "batch items");
+    SF_HIP(hipStreamSynchronize(st), "batch layout sync");
+    *out = G;
+    guard.G = nullptr;
     return SF_OK;
 }
 
@@ -670,121 +827,62 @@ int build_layout(sf_batch *b, const sf_batch_tiling *req, BatchLayout *out)
             if (L) free_layout(*L);
         }
     } guard{&L};
-    ListCfg lmax;
-    int rc = resolve_tiling(b, req, &L.t, &lmax);
+    L.t = req ? *req : sf_batch_tiling{};
+    std::vector<int> members[2];
+    int rc = split_members(b, &L.t, members);
     if (rc) return rc;
-    const sf_batch_tiling &t = L.t;
-    L.fl = sf::field_launch_for(lmax);
-    L.fl.grid = b->ncu * t.blocks_per_cu;
-    hipStream_t st = b->stream;
-
-    const int n = (int)b->scenes.size();
-    std::vector<SceneView> views((size_t)n);
-    std::vector<double> strip_cost((size_t)n);
-    std::map<std::tuple<int, double, double>, float *> tables;
-    int64_t dec_total = 0, com_total = 0;
-    for (int j = 0; j < n; ++j) {
-        const sf_scene *s = b->scenes[(size_t)j];
-        const ListCfg lc = sf::make_list_cfg(s->R, t.tw, t.hl, t.vec, t.nw, t.list_cap);
-        const auto key = std::make_tuple(s->R, s->k, s->alpha);
-        float *&tab = tables[key];
-        if (!tab) {
-            if ((rc = balloc(L.bufs, &tab, (size_t)lc.vec * lc.copy_elems, "batch phi table")))
-                return rc;
-            SF_HIP(sf::launch_phi_copies(tab, lc, s->k, s->alpha, st), "batch phi table");
-        }
-        SceneView v = s->view;
-        sf::set_view_layout(v, lc, tab);
-        v.chunk = std::min(s->chunk, t.max_chunk);
-        v.dec_block0 = (int32_t)dec_total;
-        v.com_block0 = (int32_t)com_total;
-        dec_total += sf::decide_blocks(s->wpr, s->H, v.chunk);
-        com_total += sf::commit_blocks(s->N);
-        if (dec_total >= INT32_MAX / 2 || com_total >= INT32_MAX / 2)
-            return fail(SF_EINVAL, "batch too large for one launch");
-        L.max_chunk = std::max(L.max_chunk, v.chunk);
-        views[(size_t)j] = v;
-        // relative cost of one strip: its su, plus the sources each wave
-        // gathers (density times the wave tile's halo window)
-        const double rho = (double)s->N / ((double)s->W * s->H);
-        strip_cost[(size_t)j] = (double)lc.tw * lc.wt +
-                                4.0 * lc.nw * rho * (lc.tw + 2.0 * s->R) * (lc.th + 2.0 * s->R);
+    L.n_groups = L.t.groups;
+    std::vector<SceneView> views(b->scenes.size());
+    for (int gi = 0; gi < L.n_groups; ++gi) {
+        if ((rc = build_group(b, members[gi], L.t.group[gi], &L.g[gi], views))) return rc;
+        L.t.group[gi] = L.g[gi].t;
     }
-    L.dec_blocks = (int)dec_total;
-    L.com_blocks = (int)com_total;
-    std::vector<int32_t> dec_scene((size_t)dec_total), com_scene((size_t)com_total);
-    for (int j = 0; j < n; ++j) {
-        const SceneView &v = views[(size_t)j];
-        const int64_t d1 = j + 1 < n ? views[(size_t)j + 1].dec_block0 : dec_total;
-        const int64_t c1 = j + 1 < n ? views[(size_t)j + 1].com_block0 : com_total;
-        std::fill(dec_scene.begin() + v.dec_block0, dec_scene.begin() + d1, j);
-        std::fill(com_scene.begin() + v.com_block0, com_scene.begin() + c1, j);
-    }
-
-    // field items: runs of strips of about equal estimated cost, scenes that
-    // share a table adjacent (largest radius first), so that a workgroup's
-    // successive items rarely reload the table
-    double total = 0.0;
-    for (int j = 0; j < n; ++j) total += strip_cost[(size_t)j] * views[(size_t)j].n_strips;
-    const double per_item = total / std::max(1.0, (double)L.fl.grid * t.items_per_block);
-    std::vector<int> order((size_t)n);
-    for (int j = 0; j < n; ++j) order[(size_t)j] = j;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
-        const sf_scene *x = b->scenes[(size_t)a], *y = b->scenes[(size_t)c];
-        return std::make_tuple(-x->R, x->k, x->alpha, -strip_cost[(size_t)a]) <
-               std::make_tuple(-y->R, y->k, y->alpha, -strip_cost[(size_t)c]);
-    });
-    std::vector<int32_t> items;
-    for (int j : order) {
-        const int ns = views[(size_t)j].n_strips;
-        const int per = (int)std::max(1.0, std::min((double)ns,
-                                                    std::floor(per_item / strip_cost[(size_t)j] + 0.5)));
-        for (int a = 0; a < ns; a += per) {
-            items.push_back(j);
-            items.push_back(a);
-            items.push_back(std::min(ns, a + per));
-            items.push_back(0);
-        }
-    }
-    L.n_items = (int)(items.size() / 4);
-
-    if ((rc = balloc(L.bufs, &L.d_views, views.size(), "batch views")) ||
-        (rc = balloc(L.bufs, &L.d_dec_scene, dec_scene.size(), "batch decide map")) ||
-        (rc = balloc(L.bufs, &L.d_com_scene, com_scene.size(), "batch commit map")) ||
-        (rc = balloc(L.bufs, &L.d_items, items.size(), "batch items")) ||
+    if (L.n_groups == 1) L.t.group[1] = L.t.group[0];
+    if ((rc = balloc(L.bufs, &L.d_all, views.size(), "batch views")) ||
         (rc = balloc(L.bufs, &L.d_totals, views.size() * 8, "batch totals")))
         return rc;
-    SF_HIP(hipMemcpyAsync(L.d_views, views.data(), views.size() * sizeof(SceneView),
-                          hipMemcpyHostToDevice, st),
+    SF_HIP(hipMemcpyAsync(L.d_all, views.data(), views.size() * sizeof(SceneView),
+                          hipMemcpyHostToDevice, b->stream),
            "batch views");
-    SF_HIP(hipMemcpyAsync(L.d_dec_scene, dec_scene.data(), dec_scene.size() * 4,
-                          hipMemcpyHostToDevice, st),
-           "batch decide map");
-    SF_HIP(hipMemcpyAsync(L.d_com_scene, com_scene.data(), com_scene.size() * 4,
-                          hipMemcpyHostToDevice, st),
-           "batch commit map");
-    SF_HIP(hipMemcpyAsync(L.d_items, items.data(), items.size() * 4, hipMemcpyHostToDevice, st),
-           "batch items");
-    SF_HIP(hipStreamSynchronize(st), "batch layout sync");
+    SF_HIP(hipStreamSynchronize(b->stream), "batch layout sync");
     *out = L;
     guard.L = nullptr;
     return SF_OK;
 }
 
-int batch_field(const sf_batch *b, const BatchLayout &L, hipStream_t st,
-                const sf::LaunchEvents *ev = nullptr)
+int group_field(const GroupLayout &G, hipStream_t st, const sf::LaunchEvents *ev = nullptr)
 {
-    SF_HIP(sf::launch_field(L.fl, L.d_views, L.d_items, L.n_items, st, ev), "batch field");
+    SF_HIP(sf::launch_field(G.fl, G.d_views, G.d_items, G.n_items, st, ev), "batch field");
     return SF_OK;
 }
 
-int batch_tick(const sf_batch *b, hipStream_t st)
+int group_tick(const GroupLayout &G, hipStream_t st)
+{
+    SF_HIP(sf::launch_decide_claim(G.d_views, G.d_dec_scene, G.dec_blocks, G.max_rows, st),
+           "batch decide");
+    SF_HIP(sf::launch_commit(G.d_views, G.d_com_scene, G.com_blocks, st), "batch commit");
+    return group_field(G, st);
+}
+
+// `k` ticks of every group: group 0 on `main`, group 1 on `aux`, forked
+// from and joined back into `main` (the groups share no scene).
+int batch_ticks(const sf_batch *b, int k, hipStream_t main, hipStream_t aux)
 {
     const BatchLayout &L = b->cur;
-    SF_HIP(sf::launch_decide_claim(L.d_views, L.d_dec_scene, L.dec_blocks, L.max_chunk, st),
-           "batch decide");
-    SF_HIP(sf::launch_commit(L.d_views, L.d_com_scene, L.com_blocks, st), "batch commit");
-    return batch_field(b, L, st);
+    int rc;
+    if (L.n_groups == 2) {
+        SF_HIP(hipEventRecord(b->fork, main), "fork");
+        SF_HIP(hipStreamWaitEvent(aux, b->fork, 0), "fork wait");
+    }
+    for (int i = 0; i < k; ++i)
+        if ((rc = group_tick(L.g[0], main))) return rc;
+    if (L.n_groups == 2) {
+        for (int i = 0; i < k; ++i)
+            if ((rc = group_tick(L.g[1], aux))) return rc;
+        SF_HIP(hipEventRecord(b->join, aux), "join");
+        SF_HIP(hipStreamWaitEvent(main, b->join, 0), "join wait");
+    }
+    return SF_OK;
 }
 
 // Executable graph of `k` ticks, captured on first use.
@@ -796,8 +894,7 @@ int batch_graph(sf_batch *b, int k, hipGraphExec_t *out)
         return SF_OK;
     }
     SF_HIP(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal), "begin capture");
-    int rc = SF_OK;
-    for (int i = 0; i < k && rc == SF_OK; ++i) rc = batch_tick(b, b->capture);
+    const int rc = batch_ticks(b, k, b->capture, b->capture_aux);
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(b->capture, &g);
     if (rc) {
@@ -817,6 +914,15 @@ int batch_graph(sf_batch *b, int k, hipGraphExec_t *out)
 }
 
 constexpr int kGraphTicks = 8;
+
+void destroy_batch_streams(sf_batch *b)
+{
+    if (b->aux) (void)hipStreamDestroy(b->aux);
+    if (b->capture) (void)hipStreamDestroy(b->capture);
+    if (b->capture_aux) (void)hipStreamDestroy(b->capture_aux);
+    if (b->fork) (void)hipEventDestroy(b->fork);
+    if (b->join) (void)hipEventDestroy(b->join);
+}
 
 int batch_create(sf_scene *const *scenes, int32_t n, const sf_batch_tiling *tiling,
                  void *hip_stream, sf_batch **out)
@@ -840,7 +946,7 @@ int batch_create(sf_scene *const *scenes, int32_t n, const sf_batch_tiling *tili
         {
             if (*b) {
                 free_layout((*b)->cur);
-                if ((*b)->capture) (void)hipStreamDestroy((*b)->capture);
+                destroy_batch_streams(*b);
                 delete *b;
             }
         }
@@ -854,7 +960,11 @@ int batch_create(sf_scene *const *scenes, int32_t n, const sf_batch_tiling *tili
            "LDS size");
     b->max_lds = (size_t)max_lds;
     SF_HIP(sf::set_field_lds_limit(b->max_lds - 1024), "LDS limit");
+    SF_HIP(hipStreamCreateWithFlags(&b->aux, hipStreamNonBlocking), "batch stream");
     SF_HIP(hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking), "capture stream");
+    SF_HIP(hipStreamCreateWithFlags(&b->capture_aux, hipStreamNonBlocking), "capture stream");
+    SF_HIP(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming), "fork event");
+    SF_HIP(hipEventCreateWithFlags(&b->join, hipEventDisableTiming), "join event");
     for (sf_scene *s : b->scenes) SF_HIP(hipStreamSynchronize(s->stream), "scene sync");
     int rc = build_layout(b, tiling, &b->cur);
     if (rc) return rc;
@@ -864,6 +974,23 @@ int batch_create(sf_scene *const *scenes, int32_t n, const sf_batch_tiling *tili
     }
     *out = b;
     b = nullptr;
+    return SF_OK;
+}
+
+// Median of `reps` timed field launches of group layout G.
+int time_group_field(sf_batch *b, const GroupLayout &G, int reps, const EventPair &ep,
+                     double *med)
+{
+    std::vector<float> ms((size_t)reps);
+    const sf::LaunchEvents lev{ep.a, ep.b};
+    for (int r = 0; r < reps; ++r) {
+        int rc = group_field(G, b->stream, &lev);
+        if (rc) return rc;
+        SF_HIP(hipEventSynchronize(ep.b), "tune sync");
+        SF_HIP(hipEventElapsedTime(&ms[(size_t)r], ep.a, ep.b), "tune timing");
+    }
+    std::sort(ms.begin(), ms.end());
+    *med = ms[ms.size() / 2];
     return SF_OK;
 }
 
@@ -889,46 +1016,40 @@ int batch_tune(sf_batch *b, int32_t reps, sf_batch_tiling *chosen)
                                     {32, 4, 2, 4}, {32, 4, 4, 4}, {8, 4, 4, 4},  {8, 2, 2, 4}};
     const int caps[] = {1024, 2048, 4096};
     const int ipbs[] = {2, 8};
-    double best_ms = 1e30;
     sf_batch_tiling best = b->cur.t;
-    std::vector<float> ms((size_t)reps);
-    for (const auto &sh : shapes) {
-        for (int cap : caps) {
-            for (int ipb : ipbs) {
-                sf_batch_tiling t = b->cur.t;
-                t.tw = sh[0];
-                t.hl = sh[1];
-                t.vec = sh[2];
-                t.nw = sh[3];
-                t.list_cap = cap;
-                t.blocks_per_cu = 0;
-                t.items_per_block = ipb;
-                BatchLayout L;
-                if (build_layout(b, &t, &L) != SF_OK) continue;  // shape does not fit
-                int rc = SF_OK;
-                const sf::LaunchEvents lev{ep.a, ep.b};
-                for (int r = 0; r < reps && rc == SF_OK; ++r) {
-                    rc = batch_field(b, L, b->stream, &lev);
-                    if (rc == SF_OK) {
-                        const hipError_t e1 = hipEventSynchronize(ep.b);
-                        const hipError_t e2 = e1 == hipSuccess
-                                                  ? hipEventElapsedTime(&ms[(size_t)r], ep.a, ep.b)
-                                                  : e1;
-                        if (e2 != hipSuccess) rc = hip_fail(e2, "tune timing");
+    std::vector<SceneView> scratch_views(b->scenes.size());
+    for (int gi = 0; gi < b->cur.n_groups; ++gi) {
+        const std::vector<int> members = b->cur.g[gi].members;
+        double best_ms = 1e30;
+        for (const auto &sh : shapes) {
+            for (int cap : caps) {
+                for (int ipb : ipbs) {
+                    sf_group_tiling t = b->cur.g[gi].t;
+                    t.tw = sh[0];
+                    t.hl = sh[1];
+                    t.vec = sh[2];
+                    t.nw = sh[3];
+                    t.list_cap = cap;
+                    t.blocks_per_cu = 0;
+                    t.items_per_block = ipb;
+                    GroupLayout G;
+                    if (build_group(b, members, t, &G, scratch_views) != SF_OK)
+                        continue;  // shape does not fit this group
+                    double med = 0.0;
+                    const int rc = time_group_field(b, G, reps, ep, &med);
+                    const sf_group_tiling used = G.t;
+                    free_group(G);
+                    if (rc) return rc;
+                    if (med < best_ms) {
+                        best_ms = med;
+                        best.group[gi] = used;
                     }
-                }
-                free_layout(L);
-                if (rc) return rc;
-                std::vector<float> sorted = ms;
-                std::sort(sorted.begin(), sorted.end());
-                const double med = sorted[sorted.size() / 2];
-                if (med < best_ms) {
-                    best_ms = med;
-                    best = t;
                 }
             }
         }
     }
+    if (b->cur.n_groups == 1) best.group[1] = best.group[0];
+    g_last_error.clear();
     BatchLayout L;
     int rc = build_layout(b, &best, &L);
     if (rc) return rc;
@@ -1155,7 +1276,7 @@ int sf_batch_step(sf_batch *b, int32_t n_steps)
         if (n_steps == 1) {
             // a single tick is launched directly (a batch whose membership
             // changes every tick would not reuse a captured graph)
-            return batch_tick(b, b->stream);
+            return batch_ticks(b, 1, b->stream, b->aux);
         }
         while (n_steps > 0) {
             const int k = std::min(n_steps, kGraphTicks);
@@ -1179,7 +1300,7 @@ int sf_batch_stats(const sf_batch *b, sf_stats_t *out)
     try {
         const size_t n = b->scenes.size();
         std::vector<unsigned long long> h(n * 8);
-        SF_HIP(sf::launch_sum_counters(b->cur.d_views, (int)n, b->cur.d_totals, b->stream),
+        SF_HIP(sf::launch_sum_counters(b->cur.d_all, (int)n, b->cur.d_totals, b->stream),
                "batch totals");
         SF_HIP(hipMemcpyAsync(h.data(), b->cur.d_totals, h.size() * 8, hipMemcpyDeviceToHost,
                               b->stream),
@@ -1218,9 +1339,10 @@ void sf_batch_destroy(sf_batch *b)
         s->batch = nullptr;
         s->stream = s->own_stream;
     }
+    (void)hipStreamSynchronize(b->aux);
     drop_graphs(b);
     free_layout(b->cur);
-    if (b->capture) (void)hipStreamDestroy(b->capture);
+    destroy_batch_streams(b);
     delete b;
 }
 

@@ -96,7 +96,7 @@ hipError_t set_field_lds_limit(size_t bytes);
 struct SceneView {
     int32_t W, H, wpr, N;
     int32_t R;
-    int32_t chunk;       // decide: bitmap words per wave
+    int32_t dec_rows;    // decide: tile rows (tiles are 64 su wide)
     int32_t dec_block0;  // first workgroup of this scene in the decide launch
     int32_t com_block0;  // first workgroup of this scene in the commit launch
     // field gather layout of this scene's radius under the launch's tile shape
@@ -123,7 +123,7 @@ struct SceneView {
 void set_view_layout(SceneView &v, const ListCfg &c, const float *tab);
 
 // Workgroups of a scene in the decide and commit launches.
-int decide_blocks(int wpr, int H, int chunk);
+int decide_blocks(int wpr, int H, int rows);
 int commit_blocks(int N);
 
 // One field launch over `n_items` work items (int4: scene, first strip,
@@ -176,13 +176,15 @@ hipError_t launch_static_S(const int32_t *D, const double *O, const uint8_t *obs
 hipError_t launch_occ_init(const int32_t *pos, int N, unsigned long long *occ, int wpr, int W,
                            const int32_t *ext, unsigned long long *owner,
                            unsigned long long *ctr, hipStream_t st);
-// Words of the occupancy bitmap handled per wave by the decide kernel.
-int pick_decide_chunk(int W, int H, int N);
+// Rows of a decide tile (4..32) for a scene; LDS bytes of a launch whose
+// tallest tile has `max_rows` rows.
+int decide_rows(int W, int H, int N, int ncu);
+size_t decide_lds_bytes(int max_rows);
 // Decide + claim over `n_blocks` workgroups.  `block_scene[b]` names the
 // scene of workgroup b (NULL: every workgroup belongs to views[0]);
-// `max_chunk` is the largest chunk of the launch's scenes (sizes the LDS).
+// `max_rows` is the tallest decide tile of the launch's scenes (sizes the LDS).
 hipError_t launch_decide_claim(const SceneView *views, const int32_t *block_scene, int n_blocks,
-                               int max_chunk, hipStream_t st, const LaunchEvents *ev = nullptr);
+                               int max_rows, hipStream_t st, const LaunchEvents *ev = nullptr);
 hipError_t launch_commit(const SceneView *views, const int32_t *block_scene, int n_blocks,
                          hipStream_t st, const LaunchEvents *ev = nullptr);
 // dst[ext[i]] = src[i] for i < n (internal to caller order).

@@ -57,21 +57,30 @@ __device__ __forceinline__ void block_sum_add(unsigned int v, Ctr ctr, int id)
     __syncthreads();
 }
 
-// Same for a signed delta (two's-complement add).
-template <typename Ctr>
-__device__ __forceinline__ void block_delta_add(int v, Ctr ctr, int id)
+// Several running totals at once: the block sum of v[k] is added (one thread,
+// copy block % kSlots) to total ids[k]; signed values add in two's
+// complement.  One LDS exchange for all of them.  Every thread of the block
+// must call it; it synchronises the block.
+template <int NV, typename Ctr>
+__device__ __forceinline__ void block_sums_add(const int (&v)[NV], Ctr ctr, const int (&ids)[NV])
 {
-    __shared__ int part[16];
-    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
+    __shared__ int part[NV][16];
     const int wv = threadIdx.x >> 6;
-    if (lane_id() == 0) part[wv] = v;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        int x = v[k];
+        for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d);
+        if (lane_id() == 0) part[k][wv] = x;
+    }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        long long s = 0;
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += part[w];
-        if (s)
-            __hip_atomic_fetch_add(&ctr[ctr_index(id, blockIdx.x % kSlots)], (unsigned long long)s,
-                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x < NV) {
+        const int k = threadIdx.x;
+        long long sum = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) sum += part[k][w];
+        if (sum)
+            __hip_atomic_fetch_add(&ctr[ctr_index(ids[k], blockIdx.x % kSlots)],
+                                   (unsigned long long)sum, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
     }
     __syncthreads();
 }
@@ -776,15 +785,19 @@ __global__ void k_occ_init(const int32_t *__restrict__ pos, int N, unsigned long
 
 // ---- bin + decide + claim (k-2, k-3 registration) --------------------------------------
 //
-// Binning is a counting sort whose bins are the 64-su row words of the
-// occupancy bitmap: each wave takes `chunk` consecutive words, the per-word
-// counts are popcounts, a wave prefix sum gives each word's first slot, and
-// every lane scatters its word's su indices (ascending x) into a wave-private
-// LDS list.  The wave then decides for the listed pedestrians 64 at a time,
-// so neighbouring lanes work on neighbouring su.
+// A workgroup takes a tile of 64 columns (one bitmap word per row) by `rows`
+// rows.  Binning is a counting sort whose bins are the tile's row words: one
+// wave popcounts them, prefix-sums over its lanes and scatters the su of each
+// row (ascending x) into an LDS list.  The four waves share the loads of the
+// field tile.  Tiles without pedestrians stop there.
+// Otherwise the tile's field with a one-su halo is staged in LDS (coalesced
+// row reads, +inf outside the grid, which no candidate test accepts), and
+// one thread per listed pedestrian takes the decision from LDS: the field at
+// the 9 candidates and the occupancy bits of the 8 neighbours.
 
 constexpr int kDecideThreads = 256;
 constexpr int kCommitThreads = 256;
+constexpr int kTileCols = 66;  // 64 columns and the halo column on each side
 
 // The view of this workgroup's scene: views[block_scene[block]] (MULTI) or
 // the kernel argument `one`.
@@ -800,13 +813,12 @@ __device__ __forceinline__ const SceneView &block_view(const SceneView &one,
 template <bool MULTI>
 __global__ __launch_bounds__(kDecideThreads) void k_decide_claim(
     SceneView one, const SceneView *__restrict__ views, const int32_t *__restrict__ block_scene,
-    int max_chunk)
+    int max_rows)
 {
-    extern __shared__ int32_t list_raw[];
-    const int lane = (int)lane_id();
-    const int wv = threadIdx.x >> 6;
+    extern __shared__ __align__(16) unsigned char dec_raw[];
+    __shared__ int n_listed;
     const SceneView &v = block_view<MULTI>(one, views, block_scene);
-    const int W = v.W, H = v.H, wpr = v.wpr, chunk = v.chunk;
+    const int W = v.W, H = v.H, wpr = v.wpr, rows = v.dec_rows;
     const gptr<const unsigned long long> occ = to_global((const unsigned long long *)v.occ);
     const gptr<const float> P = to_global((const float *)v.P);
     const gptr<const unsigned long long> owner = to_global((const unsigned long long *)v.owner);
@@ -814,57 +826,76 @@ __global__ __launch_bounds__(kDecideThreads) void k_decide_claim(
                                    ctr = to_global(v.ctr);
     const gptr<int32_t> target = to_global(v.target);
     const gptr<uint8_t> flags = to_global(v.flags);
-    int32_t *list = list_raw + (size_t)wv * max_chunk * 64;
-    const size_t nwords = (size_t)wpr * H;
-    const size_t w =
-        ((size_t)(blockIdx.x - v.dec_block0) * (kDecideThreads / 64) + wv) * chunk + lane;
-    unsigned long long m = 0;
-    if (lane < chunk && w < nwords) m = occ[w];
-    const int cntl = __popcll(m);
-    int total;
-    int o = wave_excl_small(cntl, total);
-    if (m) {
-        const int y = (int)(w / wpr);
-        const int xb = (int)(w % wpr) * 64;
-        while (m) {
-            const int b = __builtin_ctzll(m);
-            m &= m - 1ull;
-            list[o++] = y * W + xb + b;
-        }
+    // LDS: bitmap words (rows + 2) x 3 (left, own, right word), the field
+    // tile (rows + 2) x kTileCols, the pedestrian list (64 * rows su)
+    unsigned long long *words = reinterpret_cast<unsigned long long *>(dec_raw);
+    float *tile = reinterpret_cast<float *>(words + (max_rows + 2) * 3);
+    int32_t *list = reinterpret_cast<int32_t *>(tile + (max_rows + 2) * kTileCols);
+
+    const int tid = (int)threadIdx.x;
+    const int lb = (int)blockIdx.x - v.dec_block0;
+    const int tx = lb % wpr, ty = lb / wpr;
+    const int x0 = tx * 64, y0 = ty * rows;
+    for (int k = tid; k < (rows + 2) * 3; k += kDecideThreads) {
+        const int r = k / 3, c = k - r * 3;
+        const int y = y0 - 1 + r, w = tx - 1 + c;
+        words[k] = (y >= 0 && y < H && w >= 0 && w < wpr) ? occ[(size_t)y * wpr + w] : 0ull;
     }
-    // the list is private to the wave: its writes complete before it is read
-    __builtin_amdgcn_s_waitcnt(0xC07F);
-    asm volatile("" ::: "memory");
     const unsigned long long t = ctr[0];
+    __syncthreads();
+    if (tid < 64) {
+        // one wave bins the tile: row r's su go to list[excl(r) ...]
+        const unsigned long long m = tid < rows ? words[(tid + 1) * 3 + 1] : 0ull;
+        int total;
+        int o = wave_excl_small(__popcll(m), total);
+        unsigned long long b = m;
+        const int rowbase = (y0 + tid) * W + x0;
+        while (b) {
+            const int bit = __builtin_ctzll(b);
+            b &= b - 1ull;
+            list[o++] = rowbase + bit;
+        }
+        if (tid == 0) n_listed = total;
+    }
+    __syncthreads();
+    const int total = n_listed;
+    if (total == 0) return;  // uniform: no pedestrian in this tile
+    for (int k = tid; k < (rows + 2) * kTileCols; k += kDecideThreads) {
+        const int r = k / kTileCols, c = k - r * kTileCols;
+        const int y = y0 - 1 + r, x = x0 - 1 + c;
+        tile[k] = (y >= 0 && y < H && x >= 0 && x < W) ? P[(size_t)y * W + x] : INFINITY;
+    }
+    __syncthreads();
+
     const unsigned long long seed = v.seed;
     const float phi_axial = v.phi_axial, phi_diag = v.phi_diag;
     unsigned int movers = 0, ties = 0;
-    for (int base = 0; base < total; base += 64) {
-        const int k = base + lane;
-        if (k >= total) break;
+    for (int k = tid; k < total; k += kDecideThreads) {
         const int p = list[k];
         const unsigned long long who = owner[p];
         const int i = (int)(uint32_t)who;
         const uint32_t eid = (uint32_t)(who >> 32);
         const int y = p / W, x = p - y * W;
-        float lo = P[p], lo2 = INFINITY;
+        const int ly = y - y0 + 1, lx = x - x0 + 1;  // position in the tile
+        float lo = tile[ly * kTileCols + lx], lo2 = INFINITY;
         int best = 0;
 #pragma unroll
         for (int d = 1; d <= 8; ++d) {
-            const int nx = x + kDirX[d], ny = y + kDirY[d];
-            if (nx >= 0 && ny >= 0 && nx < W && ny < H) {
-                const unsigned long long wbits = occ[(size_t)ny * wpr + (nx >> 6)];
-                const float pc = P[(size_t)ny * W + nx];
-                // P is +inf on obstacle su
-                if (!((wbits >> (nx & 63)) & 1ull) && pc < INFINITY) {
-                    const float u = pc - ((d & 1) ? phi_axial : phi_diag);
-                    if (u < lo) {
-                        lo2 = lo;
-                        lo = u;
-                        best = d;
-                    } else if (u < lo2) {
-                        lo2 = u;
-                    }
+            const int ny = ly + kDirY[d], nx = lx + kDirX[d];
+            // bit of column x + dx in the three words of row ny (word 0 covers
+            // x0 - 64 .. x0 - 1); out-of-grid neighbours read +inf
+            const int gx = nx + 63;
+            const unsigned long long wbits = words[ny * 3 + (gx >> 6)];
+            const float pc = tile[ny * kTileCols + nx];
+            // P is +inf on obstacle su and outside the grid
+            if (!((wbits >> (gx & 63)) & 1ull) && pc < INFINITY) {
+                const float u = pc - ((d & 1) ? phi_axial : phi_diag);
+                if (u < lo) {
+                    lo2 = lo;
+                    lo = u;
+                    best = d;
+                } else if (u < lo2) {
+                    lo2 = u;
                 }
             }
         }
@@ -886,8 +917,7 @@ __global__ __launch_bounds__(kDecideThreads) void k_decide_claim(
         movers += mover;
         ties += tied;
     }
-    block_sum_add(movers, ctr, kMovers);
-    block_sum_add(ties, ctr, kTied);
+    block_sums_add<2>({(int)movers, (int)ties}, ctr, {kMovers, kTied});
 }
 
 // ---- commit (k-4 moves, exits) -------------------------------------------------------
@@ -911,16 +941,17 @@ __global__ __launch_bounds__(kCommitThreads) void k_commit(SceneView one,
                                    ctr = to_global(v.ctr);
     bool was_live = false, won = false, left = false;
     if (i < v.N) {
+        // independent loads first (one round trip), then the claim word
         const int p = pos[i];
+        const uint8_t f = flags[i];
+        const int tgt = target[i];
+        const unsigned long long kk = key[i];
         if (p < 0) {
             target[i] = -1;
             flags[i] = 0;
         } else {
             was_live = true;
-            const uint8_t f = flags[i];
             if (f & kMover) {
-                const int tgt = target[i];
-                const unsigned long long kk = key[i];
                 // the winner is the only registrant that finds its own key; it
                 // also resets the word, which losers then read as "not mine"
                 if (claim[tgt] == kk) {
@@ -947,10 +978,8 @@ __global__ __launch_bounds__(kCommitThreads) void k_commit(SceneView one,
     }
     if (lb == 0 && threadIdx.x == 0)
         __hip_atomic_fetch_add(&ctr[0], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    block_sum_add(was_live ? 1u : 0u, ctr, kPedSteps);
-    block_sum_add(won ? 1u : 0u, ctr, kMoved);
-    block_sum_add(left ? 1u : 0u, ctr, kEvacuated);
-    block_delta_add(left ? -1 : 0, ctr, kLive);
+    block_sums_add<4>({was_live ? 1 : 0, won ? 1 : 0, left ? 1 : 0, left ? -1 : 0}, ctr,
+                      {kPedSteps, kMoved, kEvacuated, kLive});
 }
 
 // ---- caller-order output ---------------------------------------------------------------
@@ -1332,39 +1361,40 @@ hipError_t launch_occ_init(const int32_t *pos, int N, unsigned long long *occ, i
     return hipGetLastError();
 }
 
-int pick_decide_chunk(int W, int H, int N)
+int decide_rows(int W, int H, int N, int ncu)
 {
-    // a wave of `chunk` words holds chunk * 64 * N / (W*H) pedestrians on
-    // average: aim at about one per lane
-    const double su_per_ped = (double)W * H / (N > 0 ? N : 1);
-    int c = 4;
-    while (c < 64 && c * 2 <= su_per_ped) c *= 2;
-    return c;
+    // taller tiles amortise the halo rows; keep at least 8 tiles (workgroups)
+    // per compute unit
+    const double tiles_per_row = (double)((W + 63) / 64);
+    int r = 4;
+    while (r < 32 && tiles_per_row * ((H + 2 * r - 1) / (2 * r)) >= 8.0 * ncu) r *= 2;
+    (void)N;
+    return r;
 }
 
-int decide_blocks(int wpr, int H, int chunk)
+size_t decide_lds_bytes(int max_rows)
 {
-    const size_t per_block = (size_t)(kDecideThreads / 64) * chunk;
-    return (int)blocks_for((size_t)wpr * H, (unsigned)per_block, 1u << 30);
+    return (size_t)(max_rows + 2) * 3 * 8 + (size_t)(max_rows + 2) * kTileCols * 4 +
+           (size_t)64 * max_rows * 4;
 }
+
+int decide_blocks(int wpr, int H, int rows) { return wpr * ((H + rows - 1) / rows); }
 
 int commit_blocks(int N) { return (int)blocks_for((size_t)N, kCommitThreads, 1u << 30); }
 
 hipError_t launch_decide_claim(const SceneView *views, const int32_t *block_scene, int n_blocks,
-                               int max_chunk, hipStream_t st, const LaunchEvents *ev)
+                               int max_rows, hipStream_t st, const LaunchEvents *ev)
 {
-    const size_t lds = (size_t)(kDecideThreads / 64) * max_chunk * 64 * sizeof(int32_t);
     const SceneView none = {};
-    return launch(k_decide_claim<true>, dim3(n_blocks), dim3(kDecideThreads), lds, st, ev, none,
-                  views, block_scene, max_chunk);
+    return launch(k_decide_claim<true>, dim3(n_blocks), dim3(kDecideThreads),
+                  decide_lds_bytes(max_rows), st, ev, none, views, block_scene, max_rows);
 }
 
 hipError_t launch_decide_one(const SceneView &view, hipStream_t st, const LaunchEvents *ev)
 {
-    const size_t lds = (size_t)(kDecideThreads / 64) * view.chunk * 64 * sizeof(int32_t);
-    return launch(k_decide_claim<false>, dim3(decide_blocks(view.wpr, view.H, view.chunk)),
-                  dim3(kDecideThreads), lds, st, ev, view, (const SceneView *)nullptr,
-                  (const int32_t *)nullptr, view.chunk);
+    return launch(k_decide_claim<false>, dim3(decide_blocks(view.wpr, view.H, view.dec_rows)),
+                  dim3(kDecideThreads), decide_lds_bytes(view.dec_rows), st, ev, view,
+                  (const SceneView *)nullptr, (const int32_t *)nullptr, view.dec_rows);
 }
 
 hipError_t launch_scatter_i32(const int32_t *src, const int32_t *ext, int32_t *dst, int n,

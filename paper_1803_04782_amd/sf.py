@@ -59,15 +59,43 @@ class Stats(ctypes.Structure):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
-class Tiling(ctypes.Structure):
-    """sf_batch_tiling: field tile shape and schedule of a batch (0 = default)."""
+class GroupTiling(ctypes.Structure):
+    """sf_group_tiling: field tile shape and schedule of one batch group."""
     _fields_ = [("tw", ctypes.c_int32), ("hl", ctypes.c_int32), ("vec", ctypes.c_int32),
                 ("nw", ctypes.c_int32), ("list_cap", ctypes.c_int32),
                 ("blocks_per_cu", ctypes.c_int32), ("items_per_block", ctypes.c_int32),
-                ("max_chunk", ctypes.c_int32)]
+                ("decide_rows", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+class Tiling(ctypes.Structure):
+    """sf_batch_tiling: split of a batch into groups and each group's tiling
+    (zero fields = library defaults)."""
+    _fields_ = [("groups", ctypes.c_int32), ("split_radius", ctypes.c_int32),
+                ("group", GroupTiling * 2)]
+
+    @classmethod
+    def from_dict(cls, d: dict) -> "Tiling":
+        """{"groups", "split_radius", "group": [dict, dict]} or a flat dict of
+        group fields applied to both groups."""
+        t = cls()
+        group_keys = {k for k, _ in GroupTiling._fields_}
+        flat = {k: v for k, v in d.items() if k in group_keys}
+        for gi in range(2):
+            g = dict(flat)
+            if "group" in d:
+                g.update(d["group"][gi])
+            for k, v in g.items():
+                setattr(t.group[gi], k, int(v))
+        t.groups = int(d.get("groups", 0))
+        t.split_radius = int(d.get("split_radius", 0))
+        return t
+
+    def as_dict(self):
+        return {"groups": int(self.groups), "split_radius": int(self.split_radius),
+                "group": [self.group[0].as_dict(), self.group[1].as_dict()]}
 
 
 class SfError(RuntimeError):
@@ -246,7 +274,7 @@ class Batch:
         lib = load()
         self.scenes = list(scenes)
         arr = (ctypes.c_void_p * len(self.scenes))(*[s.handle.value for s in self.scenes])
-        t = Tiling(**tiling) if tiling else None
+        t = Tiling.from_dict(tiling) if tiling else None
         h = ctypes.c_void_p()
         _check(lib.sf_batch_create(arr, len(self.scenes), ctypes.byref(t) if t else None,
                                    _stream_handle(stream), ctypes.byref(h)))
