@@ -526,7 +526,25 @@ __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
     FieldScene v = work.scene(it.x);
     int t = it.y;
     typedef VecOf<4>::type f4;
-    for (int i = tid; i < v.tab_elems / 4; i += NT) reinterpret_cast<f4 *>(tab)[i] = v.tab[i];
+    // stamp copies into LDS: each thread's loads are all issued before the
+    // stores, so the copy costs one memory round trip per 8 vectors
+    auto load_table = [&](const FieldScene &s) {
+        const int n4 = s.tab_elems / 4;
+        for (int i0 = 0; i0 < n4; i0 += 8 * NT) {
+            f4 r[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int i = i0 + u * NT + tid;
+                if (i < n4) r[u] = s.tab[i];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int i = i0 + u * NT + tid;
+                if (i < n4) reinterpret_cast<f4 *>(tab)[i] = r[u];
+            }
+        }
+    };
+    load_table(v);
 
     // Strip geometry: halo rows [ya, ya + nr), halo bitmap words [wa, wa + nwd).
     struct Strip {
@@ -736,8 +754,7 @@ __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
         // one after the gather, or after the scan when there is no source).
         if (nitem != item) {
             if (nv.tab != v.tab) {
-                for (int i = tid; i < nv.tab_elems / 4; i += NT)
-                    reinterpret_cast<f4 *>(tab)[i] = nv.tab[i];
+                load_table(nv);
                 __syncthreads();
             }
             item = nitem;
