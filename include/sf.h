@@ -37,6 +37,10 @@
  *     the null stream) on the device that was current at creation.
  *   - Calls on different scenes may run on different threads; calls on one
  *     scene must not overlap.
+ *   - Environment overrides read by sf_create_scene, for tuning only (results
+ *     do not depend on them bit for bit): SF_TILE="TWxHLxVECxNW[xCAP]" (field
+ *     tile shape and source-list capacity), SF_FIELD_BLOCKS_PER_CU (field
+ *     workgroups per compute unit), SF_DECIDE_ROWS (decide tile rows).
  */
 #ifndef SF_H
 #define SF_H

@@ -488,6 +488,13 @@ int create(const sf_scene_desc *d, void *hip_stream, sf_scene **out)
     {
         int per_cu = (int)std::max<size_t>(1, (size_t)(160 * 1024) / s->lc.lds_bytes);
         per_cu = std::min(per_cu, std::max(1, 32 / (s->lc.nw)));
+        if (const char *e = std::getenv("SF_FIELD_BLOCKS_PER_CU")) {
+            // override of the field kernel's persistent workgroups per CU (speed only)
+            const int b = std::atoi(e);
+            if (b < 1 || b > 64)
+                return fail(SF_EINVAL, "SF_FIELD_BLOCKS_PER_CU=%s outside 1..64", e);
+            per_cu = b;
+        }
         s->lc.grid = s->ncu * per_cu;
     }
 

@@ -105,3 +105,49 @@ def lockstep(g, st, t0: int, n_steps: int, every: int = 1) -> Report:
         t += 1
         done += 1
     return rep
+
+
+def tie_nearby(st, occ, owner, targets) -> bool:
+    """True if a registrant of one of `targets` is near-tied (cascade)."""
+    W, H = st.W, st.H
+    for q in targets:
+        qx, qy = q % W, q // W
+        for dx in (-1, 0, 1):
+            for dy in (-1, 0, 1):
+                x, y = qx + dx, qy + dy
+                if (dx or dy) and 0 <= x < W and 0 <= y < H and owner[y * W + x] >= 0:
+                    if oracle.decide_at(st, occ, y * W + x)[1]:
+                        return True
+    return False
+
+
+def sampled_field_err(st, obstacle, pos, P_gpu, cells) -> float:
+    """Max relative field error at sampled su from the oracle's point route."""
+    occ = oracle.occupancy(st.W, st.H, pos)
+    ref = oracle.field_at(st, occ, cells)
+    free = obstacle[cells] == 0
+    if not free.any():
+        return 0.0
+    return float(np.max(np.abs(P_gpu[cells][free] - ref[free]) /
+                        np.maximum(np.abs(ref[free]), 1.0)))
+
+
+def sampled_outcomes(st, exit_mask, pos, t, ids, tgt_g, flags_g, pos_g):
+    """Untied mismatches among pedestrians `ids` for the tick from positions
+    `pos` at tick t, against the oracle's point route (target, election,
+    exit).  Each entry: (id, oracle target, GPU target, oracle moved, GPU won)."""
+    from paper_1803_04782_amd.sf import SF_FLAG_WON
+
+    occ = oracle.occupancy(st.W, st.H, pos)
+    live = np.flatnonzero(pos >= 0)
+    owner = np.full(st.W * st.H, -1, np.int64)
+    owner[pos[live]] = live
+    bad = []
+    for i in ids:
+        tgt, moved, tied = oracle.outcome_at(st, occ, owner, pos, int(i), t)
+        won_g = bool(flags_g[i] & SF_FLAG_WON)
+        same = tgt == tgt_g[i] and moved == won_g and (
+            pos_g[i] == (-1 if moved and exit_mask[tgt] else (tgt if moved else pos[i])))
+        if not same and not tied and not tie_nearby(st, occ, owner, (tgt, int(tgt_g[i]))):
+            bad.append((int(i), tgt, int(tgt_g[i]), moved, won_g))
+    return bad

@@ -7,6 +7,8 @@ the launch), across graph replays with eager work between them, for every
 tiling and after the autotuner; and a batch passes the lockstep comparison
 with the FP64 oracle (field within 1e-5 relative, no untied mismatch).
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -15,7 +17,8 @@ from paper_1803_04782_amd import scenes
 
 pytestmark = pytest.mark.gpu
 
-from parity import FIELD_RTOL, Report, classify, field_rel_err  # noqa: E402
+from parity import (FIELD_RTOL, Report, classify, field_rel_err,  # noqa: E402
+                    sampled_field_err, sampled_outcomes)
 
 
 @pytest.fixture(scope="module")
@@ -201,4 +204,50 @@ def test_batch_membership_rules(sf):
     b2.close()
     gs[1].step(1)
     for g in gs:
+        g.close()
+
+
+@pytest.mark.skipif(os.environ.get("SF_SKIP_ENSEMBLE") == "1", reason="disabled by env")
+def test_ensemble256_full_size(sf):
+    """The 256-scene ensemble at full size in the benchmark's launch
+    configuration (autotuned two-group tiling, graph replays): every scene
+    matches itself stepped alone, and sampled field values and tick outcomes
+    of the three largest scenes match the oracle's point routes."""
+    scs = scenes.ensemble(n_scenes=256, seed=3)
+    _say(f"[ensemble256] {sum(s.width * s.height for s in scs):.3g} su, "
+         f"{sum(s.n_peds for s in scs)} pedestrians")
+    alone = [sf.GpuScene(s) for s in scs]
+    member = [sf.GpuScene(s) for s in scs]
+    rng = np.random.default_rng(5)
+    largest = [int(j) for j in np.argsort([s.width * s.height for s in scs])[-3:]]
+    sts = {j: oracle.statics(scs[j], with_obstacle_field=False) for j in largest}
+    with sf.Batch(member) as b:
+        _say("   tuned", b.tune(reps=1))
+        b.step(11)  # a graph of 8 ticks, then one of 3
+        for g in alone:
+            g.step(11)
+        totals = b.stats()
+        for j, (a, m) in enumerate(zip(alone, member)):
+            assert np.array_equal(a.positions(), m.positions()), j
+            assert totals[j] == a.stats(), j
+        _say("   positions and totals of all 256 scenes identical")
+        before = {}
+        for j in largest:
+            sc, g = scs[j], member[j]
+            pos, P = g.positions(), g.field()
+            cells = rng.choice(sc.width * sc.height, size=300, replace=False)
+            err = sampled_field_err(sts[j], sc.obstacle, pos, P, cells)
+            assert err <= FIELD_RTOL, (j, err)
+            live = np.flatnonzero(pos >= 0)
+            before[j] = (pos, rng.choice(live, size=min(40, live.size), replace=False),
+                         totals[j]["step"])
+        b.step(1)
+        for j in largest:
+            pos, ids, t = before[j]
+            tgt_g, flags_g = member[j].last_moves()
+            bad = sampled_outcomes(sts[j], scs[j].exit, pos, t, ids, tgt_g, flags_g,
+                                   member[j].positions())
+            assert not bad, (j, bad[:5])
+        _say("   sampled oracle checks of the 3 largest scenes passed")
+    for g in alone + member:
         g.close()
