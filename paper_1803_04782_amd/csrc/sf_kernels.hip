@@ -602,13 +602,18 @@ __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
         const int yb = ya + nr - 1;
         const unsigned long long ma = ~0ull << (xa & 63), mb = ~0ull >> (63 - (xb & 63));
 
-        // 1. this thread's halo row
+        // 1. this thread's halo row (only the first nr threads hold one; whole
+        // waves without a row skip the masking)
+        const bool wave_rows = wv * 64 < nr;
         unsigned long long m0 = n0, m1 = n1, m2 = n2;
-        m0 &= ma;
-        if (nwd == 1) m0 &= mb;
-        if (nwd == 2) m1 &= mb;
-        if (nwd == 3) m2 &= mb;
-        const int cnt = __popcll(m0) + __popcll(m1) + __popcll(m2);
+        int cnt = 0;
+        if (wave_rows) {
+            m0 &= ma;
+            if (nwd == 1) m0 &= mb;
+            if (nwd == 2) m1 &= mb;
+            if (nwd == 3) m2 &= mb;
+            cnt = __popcll(m0) + __popcll(m1) + __popcll(m2);
+        }
         // keep the loads below after the use of the prefetched words, so that
         // the wait for those does not also wait for the new requests
         asm volatile("" ::"v"(cnt) : "memory");
@@ -626,9 +631,10 @@ __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
         }
         if (more) fetch_rows(nv, nt);
 
-        // 2. block exclusive scan of the row counts (ballots within a wave)
-        int wtot;
-        const int wexcl = wave_excl_small(cnt, wtot);
+        // 2. block exclusive scan of the row counts (ballots within a wave);
+        // waves that hold no halo row skip the ballots (their counts are 0)
+        int wtot = 0, wexcl = 0;
+        if (wave_rows) wexcl = wave_excl_small(cnt, wtot);
         if (lane == 0) wave_tot[wv] = wtot;
         __syncthreads();
         int before = 0, total = 0;
