@@ -280,6 +280,9 @@ def main():
     ap.add_argument("--max-scenes", type=int, default=256, help="resident slots (serving)")
     ap.add_argument("--pool", type=int, default=64, help="request pool size (serving)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--field-update", type=int, default=0,
+                    help="K >= 2: incremental field update with a full superposition every K "
+                         "ticks (sf_set_field_update); 0 = full superposition every tick")
     ap.add_argument("--no-ensemble", action="store_true",
                     help="hall1024: skip the attached batched-vs-plain ensemble comparison")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -300,7 +303,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
-              "path is a design, not part of this build", file=sys.stderr)
+              "path is described in the design notes, not implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -323,6 +326,8 @@ def main():
           f"R={sc.radius}", file=sys.stderr, flush=True)
     free_su = int((sc.obstacle == 0).sum())
     g = sf.GpuScene(sc, stream=stream)
+    if args.field_update:
+        g.set_field_update(args.field_update)
     try:
         # warm-up ticks, then back to the initial state for the timed run
         g.step(args.warmup)
@@ -377,7 +382,10 @@ def main():
     out = {"metric": METRIC, "value": value, "unit": "pedestrian-steps/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1000.0 * dt / args.steps,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "field_us_per_tick": ktimes["superpose"]["avg_us"] * ktimes["superpose"]["launches"]
+           / max(args.steps, 1),
            "data": "synthetic", "config": {"workload": sc.name, "grid": [sc.width, sc.height],
+                                           "field_update": args.field_update,
                                            "pedestrians": sc.n_peds, "radius": sc.radius,
                                            "ticks": args.steps, "parallelism": "single-gpu"},
            "su_field_updates_per_s": su_updates, "kernels": ktimes, "roofline": roofline,

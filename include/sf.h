@@ -154,6 +154,18 @@ int sf_stats(const sf_scene *s, sf_stats_t *out);
 /* Block until all work enqueued for the scene has finished. */
 int sf_sync(const sf_scene *s);
 
+/* Field update mode.  refresh_ticks <= 1 (default 0): the field is
+ * superposed from all pedestrians every tick.  refresh_ticks = K >= 2: the
+ * incremental update of Algorithm 1 (k-4 buffers the field changes of the
+ * pedestrians that moved, k-5 writes them back): between full superpositions,
+ * a tick adds the stamps at the su its winners entered and subtracts those at
+ * the su they left, and every K-th tick the field is superposed in full again
+ * (FP32 rounding of the updates accumulates between refreshes).  The update
+ * reuses the superposition kernel with the moved pedestrians as sources, so
+ * it is deterministic and independent of the launch shape.  Blocks.
+ * SF_EINVAL for a negative value or a scene that belongs to a batch. */
+int sf_set_field_update(sf_scene *s, int32_t refresh_ticks);
+
 /* Per-kernel timing: while enabled, every launch of the kernels listed above
  * records a start/stop HIP event pair as part of its own dispatch (the
  * kernel's execution interval, no extra stream packets).  enable = 1 starts a fresh
@@ -180,7 +192,7 @@ void sf_destroy_scene(sf_scene *s);
  * sf_field, sf_positions, sf_last_moves, sf_static_field, sf_stats and sf_sync
  * on the scene are ordered after the batch's enqueued ticks, while sf_step and
  * sf_set_state on it fail with SF_EINVAL.  A scene belongs to at most one batch
- * at a time.  Destroy a batch before its scenes; if a member scene is destroyed
+ * at a time, and scenes in the incremental field update mode cannot join one.  Destroy a batch before its scenes; if a member scene is destroyed
  * first, later sf_batch_step calls on that batch fail with SF_EINVAL. */
 typedef struct sf_batch sf_batch; /* opaque, library-owned */
 

@@ -88,6 +88,13 @@ struct sf_scene {
     // the field work items and the launch sizes
     SceneView view = {};
     int strips_per_block = 1;  // field: strips per work item (items dealt round robin)
+    // incremental field update (sf_set_field_update): refresh period, ticks
+    // since the last full superposition, the moved bitmaps, the negated
+    // stamp copies and the two update views (S = P, sources = moved bitmap)
+    int refresh = 0, since_full = 0;
+    unsigned long long *moved_from = nullptr, *moved_to = nullptr;
+    float *neg_tab = nullptr;
+    SceneView view_to = {}, view_from = {};
     FieldLaunch fl;
     // batch membership: while a batch holds the scene, `stream` is the
     // batch's stream and `own_stream` the one given at create
@@ -267,6 +274,12 @@ int timing_events(sf_scene *s, int k, sf::LaunchEvents *ev)
 // field of those positions.  Other counters are left as they are.
 int rebuild_dynamic(sf_scene *s)
 {
+    s->since_full = 0;
+    if (s->moved_from) {
+        const size_t nwords = (size_t)s->wpr * s->H;
+        SF_HIP(sf::launch_fill_u64(s->moved_from, nwords, 0ull, s->stream), "clear moves");
+        SF_HIP(sf::launch_fill_u64(s->moved_to, nwords, 0ull, s->stream), "clear moves");
+    }
     const size_t nwords = (size_t)s->wpr * s->H;
     SF_HIP(sf::launch_fill_u64(s->occ, nwords, 0ull, s->stream), "clear occupancy");
     SF_HIP(sf::launch_fill_u64(s->owner, (size_t)s->W * s->H, ~0ull, s->stream), "clear owners");
@@ -585,7 +598,50 @@ int enqueue_tick(sf_scene *s)
     if ((rc = timing_events(s, SF_KERNEL_COMMIT, &ev))) return rc;
     SF_HIP(sf::launch_commit_one(s->view, st, &ev), "commit");
     if ((rc = timing_events(s, SF_KERNEL_SUPERPOSE, &ev))) return rc;
-    SF_HIP(sf::launch_field_one(s->fl, s->view, s->strips_per_block, st, &ev), "superpose");
+    if (s->refresh > 1 && s->since_full + 1 < s->refresh) {
+        // P += stamps at the su entered - stamps at the su left this tick
+        SF_HIP(sf::launch_field_one(s->fl, s->view_to, s->strips_per_block, st, &ev), "update");
+        if ((rc = timing_events(s, SF_KERNEL_SUPERPOSE, &ev))) return rc;
+        SF_HIP(sf::launch_field_one(s->fl, s->view_from, s->strips_per_block, st, &ev), "update");
+        ++s->since_full;
+    } else {
+        SF_HIP(sf::launch_field_one(s->fl, s->view, s->strips_per_block, st, &ev), "superpose");
+        s->since_full = 0;
+    }
+    return SF_OK;
+}
+
+// Switches a scene between the full superposition every tick (refresh <= 1)
+// and the incremental update with a full superposition every `refresh` ticks.
+int set_field_update(sf_scene *s, int32_t refresh)
+{
+    if (refresh > 1 && !s->moved_from) {
+        const size_t nwords = (size_t)s->wpr * s->H;
+        int rc;
+        if ((rc = dalloc(s, &s->moved_from, nwords, "moved bitmap")) ||
+            (rc = dalloc(s, &s->moved_to, nwords, "moved bitmap")) ||
+            (rc = dalloc(s, &s->neg_tab, (size_t)s->lc.vec * s->lc.copy_elems, "phi table")))
+            return rc;
+        SF_HIP(sf::launch_phi_copies(s->neg_tab, s->lc, -s->k, s->alpha, s->stream), "phi table");
+        SF_HIP(sf::launch_fill_u64(s->moved_from, nwords, 0ull, s->stream), "clear moves");
+        SF_HIP(sf::launch_fill_u64(s->moved_to, nwords, 0ull, s->stream), "clear moves");
+    }
+    s->refresh = refresh > 1 ? refresh : 0;
+    SceneView &v = s->view;
+    v.moved_from = s->refresh ? s->moved_from : nullptr;
+    v.moved_to = s->refresh ? s->moved_to : nullptr;
+    if (s->refresh) {
+        // the field kernel with S := P (in place) and the moved bitmaps as sources
+        s->view_to = v;
+        s->view_to.S = s->P;
+        s->view_to.occ = s->moved_to;
+        s->view_from = s->view_to;
+        s->view_from.occ = s->moved_from;
+        s->view_from.tab = s->neg_tab;
+    }
+    // the next tick starts a new refresh period from a full field
+    s->since_full = s->refresh;
+    SF_HIP(hipStreamSynchronize(s->stream), "field update sync");
     return SF_OK;
 }
 
@@ -941,6 +997,8 @@ int batch_create(sf_scene *const *scenes, int32_t n, const sf_batch_tiling *tili
         const sf_scene *s = scenes[i];
         if (!s) return fail(SF_EINVAL, "scene %d is NULL", i);
         if (s->batch) return fail(SF_EINVAL, "scene %d already belongs to a batch", i);
+        if (s->refresh)
+            return fail(SF_EINVAL, "scene %d uses the incremental field update", i);
         if (s->device != dev) return fail(SF_EINVAL, "scene %d is on device %d, not %d", i, s->device, dev);
         for (int32_t j = 0; j < i; ++j)
             if (scenes[j] == s) return fail(SF_EINVAL, "scene %d is listed twice", i);
@@ -1209,6 +1267,20 @@ int sf_sync(const sf_scene *s)
     DeviceGuard g(s->device);
     SF_HIP(hipStreamSynchronize(s->stream), "sync");
     return SF_OK;
+}
+
+int sf_set_field_update(sf_scene *s, int32_t refresh_ticks)
+{
+    if (!s) return fail(SF_EINVAL, "scene is NULL");
+    if (refresh_ticks < 0 || refresh_ticks > (1 << 20))
+        return fail(SF_EINVAL, "refresh_ticks %d outside 0..2^20", refresh_ticks);
+    if (s->batch) return fail(SF_EINVAL, "the scene belongs to a batch");
+    DeviceGuard g(s->device);
+    try {
+        return set_field_update(s, refresh_ticks);
+    } catch (const std::bad_alloc &) {
+        return fail(SF_ENOMEM, "host allocation failed");
+    }
 }
 
 int sf_set_timing(sf_scene *s, int enable)

@@ -117,6 +117,10 @@ struct SceneView {
     uint8_t *flags;
     const uint8_t *exitm;
     const int32_t *ext;
+    // incremental field update (NULL: the field is recomputed every tick):
+    // bitmaps of the su the tick's winners left and entered, set by commit,
+    // read by the field update, cleared by the next tick's decide
+    unsigned long long *moved_from, *moved_to;
 };
 
 // Field layout fields of `v` for shape `c` (built for the scene's radius).

@@ -865,6 +865,12 @@ __global__ __launch_bounds__(kDecideThreads) void k_decide_claim(
         words[k] = (y >= 0 && y < H && w >= 0 && w < wpr) ? occ[(size_t)y * wpr + w] : 0ull;
     }
     const unsigned long long t = ctr[0];
+    if (v.moved_from && tid < rows && y0 + tid < H) {
+        // the previous tick's moves have been applied to the field
+        const size_t wi = (size_t)(y0 + tid) * wpr + tx;
+        to_global(v.moved_from)[wi] = 0ull;
+        to_global(v.moved_to)[wi] = 0ull;
+    }
     __syncthreads();
     if (tid < 64) {
         // one wave bins the tile: row r's su go to list[excl(r) ...]
@@ -981,16 +987,24 @@ __global__ __launch_bounds__(kCommitThreads) void k_commit(SceneView one,
                     won = true;
                     claim[tgt] = ~0ull;
                     const int y = p / W, x = p - y * W;
-                    __hip_atomic_fetch_and(&occ[(size_t)y * wpr + (x >> 6)], ~(1ull << (x & 63)),
-                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    const size_t wp = (size_t)y * wpr + (x >> 6);
+                    __hip_atomic_fetch_and(&occ[wp], ~(1ull << (x & 63)), __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                    if (v.moved_from)
+                        __hip_atomic_fetch_or(&to_global(v.moved_from)[wp], 1ull << (x & 63),
+                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     owner[p] = ~0ull;
                     if (exitm[tgt]) {
                         left = true;
                         pos[i] = -1;
                     } else {
                         const int ty = tgt / W, tx = tgt - ty * W;
-                        __hip_atomic_fetch_or(&occ[(size_t)ty * wpr + (tx >> 6)], 1ull << (tx & 63),
-                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        const size_t wt = (size_t)ty * wpr + (tx >> 6);
+                        __hip_atomic_fetch_or(&occ[wt], 1ull << (tx & 63), __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+                        if (v.moved_to)
+                            __hip_atomic_fetch_or(&to_global(v.moved_to)[wt], 1ull << (tx & 63),
+                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                         owner[tgt] = ((unsigned long long)(uint32_t)ext[i] << 32) | (uint32_t)i;
                         pos[i] = tgt;
                     }
