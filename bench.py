@@ -241,7 +241,7 @@ def bench_serving(args, stream):
         reqs = [serve.Request(i, float(a), (lambda s=pool[i % len(pool)]: s), max_steps=2000)
                 for i, a in enumerate(arrivals)]
         srv = serve.Server(int(args.budget_gib * (1 << 30)), max_scenes=args.max_scenes,
-                           stream=stream)
+                           stream=stream, create_stream=torch.cuda.Stream())
         say(f"rate {lam:g}/s: {len(reqs)} requests over {args.serve_seconds:g} s")
         out = srv.run(reqs, stop_admitting_at=args.serve_seconds, drain=False,
                       deadline=args.serve_seconds)

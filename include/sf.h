@@ -256,6 +256,12 @@ int sf_batch_sync(const sf_batch *b);
  * back to their own streams. */
 void sf_batch_destroy(sf_batch *b);
 
+/* Number of HIP devices visible to the library's HIP runtime (0 without one
+ * or when the runtime cannot start; never fails).  A process must hold one
+ * HIP runtime: a host program that carries its own (a framework's) loads it
+ * before this library, so that the library binds to it. */
+int sf_device_count(void);
+
 /* Message of the last failure on the calling thread ("" if none). */
 const char *sf_last_error(void);
 

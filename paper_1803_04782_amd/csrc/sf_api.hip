@@ -390,11 +390,16 @@ int upload_positions(sf_scene *s, const int32_t *pos)
 {
     const int N = s->N;
     std::vector<int32_t> order((size_t)N), pint((size_t)N);
-    for (int i = 0; i < N; ++i) order[(size_t)i] = i;
-    // evacuated (-1) compare as the largest unsigned value: they go last
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int a, int b) { return (uint32_t)pos[a] < (uint32_t)pos[b]; });
-    for (int i = 0; i < N; ++i) pint[(size_t)i] = pos[order[(size_t)i]];
+    // sort (position, id) pairs packed in 64-bit keys; evacuated (-1) read as
+    // the largest unsigned position and go last, in id order
+    std::vector<uint64_t> keyed((size_t)N);
+    for (int i = 0; i < N; ++i)
+        keyed[(size_t)i] = ((uint64_t)(uint32_t)pos[i] << 32) | (uint32_t)i;
+    std::sort(keyed.begin(), keyed.end());
+    for (int i = 0; i < N; ++i) {
+        order[(size_t)i] = (int32_t)(uint32_t)keyed[(size_t)i];
+        pint[(size_t)i] = (int32_t)(keyed[(size_t)i] >> 32);
+    }
     s->h_ext = order;
     if (N) {
         SF_HIP(hipMemcpyAsync(s->pos, pint.data(), (size_t)N * sizeof(int32_t),
@@ -1423,6 +1428,16 @@ void sf_batch_destroy(sf_batch *b)
     free_layout(b->cur);
     destroy_batch_streams(b);
     delete b;
+}
+
+int sf_device_count(void)
+{
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess) {
+        (void)hipGetLastError();
+        n = 0;
+    }
+    return n;
 }
 
 const char *sf_last_error(void) { return g_last_error.c_str(); }

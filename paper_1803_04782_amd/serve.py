@@ -9,8 +9,12 @@ builds a new batch (the scenes' device state stays where it is).  Scene
 state never leaves the device between ticks.  All arithmetic runs in the HIP
 library; this module only schedules.
 
-The per-tick latency a resident scene sees is the wall time of one iteration
-(admissions and retirements included).
+Building a scene (validation, static fields) takes milliseconds, during which
+resident scenes do not tick; at most `max_admit_per_tick` scenes are admitted
+between two ticks, which bounds that pause.
+
+The per-tick latency a resident scene sees is the wall time between two of
+its ticks (admissions and retirements included).
 """
 from __future__ import annotations
 
@@ -89,13 +93,17 @@ class Server:
 
     def __init__(self, budget_bytes: int, max_scenes: int = 512, stream=None,
                  tiling: Optional[dict] = None, keep_positions: bool = False,
-                 clock=time.perf_counter):
+                 clock=time.perf_counter, max_admit_per_tick: int = 1,
+                 create_stream=None):
         self.budget = int(budget_bytes)
         self.max_scenes = int(max_scenes)
         self.stream = stream
         self.tiling = tiling
         self.keep_positions = keep_positions
         self.clock = clock
+        self.max_admit_per_tick = int(max_admit_per_tick)
+        # stream on which admitted scenes are built (default: the tick stream)
+        self.create_stream = create_stream if create_stream is not None else stream
 
     def run(self, requests: List[Request], stop_admitting_at: Optional[float] = None,
             drain: bool = True, deadline: Optional[float] = None) -> dict:
@@ -130,7 +138,10 @@ class Server:
                     queue.append(pending.popleft())
                 changed = False
                 # admission in arrival order while the head of the queue fits
-                while admitting and queue and len(resident) < self.max_scenes:
+                # (all at once while nothing is resident)
+                admitted_now = 0
+                while (admitting and queue and len(resident) < self.max_scenes
+                       and (admitted_now < self.max_admit_per_tick or not resident)):
                     req = queue[0]
                     scene = req.scene()
                     need = footprint_bytes(scene)
@@ -144,13 +155,14 @@ class Server:
                     if batch is not None:
                         batch.close()
                         batch = None
-                    g = sf.GpuScene(scene, stream=self.stream)
-                    resident.append(_Resident(req, scene, g, now(), need))
+                    g = sf.GpuScene(scene, stream=self.create_stream)
+                    resident.append(_Resident(req, None, g, now(), need))
                     used += need
                     admitted_n += 1
+                    admitted_now += 1
                     max_used = max(max_used, used)
-                    max_resident = max(max_resident, len(resident))
                     changed = True
+                max_resident = max(max_resident, len(resident))
                 if not resident:
                     last_end = None
                     if not admitting or (not pending and not queue):

@@ -35,7 +35,7 @@ EXPORTS = ("sf_create_scene", "sf_step", "sf_field", "sf_positions", "sf_last_mo
            "sf_static_field", "sf_set_state", "sf_stats", "sf_sync", "sf_set_timing",
            "sf_kernel_time", "sf_set_field_update", "sf_destroy_scene", "sf_batch_create", "sf_batch_tune",
            "sf_batch_get_tiling", "sf_batch_step", "sf_batch_stats", "sf_batch_sync",
-           "sf_batch_destroy",
+           "sf_batch_destroy", "sf_device_count",
            "sf_last_error")
 _VOID = ("sf_destroy_scene", "sf_batch_destroy", "sf_last_error")
 
@@ -107,6 +107,15 @@ class SfError(RuntimeError):
 _lib = None
 
 
+def _hip_runtimes():
+    """Distinct HIP runtime files mapped into this process (Linux)."""
+    try:
+        with open("/proc/self/maps") as f:
+            return sorted({line.split()[-1] for line in f if "libamdhip64" in line})
+    except OSError:
+        return []
+
+
 def load():
     """Load libsf.so (raises if it is missing: there is no fallback path)."""
     global _lib
@@ -114,7 +123,17 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    # torch ships its own HIP runtime.  Imported first, it is the one the
+    # library binds to; loaded the other way round, the process maps two HIP
+    # (and HSA) runtimes and whichever starts second finds no device.
+    import torch  # noqa: F401
+
     lib = ctypes.CDLL(LIB_PATH)
+    runtimes = _hip_runtimes()
+    if len(runtimes) > 1:
+        raise RuntimeError("two HIP runtimes are loaded in this process "
+                           f"({', '.join(runtimes)}): import torch before anything "
+                           "that links the system HIP runtime")
     P, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
     lib.sf_create_scene.argtypes = [ctypes.POINTER(SceneDesc), P, ctypes.POINTER(P)]
     lib.sf_step.argtypes = [P, i32]
@@ -142,11 +161,17 @@ def load():
     lib.sf_batch_destroy.restype = None
     lib.sf_last_error.restype = ctypes.c_char_p
     lib.sf_last_error.argtypes = []
+    lib.sf_device_count.argtypes = []
     for name in EXPORTS:
         if name not in _VOID:
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
+
+
+def device_count() -> int:
+    """HIP devices the library sees (0 without one)."""
+    return int(load().sf_device_count())
 
 
 def _check(rc: int):

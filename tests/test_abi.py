@@ -37,6 +37,17 @@ def test_exports_every_declared_symbol(sf):
         assert hasattr(lib, n), n
 
 
+def test_binds_to_the_one_hip_runtime_of_the_process(sf):
+    # the library must share torch's HIP runtime: a second copy in the
+    # process leaves whichever starts second without a device
+    runtimes = sf._hip_runtimes()
+    assert len(runtimes) == 1, runtimes
+    import torch
+
+    assert os.path.dirname(runtimes[0]) == os.path.join(os.path.dirname(torch.__file__), "lib")
+    assert sf.device_count() >= 0
+
+
 def _base():
     return scenes.random_scene(16, 12, n_peds=10, radius=2, seed=1, bernoulli=0.0)
 

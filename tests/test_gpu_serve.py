@@ -36,7 +36,11 @@ def test_serving_results_match_scenes_alone(sf):
             for i, a in enumerate(arrivals)]
     # a budget of about five mid-sized scenes forces queueing and turnover
     budget = 5 * serve.footprint_bytes(_request_scene(0))
-    srv = serve.Server(budget, max_scenes=6, keep_positions=True)
+    import torch
+
+    # admitted scenes are built on their own stream while the others tick
+    srv = serve.Server(budget, max_scenes=6, keep_positions=True,
+                       create_stream=torch.cuda.Stream())
     out = srv.run(reqs)
     print({k: v for k, v in out.items() if k != "results"}, flush=True)
     assert out["finished"] == len(reqs)

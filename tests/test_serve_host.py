@@ -99,3 +99,25 @@ def test_poisson_arrivals_rate():
     t = serve.poisson_arrivals(200.0, 50.0, seed=4)
     assert np.all(np.diff(t) > 0) and t[-1] < 50.0
     assert abs(len(t) / 50.0 - 200.0) < 200.0 * 0.05
+
+
+def test_admissions_per_tick_are_bounded(monkeypatch):
+    clock = _Clock()
+    log = []
+    fake = _fake_sf(clock, log)
+    monkeypatch.setattr(serve, "sf", fake)
+    reqs = [serve.Request(i, arrival=0.0, make_scene=(lambda: _FakeScene(60, 60, 10, 50)),
+                          max_steps=5) for i in range(12)]
+    created_per_tick = []
+
+    class Counting(fake.Batch):
+        def __init__(self, members, tiling=None, stream=None):
+            super().__init__(members, tiling, stream)
+            created_per_tick.append(sum(1 for e in log if e[0] == "create"))
+
+    monkeypatch.setattr(fake, "Batch", Counting)
+    out = serve.Server(1 << 40, max_scenes=8, clock=clock, max_admit_per_tick=2).run(reqs)
+    assert out["finished"] == 12
+    # the first batch takes every scene it can; later ones at most 2 newcomers
+    steps = [b - a for a, b in zip(created_per_tick, created_per_tick[1:])]
+    assert max(steps) <= 2
