@@ -313,37 +313,47 @@ int build_statics(sf_scene *s, const uint8_t *h_obst, const uint8_t *h_exit)
     const int W = s->W, H = s->H, n = W * H;
     hipStream_t st = s->stream;
     uint8_t *obst = nullptr;
-    int32_t *fa = nullptr, *fb = nullptr;
-    unsigned int *cnt = nullptr;
-    unsigned long long *obits = nullptr;
+    unsigned int *active = nullptr;
+    unsigned long long *obits = nullptr, *vis[2] = {nullptr, nullptr},
+                       *front[2] = {nullptr, nullptr};
     double *tab64 = nullptr, *O = nullptr;
     int rc;
     // temporaries are released right after the statics are built
     const size_t first_tmp = s->owned.size();
+    const size_t nbw = (size_t)s->wpr * H;
     if ((rc = dalloc(s, &obst, (size_t)n, "obstacle mask")) ||
-        (rc = dalloc(s, &fa, (size_t)n, "BFS frontier")) ||
-        (rc = dalloc(s, &fb, (size_t)n, "BFS frontier")) ||
-        (rc = dalloc(s, &cnt, 4, "BFS counters")) ||
-        (rc = dalloc(s, &obits, (size_t)s->wpr * H, "obstacle bitmap")))
+        (rc = dalloc(s, &obits, nbw, "obstacle bitmap")) ||
+        (rc = dalloc(s, &vis[0], nbw, "BFS visited set")) ||
+        (rc = dalloc(s, &vis[1], nbw, "BFS visited set")) ||
+        (rc = dalloc(s, &front[0], nbw, "BFS frontier")) ||
+        (rc = dalloc(s, &front[1], nbw, "BFS frontier")) ||
+        (rc = dalloc(s, &active, (size_t)sf::bfs_ring(), "BFS counters")))
         return rc;
     SF_HIP(hipMemcpyAsync(obst, h_obst, (size_t)n, hipMemcpyHostToDevice, st), "copy obstacles");
     SF_HIP(hipMemcpyAsync(s->exitm, h_exit, (size_t)n, hipMemcpyHostToDevice, st), "copy exits");
+    SF_HIP(sf::launch_mask_to_bits(obst, obits, W, H, s->wpr, st), "obstacle bitmap");
 
-    // destination field: BFS over free su from the exit set
-    SF_HIP(sf::launch_fill_i32(reinterpret_cast<int32_t *>(cnt), 4, 0, st), "clear BFS counters");
-    SF_HIP(sf::launch_bfs_init(obst, s->exitm, s->D, fa, cnt, n, st), "BFS init");
-    const int bfs_grid = std::min(1024, std::max(1, s->ncu * 4));
-    const int chunk = 64;
-    for (int level = 0;; level += chunk) {
-        SF_HIP(sf::launch_bfs_levels(obst, s->D, fa, fb, cnt, W, H, level, chunk, bfs_grid, st),
-               "BFS expand");
+    // destination field: BFS over free su from the exit set, a batch of
+    // launches between looks at whether a frontier is left
+    SF_HIP(sf::launch_bfs_seed(s->exitm, s->D, n, st), "BFS seed");
+    SF_HIP(sf::launch_mask_to_bits(s->exitm, vis[0], W, H, s->wpr, st), "BFS seed");
+    SF_HIP(sf::launch_mask_to_bits(s->exitm, front[0], W, H, s->wpr, st), "BFS seed");
+    SF_HIP(sf::launch_fill_i32(reinterpret_cast<int32_t *>(active), sf::bfs_ring(), 0, st),
+           "clear BFS counters");
+    // no distance exceeds the number of su
+    const long long max_launches = (long long)n / sf::bfs_levels_per_launch() + 2;
+    const int per_look = 8;
+    for (int j = 0;; ++j) {
+        SF_HIP(sf::launch_bfs_block(obits, vis, front, s->D, W, H, s->wpr, j, active, st),
+               "BFS levels");
+        if ((j + 1) % per_look) continue;
         unsigned int left = 0;
-        SF_HIP(hipMemcpyAsync(&left, &cnt[(level + chunk) % 3], sizeof left,
+        SF_HIP(hipMemcpyAsync(&left, &active[j % sf::bfs_ring()], sizeof left,
                               hipMemcpyDeviceToHost, st),
-               "BFS frontier size");
+               "BFS frontier flag");
         SF_HIP(hipStreamSynchronize(st), "BFS sync");
         if (left == 0) break;
-        if (level > n) return fail(SF_EDEVICE, "BFS did not terminate");
+        if (j > max_launches) return fail(SF_EDEVICE, "BFS did not terminate");
     }
     SF_HIP(sf::launch_fill_u64(s->ctr, sf::kCtrWords, 0ull, st), "clear counters");
     SF_HIP(sf::launch_count_unreachable(obst, s->D, n, s->ctr, st), "reachability");
@@ -373,7 +383,6 @@ int build_statics(sf_scene *s, const uint8_t *h_obst, const uint8_t *h_exit)
         ocg.grid = std::max(1, s->ncu * (int)std::max<size_t>(1, (size_t)max_lds / oc.lds_bytes));
     }
     SF_HIP(sf::launch_phi_table_f64(tab64, oc, s->k_obs, s->alpha_obs, st), "obstacle table");
-    SF_HIP(sf::launch_mask_to_bits(obst, obits, W, H, s->wpr, st), "obstacle bitmap");
     SF_HIP(sf::launch_superpose_f64(ocg, obits, s->wpr, tab64, O, W, H, st), "obstacle field");
     SF_HIP(sf::launch_static_S(s->D, O, obst, s->w_dest, s->S, n, st), "static field");
     SF_HIP(hipStreamSynchronize(st), "statics sync");

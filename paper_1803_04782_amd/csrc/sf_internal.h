@@ -165,11 +165,18 @@ hipError_t launch_phi_table_f64(double *tab, const SupCfg &c, double k, double a
                                 hipStream_t st);
 // Multi-source BFS of the destination field.  `levels` expansions are
 // enqueued starting at `level0`; frontier sizes live in cnt[3] on the device.
-hipError_t launch_bfs_init(const uint8_t *obst, const uint8_t *exitm, int32_t *D,
-                           int32_t *frontier, unsigned int *cnt, int n, hipStream_t st);
-hipError_t launch_bfs_levels(const uint8_t *obst, int32_t *D, int32_t *fa, int32_t *fb,
-                             unsigned int *cnt, int W, int H, int level0, int levels,
-                             int grid, hipStream_t st);
+// Destination-field BFS: D = 0 on exit su, -1 elsewhere; then launch j =
+// 0, 1, ... advances bfs_levels_per_launch() levels over the free-su bitmap
+// (obstacle bits obits), reading the visited set and frontier from vis[j & 1]
+// and fr[j & 1] (both seeded with the exit bits for j = 0) and writing them
+// to the other buffers; active[j % bfs_ring()] > 0 iff a frontier remains
+// after launch j (active[0] is cleared before launch 0).
+hipError_t launch_bfs_seed(const uint8_t *exitm, int32_t *D, int n, hipStream_t st);
+int bfs_levels_per_launch();
+int bfs_ring();
+hipError_t launch_bfs_block(const unsigned long long *obits, unsigned long long *const vis[2],
+                            unsigned long long *const fr[2], int32_t *D, int W, int H, int wpr,
+                            int j, unsigned int *active, hipStream_t st);
 hipError_t launch_count_unreachable(const uint8_t *obst, const int32_t *D, int n,
                                     unsigned long long *ctr, hipStream_t st);
 hipError_t launch_superpose_f64(const SupCfg &c, const unsigned long long *bits, int wpr,

@@ -85,20 +85,6 @@ __device__ __forceinline__ void block_sums_add(const int (&v)[NV], Ctr ctr, cons
     __syncthreads();
 }
 
-// Wave-aggregated append: lanes with `pred` get consecutive slots of a list
-// whose length is *cnt; one atomic per wave.
-__device__ __forceinline__ unsigned int wave_append(bool pred, unsigned int *cnt)
-{
-    const unsigned long long b = __ballot(pred);
-    if (b == 0) return 0;
-    unsigned int base = 0;
-    const int leader = __ffsll((long long)b) - 1;
-    if ((int)lane_id() == leader) base = atomicAdd(cnt, (unsigned int)__popcll(b));
-    base = __shfl(base, leader);
-    const unsigned long long below = b & ((1ull << lane_id()) - 1ull);
-    return base + (unsigned int)__popcll(below);
-}
-
 // Pointer into LDS (address space 3): 32-bit byte addresses, ds_* instructions.
 template <typename T>
 using lds_ptr = const __attribute__((address_space(3))) T *;
@@ -203,55 +189,127 @@ __global__ void k_phi_table(T *tab, int ncols, int nrows, int stride, int padx, 
 
 // ---- destination field: multi-source BFS --------------------------------------
 
-__global__ void k_bfs_init(const uint8_t *__restrict__ obst, const uint8_t *__restrict__ exitm,
-                           int32_t *__restrict__ D, int32_t *__restrict__ frontier,
-                           unsigned int *cnt, int n)
+__global__ void k_bfs_seed(const uint8_t *__restrict__ exitm, int32_t *__restrict__ D, int n)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    bool src = false;
-    if (c < n) {
-        src = exitm[c] && !obst[c];
-        D[c] = src ? 0 : -1;
-    }
-    const unsigned int slot = wave_append(src, &cnt[0]);
-    if (src) frontier[slot] = c;
+    if (c < n) D[c] = exitm[c] ? 0 : -1;  // exit su are never obstacles
 }
 
-// Expansion of BFS level L: frontier of level L (count cnt[L%3]) -> level L+1
-// (count cnt[(L+1)%3]); cnt[(L+2)%3] is cleared for the next launch.
-__global__ void k_bfs_expand(const uint8_t *__restrict__ obst, int32_t *D,
-                             const int32_t *__restrict__ fin, int32_t *__restrict__ fout,
-                             unsigned int *cnt, int W, int H, int L)
+// Level-synchronous BFS on bitmaps (bit x & 63 of word x >> 6 of a row), one
+// launch per kBfsLevels levels.  A workgroup owns a tile of kBfsTileWords
+// words by kBfsTileRows rows and advances the tile plus a ring one word
+// (64 su) wide and kBfsGhost rows high: a level moves every su's error at
+// most one su, so after kBfsLevels <= 64 levels the ring absorbed all of it
+// and the tile's frontier and visited set are exact.  Per level
+//   new = dilate8(frontier) & free & ~visited
+// where dilate8 ORs the word with its one-bit shifts (carries from the
+// neighbouring words) and then with the rows above and below.  Only the
+// frontier is shared (LDS, double-buffered); each thread keeps its three
+// words' free and visited bits and the level at which each tile su was
+// reached (six bit planes) in registers, and writes D once, after the last
+// level.  The visited set and frontier are read from one buffer and the tile's
+// words written to the other (workgroups of a launch that run later still
+// read the launch's starting state in their ring).  active[j % kBfsRing]
+// counts the workgroups whose tile still has a
+// frontier after launch j; a launch that finds that count zero for launch
+// j - 1 returns at once (the search is over).
+constexpr int kBfsTileWords = 4, kBfsTileRows = 256, kBfsGhost = 64, kBfsLevels = 64;
+constexpr int kBfsRegW = kBfsTileWords + 2, kBfsRegH = kBfsTileRows + 2 * kBfsGhost;
+constexpr int kBfsRowsPer = 3, kBfsThreads = kBfsRegW * kBfsRegH / kBfsRowsPer;  // 768
+constexpr int kBfsRing = 4;
+static_assert(kBfsGhost >= kBfsLevels && 64 >= kBfsLevels, "ghost ring narrower than a launch");
+static_assert(kBfsRegH % kBfsRowsPer == 0, "rows per thread");
+
+__global__ __launch_bounds__(kBfsThreads) void k_bfs_block(
+    const unsigned long long *__restrict__ obits, const unsigned long long *__restrict__ vis_in,
+    const unsigned long long *__restrict__ fr_in, unsigned long long *__restrict__ vis_out,
+    unsigned long long *__restrict__ fr_out, int32_t *__restrict__ D, int W, int H, int wpr, int j,
+    unsigned int *active)
 {
-    const unsigned int n_in = cnt[L % 3];
-    const unsigned int nthreads = gridDim.x * blockDim.x;
-    const unsigned int tid = blockIdx.x * blockDim.x + threadIdx.x;
-    if (tid == 0) cnt[(L + 2) % 3] = 0u;
-    // every lane of a wave runs the same number of iterations (wave_append
-    // needs the whole wave)
-    const unsigned int rounds = (n_in + nthreads - 1) / nthreads;
-    for (unsigned int r = 0; r < rounds; ++r) {
-        const unsigned int i = r * nthreads + tid;
-        const bool act = i < n_in;
-        int x = 0, y = 0;
-        if (act) {
-            const int c = fin[i];
-            x = c % W;
-            y = c / W;
-        }
+    __shared__ unsigned long long front[2][kBfsRegH][kBfsRegW];
+    const int tid = (int)threadIdx.x;
+    if (blockIdx.x == 0 && blockIdx.y == 0 && tid == 0) active[(j + 1) % kBfsRing] = 0u;
+    if (j > 0 && active[(j + kBfsRing - 1) % kBfsRing] == 0u) return;
+
+    const int c = tid % kBfsRegW, g = tid / kBfsRegW;
+    const int wcol = (int)blockIdx.x * kBfsTileWords - 1 + c;
+    const int ry0 = (int)blockIdx.y * kBfsTileRows - kBfsGhost;  // region row 0
+    const bool col_in = wcol >= 0 && wcol < wpr;
+    const bool col_tile = c >= 1 && c <= kBfsTileWords;
+    const unsigned long long in_grid =
+        (wcol == wpr - 1 && (W & 63)) ? (1ull << (W & 63)) - 1ull : ~0ull;
+
+    unsigned long long fre[kBfsRowsPer], vs[kBfsRowsPer], last[kBfsRowsPer];
+    unsigned long long reached[kBfsRowsPer], plane[kBfsRowsPer][6];
 #pragma unroll
-        for (int d = 1; d <= 8; ++d) {
-            const int nx = x + kDirX[d], ny = y + kDirY[d];
-            bool found = false;
-            int nc = 0;
-            if (act && nx >= 0 && ny >= 0 && nx < W && ny < H) {
-                nc = ny * W + nx;
-                if (!obst[nc] && D[nc] < 0) found = atomicCAS(&D[nc], -1, L + 1) == -1;
+    for (int i = 0; i < kBfsRowsPer; ++i) {
+        const int r = g * kBfsRowsPer + i, y = ry0 + r;
+        const bool ok = col_in && y >= 0 && y < H;
+        const size_t idx = (size_t)y * wpr + wcol;
+        fre[i] = ok ? ~obits[idx] & in_grid : 0ull;
+        vs[i] = ok ? vis_in[idx] : 0ull;
+        last[i] = ok ? fr_in[idx] : 0ull;
+        front[0][r][c] = last[i];
+        reached[i] = 0ull;
+#pragma unroll
+        for (int b = 0; b < 6; ++b) plane[i][b] = 0ull;
+    }
+    __syncthreads();
+
+    int cur = 0;
+    for (int l = 0; l < kBfsLevels; ++l) {
+        unsigned long long h[kBfsRowsPer + 2];
+#pragma unroll
+        for (int k = 0; k < kBfsRowsPer + 2; ++k) {
+            const int r = g * kBfsRowsPer - 1 + k;
+            unsigned long long v = 0ull;
+            if (r >= 0 && r < kBfsRegH) {
+                const unsigned long long m = front[cur][r][c];
+                const unsigned long long lf = c > 0 ? front[cur][r][c - 1] : 0ull;
+                const unsigned long long rt = c < kBfsRegW - 1 ? front[cur][r][c + 1] : 0ull;
+                v = m | (m << 1) | (lf >> 63) | (m >> 1) | (rt << 63);
             }
-            const unsigned int slot = wave_append(found, &cnt[(L + 1) % 3]);
-            if (found) fout[slot] = nc;
+            h[k] = v;
+        }
+        int any = 0;
+#pragma unroll
+        for (int i = 0; i < kBfsRowsPer; ++i) {
+            const int r = g * kBfsRowsPer + i;
+            const unsigned long long nw = (h[i] | h[i + 1] | h[i + 2]) & fre[i] & ~vs[i];
+            vs[i] |= nw;
+            last[i] = nw;
+            front[cur ^ 1][r][c] = nw;
+            any |= nw != 0ull;
+            reached[i] |= nw;
+#pragma unroll
+            for (int b = 0; b < 6; ++b) plane[i][b] |= nw & (0ull - (unsigned long long)((l >> b) & 1));
+        }
+        cur ^= 1;
+        if (!__syncthreads_or(any)) break;  // the region's frontier is empty
+    }
+
+    // the tile's words: visited set, frontier and D of the su reached here
+    int live = 0;
+#pragma unroll
+    for (int i = 0; i < kBfsRowsPer; ++i) {
+        const int r = g * kBfsRowsPer + i, y = ry0 + r;
+        if (!col_tile || !col_in || r < kBfsGhost || r >= kBfsGhost + kBfsTileRows || y >= H)
+            continue;
+        const size_t idx = (size_t)y * wpr + wcol;
+        vis_out[idx] = vs[i];
+        fr_out[idx] = last[i];
+        live |= last[i] != 0ull;
+        unsigned long long m = reached[i];
+        while (m) {
+            const int b = __builtin_ctzll(m);
+            m &= m - 1ull;
+            int lv = 0;
+#pragma unroll
+            for (int q = 0; q < 6; ++q) lv |= (int)((plane[i][q] >> b) & 1ull) << q;
+            D[(size_t)y * W + wcol * 64 + b] = j * kBfsLevels + lv + 1;
         }
     }
+    if (__syncthreads_or(live) && tid == 0) atomicAdd(&active[j % kBfsRing], 1u);
 }
 
 __global__ void k_count_unreachable(const uint8_t *__restrict__ obst, const int32_t *__restrict__ D,
@@ -1152,27 +1210,24 @@ hipError_t launch_phi_table_f64(double *tab, const SupCfg &c, double k, double a
     return hipGetLastError();
 }
 
-hipError_t launch_bfs_init(const uint8_t *obst, const uint8_t *exitm, int32_t *D, int32_t *frontier,
-                           unsigned int *cnt, int n, hipStream_t st)
+hipError_t launch_bfs_seed(const uint8_t *exitm, int32_t *D, int n, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_bfs_init, dim3(blocks_for(n, 256)), dim3(256), 0, st, obst, exitm, D,
-                       frontier, cnt, n);
+    hipLaunchKernelGGL(k_bfs_seed, dim3(blocks_for(n, 256)), dim3(256), 0, st, exitm, D, n);
     return hipGetLastError();
 }
 
-hipError_t launch_bfs_levels(const uint8_t *obst, int32_t *D, int32_t *fa, int32_t *fb,
-                             unsigned int *cnt, int W, int H, int level0, int levels, int grid,
-                             hipStream_t st)
+int bfs_levels_per_launch() { return kBfsLevels; }
+int bfs_ring() { return kBfsRing; }
+
+hipError_t launch_bfs_block(const unsigned long long *obits, unsigned long long *const vis[2],
+                            unsigned long long *const fr[2], int32_t *D, int W, int H, int wpr,
+                            int j, unsigned int *active, hipStream_t st)
 {
-    for (int L = level0; L < level0 + levels; ++L) {
-        const int32_t *fin = (L & 1) ? fb : fa;
-        int32_t *fout = (L & 1) ? fa : fb;
-        hipLaunchKernelGGL(k_bfs_expand, dim3(grid), dim3(256), 0, st, obst, D, fin, fout, cnt, W,
-                           H, L);
-        const hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
+    const dim3 grid((unsigned)((wpr + kBfsTileWords - 1) / kBfsTileWords),
+                    (unsigned)((H + kBfsTileRows - 1) / kBfsTileRows));
+    hipLaunchKernelGGL(k_bfs_block, grid, dim3(kBfsThreads), 0, st, obits, vis[j & 1], fr[j & 1],
+                       vis[(j + 1) & 1], fr[(j + 1) & 1], D, W, H, wpr, j, active);
+    return hipGetLastError();
 }
 
 hipError_t launch_count_unreachable(const uint8_t *obst, const int32_t *D, int n,
