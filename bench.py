@@ -241,7 +241,7 @@ def bench_serving(args, stream):
         reqs = [serve.Request(i, float(a), (lambda s=pool[i % len(pool)]: s), max_steps=2000)
                 for i, a in enumerate(arrivals)]
         srv = serve.Server(int(args.budget_gib * (1 << 30)), max_scenes=args.max_scenes,
-                           stream=stream, create_stream=torch.cuda.Stream())
+                           stream=stream, background_builds=not args.sync_builds)
         say(f"rate {lam:g}/s: {len(reqs)} requests over {args.serve_seconds:g} s")
         out = srv.run(reqs, stop_admitting_at=args.serve_seconds, drain=False,
                       deadline=args.serve_seconds)
@@ -258,7 +258,9 @@ def bench_serving(args, stream):
            "config": {"workload": "serving", "rates_per_s": rates,
                       "window_s": args.serve_seconds, "max_steps": 2000,
                       "budget_gib": args.budget_gib, "max_scenes": args.max_scenes,
-                      "request_pool": len(pool), "parallelism": "single-gpu"},
+                      "request_pool": len(pool),
+                      "builds": "between ticks" if args.sync_builds else "worker thread",
+                      "parallelism": "single-gpu"},
            "runs": runs, "roofline": None, "cpu_baseline": None}
     print(json.dumps(out), flush=True)
 
@@ -275,6 +277,8 @@ def main():
     ap.add_argument("--rates", default="50,200,800", help="arrival rates per s (serving)")
     ap.add_argument("--serve-seconds", type=float, default=30.0,
                     help="arrival window per rate (serving)")
+    ap.add_argument("--sync-builds", action="store_true",
+                    help="serving: build admitted scenes between ticks, not on a worker thread")
     ap.add_argument("--budget-gib", type=float, default=64.0,
                     help="device memory admitted scenes may hold (serving)")
     ap.add_argument("--max-scenes", type=int, default=256, help="resident slots (serving)")

@@ -9,9 +9,14 @@ builds a new batch (the scenes' device state stays where it is).  Scene
 state never leaves the device between ticks.  All arithmetic runs in the HIP
 library; this module only schedules.
 
-Building a scene (validation, static fields) takes milliseconds, during which
-resident scenes do not tick; at most `max_admit_per_tick` scenes are admitted
-between two ticks, which bounds that pause.
+Building a scene (validation, static fields) takes milliseconds.  By default
+admitted scenes are built one after another on a worker thread, on a stream
+of their own, while the resident scenes keep ticking (the library's calls
+release the interpreter lock); a scene joins the batch at the first tick
+after its build completes, and scenes being built hold their memory and
+slot from the moment of admission.  With `background_builds=False` the
+builds run between ticks instead, at most `max_admit_per_tick` of them
+between two ticks.
 
 The per-tick latency a resident scene sees is the wall time between two of
 its ticks (admissions and retirements included).
@@ -20,6 +25,8 @@ from __future__ import annotations
 
 import collections
 import dataclasses
+import queue as _queue
+import threading
 import time
 from typing import Callable, List, Optional
 
@@ -94,7 +101,8 @@ class Server:
     def __init__(self, budget_bytes: int, max_scenes: int = 512, stream=None,
                  tiling: Optional[dict] = None, keep_positions: bool = False,
                  clock=time.perf_counter, max_admit_per_tick: int = 1,
-                 create_stream=None):
+                 create_stream=None, background_builds: bool = True,
+                 max_building: int = 2):
         self.budget = int(budget_bytes)
         self.max_scenes = int(max_scenes)
         self.stream = stream
@@ -102,8 +110,31 @@ class Server:
         self.keep_positions = keep_positions
         self.clock = clock
         self.max_admit_per_tick = int(max_admit_per_tick)
-        # stream on which admitted scenes are built (default: the tick stream)
-        self.create_stream = create_stream if create_stream is not None else stream
+        self.background = bool(background_builds)
+        # admitted scenes waiting for or in their build (background mode)
+        self.max_building = max(1, int(max_building))
+        # stream on which admitted scenes are built: in background mode one
+        # that does not wait for the ticks (a torch stream), otherwise the
+        # tick stream
+        self.create_stream = create_stream
+        if self.create_stream is None and not self.background:
+            self.create_stream = stream
+
+    def _builder(self, jobs, done, stream):
+        device = getattr(stream, "device", None)
+        if device is not None:  # the current device is per thread
+            import torch
+
+            torch.cuda.set_device(device)
+        while True:
+            job = jobs.get()
+            if job is None:
+                return
+            req, scene, need = job
+            try:
+                done.put((req, need, sf.GpuScene(scene, stream=stream), None))
+            except BaseException as e:  # reported by the serving loop
+                done.put((req, need, None, e))
 
     def run(self, requests: List[Request], stop_admitting_at: Optional[float] = None,
             drain: bool = True, deadline: Optional[float] = None) -> dict:
@@ -128,6 +159,29 @@ class Server:
         def now():
             return self.clock() - t0
 
+        building = 0
+        jobs: "_queue.Queue" = _queue.Queue()
+        done_q: "_queue.Queue" = _queue.Queue()
+        worker = None
+        if self.background:
+            cs = self.create_stream
+            if cs is None:
+                import torch
+
+                cs = torch.cuda.Stream()
+            worker = threading.Thread(target=self._builder, args=(jobs, done_q, cs),
+                                      name="sf-scene-builder", daemon=True)
+            worker.start()
+
+        def join_built(item):
+            nonlocal building, used
+            req, need, g, err = item
+            building -= 1
+            if err is not None:
+                used -= need
+                raise err
+            resident.append(_Resident(req, None, g, now(), need))
+
         try:
             while True:
                 t = now()
@@ -137,35 +191,56 @@ class Server:
                 while pending and pending[0].arrival <= t:
                     queue.append(pending.popleft())
                 changed = False
+                # scenes whose build completed join before this tick
+                if self.background:
+                    while True:
+                        try:
+                            item = done_q.get_nowait()
+                        except _queue.Empty:
+                            break
+                        join_built(item)
+                        changed = True
                 # admission in arrival order while the head of the queue fits
-                # (all at once while nothing is resident)
+                # (synchronous builds: all at once while nothing is resident)
                 admitted_now = 0
-                while (admitting and queue and len(resident) < self.max_scenes
-                       and (admitted_now < self.max_admit_per_tick or not resident)):
+                while admitting and queue and len(resident) + building < self.max_scenes:
+                    if self.background:
+                        if building >= self.max_building:
+                            break
+                    elif admitted_now >= self.max_admit_per_tick and resident:
+                        break
                     req = queue[0]
                     scene = req.scene()
                     need = footprint_bytes(scene)
                     if used + need > self.budget:
-                        if not resident:
+                        if not resident and not building:
                             raise ValueError(f"request {req.rid} needs {need} B, more than "
                                              f"the whole budget of {self.budget} B")
                         break
                     queue.popleft()
                     req._scene = None  # the device copy is the state from here on
+                    used += need
+                    admitted_n += 1
+                    admitted_now += 1
+                    max_used = max(max_used, used)
+                    if self.background:
+                        building += 1
+                        jobs.put((req, scene, need))
+                        continue
                     if batch is not None:
                         batch.close()
                         batch = None
                     g = sf.GpuScene(scene, stream=self.create_stream)
                     resident.append(_Resident(req, None, g, now(), need))
-                    used += need
-                    admitted_n += 1
-                    admitted_now += 1
-                    max_used = max(max_used, used)
+                    changed = True
+                if not resident and building:
+                    # nothing to tick: wait for the first build
+                    join_built(done_q.get())
                     changed = True
                 max_resident = max(max_resident, len(resident))
                 if not resident:
                     last_end = None
-                    if not admitting or (not pending and not queue):
+                    if not admitting or (not pending and not queue and not building):
                         break
                     if pending and not queue:
                         wait = pending[0].arrival - now()
@@ -206,6 +281,16 @@ class Server:
                     ids = {id(r) for r, _ in done}
                     resident = [r for r in resident if id(r) not in ids]
         finally:
+            if worker is not None:
+                jobs.put(None)
+                worker.join()
+                while True:  # builds that completed after the loop ended
+                    try:
+                        item = done_q.get_nowait()
+                    except _queue.Empty:
+                        break
+                    if item[2] is not None:
+                        item[2].close()
             if batch is not None:
                 batch.close()
             for r in resident:

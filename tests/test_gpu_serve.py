@@ -29,7 +29,8 @@ def _request_scene(i):
                               occupancy=occ, name=f"req{i}")
 
 
-def test_serving_results_match_scenes_alone(sf):
+@pytest.mark.parametrize("background", [True, False], ids=["background-builds", "sync-builds"])
+def test_serving_results_match_scenes_alone(sf, background):
     n = 24
     arrivals = serve.poisson_arrivals(400.0, 0.5, seed=4)[:n]
     reqs = [serve.Request(i, float(a), (lambda i=i: _request_scene(i)), max_steps=120)
@@ -38,9 +39,10 @@ def test_serving_results_match_scenes_alone(sf):
     budget = 5 * serve.footprint_bytes(_request_scene(0))
     import torch
 
-    # admitted scenes are built on their own stream while the others tick
+    # admitted scenes are built on a stream of their own (on a worker thread,
+    # or between ticks) while the others tick on the default stream
     srv = serve.Server(budget, max_scenes=6, keep_positions=True,
-                       create_stream=torch.cuda.Stream())
+                       create_stream=torch.cuda.Stream(), background_builds=background)
     out = srv.run(reqs)
     print({k: v for k, v in out.items() if k != "results"}, flush=True)
     assert out["finished"] == len(reqs)
