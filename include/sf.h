@@ -39,8 +39,8 @@
  *     scene must not overlap.
  *   - Environment overrides read by sf_create_scene, for tuning only (results
  *     do not depend on them bit for bit): SF_TILE="TWxHLxVECxNW[xCAP]" (field
- *     tile shape and source-list capacity), SF_FIELD_BLOCKS_PER_CU (field
- *     workgroups per compute unit), SF_DECIDE_ROWS (decide tile rows).
+ *     tile shape and source-list capacity) and SF_FIELD_BLOCKS_PER_CU (field
+ *     workgroups per compute unit).
  */
 #ifndef SF_H
 #define SF_H
@@ -100,8 +100,7 @@ typedef struct {
 
 /* Kernels that sf_kernel_time can report. */
 #define SF_KERNEL_SUPERPOSE 0 /* field write-back (k-5 role): P from positions  */
-#define SF_KERNEL_DECIDE 1    /* counting-sort binning + decide + register
-                                 (k-1 .. k-3 roles)                              */
+#define SF_KERNEL_DECIDE 1    /* decide + register (k-2, k-3 roles)             */
 #define SF_KERNEL_COMMIT 2    /* move winners, evacuate (k-4)                    */
 #define SF_KERNEL_COUNT 3
 
@@ -206,7 +205,6 @@ typedef struct {
     int32_t blocks_per_cu;     /* field kernel: workgroups per compute unit     */
     int32_t items_per_block;   /* field kernel: work items (runs of strips of
                                   one scene) dealt to each workgroup per tick  */
-    int32_t decide_rows;       /* decide kernel: rows of a 64-su-wide tile      */
 } sf_group_tiling;
 
 /* A batch splits its scenes into up to two groups by field radius: group 0

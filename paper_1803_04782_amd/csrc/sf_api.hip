@@ -66,7 +66,6 @@ struct sf_scene {
     int ncu = 0;
     // layout
     int wpr = 0;          // 64-bit words per bitmap row
-    int dec_rows = 8;     // rows of a decide tile
     ListCfg lc;           // pedestrian field launch shape
     float phi_axial = 0.f, phi_diag = 0.f;
     // device state
@@ -75,7 +74,6 @@ struct sf_scene {
     uint8_t *exitm = nullptr;
     unsigned long long *occ = nullptr, *claim = nullptr, *key = nullptr;
     int32_t *pos = nullptr, *target = nullptr;
-    unsigned long long *owner = nullptr;  // see SceneView::owner
     // Per-pedestrian arrays use internal ids: live pedestrians in row-major
     // order of their positions when the state was set, then the evacuated
     // ones, so that neighbouring su hold neighbouring ids.  ext (device) and
@@ -116,7 +114,7 @@ struct GroupLayout {
     sf_group_tiling t = {};
     std::vector<int> members;  // indices into sf_batch::scenes
     FieldLaunch fl;
-    int n_items = 0, dec_blocks = 0, com_blocks = 0, max_rows = 4;
+    int n_items = 0, dec_blocks = 0, com_blocks = 0;
     SceneView *d_views = nullptr;
     int32_t *d_dec_scene = nullptr, *d_com_scene = nullptr, *d_items = nullptr;
     std::vector<void *> bufs;
@@ -270,7 +268,7 @@ int timing_events(sf_scene *s, int k, sf::LaunchEvents *ev)
     return SF_OK;
 }
 
-// Occupancy, owner map and live count from the current positions, then the
+// Occupancy and live count from the current positions, then the
 // field of those positions.  Other counters are left as they are.
 int rebuild_dynamic(sf_scene *s)
 {
@@ -282,9 +280,7 @@ int rebuild_dynamic(sf_scene *s)
     }
     const size_t nwords = (size_t)s->wpr * s->H;
     SF_HIP(sf::launch_fill_u64(s->occ, nwords, 0ull, s->stream), "clear occupancy");
-    SF_HIP(sf::launch_fill_u64(s->owner, (size_t)s->W * s->H, ~0ull, s->stream), "clear owners");
-    SF_HIP(sf::launch_occ_init(s->pos, s->N, s->occ, s->wpr, s->W, s->ext, s->owner, s->ctr,
-                               s->stream),
+    SF_HIP(sf::launch_occ_init(s->pos, s->N, s->occ, s->wpr, s->W, s->ctr, s->stream),
            "occupancy");
     SF_HIP(sf::launch_field_one(s->fl, s->view, s->strips_per_block, s->stream), "superpose");
     return SF_OK;
@@ -482,13 +478,6 @@ int create(const sf_scene_desc *d, void *hip_stream, sf_scene **out)
     SF_HIP(hipDeviceGetAttribute(&s->ncu, hipDeviceAttributeMultiprocessorCount, s->device),
            "CU count");
     s->wpr = (s->W + 63) / 64;
-    s->dec_rows = sf::decide_rows(s->W, s->H, s->N, s->ncu);
-    if (const char *e = std::getenv("SF_DECIDE_ROWS")) {
-        // override of the decide kernel's tile rows (speed only)
-        const int r = std::atoi(e);
-        if (r < 1 || r > 64) return fail(SF_EINVAL, "SF_DECIDE_ROWS=%s outside 1..64", e);
-        s->dec_rows = r;
-    }
 
     int max_lds = 0;
     SF_HIP(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, s->device),
@@ -534,7 +523,6 @@ int create(const sf_scene_desc *d, void *hip_stream, sf_scene **out)
         (rc = dalloc(s, &s->claim, n, "claims")) || (rc = dalloc(s, &s->key, N, "keys")) ||
         (rc = dalloc(s, &s->pos, N, "positions")) || (rc = dalloc(s, &s->target, N, "targets")) ||
         (rc = dalloc(s, &s->ext, N, "id map")) ||
-        (rc = dalloc(s, &s->owner, n, "owners")) ||
         (rc = dalloc(s, &s->flags, (N + 3) & ~(size_t)3, "flags")) ||
         (rc = dalloc(s, &s->ctr, sf::kCtrWords, "counters")))
         return rc;
@@ -577,7 +565,6 @@ int setup_launches(sf_scene *s)
     v.wpr = s->wpr;
     v.N = s->N;
     v.R = s->R;
-    v.dec_rows = s->dec_rows;
     v.dec_block0 = 0;
     v.com_block0 = 0;
     v.phi_axial = s->phi_axial;
@@ -589,7 +576,6 @@ int setup_launches(sf_scene *s)
     v.claim = s->claim;
     v.key = s->key;
     v.ctr = s->ctr;
-    v.owner = s->owner;
     v.pos = s->pos;
     v.target = s->target;
     v.flags = s->flags;
@@ -768,9 +754,6 @@ int resolve_group_tiling(const sf_batch *b, int R, sf_group_tiling *t, ListCfg *
     if (t->items_per_block == 0) t->items_per_block = 8;
     if (t->items_per_block < 1 || t->items_per_block > 4096)
         return fail(SF_EINVAL, "items_per_block %d outside 1..4096", t->items_per_block);
-    if (t->decide_rows == 0) t->decide_rows = 32;
-    if (t->decide_rows < 1 || t->decide_rows > 64)
-        return fail(SF_EINVAL, "decide_rows %d outside 1..64", t->decide_rows);
     *lc = c;
     return SF_OK;
 }
@@ -817,14 +800,12 @@ int build_group(sf_batch *b, const std::vector<int> &members, const sf_group_til
         }
         SceneView v = s->view;
         sf::set_view_layout(v, lc, tab);
-        v.dec_rows = t.decide_rows;
         v.dec_block0 = (int32_t)dec_total;
         v.com_block0 = (int32_t)com_total;
-        dec_total += sf::decide_blocks(s->wpr, s->H, v.dec_rows);
+        dec_total += sf::decide_blocks(s->N);
         com_total += sf::commit_blocks(s->N);
         if (dec_total >= INT32_MAX / 2 || com_total >= INT32_MAX / 2)
             return fail(SF_EINVAL, "batch too large for one launch");
-        G.max_rows = std::max(G.max_rows, v.dec_rows);
         gv[(size_t)q] = v;
         views[(size_t)members[(size_t)q]] = v;
         // relative cost of one strip: its su, plus the sources each wave
@@ -935,7 +916,7 @@ int group_field(const GroupLayout &G, hipStream_t st, const sf::LaunchEvents *ev
 
 int group_tick(const GroupLayout &G, hipStream_t st)
 {
-    SF_HIP(sf::launch_decide_claim(G.d_views, G.d_dec_scene, G.dec_blocks, G.max_rows, st),
+    SF_HIP(sf::launch_decide_claim(G.d_views, G.d_dec_scene, G.dec_blocks, st),
            "batch decide");
     SF_HIP(sf::launch_commit(G.d_views, G.d_com_scene, G.com_blocks, st), "batch commit");
     return group_field(G, st);

@@ -88,7 +88,7 @@ ListCfg pick_list_cfg(int radius, size_t max_lds);
 bool list_shape_compiled(int tw, int hl, int vec, int nw);
 hipError_t launch_phi_copies(float *tab, const ListCfg &c, double k, double alpha,
                              hipStream_t st);
-// Dynamic LDS limit of the field and decide kernels.
+// Dynamic LDS limit of the field kernels.
 hipError_t set_field_lds_limit(size_t bytes);
 
 // What the per-tick kernels read of one scene.  A launch covers one or more
@@ -96,7 +96,6 @@ hipError_t set_field_lds_limit(size_t bytes);
 struct SceneView {
     int32_t W, H, wpr, N;
     int32_t R;
-    int32_t dec_rows;    // decide: tile rows (tiles are 64 su wide)
     int32_t dec_block0;  // first workgroup of this scene in the decide launch
     int32_t com_block0;  // first workgroup of this scene in the commit launch
     // field gather layout of this scene's radius under the launch's tile shape
@@ -110,9 +109,7 @@ struct SceneView {
     unsigned long long *occ, *claim, *key, *ctr;
     // per-pedestrian arrays are indexed by an internal id (pedestrians in
     // row-major order of their positions when the state was set); ext maps
-    // it to the caller's id, which keys the election.  owner[su] holds
-    // (caller id << 32) | internal id of the pedestrian there, ~0 if none.
-    unsigned long long *owner;
+    // it to the caller's id, which keys the election
     int32_t *pos, *target;
     uint8_t *flags;
     const uint8_t *exitm;
@@ -127,7 +124,7 @@ struct SceneView {
 void set_view_layout(SceneView &v, const ListCfg &c, const float *tab);
 
 // Workgroups of a scene in the decide and commit launches.
-int decide_blocks(int wpr, int H, int rows);
+int decide_blocks(int N);
 int commit_blocks(int N);
 
 // One field launch over `n_items` work items (int4: scene, first strip,
@@ -185,17 +182,12 @@ hipError_t set_superpose_lds_limit(size_t f64_bytes);
 hipError_t launch_static_S(const int32_t *D, const double *O, const uint8_t *obst,
                            double w_dest, float *S, int n, hipStream_t st);
 hipError_t launch_occ_init(const int32_t *pos, int N, unsigned long long *occ, int wpr, int W,
-                           const int32_t *ext, unsigned long long *owner,
                            unsigned long long *ctr, hipStream_t st);
-// Rows of a decide tile (4..32) for a scene; LDS bytes of a launch whose
-// tallest tile has `max_rows` rows.
-int decide_rows(int W, int H, int N, int ncu);
-size_t decide_lds_bytes(int max_rows);
-// Decide + claim over `n_blocks` workgroups.  `block_scene[b]` names the
-// scene of workgroup b (NULL: every workgroup belongs to views[0]);
-// `max_rows` is the tallest decide tile of the launch's scenes (sizes the LDS).
+// Decide + claim over `n_blocks` workgroups, decide_blocks(N) per scene.
+// `block_scene[b]` names the scene of workgroup b (NULL: every workgroup
+// belongs to views[0]).
 hipError_t launch_decide_claim(const SceneView *views, const int32_t *block_scene, int n_blocks,
-                               int max_rows, hipStream_t st, const LaunchEvents *ev = nullptr);
+                               hipStream_t st, const LaunchEvents *ev = nullptr);
 hipError_t launch_commit(const SceneView *views, const int32_t *block_scene, int n_blocks,
                          hipStream_t st, const LaunchEvents *ev = nullptr);
 // dst[ext[i]] = src[i] for i < n (internal to caller order).

@@ -851,34 +851,37 @@ __global__ void k_phi_copies(float *tab, int vec, int copy_elems, int ncols, int
 // ---- occupancy ----------------------------------------------------------------------
 
 __global__ void k_occ_init(const int32_t *__restrict__ pos, int N, unsigned long long *occ, int wpr,
-                           int W, const int32_t *__restrict__ ext,
-                           unsigned long long *__restrict__ owner, unsigned long long *ctr)
+                           int W, unsigned long long *ctr)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int p = i < N ? pos[i] : -1;
     if (p >= 0) {
         const int y = p / W, x = p - y * W;
         atomicOr(&occ[(size_t)y * wpr + (x >> 6)], 1ull << (x & 63));
-        owner[p] = ((unsigned long long)(uint32_t)ext[i] << 32) | (uint32_t)i;
     }
     block_sum_add(p >= 0 ? 1u : 0u, ctr, kLive);
 }
 
-// ---- bin + decide + claim (k-2, k-3 registration) --------------------------------------
+// ---- decide + claim (k-2, k-3 registration) --------------------------------------------
 //
-// A workgroup takes a tile of 64 columns (one bitmap word per row) by `rows`
-// rows.  Binning is a counting sort whose bins are the tile's row words: one
-// wave popcounts them, prefix-sums over its lanes and scatters the su of each
-// row (ascending x) into an LDS list.  The four waves share the loads of the
-// field tile.  Tiles without pedestrians stop there.
-// Otherwise the tile's field with a one-su halo is staged in LDS (coalesced
-// row reads, +inf outside the grid, which no candidate test accepts), and
-// one thread per listed pedestrian takes the decision from LDS: the field at
-// the 9 candidates and the occupancy bits of the 8 neighbours.
+// One thread per pedestrian (internal id i, ids ordered by position at
+// creation, so a wave's pedestrians are close together and share cache
+// lines).  Its loads are independent and issued together: the occupancy bits
+// of the three rows around it (one bitmap word per row, and the neighbouring
+// word when it stands at a word edge) and the field at the 9 candidate su.
+// Then the decision, the election key and the claim (an atomic minimum on
+// the target's claim word).  Pedestrians that have left are skipped (the
+// commit kernel clears their outputs).
 
 constexpr int kDecideThreads = 256;
 constexpr int kCommitThreads = 256;
-constexpr int kTileCols = 66;  // 64 columns and the halo column on each side
+
+// workgroups of one scene's decide launch (at least one: it also clears the
+// moved-su bitmaps)
+__host__ __device__ constexpr int decide_block_count(int N)
+{
+    return N > 0 ? (N + kDecideThreads - 1) / kDecideThreads : 1;
+}
 
 // The view of this workgroup's scene: views[block_scene[block]] (MULTI) or
 // the kernel argument `one`.
@@ -893,89 +896,69 @@ __device__ __forceinline__ const SceneView &block_view(const SceneView &one,
 
 template <bool MULTI>
 __global__ __launch_bounds__(kDecideThreads) void k_decide_claim(
-    SceneView one, const SceneView *__restrict__ views, const int32_t *__restrict__ block_scene,
-    int max_rows)
+    SceneView one, const SceneView *__restrict__ views, const int32_t *__restrict__ block_scene)
 {
-    extern __shared__ __align__(16) unsigned char dec_raw[];
-    __shared__ int n_listed;
     const SceneView &v = block_view<MULTI>(one, views, block_scene);
-    const int W = v.W, H = v.H, wpr = v.wpr, rows = v.dec_rows;
+    const int W = v.W, H = v.H, wpr = v.wpr, N = v.N;
+    const int lb = (int)blockIdx.x - v.dec_block0;
+    const int i = lb * kDecideThreads + (int)threadIdx.x;
     const gptr<const unsigned long long> occ = to_global((const unsigned long long *)v.occ);
     const gptr<const float> P = to_global((const float *)v.P);
-    const gptr<const unsigned long long> owner = to_global((const unsigned long long *)v.owner);
     const gptr<unsigned long long> claim = to_global(v.claim), key = to_global(v.key),
                                    ctr = to_global(v.ctr);
     const gptr<int32_t> target = to_global(v.target);
     const gptr<uint8_t> flags = to_global(v.flags);
-    // LDS: bitmap words (rows + 2) x 3 (left, own, right word), the field
-    // tile (rows + 2) x kTileCols, the pedestrian list (64 * rows su)
-    unsigned long long *words = reinterpret_cast<unsigned long long *>(dec_raw);
-    float *tile = reinterpret_cast<float *>(words + (max_rows + 2) * 3);
-    int32_t *list = reinterpret_cast<int32_t *>(tile + (max_rows + 2) * kTileCols);
-
-    const int tid = (int)threadIdx.x;
-    const int lb = (int)blockIdx.x - v.dec_block0;
-    const int tx = lb % wpr, ty = lb / wpr;
-    const int x0 = tx * 64, y0 = ty * rows;
-    for (int k = tid; k < (rows + 2) * 3; k += kDecideThreads) {
-        const int r = k / 3, c = k - r * 3;
-        const int y = y0 - 1 + r, w = tx - 1 + c;
-        words[k] = (y >= 0 && y < H && w >= 0 && w < wpr) ? occ[(size_t)y * wpr + w] : 0ull;
+    if (v.moved_from) {
+        // the previous tick's moves have been applied to the field
+        const int nb = decide_block_count(N);
+        const size_t nwd = (size_t)wpr * H;
+        for (size_t k = (size_t)lb * kDecideThreads + threadIdx.x; k < nwd;
+             k += (size_t)nb * kDecideThreads) {
+            to_global(v.moved_from)[k] = 0ull;
+            to_global(v.moved_to)[k] = 0ull;
+        }
     }
     const unsigned long long t = ctr[0];
-    if (v.moved_from && tid < rows && y0 + tid < H) {
-        // the previous tick's moves have been applied to the field
-        const size_t wi = (size_t)(y0 + tid) * wpr + tx;
-        to_global(v.moved_from)[wi] = 0ull;
-        to_global(v.moved_to)[wi] = 0ull;
-    }
-    __syncthreads();
-    if (tid < 64) {
-        // one wave bins the tile: row r's su go to list[excl(r) ...]
-        const unsigned long long m = tid < rows ? words[(tid + 1) * 3 + 1] : 0ull;
-        int total;
-        int o = wave_excl_small(__popcll(m), total);
-        unsigned long long b = m;
-        const int rowbase = (y0 + tid) * W + x0;
-        while (b) {
-            const int bit = __builtin_ctzll(b);
-            b &= b - 1ull;
-            list[o++] = rowbase + bit;
-        }
-        if (tid == 0) n_listed = total;
-    }
-    __syncthreads();
-    const int total = n_listed;
-    if (total == 0) return;  // uniform: no pedestrian in this tile
-    for (int k = tid; k < (rows + 2) * kTileCols; k += kDecideThreads) {
-        const int r = k / kTileCols, c = k - r * kTileCols;
-        const int y = y0 - 1 + r, x = x0 - 1 + c;
-        tile[k] = (y >= 0 && y < H && x >= 0 && x < W) ? P[(size_t)y * W + x] : INFINITY;
-    }
-    __syncthreads();
-
     const unsigned long long seed = v.seed;
     const float phi_axial = v.phi_axial, phi_diag = v.phi_diag;
     unsigned int movers = 0, ties = 0;
-    for (int k = tid; k < total; k += kDecideThreads) {
-        const int p = list[k];
-        const unsigned long long who = owner[p];
-        const int i = (int)(uint32_t)who;
-        const uint32_t eid = (uint32_t)(who >> 32);
+    const int p = i < N ? to_global((const int32_t *)v.pos)[i] : -1;
+    if (p >= 0) {
+        const uint32_t eid = (uint32_t)to_global((const int32_t *)v.ext)[i];
         const int y = p / W, x = p - y * W;
-        const int ly = y - y0 + 1, lx = x - x0 + 1;  // position in the tile
-        float lo = tile[ly * kTileCols + lx], lo2 = INFINITY;
+        const int w = x >> 6, b = x & 63;
+        // occupancy of columns x - 1, x, x + 1 in rows y - 1, y, y + 1: bit
+        // (dx + 1) of nb3[dy + 1]
+        unsigned int nb3[3];
+        float pv[3][3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            const int yy = y - 1 + r;
+            const bool row_in = yy >= 0 && yy < H;
+            const size_t rw = (size_t)yy * wpr;
+            const unsigned long long mid = row_in ? occ[rw + w] : 0ull;
+            const unsigned long long lft = row_in && b == 0 && w > 0 ? occ[rw + w - 1] : 0ull;
+            const unsigned long long rgt = row_in && b == 63 && w + 1 < wpr ? occ[rw + w + 1] : 0ull;
+            const unsigned int cl = b > 0 ? (unsigned int)(mid >> (b - 1)) & 1u
+                                          : (unsigned int)(lft >> 63);
+            const unsigned int cc = (unsigned int)(mid >> b) & 1u;
+            const unsigned int cr = b < 63 ? (unsigned int)(mid >> (b + 1)) & 1u
+                                           : (unsigned int)rgt & 1u;
+            nb3[r] = cl | (cc << 1) | (cr << 2);
+            // P is +inf on obstacle su; outside the grid reads +inf too
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const int xx = x - 1 + c;
+                pv[r][c] = row_in && xx >= 0 && xx < W ? P[(size_t)yy * W + xx] : INFINITY;
+            }
+        }
+        float lo = pv[1][1], lo2 = INFINITY;
         int best = 0;
 #pragma unroll
         for (int d = 1; d <= 8; ++d) {
-            const int ny = ly + kDirY[d], nx = lx + kDirX[d];
-            // bit of column x + dx in the three words of row ny (word 0 covers
-            // x0 - 64 .. x0 - 1); out-of-grid neighbours read +inf
-            const int gx = nx + 63;
-            const unsigned long long wbits = words[ny * 3 + (gx >> 6)];
-            const float pc = tile[ny * kTileCols + nx];
-            // P is +inf on obstacle su and outside the grid
-            if (!((wbits >> (gx & 63)) & 1ull) && pc < INFINITY) {
+            const int r = 1 + kDirY[d], c = 1 + kDirX[d];
+            const float pc = pv[r][c];
+            if (!((nb3[r] >> c) & 1u) && pc < INFINITY) {
                 const float u = pc - ((d & 1) ? phi_axial : phi_diag);
                 if (u < lo) {
                     lo2 = lo;
@@ -1019,8 +1002,6 @@ __global__ __launch_bounds__(kCommitThreads) void k_commit(SceneView one,
     const int i = lb * kCommitThreads + (int)threadIdx.x;
     const int W = v.W, wpr = v.wpr;
     const gptr<int32_t> pos = to_global(v.pos), target = to_global(v.target);
-    const gptr<unsigned long long> owner = to_global(v.owner);
-    const gptr<const int32_t> ext = to_global(v.ext);
     const gptr<uint8_t> flags = to_global(v.flags);
     const gptr<const uint8_t> exitm = to_global(v.exitm);
     const gptr<const unsigned long long> key = to_global((const unsigned long long *)v.key);
@@ -1041,7 +1022,9 @@ __global__ __launch_bounds__(kCommitThreads) void k_commit(SceneView one,
             if (f & kMover) {
                 // the winner is the only registrant that finds its own key; it
                 // also resets the word, which losers then read as "not mine"
-                if (claim[tgt] == kk) {
+                const unsigned long long cw = claim[tgt];
+                const bool to_exit = exitm[tgt] != 0;
+                if (cw == kk) {
                     won = true;
                     claim[tgt] = ~0ull;
                     const int y = p / W, x = p - y * W;
@@ -1051,8 +1034,7 @@ __global__ __launch_bounds__(kCommitThreads) void k_commit(SceneView one,
                     if (v.moved_from)
                         __hip_atomic_fetch_or(&to_global(v.moved_from)[wp], 1ull << (x & 63),
                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    owner[p] = ~0ull;
-                    if (exitm[tgt]) {
+                    if (to_exit) {
                         left = true;
                         pos[i] = -1;
                     } else {
@@ -1063,7 +1045,6 @@ __global__ __launch_bounds__(kCommitThreads) void k_commit(SceneView one,
                         if (v.moved_to)
                             __hip_atomic_fetch_or(&to_global(v.moved_to)[wt], 1ull << (tx & 63),
                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        owner[tgt] = ((unsigned long long)(uint32_t)ext[i] << 32) | (uint32_t)i;
                         pos[i] = tgt;
                     }
                     flags[i] = f | kWon;
@@ -1391,11 +1372,7 @@ hipError_t set_field_lds_limit(size_t bytes)
     if (e != hipSuccess) return e;
     SF_LIST_SHAPES(SF_SET)
 #undef SF_SET
-    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_decide_claim<false>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_decide_claim<true>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    return hipSuccess;
 }
 
 hipError_t launch_field(const FieldLaunch &f, const SceneView *views, const int32_t *items,
@@ -1445,48 +1422,29 @@ hipError_t launch_static_S(const int32_t *D, const double *O, const uint8_t *obs
 }
 
 hipError_t launch_occ_init(const int32_t *pos, int N, unsigned long long *occ, int wpr, int W,
-                           const int32_t *ext, unsigned long long *owner, unsigned long long *ctr,
-                           hipStream_t st)
+                           unsigned long long *ctr, hipStream_t st)
 {
     hipLaunchKernelGGL(k_occ_init, dim3(blocks_for(N, 256)), dim3(256), 0, st, pos, N, occ, wpr, W,
-                       ext, owner, ctr);
+                       ctr);
     return hipGetLastError();
 }
 
-int decide_rows(int W, int H, int N, int ncu)
-{
-    // taller tiles amortise the halo rows; keep at least 8 tiles (workgroups)
-    // per compute unit
-    const double tiles_per_row = (double)((W + 63) / 64);
-    int r = 4;
-    while (r < 32 && tiles_per_row * ((H + 2 * r - 1) / (2 * r)) >= 8.0 * ncu) r *= 2;
-    (void)N;
-    return r;
-}
-
-size_t decide_lds_bytes(int max_rows)
-{
-    return (size_t)(max_rows + 2) * 3 * 8 + (size_t)(max_rows + 2) * kTileCols * 4 +
-           (size_t)64 * max_rows * 4;
-}
-
-int decide_blocks(int wpr, int H, int rows) { return wpr * ((H + rows - 1) / rows); }
+int decide_blocks(int N) { return decide_block_count(N); }
 
 int commit_blocks(int N) { return (int)blocks_for((size_t)N, kCommitThreads, 1u << 30); }
 
 hipError_t launch_decide_claim(const SceneView *views, const int32_t *block_scene, int n_blocks,
-                               int max_rows, hipStream_t st, const LaunchEvents *ev)
+                               hipStream_t st, const LaunchEvents *ev)
 {
     const SceneView none = {};
-    return launch(k_decide_claim<true>, dim3(n_blocks), dim3(kDecideThreads),
-                  decide_lds_bytes(max_rows), st, ev, none, views, block_scene, max_rows);
+    return launch(k_decide_claim<true>, dim3(n_blocks), dim3(kDecideThreads), 0, st, ev, none,
+                  views, block_scene);
 }
 
 hipError_t launch_decide_one(const SceneView &view, hipStream_t st, const LaunchEvents *ev)
 {
-    return launch(k_decide_claim<false>, dim3(decide_blocks(view.wpr, view.H, view.dec_rows)),
-                  dim3(kDecideThreads), decide_lds_bytes(view.dec_rows), st, ev, view,
-                  (const SceneView *)nullptr, (const int32_t *)nullptr, view.dec_rows);
+    return launch(k_decide_claim<false>, dim3(decide_blocks(view.N)), dim3(kDecideThreads), 0, st,
+                  ev, view, (const SceneView *)nullptr, (const int32_t *)nullptr);
 }
 
 hipError_t launch_scatter_i32(const int32_t *src, const int32_t *ext, int32_t *dst, int n,

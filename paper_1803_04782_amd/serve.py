@@ -35,10 +35,10 @@ import numpy as np
 from . import sf
 
 # Device bytes a resident scene holds (the library's per-scene arrays):
-# per su  S, P, D (4 B each), exit mask (1), claims (8), owners (8), occupancy
-# bits (1/8); per pedestrian  keys (8), positions, targets, id map (4 each),
-# flags (1); plus counters and the stamp copies (< 1 MiB).
-BYTES_PER_SU = 4 + 4 + 4 + 1 + 8 + 8 + 0.125
+# per su  S, P, D (4 B each), exit mask (1), claims (8), occupancy bits (1/8);
+# per pedestrian  keys (8), positions, targets, id map (4 each), flags (1);
+# plus counters and the stamp copies (< 1 MiB).
+BYTES_PER_SU = 4 + 4 + 4 + 1 + 8 + 0.125
 BYTES_PER_PED = 8 + 4 + 4 + 4 + 1
 FIXED_BYTES = 1 << 20
 

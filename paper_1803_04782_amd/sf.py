@@ -63,8 +63,7 @@ class GroupTiling(ctypes.Structure):
     """sf_group_tiling: field tile shape and schedule of one batch group."""
     _fields_ = [("tw", ctypes.c_int32), ("hl", ctypes.c_int32), ("vec", ctypes.c_int32),
                 ("nw", ctypes.c_int32), ("list_cap", ctypes.c_int32),
-                ("blocks_per_cu", ctypes.c_int32), ("items_per_block", ctypes.c_int32),
-                ("decide_rows", ctypes.c_int32)]
+                ("blocks_per_cu", ctypes.c_int32), ("items_per_block", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}

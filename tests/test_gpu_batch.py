@@ -88,11 +88,11 @@ def test_batch_members_match_scenes_alone(sf):
 @pytest.mark.parametrize("tiling", [
     dict(tw=16, hl=2, vec=2, nw=4),
     dict(tw=32, hl=4, vec=2, nw=4, items_per_block=1),
-    dict(tw=8, hl=2, vec=2, nw=4, list_cap=4096, items_per_block=64, decide_rows=4),
-    dict(tw=16, hl=4, vec=2, nw=8, blocks_per_cu=1, decide_rows=64),
+    dict(tw=8, hl=2, vec=2, nw=4, list_cap=4096, items_per_block=64),
+    dict(tw=16, hl=4, vec=2, nw=8, blocks_per_cu=1),
     dict(groups=1),
     dict(groups=2, split_radius=16,
-         group=[dict(tw=32, hl=4, vec=4, nw=4, decide_rows=8), dict(tw=16, hl=2, vec=2, nw=8)]),
+         group=[dict(tw=32, hl=4, vec=4, nw=4), dict(tw=16, hl=2, vec=2, nw=8)]),
 ])
 def test_batch_tilings_identical(sf, tiling):
     scs = _mixed_scenes()[:5]
