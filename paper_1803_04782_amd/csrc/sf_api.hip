@@ -502,8 +502,13 @@ int create(const sf_scene_desc *d, void *hip_stream, sf_scene **out)
     // the kernel also holds a few bytes of static LDS
     SF_HIP(sf::set_field_lds_limit((size_t)max_lds - 1024), "LDS limit");
     {
+        // as many persistent workgroups as a compute unit holds at once: more
+        // would run as a partial second round
         int per_cu = (int)std::max<size_t>(1, (size_t)(160 * 1024) / s->lc.lds_bytes);
         per_cu = std::min(per_cu, std::max(1, 32 / (s->lc.nw)));
+        const int resident = sf::field_resident_blocks(s->lc.tw, s->lc.hl, s->lc.vec, s->lc.nw,
+                                                       s->lc.lds_bytes, false);
+        if (resident > 0) per_cu = std::min(per_cu, resident);
         if (const char *e = std::getenv("SF_FIELD_BLOCKS_PER_CU")) {
             // override of the field kernel's persistent workgroups per CU (speed only)
             const int b = std::atoi(e);
@@ -747,7 +752,9 @@ int resolve_group_tiling(const sf_batch *b, int R, sf_group_tiling *t, ListCfg *
     if (c.list_cap < 2 * c.max_row || c.halo_rows > 64 * t->nw || c.lds_bytes > lds_cap)
         return fail(SF_EINVAL, "tiling %dx%dx%dx%d with list_cap %d does not fit radius %d",
                     t->tw, t->hl, t->vec, t->nw, t->list_cap, R);
-    const int bpc_max = std::max(1, std::min((int)((160 * 1024) / c.lds_bytes), 32 / t->nw));
+    int bpc_max = std::max(1, std::min((int)((160 * 1024) / c.lds_bytes), 32 / t->nw));
+    const int resident = sf::field_resident_blocks(t->tw, t->hl, t->vec, t->nw, c.lds_bytes, true);
+    if (resident > 0) bpc_max = std::min(bpc_max, resident);  // no partial second round
     if (t->blocks_per_cu == 0) t->blocks_per_cu = bpc_max;
     if (t->blocks_per_cu < 1 || t->blocks_per_cu > 64)
         return fail(SF_EINVAL, "blocks_per_cu %d outside 1..64", t->blocks_per_cu);

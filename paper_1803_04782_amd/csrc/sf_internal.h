@@ -138,6 +138,9 @@ struct FieldLaunch {
     size_t lds_bytes = 0;
 };
 FieldLaunch field_launch_for(const ListCfg &c);  // tab_max/halo_max of c, grid = c.grid
+// Workgroups of the field kernel of this shape that one compute unit holds at
+// once with `lds_bytes` of dynamic LDS (registers and LDS; 0 if unknown).
+int field_resident_blocks(int tw, int hl, int vec, int nw, size_t lds_bytes, bool multi);
 size_t field_lds_bytes(const FieldLaunch &f);
 hipError_t launch_field(const FieldLaunch &f, const SceneView *views, const int32_t *items,
                         int n_items, hipStream_t st, const LaunchEvents *ev = nullptr);

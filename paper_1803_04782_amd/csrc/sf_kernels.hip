@@ -1390,6 +1390,23 @@ hipError_t launch_field(const FieldLaunch &f, const SceneView *views, const int3
     return hipErrorInvalidValue;
 }
 
+int field_resident_blocks(int tw, int hl, int vec, int nw, size_t lds_bytes, bool multi)
+{
+    int n = 0;
+    hipError_t e = hipErrorInvalidValue;
+#define SF_OCC(a, b, v, w)                                                                        \
+    if (tw == a && hl == b && vec == v && nw == w)                                               \
+        e = multi ? hipOccupancyMaxActiveBlocksPerMultiprocessor(                                \
+                        &n, reinterpret_cast<const void *>(&k_field<a, b, v, w, true>), w * 64,   \
+                        lds_bytes)                                                               \
+                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(                                \
+                        &n, reinterpret_cast<const void *>(&k_field<a, b, v, w, false>), w * 64,  \
+                        lds_bytes);
+    SF_LIST_SHAPES(SF_OCC)
+#undef SF_OCC
+    return e == hipSuccess ? n : 0;
+}
+
 hipError_t launch_field_one(const FieldLaunch &f, const SceneView &view, int per,
                             hipStream_t st, const LaunchEvents *ev)
 {
