@@ -11,7 +11,8 @@ phi(0) = 0 (section 3.1, Fig. 1 caption and Table I's 1x1 entry), the
 destination field as 8-neighbour BFS distance to the openings, linear
 superposition of all fields (Algorithms 2/3: only the total matters), the
 tick of Algorithm 1 (decide, register-and-elect, move), and Philox4x32-10 keys
-for the election.
+for the election; for the periodic workloads of section 5, a torus without
+openings and per-pedestrian headings (a uniform destination slope).
 """
 from __future__ import annotations
 
@@ -57,20 +58,21 @@ def _load():
     lib.orc_bfs_distance.restype = i64
     lib.orc_bfs_distance.argtypes = [i32, i32, P, P, P]
     lib.orc_source_field.restype = None
-    lib.orc_source_field.argtypes = [i32, i32, P, i32, f64, f64, P]
+    lib.orc_source_field.argtypes = [i32, i32, P, i32, f64, f64, i32, P]
     lib.orc_total_field.restype = None
-    lib.orc_total_field.argtypes = [i32, i32, P, P, P, f64, i32, P, i32, f64, f64, P]
+    lib.orc_total_field.argtypes = [i32, i32, P, P, P, f64, i32, P, i32, f64, f64, i32, P]
     lib.orc_philox4x32_10.restype = None
     lib.orc_philox4x32_10.argtypes = [P, P, P]
     lib.orc_claim_key.restype = u64
     lib.orc_claim_key.argtypes = [i32, i64, u64]
     lib.orc_step.restype = i64
-    lib.orc_step.argtypes = [i32, i32, P, P, P, i32, f64, f64, u64, i64, i32, P, P, P, P]
+    lib.orc_step.argtypes = [i32, i32, P, P, P, i32, f64, f64, i32, P, f64, u64, i64, i32, P, P,
+                             P, P]
     lib.orc_field_at.restype = f64
-    lib.orc_field_at.argtypes = [i32, i32, P, P, P, f64, i32, f64, f64, i32, f64, f64, i64]
+    lib.orc_field_at.argtypes = [i32, i32, P, P, P, f64, i32, f64, f64, i32, f64, f64, i32, i64]
     lib.orc_decide_at.restype = None
-    lib.orc_decide_at.argtypes = [i32, i32, P, P, P, f64, i32, f64, f64, i32, f64, f64, i32,
-                                  P, P, P]
+    lib.orc_decide_at.argtypes = [i32, i32, P, P, P, f64, i32, f64, f64, i32, f64, f64, i32, i32,
+                                  f64, i32, P, P, P]
     _lib = lib
     return lib
 
@@ -106,10 +108,12 @@ def bfs_distance(W: int, H: int, obstacle, exitm):
     return D, int(unreach)
 
 
-def source_field(W: int, H: int, src_mask, R: int, k: float, alpha: float) -> np.ndarray:
+def source_field(W: int, H: int, src_mask, R: int, k: float, alpha: float,
+                 periodic: bool = False) -> np.ndarray:
     src = _c(src_mask, np.uint8)
     out = np.empty(W * H, dtype=np.float64)
-    _load().orc_source_field(W, H, _ptr(src), int(R), float(k), float(alpha), _ptr(out))
+    _load().orc_source_field(W, H, _ptr(src), int(R), float(k), float(alpha), int(periodic),
+                             _ptr(out))
     return out
 
 
@@ -132,6 +136,12 @@ class Statics:
     w_dest: float
     seed: int
     unreachable: int
+    periodic: bool = False
+    heading: Optional[np.ndarray] = None  # uint8 [N] by pedestrian id, or None
+    w_heading: float = 1.0
+
+    def heading_of(self, i: int) -> int:
+        return 0 if self.heading is None else int(self.heading[i])
 
     @property
     def S(self) -> np.ndarray:
@@ -146,13 +156,21 @@ def statics(scene, with_obstacle_field: bool = True) -> Statics:
     W, H = int(scene.width), int(scene.height)
     ob = _c(scene.obstacle, np.uint8)
     ex = _c(scene.exit, np.uint8)
-    D, unreach = bfs_distance(W, H, ob, ex)
+    periodic = bool(getattr(scene, "periodic", False))
+    if periodic:
+        # a torus without openings: no destination field
+        D, unreach = np.zeros(W * H, dtype=np.int32), 0
+    else:
+        D, unreach = bfs_distance(W, H, ob, ex)
     R_obs = int(scene.radius if getattr(scene, "radius_obs", -1) < 0 else scene.radius_obs)
-    O = (source_field(W, H, ob, R_obs, scene.k_obs, scene.alpha_obs)
+    O = (source_field(W, H, ob, R_obs, scene.k_obs, scene.alpha_obs, periodic)
          if with_obstacle_field else None)
+    hd = getattr(scene, "heading", None)
     return Statics(W, H, ob, ex, D, O, int(scene.radius), float(scene.k), float(scene.alpha),
                    R_obs, float(scene.k_obs), float(scene.alpha_obs), float(scene.w_dest),
-                   int(scene.seed), unreach)
+                   int(scene.seed), unreach, periodic,
+                   None if hd is None else _c(hd, np.uint8),
+                   float(getattr(scene, "w_heading", 1.0)))
 
 
 def total_field(st: Statics, pos) -> np.ndarray:
@@ -160,7 +178,8 @@ def total_field(st: Statics, pos) -> np.ndarray:
     p = _c(pos, np.int32)
     P = np.empty(st.W * st.H, dtype=np.float64)
     _load().orc_total_field(st.W, st.H, _ptr(st.obstacle), _ptr(st.D), _ptr(_c(st.O, np.float64)),
-                            st.w_dest, p.shape[0], _ptr(p), st.R, st.k, st.alpha, _ptr(P))
+                            st.w_dest, p.shape[0], _ptr(p), st.R, st.k, st.alpha,
+                            int(st.periodic), _ptr(P))
     return P
 
 
@@ -199,9 +218,11 @@ def step(st: Statics, pos, t: int, P: Optional[np.ndarray] = None) -> StepResult
     target = np.empty(n, dtype=np.int32)
     moved = np.empty(n, dtype=np.uint8)
     tied = np.empty(n, dtype=np.uint8)
+    hd = None if st.heading is None else _ptr(st.heading)
     left = _load().orc_step(st.W, st.H, _ptr(st.obstacle), _ptr(st.exit), _ptr(P), st.R,
-                            st.k, st.alpha, st.seed & (2**64 - 1), int(t), n, _ptr(newpos),
-                            _ptr(target), _ptr(moved), _ptr(tied))
+                            st.k, st.alpha, int(st.periodic), hd, st.w_heading,
+                            st.seed & (2**64 - 1), int(t), n, _ptr(newpos), _ptr(target),
+                            _ptr(moved), _ptr(tied))
     return StepResult(P, target, moved, tied, newpos, int(left))
 
 
@@ -231,18 +252,20 @@ def field_at(st: Statics, occ: np.ndarray, cells) -> np.ndarray:
     for j, c in enumerate(np.asarray(cells, dtype=np.int64)):
         out[j] = lib.orc_field_at(st.W, st.H, _ptr(st.obstacle), _ptr(occ), _ptr(st.D),
                                   st.w_dest, st.R, st.k, st.alpha, st.R_obs, st.k_obs,
-                                  st.alpha_obs, int(c))
+                                  st.alpha_obs, int(st.periodic), int(c))
     return out
 
 
-def decide_at(st: Statics, occ: np.ndarray, p: int):
-    """(target su, tied, P on the 3x3 block by direction) for the pedestrian at p."""
+def decide_at(st: Statics, occ: np.ndarray, p: int, heading: int = 0):
+    """(target su, tied, P on the 3x3 block by direction) for the pedestrian at
+    p with the given heading."""
     t = np.empty(1, dtype=np.int32)
     tied = np.empty(1, dtype=np.uint8)
     P9 = np.empty(9, dtype=np.float64)
     _load().orc_decide_at(st.W, st.H, _ptr(st.obstacle), _ptr(occ), _ptr(st.D), st.w_dest,
-                          st.R, st.k, st.alpha, st.R_obs, st.k_obs, st.alpha_obs, int(p),
-                          _ptr(t), _ptr(tied), _ptr(P9))
+                          st.R, st.k, st.alpha, st.R_obs, st.k_obs, st.alpha_obs,
+                          int(st.periodic), int(heading), st.w_heading, int(p), _ptr(t),
+                          _ptr(tied), _ptr(P9))
     return int(t[0]), bool(tied[0]), P9
 
 
@@ -253,7 +276,7 @@ def outcome_at(st: Statics, occ: np.ndarray, owner: np.ndarray, pos, i: int, t: 
     """Full tick outcome of pedestrian i from point evaluations only:
     (target, moved, tied).  `owner[c]` is the id at su c or -1."""
     p = int(pos[i])
-    tgt, tied, _ = decide_at(st, occ, p)
+    tgt, tied, _ = decide_at(st, occ, p, st.heading_of(i))
     if tgt == p:
         return tgt, False, tied
     # every live pedestrian that can register at tgt stands next to it
@@ -262,12 +285,14 @@ def outcome_at(st: Statics, occ: np.ndarray, owner: np.ndarray, pos, i: int, t: 
     best = None
     for dx, dy in DIRS[1:]:
         x, y = tx + dx, ty + dy
-        if not (0 <= x < W and 0 <= y < H):
+        if st.periodic:
+            x, y = x % W, y % H
+        elif not (0 <= x < W and 0 <= y < H):
             continue
         j = int(owner[y * W + x])
         if j < 0:
             continue
-        tj = tgt if j == i else decide_at(st, occ, y * W + x)[0]
+        tj = tgt if j == i else decide_at(st, occ, y * W + x, st.heading_of(j))[0]
         if tj != tgt:
             continue
         key = claim_key(j, t, st.seed)

@@ -39,6 +39,20 @@
  *                  Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) with
  *                  counter (id, t_lo, t_hi, 0) and key (seed_lo, seed_hi).
  *
+ * The experiments of section 5 run on a periodic boundary with pedestrian
+ * flows in 1, 2, 4 or 8 directions and no openings; the readings for them:
+ *   periodic       both axes wrap (a torus): field windows, candidates and
+ *                  positions are taken modulo W and H; no exits, so no
+ *                  destination field (D = 0);
+ *   heading        pedestrian i may carry a heading h_i (one of the eight
+ *                  directions e1..e8, 0 = none): the candidate reached by
+ *                  move e_d (d = 1..8) gets -w_h * cos(angle(e_h, e_d)) added
+ *                  to its value, staying gets 0.  The direction list turns by
+ *                  45 degrees per index, so the angle is 45 * min(|h - d|,
+ *                  8 - |h - d|) degrees and the cosine is one of 1, 1/sqrt2, 0,
+ *                  -1/sqrt2, -1; the FP32 decision uses fl32(w_h) and
+ *                  fl32(w_h / sqrt2) with the cosine's sign.
+ *
  * Direction list: e0 = (0,0) stay, e1 = (1,0), e2 = (1,1), e3 = (0,1),
  * e4 = (-1,1), e5 = (-1,0), e6 = (-1,-1), e7 = (0,-1), e8 = (1,-1); x is the
  * column (east +), y the row (south +); linear index c = y*W + x.
@@ -116,9 +130,10 @@ int64_t orc_bfs_distance(int W, int H, const uint8_t *obst, const uint8_t *exitm
 
 /* out[c] = sum over source su s (src[s] != 0) of phi(c - s), for every su c of
  * the grid.  Each source spreads its window; contributions outside the grid
- * are dropped.  Plain scatter in source raster order, FP64. */
+ * are dropped, or wrap around when `periodic`.  Plain scatter in source raster
+ * order, FP64. */
 void orc_source_field(int W, int H, const uint8_t *src, int R, double k, double alpha,
-                      double *out)
+                      int periodic, double *out)
 {
     int64_t n = (int64_t)W * H;
     int m = 2 * R + 1;
@@ -130,10 +145,16 @@ void orc_source_field(int W, int H, const uint8_t *src, int R, double k, double 
         int sx = (int)(s % W), sy = (int)(s / W);
         for (int dy = -R; dy <= R; ++dy) {
             int y = sy + dy;
-            if (y < 0 || y >= H) continue;
+            if (periodic)
+                y = ((y % H) + H) % H;
+            else if (y < 0 || y >= H)
+                continue;
             for (int dx = -R; dx <= R; ++dx) {
                 int x = sx + dx;
-                if (x < 0 || x >= W) continue;
+                if (periodic)
+                    x = ((x % W) + W) % W;
+                else if (x < 0 || x >= W)
+                    continue;
                 out[(int64_t)y * W + x] += tab[(dy + R) * m + (dx + R)];
             }
         }
@@ -153,12 +174,12 @@ void orc_occupancy(int W, int H, int32_t n_peds, const int32_t *pos, uint8_t *oc
  * Phi is the superposed pedestrian field of the live pedestrians. */
 void orc_total_field(int W, int H, const uint8_t *obst, const int32_t *D, const double *O,
                      double w_dest, int32_t n_peds, const int32_t *pos, int R, double k,
-                     double alpha, double *P)
+                     double alpha, int periodic, double *P)
 {
     int64_t n = (int64_t)W * H;
     uint8_t *occ = (uint8_t *)malloc((size_t)(n > 0 ? n : 1));
     orc_occupancy(W, H, n_peds, pos, occ);
-    orc_source_field(W, H, occ, R, k, alpha, P);
+    orc_source_field(W, H, occ, R, k, alpha, periodic, P);
     for (int64_t c = 0; c < n; ++c)
         P[c] = obst[c] ? INFINITY : w_dest * (double)D[c] + O[c] + P[c];
     free(occ);
@@ -205,20 +226,55 @@ uint64_t orc_claim_key(int32_t id, int64_t t, uint64_t seed)
 
 /* ---- one tick ------------------------------------------------------------ */
 
+/* Multiples of 45 degrees between directions h and d (both 1..8). */
+static int turn_steps(int h, int d)
+{
+    int s = h > d ? h - d : d - h;
+    return s > 4 ? 8 - s : s;
+}
+
+/* Heading term of the move e_d (d = 0: staying) for heading h (0: none), in
+ * FP64 and as the FP32 decision sees it. */
+static double heading_term64(int h, int d, double w_h)
+{
+    if (h == 0 || d == 0) return 0.0;
+    static const double cosv[5] = {1.0, 0.70710678118654752440, 0.0,
+                                   -0.70710678118654752440, -1.0};
+    return -w_h * cosv[turn_steps(h, d)];
+}
+
+static float heading_term32(int h, int d, double w_h)
+{
+    if (h == 0 || d == 0) return 0.0f;
+    float ca = (float)w_h, cd = (float)(w_h / sqrt(2.0));
+    switch (turn_steps(h, d)) {
+    case 0: return -ca;
+    case 1: return -cd;
+    case 2: return 0.0f;
+    case 3: return cd;
+    default: return ca;
+    }
+}
+
 /* Decision of one live pedestrian at su p, given the step-start field P and
  * occupancy.  Writes the chosen su and whether the two best candidates are a
  * near tie.  phi1 / phi2: the pedestrian's own field at an axial / diagonal
- * neighbour. */
+ * neighbour; h, w_h: its heading and the heading weight. */
 static void decide_one(int W, int H, const uint8_t *obst, const uint8_t *occ,
-                       const double *P, double phi_axial, double phi_diag, int32_t p,
-                       int32_t *target, uint8_t *tied)
+                       const double *P, double phi_axial, double phi_diag, int periodic,
+                       int h, double w_h, int32_t p, int32_t *target, uint8_t *tied)
 {
     int x = p % W, y = p / W;
     float best32 = 0.0f;
     int best_dir = -1;
+    int64_t best_c = p;
     double u_lo = INFINITY, u_lo2 = INFINITY; /* two smallest FP64 values */
     for (int d = 0; d <= 8; ++d) {
         int nx = x + DIR_X[d], ny = y + DIR_Y[d];
+        if (periodic) {
+            nx = (nx + W) % W;
+            ny = (ny + H) % H;
+        }
         if (d > 0) {
             if (nx < 0 || ny < 0 || nx >= W || ny >= H) continue;
             int64_t nc = (int64_t)ny * W + nx;
@@ -226,11 +282,12 @@ static void decide_one(int W, int H, const uint8_t *obst, const uint8_t *occ,
         }
         int64_t c = (int64_t)ny * W + nx;
         double own = d == 0 ? 0.0 : ((d & 1) ? phi_axial : phi_diag);
-        double u64 = P[c] - own;
-        float u32 = (float)P[c] - (float)own;
+        double u64 = P[c] - own + heading_term64(h, d, w_h);
+        float u32 = ((float)P[c] - (float)own) + heading_term32(h, d, w_h);
         if (best_dir < 0 || u32 < best32) {
             best32 = u32;
             best_dir = d;
+            best_c = c;
         }
         if (u64 < u_lo) {
             u_lo2 = u_lo;
@@ -239,7 +296,7 @@ static void decide_one(int W, int H, const uint8_t *obst, const uint8_t *occ,
             u_lo2 = u64;
         }
     }
-    *target = (int32_t)((int64_t)(y + DIR_Y[best_dir]) * W + (x + DIR_X[best_dir]));
+    *target = (int32_t)best_c;
     double scale = fabs(u_lo);
     if (fabs(u_lo2) > scale) scale = fabs(u_lo2);
     if (scale < 1.0) scale = 1.0;
@@ -248,14 +305,16 @@ static void decide_one(int W, int H, const uint8_t *obst, const uint8_t *occ,
 
 /* One tick from state (pos, t).
  *   P       [W*H]  the step-start total field (orc_total_field of pos)
+ *   heading [N]    headings (NULL: none)
  *   pos     [N]    in: step-start positions (-1 = evacuated); out: new ones
  *   target  [N]    out: chosen su (own su when staying; -1 when evacuated)
  *   moved   [N]    out: 1 if the pedestrian won its election and moved
  *   tied    [N]    out: 1 if its two best candidates are a near tie
  * Returns the number of pedestrians that left through an exit this tick. */
 int64_t orc_step(int W, int H, const uint8_t *obst, const uint8_t *exitm, const double *P,
-                 int R, double k, double alpha, uint64_t seed, int64_t t, int32_t n_peds,
-                 int32_t *pos, int32_t *target, uint8_t *moved, uint8_t *tied)
+                 int R, double k, double alpha, int periodic, const uint8_t *heading,
+                 double w_h, uint64_t seed, int64_t t, int32_t n_peds, int32_t *pos,
+                 int32_t *target, uint8_t *moved, uint8_t *tied)
 {
     int64_t n = (int64_t)W * H;
     uint8_t *occ = (uint8_t *)malloc((size_t)(n > 0 ? n : 1));
@@ -269,7 +328,8 @@ int64_t orc_step(int W, int H, const uint8_t *obst, const uint8_t *exitm, const 
         tied[i] = 0;
         target[i] = -1;
         if (pos[i] < 0) continue;
-        decide_one(W, H, obst, occ, P, phi_axial, phi_diag, pos[i], &target[i], &tied[i]);
+        decide_one(W, H, obst, occ, P, phi_axial, phi_diag, periodic, heading ? heading[i] : 0,
+                   w_h, pos[i], &target[i], &tied[i]);
     }
 
     /* k-3: per claimed su, the registered pedestrian with the smallest key. */
@@ -303,28 +363,36 @@ int64_t orc_step(int W, int H, const uint8_t *obst, const uint8_t *exitm, const 
 
 /* P at one su from masks (no full-grid pass): w_D*D + sum over obstacle su in
  * the obstacle window + sum over occupied su in the pedestrian window. */
+/* Source su row / column of an offset from c: -1 if it falls off a bounded
+ * grid, wrapped on a periodic one. */
+static int wrap_or_drop(int v, int n, int periodic)
+{
+    if (periodic) return ((v % n) + n) % n;
+    return (v < 0 || v >= n) ? -1 : v;
+}
+
 double orc_field_at(int W, int H, const uint8_t *obst, const uint8_t *occ, const int32_t *D,
                     double w_dest, int R, double k, double alpha, int R_obs, double k_obs,
-                    double alpha_obs, int64_t c)
+                    double alpha_obs, int periodic, int64_t c)
 {
     if (obst[c]) return INFINITY;
     int x = (int)(c % W), y = (int)(c / W);
     double o = 0.0, f = 0.0;
     for (int dy = -R_obs; dy <= R_obs; ++dy) {
-        int sy = y - dy;
-        if (sy < 0 || sy >= H) continue;
+        int sy = wrap_or_drop(y - dy, H, periodic);
+        if (sy < 0) continue;
         for (int dx = -R_obs; dx <= R_obs; ++dx) {
-            int sx = x - dx;
-            if (sx < 0 || sx >= W) continue;
+            int sx = wrap_or_drop(x - dx, W, periodic);
+            if (sx < 0) continue;
             if (obst[(int64_t)sy * W + sx]) o += orc_phi(dx, dy, R_obs, k_obs, alpha_obs);
         }
     }
     for (int dy = -R; dy <= R; ++dy) {
-        int sy = y - dy;
-        if (sy < 0 || sy >= H) continue;
+        int sy = wrap_or_drop(y - dy, H, periodic);
+        if (sy < 0) continue;
         for (int dx = -R; dx <= R; ++dx) {
-            int sx = x - dx;
-            if (sx < 0 || sx >= W) continue;
+            int sx = wrap_or_drop(x - dx, W, periodic);
+            if (sx < 0) continue;
             if (occ[(int64_t)sy * W + sx]) f += orc_phi(dx, dy, R, k, alpha);
         }
     }
@@ -335,18 +403,19 @@ double orc_field_at(int W, int H, const uint8_t *obst, const uint8_t *occ, const
  * field on its 3x3 neighbourhood.  Same rule as the full-grid tick. */
 void orc_decide_at(int W, int H, const uint8_t *obst, const uint8_t *occ, const int32_t *D,
                    double w_dest, int R, double k, double alpha, int R_obs, double k_obs,
-                   double alpha_obs, int32_t p, int32_t *target, uint8_t *tied,
-                   double *P9)
+                   double alpha_obs, int periodic, int h, double w_h, int32_t p,
+                   int32_t *target, uint8_t *tied, double *P9)
 {
     double Ploc[9];
     int x = p % W, y = p / W;
     /* field on the 3x3 block around p, stored by direction */
     for (int d = 0; d <= 8; ++d) {
-        int nx = x + DIR_X[d], ny = y + DIR_Y[d];
+        int nx = wrap_or_drop(x + DIR_X[d], W, periodic);
+        int ny = wrap_or_drop(y + DIR_Y[d], H, periodic);
         Ploc[d] = INFINITY;
-        if (nx < 0 || ny < 0 || nx >= W || ny >= H) continue;
+        if (nx < 0 || ny < 0) continue;
         Ploc[d] = orc_field_at(W, H, obst, occ, D, w_dest, R, k, alpha, R_obs, k_obs,
-                               alpha_obs, (int64_t)ny * W + nx);
+                               alpha_obs, periodic, (int64_t)ny * W + nx);
     }
     if (P9)
         for (int d = 0; d <= 8; ++d) P9[d] = Ploc[d];
@@ -359,8 +428,9 @@ void orc_decide_at(int W, int H, const uint8_t *obst, const uint8_t *occ, const 
         P3[j] = INFINITY;
     }
     for (int d = 0; d <= 8; ++d) {
-        int nx = x + DIR_X[d], ny = y + DIR_Y[d];
-        if (nx < 0 || ny < 0 || nx >= W || ny >= H) continue;
+        int nx = wrap_or_drop(x + DIR_X[d], W, periodic);
+        int ny = wrap_or_drop(y + DIR_Y[d], H, periodic);
+        if (nx < 0 || ny < 0) continue;
         int64_t nc = (int64_t)ny * W + nx;
         int j = (DIR_Y[d] + 1) * 3 + (DIR_X[d] + 1);
         o3[j] = obst[nc];
@@ -368,8 +438,9 @@ void orc_decide_at(int W, int H, const uint8_t *obst, const uint8_t *occ, const 
         P3[j] = Ploc[d];
     }
     int32_t t3;
-    decide_one(3, 3, o3, c3, P3, orc_phi(1, 0, R, k, alpha), orc_phi(1, 1, R, k, alpha), 4,
-               &t3, tied);
-    int tx = t3 % 3 - 1, ty = t3 / 3 - 1;
-    *target = (int32_t)((int64_t)(y + ty) * W + (x + tx));
+    decide_one(3, 3, o3, c3, P3, orc_phi(1, 0, R, k, alpha), orc_phi(1, 1, R, k, alpha), 0, h,
+               w_h, 4, &t3, tied);
+    int tx = wrap_or_drop(x + t3 % 3 - 1, W, periodic);
+    int ty = wrap_or_drop(y + t3 / 3 - 1, H, periodic);
+    *target = (int32_t)((int64_t)ty * W + tx);
 }

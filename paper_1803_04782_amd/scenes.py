@@ -8,8 +8,9 @@ the FP64 oracle can be fed from it.
 Scene geometry follows the paper's discrete model: a rectangular grid of space
 units (su), one su per pedestrian (1x1 footprint, section 5 experiments),
 openings (exits) where pedestrians leave, and static obstacles.  The paper's
-experiments use a periodic boundary; the scenes here use walls with exits
-instead, so that the static destination field is defined.
+experiments use a periodic boundary; most scenes here use walls with exits
+instead, so that the static destination field is defined, and `flow_scene`
+builds the paper's own workload: a torus with headed flows.
 
 Recipe (all random draws from numpy PCG64 with the stated seed):
   * the border ring of su is obstacle (walls);
@@ -26,7 +27,7 @@ Recipe (all random draws from numpy PCG64 with the stated seed):
 from __future__ import annotations
 
 from dataclasses import dataclass, field, replace
-from typing import List, Sequence
+from typing import List, Optional, Sequence
 
 import numpy as np
 
@@ -55,6 +56,9 @@ class Scene:
     steps: int = 0  # number of steps the workload runs
     name: str = ""
     meta: dict = field(default_factory=dict)
+    periodic: bool = False  # both axes wrap (a torus; no walls or exits)
+    heading: Optional[np.ndarray] = None  # uint8 [N]: direction index 1..8, 0 = none
+    w_heading: float = 1.0  # weight of the heading slope
 
     @property
     def n_peds(self) -> int:
@@ -216,6 +220,33 @@ def ensemble(n_scenes: int = 256, seed: int = 3, side=(128, 2048), steps: int = 
                                seed=sc_seed, rect_coverage=cov, occupancy=occ, steps=steps,
                                name=f"ens{s}"))
     return out
+
+
+# Headings of the flows of section 5 (indices into the direction list e1..e8:
+# 1 east, 2 south-east, 3 south, ..., 8 north-east).
+FLOW_HEADINGS = {1: (1,), 2: (1, 5), 4: (1, 3, 5, 7), 8: (1, 2, 3, 4, 5, 6, 7, 8)}
+
+
+def flow_scene(width: int, height: int, density: float, directions: int, *, radius: int = 3,
+               seed: int = 0, steps: int = 1000, w_heading: float = 1.0) -> Scene:
+    """The paper's experiment workload: a width x height torus (periodic
+    boundary, no obstacles or exits), round(density * su) pedestrians drawn
+    uniformly without replacement, split evenly over the `directions` (1, 2,
+    4 or 8) headings in random order, fields of half-width `radius` (3: the
+    7x7 geometry), `steps` ticks."""
+    if directions not in FLOW_HEADINGS:
+        raise ValueError(f"directions must be one of {sorted(FLOW_HEADINGS)}")
+    rng = np.random.Generator(np.random.PCG64([seed, width, height, directions]))
+    n = width * height
+    N = int(round(density * n))
+    pos = np.sort(rng.choice(n, size=N, replace=False)).astype(np.int32)
+    hs = np.array(FLOW_HEADINGS[directions], dtype=np.uint8)
+    heading = rng.permutation(np.resize(hs, N)).astype(np.uint8)
+    return Scene(width=width, height=height, obstacle=np.zeros(n, np.uint8),
+                 exit=np.zeros(n, np.uint8), pos=pos, radius=radius,
+                 seed=int(rng.integers(0, 2**63 - 1)), steps=steps,
+                 name=f"flow{width}x{height}d{density:g}k{directions}", periodic=True,
+                 heading=heading, w_heading=w_heading)
 
 
 def random_scene(width: int, height: int, n_peds: int, radius: int, seed: int, *,
