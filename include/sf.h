@@ -79,6 +79,17 @@ typedef struct {
     double w_dest;            /* weight of the destination field                  */
     uint64_t seed;            /* election key of the counter-based generator      */
     int64_t start_step;       /* tick index of the initial state (>= 0)           */
+    /* The periodic workload of the paper's experiments (section 5): */
+    int32_t periodic;         /* 1: both axes wrap (a torus): field windows and
+                                 moves cross the edges; no obstacle or exit su
+                                 may be set and width must be >= 64; 0: walls
+                                 and exits as above                               */
+    const uint8_t *heading;   /* [n_peds] per pedestrian: 0 = none, d = 1..8 the
+                                 direction e_d of the direction list; a move e_m
+                                 gets -w_heading * cos(angle(e_d, e_m)) added to
+                                 its value (staying: 0).  NULL = no headings;
+                                 copied                                          */
+    double w_heading;         /* weight of the heading term                       */
 } sf_scene_desc;
 
 /* Running totals of a scene. */
@@ -106,12 +117,14 @@ typedef struct {
 
 /* Create a scene: validate the descriptor, copy it to the device, build the
  * static fields (BFS destination field and obstacle field, fused to one FP32
- * array), bin the pedestrians and compute the field of the initial
- * positions.  `hip_stream` is a hipStream_t (NULL for the null stream).
- * Blocks until the scene is ready.  Errors: SF_EINVAL (bad sizes, pointers,
- * radius, non-finite parameters, exit on an obstacle, no exit, pedestrian out
- * of range / on an obstacle or exit / duplicated), SF_EUNREACHABLE (a free su
- * cannot reach an exit), SF_ENOMEM, SF_EDEVICE.  On error *out is NULL. */
+ * array; zero on a periodic scene), bin the pedestrians and compute the field
+ * of the initial positions.  `hip_stream` is a hipStream_t (NULL for the null
+ * stream).  Blocks until the scene is ready.  Errors: SF_EINVAL (bad sizes,
+ * pointers, radius, non-finite parameters, exit on an obstacle, no exit,
+ * pedestrian out of range / on an obstacle or exit / duplicated, heading
+ * above 8; periodic: an obstacle or exit su, width < 64, 2R+1 above a side),
+ * SF_EUNREACHABLE (a free su cannot reach an exit), SF_ENOMEM, SF_EDEVICE.
+ * On error *out is NULL. */
 int sf_create_scene(const sf_scene_desc *desc, void *hip_stream, sf_scene **out);
 
 /* Enqueue n_steps ticks (Algorithm 1 loop body, n_steps >= 0) on the scene's

@@ -61,6 +61,9 @@ struct sf_scene {
     double k = 1, alpha = -0.5, k_obs = 1, alpha_obs = -0.5, w_dest = 1;
     unsigned long long seed = 0;
     int64_t start_step = 0;
+    bool periodic = false;
+    double w_heading = 1;
+    std::vector<uint8_t> h_heading;  // by caller id; empty: no headings
     int device = 0;
     hipStream_t stream = nullptr;
     int ncu = 0;
@@ -80,6 +83,7 @@ struct sf_scene {
     // h_ext (host) map an internal id to the caller's id.
     int32_t *ext = nullptr;
     std::vector<int32_t> h_ext;
+    uint8_t *heading = nullptr;  // by internal id (NULL: no headings)
     uint8_t *flags = nullptr;
     unsigned long long *ctr = nullptr;  // see sf::ctr_index
     // what the per-tick kernels read: the view (host copy and device copy),
@@ -211,12 +215,31 @@ int validate(const sf_scene_desc *d)
         return fail(SF_EINVAL, "radius %d outside 0..%d", d->radius, SF_MAX_RADIUS);
     if (d->radius_obs < -1 || d->radius_obs > SF_MAX_RADIUS)
         return fail(SF_EINVAL, "radius_obs %d outside -1..%d", d->radius_obs, SF_MAX_RADIUS);
-    const double params[5] = {d->k, d->alpha, d->k_obs, d->alpha_obs, d->w_dest};
+    const double params[6] = {d->k, d->alpha, d->k_obs, d->alpha_obs, d->w_dest, d->w_heading};
     for (double v : params)
         if (!std::isfinite(v)) return fail(SF_EINVAL, "field parameters must be finite");
     if (d->start_step < 0) return fail(SF_EINVAL, "start_step %lld is negative",
                                        (long long)d->start_step);
+    if (d->periodic != 0 && d->periodic != 1)
+        return fail(SF_EINVAL, "periodic = %d is neither 0 nor 1", d->periodic);
+    if (d->heading)
+        for (int i = 0; i < d->n_peds; ++i)
+            if (d->heading[i] > 8)
+                return fail(SF_EINVAL, "pedestrian %d has heading %d above 8", i, d->heading[i]);
     const int64_t n = (int64_t)d->width * d->height;
+    if (d->periodic) {
+        // a torus: the halo words of the field kernel wrap at most once
+        if (d->width < 64)
+            return fail(SF_EINVAL, "periodic grid width %d is below 64", d->width);
+        if (2 * d->radius + 1 > std::min(d->width, d->height))
+            return fail(SF_EINVAL, "periodic grid %d x %d is narrower than the %d-su window",
+                        d->width, d->height, 2 * d->radius + 1);
+        for (int64_t c = 0; c < n; ++c)
+            if (d->obstacle[c] || d->exit[c])
+                return fail(SF_EINVAL, "periodic scene has an obstacle or exit at su %lld",
+                            (long long)c);
+        return SF_OK;
+    }
     int64_t exits = 0;
     for (int64_t c = 0; c < n; ++c) {
         if (d->exit[c]) {
@@ -308,6 +331,16 @@ int build_statics(sf_scene *s, const uint8_t *h_obst, const uint8_t *h_exit)
 {
     const int W = s->W, H = s->H, n = W * H;
     hipStream_t st = s->stream;
+    if (s->periodic) {
+        // a torus without obstacles or openings: no static field
+        SF_HIP(sf::launch_fill_i32(s->D, (size_t)n, 0, st), "destination field");
+        SF_HIP(sf::launch_fill_i32(reinterpret_cast<int32_t *>(s->S), (size_t)n, 0, st),
+               "static field");
+        SF_HIP(hipMemcpyAsync(s->exitm, h_exit, (size_t)n, hipMemcpyHostToDevice, st),
+               "copy exits");
+        SF_HIP(hipStreamSynchronize(st), "statics sync");
+        return SF_OK;
+    }
     uint8_t *obst = nullptr;
     unsigned int *active = nullptr;
     unsigned long long *obits = nullptr, *vis[2] = {nullptr, nullptr},
@@ -406,6 +439,14 @@ int upload_positions(sf_scene *s, const int32_t *pos)
         pint[(size_t)i] = (int32_t)(keyed[(size_t)i] >> 32);
     }
     s->h_ext = order;
+    if (N && s->heading) {
+        std::vector<uint8_t> hint((size_t)N);
+        for (int i = 0; i < N; ++i) hint[(size_t)i] = s->h_heading[(size_t)order[(size_t)i]];
+        SF_HIP(hipMemcpyAsync(s->heading, hint.data(), (size_t)N, hipMemcpyHostToDevice,
+                              s->stream),
+               "copy headings");
+        SF_HIP(hipStreamSynchronize(s->stream), "headings sync");
+    }
     if (N) {
         SF_HIP(hipMemcpyAsync(s->pos, pint.data(), (size_t)N * sizeof(int32_t),
                               hipMemcpyHostToDevice, s->stream),
@@ -472,6 +513,9 @@ int create(const sf_scene_desc *d, void *hip_stream, sf_scene **out)
     s->w_dest = d->w_dest;
     s->seed = d->seed;
     s->start_step = d->start_step;
+    s->periodic = d->periodic != 0;
+    s->w_heading = d->w_heading;
+    if (d->heading && s->N) s->h_heading.assign(d->heading, d->heading + s->N);
     s->stream = static_cast<hipStream_t>(hip_stream);
     s->own_stream = s->stream;
     SF_HIP(hipGetDevice(&s->device), "hipGetDevice");
@@ -531,6 +575,7 @@ int create(const sf_scene_desc *d, void *hip_stream, sf_scene **out)
         (rc = dalloc(s, &s->flags, (N + 3) & ~(size_t)3, "flags")) ||
         (rc = dalloc(s, &s->ctr, sf::kCtrWords, "counters")))
         return rc;
+    if (!s->h_heading.empty() && (rc = dalloc(s, &s->heading, N, "headings"))) return rc;
 
     hipStream_t st = s->stream;
     SF_HIP(sf::launch_fill_u64(s->claim, n, ~0ull, st), "clear claims");
@@ -586,6 +631,10 @@ int setup_launches(sf_scene *s)
     v.flags = s->flags;
     v.exitm = s->exitm;
     v.ext = s->ext;
+    v.periodic = s->periodic ? 1 : 0;
+    v.heading = s->heading;
+    v.hw_axis = (float)s->w_heading;
+    v.hw_diag = (float)(s->w_heading / std::sqrt(2.0));
     sf::set_view_layout(v, s->lc, s->tab);
     s->fl = sf::field_launch_for(s->lc);
     // one strip per item: workgroup b takes strips b, b + grid, ...

@@ -114,6 +114,12 @@ struct SceneView {
     uint8_t *flags;
     const uint8_t *exitm;
     const int32_t *ext;
+    // periodic boundary (both axes wrap) and per-pedestrian headings (by
+    // internal id, NULL: none) with the FP32 heading weights fl32(w_h) and
+    // fl32(w_h / sqrt 2) of aligned and 45-degree moves
+    int32_t periodic;
+    const uint8_t *heading;
+    float hw_axis, hw_diag;
     // incremental field update (NULL: the field is recomputed every tick):
     // bitmaps of the su the tick's winners left and entered, set by commit,
     // read by the field update, cleared by the next tick's decide

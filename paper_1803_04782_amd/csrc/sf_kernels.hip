@@ -508,7 +508,7 @@ __device__ __forceinline__ void gather_one(V *acc, int a)
 // The part of a scene's view that the field kernel reads, kept in scalar
 // registers (a whole SceneView copy would be placed in private memory).
 struct FieldScene {
-    int W, H, wpr, R, tiles_x, copy_elems, stride, padx, pady, max_row, tab_elems;
+    int W, H, wpr, R, tiles_x, copy_elems, stride, padx, pady, max_row, tab_elems, periodic;
     gptr<const VecOf<4>::type> tab;
     gptr<const float> S;
     gptr<float> P;
@@ -529,11 +529,37 @@ __device__ __forceinline__ FieldScene field_scene(const SceneView &v)
     f.pady = v.pady;
     f.max_row = v.max_row;
     f.tab_elems = v.tab_elems;
+    f.periodic = v.periodic;
     f.tab = to_global(reinterpret_cast<const VecOf<4>::type *>(v.tab));
     f.S = to_global(v.S);
     f.P = to_global(v.P);
     f.occ = to_global(v.occ);
     return f;
+}
+
+// `n` (1..64) bits of a bitmap row starting at column s, s + n <= W.
+__device__ __forceinline__ unsigned long long row_bits(gptr<const unsigned long long> row, int s,
+                                                       int n, int wpr)
+{
+    const int w = s >> 6, b = s & 63;
+    unsigned long long v = row[w] >> b;
+    if (b != 0 && w + 1 < wpr) v |= row[w + 1] << (64 - b);
+    return n == 64 ? v : v & ((1ull << n) - 1ull);
+}
+
+// Word w of a periodic row seen without wrapping: bit j is the su at column
+// (64 w + j) mod W (W >= 64, so the 64 columns cross the seam at most once).
+__device__ __forceinline__ unsigned long long wrapped_word(gptr<const unsigned long long> row,
+                                                           int w, int W, int wpr)
+{
+    const int x0 = w * 64;
+    if (x0 >= 0 && x0 + 64 <= W) return row[w];
+    int s = x0 % W;
+    s += s < 0 ? W : 0;
+    const int n1 = min(64, W - s);
+    unsigned long long v = row_bits(row, s, n1, wpr);
+    if (n1 < 64) v |= row_bits(row, 0, 64 - n1, wpr) << n1;
+    return v;
 }
 
 // Work items of a field launch.  MULTI: items[i] from the table and the
@@ -605,6 +631,9 @@ __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
     load_table(v);
 
     // Strip geometry: halo rows [ya, ya + nr), halo bitmap words [wa, wa + nwd).
+    // On a periodic scene the halo is not clipped: rows and columns outside
+    // the grid are those across the opposite edge (coordinates stay unwrapped,
+    // so every source's offset from a lane is its nearest image).
     struct Strip {
         int X0, Y0, ya, nr, xa, xb, wa, nwd;
     };
@@ -613,11 +642,18 @@ __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
         const int ty = ts / s.tiles_x, tx = ts - ty * s.tiles_x;
         g.X0 = tx * TW;
         g.Y0 = ty * WT;
-        g.ya = max(g.Y0 - s.R, 0);
-        g.nr = min(g.Y0 + WT - 1 + s.R, s.H - 1) - g.ya + 1;
-        g.xa = max(g.X0 - s.R, 0);
-        g.xb = min(g.X0 + TW - 1 + s.R, s.W - 1);
-        g.wa = g.xa >> 6;
+        if (s.periodic) {
+            g.ya = g.Y0 - s.R;
+            g.nr = min(g.Y0 + WT - 1, s.H - 1) + s.R - g.ya + 1;
+            g.xa = g.X0 - s.R;
+            g.xb = min(g.X0 + TW - 1, s.W - 1) + s.R;
+        } else {
+            g.ya = max(g.Y0 - s.R, 0);
+            g.nr = min(g.Y0 + WT - 1 + s.R, s.H - 1) - g.ya + 1;
+            g.xa = max(g.X0 - s.R, 0);
+            g.xb = min(g.X0 + TW - 1 + s.R, s.W - 1);
+        }
+        g.wa = g.xa >> 6;  // floor, also for the negative columns of a periodic halo
         g.nwd = (g.xb >> 6) - g.wa + 1;
         return g;
     };
@@ -628,10 +664,20 @@ __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
         n0 = n1 = n2 = 0;
         const Strip g = strip(s, ts);
         if (tid < g.nr) {
-            const gptr<const unsigned long long> row = s.occ + (size_t)(g.ya + tid) * s.wpr + g.wa;
-            n0 = row[0];
-            if (g.nwd > 1) n1 = row[1];
-            if (g.nwd > 2) n2 = row[2];
+            if (s.periodic) {
+                int y = (g.ya + tid) % s.H;
+                y += y < 0 ? s.H : 0;
+                const gptr<const unsigned long long> row = s.occ + (size_t)y * s.wpr;
+                n0 = wrapped_word(row, g.wa, s.W, s.wpr);
+                if (g.nwd > 1) n1 = wrapped_word(row, g.wa + 1, s.W, s.wpr);
+                if (g.nwd > 2) n2 = wrapped_word(row, g.wa + 2, s.W, s.wpr);
+            } else {
+                const gptr<const unsigned long long> row =
+                    s.occ + (size_t)(g.ya + tid) * s.wpr + g.wa;
+                n0 = row[0];
+                if (g.nwd > 1) n1 = row[1];
+                if (g.nwd > 2) n2 = row[2];
+            }
         }
     };
     fetch_rows(v, t);
@@ -925,33 +971,71 @@ __global__ __launch_bounds__(kDecideThreads) void k_decide_claim(
     const int p = i < N ? to_global((const int32_t *)v.pos)[i] : -1;
     if (p >= 0) {
         const uint32_t eid = (uint32_t)to_global((const int32_t *)v.ext)[i];
+        const int h = v.heading ? (int)to_global(v.heading)[i] : 0;
         const int y = p / W, x = p - y * W;
-        const int w = x >> 6, b = x & 63;
         // occupancy of columns x - 1, x, x + 1 in rows y - 1, y, y + 1: bit
-        // (dx + 1) of nb3[dy + 1]
+        // (dx + 1) of nb3[dy + 1]; the field there in pv (+inf on obstacle su
+        // and outside a bounded grid); the su of each in cell[][] (periodic:
+        // wrapped across the edges)
         unsigned int nb3[3];
         float pv[3][3];
+        int col[3], row[3];
+        if (v.periodic) {
+            col[0] = x == 0 ? W - 1 : x - 1;
+            col[1] = x;
+            col[2] = x == W - 1 ? 0 : x + 1;
 #pragma unroll
-        for (int r = 0; r < 3; ++r) {
-            const int yy = y - 1 + r;
-            const bool row_in = yy >= 0 && yy < H;
-            const size_t rw = (size_t)yy * wpr;
-            const unsigned long long mid = row_in ? occ[rw + w] : 0ull;
-            const unsigned long long lft = row_in && b == 0 && w > 0 ? occ[rw + w - 1] : 0ull;
-            const unsigned long long rgt = row_in && b == 63 && w + 1 < wpr ? occ[rw + w + 1] : 0ull;
-            const unsigned int cl = b > 0 ? (unsigned int)(mid >> (b - 1)) & 1u
-                                          : (unsigned int)(lft >> 63);
-            const unsigned int cc = (unsigned int)(mid >> b) & 1u;
-            const unsigned int cr = b < 63 ? (unsigned int)(mid >> (b + 1)) & 1u
-                                           : (unsigned int)rgt & 1u;
-            nb3[r] = cl | (cc << 1) | (cr << 2);
-            // P is +inf on obstacle su; outside the grid reads +inf too
+            for (int r = 0; r < 3; ++r) {
+                int yy = y - 1 + r;
+                yy += yy < 0 ? H : (yy >= H ? -H : 0);
+                row[r] = yy;
+                const size_t rw = (size_t)yy * wpr;
+                unsigned int m = 0;
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const int xx = x - 1 + c;
-                pv[r][c] = row_in && xx >= 0 && xx < W ? P[(size_t)yy * W + xx] : INFINITY;
+                for (int c = 0; c < 3; ++c) {
+                    m |= (unsigned int)(occ[rw + (col[c] >> 6)] >> (col[c] & 63) & 1ull) << c;
+                    pv[r][c] = P[(size_t)yy * W + col[c]];
+                }
+                nb3[r] = m;
+            }
+        } else {
+            const int w = x >> 6, b = x & 63;
+            col[0] = x - 1;
+            col[1] = x;
+            col[2] = x + 1;
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                const int yy = y - 1 + r;
+                row[r] = yy;
+                const bool row_in = yy >= 0 && yy < H;
+                const size_t rw = (size_t)yy * wpr;
+                const unsigned long long mid = row_in ? occ[rw + w] : 0ull;
+                const unsigned long long lft = row_in && b == 0 && w > 0 ? occ[rw + w - 1] : 0ull;
+                const unsigned long long rgt =
+                    row_in && b == 63 && w + 1 < wpr ? occ[rw + w + 1] : 0ull;
+                const unsigned int cl = b > 0 ? (unsigned int)(mid >> (b - 1)) & 1u
+                                              : (unsigned int)(lft >> 63);
+                const unsigned int cc = (unsigned int)(mid >> b) & 1u;
+                const unsigned int cr = b < 63 ? (unsigned int)(mid >> (b + 1)) & 1u
+                                               : (unsigned int)rgt & 1u;
+                nb3[r] = cl | (cc << 1) | (cr << 2);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const int xx = x - 1 + c;
+                    pv[r][c] = row_in && xx >= 0 && xx < W ? P[(size_t)yy * W + xx] : INFINITY;
+                }
             }
         }
+        // heading term of move d: -w_h cos(45 deg * turn), turn = 0..4
+        const float hw_axis = v.hw_axis, hw_diag = v.hw_diag;
+        auto heading_term = [&](int d) -> float {
+            if (h == 0) return 0.0f;
+            int turn = h > d ? h - d : d - h;
+            turn = turn > 4 ? 8 - turn : turn;
+            return turn == 0 ? -hw_axis
+                             : turn == 1 ? -hw_diag
+                                         : turn == 2 ? 0.0f : turn == 3 ? hw_diag : hw_axis;
+        };
         float lo = pv[1][1], lo2 = INFINITY;
         int best = 0;
 #pragma unroll
@@ -959,7 +1043,7 @@ __global__ __launch_bounds__(kDecideThreads) void k_decide_claim(
             const int r = 1 + kDirY[d], c = 1 + kDirX[d];
             const float pc = pv[r][c];
             if (!((nb3[r] >> c) & 1u) && pc < INFINITY) {
-                const float u = pc - ((d & 1) ? phi_axial : phi_diag);
+                const float u = (pc - ((d & 1) ? phi_axial : phi_diag)) + heading_term(d);
                 if (u < lo) {
                     lo2 = lo;
                     lo = u;
@@ -974,7 +1058,7 @@ __global__ __launch_bounds__(kDecideThreads) void k_decide_claim(
         int tgt = p;
         bool mover = false;
         if (best != 0) {
-            tgt = (y + kDirY[best]) * W + (x + kDirX[best]);
+            tgt = row[1 + kDirY[best]] * W + col[1 + kDirX[best]];
             const uint32_t r = philox_w0(eid, (uint32_t)t, (uint32_t)(t >> 32), 0u,
                                          (uint32_t)seed, (uint32_t)(seed >> 32));
             const unsigned long long kk = ((unsigned long long)r << 32) | eid;

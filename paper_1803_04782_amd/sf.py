@@ -47,7 +47,9 @@ class SceneDesc(ctypes.Structure):
                 ("radius", ctypes.c_int32), ("k", ctypes.c_double), ("alpha", ctypes.c_double),
                 ("k_obs", ctypes.c_double), ("alpha_obs", ctypes.c_double),
                 ("radius_obs", ctypes.c_int32), ("w_dest", ctypes.c_double),
-                ("seed", ctypes.c_uint64), ("start_step", ctypes.c_int64)]
+                ("seed", ctypes.c_uint64), ("start_step", ctypes.c_int64),
+                ("periodic", ctypes.c_int32), ("heading", ctypes.c_void_p),
+                ("w_heading", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -187,14 +189,22 @@ def make_desc(scene, start_step: Optional[int] = None):
     ob = np.ascontiguousarray(scene.obstacle, dtype=np.uint8)
     ex = np.ascontiguousarray(scene.exit, dtype=np.uint8)
     pos = np.ascontiguousarray(scene.pos, dtype=np.int32)
+    hd = getattr(scene, "heading", None)
+    if hd is not None:
+        hd = np.ascontiguousarray(hd, dtype=np.uint8)
+        if hd.shape != pos.shape:
+            raise ValueError(f"heading has {hd.shape[0]} entries for {pos.shape[0]} pedestrians")
     d = SceneDesc(width=int(scene.width), height=int(scene.height), obstacle=_ptr(ob).value,
                   exit=_ptr(ex).value, n_peds=int(pos.shape[0]),
                   pos=_ptr(pos).value if pos.size else None, radius=int(scene.radius),
                   k=float(scene.k), alpha=float(scene.alpha), k_obs=float(scene.k_obs),
                   alpha_obs=float(scene.alpha_obs), radius_obs=int(scene.radius_obs),
                   w_dest=float(scene.w_dest), seed=int(scene.seed) & (2**64 - 1),
-                  start_step=int(scene.start_step if start_step is None else start_step))
-    return d, (ob, ex, pos)
+                  start_step=int(scene.start_step if start_step is None else start_step),
+                  periodic=int(bool(getattr(scene, "periodic", False))),
+                  heading=_ptr(hd).value if hd is not None and hd.size else None,
+                  w_heading=float(getattr(scene, "w_heading", 1.0)))
+    return d, (ob, ex, pos, hd)
 
 
 def _stream_handle(stream):

@@ -115,8 +115,11 @@ def tie_nearby(st, occ, owner, targets) -> bool:
         for dx in (-1, 0, 1):
             for dy in (-1, 0, 1):
                 x, y = qx + dx, qy + dy
+                if st.periodic:
+                    x, y = x % W, y % H
                 if (dx or dy) and 0 <= x < W and 0 <= y < H and owner[y * W + x] >= 0:
-                    if oracle.decide_at(st, occ, y * W + x)[1]:
+                    j = int(owner[y * W + x])
+                    if oracle.decide_at(st, occ, y * W + x, st.heading_of(j))[1]:
                         return True
     return False
 

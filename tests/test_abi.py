@@ -3,6 +3,7 @@ rejects bad descriptors on the host before touching the device."""
 import math
 import os
 import re
+from dataclasses import replace
 
 import numpy as np
 import pytest
@@ -89,6 +90,21 @@ def test_validation_errors(sf):
     ob[free_exit] = 1
     cases["exit on obstacle"] = _mut(obstacle=ob)
     cases["no exit"] = _mut(exit=np.zeros_like(base.exit))
+    hd = np.ones(base.n_peds, np.uint8)
+    hd[3] = 9
+    cases["heading above 8"] = _mut(heading=hd)
+    cases["nan w_heading"] = _mut(w_heading=math.nan)
+    flow = scenes.flow_scene(80, 70, 0.2, 4, radius=3, seed=1)
+    ob = flow.obstacle.copy()
+    ob[5] = 1
+    cases["periodic with obstacle"] = replace(flow, obstacle=ob)
+    ex = flow.exit.copy()
+    ex[5] = 1
+    cases["periodic with exit"] = replace(flow, exit=ex)
+    narrow = scenes.flow_scene(60, 70, 0.2, 4, radius=3, seed=1)
+    cases["periodic narrower than a word"] = narrow
+    cases["periodic window wider than the grid"] = replace(
+        scenes.flow_scene(64, 20, 0.2, 1, radius=3, seed=1), radius=10)
     for name, sc in cases.items():
         rc, msg = sf.create_error(sc)
         assert rc == sf.SF_EINVAL, (name, rc, msg)

@@ -1,0 +1,160 @@
+"""GPU parity of the periodic workload of the paper's experiments (a torus
+with headed flows, section 5) and of headings on bounded scenes.
+
+Bar: field within 1e-5 relative of the oracle's FP64 field at every compared
+tick, no untied mismatch of target, election or position (lockstep protocol
+of parity.py); launch-shape and batch independence bit for bit.  Sizes cover
+a width of exactly one bitmap word, widths and heights off the word and tile
+sizes, radii from the paper's 7x7 window to 33x33, densities 0.2 to 0.9, and
+the full 1000 x 1000, density 0.5, 8-directional scenario on sampled su and
+pedestrians.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1803_04782_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+from parity import FIELD_RTOL, lockstep, sampled_field_err, sampled_outcomes  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def sf():
+    from paper_1803_04782_amd import sf as _sf
+
+    _sf.load()
+    return _sf
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+CASES = [
+    ("100x100-d0.5-k8-R3", lambda: scenes.flow_scene(100, 100, 0.5, 8, radius=3, seed=1), 40),
+    ("130x97-d0.3-k4-R5", lambda: scenes.flow_scene(130, 97, 0.3, 4, radius=5, seed=2), 30),
+    ("64x80-d0.7-k2-R3", lambda: scenes.flow_scene(64, 80, 0.7, 2, radius=3, seed=3), 30),
+    ("200x150-d0.2-k1-R16", lambda: scenes.flow_scene(200, 150, 0.2, 1, radius=16, seed=4), 15),
+    ("300x70-d0.9-k8-R3", lambda: scenes.flow_scene(300, 70, 0.9, 8, radius=3, seed=5), 25),
+]
+
+
+@pytest.mark.parametrize("name,make,ticks", CASES, ids=[c[0] for c in CASES])
+def test_periodic_lockstep(sf, name, make, ticks):
+    sc = make()
+    st = oracle.statics(sc)
+    with sf.GpuScene(sc) as g:
+        rep = lockstep(g, st, sc.start_step, ticks)
+        s = g.stats()
+    _say(f"[periodic] {name}", rep)
+    assert rep.max_field_err <= FIELD_RTOL, rep
+    assert rep.untied == 0, (rep, rep.first_untied)
+    assert s["live"] == sc.n_peds and s["evacuated"] == 0
+
+
+def test_headings_on_a_bounded_scene(sf):
+    sc = scenes.random_scene(150, 120, n_peds=1500, radius=6, seed=12, bernoulli=0.03,
+                             exits=("E", "W"), exit_width=8)
+    rng = np.random.default_rng(0)
+    sc.heading = rng.integers(0, 9, size=sc.n_peds).astype(np.uint8)
+    sc.w_heading = 0.75
+    st = oracle.statics(sc)
+    with sf.GpuScene(sc) as g:
+        rep = lockstep(g, st, sc.start_step, 30)
+    _say("[heading bounded]", rep)
+    assert rep.max_field_err <= FIELD_RTOL, rep
+    assert rep.untied == 0, (rep, rep.first_untied)
+
+
+@pytest.mark.parametrize("h", [1, 2, 3, 7, 8])
+def test_lone_walker_wraps_around(sf, h):
+    W = H = 96
+    x0, y0 = 3, 90
+    sc = scenes.Scene(width=W, height=H, obstacle=np.zeros(W * H, np.uint8),
+                      exit=np.zeros(W * H, np.uint8), pos=np.array([y0 * W + x0], np.int32),
+                      radius=3, periodic=True, heading=np.array([h], np.uint8))
+    dx, dy = oracle.DIRS[h]
+    with sf.GpuScene(sc) as g:
+        for t in (1, 7, 50, 96):
+            g.step(t - g.stats()["step"])
+            x, y = (x0 + t * dx) % W, (y0 + t * dy) % H
+            assert g.positions()[0] == y * W + x, (h, t)
+
+
+def test_periodic_tile_shape_invariance(sf, monkeypatch):
+    sc = scenes.flow_scene(190, 133, 0.4, 8, radius=7, seed=6)
+    out = []
+    for shape in ("16x2x2x8", "32x4x4x4", "8x2x2x4", "16x4x2x4"):
+        monkeypatch.setenv("SF_TILE", shape)
+        with sf.GpuScene(sc) as g:
+            g.step(10)
+            out.append((shape, g.field(), g.positions()))
+    for shape, f, p in out[1:]:
+        assert np.array_equal(f, out[0][1]), shape
+        assert np.array_equal(p, out[0][2]), shape
+
+
+def test_periodic_and_bounded_scenes_in_one_batch(sf):
+    members = [scenes.flow_scene(100, 100, 0.5, 8, radius=3, seed=7),
+               scenes.random_scene(140, 90, n_peds=900, radius=4, seed=8, bernoulli=0.03),
+               scenes.flow_scene(257, 64, 0.3, 4, radius=12, seed=9),
+               scenes.flow_scene(70, 300, 0.6, 2, radius=3, seed=10)]
+    alone = []
+    for sc in members:
+        with sf.GpuScene(sc) as g:
+            g.step(12)
+            alone.append((g.field(), g.positions()))
+    gs = [sf.GpuScene(sc) for sc in members]
+    try:
+        with sf.Batch(gs) as b:
+            b.step(12)
+            b.sync()
+            for j, g in enumerate(gs):
+                assert np.array_equal(g.field(), alone[j][0]), j
+                assert np.array_equal(g.positions(), alone[j][1]), j
+    finally:
+        for g in gs:
+            g.close()
+
+
+def test_periodic_incremental_update(sf):
+    sc = scenes.flow_scene(128, 100, 0.4, 8, radius=4, seed=11)
+    st = oracle.statics(sc)
+    with sf.GpuScene(sc) as g:
+        g.set_field_update(8)
+        rep = lockstep(g, st, sc.start_step, 30)
+    _say("[periodic incremental K=8]", rep)
+    assert rep.max_field_err <= FIELD_RTOL, rep
+    assert rep.untied == 0, (rep, rep.first_untied)
+
+
+def test_paper_scenario_1000_sampled(sf):
+    """1000 x 1000 torus, density 0.5 (500,000 pedestrians), 8-directional
+    flow, 7x7 fields: sampled su and pedestrians from the oracle's point
+    route at three ticks, including su on the seams."""
+    sc = scenes.flow_scene(1000, 1000, 0.5, 8, radius=3, seed=0)
+    st = oracle.statics(sc, with_obstacle_field=False)
+    rng = np.random.default_rng(1)
+    W, H = sc.width, sc.height
+    edge = np.concatenate([np.arange(W), (H - 1) * W + np.arange(W), np.arange(H) * W,
+                           np.arange(H) * W + W - 1])
+    with sf.GpuScene(sc) as g:
+        for t in (0, 1, 25):
+            g.step(t - g.stats()["step"])
+            pos = g.positions()
+            P = g.field()
+            cells = np.concatenate([rng.choice(W * H, size=300, replace=False),
+                                    rng.choice(edge, size=100, replace=False)])
+            err = sampled_field_err(st, sc.obstacle, pos, P, cells)
+            assert err <= FIELD_RTOL, (t, err)
+            on_edge = np.flatnonzero(np.isin(pos, edge))
+            ids = np.concatenate([rng.choice(len(pos), size=60, replace=False),
+                                  rng.choice(on_edge, size=40, replace=False)])
+            g.step(1)
+            tgt_g, flags_g = g.last_moves()
+            bad = sampled_outcomes(st, sc.exit, pos, t, ids, tgt_g, flags_g, g.positions())
+            assert not bad, (t, bad[:5])
+            _say(f"[paper 1000^2] t={t} field err {err:.2e} ok")
+        assert g.stats()["live"] == sc.n_peds
