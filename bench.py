@@ -21,6 +21,12 @@ loop of per-scene ticks and once as a batch (one decide, commit and field
 launch per tick for all scenes, graph replays, autotuned tiling), with both
 results checked to be identical and a lockstep tick of the smallest scenes
 against the oracle.
+
+--workload flow1000 runs the paper's own experiment scenario (section 5,
+Table IV): a 1000x1000 torus, density 0.5, 8-directional flow, 7x7 fields,
+1000 ticks, with the paper's time quoted beside it as context; --workload
+flow-sweep runs its 360-combination grid (sides 100..1000, densities
+0.1..0.9, 1/2/4/8 directions).
 """
 from __future__ import annotations
 
@@ -53,6 +59,8 @@ def window_contributions(sc) -> float:
     the grid and the pedestrian's window, own su excluded, at the initial
     positions."""
     W, H, R = sc.width, sc.height, sc.radius
+    if getattr(sc, "periodic", False):
+        return float((2 * R + 1) ** 2 - 1)  # a torus: every window is whole
     x = sc.pos % W
     y = sc.pos // W
     wx = np.minimum(x + R, W - 1) - np.maximum(x - R, 0) + 1
@@ -220,6 +228,67 @@ def bench_ensemble(args, stream, steps=None, emit=True):
     return out
 
 
+# The paper's time for the same scenario (Table IV, 7x7 fields; 1000 ticks per
+# reported run), on a GPU it does not name and with its own field laws: context
+# only, not a target.
+PAPER_FLOW1000 = {"seconds_per_1000_ticks": 62.0, "ms_per_tick": 62.0,
+                  "pedestrian_steps_per_s": 500000 / 0.062,
+                  "hardware": "unnamed GPU (OpenCL), FP32", "source": "Table IV, 7x7 column"}
+
+
+def bench_flow_sweep(args, stream):
+    """The paper's experiment grid (section 5): tori of 100^2 .. 1000^2 su,
+    density 0.1 .. 0.9, 1/2/4/8-directional flows, 7x7 fields, `steps` ticks
+    each (default 1000).  Prints one JSON line: aggregate pedestrian-steps/s
+    and the ms per tick of every combination."""
+    import torch
+
+    from paper_1803_04782_amd import scenes, sf
+
+    def say(*a):
+        print("[bench]", *a, file=sys.stderr, flush=True)
+
+    steps = args.steps if args.steps is not None else 1000
+    sides = [int(v) for v in args.sweep_sides.split(",")]
+    dens = [float(v) for v in args.sweep_densities.split(",")]
+    dirs = [int(v) for v in args.sweep_directions.split(",")]
+    rows = []
+    total_ps, total_t = 0, 0.0
+    for n in sides:
+        for d in dens:
+            for k in dirs:
+                sc = scenes.flow_scene(n, n, d, k, radius=3, seed=0, steps=steps)
+                g = sf.GpuScene(sc, stream=stream)
+                try:
+                    g.step(5)
+                    g.set_state(sc.pos, 0)
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    g.step(steps)
+                    torch.cuda.synchronize()
+                    dt = time.perf_counter() - t0
+                    ps = g.stats()["ped_steps"]
+                    moved = g.stats()["moved"]
+                finally:
+                    g.close()
+                total_ps += ps
+                total_t += dt
+                rows.append({"side": n, "density": d, "directions": k, "pedestrians": sc.n_peds,
+                             "ms_per_tick": 1000.0 * dt / steps, "pedestrian_steps_per_s": ps / dt,
+                             "moved_fraction": moved / max(ps, 1)})
+            say(f"side {n} density {d:g}: " + ", ".join(
+                f"k{r['directions']} {r['ms_per_tick']:.4f} ms" for r in rows[-len(dirs):]))
+    out = {"metric": METRIC, "value": total_ps / total_t, "unit": "pedestrian-steps/s",
+           "n_gpus": 1, "steps": steps, "warmup": 5,
+           "ms_per_step": 1000.0 * total_t / (steps * len(rows)), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "flow-sweep", "sides": sides, "densities": dens,
+                      "directions": dirs, "radius": 3, "periodic": True, "ticks": steps,
+                      "combinations": len(rows), "parallelism": "single-gpu"},
+           "runs": rows, "paper_context": PAPER_FLOW1000, "roofline": None, "cpu_baseline": None}
+    print(json.dumps(out), flush=True)
+
+
 def bench_serving(args, stream):
     """Serving loop under Poisson arrivals at several rates."""
     import torch
@@ -272,7 +341,8 @@ def main():
                     help="timed ticks (default: the workload's own tick count)")
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="hall1024",
-                    choices=["hall1024", "room64", "plaza8192", "ensemble256", "serving"])
+                    choices=["hall1024", "room64", "plaza8192", "flow1000", "flow-sweep",
+                             "ensemble256", "serving"])
     ap.add_argument("--scenes", type=int, default=256, help="ensemble size (ensemble256)")
     ap.add_argument("--rates", default="50,200,800", help="arrival rates per s (serving)")
     ap.add_argument("--serve-seconds", type=float, default=30.0,
@@ -284,6 +354,11 @@ def main():
     ap.add_argument("--max-scenes", type=int, default=256, help="resident slots (serving)")
     ap.add_argument("--pool", type=int, default=64, help="request pool size (serving)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--sweep-sides", default="100,200,300,400,500,600,700,800,900,1000",
+                    help="flow-sweep: torus sides")
+    ap.add_argument("--sweep-densities", default="0.1,0.2,0.3,0.4,0.5,0.6,0.7,0.8,0.9",
+                    help="flow-sweep: pedestrians per su")
+    ap.add_argument("--sweep-directions", default="1,2,4,8", help="flow-sweep: flow directions")
     ap.add_argument("--field-update", type=int, default=0,
                     help="K >= 2: incremental field update with a full superposition every K "
                          "ticks (sf_set_field_update); 0 = full superposition every tick")
@@ -322,6 +397,9 @@ def main():
         return
     if args.workload == "serving":
         bench_serving(args, stream)
+        return
+    if args.workload == "flow-sweep":
+        bench_flow_sweep(args, stream)
         return
     sc = scenes.WORKLOADS[args.workload]()
     if args.steps is None:
@@ -394,6 +472,9 @@ def main():
                                            "ticks": args.steps, "parallelism": "single-gpu"},
            "su_field_updates_per_s": su_updates, "kernels": ktimes, "roofline": roofline,
            "stats": s}
+    if args.workload == "flow1000":
+        out["config"].update({"periodic": True, "density": 0.5, "directions": 8})
+        out["paper_context"] = PAPER_FLOW1000
     if not args.no_cpu:
         base, gate = cpu_baseline(sc, (pos_g, P_g, t_g, tgt_g, flags_g, pos_next),
                                   args.cpu_seconds)

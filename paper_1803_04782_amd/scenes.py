@@ -198,7 +198,14 @@ def plaza8192() -> Scene:
                        name="plaza8192")
 
 
-WORKLOADS = {"room64": room64, "hall1024": hall1024, "plaza8192": plaza8192}
+def flow1000() -> Scene:
+    """The paper's baseline experiment scenario: 1000x1000 torus, density 0.5
+    (500,000 pedestrians), 8-directional flow, 7x7 fields, 1000 ticks, seed 0."""
+    return replace(flow_scene(1000, 1000, 0.5, 8, radius=3, seed=0, steps=1000), name="flow1000")
+
+
+WORKLOADS = {"room64": room64, "hall1024": hall1024, "plaza8192": plaza8192,
+             "flow1000": flow1000}
 
 
 def ensemble(n_scenes: int = 256, seed: int = 3, side=(128, 2048), steps: int = 300):
