@@ -90,6 +90,9 @@ struct sf_scene {
     // the field work items and the launch sizes
     SceneView view = {};
     int strips_per_block = 1;  // field: strips per work item (items dealt round robin)
+    // single-scene field launches use the dense small-radius stencil (same
+    // result bit for bit as the gather, which batches keep using)
+    bool dense = false;
     // incremental field update (sf_set_field_update): refresh period, ticks
     // since the last full superposition, the moved bitmaps, the negated
     // stamp copies and the two update views (S = P, sources = moved bitmap)
@@ -291,6 +294,14 @@ int timing_events(sf_scene *s, int k, sf::LaunchEvents *ev)
     return SF_OK;
 }
 
+// One single-scene field launch with view `v` (the scene's own, or an update view).
+hipError_t scene_field(const sf_scene *s, const SceneView &v, hipStream_t st,
+                       const sf::LaunchEvents *ev = nullptr)
+{
+    if (s->dense) return sf::launch_field_dense(v, s->ncu * 8, st, ev);
+    return sf::launch_field_one(s->fl, v, s->strips_per_block, st, ev);
+}
+
 // Occupancy and live count from the current positions, then the
 // field of those positions.  Other counters are left as they are.
 int rebuild_dynamic(sf_scene *s)
@@ -305,7 +316,7 @@ int rebuild_dynamic(sf_scene *s)
     SF_HIP(sf::launch_fill_u64(s->occ, nwords, 0ull, s->stream), "clear occupancy");
     SF_HIP(sf::launch_occ_init(s->pos, s->N, s->occ, s->wpr, s->W, s->ctr, s->stream),
            "occupancy");
-    SF_HIP(sf::launch_field_one(s->fl, s->view, s->strips_per_block, s->stream), "superpose");
+    SF_HIP(scene_field(s, s->view, s->stream), "superpose");
     return SF_OK;
 }
 
@@ -639,6 +650,16 @@ int setup_launches(sf_scene *s)
     s->fl = sf::field_launch_for(s->lc);
     // one strip per item: workgroup b takes strips b, b + grid, ...
     s->strips_per_block = 1;
+    // the dense stencil for small windows in dense crowds: its (2R+1)^2 fmas
+    // per su beat the gather once the crowd fills ~15% of the su
+    s->dense = s->R >= 1 && s->R <= sf::kDenseMaxRadius &&
+               (double)s->N >= 0.15 * (double)s->W * (double)s->H;
+    if (const char *e = std::getenv("SF_FIELD_DENSE")) {
+        // override (speed only: both kernels give the same field bit for bit)
+        const int d = std::atoi(e);
+        if (d == 0) s->dense = false;
+        if (d == 1) s->dense = s->R >= 1 && s->R <= sf::kDenseMaxRadius;
+    }
     return SF_OK;
 }
 
@@ -654,12 +675,12 @@ int enqueue_tick(sf_scene *s)
     if ((rc = timing_events(s, SF_KERNEL_SUPERPOSE, &ev))) return rc;
     if (s->refresh > 1 && s->since_full + 1 < s->refresh) {
         // P += stamps at the su entered - stamps at the su left this tick
-        SF_HIP(sf::launch_field_one(s->fl, s->view_to, s->strips_per_block, st, &ev), "update");
+        SF_HIP(scene_field(s, s->view_to, st, &ev), "update");
         if ((rc = timing_events(s, SF_KERNEL_SUPERPOSE, &ev))) return rc;
-        SF_HIP(sf::launch_field_one(s->fl, s->view_from, s->strips_per_block, st, &ev), "update");
+        SF_HIP(scene_field(s, s->view_from, st, &ev), "update");
         ++s->since_full;
     } else {
-        SF_HIP(sf::launch_field_one(s->fl, s->view, s->strips_per_block, st, &ev), "superpose");
+        SF_HIP(scene_field(s, s->view, st, &ev), "superpose");
         s->since_full = 0;
     }
     return SF_OK;

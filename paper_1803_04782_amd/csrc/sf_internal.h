@@ -155,6 +155,11 @@ hipError_t launch_field(const FieldLaunch &f, const SceneView *views, const int3
 // min(f.grid, items)); decide and commit launch the scene's own blocks.
 hipError_t launch_field_one(const FieldLaunch &f, const SceneView &view, int per,
                             hipStream_t st, const LaunchEvents *ev = nullptr);
+// Single-scene field by the dense small-radius stencil (radius 1..kDenseMaxRadius),
+// bit-identical to launch_field_one; `grid` caps the persistent workgroups.
+constexpr int kDenseMaxRadius = 4;
+hipError_t launch_field_dense(const SceneView &view, int grid, hipStream_t st,
+                              const LaunchEvents *ev = nullptr);
 hipError_t launch_decide_one(const SceneView &view, hipStream_t st,
                              const LaunchEvents *ev = nullptr);
 hipError_t launch_commit_one(const SceneView &view, hipStream_t st,

@@ -908,6 +908,111 @@ __global__ void k_occ_init(const int32_t *__restrict__ pos, int N, unsigned long
     block_sum_add(p >= 0 ? 1u : 0u, ctr, kLive);
 }
 
+// ---- small-radius field: dense stencil over the occupancy bits -------------------
+//
+// With a small window and a dense crowd most of the gather's adds are the zero
+// padding of its stamp.  This kernel walks the (2R+1)^2 offsets of every su
+// instead.  Lane l owns column X0 + l of a 64-column tile and HL consecutive
+// rows; per window row it cuts its 2R+1 occupancy bits out of the row's three
+// words around the tile (the same words for the whole wave) and per offset
+// adds phi when the bit is set, as acc = fma(bit, phi, acc) with phi the
+// stamp's FP32 value (uniform across the wave).  The offsets are taken
+// source row by source row, top to bottom, and west to east within a row:
+// the row-major source order in which the gather adds them, so the field is
+// bit-identical to the gather's (adding a zero leaves the sum unchanged).
+
+constexpr int kDenseHL = 8;       // rows per lane
+constexpr int kDenseWaves = 4;    // waves per workgroup (tile: 64 x 32 su)
+
+template <int R>
+__global__ __launch_bounds__(kDenseWaves * 64) void k_field_dense(SceneView one, int n_tiles)
+{
+    constexpr int K = 2 * R + 1, NR = kDenseHL + 2 * R;
+    const int W = one.W, H = one.H, wpr = one.wpr;
+    const gptr<const unsigned long long> occ = to_global((const unsigned long long *)one.occ);
+    const gptr<const float> S = to_global(one.S);
+    const gptr<float> P = to_global(one.P);
+    const gptr<const float> tab = to_global(one.tab);
+    const int lane = (int)threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+    // phi(dx, dy) from the first stamp copy: entry (dx + padx) * stride + dy + pady,
+    // held in vector registers (each value serves up to HL fmas per window
+    // row; in scalar registers they would not fit beside the loop's own)
+    float phi[K][K];
+    const int base = opaque_lane((one.padx - R) * one.stride + one.pady - R);
+#pragma unroll
+    for (int a = 0; a < K; ++a)
+#pragma unroll
+        for (int b = 0; b < K; ++b) phi[a][b] = tab[base + a * one.stride + b];
+    const int tiles_x = (W + 63) >> 6;
+    // the tile's window rows: 3 bitmap words (columns X0 - 64 .. X0 + 127) of
+    // rows Y0 - R .. Y0 + TH + R - 1, staged by the whole workgroup at once
+    constexpr int TH = kDenseWaves * kDenseHL, TR = TH + 2 * R;
+    __shared__ unsigned long long rows[TR][3];
+    const int tid = (int)threadIdx.x;
+    for (int t = (int)blockIdx.x; t < n_tiles; t += (int)gridDim.x) {
+        const int ty = t / tiles_x, tx = t - ty * tiles_x;
+        const int x = tx * 64 + lane;
+        const int Y0 = ty * TH, y0 = Y0 + wv * kDenseHL;
+        for (int k = tid; k < TR * 3; k += kDenseWaves * 64) {
+            const int r = k / 3, c = k - r * 3;
+            int sy = Y0 - R + r;
+            unsigned long long wd = 0ull;
+            if (one.periodic) {
+                sy += sy < 0 ? H : (sy >= H ? -H : 0);
+                wd = wrapped_word(occ + (size_t)sy * wpr, tx - 1 + c, W, wpr);
+            } else if (sy >= 0 && sy < H && tx - 1 + c >= 0 && tx - 1 + c < wpr) {
+                wd = occ[(size_t)sy * wpr + tx - 1 + c];
+            }
+            rows[r][c] = wd;
+        }
+        // S of this lane's su, requested before the wait
+        float sv[kDenseHL];
+#pragma unroll
+        for (int h = 0; h < kDenseHL; ++h) {
+            const int y = y0 + h;
+            sv[h] = x < W && y < H ? S[(size_t)y * W + x] : 0.0f;
+        }
+        __syncthreads();
+        if (y0 < H) {  // uniform across the wave
+            float acc[kDenseHL];
+#pragma unroll
+            for (int h = 0; h < kDenseHL; ++h) acc[h] = 0.0f;
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                const unsigned long long wl = rows[wv * kDenseHL + r][0];
+                const unsigned long long wc = rows[wv * kDenseHL + r][1];
+                const unsigned long long wr = rows[wv * kDenseHL + r][2];
+                // bits of columns x - R .. x + R: from bit 64 + lane - R of wl:wc:wr
+                const int p = 64 + lane - R;
+                unsigned long long win;
+                if (p < 64)
+                    win = (wl >> p) | (wc << (64 - p));  // p >= 64 - R > 0
+                else if (p == 64)
+                    win = wc;
+                else
+                    win = (wc >> (p - 64)) | (wr << (128 - p));
+#pragma unroll
+                for (int i = 0; i < K; ++i) {  // source column x - R + i
+                    const float bit = (float)(unsigned int)((win >> i) & 1ull);
+#pragma unroll
+                    for (int h = 0; h < kDenseHL; ++h) {
+                        const int dy = h + R - r;  // output row y0 + h minus source row
+                        if (dy >= -R && dy <= R)
+                            acc[h] = fmaf(bit, phi[2 * R - i][dy + R], acc[h]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int h = 0; h < kDenseHL; ++h) {
+                const int y = y0 + h;
+                if (x < W && y < H) P[(size_t)y * W + x] = sv[h] + acc[h];
+            }
+        }
+        __syncthreads();  // the rows are restaged for the next tile
+    }
+}
+
 // ---- decide + claim (k-2, k-3 registration) --------------------------------------------
 //
 // One thread per pedestrian (internal id i, ids ordered by position at
@@ -1489,6 +1594,21 @@ int field_resident_blocks(int tw, int hl, int vec, int nw, size_t lds_bytes, boo
     SF_LIST_SHAPES(SF_OCC)
 #undef SF_OCC
     return e == hipSuccess ? n : 0;
+}
+
+hipError_t launch_field_dense(const SceneView &view, int grid, hipStream_t st,
+                              const LaunchEvents *ev)
+{
+    const int tiles = ((view.W + 63) / 64) * ((view.H + kDenseWaves * kDenseHL - 1) /
+                                                (kDenseWaves * kDenseHL));
+    const dim3 g((unsigned)std::max(1, std::min(grid, tiles))), b(kDenseWaves * 64);
+    switch (view.R) {
+    case 1: return launch(k_field_dense<1>, g, b, 0, st, ev, view, tiles);
+    case 2: return launch(k_field_dense<2>, g, b, 0, st, ev, view, tiles);
+    case 3: return launch(k_field_dense<3>, g, b, 0, st, ev, view, tiles);
+    case 4: return launch(k_field_dense<4>, g, b, 0, st, ev, view, tiles);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_field_one(const FieldLaunch &f, const SceneView &view, int per,
