@@ -66,8 +66,8 @@ def _load():
     lib.orc_claim_key.restype = u64
     lib.orc_claim_key.argtypes = [i32, i64, u64]
     lib.orc_step.restype = i64
-    lib.orc_step.argtypes = [i32, i32, P, P, P, i32, f64, f64, i32, P, f64, u64, i64, i32, P, P,
-                             P, P]
+    lib.orc_step.argtypes = [i32, i32, P, P, P, i32, f64, f64, i32, P, f64, P, u64, i64, i32, P,
+                             P, P, P]
     lib.orc_field_at.restype = f64
     lib.orc_field_at.argtypes = [i32, i32, P, P, P, f64, i32, f64, f64, i32, f64, f64, i32, i64]
     lib.orc_decide_at.restype = None
@@ -139,6 +139,13 @@ class Statics:
     periodic: bool = False
     heading: Optional[np.ndarray] = None  # uint8 [N] by pedestrian id, or None
     w_heading: float = 1.0
+    walk_period: Optional[np.ndarray] = None  # uint8 [N] by pedestrian id, or None
+
+    def acts(self, i: int, t: int) -> bool:
+        """Whether pedestrian i decides on tick t (walk period)."""
+        if self.walk_period is None or self.walk_period[i] <= 1:
+            return True
+        return (int(t) + int(i)) % int(self.walk_period[i]) == 0
 
     def heading_of(self, i: int) -> int:
         return 0 if self.heading is None else int(self.heading[i])
@@ -166,11 +173,13 @@ def statics(scene, with_obstacle_field: bool = True) -> Statics:
     O = (source_field(W, H, ob, R_obs, scene.k_obs, scene.alpha_obs, periodic)
          if with_obstacle_field else None)
     hd = getattr(scene, "heading", None)
+    wp = getattr(scene, "walk_period", None)
     return Statics(W, H, ob, ex, D, O, int(scene.radius), float(scene.k), float(scene.alpha),
                    R_obs, float(scene.k_obs), float(scene.alpha_obs), float(scene.w_dest),
                    int(scene.seed), unreach, periodic,
                    None if hd is None else _c(hd, np.uint8),
-                   float(getattr(scene, "w_heading", 1.0)))
+                   float(getattr(scene, "w_heading", 1.0)),
+                   None if wp is None else _c(wp, np.uint8))
 
 
 def total_field(st: Statics, pos) -> np.ndarray:
@@ -219,8 +228,9 @@ def step(st: Statics, pos, t: int, P: Optional[np.ndarray] = None) -> StepResult
     moved = np.empty(n, dtype=np.uint8)
     tied = np.empty(n, dtype=np.uint8)
     hd = None if st.heading is None else _ptr(st.heading)
+    wp = None if st.walk_period is None else _ptr(st.walk_period)
     left = _load().orc_step(st.W, st.H, _ptr(st.obstacle), _ptr(st.exit), _ptr(P), st.R,
-                            st.k, st.alpha, int(st.periodic), hd, st.w_heading,
+                            st.k, st.alpha, int(st.periodic), hd, st.w_heading, wp,
                             st.seed & (2**64 - 1), int(t), n, _ptr(newpos), _ptr(target),
                             _ptr(moved), _ptr(tied))
     return StepResult(P, target, moved, tied, newpos, int(left))
@@ -276,6 +286,8 @@ def outcome_at(st: Statics, occ: np.ndarray, owner: np.ndarray, pos, i: int, t: 
     """Full tick outcome of pedestrian i from point evaluations only:
     (target, moved, tied).  `owner[c]` is the id at su c or -1."""
     p = int(pos[i])
+    if not st.acts(i, t):
+        return p, False, False
     tgt, tied, _ = decide_at(st, occ, p, st.heading_of(i))
     if tgt == p:
         return tgt, False, tied
@@ -290,7 +302,7 @@ def outcome_at(st: Statics, occ: np.ndarray, owner: np.ndarray, pos, i: int, t: 
         elif not (0 <= x < W and 0 <= y < H):
             continue
         j = int(owner[y * W + x])
-        if j < 0:
+        if j < 0 or not st.acts(j, t):
             continue
         tj = tgt if j == i else decide_at(st, occ, y * W + x, st.heading_of(j))[0]
         if tj != tgt:

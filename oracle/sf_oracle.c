@@ -52,6 +52,11 @@
  *                  8 - |h - d|) degrees and the cosine is one of 1, 1/sqrt2, 0,
  *                  -1/sqrt2, -1; the FP32 decision uses fl32(w_h) and
  *                  fl32(w_h / sqrt2) with the cosine's sign.
+ *   walk period    pedestrian i may carry a walk period p_i >= 1 (section 5:
+ *                  speed 1/p_i su per tick): it acts only on ticks t with
+ *                  (t + i) mod p_i = 0; on the others it stays without
+ *                  deciding or registering (it still occupies its su and
+ *                  spreads its field).
  *
  * Direction list: e0 = (0,0) stay, e1 = (1,0), e2 = (1,1), e3 = (0,1),
  * e4 = (-1,1), e5 = (-1,0), e6 = (-1,-1), e7 = (0,-1), e8 = (1,-1); x is the
@@ -303,9 +308,17 @@ static void decide_one(int W, int H, const uint8_t *obst, const uint8_t *occ,
     *tied = (isfinite(u_lo2) && (u_lo2 - u_lo) <= 1e-5 * scale) ? 1 : 0;
 }
 
+/* Whether pedestrian i acts on tick t (walk period p, NULL or 1: every tick). */
+static int acts(const uint8_t *period, int32_t i, int64_t t)
+{
+    if (!period || period[i] <= 1) return 1;
+    return ((uint64_t)t + (uint64_t)i) % period[i] == 0;
+}
+
 /* One tick from state (pos, t).
  *   P       [W*H]  the step-start total field (orc_total_field of pos)
  *   heading [N]    headings (NULL: none)
+ *   period  [N]    walk periods (NULL: every pedestrian acts every tick)
  *   pos     [N]    in: step-start positions (-1 = evacuated); out: new ones
  *   target  [N]    out: chosen su (own su when staying; -1 when evacuated)
  *   moved   [N]    out: 1 if the pedestrian won its election and moved
@@ -313,8 +326,8 @@ static void decide_one(int W, int H, const uint8_t *obst, const uint8_t *occ,
  * Returns the number of pedestrians that left through an exit this tick. */
 int64_t orc_step(int W, int H, const uint8_t *obst, const uint8_t *exitm, const double *P,
                  int R, double k, double alpha, int periodic, const uint8_t *heading,
-                 double w_h, uint64_t seed, int64_t t, int32_t n_peds, int32_t *pos,
-                 int32_t *target, uint8_t *moved, uint8_t *tied)
+                 double w_h, const uint8_t *period, uint64_t seed, int64_t t, int32_t n_peds,
+                 int32_t *pos, int32_t *target, uint8_t *moved, uint8_t *tied)
 {
     int64_t n = (int64_t)W * H;
     uint8_t *occ = (uint8_t *)malloc((size_t)(n > 0 ? n : 1));
@@ -328,6 +341,10 @@ int64_t orc_step(int W, int H, const uint8_t *obst, const uint8_t *exitm, const 
         tied[i] = 0;
         target[i] = -1;
         if (pos[i] < 0) continue;
+        if (!acts(period, i, t)) {
+            target[i] = pos[i]; /* resting this tick */
+            continue;
+        }
         decide_one(W, H, obst, occ, P, phi_axial, phi_diag, periodic, heading ? heading[i] : 0,
                    w_h, pos[i], &target[i], &tied[i]);
     }

@@ -59,6 +59,7 @@ class Scene:
     periodic: bool = False  # both axes wrap (a torus; no walls or exits)
     heading: Optional[np.ndarray] = None  # uint8 [N]: direction index 1..8, 0 = none
     w_heading: float = 1.0  # weight of the heading slope
+    walk_period: Optional[np.ndarray] = None  # uint8 [N]: acts on ticks t with (t+id) % p == 0
 
     @property
     def n_peds(self) -> int:
@@ -235,12 +236,14 @@ FLOW_HEADINGS = {1: (1,), 2: (1, 5), 4: (1, 3, 5, 7), 8: (1, 2, 3, 4, 5, 6, 7, 8
 
 
 def flow_scene(width: int, height: int, density: float, directions: int, *, radius: int = 3,
-               seed: int = 0, steps: int = 1000, w_heading: float = 1.0) -> Scene:
+               seed: int = 0, steps: int = 1000, w_heading: float = 1.0,
+               max_walk_period: int = 1) -> Scene:
     """The paper's experiment workload: a width x height torus (periodic
     boundary, no obstacles or exits), round(density * su) pedestrians drawn
     uniformly without replacement, split evenly over the `directions` (1, 2,
     4 or 8) headings in random order, fields of half-width `radius` (3: the
-    7x7 geometry), `steps` ticks."""
+    7x7 geometry), `steps` ticks; walk periods uniform in 1..max_walk_period
+    (1: everyone acts every tick)."""
     if directions not in FLOW_HEADINGS:
         raise ValueError(f"directions must be one of {sorted(FLOW_HEADINGS)}")
     rng = np.random.Generator(np.random.PCG64([seed, width, height, directions]))
@@ -249,11 +252,15 @@ def flow_scene(width: int, height: int, density: float, directions: int, *, radi
     pos = np.sort(rng.choice(n, size=N, replace=False)).astype(np.int32)
     hs = np.array(FLOW_HEADINGS[directions], dtype=np.uint8)
     heading = rng.permutation(np.resize(hs, N)).astype(np.uint8)
+    seed_sc = int(rng.integers(0, 2**63 - 1))
+    walk = None
+    if max_walk_period > 1:
+        walk = np.random.Generator(np.random.PCG64([seed, 7, max_walk_period])).integers(
+            1, max_walk_period + 1, size=N).astype(np.uint8)
     return Scene(width=width, height=height, obstacle=np.zeros(n, np.uint8),
-                 exit=np.zeros(n, np.uint8), pos=pos, radius=radius,
-                 seed=int(rng.integers(0, 2**63 - 1)), steps=steps,
+                 exit=np.zeros(n, np.uint8), pos=pos, radius=radius, seed=seed_sc, steps=steps,
                  name=f"flow{width}x{height}d{density:g}k{directions}", periodic=True,
-                 heading=heading, w_heading=w_heading)
+                 heading=heading, w_heading=w_heading, walk_period=walk)
 
 
 def random_scene(width: int, height: int, n_peds: int, radius: int, seed: int, *,

@@ -155,3 +155,57 @@ def test_dense_flow_invariants():
         assert np.all(occ[r.target[mv]] == 0)
         assert np.array_equal(r.moved == 1, r.pos != pos)
         pos = r.pos
+
+
+@pytest.mark.parametrize("p", [2, 3, 5])
+def test_walk_period_closed_form(p):
+    """Two lone walkers (ids 0 and 1, period p, heading east) on an empty
+    torus: id i moves exactly on the ticks t with (t + i) mod p = 0."""
+    W, H = 40, 30
+    start = np.array([5 * W + 3, 20 * W + 3], np.int32)
+    sc = scenes.Scene(width=W, height=H, obstacle=np.zeros(W * H, np.uint8),
+                      exit=np.zeros(W * H, np.uint8), pos=start, radius=2, periodic=True,
+                      heading=np.array([1, 1], np.uint8),
+                      walk_period=np.array([p, p], np.uint8))
+    st = oracle.statics(sc)
+    pos = start.copy()
+    for t in range(3 * p + 2):
+        r = oracle.step(st, pos, t)
+        for i in range(2):
+            acts = (t + i) % p == 0
+            assert r.moved[i] == int(acts) and r.tied[i] == 0
+            assert r.target[i] == (pos[i] + 1 if acts else pos[i])
+        pos = r.pos
+    for i in range(2):
+        moves = sum(1 for t in range(3 * p + 2) if (t + i) % p == 0)
+        assert pos[i] == start[i] + moves
+
+
+def test_walk_period_one_is_no_period():
+    sc = _flow(29, 31, 0.5, 8, 3, seed=13)
+    st0 = oracle.statics(sc)
+    sc.walk_period = np.ones(sc.n_peds, np.uint8)
+    st1 = oracle.statics(sc)
+    pos0 = pos1 = sc.pos.copy()
+    for t in range(6):
+        r0, r1 = oracle.step(st0, pos0, t), oracle.step(st1, pos1, t)
+        for f in ("target", "moved", "tied", "pos"):
+            assert np.array_equal(getattr(r0, f), getattr(r1, f)), f
+        pos0, pos1 = r0.pos, r1.pos
+
+
+def test_resting_pedestrians_do_not_register():
+    sc = scenes.flow_scene(37, 33, 0.4, 4, radius=3, seed=14, max_walk_period=5)
+    st = oracle.statics(sc)
+    assert sc.walk_period.min() == 1 and sc.walk_period.max() == 5
+    pos = sc.pos.copy()
+    ids = np.arange(sc.n_peds)
+    moved_total = 0
+    for t in range(10):
+        r = oracle.step(st, pos, t)
+        rest = (t + ids) % sc.walk_period != 0
+        assert np.all(r.target[rest] == pos[rest])
+        assert np.all(r.moved[rest] == 0) and np.all(r.tied[rest] == 0)
+        moved_total += int(r.moved.sum())
+        pos = r.pos
+    assert moved_total > 0
