@@ -26,7 +26,8 @@ against the oracle.
 Table IV): a 1000x1000 torus, density 0.5, 8-directional flow, 7x7 fields,
 1000 ticks, with the paper's time quoted beside it as context; --workload
 flow-sweep runs its 360-combination grid (sides 100..1000, densities
-0.1..0.9, 1/2/4/8 directions).
+0.1..0.9, 1/2/4/8 directions) and --workload flow-walk its walk-period
+experiment (Table V: flow1000 with periods uniform in 1..max, max = 1..11).
 """
 from __future__ import annotations
 
@@ -289,6 +290,59 @@ def bench_flow_sweep(args, stream):
     print(json.dumps(out), flush=True)
 
 
+# The paper's times for flow1000 with walk periods uniform in 1..max (Table V,
+# current GPU model; seconds per 1000 ticks): context only.
+PAPER_WALK = {1: 62.0, 3: 64.0, 5: 64.0, 7: 63.0, 9: 62.0, 11: 62.0}
+
+
+def bench_flow_walk(args, stream):
+    """flow1000 with walk periods uniform in 1..max for max = 1, 3, ..., 11
+    (the experiment of the paper's Table V); one JSON line with ms per tick
+    per maximal period."""
+    import torch
+
+    from paper_1803_04782_amd import scenes, sf
+
+    steps = args.steps if args.steps is not None else 1000
+    rows = []
+    total_ps, total_t = 0, 0.0
+    for pmax in (1, 3, 5, 7, 9, 11):
+        sc = scenes.flow_scene(1000, 1000, 0.5, 8, radius=3, seed=0, steps=steps,
+                               max_walk_period=pmax)
+        g = sf.GpuScene(sc, stream=stream)
+        try:
+            g.step(5)
+            g.set_state(sc.pos, 0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            g.step(steps)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            st = g.stats()
+        finally:
+            g.close()
+        total_ps += st["ped_steps"]
+        total_t += dt
+        rows.append({"max_walk_period": pmax, "ms_per_tick": 1000.0 * dt / steps,
+                     "pedestrian_steps_per_s": st["ped_steps"] / dt,
+                     "registered_fraction": st["movers"] / max(st["ped_steps"], 1),
+                     "paper_ms_per_tick": PAPER_WALK[pmax]})
+        print(f"[bench] max walk period {pmax}: {rows[-1]['ms_per_tick']:.4f} ms per tick",
+              file=sys.stderr, flush=True)
+    out = {"metric": METRIC, "value": total_ps / total_t, "unit": "pedestrian-steps/s",
+           "n_gpus": 1, "steps": steps, "warmup": 5,
+           "ms_per_step": 1000.0 * total_t / (steps * len(rows)), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "flow-walk", "grid": [1000, 1000], "density": 0.5,
+                      "directions": 8, "radius": 3, "periodic": True, "ticks": steps,
+                      "max_walk_periods": [r["max_walk_period"] for r in rows],
+                      "parallelism": "single-gpu"},
+           "runs": rows, "paper_context": {"source": "Table V, current GPU model",
+                                           "hardware": PAPER_FLOW1000["hardware"]},
+           "roofline": None, "cpu_baseline": None}
+    print(json.dumps(out), flush=True)
+
+
 def bench_serving(args, stream):
     """Serving loop under Poisson arrivals at several rates."""
     import torch
@@ -342,7 +396,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="hall1024",
                     choices=["hall1024", "room64", "plaza8192", "flow1000", "flow-sweep",
-                             "ensemble256", "serving"])
+                             "flow-walk", "ensemble256", "serving"])
     ap.add_argument("--scenes", type=int, default=256, help="ensemble size (ensemble256)")
     ap.add_argument("--rates", default="50,200,800", help="arrival rates per s (serving)")
     ap.add_argument("--serve-seconds", type=float, default=30.0,
@@ -400,6 +454,9 @@ def main():
         return
     if args.workload == "flow-sweep":
         bench_flow_sweep(args, stream)
+        return
+    if args.workload == "flow-walk":
+        bench_flow_walk(args, stream)
         return
     sc = scenes.WORKLOADS[args.workload]()
     if args.steps is None:

@@ -90,6 +90,10 @@ typedef struct {
                                  its value (staying: 0).  NULL = no headings;
                                  copied                                          */
     double w_heading;         /* weight of the heading term                       */
+    const uint8_t *walk_period; /* [n_peds] per pedestrian, >= 1: pedestrian i acts
+                                 only on ticks t with (t + i) mod p_i = 0 and rests
+                                 (stays, registers for nothing) on the others.
+                                 NULL = every pedestrian acts every tick; copied */
 } sf_scene_desc;
 
 /* Running totals of a scene. */
@@ -122,7 +126,8 @@ typedef struct {
  * stream).  Blocks until the scene is ready.  Errors: SF_EINVAL (bad sizes,
  * pointers, radius, non-finite parameters, exit on an obstacle, no exit,
  * pedestrian out of range / on an obstacle or exit / duplicated, heading
- * above 8; periodic: an obstacle or exit su, width < 64, 2R+1 above a side),
+ * above 8, walk period 0; periodic: an obstacle or exit su, width < 64, 2R+1
+ * above a side),
  * SF_EUNREACHABLE (a free su cannot reach an exit), SF_ENOMEM, SF_EDEVICE.
  * On error *out is NULL. */
 int sf_create_scene(const sf_scene_desc *desc, void *hip_stream, sf_scene **out);

@@ -64,6 +64,7 @@ struct sf_scene {
     bool periodic = false;
     double w_heading = 1;
     std::vector<uint8_t> h_heading;  // by caller id; empty: no headings
+    std::vector<uint8_t> h_walk;     // walk periods by caller id; empty: none
     int device = 0;
     hipStream_t stream = nullptr;
     int ncu = 0;
@@ -84,6 +85,7 @@ struct sf_scene {
     int32_t *ext = nullptr;
     std::vector<int32_t> h_ext;
     uint8_t *heading = nullptr;  // by internal id (NULL: no headings)
+    uint8_t *walk = nullptr;     // walk periods by internal id (NULL: none)
     uint8_t *flags = nullptr;
     unsigned long long *ctr = nullptr;  // see sf::ctr_index
     // what the per-tick kernels read: the view (host copy and device copy),
@@ -229,6 +231,10 @@ int validate(const sf_scene_desc *d)
         for (int i = 0; i < d->n_peds; ++i)
             if (d->heading[i] > 8)
                 return fail(SF_EINVAL, "pedestrian %d has heading %d above 8", i, d->heading[i]);
+    if (d->walk_period)
+        for (int i = 0; i < d->n_peds; ++i)
+            if (d->walk_period[i] == 0)
+                return fail(SF_EINVAL, "pedestrian %d has walk period 0", i);
     const int64_t n = (int64_t)d->width * d->height;
     if (d->periodic) {
         // a torus: the halo words of the field kernel wrap at most once
@@ -450,13 +456,18 @@ int upload_positions(sf_scene *s, const int32_t *pos)
         pint[(size_t)i] = (int32_t)(keyed[(size_t)i] >> 32);
     }
     s->h_ext = order;
+    // per-pedestrian attributes follow the internal order
+    std::vector<uint8_t> hint((size_t)N), wint((size_t)N);
     if (N && s->heading) {
-        std::vector<uint8_t> hint((size_t)N);
         for (int i = 0; i < N; ++i) hint[(size_t)i] = s->h_heading[(size_t)order[(size_t)i]];
         SF_HIP(hipMemcpyAsync(s->heading, hint.data(), (size_t)N, hipMemcpyHostToDevice,
                               s->stream),
                "copy headings");
-        SF_HIP(hipStreamSynchronize(s->stream), "headings sync");
+    }
+    if (N && s->walk) {
+        for (int i = 0; i < N; ++i) wint[(size_t)i] = s->h_walk[(size_t)order[(size_t)i]];
+        SF_HIP(hipMemcpyAsync(s->walk, wint.data(), (size_t)N, hipMemcpyHostToDevice, s->stream),
+               "copy walk periods");
     }
     if (N) {
         SF_HIP(hipMemcpyAsync(s->pos, pint.data(), (size_t)N * sizeof(int32_t),
@@ -527,6 +538,7 @@ int create(const sf_scene_desc *d, void *hip_stream, sf_scene **out)
     s->periodic = d->periodic != 0;
     s->w_heading = d->w_heading;
     if (d->heading && s->N) s->h_heading.assign(d->heading, d->heading + s->N);
+    if (d->walk_period && s->N) s->h_walk.assign(d->walk_period, d->walk_period + s->N);
     s->stream = static_cast<hipStream_t>(hip_stream);
     s->own_stream = s->stream;
     SF_HIP(hipGetDevice(&s->device), "hipGetDevice");
@@ -587,6 +599,7 @@ int create(const sf_scene_desc *d, void *hip_stream, sf_scene **out)
         (rc = dalloc(s, &s->ctr, sf::kCtrWords, "counters")))
         return rc;
     if (!s->h_heading.empty() && (rc = dalloc(s, &s->heading, N, "headings"))) return rc;
+    if (!s->h_walk.empty() && (rc = dalloc(s, &s->walk, N, "walk periods"))) return rc;
 
     hipStream_t st = s->stream;
     SF_HIP(sf::launch_fill_u64(s->claim, n, ~0ull, st), "clear claims");
@@ -644,6 +657,7 @@ int setup_launches(sf_scene *s)
     v.ext = s->ext;
     v.periodic = s->periodic ? 1 : 0;
     v.heading = s->heading;
+    v.walk = s->walk;
     v.hw_axis = (float)s->w_heading;
     v.hw_diag = (float)(s->w_heading / std::sqrt(2.0));
     sf::set_view_layout(v, s->lc, s->tab);

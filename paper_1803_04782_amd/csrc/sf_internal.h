@@ -120,6 +120,9 @@ struct SceneView {
     int32_t periodic;
     const uint8_t *heading;
     float hw_axis, hw_diag;
+    // walk periods by internal id (NULL: none): pedestrian with caller id e
+    // and period p acts on tick t iff (t + e) mod p == 0
+    const uint8_t *walk;
     // incremental field update (NULL: the field is recomputed every tick):
     // bitmaps of the su the tick's winners left and entered, set by commit,
     // read by the field update, cleared by the next tick's decide

@@ -1077,104 +1077,111 @@ __global__ __launch_bounds__(kDecideThreads) void k_decide_claim(
     if (p >= 0) {
         const uint32_t eid = (uint32_t)to_global((const int32_t *)v.ext)[i];
         const int h = v.heading ? (int)to_global(v.heading)[i] : 0;
-        const int y = p / W, x = p - y * W;
-        // occupancy of columns x - 1, x, x + 1 in rows y - 1, y, y + 1: bit
-        // (dx + 1) of nb3[dy + 1]; the field there in pv (+inf on obstacle su
-        // and outside a bounded grid); the su of each in cell[][] (periodic:
-        // wrapped across the edges)
-        unsigned int nb3[3];
-        float pv[3][3];
-        int col[3], row[3];
-        if (v.periodic) {
-            col[0] = x == 0 ? W - 1 : x - 1;
-            col[1] = x;
-            col[2] = x == W - 1 ? 0 : x + 1;
-#pragma unroll
-            for (int r = 0; r < 3; ++r) {
-                int yy = y - 1 + r;
-                yy += yy < 0 ? H : (yy >= H ? -H : 0);
-                row[r] = yy;
-                const size_t rw = (size_t)yy * wpr;
-                unsigned int m = 0;
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    m |= (unsigned int)(occ[rw + (col[c] >> 6)] >> (col[c] & 63) & 1ull) << c;
-                    pv[r][c] = P[(size_t)yy * W + col[c]];
-                }
-                nb3[r] = m;
-            }
+        const unsigned int wp = v.walk ? (unsigned int)to_global(v.walk)[i] : 1u;
+        if (wp > 1u && (t + eid) % wp != 0ull) {
+            // resting this tick: stays, registers for nothing
+            target[i] = p;
+            flags[i] = 0;
         } else {
-            const int w = x >> 6, b = x & 63;
-            col[0] = x - 1;
-            col[1] = x;
-            col[2] = x + 1;
-#pragma unroll
-            for (int r = 0; r < 3; ++r) {
-                const int yy = y - 1 + r;
-                row[r] = yy;
-                const bool row_in = yy >= 0 && yy < H;
-                const size_t rw = (size_t)yy * wpr;
-                const unsigned long long mid = row_in ? occ[rw + w] : 0ull;
-                const unsigned long long lft = row_in && b == 0 && w > 0 ? occ[rw + w - 1] : 0ull;
-                const unsigned long long rgt =
-                    row_in && b == 63 && w + 1 < wpr ? occ[rw + w + 1] : 0ull;
-                const unsigned int cl = b > 0 ? (unsigned int)(mid >> (b - 1)) & 1u
-                                              : (unsigned int)(lft >> 63);
-                const unsigned int cc = (unsigned int)(mid >> b) & 1u;
-                const unsigned int cr = b < 63 ? (unsigned int)(mid >> (b + 1)) & 1u
-                                               : (unsigned int)rgt & 1u;
-                nb3[r] = cl | (cc << 1) | (cr << 2);
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    const int xx = x - 1 + c;
-                    pv[r][c] = row_in && xx >= 0 && xx < W ? P[(size_t)yy * W + xx] : INFINITY;
+            const int y = p / W, x = p - y * W;
+            // occupancy of columns x - 1, x, x + 1 in rows y - 1, y, y + 1: bit
+            // (dx + 1) of nb3[dy + 1]; the field there in pv (+inf on obstacle su
+            // and outside a bounded grid); their rows and columns in row[] and
+            // col[] (periodic: wrapped across the edges)
+            unsigned int nb3[3];
+            float pv[3][3];
+            int col[3], row[3];
+            if (v.periodic) {
+                col[0] = x == 0 ? W - 1 : x - 1;
+                col[1] = x;
+                col[2] = x == W - 1 ? 0 : x + 1;
+    #pragma unroll
+                for (int r = 0; r < 3; ++r) {
+                    int yy = y - 1 + r;
+                    yy += yy < 0 ? H : (yy >= H ? -H : 0);
+                    row[r] = yy;
+                    const size_t rw = (size_t)yy * wpr;
+                    unsigned int m = 0;
+    #pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        m |= (unsigned int)(occ[rw + (col[c] >> 6)] >> (col[c] & 63) & 1ull) << c;
+                        pv[r][c] = P[(size_t)yy * W + col[c]];
+                    }
+                    nb3[r] = m;
+                }
+            } else {
+                const int w = x >> 6, b = x & 63;
+                col[0] = x - 1;
+                col[1] = x;
+                col[2] = x + 1;
+    #pragma unroll
+                for (int r = 0; r < 3; ++r) {
+                    const int yy = y - 1 + r;
+                    row[r] = yy;
+                    const bool row_in = yy >= 0 && yy < H;
+                    const size_t rw = (size_t)yy * wpr;
+                    const unsigned long long mid = row_in ? occ[rw + w] : 0ull;
+                    const unsigned long long lft = row_in && b == 0 && w > 0 ? occ[rw + w - 1] : 0ull;
+                    const unsigned long long rgt =
+                        row_in && b == 63 && w + 1 < wpr ? occ[rw + w + 1] : 0ull;
+                    const unsigned int cl = b > 0 ? (unsigned int)(mid >> (b - 1)) & 1u
+                                                  : (unsigned int)(lft >> 63);
+                    const unsigned int cc = (unsigned int)(mid >> b) & 1u;
+                    const unsigned int cr = b < 63 ? (unsigned int)(mid >> (b + 1)) & 1u
+                                                   : (unsigned int)rgt & 1u;
+                    nb3[r] = cl | (cc << 1) | (cr << 2);
+    #pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        const int xx = x - 1 + c;
+                        pv[r][c] = row_in && xx >= 0 && xx < W ? P[(size_t)yy * W + xx] : INFINITY;
+                    }
                 }
             }
-        }
-        // heading term of move d: -w_h cos(45 deg * turn), turn = 0..4
-        const float hw_axis = v.hw_axis, hw_diag = v.hw_diag;
-        auto heading_term = [&](int d) -> float {
-            if (h == 0) return 0.0f;
-            int turn = h > d ? h - d : d - h;
-            turn = turn > 4 ? 8 - turn : turn;
-            return turn == 0 ? -hw_axis
-                             : turn == 1 ? -hw_diag
-                                         : turn == 2 ? 0.0f : turn == 3 ? hw_diag : hw_axis;
-        };
-        float lo = pv[1][1], lo2 = INFINITY;
-        int best = 0;
-#pragma unroll
-        for (int d = 1; d <= 8; ++d) {
-            const int r = 1 + kDirY[d], c = 1 + kDirX[d];
-            const float pc = pv[r][c];
-            if (!((nb3[r] >> c) & 1u) && pc < INFINITY) {
-                const float u = (pc - ((d & 1) ? phi_axial : phi_diag)) + heading_term(d);
-                if (u < lo) {
-                    lo2 = lo;
-                    lo = u;
-                    best = d;
-                } else if (u < lo2) {
-                    lo2 = u;
+            // heading term of move d: -w_h cos(45 deg * turn), turn = 0..4
+            const float hw_axis = v.hw_axis, hw_diag = v.hw_diag;
+            auto heading_term = [&](int d) -> float {
+                if (h == 0) return 0.0f;
+                int turn = h > d ? h - d : d - h;
+                turn = turn > 4 ? 8 - turn : turn;
+                return turn == 0 ? -hw_axis
+                                 : turn == 1 ? -hw_diag
+                                             : turn == 2 ? 0.0f : turn == 3 ? hw_diag : hw_axis;
+            };
+            float lo = pv[1][1], lo2 = INFINITY;
+            int best = 0;
+    #pragma unroll
+            for (int d = 1; d <= 8; ++d) {
+                const int r = 1 + kDirY[d], c = 1 + kDirX[d];
+                const float pc = pv[r][c];
+                if (!((nb3[r] >> c) & 1u) && pc < INFINITY) {
+                    const float u = (pc - ((d & 1) ? phi_axial : phi_diag)) + heading_term(d);
+                    if (u < lo) {
+                        lo2 = lo;
+                        lo = u;
+                        best = d;
+                    } else if (u < lo2) {
+                        lo2 = u;
+                    }
                 }
             }
+            const float scale = fmaxf(fmaxf(fabsf(lo), fabsf(lo2)), 1.0f);
+            const bool tied = lo2 < INFINITY && (lo2 - lo) <= 1e-5f * scale;
+            int tgt = p;
+            bool mover = false;
+            if (best != 0) {
+                tgt = row[1 + kDirY[best]] * W + col[1 + kDirX[best]];
+                const uint32_t r = philox_w0(eid, (uint32_t)t, (uint32_t)(t >> 32), 0u,
+                                             (uint32_t)seed, (uint32_t)(seed >> 32));
+                const unsigned long long kk = ((unsigned long long)r << 32) | eid;
+                __hip_atomic_fetch_min(&claim[tgt], kk, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                key[i] = kk;
+                mover = true;
+            }
+            target[i] = tgt;
+            flags[i] = (uint8_t)((mover ? kMover : 0u) | (tied ? kTied : 0u));
+            movers += mover;
+            ties += tied;
         }
-        const float scale = fmaxf(fmaxf(fabsf(lo), fabsf(lo2)), 1.0f);
-        const bool tied = lo2 < INFINITY && (lo2 - lo) <= 1e-5f * scale;
-        int tgt = p;
-        bool mover = false;
-        if (best != 0) {
-            tgt = row[1 + kDirY[best]] * W + col[1 + kDirX[best]];
-            const uint32_t r = philox_w0(eid, (uint32_t)t, (uint32_t)(t >> 32), 0u,
-                                         (uint32_t)seed, (uint32_t)(seed >> 32));
-            const unsigned long long kk = ((unsigned long long)r << 32) | eid;
-            __hip_atomic_fetch_min(&claim[tgt], kk, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            key[i] = kk;
-            mover = true;
-        }
-        target[i] = tgt;
-        flags[i] = (uint8_t)((mover ? kMover : 0u) | (tied ? kTied : 0u));
-        movers += mover;
-        ties += tied;
     }
     block_sums_add<2>({(int)movers, (int)ties}, ctr, {kMovers, kTied});
 }

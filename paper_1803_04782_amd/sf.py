@@ -49,7 +49,7 @@ class SceneDesc(ctypes.Structure):
                 ("radius_obs", ctypes.c_int32), ("w_dest", ctypes.c_double),
                 ("seed", ctypes.c_uint64), ("start_step", ctypes.c_int64),
                 ("periodic", ctypes.c_int32), ("heading", ctypes.c_void_p),
-                ("w_heading", ctypes.c_double)]
+                ("w_heading", ctypes.c_double), ("walk_period", ctypes.c_void_p)]
 
 
 class Stats(ctypes.Structure):
@@ -189,11 +189,15 @@ def make_desc(scene, start_step: Optional[int] = None):
     ob = np.ascontiguousarray(scene.obstacle, dtype=np.uint8)
     ex = np.ascontiguousarray(scene.exit, dtype=np.uint8)
     pos = np.ascontiguousarray(scene.pos, dtype=np.int32)
-    hd = getattr(scene, "heading", None)
-    if hd is not None:
-        hd = np.ascontiguousarray(hd, dtype=np.uint8)
-        if hd.shape != pos.shape:
-            raise ValueError(f"heading has {hd.shape[0]} entries for {pos.shape[0]} pedestrians")
+    per_ped = []
+    for name in ("heading", "walk_period"):
+        a = getattr(scene, name, None)
+        if a is not None:
+            a = np.ascontiguousarray(a, dtype=np.uint8)
+            if a.shape != pos.shape:
+                raise ValueError(f"{name} has {a.shape[0]} entries for {pos.shape[0]} pedestrians")
+        per_ped.append(a)
+    hd, wk = per_ped
     d = SceneDesc(width=int(scene.width), height=int(scene.height), obstacle=_ptr(ob).value,
                   exit=_ptr(ex).value, n_peds=int(pos.shape[0]),
                   pos=_ptr(pos).value if pos.size else None, radius=int(scene.radius),
@@ -203,8 +207,9 @@ def make_desc(scene, start_step: Optional[int] = None):
                   start_step=int(scene.start_step if start_step is None else start_step),
                   periodic=int(bool(getattr(scene, "periodic", False))),
                   heading=_ptr(hd).value if hd is not None and hd.size else None,
-                  w_heading=float(getattr(scene, "w_heading", 1.0)))
-    return d, (ob, ex, pos, hd)
+                  w_heading=float(getattr(scene, "w_heading", 1.0)),
+                  walk_period=_ptr(wk).value if wk is not None and wk.size else None)
+    return d, (ob, ex, pos, hd, wk)
 
 
 def _stream_handle(stream):

@@ -94,6 +94,9 @@ def test_validation_errors(sf):
     hd[3] = 9
     cases["heading above 8"] = _mut(heading=hd)
     cases["nan w_heading"] = _mut(w_heading=math.nan)
+    wk = np.ones(base.n_peds, np.uint8)
+    wk[2] = 0
+    cases["walk period 0"] = _mut(walk_period=wk)
     flow = scenes.flow_scene(80, 70, 0.2, 4, radius=3, seed=1)
     ob = flow.obstacle.copy()
     ob[5] = 1

@@ -1,5 +1,6 @@
 """GPU parity of the periodic workload of the paper's experiments (a torus
-with headed flows, section 5) and of headings on bounded scenes.
+with headed flows, section 5), of headings on bounded scenes, and of walk
+periods (pedestrians that act every p-th tick).
 
 Bar: field within 1e-5 relative of the oracle's FP64 field at every compared
 tick, no untied mismatch of target, election or position (lockstep protocol
@@ -158,3 +159,68 @@ def test_paper_scenario_1000_sampled(sf):
             assert not bad, (t, bad[:5])
             _say(f"[paper 1000^2] t={t} field err {err:.2e} ok")
         assert g.stats()["live"] == sc.n_peds
+
+
+WALK_CASES = [
+    ("torus-100x100-k8-wp5", lambda: scenes.flow_scene(100, 100, 0.5, 8, radius=3, seed=21,
+                                                        max_walk_period=5)),
+    ("torus-130x97-k4-wp11", lambda: scenes.flow_scene(130, 97, 0.6, 4, radius=5, seed=22,
+                                                        max_walk_period=11)),
+]
+
+
+@pytest.mark.parametrize("name,make", WALK_CASES, ids=[c[0] for c in WALK_CASES])
+def test_walk_period_lockstep(sf, name, make):
+    sc = make()
+    st = oracle.statics(sc)
+    with sf.GpuScene(sc) as g:
+        rep = lockstep(g, st, sc.start_step, 30)
+    _say(f"[walk period] {name}", rep)
+    assert rep.max_field_err <= FIELD_RTOL, rep
+    assert rep.untied == 0, (rep, rep.first_untied)
+
+
+def test_walk_period_on_a_bounded_scene_and_in_a_batch(sf):
+    sc = scenes.random_scene(160, 110, n_peds=2500, radius=5, seed=23, bernoulli=0.03,
+                             exits=("E", "S"), exit_width=6)
+    rng = np.random.default_rng(5)
+    sc.walk_period = rng.integers(1, 8, size=sc.n_peds).astype(np.uint8)
+    sc.start_step = 17  # the phase of every period depends on the tick index
+    st = oracle.statics(sc)
+    with sf.GpuScene(sc) as g:
+        rep = lockstep(g, st, sc.start_step, 25)
+    _say("[walk period bounded]", rep)
+    assert rep.max_field_err <= FIELD_RTOL, rep
+    assert rep.untied == 0, (rep, rep.first_untied)
+    other = scenes.flow_scene(90, 80, 0.5, 8, radius=3, seed=24, max_walk_period=3)
+    alone = []
+    for s in (sc, other):
+        with sf.GpuScene(s) as g:
+            g.step(9)
+            alone.append(g.positions())
+    gs = [sf.GpuScene(s) for s in (sc, other)]
+    try:
+        with sf.Batch(gs) as b:
+            b.step(9)
+            b.sync()
+            for j, g in enumerate(gs):
+                assert np.array_equal(g.positions(), alone[j]), j
+    finally:
+        for g in gs:
+            g.close()
+
+
+def test_lone_walkers_keep_their_period(sf):
+    W, H, p = 80, 70, 4
+    start = np.array([10 * W + 3, 40 * W + 3, 60 * W + 3], np.int32)
+    sc = scenes.Scene(width=W, height=H, obstacle=np.zeros(W * H, np.uint8),
+                      exit=np.zeros(W * H, np.uint8), pos=start, radius=2, periodic=True,
+                      heading=np.array([1, 1, 1], np.uint8),
+                      walk_period=np.array([p, p, 1], np.uint8))
+    with sf.GpuScene(sc) as g:
+        T = 23
+        g.step(T)
+        pos = g.positions()
+    for i, per in enumerate((p, p, 1)):
+        moves = sum(1 for t in range(T) if (t + i) % per == 0)
+        assert pos[i] == start[i] + moves, (i, pos[i], start[i], moves)
