@@ -137,7 +137,8 @@ int decide_blocks(int N);
 int commit_blocks(int N);
 
 // One field launch over `n_items` work items (int4: scene, first strip,
-// end strip, unused).  Workgroup b takes items b, b + grid, b + 2*grid, ...
+// end strip, unused).  The workgroups on each XCD share a contiguous run of
+// the items (in proportion to their number) round robin.
 // `tab_max` is the largest tab_elems of the launch's scenes and `halo_max`
 // the largest halo row count; both size the dynamic LDS.
 struct FieldLaunch {
@@ -154,8 +155,8 @@ size_t field_lds_bytes(const FieldLaunch &f);
 hipError_t launch_field(const FieldLaunch &f, const SceneView *views, const int32_t *items,
                         int n_items, hipStream_t st, const LaunchEvents *ev = nullptr);
 // Single-scene forms: the view is passed by value.  Field item i is strips
-// [i*per, (i+1)*per) and workgroup b takes items b, b + grid, ... (grid =
-// min(f.grid, items)); decide and commit launch the scene's own blocks.
+// [i*per, (i+1)*per), dealt as above (grid = min(f.grid, items)); decide and
+// commit launch the scene's own blocks.
 hipError_t launch_field_one(const FieldLaunch &f, const SceneView &view, int per,
                             hipStream_t st, const LaunchEvents *ev = nullptr);
 // Single-scene field by the dense small-radius stencil (radius 1..kDenseMaxRadius),

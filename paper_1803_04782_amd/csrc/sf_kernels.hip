@@ -604,8 +604,21 @@ __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
     const int col = lane % TW, rg = lane / TW;
     const int tbase = (int)(uint32_t)(uintptr_t)((lds_ptr<float>)tab);
 
-    int item = (int)blockIdx.x;
-    if (item >= n_items) return;
+    // Work items of one scene by XCD: workgroup b runs on XCD b mod 8 (each
+    // XCD has its own L2).  XCD x owns a contiguous share of the strips, in
+    // proportion to its workgroups, and deals it round robin to them, so that
+    // neighbouring strips (which share the cache lines of S, P and the bitmap
+    // rows) are worked on under one L2.  A batch's items are ordered for load
+    // balance instead and are dealt round robin over the whole grid.
+    const int NG = (int)gridDim.x, xb = (int)blockIdx.x & 7, kb = (int)blockIdx.x >> 3;
+    int gx = NG, item = (int)blockIdx.x, item_end = n_items;
+    if constexpr (!MULTI) {
+        gx = (NG >> 3) + (xb < (NG & 7) ? 1 : 0);           // workgroups on this XCD
+        const int sx = xb * (NG >> 3) + min(xb, NG & 7);    // their first logical index
+        item_end = (int)((long long)(sx + gx) * n_items / NG);
+        item = (int)((long long)sx * n_items / NG) + kb;
+    }
+    if (item >= item_end) return;
     int4 it = work.item(item);
     FieldScene v = work.scene(it.x);
     int t = it.y;
@@ -690,14 +703,14 @@ __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
         int4 nit = it;
         FieldScene nv = v;
         if (nt >= it.z) {
-            nitem = item + (int)gridDim.x;
-            if (nitem < n_items) {
+            nitem = item + gx;
+            if (nitem < item_end) {
                 nit = work.item(nitem);
                 nt = nit.y;
                 if (nit.x != it.x) nv = work.scene(nit.x);
             }
         }
-        const bool more = nitem < n_items;
+        const bool more = nitem < item_end;
 
         const Strip g = strip(v, t);
         const int W = v.W, H = v.H, R = v.R, stride = v.stride, padx = v.padx, pady = v.pady;
