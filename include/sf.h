@@ -23,7 +23,11 @@
  *   - the election of k-3 among the <= 8 registrants of an su keeps the
  *     smallest key (Philox4x32-10(counter = (id, t_lo, t_hi, 0),
  *     key = (seed_lo, seed_hi)).word0 << 32) | id; losers stay;
- *   - entering an exit su removes the pedestrian in the same tick.
+ *   - entering an exit su removes the pedestrian in the same tick;
+ *   - section 5's experiments: a periodic boundary (a torus, no exits),
+ *     headed flows (a heading adds -w_heading*cos(angle(heading, move)) to a
+ *     candidate's value) and walk periods (pedestrian i with period p acts
+ *     on ticks t with (t + i) mod p = 0 only).
  *
  * Conventions.
  *   - Grids are row-major, x fastest; linear su index c = y*width + x.
@@ -39,8 +43,9 @@
  *     scene must not overlap.
  *   - Environment overrides read by sf_create_scene, for tuning only (results
  *     do not depend on them bit for bit): SF_TILE="TWxHLxVECxNW[xCAP]" (field
- *     tile shape and source-list capacity) and SF_FIELD_BLOCKS_PER_CU (field
- *     workgroups per compute unit).
+ *     tile shape and source-list capacity), SF_FIELD_BLOCKS_PER_CU (field
+ *     workgroups per compute unit) and SF_FIELD_DENSE=0/1 (the dense
+ *     small-radius field stencil off / on where the radius allows it).
  */
 #ifndef SF_H
 #define SF_H
