@@ -209,3 +209,25 @@ def test_resting_pedestrians_do_not_register():
         moved_total += int(r.moved.sum())
         pos = r.pos
     assert moved_total > 0
+
+
+@pytest.mark.parametrize("wp", [1, 4])
+def test_point_route_matches_full_grid_on_a_torus(wp):
+    """The point-evaluation route (field at chosen su, one pedestrian's full
+    tick outcome) used to check large GPU runs equals the full-grid tick on
+    a torus with headings and walk periods, seams included."""
+    sc = scenes.flow_scene(21, 17, 0.45, 8, radius=3, seed=15, max_walk_period=wp)
+    st = oracle.statics(sc)
+    W, H = sc.width, sc.height
+    occ = oracle.occupancy(W, H, sc.pos)
+    P = oracle.total_field(st, sc.pos)
+    Pp = oracle.field_at(st, occ, np.arange(W * H))
+    np.testing.assert_allclose(Pp, P, rtol=1e-13, atol=1e-12)
+    owner = np.full(W * H, -1, np.int64)
+    owner[sc.pos] = np.arange(sc.n_peds)
+    for t in (0, 1, 2, 3):
+        r = oracle.step(st, sc.pos, t, P=P)
+        for i in range(sc.n_peds):
+            tgt, mv, tied = oracle.outcome_at(st, occ, owner, sc.pos, i, t)
+            assert tgt == r.target[i] and mv == bool(r.moved[i]) and tied == bool(r.tied[i]), \
+                (t, i)
