@@ -29,7 +29,9 @@ namespace {
 constexpr int kDirX[9] = {0, 1, 1, 0, -1, -1, -1, 0, 1};
 constexpr int kDirY[9] = {0, 0, 1, 1, 1, 0, -1, -1, -1};
 
-constexpr uint8_t kMover = 1u, kWon = 2u, kTied = 4u;
+// per-pedestrian flag bits of the last tick (SF_FLAG_* of the public header);
+// distinct from the running-total ids kMovers, kMoved, kTied
+constexpr uint8_t kFlagMover = 1u, kFlagWon = 2u, kFlagTied = 4u;
 
 // ---- small helpers ------------------------------------------------------------
 
@@ -1191,7 +1193,7 @@ __global__ __launch_bounds__(kDecideThreads) void k_decide_claim(
                 mover = true;
             }
             target[i] = tgt;
-            flags[i] = (uint8_t)((mover ? kMover : 0u) | (tied ? kTied : 0u));
+            flags[i] = (uint8_t)((mover ? kFlagMover : 0u) | (tied ? kFlagTied : 0u));
             movers += mover;
             ties += tied;
         }
@@ -1228,7 +1230,7 @@ __global__ __launch_bounds__(kCommitThreads) void k_commit(SceneView one,
             flags[i] = 0;
         } else {
             was_live = true;
-            if (f & kMover) {
+            if (f & kFlagMover) {
                 // the winner is the only registrant that finds its own key; it
                 // also resets the word, which losers then read as "not mine"
                 const unsigned long long cw = claim[tgt];
@@ -1256,7 +1258,7 @@ __global__ __launch_bounds__(kCommitThreads) void k_commit(SceneView one,
                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                         pos[i] = tgt;
                     }
-                    flags[i] = f | kWon;
+                    flags[i] = f | kFlagWon;
                 }
             }
         }

@@ -203,15 +203,21 @@ def test_stats_consistency(sf):
     sc = scenes.random_scene(90, 70, n_peds=700, radius=4, seed=5, bernoulli=0.02,
                              exits=("E", "W", "N"), exit_width=8)
     with sf.GpuScene(sc) as g:
-        total = 0
+        total = movers = moved = tied = 0
         for _ in range(40):
             total += int((g.positions() >= 0).sum())
             g.step(1)
+            _, flags = g.last_moves()
+            movers += int(((flags & sf.SF_FLAG_MOVER) != 0).sum())
+            moved += int(((flags & sf.SF_FLAG_WON) != 0).sum())
+            tied += int(((flags & sf.SF_FLAG_TIED) != 0).sum())
         s = g.stats()
         assert s["ped_steps"] == total
         assert s["live"] + s["evacuated"] == sc.n_peds
         assert s["live"] == int((g.positions() >= 0).sum())
-        assert s["moved"] <= s["movers"]
+        # the running totals are the sums of the per-tick flags
+        assert (s["movers"], s["moved"], s["tied"]) == (movers, moved, tied)
+        assert tied > 0  # the scene has near ties, so the tie total is exercised
 
 
 @pytest.mark.skipif(os.environ.get("SF_SKIP_PLAZA") == "1", reason="plaza disabled by env")
