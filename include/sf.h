@@ -183,8 +183,9 @@ int sf_sync(const sf_scene *s);
  * a tick adds the stamps at the su its winners entered and subtracts those at
  * the su they left, and every K-th tick the field is superposed in full again
  * (FP32 rounding of the updates accumulates between refreshes).  The update
- * reuses the superposition kernel with the moved pedestrians as sources, so
- * it is deterministic and independent of the launch shape.  Blocks.
+ * is one launch of the superposition kernel with the su entered and the su
+ * left as two source sets, each summed in row-major source order, so it is
+ * deterministic and independent of the launch shape.  Blocks.
  * SF_EINVAL for a negative value or a scene that belongs to a batch. */
 int sf_set_field_update(sf_scene *s, int32_t refresh_ticks);
 

@@ -96,12 +96,11 @@ struct sf_scene {
     // result bit for bit as the gather, which batches keep using)
     bool dense = false;
     // incremental field update (sf_set_field_update): refresh period, ticks
-    // since the last full superposition, the moved bitmaps, the negated
-    // stamp copies and the two update views (S = P, sources = moved bitmap)
+    // since the last full superposition, the moved bitmaps and the update
+    // view (S = P, sources = the su entered, moved_from = the su left)
     int refresh = 0, since_full = 0;
     unsigned long long *moved_from = nullptr, *moved_to = nullptr;
-    float *neg_tab = nullptr;
-    SceneView view_to = {}, view_from = {};
+    SceneView view_upd = {};
     FieldLaunch fl;
     // batch membership: while a batch holds the scene, `stream` is the
     // batch's stream and `own_stream` the one given at create
@@ -688,10 +687,9 @@ int enqueue_tick(sf_scene *s)
     SF_HIP(sf::launch_commit_one(s->view, st, &ev), "commit");
     if ((rc = timing_events(s, SF_KERNEL_SUPERPOSE, &ev))) return rc;
     if (s->refresh > 1 && s->since_full + 1 < s->refresh) {
-        // P += stamps at the su entered - stamps at the su left this tick
-        SF_HIP(scene_field(s, s->view_to, st, &ev), "update");
-        if ((rc = timing_events(s, SF_KERNEL_SUPERPOSE, &ev))) return rc;
-        SF_HIP(scene_field(s, s->view_from, st, &ev), "update");
+        // P = (P + stamps at the su entered) - stamps at the su left this tick
+        SF_HIP(sf::launch_field_update(s->fl, s->view_upd, s->strips_per_block, st, &ev),
+               "update");
         ++s->since_full;
     } else {
         SF_HIP(scene_field(s, s->view, st, &ev), "superpose");
@@ -708,10 +706,8 @@ int set_field_update(sf_scene *s, int32_t refresh)
         const size_t nwords = (size_t)s->wpr * s->H;
         int rc;
         if ((rc = dalloc(s, &s->moved_from, nwords, "moved bitmap")) ||
-            (rc = dalloc(s, &s->moved_to, nwords, "moved bitmap")) ||
-            (rc = dalloc(s, &s->neg_tab, (size_t)s->lc.vec * s->lc.copy_elems, "phi table")))
+            (rc = dalloc(s, &s->moved_to, nwords, "moved bitmap")))
             return rc;
-        SF_HIP(sf::launch_phi_copies(s->neg_tab, s->lc, -s->k, s->alpha, s->stream), "phi table");
         SF_HIP(sf::launch_fill_u64(s->moved_from, nwords, 0ull, s->stream), "clear moves");
         SF_HIP(sf::launch_fill_u64(s->moved_to, nwords, 0ull, s->stream), "clear moves");
     }
@@ -721,12 +717,9 @@ int set_field_update(sf_scene *s, int32_t refresh)
     v.moved_to = s->refresh ? s->moved_to : nullptr;
     if (s->refresh) {
         // the field kernel with S := P (in place) and the moved bitmaps as sources
-        s->view_to = v;
-        s->view_to.S = s->P;
-        s->view_to.occ = s->moved_to;
-        s->view_from = s->view_to;
-        s->view_from.occ = s->moved_from;
-        s->view_from.tab = s->neg_tab;
+        s->view_upd = v;
+        s->view_upd.S = s->P;
+        s->view_upd.occ = s->moved_to;
     }
     // the next tick starts a new refresh period from a full field
     s->since_full = s->refresh;

@@ -159,6 +159,12 @@ hipError_t launch_field(const FieldLaunch &f, const SceneView *views, const int3
 // commit launch the scene's own blocks.
 hipError_t launch_field_one(const FieldLaunch &f, const SceneView &view, int per,
                             hipStream_t st, const LaunchEvents *ev = nullptr);
+// Incremental update of a single scene's field in one launch: view.S = view.P
+// (in place), view.occ = bitmap of the su entered, view.moved_from = bitmap
+// of the su left; P = (P + Phi(entered)) - Phi(left), each sum as launch_field_one
+// computes it.
+hipError_t launch_field_update(const FieldLaunch &f, const SceneView &view, int per,
+                               hipStream_t st, const LaunchEvents *ev = nullptr);
 // Single-scene field by the dense small-radius stencil (radius 1..kDenseMaxRadius),
 // bit-identical to launch_field_one; `grid` caps the persistent workgroups.
 constexpr int kDenseMaxRadius = 4;

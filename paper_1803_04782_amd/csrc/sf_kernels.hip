@@ -515,6 +515,7 @@ struct FieldScene {
     gptr<const float> S;
     gptr<float> P;
     gptr<const unsigned long long> occ;
+    gptr<const unsigned long long> occ2;  // second source bitmap (update launches)
 };
 
 __device__ __forceinline__ FieldScene field_scene(const SceneView &v)
@@ -536,6 +537,7 @@ __device__ __forceinline__ FieldScene field_scene(const SceneView &v)
     f.S = to_global(v.S);
     f.P = to_global(v.P);
     f.occ = to_global(v.occ);
+    f.occ2 = to_global((const unsigned long long *)v.moved_from);
     return f;
 }
 
@@ -585,12 +587,19 @@ struct FieldWork {
     }
 };
 
-template <int TW, int HL, int VEC, int NW, bool MULTI>
+// DUAL (single scene only): the incremental update P = (P + Phi(occ)) -
+// Phi(occ2) in one launch, S = P, occ = the su entered and occ2 = the su left
+// this tick.  Each bitmap gets its own scan, list and gather into its own
+// accumulators, so both sums are those of two plain launches (the second with
+// the stamp negated) bit for bit.
+template <int TW, int HL, int VEC, int NW, bool MULTI, bool DUAL = false>
 __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
                                                    const SceneView *__restrict__ views,
                                                    const int4 *__restrict__ items, int n_items,
                                                    int per, int tab_max, int list_cap)
 {
+    static_assert(!(DUAL && MULTI), "the update launch covers one scene");
+    constexpr int NSRC = DUAL ? 2 : 1;
     const FieldWork<MULTI> work{one, views, items, per};
     constexpr int G = 64 / TW, TH = G * HL, WT = NW * TH, NT = NW * 64, NQ = HL / VEC;
     typedef typename VecOf<VEC>::type vec_t;
@@ -674,24 +683,30 @@ __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
     };
     // bitmap words of this thread's halo row of a strip (issued early: the
     // loads stay in flight across the previous strip's work)
-    unsigned long long n0 = 0, n1 = 0, n2 = 0;
+    unsigned long long nw_[NSRC][3];
     auto fetch_rows = [&](const FieldScene &s, int ts) {
-        n0 = n1 = n2 = 0;
+#pragma unroll
+        for (int src = 0; src < NSRC; ++src) nw_[src][0] = nw_[src][1] = nw_[src][2] = 0;
         const Strip g = strip(s, ts);
         if (tid < g.nr) {
-            if (s.periodic) {
-                int y = (g.ya + tid) % s.H;
-                y += y < 0 ? s.H : 0;
-                const gptr<const unsigned long long> row = s.occ + (size_t)y * s.wpr;
-                n0 = wrapped_word(row, g.wa, s.W, s.wpr);
-                if (g.nwd > 1) n1 = wrapped_word(row, g.wa + 1, s.W, s.wpr);
-                if (g.nwd > 2) n2 = wrapped_word(row, g.wa + 2, s.W, s.wpr);
-            } else {
-                const gptr<const unsigned long long> row =
-                    s.occ + (size_t)(g.ya + tid) * s.wpr + g.wa;
-                n0 = row[0];
-                if (g.nwd > 1) n1 = row[1];
-                if (g.nwd > 2) n2 = row[2];
+#pragma unroll
+            for (int src = 0; src < NSRC; ++src) {
+                const gptr<const unsigned long long> bits = src ? s.occ2 : s.occ;
+                unsigned long long *n = nw_[src];
+                if (s.periodic) {
+                    int y = (g.ya + tid) % s.H;
+                    y += y < 0 ? s.H : 0;
+                    const gptr<const unsigned long long> row = bits + (size_t)y * s.wpr;
+                    n[0] = wrapped_word(row, g.wa, s.W, s.wpr);
+                    if (g.nwd > 1) n[1] = wrapped_word(row, g.wa + 1, s.W, s.wpr);
+                    if (g.nwd > 2) n[2] = wrapped_word(row, g.wa + 2, s.W, s.wpr);
+                } else {
+                    const gptr<const unsigned long long> row =
+                        bits + (size_t)(g.ya + tid) * s.wpr + g.wa;
+                    n[0] = row[0];
+                    if (g.nwd > 1) n[1] = row[1];
+                    if (g.nwd > 2) n[2] = row[2];
+                }
             }
         }
     };
@@ -724,18 +739,27 @@ __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
         // 1. this thread's halo row (only the first nr threads hold one; whole
         // waves without a row skip the masking)
         const bool wave_rows = wv * 64 < nr;
-        unsigned long long m0 = n0, m1 = n1, m2 = n2;
-        int cnt = 0;
-        if (wave_rows) {
-            m0 &= ma;
-            if (nwd == 1) m0 &= mb;
-            if (nwd == 2) m1 &= mb;
-            if (nwd == 3) m2 &= mb;
-            cnt = __popcll(m0) + __popcll(m1) + __popcll(m2);
+        unsigned long long mw[NSRC][3];
+        int cnts[NSRC];
+#pragma unroll
+        for (int src = 0; src < NSRC; ++src) {
+            unsigned long long m0 = nw_[src][0], m1 = nw_[src][1], m2 = nw_[src][2];
+            int cnt = 0;
+            if (wave_rows) {
+                m0 &= ma;
+                if (nwd == 1) m0 &= mb;
+                if (nwd == 2) m1 &= mb;
+                if (nwd == 3) m2 &= mb;
+                cnt = __popcll(m0) + __popcll(m1) + __popcll(m2);
+            }
+            mw[src][0] = m0;
+            mw[src][1] = m1;
+            mw[src][2] = m2;
+            cnts[src] = cnt;
         }
         // keep the loads below after the use of the prefetched words, so that
         // the wait for those does not also wait for the new requests
-        asm volatile("" ::"v"(cnt) : "memory");
+        asm volatile("" ::"v"(cnts[0]), "v"(cnts[NSRC - 1]) : "memory");
         // S of this lane's su and the next strip's halo rows are requested now
         // and arrive while this strip is gathered
         const int x = X0 + col;
@@ -750,126 +774,136 @@ __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
         }
         if (more) fetch_rows(nv, nt);
 
-        // 2. block exclusive scan of the row counts (ballots within a wave);
-        // waves that hold no halo row skip the ballots (their counts are 0)
-        int wtot = 0, wexcl = 0;
-        if (wave_rows) wexcl = wave_excl_small(cnt, wtot);
-        if (lane == 0) wave_tot[wv] = wtot;
-        __syncthreads();
-        int before = 0, total = 0;
-#pragma unroll
-        for (int w = 0; w < NW; ++w) {
-            const int u = wave_tot[w];
-            before += w < wv ? u : 0;
-            total += u;
-        }
-        const int excl = before + wexcl;
-        if (tid < nr) row_excl[tid] = excl;
-        if (tid == 0) row_excl[nr] = total;
-        __syncthreads();
-
         // this wave's halo rows (relative to ya) and per-lane base address
         const int ra = max(y0w - R, ya) - ya;
         const int rb = min(y0w + TH - 1 + R, yb) - ya;
         const int lb = opaque_lane(tbase + ((X0 + col + padx) * stride + (y0w + rg * HL + pady)) * 4);
-        vec_t acc[NQ];
+        vec_t accs[NSRC][NQ];
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) acc[q] = (vec_t)(0.0f);
+        for (int src = 0; src < NSRC; ++src)
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) accs[src][q] = (vec_t)(0.0f);
 
-        const int cap = list_cap - v.max_row;
-        const int npass = (total + cap - 1) / cap;
-        for (int k = 0; k < npass; ++k) {
-            int start = 0, end = total;
-            if (npass > 1) {
-                start = row_excl[lower_bound_lds(row_excl, nr, k * cap)];
-                if (k + 1 < npass) end = row_excl[lower_bound_lds(row_excl, nr, (k + 1) * cap)];
-            }
-            // 3. entries of the rows in this pass
-            if (tid < nr && cnt > 0 && excl >= start && excl < end) {
-                const int py = ya + tid;
-                const int c = (py - pady) & (VEC - 1);
-                const int rowterm = c * v.copy_elems * 4 - (py - c) * 4;
-                int o = excl - start;
 #pragma unroll
-                for (int j = 0; j < 3; ++j) {
-                    unsigned long long mj = j == 0 ? m0 : (j == 1 ? m1 : m2);
-                    const int xw = (wa + j) * 64;
-                    while (mj) {
-                        const int b = __builtin_ctzll(mj);
-                        mj &= mj - 1ull;
-                        list[o++] = rowterm - (xw + b) * stride * 4;
+        for (int src = 0; src < NSRC; ++src) {
+            vec_t *acc = accs[src];
+            const int cnt = cnts[src];
+            const unsigned long long m0 = mw[src][0], m1 = mw[src][1], m2 = mw[src][2];
+            // 2. block exclusive scan of the row counts (ballots within a wave);
+            // waves that hold no halo row skip the ballots (their counts are 0)
+            int wtot = 0, wexcl = 0;
+            if (wave_rows) wexcl = wave_excl_small(cnt, wtot);
+            if (lane == 0) wave_tot[wv] = wtot;
+            __syncthreads();
+            int before = 0, total = 0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                const int u = wave_tot[w];
+                before += w < wv ? u : 0;
+                total += u;
+            }
+            const int excl = before + wexcl;
+            if (tid < nr) row_excl[tid] = excl;
+            if (tid == 0) row_excl[nr] = total;
+            __syncthreads();
+
+            const int cap = list_cap - v.max_row;
+            const int npass = (total + cap - 1) / cap;
+            for (int k = 0; k < npass; ++k) {
+                int start = 0, end = total;
+                if (npass > 1) {
+                    start = row_excl[lower_bound_lds(row_excl, nr, k * cap)];
+                    if (k + 1 < npass) end = row_excl[lower_bound_lds(row_excl, nr, (k + 1) * cap)];
+                }
+                // 3. entries of the rows in this pass
+                if (tid < nr && cnt > 0 && excl >= start && excl < end) {
+                    const int py = ya + tid;
+                    const int c = (py - pady) & (VEC - 1);
+                    const int rowterm = c * v.copy_elems * 4 - (py - c) * 4;
+                    int o = excl - start;
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) {
+                        unsigned long long mj = j == 0 ? m0 : (j == 1 ? m1 : m2);
+                        const int xw = (wa + j) * 64;
+                        while (mj) {
+                            const int b = __builtin_ctzll(mj);
+                            mj &= mj - 1ull;
+                            list[o++] = rowterm - (xw + b) * stride * 4;
+                        }
                     }
                 }
-            }
-            __syncthreads();
-            // 4. gather: list entries are read four at a time (one broadcast
-            // LDS load), each source costs one address add per lane
-            if (ra <= rb) {
-                const int lo = __builtin_amdgcn_readfirstlane(max(row_excl[ra], start) - start);
-                const int hi = __builtin_amdgcn_readfirstlane(min(row_excl[rb + 1], end) - start);
-                int i = lo;
-                for (; i < hi && (i & 3); ++i) gather_one<NQ>(acc, lb + list[i]);
-                const int4 *list4 = reinterpret_cast<const int4 *>(list);
-                // eight sources per round: eight table reads are in flight
-                // before the adds, and the next round's entries are read
-                // behind them (reading up to eight entries past the pass stays
-                // inside the allocation: row_excl follows the list)
-                if (i + 8 <= hi) {
-                    int4 ea = list4[i >> 2];
-                    int4 eb = list4[(i >> 2) + 1];
-                    for (; i + 8 <= hi; i += 8) {
-                        const int a[8] = {ea.x, ea.y, ea.z, ea.w, eb.x, eb.y, eb.z, eb.w};
-                        ea = list4[(i >> 2) + 2];
-                        eb = list4[(i >> 2) + 3];
-                        // the compiler keeps this order: next entries, table
-                        // reads, adds (no wait is implied by the barriers)
-                        asm volatile("" ::: "memory");
-                        vec_t u8[8][NQ];
+                __syncthreads();
+                // 4. gather: list entries are read four at a time (one broadcast
+                // LDS load), each source costs one address add per lane
+                if (ra <= rb) {
+                    const int lo = __builtin_amdgcn_readfirstlane(max(row_excl[ra], start) - start);
+                    const int hi = __builtin_amdgcn_readfirstlane(min(row_excl[rb + 1], end) - start);
+                    int i = lo;
+                    for (; i < hi && (i & 3); ++i) gather_one<NQ>(acc, lb + list[i]);
+                    const int4 *list4 = reinterpret_cast<const int4 *>(list);
+                    // eight sources per round: eight table reads are in flight
+                    // before the adds, and the next round's entries are read
+                    // behind them (reading up to eight entries past the pass stays
+                    // inside the allocation: row_excl follows the list)
+                    if (i + 8 <= hi) {
+                        int4 ea = list4[i >> 2];
+                        int4 eb = list4[(i >> 2) + 1];
+                        for (; i + 8 <= hi; i += 8) {
+                            const int a[8] = {ea.x, ea.y, ea.z, ea.w, eb.x, eb.y, eb.z, eb.w};
+                            ea = list4[(i >> 2) + 2];
+                            eb = list4[(i >> 2) + 3];
+                            // the compiler keeps this order: next entries, table
+                            // reads, adds (no wait is implied by the barriers)
+                            asm volatile("" ::: "memory");
+                            vec_t u8[8][NQ];
 #pragma unroll
-                        for (int u = 0; u < 8; ++u) {
+                            for (int u = 0; u < 8; ++u) {
+                                const lds_vec sp = reinterpret_cast<lds_vec>((uint32_t)(lb + a[u]));
+#pragma unroll
+                                for (int q = 0; q < NQ; ++q) u8[u][q] = sp[q];
+                            }
+                            asm volatile("" ::: "memory");
+                            // row-major source order per accumulator
+#pragma unroll
+                            for (int u = 0; u < 8; ++u) {
+#pragma unroll
+                                for (int q = 0; q < NQ; ++q) acc[q] += u8[u][q];
+                            }
+                        }
+                    }
+                    if (i + 4 <= hi) {
+                        const int4 ea = list4[i >> 2];
+                        const int a[4] = {ea.x, ea.y, ea.z, ea.w};
+                        vec_t u4[4][NQ];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
                             const lds_vec sp = reinterpret_cast<lds_vec>((uint32_t)(lb + a[u]));
 #pragma unroll
-                            for (int q = 0; q < NQ; ++q) u8[u][q] = sp[q];
+                            for (int q = 0; q < NQ; ++q) u4[u][q] = sp[q];
                         }
-                        asm volatile("" ::: "memory");
-                        // row-major source order per accumulator
 #pragma unroll
-                        for (int u = 0; u < 8; ++u) {
+                        for (int u = 0; u < 4; ++u) {
 #pragma unroll
-                            for (int q = 0; q < NQ; ++q) acc[q] += u8[u][q];
+                            for (int q = 0; q < NQ; ++q) acc[q] += u4[u][q];
                         }
+                        i += 4;
                     }
+                    for (; i < hi; ++i) gather_one<NQ>(acc, lb + list[i]);
                 }
-                if (i + 4 <= hi) {
-                    const int4 ea = list4[i >> 2];
-                    const int a[4] = {ea.x, ea.y, ea.z, ea.w};
-                    vec_t u4[4][NQ];
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const lds_vec sp = reinterpret_cast<lds_vec>((uint32_t)(lb + a[u]));
-#pragma unroll
-                        for (int q = 0; q < NQ; ++q) u4[u][q] = sp[q];
-                    }
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-#pragma unroll
-                        for (int q = 0; q < NQ; ++q) acc[q] += u4[u][q];
-                    }
-                    i += 4;
-                }
-                for (; i < hi; ++i) gather_one<NQ>(acc, lb + list[i]);
+                __syncthreads();
             }
-            __syncthreads();
         }
 
-        // 5. P = S + Phi for this lane's su
+        // 5. P = S + Phi for this lane's su (DUAL: (S + Phi(occ)) - Phi(occ2))
         if (x < W) {
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
 #pragma unroll
                 for (int j = 0; j < VEC; ++j) {
                     const int y = y0w + rg * HL + q * VEC + j;
-                    if (y < H) v.P[(size_t)y * W + x] = sv[q * VEC + j] + acc[q][j];
+                    float r = sv[q * VEC + j] + accs[0][q][j];
+                    if constexpr (DUAL) r = r - accs[NSRC - 1][q][j];
+                    if (y < H) v.P[(size_t)y * W + x] = r;
                 }
             }
         }
@@ -1110,14 +1144,14 @@ __global__ __launch_bounds__(kDecideThreads) void k_decide_claim(
                 col[0] = x == 0 ? W - 1 : x - 1;
                 col[1] = x;
                 col[2] = x == W - 1 ? 0 : x + 1;
-    #pragma unroll
+#pragma unroll
                 for (int r = 0; r < 3; ++r) {
                     int yy = y - 1 + r;
                     yy += yy < 0 ? H : (yy >= H ? -H : 0);
                     row[r] = yy;
                     const size_t rw = (size_t)yy * wpr;
                     unsigned int m = 0;
-    #pragma unroll
+#pragma unroll
                     for (int c = 0; c < 3; ++c) {
                         m |= (unsigned int)(occ[rw + (col[c] >> 6)] >> (col[c] & 63) & 1ull) << c;
                         pv[r][c] = P[(size_t)yy * W + col[c]];
@@ -1129,7 +1163,7 @@ __global__ __launch_bounds__(kDecideThreads) void k_decide_claim(
                 col[0] = x - 1;
                 col[1] = x;
                 col[2] = x + 1;
-    #pragma unroll
+#pragma unroll
                 for (int r = 0; r < 3; ++r) {
                     const int yy = y - 1 + r;
                     row[r] = yy;
@@ -1145,7 +1179,7 @@ __global__ __launch_bounds__(kDecideThreads) void k_decide_claim(
                     const unsigned int cr = b < 63 ? (unsigned int)(mid >> (b + 1)) & 1u
                                                    : (unsigned int)rgt & 1u;
                     nb3[r] = cl | (cc << 1) | (cr << 2);
-    #pragma unroll
+#pragma unroll
                     for (int c = 0; c < 3; ++c) {
                         const int xx = x - 1 + c;
                         pv[r][c] = row_in && xx >= 0 && xx < W ? P[(size_t)yy * W + xx] : INFINITY;
@@ -1164,7 +1198,7 @@ __global__ __launch_bounds__(kDecideThreads) void k_decide_claim(
             };
             float lo = pv[1][1], lo2 = INFINITY;
             int best = 0;
-    #pragma unroll
+#pragma unroll
             for (int d = 1; d <= 8; ++d) {
                 const int r = 1 + kDirY[d], c = 1 + kDirX[d];
                 const float pc = pv[r][c];
@@ -1580,6 +1614,9 @@ hipError_t set_field_lds_limit(size_t bytes)
     if (e != hipSuccess) return e;                                                            \
     e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_field<a, b, v, n, true>),        \
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);          \
+    if (e != hipSuccess) return e;                                                            \
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_field<a, b, v, n, false, true>), \
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);          \
     if (e != hipSuccess) return e;
     SF_LIST_SHAPES(SF_SET)
 #undef SF_SET
@@ -1643,6 +1680,21 @@ hipError_t launch_field_one(const FieldLaunch &f, const SceneView &view, int per
         return launch(k_field<a, b, v, n, false>, dim3(grid), dim3(n * 64), f.lds_bytes, st,     \
                       ev, view, (const SceneView *)nullptr, (const int4 *)nullptr, n_items, per, \
                       f.tab_max, f.list_cap);
+    SF_LIST_SHAPES(SF_DISPATCH)
+#undef SF_DISPATCH
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_field_update(const FieldLaunch &f, const SceneView &view, int per,
+                               hipStream_t st, const LaunchEvents *ev)
+{
+    const int n_items = std::max(1, (view.n_strips + per - 1) / per);
+    const int grid = std::max(1, std::min(f.grid, n_items));
+#define SF_DISPATCH(a, b, v, n)                                                                   \
+    if (f.tw == a && f.hl == b && f.vec == v && f.nw == n)                                      \
+        return launch(k_field<a, b, v, n, false, true>, dim3(grid), dim3(n * 64), f.lds_bytes,  \
+                      st, ev, view, (const SceneView *)nullptr, (const int4 *)nullptr, n_items, \
+                      per, f.tab_max, f.list_cap);
     SF_LIST_SHAPES(SF_DISPATCH)
 #undef SF_DISPATCH
     return hipErrorInvalidValue;
