@@ -193,8 +193,8 @@ __global__ void k_phi_table(T *tab, int ncols, int nrows, int stride, int padx, 
 
 __global__ void k_bfs_seed(const uint8_t *__restrict__ exitm, int32_t *__restrict__ D, int n)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c < n) D[c] = exitm[c] ? 0 : -1;  // exit su are never obstacles
+    const size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < (size_t)n) D[c] = exitm[c] ? 0 : -1;  // exit su are never obstacles
 }
 
 // Level-synchronous BFS on bitmaps (bit x & 63 of word x >> 6 of a row), one
@@ -317,8 +317,8 @@ __global__ __launch_bounds__(kBfsThreads) void k_bfs_block(
 __global__ void k_count_unreachable(const uint8_t *__restrict__ obst, const int32_t *__restrict__ D,
                                     int n, unsigned long long *ctr)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    const bool bad = c < n && !obst[c] && D[c] < 0;
+    const size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool bad = c < (size_t)n && !obst[c] && D[c] < 0;
     block_sum_add(bad ? 1u : 0u, ctr, kScratch);
 }
 
@@ -326,8 +326,8 @@ __global__ void k_static_S(const int32_t *__restrict__ D, const double *__restri
                            const uint8_t *__restrict__ obst, double w_dest, float *__restrict__ S,
                            int n)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= n) return;
+    const size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= (size_t)n) return;
     S[c] = obst[c] ? INFINITY : (float)(w_dest * (double)D[c] + O[c]);
 }
 
@@ -948,8 +948,8 @@ __global__ void k_phi_copies(float *tab, int vec, int copy_elems, int ncols, int
 __global__ void k_occ_init(const int32_t *__restrict__ pos, int N, unsigned long long *occ, int wpr,
                            int W, unsigned long long *ctr)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int p = i < N ? pos[i] : -1;
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int p = i < (size_t)N ? pos[i] : -1;
     if (p >= 0) {
         const int y = p / W, x = p - y * W;
         atomicOr(&occ[(size_t)y * wpr + (x >> 6)], 1ull << (x & 63));
@@ -1309,8 +1309,8 @@ template <typename T>
 __global__ void k_scatter(const T *__restrict__ src, const int32_t *__restrict__ ext,
                           T *__restrict__ dst, int n)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) dst[ext[i]] = src[i];
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < (size_t)n) dst[ext[i]] = src[i];
 }
 
 // ---- batched counter read-out --------------------------------------------------------
@@ -1347,6 +1347,10 @@ hipError_t launch(K kernel, dim3 grid, dim3 block, size_t lds, hipStream_t st,
     return hipGetLastError();
 }
 
+// Workgroups for n elements of bs threads, at most `cap`: grid-stride kernels
+// take the default cap; kernels with one thread per element pass kCoverAll
+// (n < 2^31 elements fit it).
+constexpr unsigned int kCoverAll = 1u << 30;
 inline unsigned int blocks_for(size_t n, unsigned int bs, unsigned int cap = 65535u * 16u)
 {
     size_t b = (n + bs - 1) / bs;
@@ -1438,7 +1442,8 @@ hipError_t launch_phi_table_f64(double *tab, const SupCfg &c, double k, double a
 
 hipError_t launch_bfs_seed(const uint8_t *exitm, int32_t *D, int n, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_bfs_seed, dim3(blocks_for(n, 256)), dim3(256), 0, st, exitm, D, n);
+    hipLaunchKernelGGL(k_bfs_seed, dim3(blocks_for(n, 256, kCoverAll)), dim3(256), 0, st, exitm,
+                       D, n);
     return hipGetLastError();
 }
 
@@ -1459,8 +1464,8 @@ hipError_t launch_bfs_block(const unsigned long long *obits, unsigned long long 
 hipError_t launch_count_unreachable(const uint8_t *obst, const int32_t *D, int n,
                                     unsigned long long *out, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_count_unreachable, dim3(blocks_for(n, 256)), dim3(256), 0, st, obst, D, n,
-                       out);
+    hipLaunchKernelGGL(k_count_unreachable, dim3(blocks_for(n, 256, kCoverAll)), dim3(256), 0, st,
+                       obst, D, n, out);
     return hipGetLastError();
 }
 
@@ -1711,16 +1716,16 @@ hipError_t launch_superpose_f64(const SupCfg &c, const unsigned long long *bits,
 hipError_t launch_static_S(const int32_t *D, const double *O, const uint8_t *obst, double w_dest,
                            float *S, int n, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_static_S, dim3(blocks_for(n, 256)), dim3(256), 0, st, D, O, obst, w_dest,
-                       S, n);
+    hipLaunchKernelGGL(k_static_S, dim3(blocks_for(n, 256, kCoverAll)), dim3(256), 0, st, D, O,
+                       obst, w_dest, S, n);
     return hipGetLastError();
 }
 
 hipError_t launch_occ_init(const int32_t *pos, int N, unsigned long long *occ, int wpr, int W,
                            unsigned long long *ctr, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_occ_init, dim3(blocks_for(N, 256)), dim3(256), 0, st, pos, N, occ, wpr, W,
-                       ctr);
+    hipLaunchKernelGGL(k_occ_init, dim3(blocks_for(N, 256, kCoverAll)), dim3(256), 0, st, pos, N,
+                       occ, wpr, W, ctr);
     return hipGetLastError();
 }
 
@@ -1745,16 +1750,16 @@ hipError_t launch_decide_one(const SceneView &view, hipStream_t st, const Launch
 hipError_t launch_scatter_i32(const int32_t *src, const int32_t *ext, int32_t *dst, int n,
                               hipStream_t st)
 {
-    hipLaunchKernelGGL(k_scatter<int32_t>, dim3(blocks_for((size_t)n, 256)), dim3(256), 0, st,
-                       src, ext, dst, n);
+    hipLaunchKernelGGL(k_scatter<int32_t>, dim3(blocks_for((size_t)n, 256, kCoverAll)), dim3(256),
+                       0, st, src, ext, dst, n);
     return hipGetLastError();
 }
 
 hipError_t launch_scatter_u8(const uint8_t *src, const int32_t *ext, uint8_t *dst, int n,
                              hipStream_t st)
 {
-    hipLaunchKernelGGL(k_scatter<uint8_t>, dim3(blocks_for((size_t)n, 256)), dim3(256), 0, st,
-                       src, ext, dst, n);
+    hipLaunchKernelGGL(k_scatter<uint8_t>, dim3(blocks_for((size_t)n, 256, kCoverAll)), dim3(256),
+                       0, st, src, ext, dst, n);
     return hipGetLastError();
 }
 

@@ -4,8 +4,8 @@ on grids built to stress the tiled search: serpentine walls whose shortest
 paths cross tile borders hundreds of times, widths and heights off the
 64-su word and the tile size, a grid narrower than one word, a grid of more
 tiles than the device runs at once (later workgroups of a launch must still
-see the launch's starting state), and an unreachable pocket far from the
-exit."""
+see the launch's starting state), an unreachable pocket far from the
+exit, and a room of more than 2^28 su checked against closed forms."""
 import numpy as np
 import pytest
 
@@ -84,3 +84,52 @@ def test_unreachable_pocket_across_tiles(sf):
     rc, msg = sf.create_error(sc)
     assert rc == sf.SF_EUNREACHABLE, msg
     assert "1521 free su" in msg  # the 39 x 39 su inside the box
+
+
+def test_room_beyond_2_28_su(sf):
+    """A walled room of 16448 x 16448 su (2^28 + 2.1 M su) with one 16-su exit
+    on the east wall: the set-up kernels that take one thread per su (exit
+    seeds, reachability count, S) must reach the su beyond index 2^28.  In an
+    empty room D is the Chebyshev distance to the exit segment (closed form);
+    beyond the walls' obstacle window S = D exactly; and wherever no
+    pedestrian is within R the field is S."""
+    W = H = 16448
+    R = 2
+    y0 = H // 2 - 8
+    ob = np.zeros((H, W), np.uint8)
+    ob[0, :] = ob[-1, :] = 1
+    ob[:, 0] = ob[:, -1] = 1
+    ex = np.zeros((H, W), np.uint8)
+    ex[y0:y0 + 16, W - 1] = 1
+    ob[y0:y0 + 16, W - 1] = 0
+    rng = np.random.default_rng(17)
+    px = rng.integers(1, W - 1, 3000)
+    py = np.concatenate([rng.integers(H - 400, H - 1, 2000), rng.integers(1, H - 1, 1000)])
+    pos = np.unique(py * W + px).astype(np.int32)
+    sc = scenes.Scene(width=W, height=H, obstacle=ob.ravel(), exit=ex.ravel(), pos=pos,
+                      radius=R, name="room16448")
+    del ob, ex
+    print(f"[room16448] {W * H} su, {pos.size} pedestrians", flush=True)
+    with sf.GpuScene(sc) as g:
+        S, D = g.static_field()
+        P = g.field()
+        g.step(3)
+        after = g.positions()
+    xs = np.concatenate([rng.integers(1, W - 1, 6000), rng.integers(W - 40, W - 1, 500)])
+    # rows from 16321 on hold only su beyond index 2^28
+    ys = np.concatenate([rng.integers(1, H - 1, 3000), rng.integers(H - 120, H - 1, 3500)])
+    idx = ys.astype(np.int64) * W + xs
+    assert np.count_nonzero(idx >= (1 << 28)) >= 3500
+    dy = np.where(ys < y0, y0 - ys, np.where(ys > y0 + 15, ys - (y0 + 15), 0))
+    want = np.maximum(W - 1 - xs, dy)
+    assert np.array_equal(D[idx], want)
+    far = (xs > R) & (xs < W - 1 - R) & (ys > R) & (ys < H - 1 - R)
+    assert np.array_equal(S[idx[far]], want[far].astype(np.float32))
+    qx, qy = pos % W, pos // W
+    alone = np.array([not np.any((np.abs(qx - x) <= R) & (np.abs(qy - y) <= R))
+                      for x, y in zip(xs, ys)])
+    assert alone.sum() > 5000
+    assert np.array_equal(P[idx[alone]], S[idx[alone]])
+    assert D[W - 1 + (y0 + 3) * W] == 0 and D[(H - 1) * W + W // 2] == -1
+    live = after[after >= 0]
+    assert np.all(after >= -1) and np.all(live < W * H) and np.unique(live).size == live.size
