@@ -65,6 +65,10 @@ extern "C" {
 /* Largest field half-width R (pedestrian and obstacle fields) accepted. */
 #define SF_MAX_RADIUS 48
 
+/* Largest number of pedestrians of one scene (per-pedestrian launches index
+ * whole workgroups of 256 with 32-bit ids). */
+#define SF_MAX_PEDS (2147483647 - 1023)
+
 typedef struct sf_scene sf_scene; /* opaque, library-owned */
 
 /* Scene description (section 2 grid, pedestrians, field geometry; Algorithm 1
@@ -74,7 +78,8 @@ typedef struct {
     int32_t width, height;    /* grid size in su; width*height < 2^31            */
     const uint8_t *obstacle;  /* [height*width] 1 = obstacle (walls included)    */
     const uint8_t *exit;      /* [height*width] 1 = exit su; never an obstacle   */
-    int32_t n_peds;           /* number of pedestrians; id = index in pos        */
+    int32_t n_peds;           /* number of pedestrians, 0..SF_MAX_PEDS; id =
+                                 index in pos                                    */
     const int32_t *pos;       /* [n_peds] linear su index, distinct, on free
                                  non-exit su                                      */
     int32_t radius;           /* pedestrian field half-width R, 0..SF_MAX_RADIUS */

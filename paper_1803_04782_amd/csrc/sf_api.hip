@@ -214,6 +214,8 @@ int validate(const sf_scene_desc *d)
         return fail(SF_EINVAL, "grid %d x %d has 2^31 su or more", d->width, d->height);
     if (!d->obstacle || !d->exit) return fail(SF_EINVAL, "obstacle and exit masks are required");
     if (d->n_peds < 0) return fail(SF_EINVAL, "n_peds = %d is negative", d->n_peds);
+    if (d->n_peds > SF_MAX_PEDS)
+        return fail(SF_EINVAL, "n_peds = %d is above %d", d->n_peds, SF_MAX_PEDS);
     if (d->n_peds > 0 && !d->pos) return fail(SF_EINVAL, "pos is NULL with n_peds = %d", d->n_peds);
     if (d->radius < 0 || d->radius > SF_MAX_RADIUS)
         return fail(SF_EINVAL, "radius %d outside 0..%d", d->radius, SF_MAX_RADIUS);

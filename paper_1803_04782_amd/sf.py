@@ -21,6 +21,7 @@ SF_ENOMEM = -2
 SF_EDEVICE = -3
 SF_EUNREACHABLE = -4
 SF_MAX_RADIUS = 48
+SF_MAX_PEDS = 2147483647 - 1023
 
 SF_FLAG_MOVER = 1
 SF_FLAG_WON = 2

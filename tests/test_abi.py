@@ -114,6 +114,18 @@ def test_validation_errors(sf):
         assert msg, name
 
 
+def test_pedestrian_count_limit(sf):
+    """n_peds above SF_MAX_PEDS is refused before any array is read."""
+    import ctypes
+
+    desc, keep = sf.make_desc(_base())
+    desc.n_peds = sf.SF_MAX_PEDS + 1
+    h = ctypes.c_void_p()
+    rc = sf.load().sf_create_scene(ctypes.byref(desc), None, ctypes.byref(h))
+    assert rc == sf.SF_EINVAL and "above" in sf.load().sf_last_error().decode()
+    del keep
+
+
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     from paper_1803_04782_amd import sf as _sf
 
