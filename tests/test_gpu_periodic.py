@@ -224,3 +224,66 @@ def test_lone_walkers_keep_their_period(sf):
     for i, per in enumerate((p, p, 1)):
         moves = sum(1 for t in range(T) if (t + i) % per == 0)
         assert pos[i] == start[i] + moves, (i, pos[i], start[i], moves)
+
+
+def test_packed_torus_beyond_2_28_pedestrians(sf):
+    """A 16448 x 16448 torus filled with pedestrians except 1000 holes
+    (2^28 + 2.1 M pedestrians, R = 1): the launches with one thread per
+    pedestrian (occupancy build, caller-order copies) must reach the
+    pedestrians beyond index 2^28.  Closed forms: positions come back as
+    given; the field is C minus the stamps of the holes within the window
+    (C = the full 3 x 3 window: 4 axial + 4 diagonal values), the same bits
+    wherever no hole is near; pedestrians are conserved over two ticks."""
+    W = H = 16448
+    n = W * H
+    rng = np.random.default_rng(23)
+    holes = np.unique(rng.integers(0, n, 1000))
+    holes = np.concatenate([holes, [n - 1, n - W // 2]])  # two in the last row
+    holes = np.unique(holes)
+    free = np.ones(n, bool)
+    free[holes] = False
+    pos = np.flatnonzero(free).astype(np.int32)
+    del free
+    sc = scenes.Scene(width=W, height=H, obstacle=np.zeros(n, np.uint8),
+                      exit=np.zeros(n, np.uint8), pos=pos, radius=1, periodic=True)
+    N = pos.size
+    assert N > (1 << 28) + 2_000_000
+    _say(f"[packed torus] {N} pedestrians")
+    with sf.GpuScene(sc) as g:
+        back = g.positions()
+        P = g.field()
+        g.step(2)
+        after = g.positions()
+        s = g.stats()
+    assert np.array_equal(back, pos)
+    hx, hy = holes % W, holes // W
+    near = [((hy[j] + dy) % H) * W + (hx[j] + dx) % W for j in range(0, holes.size, 5)
+            for dy in (-1, 0, 1) for dx in (-1, 0, 1)]
+    cells = np.unique(np.concatenate([rng.integers(0, n, 4000), rng.integers(n - 100 * W, n, 4000),
+                                      np.array(near)]))
+    assert np.count_nonzero(cells >= (1 << 28)) > 4000
+    ax, dg = 1.0, 2.0 ** -0.25
+    C = 4 * ax + 4 * dg
+    cx, cy = cells % W, cells // W
+    want = np.full(cells.size, C)
+    hole_set = set(holes.tolist())
+    for dy in (-1, 0, 1):
+        for dx in (-1, 0, 1):
+            if dx == 0 and dy == 0:
+                continue
+            nb = ((cy + dy) % H) * W + (cx + dx) % W
+            hit = np.array([c in hole_set for c in nb.tolist()])
+            want -= hit * (ax if dx == 0 or dy == 0 else dg)
+    err = np.abs(P[cells].astype(np.float64) - want) / np.maximum(np.abs(want), 1.0)
+    assert err.max() <= FIELD_RTOL, err.max()
+    clear = want == C
+    assert clear.sum() > 6000 and np.unique(P[cells[clear]]).size == 1
+    assert s["live"] == N and s["evacuated"] == 0
+    assert np.all((after >= 0) & (after < n))
+    seen = np.zeros(n, bool)
+    seen[after] = True
+    assert np.count_nonzero(seen) == N  # distinct su
+    m = np.flatnonzero(after != pos)
+    ddx = np.abs(after[m] % W - pos[m] % W)
+    ddy = np.abs(after[m] // W - pos[m] // W)
+    assert np.all(np.minimum(ddx, W - ddx) <= 2) and np.all(np.minimum(ddy, H - ddy) <= 2)
