@@ -194,6 +194,15 @@ int sf_sync(const sf_scene *s);
  * SF_EINVAL for a negative value or a scene that belongs to a batch. */
 int sf_set_field_update(sf_scene *s, int32_t refresh_ticks);
 
+/* Superpose the field of the current positions again, n_times times (no
+ * tick; positions, counters and step index unchanged).  The result is the
+ * field sf_step leaves after a tick, bit for bit, so repeated calls change
+ * nothing; under the incremental update (sf_set_field_update) it discards the
+ * accumulated rounding and starts a new refresh period.  Enqueued on the
+ * scene's stream (timed as SF_KERNEL_SUPERPOSE); does not block.  SF_EINVAL
+ * for a negative count or a scene that belongs to a batch. */
+int sf_refresh_field(sf_scene *s, int32_t n_times);
+
 /* Per-kernel timing: while enabled, every launch of the kernels listed above
  * records a start/stop HIP event pair as part of its own dispatch (the
  * kernel's execution interval, no extra stream packets).  enable = 1 starts a fresh

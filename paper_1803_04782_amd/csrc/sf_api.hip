@@ -1224,6 +1224,26 @@ int sf_create_scene(const sf_scene_desc *desc, void *hip_stream, sf_scene **out)
     }
 }
 
+int sf_refresh_field(sf_scene *s, int32_t n_times)
+{
+    if (!s) return fail(SF_EINVAL, "scene is NULL");
+    if (n_times < 0) return fail(SF_EINVAL, "n_times %d is negative", n_times);
+    if (s->batch) return fail(SF_EINVAL, "the scene belongs to a batch");
+    DeviceGuard g(s->device);
+    try {
+        for (int32_t i = 0; i < n_times; ++i) {
+            sf::LaunchEvents ev;
+            int rc;
+            if ((rc = timing_events(s, SF_KERNEL_SUPERPOSE, &ev))) return rc;
+            SF_HIP(scene_field(s, s->view, s->stream, &ev), "superpose");
+        }
+        if (n_times > 0) s->since_full = 0;
+    } catch (const std::bad_alloc &) {
+        return fail(SF_ENOMEM, "host allocation failed");
+    }
+    return SF_OK;
+}
+
 int sf_step(sf_scene *s, int32_t n_steps)
 {
     if (!s) return fail(SF_EINVAL, "scene is NULL");

@@ -34,7 +34,7 @@ SF_KERNEL_COMMIT = 2
 # every symbol include/sf.h declares
 EXPORTS = ("sf_create_scene", "sf_step", "sf_field", "sf_positions", "sf_last_moves",
            "sf_static_field", "sf_set_state", "sf_stats", "sf_sync", "sf_set_timing",
-           "sf_kernel_time", "sf_set_field_update", "sf_destroy_scene", "sf_batch_create", "sf_batch_tune",
+           "sf_kernel_time", "sf_refresh_field", "sf_set_field_update", "sf_destroy_scene", "sf_batch_create", "sf_batch_tune",
            "sf_batch_get_tiling", "sf_batch_step", "sf_batch_stats", "sf_batch_sync",
            "sf_batch_destroy", "sf_device_count",
            "sf_last_error")
@@ -150,6 +150,7 @@ def load():
     lib.sf_kernel_time.argtypes = [P, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                                    ctypes.POINTER(i64)]
     lib.sf_set_field_update.argtypes = [P, i32]
+    lib.sf_refresh_field.argtypes = [P, i32]
     lib.sf_destroy_scene.argtypes = [P]
     lib.sf_destroy_scene.restype = None
     lib.sf_batch_create.argtypes = [ctypes.POINTER(P), i32, ctypes.POINTER(Tiling), P,
@@ -301,6 +302,11 @@ class GpuScene:
         """0/1: full superposition every tick; K >= 2: incremental update with
         a full superposition every K ticks."""
         _check(load().sf_set_field_update(self._h, int(refresh_ticks)))
+
+    def refresh_field(self, n_times: int = 1):
+        """Superpose the field of the current positions again, n_times times
+        (enqueued on the scene stream)."""
+        _check(load().sf_refresh_field(self._h, int(n_times)))
 
     def set_timing(self, on: bool):
         _check(load().sf_set_timing(self._h, 1 if on else 0))

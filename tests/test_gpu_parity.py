@@ -199,6 +199,28 @@ def test_tile_shape_invariance(sf, monkeypatch):
         assert np.array_equal(p, fields[0][1])
 
 
+def test_refresh_field(sf):
+    """sf_refresh_field superposes the current positions again: on the full
+    path the field keeps its bits and nothing else changes; under the
+    incremental update it gives the field that sf_set_state builds from the
+    same positions."""
+    sc = scenes.random_scene(230, 150, n_peds=2500, radius=7, seed=41, bernoulli=0.04)
+    with sf.GpuScene(sc) as g:
+        g.step(9)
+        P0, pos0, st0 = g.field(), g.positions(), g.stats()
+        g.refresh_field(3)
+        assert np.array_equal(g.field(), P0)
+        assert np.array_equal(g.positions(), pos0) and g.stats() == st0
+    with sf.GpuScene(sc) as g:
+        g.set_field_update(16)
+        g.step(9)
+        pos, step = g.positions(), g.stats()["step"]
+        g.refresh_field(1)
+        P_ref = g.field()
+        g.set_state(pos, step)
+        assert np.array_equal(g.field(), P_ref)
+
+
 def test_stats_consistency(sf):
     sc = scenes.random_scene(90, 70, n_peds=700, radius=4, seed=5, bernoulli=0.02,
                              exits=("E", "W", "N"), exit_width=8)
