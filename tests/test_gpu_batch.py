@@ -109,6 +109,28 @@ def test_batch_tilings_identical(sf, tiling):
         g.close()
 
 
+def test_batch_extreme_radii(sf):
+    """Members at the largest radius (48, bounded and periodic) beside R = 1
+    and R = 47, under the default tiling: every member evolves as alone."""
+    scs = [scenes.random_scene(210, 160, n_peds=2000, radius=48, seed=51, bernoulli=0.02,
+                               exits=("E", "W"), exit_width=8),
+           scenes.random_scene(120, 90, n_peds=3000, radius=1, seed=52, exits=("N",),
+                               exit_width=6),
+           scenes.flow_scene(128, 100, 0.3, 8, radius=48, seed=53),
+           scenes.random_scene(70, 50, n_peds=200, radius=47, seed=54, exits=("S",))]
+    alone = [sf.GpuScene(s) for s in scs]
+    member = [sf.GpuScene(s) for s in scs]
+    with sf.Batch(member) as b:
+        _say("[batch extreme radii] tiling", b.tiling())
+        b.step(7)
+        for g in alone:
+            g.step(7)
+        for j, (a, m) in enumerate(zip(alone, member)):
+            _assert_same(_state(a), _state(m), j)
+    for g in alone + member:
+        g.close()
+
+
 def test_batch_tune_keeps_state_and_results(sf):
     scs = _mixed_scenes()
     alone = [sf.GpuScene(s) for s in scs]

@@ -38,6 +38,7 @@ CASES = [
     ("wide-R", lambda: scenes.random_scene(200, 131, n_peds=1500, radius=33, seed=7,
                                            exits=("N",), exit_width=8), 8, 40, 1),
     ("hall1024", lambda: scenes.hall1024(), 32, 200, 10),
+    ("max-R-torus", lambda: scenes.flow_scene(130, 100, 0.3, 8, radius=48, seed=42), 8, 30, 1),
 ]
 
 
