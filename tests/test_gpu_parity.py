@@ -98,6 +98,9 @@ SMALL = [
     (150, 97, 1200, 17, 6, {"radius_obs": 5, "w_dest": 2.0}),
     (200, 131, 1500, 33, 7, {}),
     (97, 203, 900, 48, 8, {"radius_obs": 48}),
+    # attractive pedestrian and obstacle fields, and a law that grows with distance
+    (88, 77, 700, 4, 9, {"k": -0.7, "alpha": -0.8, "k_obs": -0.3}),
+    (95, 70, 650, 6, 10, {"alpha": 0.5, "k": 0.05}),
 ]
 
 
