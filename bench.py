@@ -537,6 +537,14 @@ def main():
                 "tick_launch_interval_us": ktimes["superpose"]["avg_us"],
                 "algorithmic_bytes_per_launch": alg_bytes,
                 "hbm_frac": alg_bytes / (sup_us * 1e-6) / 8.0e12}
+    # measured HBM rate (calibrated counters over the launch duration) and the
+    # launch's floor at peak: max(algorithmic bytes / 8 TB/s, adds / ALU rate)
+    if roofline["traffic"] is not None:
+        roofline["measured_hbm_GBps"] = roofline["traffic"] / (sup_us * 1e-6) / 1e9
+    t_hbm = alg_bytes / 8.0e12
+    t_alu = contrib_per_launch / (ALU_PEAK_TFLOPS * 1e12)
+    roofline["floor_us"] = 1e6 * max(t_hbm, t_alu)
+    roofline["floor_binding"] = "alu" if t_alu >= t_hbm else "hbm"
 
     out = {"metric": METRIC, "value": value, "unit": "pedestrian-steps/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1000.0 * dt / args.steps,
