@@ -634,25 +634,31 @@ __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
     FieldScene v = work.scene(it.x);
     int t = it.y;
     typedef VecOf<4>::type f4;
-    // stamp copies into LDS: each thread's loads are all issued before the
-    // stores, so the copy costs one memory round trip per 8 vectors
-    auto load_table = [&](const FieldScene &s) {
+    // stamp copies into LDS, 8 vectors per thread and batch: each thread's
+    // loads are all issued before the stores, so a batch costs one memory
+    // round trip.  The loads are unconditional (indices past the end read the
+    // last vector again): a load under a branch of its own would get a wait.
+    f4 *const tab4 = reinterpret_cast<f4 *>(tab);
+    auto table_load = [&](const FieldScene &s, int i0, f4(&r)[8]) {
         const int n4 = s.tab_elems / 4;
-        for (int i0 = 0; i0 < n4; i0 += 8 * NT) {
-            f4 r[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int i = i0 + u * NT + tid;
-                if (i < n4) r[u] = s.tab[i];
-            }
+        for (int u = 0; u < 8; ++u) r[u] = s.tab[min(i0 + u * NT + tid, n4 - 1)];
+    };
+    auto table_store = [&](const FieldScene &s, int i0, const f4(&r)[8]) {
+        const int n4 = s.tab_elems / 4;
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int i = i0 + u * NT + tid;
-                if (i < n4) reinterpret_cast<f4 *>(tab)[i] = r[u];
-            }
+        for (int u = 0; u < 8; ++u) {
+            const int i = i0 + u * NT + tid;
+            if (i < n4) tab4[i] = r[u];
         }
     };
-    load_table(v);
+    auto load_table = [&](const FieldScene &s) {
+        for (int i0 = 0; i0 < s.tab_elems / 4; i0 += 8 * NT) {
+            f4 r[8];
+            table_load(s, i0, r);
+            table_store(s, i0, r);
+        }
+    };
 
     // Strip geometry: halo rows [ya, ya + nr), halo bitmap words [wa, wa + nwd).
     // On a periodic scene the halo is not clipped: rows and columns outside
@@ -710,7 +716,19 @@ __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
             }
         }
     };
-    fetch_rows(v, t);
+    {
+        // the first batch of the stamp copies (all of them unless they exceed
+        // 8 vectors per thread) and the first strip's halo rows are requested
+        // together, in straight-line code, so that their round trips overlap
+        f4 r[8];
+        fetch_rows(v, t);
+        table_load(v, 0, r);
+        table_store(v, 0, r);
+        for (int i0 = 8 * NT; i0 < v.tab_elems / 4; i0 += 8 * NT) {
+            table_load(v, i0, r);
+            table_store(v, i0, r);
+        }
+    }
     __syncthreads();
 
     for (;;) {
@@ -1118,15 +1136,24 @@ __global__ __launch_bounds__(kDecideThreads) void k_decide_claim(
             to_global(v.moved_to)[k] = 0ull;
         }
     }
-    const unsigned long long t = ctr[0];
     const unsigned long long seed = v.seed;
     const float phi_axial = v.phi_axial, phi_diag = v.phi_diag;
     unsigned int movers = 0, ties = 0;
-    const int p = i < N ? to_global((const int32_t *)v.pos)[i] : -1;
+    // the step index and this pedestrian's arrays are requested together and
+    // waited for once (the empty asm takes all of them, so no load is moved
+    // behind a branch that would wait for it alone)
+    unsigned long long t = ctr[0];
+    int p = -1, h = 0;
+    uint32_t eid = 0;
+    unsigned int wp = 1u;
+    if (i < N) {
+        p = to_global((const int32_t *)v.pos)[i];
+        eid = (uint32_t)to_global((const int32_t *)v.ext)[i];
+        if (v.heading) h = (int)to_global(v.heading)[i];
+        if (v.walk) wp = (unsigned int)to_global(v.walk)[i];
+    }
+    asm volatile("" : "+v"(p), "+v"(eid), "+v"(h), "+v"(wp), "+v"(t));
     if (p >= 0) {
-        const uint32_t eid = (uint32_t)to_global((const int32_t *)v.ext)[i];
-        const int h = v.heading ? (int)to_global(v.heading)[i] : 0;
-        const unsigned int wp = v.walk ? (unsigned int)to_global(v.walk)[i] : 1u;
         if (wp > 1u && (t + eid) % wp != 0ull) {
             // resting this tick: stays, registers for nothing
             target[i] = p;
@@ -1163,16 +1190,35 @@ __global__ __launch_bounds__(kDecideThreads) void k_decide_claim(
                 col[0] = x - 1;
                 col[1] = x;
                 col[2] = x + 1;
+                // every load is issued unconditionally at a clamped (in-grid)
+                // su and all are waited for once; the values outside the grid
+                // or beside the word are then replaced
+                unsigned long long wm[3], wl[3], wr[3];
+                float pr[3][3];
+#pragma unroll
+                for (int r = 0; r < 3; ++r) {
+                    const int yc = min(max(y - 1 + r, 0), H - 1);
+                    const size_t rw = (size_t)yc * wpr;
+                    wm[r] = occ[rw + w];
+                    wl[r] = occ[rw + max(w - 1, 0)];
+                    wr[r] = occ[rw + min(w + 1, wpr - 1)];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c)
+                        pr[r][c] = P[(size_t)yc * W + min(max(x - 1 + c, 0), W - 1)];
+                }
+#pragma unroll
+                for (int r = 0; r < 3; ++r) {
+                    asm volatile("" : "+v"(wm[r]), "+v"(wl[r]), "+v"(wr[r]));
+                    asm volatile("" : "+v"(pr[r][0]), "+v"(pr[r][1]), "+v"(pr[r][2]));
+                }
 #pragma unroll
                 for (int r = 0; r < 3; ++r) {
                     const int yy = y - 1 + r;
                     row[r] = yy;
                     const bool row_in = yy >= 0 && yy < H;
-                    const size_t rw = (size_t)yy * wpr;
-                    const unsigned long long mid = row_in ? occ[rw + w] : 0ull;
-                    const unsigned long long lft = row_in && b == 0 && w > 0 ? occ[rw + w - 1] : 0ull;
-                    const unsigned long long rgt =
-                        row_in && b == 63 && w + 1 < wpr ? occ[rw + w + 1] : 0ull;
+                    const unsigned long long mid = row_in ? wm[r] : 0ull;
+                    const unsigned long long lft = row_in && b == 0 && w > 0 ? wl[r] : 0ull;
+                    const unsigned long long rgt = row_in && b == 63 && w + 1 < wpr ? wr[r] : 0ull;
                     const unsigned int cl = b > 0 ? (unsigned int)(mid >> (b - 1)) & 1u
                                                   : (unsigned int)(lft >> 63);
                     const unsigned int cc = (unsigned int)(mid >> b) & 1u;
@@ -1182,7 +1228,7 @@ __global__ __launch_bounds__(kDecideThreads) void k_decide_claim(
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
                         const int xx = x - 1 + c;
-                        pv[r][c] = row_in && xx >= 0 && xx < W ? P[(size_t)yy * W + xx] : INFINITY;
+                        pv[r][c] = row_in && xx >= 0 && xx < W ? pr[r][c] : INFINITY;
                     }
                 }
             }
