@@ -1021,6 +1021,14 @@ __global__ __launch_bounds__(kDenseWaves * 64) void k_field_dense(SceneView one,
         const int ty = t / tiles_x, tx = t - ty * tiles_x;
         const int x = tx * 64 + lane;
         const int Y0 = ty * TH, y0 = Y0 + wv * kDenseHL;
+        // S of this lane's su, requested first: its round trip overlaps the
+        // staging of the rows
+        float sv[kDenseHL];
+#pragma unroll
+        for (int h = 0; h < kDenseHL; ++h) {
+            const int y = y0 + h;
+            sv[h] = S[(size_t)min(y, H - 1) * W + min(x, W - 1)];
+        }
         for (int k = tid; k < TR * 3; k += kDenseWaves * 64) {
             const int r = k / 3, c = k - r * 3;
             int sy = Y0 - R + r;
@@ -1032,13 +1040,6 @@ __global__ __launch_bounds__(kDenseWaves * 64) void k_field_dense(SceneView one,
                 wd = occ[(size_t)sy * wpr + tx - 1 + c];
             }
             rows[r][c] = wd;
-        }
-        // S of this lane's su, requested before the wait
-        float sv[kDenseHL];
-#pragma unroll
-        for (int h = 0; h < kDenseHL; ++h) {
-            const int y = y0 + h;
-            sv[h] = x < W && y < H ? S[(size_t)y * W + x] : 0.0f;
         }
         __syncthreads();
         if (y0 < H) {  // uniform across the wave
