@@ -132,7 +132,7 @@ struct SceneView {
 // Field layout fields of `v` for shape `c` (built for the scene's radius).
 void set_view_layout(SceneView &v, const ListCfg &c, const float *tab);
 
-// Workgroups of a scene in the decide and commit launches.
+// Workgroups of a scene in the decide launches and in a batch's commit launch.
 int decide_blocks(int N);
 int commit_blocks(int N);
 
