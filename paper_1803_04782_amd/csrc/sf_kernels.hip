@@ -1176,7 +1176,69 @@ __global__ __launch_bounds__(kDecideThreads) void k_decide_claim(
             unsigned int nb3[3];
             float pv[3][3];
             int col[3], row[3];
-            if (v.periodic) {
+            if (v.periodic && W >= 3 && wpr >= 2) {
+                col[0] = x == 0 ? W - 1 : x - 1;
+                col[1] = x;
+                col[2] = x == W - 1 ? 0 : x + 1;
+                // per row, issued unconditionally and waited for once: the
+                // three field values from column xb0 (x - 1 clamped into
+                // [0, W - 3]), the bitmap word pair from word wp0 (holding
+                // column x and the word on the side of x's nearer word edge),
+                // and the field value and bitmap word of column xs, the
+                // neighbour across the seam of a lane at x = 0 or W - 1
+                const int w = x >> 6, b = x & 63;
+                const int xb0 = min(max(x - 1, 0), W - 3);
+                const int wp0 = min(max(b < 32 ? w - 1 : w, 0), wpr - 2);
+                const int xs = x == 0 ? W - 1 : 0, ws = xs >> 6;
+                unsigned long long q0[3], q1[3], qs[3];
+                float t0[3], t1[3], t2[3], ts[3];
+#pragma unroll
+                for (int r = 0; r < 3; ++r) {
+                    int yy = y - 1 + r;
+                    yy += yy < 0 ? H : (yy >= H ? -H : 0);
+                    row[r] = yy;
+                    const size_t rw = (size_t)yy * wpr;
+                    q0[r] = occ[rw + wp0];
+                    q1[r] = occ[rw + wp0 + 1];
+                    qs[r] = occ[rw + ws];
+                    const size_t rp = (size_t)yy * W;
+                    t0[r] = P[rp + xb0];
+                    t1[r] = P[rp + xb0 + 1];
+                    t2[r] = P[rp + xb0 + 2];
+                    ts[r] = P[rp + xs];
+                }
+#pragma unroll
+                for (int r = 0; r < 3; ++r) {
+                    asm volatile("" : "+v"(q0[r]), "+v"(q1[r]), "+v"(qs[r]));
+                    asm volatile("" : "+v"(t0[r]), "+v"(t1[r]), "+v"(t2[r]), "+v"(ts[r]));
+                }
+                const bool mid_first = wp0 == w;
+                const int sh = x - 1 - xb0;  // -1 at x = 0, +1 at x = W - 1, else 0
+#pragma unroll
+                for (int r = 0; r < 3; ++r) {
+                    const unsigned long long mid = mid_first ? q0[r] : q1[r];
+                    // the pair's other word: w - 1 when b = 0 < x, w + 1 when
+                    // b = 63 and x < W - 1
+                    const unsigned long long oth = mid_first ? q1[r] : q0[r];
+                    const unsigned int cl =
+                        x == 0 ? (unsigned int)(qs[r] >> (xs & 63)) & 1u
+                               : (b > 0 ? (unsigned int)(mid >> (b - 1)) & 1u
+                                        : (unsigned int)(oth >> 63));
+                    const unsigned int cc = (unsigned int)(mid >> b) & 1u;
+                    const unsigned int cr =
+                        x == W - 1 ? (unsigned int)qs[r] & 1u
+                                   : (b < 63 ? (unsigned int)(mid >> (b + 1)) & 1u
+                                             : (unsigned int)oth & 1u);
+                    nb3[r] = cl | (cc << 1) | (cr << 2);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        const int k = c + sh;
+                        const float tv = k <= 0 ? t0[r] : (k == 1 ? t1[r] : t2[r]);
+                        pv[r][c] = (c == 0 && x == 0) || (c == 2 && x == W - 1) ? ts[r] : tv;
+                    }
+                }
+            } else if (v.periodic) {
+                // tori narrower than 3 su or one bitmap word
                 col[0] = x == 0 ? W - 1 : x - 1;
                 col[1] = x;
                 col[2] = x == W - 1 ? 0 : x + 1;
