@@ -1371,11 +1371,11 @@ __global__ __launch_bounds__(commit_threads<MULTI>()) void k_commit(SceneView on
                                    ctr = to_global(v.ctr);
     bool was_live = false, won = false, left = false;
     if (i < v.N) {
-        // independent loads first (one round trip), then the claim word
+        // independent loads first (one round trip), then, for movers, the
+        // claim word, the exit flag and the mover's own key together
         const int p = pos[i];
         const uint8_t f = flags[i];
         const int tgt = target[i];
-        const unsigned long long kk = key[i];
         if (p < 0) {
             target[i] = -1;
             flags[i] = 0;
@@ -1386,6 +1386,7 @@ __global__ __launch_bounds__(commit_threads<MULTI>()) void k_commit(SceneView on
                 // also resets the word, which losers then read as "not mine"
                 const unsigned long long cw = claim[tgt];
                 const bool to_exit = exitm[tgt] != 0;
+                const unsigned long long kk = key[i];
                 if (cw == kk) {
                     won = true;
                     claim[tgt] = ~0ull;
