@@ -6,8 +6,10 @@ through it.  The arithmetic lives in ``sf_oracle.c`` (plain C, FP64, compiled
 with gcc, no fast-math); this module only marshals numpy arrays.
 
 Every function follows the model readings stated at the top of
-``sf_oracle.c``: field law phi(d) = k*|d|^alpha on the (2R+1)^2 window with
-phi(0) = 0 (section 3.1, Fig. 1 caption and Table I's 1x1 entry), the
+``sf_oracle.c``: field law phi(d) = fl32(k*|d|^alpha) on the (2R+1)^2 window
+with phi(0) = 0 (section 3.1, Fig. 1 caption and Table I's 1x1 entry; the
+strengths are FP32 numbers like the float caches of Algorithms 2 and 3, and
+every sum of them is formed exactly in FP64), the
 destination field as 8-neighbour BFS distance to the openings, linear
 superposition of all fields (Algorithms 2/3: only the total matters), the
 tick of Algorithm 1 (decide, register-and-elect, move), and Philox4x32-10 keys

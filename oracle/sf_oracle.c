@@ -23,10 +23,15 @@
  *   - openings remove the pedestrians that enter them (Fig. 6 caption, task 11).
  *
  * Readings taken where the paper is silent (listed in the design notes):
- *   field law      phi(d) = k * |d|_2^alpha for 0 < |d|_inf <= R, phi(0) = 0
- *                  (the paper quotes k = 1, alpha = -0.5 for the 7x7 recurrent
- *                  repulsive field of Fig. 1 and states a 1x1 geometry has no
- *                  fan-out, i.e. no strength at the field's own centre);
+ *   field law      phi(d) = fl32(k * |d|_2^alpha) for 0 < |d|_inf <= R,
+ *                  phi(0) = 0 (the paper quotes k = 1, alpha = -0.5 for the
+ *                  7x7 recurrent repulsive field of Fig. 1 and states a 1x1
+ *                  geometry has no fan-out, i.e. no strength at the field's own
+ *                  centre); strengths are FP32 numbers, as in the paper's
+ *                  float caches (Algorithms 2 and 3);
+ *   sums           every field is summed in FP64; for the laws and radii used
+ *                  here each sum of FP32 strengths is exact (their exponents
+ *                  span few binades), so the summation order does not matter;
  *   regulation     identity; no local-density term; P = w_D*D + O + Phi;
  *   candidates     own su, plus each Moore neighbour that is inside the grid,
  *                  not an obstacle and unoccupied at the start of the tick;
@@ -75,14 +80,17 @@ static const int DIR_Y[9] = {0, 0, 1, 1, 1, 0, -1, -1, -1};
 
 /* ---- field law ---------------------------------------------------------- */
 
-/* phi at offset (dx, dy) for a field of half-width R (0 outside the window). */
+/* phi at offset (dx, dy) for a field of half-width R (0 outside the window).
+ * The strength is an FP32 number: the law is evaluated in FP64 and rounded
+ * once to FP32, the precision of the paper's field caches (the float cache[]
+ * of Algorithm 2 and float s[K] of Algorithm 3).  Returned as a double. */
 double orc_phi(int dx, int dy, int R, double k, double alpha)
 {
     int adx = dx < 0 ? -dx : dx, ady = dy < 0 ? -dy : dy;
     if (adx > R || ady > R) return 0.0;
     if (dx == 0 && dy == 0) return 0.0;
     double dist = sqrt((double)dx * dx + (double)dy * dy);
-    return k * pow(dist, alpha);
+    return (double)(float)(k * pow(dist, alpha));
 }
 
 /* Full (2R+1)^2 stamp, row-major [dy+R][dx+R]. */

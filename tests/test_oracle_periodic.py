@@ -22,14 +22,14 @@ DIRS = oracle.DIRS
 
 
 def _stamp(R, k=1.0, alpha=-0.5):
-    # the field law written out independently of the oracle
+    # the field law written out independently of the oracle: FP32 strengths
     d = np.arange(-R, R + 1)
     dx, dy = np.meshgrid(d, d)
     r = np.hypot(dx, dy)
     with np.errstate(divide="ignore"):
         s = k * np.where(r > 0, r, 1.0) ** alpha
     s[R, R] = 0.0
-    return s  # [dy + R, dx + R]
+    return s.astype(np.float32).astype(np.float64)  # [dy + R, dx + R]
 
 
 @pytest.mark.parametrize("seed", range(6))
