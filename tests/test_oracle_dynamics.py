@@ -213,3 +213,57 @@ def test_golden_scene(orc, name):
         else:
             x, y = (int(v) for v in want.split(","))
             assert r.pos[i] == y * W + x, (name, key, r.pos[i] % W, r.pos[i] // W)
+
+
+# ---- edges of the near-tie band ------------------------------------------------
+
+BAND_SCENES = [("near_tie_d200_in.scene", 0.9e-5), ("near_tie_d200_out.scene", 1.1e-5),
+               ("near_tie_floor_in.scene", 0.9e-5), ("near_tie_floor_out.scene", 1.1e-5)]
+
+
+@pytest.mark.parametrize("name,ratio", BAND_SCENES)
+def test_near_tie_band_edges(orc, name, ratio):
+    """The golden scenes sit just inside (0.9e-5) and just outside (1.1e-5) the
+    band, once with |u| near 200 (the scale is max(|u1|, |u2|)) and once with
+    |u| below 1 (the floor of 1 applies).  Their candidate values are written
+    out here independently of the oracle (Chebyshev distance to the exit in an
+    empty room, obstacle strengths as FP32 numbers summed by brute force; the
+    pedestrian's own field cancels), the gap ratio is checked, and the oracle's
+    flag must be the band's verdict.  An absolute band, a ten times wider band
+    or a band without the floor of 1 each flips one of the four verdicts."""
+    sc, t, expect = _load_golden(name)
+    W, H = sc.width, sc.height
+    x0, y0 = int(sc.pos[0] % W), int(sc.pos[0] // W)
+    exits = [(c % W, c // W) for c in np.flatnonzero(sc.exit)]
+    obst = [(c % W, c // W) for c in np.flatnonzero(sc.obstacle)]
+    Ro = sc.r_obs
+
+    def dist(x, y):
+        return min(max(abs(x - ex), abs(y - ey)) for ex, ey in exits)
+
+    def obstacle_field(x, y):
+        v = 0.0
+        for ox, oy in obst:
+            dx, dy = x - ox, y - oy
+            if max(abs(dx), abs(dy)) <= Ro and (dx or dy):
+                v += float(np.float32(sc.k_obs * np.hypot(dx, dy) ** sc.alpha_obs))
+        return v
+
+    vals = []
+    for dx, dy in oracle_dirs():
+        x, y = x0 + dx, y0 + dy
+        if sc.obstacle[y * W + x]:
+            continue
+        vals.append(sc.w_dest * dist(x, y) + obstacle_field(x, y))
+    u1, u2 = sorted(vals)[:2]
+    scale = max(abs(u1), abs(u2), 1.0)
+    assert abs((u2 - u1) / scale - ratio) < 0.02 * ratio
+    band_says = (u2 - u1) <= 1e-5 * scale
+    assert band_says == (expect["tied a"] == "yes")
+    st = orc.statics(sc)
+    r = orc.step(st, sc.pos, t)
+    assert bool(r.tied[0]) == band_says
+
+
+def oracle_dirs():
+    return ((0, 0), (1, 0), (1, 1), (0, 1), (-1, 1), (-1, 0), (-1, -1), (0, -1), (1, -1))
