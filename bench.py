@@ -525,9 +525,10 @@ def main():
     contrib_per_launch = (s2["ped_steps"] / max(args.steps, 1)) * window_contributions(sc)
     sup_us = field_loop_us
     achieved = contrib_per_launch / (sup_us * 1e-6) / 1e12
-    # algorithmic bytes of one superposition launch: S read and P written once
+    # algorithmic bytes of one superposition launch: S (FP64) read and P
+    # (FP32) written once, the bitmap read once
     # per su, the occupancy bitmap read once
-    alg_bytes = 8.0 * sc.width * sc.height + 8.0 * ((sc.width + 63) // 64) * sc.height
+    alg_bytes = 12.0 * sc.width * sc.height + 8.0 * ((sc.width + 63) // 64) * sc.height
     roofline = {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / ALU_PEAK_TFLOPS,
                 "traffic": traffic_per_launch(), "kernel": "superpose",

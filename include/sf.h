@@ -10,12 +10,17 @@
  * write-back as a sum of per-source contributions.
  *
  * Readings taken where the paper is silent:
- *   - field law phi(d) = k*|d|_2^alpha on the square window |d|_inf <= R and
- *     phi(0) = 0 (Fig. 1 caption: k = 1, alpha = -0.5; Table I: a 1x1 field
- *     has no fan-out);
+ *   - field law phi(d) = fl32(k*|d|_2^alpha) on the square window
+ *     |d|_inf <= R and phi(0) = 0 (Fig. 1 caption: k = 1, alpha = -0.5;
+ *     Table I: a 1x1 field has no fan-out); strengths are FP32 numbers, the
+ *     precision of the float caches of Algorithms 2 and 3;
  *   - static destination field D = 8-neighbour unit-cost BFS distance to the
  *     exits; static obstacle field O = the same law summed over obstacle su;
- *   - total field P = w_dest*D + O + Phi, +inf on obstacle su, FP32;
+ *   - total field P = fl32(S + Phi) with S = w_dest*D + O in FP64 and Phi the
+ *     sum of the pedestrians' strengths formed in FP64, +inf on obstacle su.
+ *     For the laws used here (nonzero strengths within a factor 2^16 of one
+ *     another, windows up to (2*48+1)^2) every such sum is exact, so P is the
+ *     FP64 field rounded once to FP32 whatever the order of the terms;
  *   - a pedestrian at x chooses, among x and its free in-grid non-obstacle
  *     Moore neighbours y, the minimum of u(y) = P(y) - phi(y - x), lowest
  *     direction index on exact ties; direction order stay, (1,0), (1,1),
@@ -42,7 +47,7 @@
  *   - Calls on different scenes may run on different threads; calls on one
  *     scene must not overlap.
  *   - Environment overrides read by sf_create_scene, for tuning only (results
- *     do not depend on them bit for bit): SF_TILE="TWxHLxVECxNW[xCAP]" (field
+ *     do not depend on them bit for bit): SF_TILE="TWxHLx2xNW[xCAP]" (field
  *     tile shape and source-list capacity), SF_FIELD_BLOCKS_PER_CU (field
  *     workgroups per compute unit) and SF_FIELD_DENSE=0/1 (the dense
  *     small-radius field stencil off / on where the radius allows it).
@@ -163,10 +168,11 @@ int sf_positions(const sf_scene *s, int32_t *pos, uint8_t *alive, int dst_on_dev
  * convention as sf_field.  Before the first tick all entries are zero. */
 int sf_last_moves(const sf_scene *s, int32_t *target, uint8_t *flags, int dst_on_device);
 
-/* Copy the static fields: S = fl32(w_dest*D + O) (float32 [height*width], +inf
- * on obstacles) and D (int32 [height*width], -1 on obstacles).  Either pointer
- * may be NULL.  Same dst_on_device convention as sf_field. */
-int sf_static_field(const sf_scene *s, float *S, int32_t *D, int dst_on_device);
+/* Copy the static fields (section 2: the openings' attractive and the
+ * obstacles' repulsive field): S = w_dest*D + O (float64 [height*width],
+ * +inf on obstacles) and D (int32 [height*width], -1 on obstacles).  Either
+ * pointer may be NULL.  Same dst_on_device convention as sf_field. */
+int sf_static_field(const sf_scene *s, double *S, int32_t *D, int dst_on_device);
 
 /* Replace the pedestrian state (checkpoint resume): host positions by id
  * (int32 [n_peds], -1 = evacuated; live ones distinct, on free non-exit su)
@@ -237,8 +243,9 @@ typedef struct sf_batch sf_batch; /* opaque, library-owned */
  * default). */
 typedef struct {
     int32_t tw, hl, vec, nw;   /* field kernel: strip width in su, rows per lane,
-                                  LDS vector width, waves per workgroup; one of
-                                  the compiled shapes, or all four zero        */
+                                  stamp entries per LDS read (2), waves per
+                                  workgroup; one of the compiled shapes, or all
+                                  four zero (vec 0 reads as 2)                 */
     int32_t list_cap;          /* field kernel: source-list entries in LDS      */
     int32_t blocks_per_cu;     /* field kernel: workgroups per compute unit     */
     int32_t items_per_block;   /* field kernel: work items (runs of strips of

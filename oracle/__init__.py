@@ -39,7 +39,8 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp"
         subprocess.run(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
-                        "-fno-fast-math", "-Wall", "-o", tmp, _SRC, "-lm"], check=True)
+                        "-fno-fast-math", "-Wall", "-pthread", "-o", tmp, _SRC, "-lm"],
+                       check=True)
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
@@ -62,7 +63,9 @@ def _load():
     lib.orc_source_field.restype = None
     lib.orc_source_field.argtypes = [i32, i32, P, i32, f64, f64, i32, P]
     lib.orc_total_field.restype = None
-    lib.orc_total_field.argtypes = [i32, i32, P, P, P, f64, i32, P, i32, f64, f64, i32, P]
+    lib.orc_total_field.argtypes = [i32, i32, P, P, P, f64, i32, P, i32, f64, f64, i32, i32, P]
+    lib.orc_source_field_mt.restype = None
+    lib.orc_source_field_mt.argtypes = [i32, i32, P, i32, f64, f64, i32, i32, P]
     lib.orc_philox4x32_10.restype = None
     lib.orc_philox4x32_10.argtypes = [P, P, P]
     lib.orc_claim_key.restype = u64
@@ -111,12 +114,26 @@ def bfs_distance(W: int, H: int, obstacle, exitm):
 
 
 def source_field(W: int, H: int, src_mask, R: int, k: float, alpha: float,
-                 periodic: bool = False) -> np.ndarray:
+                 periodic: bool = False, threads: int = 1) -> np.ndarray:
+    """Superposed field of the sources (serial scatter, or row bands on
+    `threads` threads: the same bits)."""
     src = _c(src_mask, np.uint8)
     out = np.empty(W * H, dtype=np.float64)
-    _load().orc_source_field(W, H, _ptr(src), int(R), float(k), float(alpha), int(periodic),
-                             _ptr(out))
+    if threads > 1:
+        _load().orc_source_field_mt(W, H, _ptr(src), int(R), float(k), float(alpha),
+                                    int(periodic), int(threads), _ptr(out))
+    else:
+        _load().orc_source_field(W, H, _ptr(src), int(R), float(k), float(alpha),
+                                 int(periodic), _ptr(out))
     return out
+
+
+def host_threads() -> int:
+    """Host cores this process may use (the threaded field's default)."""
+    try:
+        return max(1, len(os.sched_getaffinity(0)))
+    except AttributeError:
+        return max(1, os.cpu_count() or 1)
 
 
 @dataclass
@@ -160,8 +177,9 @@ class Statics:
         return s
 
 
-def statics(scene, with_obstacle_field: bool = True) -> Statics:
-    """Static fields of a scene (any object with the Scene attributes)."""
+def statics(scene, with_obstacle_field: bool = True, threads: int = 1) -> Statics:
+    """Static fields of a scene (any object with the Scene attributes); the
+    obstacle field on `threads` threads (the same bits)."""
     W, H = int(scene.width), int(scene.height)
     ob = _c(scene.obstacle, np.uint8)
     ex = _c(scene.exit, np.uint8)
@@ -172,7 +190,7 @@ def statics(scene, with_obstacle_field: bool = True) -> Statics:
     else:
         D, unreach = bfs_distance(W, H, ob, ex)
     R_obs = int(scene.radius if getattr(scene, "radius_obs", -1) < 0 else scene.radius_obs)
-    O = (source_field(W, H, ob, R_obs, scene.k_obs, scene.alpha_obs, periodic)
+    O = (source_field(W, H, ob, R_obs, scene.k_obs, scene.alpha_obs, periodic, threads)
          if with_obstacle_field else None)
     hd = getattr(scene, "heading", None)
     wp = getattr(scene, "walk_period", None)
@@ -184,13 +202,14 @@ def statics(scene, with_obstacle_field: bool = True) -> Statics:
                    None if wp is None else _c(wp, np.uint8))
 
 
-def total_field(st: Statics, pos) -> np.ndarray:
-    """P = w_D*D + O + Phi(pos) in FP64, +inf on obstacles."""
+def total_field(st: Statics, pos, threads: int = 1) -> np.ndarray:
+    """P = w_D*D + O + Phi(pos) in FP64, +inf on obstacles (Phi on `threads`
+    threads: the same bits)."""
     p = _c(pos, np.int32)
     P = np.empty(st.W * st.H, dtype=np.float64)
     _load().orc_total_field(st.W, st.H, _ptr(st.obstacle), _ptr(st.D), _ptr(_c(st.O, np.float64)),
                             st.w_dest, p.shape[0], _ptr(p), st.R, st.k, st.alpha,
-                            int(st.periodic), _ptr(P))
+                            int(st.periodic), int(threads), _ptr(P))
     return P
 
 
@@ -220,11 +239,13 @@ class StepResult:
     left: int  # pedestrians that left through an exit
 
 
-def step(st: Statics, pos, t: int, P: Optional[np.ndarray] = None) -> StepResult:
-    """One tick from (pos, t).  `pos` is not modified."""
+def step(st: Statics, pos, t: int, P: Optional[np.ndarray] = None,
+         threads: int = 1) -> StepResult:
+    """One tick from (pos, t).  `pos` is not modified.  The step-start field is
+    computed on `threads` threads unless given (the same bits)."""
     newpos = np.array(pos, dtype=np.int32, copy=True)
     if P is None:
-        P = total_field(st, newpos)
+        P = total_field(st, newpos, threads)
     n = newpos.shape[0]
     target = np.empty(n, dtype=np.int32)
     moved = np.empty(n, dtype=np.uint8)

@@ -71,6 +71,7 @@
  * invariants and hand-worked scenes).
  */
 #include <math.h>
+#include <pthread.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -175,6 +176,81 @@ void orc_source_field(int W, int H, const uint8_t *src, int R, double k, double 
     free(tab);
 }
 
+/* The same field computed by `nthreads` POSIX threads, thread j owning a band
+ * of output rows: it scatters every source within R rows of its band, but
+ * writes only the su of its band.  Each su receives the same terms as in the
+ * serial scatter; every sum of FP32 strengths is exact in FP64, so the result
+ * is the serial one bit for bit. */
+typedef struct {
+    int W, H, R, periodic, m, y0, y1;
+    const uint8_t *src;
+    const double *tab;
+    double *out;
+} band_job;
+
+static void *band_scatter(void *arg)
+{
+    const band_job *j = (const band_job *)arg;
+    const int W = j->W, H = j->H, R = j->R, m = j->m;
+    for (int64_t c = (int64_t)j->y0 * W; c < (int64_t)j->y1 * W; ++c) j->out[c] = 0.0;
+    /* source rows whose windows reach the band (each row once, also when the
+     * window wraps around a small torus) */
+    int lo = j->y0 - R, hi = j->y1 - 1 + R;
+    if (!j->periodic) {
+        if (lo < 0) lo = 0;
+        if (hi > H - 1) hi = H - 1;
+    } else if (hi - lo + 1 > H) {
+        lo = 0;
+        hi = H - 1;
+    }
+    for (int ry = lo; ry <= hi; ++ry) {
+        const int sy = j->periodic ? ((ry % H) + H) % H : ry;
+        for (int sx = 0; sx < W; ++sx) {
+            if (!j->src[(int64_t)sy * W + sx]) continue;
+            for (int dy = -R; dy <= R; ++dy) {
+                int y = sy + dy;
+                if (j->periodic)
+                    y = ((y % H) + H) % H;
+                else if (y < 0 || y >= H)
+                    continue;
+                if (y < j->y0 || y >= j->y1) continue;
+                for (int dx = -R; dx <= R; ++dx) {
+                    int x = sx + dx;
+                    if (j->periodic)
+                        x = ((x % W) + W) % W;
+                    else if (x < 0 || x >= W)
+                        continue;
+                    j->out[(int64_t)y * W + x] += j->tab[(dy + R) * m + (dx + R)];
+                }
+            }
+        }
+    }
+    return NULL;
+}
+
+void orc_source_field_mt(int W, int H, const uint8_t *src, int R, double k, double alpha,
+                         int periodic, int nthreads, double *out)
+{
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > H) nthreads = H;
+    int m = 2 * R + 1;
+    double *tab = (double *)malloc(sizeof(double) * (size_t)m * m);
+    orc_phi_table(R, k, alpha, tab);
+    band_job *jobs = (band_job *)malloc(sizeof(band_job) * (size_t)nthreads);
+    pthread_t *th = (pthread_t *)malloc(sizeof(pthread_t) * (size_t)nthreads);
+    for (int t = 0; t < nthreads; ++t) {
+        band_job j = {W, H, R, periodic, m, (int)((int64_t)H * t / nthreads),
+                      (int)((int64_t)H * (t + 1) / nthreads), src, tab, out};
+        jobs[t] = j;
+    }
+    for (int t = 1; t < nthreads; ++t) pthread_create(&th[t], NULL, band_scatter, &jobs[t]);
+    band_scatter(&jobs[0]);
+    for (int t = 1; t < nthreads; ++t) pthread_join(th[t], NULL);
+    free(th);
+    free(jobs);
+    free(tab);
+}
+
 /* Occupancy mask from positions (pos < 0: evacuated). */
 void orc_occupancy(int W, int H, int32_t n_peds, const int32_t *pos, uint8_t *occ)
 {
@@ -184,15 +260,20 @@ void orc_occupancy(int W, int H, int32_t n_peds, const int32_t *pos, uint8_t *oc
 }
 
 /* P[c] = w_D*D[c] + O[c] + Phi[c] on non-obstacle su, +inf on obstacles.
- * Phi is the superposed pedestrian field of the live pedestrians. */
+ * Phi is the superposed pedestrian field of the live pedestrians, computed
+ * by one thread or, with nthreads > 1, by the row-band threads above (the
+ * same bits). */
 void orc_total_field(int W, int H, const uint8_t *obst, const int32_t *D, const double *O,
                      double w_dest, int32_t n_peds, const int32_t *pos, int R, double k,
-                     double alpha, int periodic, double *P)
+                     double alpha, int periodic, int nthreads, double *P)
 {
     int64_t n = (int64_t)W * H;
     uint8_t *occ = (uint8_t *)malloc((size_t)(n > 0 ? n : 1));
     orc_occupancy(W, H, n_peds, pos, occ);
-    orc_source_field(W, H, occ, R, k, alpha, periodic, P);
+    if (nthreads > 1)
+        orc_source_field_mt(W, H, occ, R, k, alpha, periodic, nthreads, P);
+    else
+        orc_source_field(W, H, occ, R, k, alpha, periodic, P);
     for (int64_t c = 0; c < n; ++c)
         P[c] = obst[c] ? INFINITY : w_dest * (double)D[c] + O[c] + P[c];
     free(occ);

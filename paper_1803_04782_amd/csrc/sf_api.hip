@@ -72,8 +72,9 @@ struct sf_scene {
     int wpr = 0;          // 64-bit words per bitmap row
     ListCfg lc;           // pedestrian field launch shape
     float phi_axial = 0.f, phi_diag = 0.f;
-    // device state
-    float *S = nullptr, *P = nullptr, *tab = nullptr;
+    // device state: S = w_dest*D + O (FP64), P = fl32(S + Phi), the stamp
+    double *S = nullptr, *tab = nullptr;
+    float *P = nullptr;
     int32_t *D = nullptr;
     uint8_t *exitm = nullptr;
     unsigned long long *occ = nullptr, *claim = nullptr, *key = nullptr;
@@ -100,6 +101,7 @@ struct sf_scene {
     // view (S = P, sources = the su entered, moved_from = the su left)
     int refresh = 0, since_full = 0;
     unsigned long long *moved_from = nullptr, *moved_to = nullptr;
+    double *phi = nullptr;  // exact pedestrian field (FP64) kept for the updates
     SceneView view_upd = {};
     FieldLaunch fl;
     // batch membership: while a batch holds the scene, `stream` is the
@@ -204,6 +206,33 @@ struct DeviceGuard {
         if (prev >= 0) (void)hipSetDevice(prev);
     }
 };
+
+// Stamp of the law phi(d) = k*|d|_2^alpha on the window |d|_inf <= R (zero at
+// d = 0 and outside it), each strength rounded once to FP32 and held as a
+// double: entry (dx, dy) at (dx + padx)*stride + dy + pady of a column-major
+// table of n doubles with ncols columns of nrows used rows, zero elsewhere.
+std::vector<double> stamp_table(int R, double k, double alpha, int ncols, int nrows, int stride,
+                                int padx, int pady, size_t n)
+{
+    std::vector<double> t(n, 0.0);
+    for (int ci = 0; ci < ncols; ++ci)
+        for (int ri = 0; ri < nrows; ++ri) {
+            const int dx = ci - padx, dy = ri - pady;
+            if (std::abs(dx) > R || std::abs(dy) > R || (dx == 0 && dy == 0)) continue;
+            const double dist = std::sqrt((double)dx * dx + (double)dy * dy);
+            t[(size_t)ci * stride + ri] = (double)(float)(k * std::pow(dist, alpha));
+        }
+    return t;
+}
+
+// Copy a host table to the device and wait for the copy.
+int upload_table(double *dst, const std::vector<double> &t, hipStream_t st)
+{
+    SF_HIP(hipMemcpyAsync(dst, t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice, st),
+           "copy stamp");
+    SF_HIP(hipStreamSynchronize(st), "stamp sync");
+    return SF_OK;
+}
 
 int validate(const sf_scene_desc *d)
 {
@@ -352,7 +381,8 @@ int build_statics(sf_scene *s, const uint8_t *h_obst, const uint8_t *h_exit)
     if (s->periodic) {
         // a torus without obstacles or openings: no static field
         SF_HIP(sf::launch_fill_i32(s->D, (size_t)n, 0, st), "destination field");
-        SF_HIP(sf::launch_fill_i32(reinterpret_cast<int32_t *>(s->S), (size_t)n, 0, st),
+        SF_HIP(sf::launch_fill_u64(reinterpret_cast<unsigned long long *>(s->S), (size_t)n, 0ull,
+                                   st),
                "static field");
         SF_HIP(hipMemcpyAsync(s->exitm, h_exit, (size_t)n, hipMemcpyHostToDevice, st),
                "copy exits");
@@ -412,7 +442,8 @@ int build_statics(sf_scene *s, const uint8_t *h_obst, const uint8_t *h_exit)
     if (unreachable)
         return fail(SF_EUNREACHABLE, "%lld free su cannot reach any exit", unreachable);
 
-    // obstacle field in FP64, fused with the destination field into S
+    // obstacle field (exact FP64 sums of FP32 strengths), fused with the
+    // destination field into S
     const SupCfg oc = sf::make_sup_cfg(s->R_obs, 8, 1, sizeof(double));
     SupCfg ocg = oc;
     if ((rc = dalloc(s, &tab64, (size_t)oc.ncols * oc.stride, "obstacle table")) ||
@@ -429,7 +460,12 @@ int build_statics(sf_scene *s, const uint8_t *h_obst, const uint8_t *h_exit)
         SF_HIP(sf::set_superpose_lds_limit((size_t)max_lds), "LDS limit");
         ocg.grid = std::max(1, s->ncu * (int)std::max<size_t>(1, (size_t)max_lds / oc.lds_bytes));
     }
-    SF_HIP(sf::launch_phi_table_f64(tab64, oc, s->k_obs, s->alpha_obs, st), "obstacle table");
+    if ((rc = upload_table(tab64,
+                           stamp_table(s->R_obs, s->k_obs, s->alpha_obs, oc.ncols, oc.nrows,
+                                       oc.stride, oc.padx, oc.pady,
+                                       (size_t)oc.ncols * oc.stride),
+                           st)))
+        return rc;
     SF_HIP(sf::launch_superpose_f64(ocg, obits, s->wpr, tab64, O, W, H, st), "obstacle field");
     SF_HIP(sf::launch_static_S(s->D, O, obst, s->w_dest, s->S, n, st), "static field");
     SF_HIP(hipStreamSynchronize(st), "statics sync");
@@ -558,9 +594,9 @@ int create(const sf_scene_desc *d, void *hip_stream, sf_scene **out)
         const int got = std::sscanf(e, "%dx%dx%dx%dx%d", &a, &b, &v, &w, &cap);
         if (got != 4 && got != 5)
             return fail(SF_EINVAL, "SF_TILE=%s is not of the form TWxHLxVECxNW[xCAP]", e);
-        if (!sf::list_shape_compiled(a, b, v, w) || cap < 1 || cap > (1 << 16))
+        if (v != 2 || !sf::list_shape_compiled(a, b, w) || cap < 1 || cap > (1 << 16))
             return fail(SF_EINVAL, "SF_TILE=%s is not a compiled shape", e);
-        s->lc = sf::make_list_cfg(s->R, a, b, v, w, cap);
+        s->lc = sf::make_list_cfg(s->R, a, b, w, cap);
         if (s->lc.halo_rows > 64 * w)
             return fail(SF_EINVAL, "SF_TILE=%s does not fit radius %d", e, s->R);
     }
@@ -574,8 +610,8 @@ int create(const sf_scene_desc *d, void *hip_stream, sf_scene **out)
         // would run as a partial second round
         int per_cu = (int)std::max<size_t>(1, (size_t)(160 * 1024) / s->lc.lds_bytes);
         per_cu = std::min(per_cu, std::max(1, 32 / (s->lc.nw)));
-        const int resident = sf::field_resident_blocks(s->lc.tw, s->lc.hl, s->lc.vec, s->lc.nw,
-                                                       s->lc.lds_bytes, false);
+        const int resident =
+            sf::field_resident_blocks(s->lc.tw, s->lc.hl, s->lc.nw, s->lc.lds_bytes, false);
         if (resident > 0) per_cu = std::min(per_cu, resident);
         if (const char *e = std::getenv("SF_FIELD_BLOCKS_PER_CU")) {
             // override of the field kernel's persistent workgroups per CU (speed only)
@@ -591,7 +627,7 @@ int create(const sf_scene_desc *d, void *hip_stream, sf_scene **out)
     const size_t N = (size_t)s->N;
     if ((rc = dalloc(s, &s->S, n, "S")) || (rc = dalloc(s, &s->P, n, "P")) ||
         (rc = dalloc(s, &s->D, n, "D")) || (rc = dalloc(s, &s->exitm, n, "exit mask")) ||
-        (rc = dalloc(s, &s->tab, (size_t)s->lc.vec * s->lc.copy_elems, "phi table")) ||
+        (rc = dalloc(s, &s->tab, (size_t)s->lc.tab_elems, "phi table")) ||
         (rc = dalloc(s, &s->occ, (size_t)s->wpr * s->H, "occupancy")) ||
         (rc = dalloc(s, &s->claim, n, "claims")) || (rc = dalloc(s, &s->key, N, "keys")) ||
         (rc = dalloc(s, &s->pos, N, "positions")) || (rc = dalloc(s, &s->target, N, "targets")) ||
@@ -607,19 +643,18 @@ int create(const sf_scene_desc *d, void *hip_stream, sf_scene **out)
     SF_HIP(sf::launch_fill_i32(s->target, N, 0, st), "clear targets");
     SF_HIP(sf::launch_fill_i32(reinterpret_cast<int32_t *>(s->flags), (N + 3) / 4, 0, st),
            "clear flags");
-    SF_HIP(sf::launch_phi_copies(s->tab, s->lc, s->k, s->alpha, st), "phi table");
+    {
+        const ListCfg &c = s->lc;
+        const std::vector<double> t = stamp_table(s->R, s->k, s->alpha, c.ncols, c.nrows,
+                                                  c.stride, c.padx, c.pady, (size_t)c.tab_elems);
+        if ((rc = upload_table(s->tab, t, st))) return rc;
+        // own-field values at axial and diagonal neighbours (FP32 numbers)
+        const size_t ia = (size_t)(c.padx + 1) * c.stride + c.pady;
+        s->phi_axial = (float)t[ia];
+        s->phi_diag = (float)t[ia + 1];
+    }
     if ((rc = upload_positions(s, d->pos))) return rc;
     if ((rc = build_statics(s, d->obstacle, d->exit))) return rc;
-    {
-        // own-field values at axial and diagonal neighbours, as the kernels see them
-        const size_t ia = (size_t)(s->lc.padx + 1) * s->lc.stride + s->lc.pady;
-        const size_t id = ia + 1;
-        SF_HIP(hipMemcpyAsync(&s->phi_axial, s->tab + ia, sizeof(float), hipMemcpyDeviceToHost, st),
-               "phi copy");
-        SF_HIP(hipMemcpyAsync(&s->phi_diag, s->tab + id, sizeof(float), hipMemcpyDeviceToHost, st),
-               "phi copy");
-        SF_HIP(hipStreamSynchronize(st), "phi sync");
-    }
     if ((rc = setup_launches(s))) return rc;
     if ((rc = reset_counters(s, s->start_step, 0))) return rc;
     if ((rc = rebuild_dynamic(s))) return rc;
@@ -708,7 +743,8 @@ int set_field_update(sf_scene *s, int32_t refresh)
         const size_t nwords = (size_t)s->wpr * s->H;
         int rc;
         if ((rc = dalloc(s, &s->moved_from, nwords, "moved bitmap")) ||
-            (rc = dalloc(s, &s->moved_to, nwords, "moved bitmap")))
+            (rc = dalloc(s, &s->moved_to, nwords, "moved bitmap")) ||
+            (rc = dalloc(s, &s->phi, (size_t)s->W * s->H, "pedestrian field")))
             return rc;
         SF_HIP(sf::launch_fill_u64(s->moved_from, nwords, 0ull, s->stream), "clear moves");
         SF_HIP(sf::launch_fill_u64(s->moved_to, nwords, 0ull, s->stream), "clear moves");
@@ -717,10 +753,11 @@ int set_field_update(sf_scene *s, int32_t refresh)
     SceneView &v = s->view;
     v.moved_from = s->refresh ? s->moved_from : nullptr;
     v.moved_to = s->refresh ? s->moved_to : nullptr;
+    // full superpositions keep the exact pedestrian field while updates use it
+    v.phi = s->refresh ? s->phi : nullptr;
     if (s->refresh) {
-        // the field kernel with S := P (in place) and the moved bitmaps as sources
+        // the field kernel with the moved bitmaps as sources, updating phi in place
         s->view_upd = v;
-        s->view_upd.S = s->P;
         s->view_upd.occ = s->moved_to;
     }
     // the next tick starts a new refresh period from a full field
@@ -809,16 +846,16 @@ int resolve_group_tiling(const sf_batch *b, int R, sf_group_tiling *t, ListCfg *
         const ListCfg d = sf::pick_list_cfg(R, lds_cap);
         t->tw = d.tw;
         t->hl = d.hl;
-        t->vec = d.vec;
         t->nw = d.nw;
         if (t->list_cap == 0) t->list_cap = d.list_cap;
     }
-    if (!sf::list_shape_compiled(t->tw, t->hl, t->vec, t->nw))
+    if (t->vec == 0) t->vec = 2;
+    if (t->vec != 2 || !sf::list_shape_compiled(t->tw, t->hl, t->nw))
         return fail(SF_EINVAL, "tiling %dx%dx%dx%d is not a compiled shape", t->tw, t->hl, t->vec,
                     t->nw);
     if (t->list_cap == 0) {
         for (int cap = 4096; cap >= 512; cap /= 2) {
-            const ListCfg c = sf::make_list_cfg(R, t->tw, t->hl, t->vec, t->nw, cap);
+            const ListCfg c = sf::make_list_cfg(R, t->tw, t->hl, t->nw, cap);
             if (c.lds_bytes <= lds_cap) {
                 t->list_cap = cap;
                 break;
@@ -827,12 +864,12 @@ int resolve_group_tiling(const sf_batch *b, int R, sf_group_tiling *t, ListCfg *
     }
     if (t->list_cap < 0 || t->list_cap > (1 << 16))
         return fail(SF_EINVAL, "list_cap %d outside 0..65536", t->list_cap);
-    const ListCfg c = sf::make_list_cfg(R, t->tw, t->hl, t->vec, t->nw, t->list_cap);
+    const ListCfg c = sf::make_list_cfg(R, t->tw, t->hl, t->nw, t->list_cap);
     if (c.list_cap < 2 * c.max_row || c.halo_rows > 64 * t->nw || c.lds_bytes > lds_cap)
         return fail(SF_EINVAL, "tiling %dx%dx%dx%d with list_cap %d does not fit radius %d",
                     t->tw, t->hl, t->vec, t->nw, t->list_cap, R);
     int bpc_max = std::max(1, std::min((int)((160 * 1024) / c.lds_bytes), 32 / t->nw));
-    const int resident = sf::field_resident_blocks(t->tw, t->hl, t->vec, t->nw, c.lds_bytes, true);
+    const int resident = sf::field_resident_blocks(t->tw, t->hl, t->nw, c.lds_bytes, true);
     if (resident > 0) bpc_max = std::min(bpc_max, resident);  // no partial second round
     if (t->blocks_per_cu == 0) t->blocks_per_cu = bpc_max;
     if (t->blocks_per_cu < 1 || t->blocks_per_cu > 64)
@@ -872,17 +909,21 @@ int build_group(sf_batch *b, const std::vector<int> &members, const sf_group_til
     const int n = (int)members.size();
     std::vector<SceneView> gv((size_t)n);
     std::vector<double> strip_cost((size_t)n);
-    std::map<std::tuple<int, double, double>, float *> tables;
+    std::map<std::tuple<int, double, double>, double *> tables;
     int64_t dec_total = 0, com_total = 0;
     for (int q = 0; q < n; ++q) {
         const sf_scene *s = b->scenes[(size_t)members[(size_t)q]];
-        const ListCfg lc = sf::make_list_cfg(s->R, t.tw, t.hl, t.vec, t.nw, t.list_cap);
+        const ListCfg lc = sf::make_list_cfg(s->R, t.tw, t.hl, t.nw, t.list_cap);
         const auto key = std::make_tuple(s->R, s->k, s->alpha);
-        float *&tab = tables[key];
+        double *&tab = tables[key];
         if (!tab) {
-            if ((rc = balloc(G.bufs, &tab, (size_t)lc.vec * lc.copy_elems, "batch phi table")))
+            if ((rc = balloc(G.bufs, &tab, (size_t)lc.tab_elems, "batch phi table"))) return rc;
+            if ((rc = upload_table(tab,
+                                   stamp_table(s->R, s->k, s->alpha, lc.ncols, lc.nrows,
+                                               lc.stride, lc.padx, lc.pady,
+                                               (size_t)lc.tab_elems),
+                                   st)))
                 return rc;
-            SF_HIP(sf::launch_phi_copies(tab, lc, s->k, s->alpha, st), "batch phi table");
         }
         SceneView v = s->view;
         sf::set_view_layout(v, lc, tab);
@@ -1157,9 +1198,8 @@ int batch_tune(sf_batch *b, int32_t reps, sf_batch_tiling *chosen)
     } ev_guard{&ep};
     if (eb != hipSuccess) return hip_fail(eb, "hipEventCreate");
 
-    static const int shapes[][4] = {{16, 2, 2, 4}, {16, 2, 2, 8}, {16, 4, 2, 4}, {16, 4, 2, 8},
-                                    {16, 4, 4, 4}, {16, 4, 4, 8}, {32, 2, 2, 4}, {32, 2, 2, 8},
-                                    {32, 4, 2, 4}, {32, 4, 4, 4}, {8, 4, 4, 4},  {8, 2, 2, 4}};
+    static const int shapes[][3] = {{16, 2, 4}, {16, 2, 8}, {16, 4, 4}, {16, 4, 8}, {32, 2, 4},
+                                    {32, 2, 8}, {32, 4, 4}, {8, 2, 4},  {8, 4, 4}};
     const int caps[] = {1024, 2048, 4096};
     const int ipbs[] = {2, 8};
     sf_batch_tiling best = b->cur.t;
@@ -1173,8 +1213,8 @@ int batch_tune(sf_batch *b, int32_t reps, sf_batch_tiling *chosen)
                     sf_group_tiling t = b->cur.g[gi].t;
                     t.tw = sh[0];
                     t.hl = sh[1];
-                    t.vec = sh[2];
-                    t.nw = sh[3];
+                    t.vec = 2;
+                    t.nw = sh[2];
                     t.list_cap = cap;
                     t.blocks_per_cu = 0;
                     t.items_per_block = ipb;
@@ -1297,12 +1337,12 @@ int sf_last_moves(const sf_scene *s, int32_t *target, uint8_t *flags, int dst_on
     }
 }
 
-int sf_static_field(const sf_scene *s, float *S, int32_t *D, int dst_on_device)
+int sf_static_field(const sf_scene *s, double *S, int32_t *D, int dst_on_device)
 {
     if (!s) return fail(SF_EINVAL, "scene is NULL");
     DeviceGuard g(s->device);
     const size_t n = (size_t)s->W * s->H;
-    int rc = copy_out(s, S, s->S, n * sizeof(float), dst_on_device);
+    int rc = copy_out(s, S, s->S, n * sizeof(double), dst_on_device);
     if (rc) return rc;
     return copy_out(s, D, s->D, n * sizeof(int32_t), dst_on_device);
 }
@@ -1317,8 +1357,8 @@ int sf_set_state(sf_scene *s, const int32_t *pos, int64_t step)
     try {
         const size_t n = (size_t)s->W * s->H;
         std::vector<uint8_t> obst(n), exitm(n);
-        std::vector<float> S(n);
-        SF_HIP(hipMemcpyAsync(S.data(), s->S, n * sizeof(float), hipMemcpyDeviceToHost, s->stream),
+        std::vector<double> S(n);
+        SF_HIP(hipMemcpyAsync(S.data(), s->S, n * sizeof(double), hipMemcpyDeviceToHost, s->stream),
                "copy S");
         SF_HIP(hipMemcpyAsync(exitm.data(), s->exitm, n, hipMemcpyDeviceToHost, s->stream),
                "copy exits");

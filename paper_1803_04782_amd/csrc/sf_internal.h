@@ -57,37 +57,34 @@ struct SupCfg {
 
 SupCfg make_sup_cfg(int radius, int tw, int hl, size_t elem);
 
-// Launch shape of the per-tick FP32 field kernel (source-list gather).
+// Launch shape of the per-tick field kernel (source-list gather).
 // A workgroup of NW waves covers a TW-column strip of NW*TH rows; wave w owns
 // rows [w*TH, (w+1)*TH).  Lane l owns column l % TW and, with rg = l / TW and
-// G = 64 / TW, the HL consecutive rows rg*HL .. rg*HL + HL-1, so its slice of
-// a source's stamp column is HL contiguous floats read as HL/VEC aligned
-// VEC-wide LDS loads (one contiguous access per lane).  The stamp is kept
-// in VEC copies, copy c shifted down by c rows, so that a source at row py
-// reads copy (py - pady) mod VEC aligned:
-//   copy c, entry (dx, dy) at c*copy_elems + (dx + padx)*stride + dy + pady + c
-//   padx = R + TW (one zero column beyond the halo for padding entries),
-//   pady = R + TH - 1, stride >= 2*pady + VEC, stride = VEC * odd (banks).
+// G = 64 / TW, the HL rows rg + G*r (r < HL), so its entries of a source's
+// stamp column are G apart and each pair is one 8-byte-aligned LDS read.
+// The stamp is held once, column-major, as doubles (FP32 strengths):
+//   entry (dx, dy) at (dx + padx)*stride + dy + pady,
+//   padx = R + TW (one zero column beyond the halo), pady = R + TH - 1,
+//   stride >= 2*pady + 1, chosen so that the 32 lanes of each half-wave read
+//   32 distinct bank pairs.
 // The strip's halo sources are listed in LDS in row-major order; the list
 // holds `list_cap` entries and longer halos are processed in several passes.
 struct ListCfg {
-    int tw = 0, hl = 0, vec = 0, nw = 0;
+    int tw = 0, hl = 0, nw = 0;
     int g = 0, th = 0, wt = 0;
     int radius = 0;
     int padx = 0, pady = 0, ncols = 0, nrows = 0, stride = 0;
-    int copy_elems = 0;  // ncols * stride rounded up to a multiple of 4
+    int tab_elems = 0;   // ncols * stride rounded up to an even count of doubles
     int list_cap = 0;
     int max_row = 0;     // most sources one halo row can hold
     int halo_rows = 0;   // most halo rows of one strip
     size_t lds_bytes = 0;
     int grid = 0;
 };
-ListCfg make_list_cfg(int radius, int tw, int hl, int vec, int nw, int list_cap);
+ListCfg make_list_cfg(int radius, int tw, int hl, int nw, int list_cap);
 // Picks the launch shape for radius R that fits `max_lds` bytes of LDS.
 ListCfg pick_list_cfg(int radius, size_t max_lds);
-bool list_shape_compiled(int tw, int hl, int vec, int nw);
-hipError_t launch_phi_copies(float *tab, const ListCfg &c, double k, double alpha,
-                             hipStream_t st);
+bool list_shape_compiled(int tw, int hl, int nw);
 // Dynamic LDS limit of the field kernels.
 hipError_t set_field_lds_limit(size_t bytes);
 
@@ -99,13 +96,16 @@ struct SceneView {
     int32_t dec_block0;  // first workgroup of this scene in the decide launch
     int32_t com_block0;  // first workgroup of this scene in the commit launch
     // field gather layout of this scene's radius under the launch's tile shape
-    int32_t tiles_x, n_strips, copy_elems, stride;
+    int32_t tiles_x, n_strips, stride;
     int32_t padx, pady, max_row, tab_elems;
     float phi_axial, phi_diag;  // own-field values at axial / diagonal neighbours
     unsigned long long seed;
-    const float *tab;           // tab_elems floats: the VEC stamp copies
-    const float *S;
-    float *P;
+    const double *tab;          // tab_elems doubles: the stamp (FP32 strengths)
+    const double *S;            // static field w_dest*D + O (FP64, +inf on obstacles)
+    float *P;                   // total field fl32(S + Phi)
+    // exact pedestrian field Phi (FP64), kept while the incremental update is
+    // on (written by full superpositions, updated in place), else NULL
+    double *phi;
     unsigned long long *occ, *claim, *key, *ctr;
     // per-pedestrian arrays are indexed by an internal id (pedestrians in
     // row-major order of their positions when the state was set); ext maps
@@ -130,7 +130,7 @@ struct SceneView {
 };
 
 // Field layout fields of `v` for shape `c` (built for the scene's radius).
-void set_view_layout(SceneView &v, const ListCfg &c, const float *tab);
+void set_view_layout(SceneView &v, const ListCfg &c, const double *tab);
 
 // Workgroups of a scene in the decide launches and in a batch's commit launch.
 int decide_blocks(int N);
@@ -142,7 +142,7 @@ int commit_blocks(int N);
 // `tab_max` is the largest tab_elems of the launch's scenes and `halo_max`
 // the largest halo row count; both size the dynamic LDS.
 struct FieldLaunch {
-    int tw = 0, hl = 0, vec = 0, nw = 0;
+    int tw = 0, hl = 0, nw = 0;
     int list_cap = 0, tab_max = 0, halo_max = 0;
     int grid = 0;
     size_t lds_bytes = 0;
@@ -150,7 +150,7 @@ struct FieldLaunch {
 FieldLaunch field_launch_for(const ListCfg &c);  // tab_max/halo_max of c, grid = c.grid
 // Workgroups of the field kernel of this shape that one compute unit holds at
 // once with `lds_bytes` of dynamic LDS (registers and LDS; 0 if unknown).
-int field_resident_blocks(int tw, int hl, int vec, int nw, size_t lds_bytes, bool multi);
+int field_resident_blocks(int tw, int hl, int nw, size_t lds_bytes, bool multi);
 size_t field_lds_bytes(const FieldLaunch &f);
 hipError_t launch_field(const FieldLaunch &f, const SceneView *views, const int32_t *items,
                         int n_items, hipStream_t st, const LaunchEvents *ev = nullptr);
@@ -159,10 +159,10 @@ hipError_t launch_field(const FieldLaunch &f, const SceneView *views, const int3
 // commit launch the scene's own blocks.
 hipError_t launch_field_one(const FieldLaunch &f, const SceneView &view, int per,
                             hipStream_t st, const LaunchEvents *ev = nullptr);
-// Incremental update of a single scene's field in one launch: view.S = view.P
-// (in place), view.occ = bitmap of the su entered, view.moved_from = bitmap
-// of the su left; P = (P + Phi(entered)) - Phi(left), each sum as launch_field_one
-// computes it.
+// Incremental update of a single scene's field in one launch: view.occ =
+// bitmap of the su entered, view.moved_from = bitmap of the su left, view.phi
+// the exact pedestrian field; phi = (phi + Phi(entered)) - Phi(left) in place
+// and P = fl32(S + phi), the same bits as launch_field_one.
 hipError_t launch_field_update(const FieldLaunch &f, const SceneView &view, int per,
                                hipStream_t st, const LaunchEvents *ev = nullptr);
 // Single-scene field by the dense small-radius stencil (radius 1..kDenseMaxRadius),
@@ -180,10 +180,6 @@ hipError_t launch_fill_u64(unsigned long long *p, size_t n, unsigned long long v
 hipError_t launch_fill_i32(int32_t *p, size_t n, int32_t v, hipStream_t st);
 hipError_t launch_mask_to_bits(const uint8_t *mask, unsigned long long *bits, int W, int H,
                                int wpr, hipStream_t st);
-hipError_t launch_phi_table_f32(float *tab, const SupCfg &c, double k, double alpha,
-                                hipStream_t st);
-hipError_t launch_phi_table_f64(double *tab, const SupCfg &c, double k, double alpha,
-                                hipStream_t st);
 // Multi-source BFS of the destination field.  `levels` expansions are
 // enqueued starting at `level0`; frontier sizes live in cnt[3] on the device.
 // Destination-field BFS: D = 0 on exit su, -1 elsewhere; then launch j =
@@ -204,7 +200,7 @@ hipError_t launch_superpose_f64(const SupCfg &c, const unsigned long long *bits,
                                 const double *tab, double *out, int W, int H, hipStream_t st);
 hipError_t set_superpose_lds_limit(size_t f64_bytes);
 hipError_t launch_static_S(const int32_t *D, const double *O, const uint8_t *obst,
-                           double w_dest, float *S, int n, hipStream_t st);
+                           double w_dest, double *S, int n, hipStream_t st);
 hipError_t launch_occ_init(const int32_t *pos, int N, unsigned long long *occ, int wpr, int W,
                            unsigned long long *ctr, hipStream_t st);
 // Decide + claim over `n_blocks` workgroups, decide_blocks(N) per scene.

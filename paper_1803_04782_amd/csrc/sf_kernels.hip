@@ -170,25 +170,6 @@ __global__ void k_mask_to_bits(const uint8_t *__restrict__ mask, unsigned long l
     }
 }
 
-// ---- field law table ----------------------------------------------------------
-
-// Column-major, zero-padded stamp: entry (dx, dy) at (dx+padx)*stride +
-// (dy+pady) holds k*|d|^alpha inside the square window, 0 elsewhere and at
-// d = 0.  Evaluated in FP64 and rounded once to T.
-template <typename T>
-__global__ void k_phi_table(T *tab, int ncols, int nrows, int stride, int padx, int pady, int R,
-                            double k, double alpha)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= ncols * stride) return;
-    const int ci = i / stride, ri = i - ci * stride;
-    const int dx = ci - padx, dy = ri - pady;
-    double v = 0.0;
-    if (ri < nrows && abs(dx) <= R && abs(dy) <= R && (dx != 0 || dy != 0))
-        v = k * pow(sqrt((double)dx * dx + (double)dy * dy), alpha);
-    tab[i] = (T)v;
-}
-
 // ---- destination field: multi-source BFS --------------------------------------
 
 __global__ void k_bfs_seed(const uint8_t *__restrict__ exitm, int32_t *__restrict__ D, int n)
@@ -322,13 +303,15 @@ __global__ void k_count_unreachable(const uint8_t *__restrict__ obst, const int3
     block_sum_add(bad ? 1u : 0u, ctr, kScratch);
 }
 
+// S = fl64(fl64(w_dest*D) + O), +inf on obstacles: the product is rounded
+// before the sum (no fused multiply-add).
 __global__ void k_static_S(const int32_t *__restrict__ D, const double *__restrict__ O,
-                           const uint8_t *__restrict__ obst, double w_dest, float *__restrict__ S,
+                           const uint8_t *__restrict__ obst, double w_dest, double *__restrict__ S,
                            int n)
 {
     const size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= (size_t)n) return;
-    S[c] = obst[c] ? INFINITY : (float)(w_dest * (double)D[c] + O[c]);
+    S[c] = obst[c] ? (double)INFINITY : __dadd_rn(__dmul_rn(w_dest, (double)D[c]), O[c]);
 }
 
 // ---- field superposition --------------------------------------------------------
@@ -339,12 +322,15 @@ __global__ void k_static_S(const int32_t *__restrict__ D, const double *__restri
 // per owned row, at immediate offsets G*r from a single per-source address.
 constexpr int kSupThreads = 256;
 
-template <typename T, int TW, int HL, bool ADD_S>
+// Static fields: out = sum over the set bits of the stamp (FP64 entries holding
+// FP32 strengths, so the sums are exact).
+template <int TW, int HL>
 __global__ __launch_bounds__(kSupThreads) void k_superpose(
-    const unsigned long long *__restrict__ bits, int wpr, const T *__restrict__ tab_g,
-    int tab_elems, int stride, int padx, int pady, int R, const float *__restrict__ S,
-    T *__restrict__ outT, float *__restrict__ outP, int W, int H, int tiles_x, int n_tiles)
+    const unsigned long long *__restrict__ bits, int wpr, const double *__restrict__ tab_g,
+    int tab_elems, int stride, int padx, int pady, int R, double *__restrict__ out, int W, int H,
+    int tiles_x, int n_tiles)
 {
+    typedef double T;
     constexpr int G = 64 / TW;
     constexpr int TH = G * HL;
     constexpr int NW = kSupThreads / 64;
@@ -421,47 +407,43 @@ __global__ __launch_bounds__(kSupThreads) void k_superpose(
 #pragma unroll
         for (int r = 0; r < HL; ++r) {
             const int y = y0 + rg + G * r;
-            if (x < W && y < H) {
-                const size_t c = (size_t)y * W + x;
-                if constexpr (ADD_S)
-                    outP[c] = S[c] + (float)acc[r];
-                else
-                    outT[c] = acc[r];
-            }
+            if (x < W && y < H) out[(size_t)y * W + x] = acc[r];
         }
     }
 }
 
 // ---- per-tick field: source-list gather ---------------------------------------------
 //
+// Exact sums.  A stamp entry is an FP32 number held as a double (the law
+// rounded once to FP32), and every contribution is added in FP64.  The
+// nonzero strengths of a law span few binades, so every partial sum of a
+// window's entries is an exact FP64 number: the pedestrian field Phi at an su
+// does not depend on the order or grouping of its terms, and P = fl32(S + Phi)
+// with S in FP64 is the same bit for bit whatever the launch shape, batch,
+// kernel (gather or dense stencil) or update path that computed it.
+//
 // A workgroup takes work items (runs of TW-column strips of NW*TH rows, each
 // run inside one scene) and for every strip:
 //  1. thread t loads the bitmap words of halo row ya + t and counts its sources;
 //  2. a block-wide exclusive scan turns the counts into list offsets, so the
-//     list holds the strip's halo sources in global row-major order;
+//     list holds the strip's halo sources in global row-major order (a
+//     counting sort whose bins are halo rows);
 //  3. each thread writes its row's entries: an entry is the byte offset that
 //     turns a lane's base address into the address of table entry
-//     (lane su - source) in the aligned copy for the source's row;
+//     (lane su - source);
 //  4. each wave walks the contiguous part of the list that lies within R rows
-//     of its own rows: per source one address add, HL/VEC aligned LDS vector
-//     loads and HL adds per lane.
+//     of its own rows: per source one address add, HL/2 paired 8-byte LDS
+//     loads and HL FP64 adds per lane.
+// Lane l owns column l % TW and rows rg + G*r (rg = l / TW, G = 64 / TW,
+// r < HL) of its wave's TW x TH tile, so its HL entries of a source are G
+// apart in the column-major stamp and two of them make one ds_read2_b64.
 // A halo with more than list_cap - max_row sources is processed in several
-// passes over consecutive row ranges, which keeps the row-major order.  The
-// bitmap rows of the next strip (possibly of the next item and scene) are
-// requested before the current strip is gathered.  The stamp copies are
-// reloaded into LDS when consecutive items belong to scenes with different
-// tables.
+// passes over consecutive row ranges.  The bitmap rows of the next strip
+// (possibly of the next item and scene) are requested before the current
+// strip is gathered.  The stamp is reloaded into LDS when consecutive items
+// belong to scenes with different tables.
 
-template <int VEC>
-struct VecOf;
-template <>
-struct VecOf<2> {
-    typedef float type __attribute__((ext_vector_type(2)));
-};
-template <>
-struct VecOf<4> {
-    typedef float type __attribute__((ext_vector_type(4)));
-};
+typedef double f64x2 __attribute__((ext_vector_type(2)));
 
 // Exclusive prefix sum over the lanes of a wave of counts in [0, 255], and the
 // wave total, from eight ballots.
@@ -494,26 +476,28 @@ __device__ __forceinline__ int lower_bound_lds(const int *a, int n, int v)
     return lo;
 }
 
-// acc[q] += table vector at LDS byte address a + q*sizeof(vec)
-template <int NQ, typename V>
-__device__ __forceinline__ void gather_one(V *acc, int a)
+// The HL stamp entries of one source for this lane (LDS byte address a, rows
+// G apart) added to acc.
+template <int HL, int G>
+__device__ __forceinline__ void gather_one(double *acc, uint32_t a)
 {
-    typedef const __attribute__((address_space(3))) V *ptr;
-    const ptr s = reinterpret_cast<ptr>((uint32_t)a);
-    V v[NQ];
+    typedef const __attribute__((address_space(3))) double *ptr;
+    const ptr s = reinterpret_cast<ptr>(a);
+    double v[HL];
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) v[q] = s[q];
+    for (int r = 0; r < HL; ++r) v[r] = s[G * r];
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) acc[q] += v[q];
+    for (int r = 0; r < HL; ++r) acc[r] += v[r];
 }
 
 // The part of a scene's view that the field kernel reads, kept in scalar
 // registers (a whole SceneView copy would be placed in private memory).
 struct FieldScene {
-    int W, H, wpr, R, tiles_x, copy_elems, stride, padx, pady, max_row, tab_elems, periodic;
-    gptr<const VecOf<4>::type> tab;
-    gptr<const float> S;
+    int W, H, wpr, R, tiles_x, stride, padx, pady, max_row, tab_elems, periodic;
+    gptr<const f64x2> tab;  // tab_elems (even) doubles, loaded as 16-byte vectors
+    gptr<const double> S;
     gptr<float> P;
+    gptr<double> phi;       // exact pedestrian field, kept for the update path (or NULL)
     gptr<const unsigned long long> occ;
     gptr<const unsigned long long> occ2;  // second source bitmap (update launches)
 };
@@ -526,16 +510,16 @@ __device__ __forceinline__ FieldScene field_scene(const SceneView &v)
     f.wpr = v.wpr;
     f.R = v.R;
     f.tiles_x = v.tiles_x;
-    f.copy_elems = v.copy_elems;
     f.stride = v.stride;
     f.padx = v.padx;
     f.pady = v.pady;
     f.max_row = v.max_row;
     f.tab_elems = v.tab_elems;
     f.periodic = v.periodic;
-    f.tab = to_global(reinterpret_cast<const VecOf<4>::type *>(v.tab));
+    f.tab = to_global(reinterpret_cast<const f64x2 *>(v.tab));
     f.S = to_global(v.S);
     f.P = to_global(v.P);
+    f.phi = to_global(v.phi);
     f.occ = to_global(v.occ);
     f.occ2 = to_global((const unsigned long long *)v.moved_from);
     return f;
@@ -587,12 +571,11 @@ struct FieldWork {
     }
 };
 
-// DUAL (single scene only): the incremental update P = (P + Phi(occ)) -
-// Phi(occ2) in one launch, S = P, occ = the su entered and occ2 = the su left
-// this tick.  Each bitmap gets its own scan, list and gather into its own
-// accumulators, so both sums are those of two plain launches (the second with
-// the stamp negated) bit for bit.
-template <int TW, int HL, int VEC, int NW, bool MULTI, bool DUAL = false>
+// DUAL (single scene only): the incremental update in one launch.  occ = the
+// su entered this tick, occ2 = the su left; Phi := (Phi + Phi(occ)) -
+// Phi(occ2) in place (exact), P = fl32(S + Phi).  Each bitmap gets its own
+// scan, list and gather into its own accumulators.
+template <int TW, int HL, int NW, bool MULTI, bool DUAL = false>
 __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
                                                    const SceneView *__restrict__ views,
                                                    const int4 *__restrict__ items, int n_items,
@@ -601,19 +584,17 @@ __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
     static_assert(!(DUAL && MULTI), "the update launch covers one scene");
     constexpr int NSRC = DUAL ? 2 : 1;
     const FieldWork<MULTI> work{one, views, items, per};
-    constexpr int G = 64 / TW, TH = G * HL, WT = NW * TH, NT = NW * 64, NQ = HL / VEC;
-    typedef typename VecOf<VEC>::type vec_t;
-    typedef const __attribute__((address_space(3))) vec_t *lds_vec;
+    constexpr int G = 64 / TW, TH = G * HL, WT = NW * TH, NT = NW * 64;
     extern __shared__ __align__(16) unsigned char lds_raw[];
     __shared__ int wave_tot[NW];
-    float *tab = reinterpret_cast<float *>(lds_raw);
+    double *tab = reinterpret_cast<double *>(lds_raw);
     int *list = reinterpret_cast<int *>(tab + tab_max);
     int *row_excl = list + list_cap;
 
     const int tid = (int)threadIdx.x, lane = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int col = lane % TW, rg = lane / TW;
-    const int tbase = (int)(uint32_t)(uintptr_t)((lds_ptr<float>)tab);
+    const uint32_t tbase = (uint32_t)(uintptr_t)((lds_ptr<double>)tab);
 
     // Work items of one scene by XCD: workgroup b runs on XCD b mod 8 (each
     // XCD has its own L2).  XCD x owns a contiguous share of the strips, in
@@ -633,28 +614,28 @@ __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
     int4 it = work.item(item);
     FieldScene v = work.scene(it.x);
     int t = it.y;
-    typedef VecOf<4>::type f4;
-    // stamp copies into LDS, 8 vectors per thread and batch: each thread's
-    // loads are all issued before the stores, so a batch costs one memory
-    // round trip.  The loads are unconditional (indices past the end read the
-    // last vector again): a load under a branch of its own would get a wait.
-    f4 *const tab4 = reinterpret_cast<f4 *>(tab);
-    auto table_load = [&](const FieldScene &s, int i0, f4(&r)[8]) {
-        const int n4 = s.tab_elems / 4;
+    // stamp into LDS, 8 vectors of 16 bytes per thread and batch: each
+    // thread's loads are all issued before the stores, so a batch costs one
+    // memory round trip.  The loads are unconditional (indices past the end
+    // read the last vector again): a load under a branch of its own would get
+    // a wait.
+    f64x2 *const tab2 = reinterpret_cast<f64x2 *>(tab);
+    auto table_load = [&](const FieldScene &s, int i0, f64x2(&r)[8]) {
+        const int n2 = s.tab_elems / 2;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) r[u] = s.tab[min(i0 + u * NT + tid, n4 - 1)];
+        for (int u = 0; u < 8; ++u) r[u] = s.tab[min(i0 + u * NT + tid, n2 - 1)];
     };
-    auto table_store = [&](const FieldScene &s, int i0, const f4(&r)[8]) {
-        const int n4 = s.tab_elems / 4;
+    auto table_store = [&](const FieldScene &s, int i0, const f64x2(&r)[8]) {
+        const int n2 = s.tab_elems / 2;
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const int i = i0 + u * NT + tid;
-            if (i < n4) tab4[i] = r[u];
+            if (i < n2) tab2[i] = r[u];
         }
     };
     auto load_table = [&](const FieldScene &s) {
-        for (int i0 = 0; i0 < s.tab_elems / 4; i0 += 8 * NT) {
-            f4 r[8];
+        for (int i0 = 0; i0 < s.tab_elems / 2; i0 += 8 * NT) {
+            f64x2 r[8];
             table_load(s, i0, r);
             table_store(s, i0, r);
         }
@@ -717,14 +698,14 @@ __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
         }
     };
     {
-        // the first batch of the stamp copies (all of them unless they exceed
-        // 8 vectors per thread) and the first strip's halo rows are requested
-        // together, in straight-line code, so that their round trips overlap
-        f4 r[8];
+        // the first batch of the stamp (all of it unless it exceeds 8 vectors
+        // per thread) and the first strip's halo rows are requested together,
+        // in straight-line code, so that their round trips overlap
+        f64x2 r[8];
         fetch_rows(v, t);
         table_load(v, 0, r);
         table_store(v, 0, r);
-        for (int i0 = 8 * NT; i0 < v.tab_elems / 4; i0 += 8 * NT) {
+        for (int i0 = 8 * NT; i0 < v.tab_elems / 2; i0 += 8 * NT) {
             table_load(v, i0, r);
             table_store(v, i0, r);
         }
@@ -778,33 +759,35 @@ __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
         // keep the loads below after the use of the prefetched words, so that
         // the wait for those does not also wait for the new requests
         asm volatile("" ::"v"(cnts[0]), "v"(cnts[NSRC - 1]) : "memory");
-        // S of this lane's su and the next strip's halo rows are requested now
-        // and arrive while this strip is gathered
+        // S (and, for an update, the previous Phi) of this lane's su and the
+        // next strip's halo rows are requested now and arrive while this
+        // strip is gathered
         const int x = X0 + col;
-        float sv[HL];
+        double sv[HL], pv[HL];
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-#pragma unroll
-            for (int j = 0; j < VEC; ++j) {
-                const int y = y0w + rg * HL + q * VEC + j;
-                sv[q * VEC + j] = (x < W && y < H) ? v.S[(size_t)y * W + x] : 0.0f;
-            }
+        for (int r = 0; r < HL; ++r) {
+            const int y = y0w + rg + G * r;
+            const size_t c = (size_t)min(y, H - 1) * W + min(x, W - 1);
+            sv[r] = v.S[c];
+            pv[r] = 0.0;
+            if constexpr (DUAL) pv[r] = v.phi[c];
         }
         if (more) fetch_rows(nv, nt);
 
         // this wave's halo rows (relative to ya) and per-lane base address
         const int ra = max(y0w - R, ya) - ya;
         const int rb = min(y0w + TH - 1 + R, yb) - ya;
-        const int lb = opaque_lane(tbase + ((X0 + col + padx) * stride + (y0w + rg * HL + pady)) * 4);
-        vec_t accs[NSRC][NQ];
+        const uint32_t lb = (uint32_t)opaque_lane(
+            (int)(tbase + (uint32_t)((X0 + col + padx) * stride + (y0w + rg + pady)) * 8u));
+        double accs[NSRC][HL];
 #pragma unroll
         for (int src = 0; src < NSRC; ++src)
 #pragma unroll
-            for (int q = 0; q < NQ; ++q) accs[src][q] = (vec_t)(0.0f);
+            for (int r = 0; r < HL; ++r) accs[src][r] = 0.0;
 
 #pragma unroll
         for (int src = 0; src < NSRC; ++src) {
-            vec_t *acc = accs[src];
+            double *acc = accs[src];
             const int cnt = cnts[src];
             const unsigned long long m0 = mw[src][0], m1 = mw[src][1], m2 = mw[src][2];
             // 2. block exclusive scan of the row counts (ballots within a wave);
@@ -833,11 +816,10 @@ __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
                     start = row_excl[lower_bound_lds(row_excl, nr, k * cap)];
                     if (k + 1 < npass) end = row_excl[lower_bound_lds(row_excl, nr, (k + 1) * cap)];
                 }
-                // 3. entries of the rows in this pass
+                // 3. entries of the rows in this pass: minus the byte offset of
+                // the source (px, py) in the column-major stamp, modulo 2^32
                 if (tid < nr && cnt > 0 && excl >= start && excl < end) {
-                    const int py = ya + tid;
-                    const int c = (py - pady) & (VEC - 1);
-                    const int rowterm = c * v.copy_elems * 4 - (py - c) * 4;
+                    const uint32_t py = (uint32_t)(ya + tid);
                     int o = excl - start;
 #pragma unroll
                     for (int j = 0; j < 3; ++j) {
@@ -846,7 +828,8 @@ __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
                         while (mj) {
                             const int b = __builtin_ctzll(mj);
                             mj &= mj - 1ull;
-                            list[o++] = rowterm - (xw + b) * stride * 4;
+                            const uint32_t px = (uint32_t)(xw + b);
+                            list[o++] = (int)(0u - (px * (uint32_t)stride + py) * 8u);
                         }
                     }
                 }
@@ -857,8 +840,9 @@ __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
                     const int lo = __builtin_amdgcn_readfirstlane(max(row_excl[ra], start) - start);
                     const int hi = __builtin_amdgcn_readfirstlane(min(row_excl[rb + 1], end) - start);
                     int i = lo;
-                    for (; i < hi && (i & 3); ++i) gather_one<NQ>(acc, lb + list[i]);
+                    for (; i < hi && (i & 3); ++i) gather_one<HL, G>(acc, lb + (uint32_t)list[i]);
                     const int4 *list4 = reinterpret_cast<const int4 *>(list);
+                    typedef const __attribute__((address_space(3))) double *lds_d;
                     // eight sources per round: eight table reads are in flight
                     // before the adds, and the next round's entries are read
                     // behind them (reading up to eight entries past the pass stays
@@ -873,55 +857,56 @@ __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
                             // the compiler keeps this order: next entries, table
                             // reads, adds (no wait is implied by the barriers)
                             asm volatile("" ::: "memory");
-                            vec_t u8[8][NQ];
+                            double u8[8][HL];
 #pragma unroll
                             for (int u = 0; u < 8; ++u) {
-                                const lds_vec sp = reinterpret_cast<lds_vec>((uint32_t)(lb + a[u]));
+                                const lds_d sp = reinterpret_cast<lds_d>(lb + (uint32_t)a[u]);
 #pragma unroll
-                                for (int q = 0; q < NQ; ++q) u8[u][q] = sp[q];
+                                for (int r = 0; r < HL; ++r) u8[u][r] = sp[G * r];
                             }
                             asm volatile("" ::: "memory");
-                            // row-major source order per accumulator
 #pragma unroll
                             for (int u = 0; u < 8; ++u) {
 #pragma unroll
-                                for (int q = 0; q < NQ; ++q) acc[q] += u8[u][q];
+                                for (int r = 0; r < HL; ++r) acc[r] += u8[u][r];
                             }
                         }
                     }
                     if (i + 4 <= hi) {
                         const int4 ea = list4[i >> 2];
                         const int a[4] = {ea.x, ea.y, ea.z, ea.w};
-                        vec_t u4[4][NQ];
+                        double u4[4][HL];
 #pragma unroll
                         for (int u = 0; u < 4; ++u) {
-                            const lds_vec sp = reinterpret_cast<lds_vec>((uint32_t)(lb + a[u]));
+                            const lds_d sp = reinterpret_cast<lds_d>(lb + (uint32_t)a[u]);
 #pragma unroll
-                            for (int q = 0; q < NQ; ++q) u4[u][q] = sp[q];
+                            for (int r = 0; r < HL; ++r) u4[u][r] = sp[G * r];
                         }
 #pragma unroll
                         for (int u = 0; u < 4; ++u) {
 #pragma unroll
-                            for (int q = 0; q < NQ; ++q) acc[q] += u4[u][q];
+                            for (int r = 0; r < HL; ++r) acc[r] += u4[u][r];
                         }
                         i += 4;
                     }
-                    for (; i < hi; ++i) gather_one<NQ>(acc, lb + list[i]);
+                    for (; i < hi; ++i) gather_one<HL, G>(acc, lb + (uint32_t)list[i]);
                 }
                 __syncthreads();
             }
         }
 
-        // 5. P = S + Phi for this lane's su (DUAL: (S + Phi(occ)) - Phi(occ2))
+        // 5. Phi of this lane's su (an update: previous Phi + entered - left),
+        // P = fl32(S + Phi)
         if (x < W) {
 #pragma unroll
-            for (int q = 0; q < NQ; ++q) {
-#pragma unroll
-                for (int j = 0; j < VEC; ++j) {
-                    const int y = y0w + rg * HL + q * VEC + j;
-                    float r = sv[q * VEC + j] + accs[0][q][j];
-                    if constexpr (DUAL) r = r - accs[NSRC - 1][q][j];
-                    if (y < H) v.P[(size_t)y * W + x] = r;
+            for (int r = 0; r < HL; ++r) {
+                const int y = y0w + rg + G * r;
+                double f = accs[0][r];
+                if constexpr (DUAL) f = (pv[r] + accs[0][r]) - accs[NSRC - 1][r];
+                if (y < H) {
+                    const size_t c = (size_t)y * W + x;
+                    if (v.phi) v.phi[c] = f;
+                    v.P[c] = (float)(sv[r] + f);
                 }
             }
         }
@@ -940,25 +925,6 @@ __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
         v = nv;
         t = nt;
     }
-}
-
-// Stamp copies for the source-list gather (see ListCfg): copy c holds
-// phi(dx, dy) at (dx + padx)*stride + (dy + pady + c); FP64 value rounded once.
-// (each copy occupies copy_elems >= ncols*stride floats; the tail is zero)
-__global__ void k_phi_copies(float *tab, int vec, int copy_elems, int ncols, int stride, int padx,
-                             int pady, int R, double k, double alpha)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= vec * copy_elems) return;
-    const int c = i / copy_elems, rem = i - c * copy_elems;
-    double v = 0.0;
-    if (rem < ncols * stride) {
-        const int ci = rem / stride, ri = rem - ci * stride;
-        const int dx = ci - padx, dy = ri - c - pady;
-        if (abs(dx) <= R && abs(dy) <= R && (dx != 0 || dy != 0))
-            v = k * pow(sqrt((double)dx * dx + (double)dy * dy), alpha);
-    }
-    tab[i] = (float)v;
 }
 
 // ---- occupancy ----------------------------------------------------------------------
@@ -982,11 +948,10 @@ __global__ void k_occ_init(const int32_t *__restrict__ pos, int N, unsigned long
 // instead.  Lane l owns column X0 + l of a 64-column tile and HL consecutive
 // rows; per window row it cuts its 2R+1 occupancy bits out of the row's three
 // words around the tile (the same words for the whole wave) and per offset
-// adds phi when the bit is set, as acc = fma(bit, phi, acc) with phi the
-// stamp's FP32 value (uniform across the wave).  The offsets are taken
-// source row by source row, top to bottom, and west to east within a row:
-// the row-major source order in which the gather adds them, so the field is
-// bit-identical to the gather's (adding a zero leaves the sum unchanged).
+// adds phi when the bit is set, as acc = fma(bit, phi, acc) in FP64 with phi
+// the stamp's value (uniform across the wave, held in vector registers).  The
+// sum is exact, as in the gather, so both kernels give the same field bit for
+// bit.
 
 constexpr int kDenseHL = 8;       // rows per lane
 constexpr int kDenseWaves = 4;    // waves per workgroup (tile: 64 x 32 su)
@@ -997,15 +962,14 @@ __global__ __launch_bounds__(kDenseWaves * 64) void k_field_dense(SceneView one,
     constexpr int K = 2 * R + 1, NR = kDenseHL + 2 * R;
     const int W = one.W, H = one.H, wpr = one.wpr;
     const gptr<const unsigned long long> occ = to_global((const unsigned long long *)one.occ);
-    const gptr<const float> S = to_global(one.S);
+    const gptr<const double> S = to_global(one.S);
     const gptr<float> P = to_global(one.P);
-    const gptr<const float> tab = to_global(one.tab);
+    const gptr<double> phi_out = to_global(one.phi);
+    const gptr<const double> tab = to_global(one.tab);
     const int lane = (int)threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
-    // phi(dx, dy) from the first stamp copy: entry (dx + padx) * stride + dy + pady,
-    // held in vector registers (each value serves up to HL fmas per window
-    // row; in scalar registers they would not fit beside the loop's own)
-    float phi[K][K];
+    // phi(dx, dy) from the stamp: entry (dx + padx) * stride + dy + pady
+    double phi[K][K];
     const int base = opaque_lane((one.padx - R) * one.stride + one.pady - R);
 #pragma unroll
     for (int a = 0; a < K; ++a)
@@ -1023,7 +987,7 @@ __global__ __launch_bounds__(kDenseWaves * 64) void k_field_dense(SceneView one,
         const int Y0 = ty * TH, y0 = Y0 + wv * kDenseHL;
         // S of this lane's su, requested first: its round trip overlaps the
         // staging of the rows
-        float sv[kDenseHL];
+        double sv[kDenseHL];
 #pragma unroll
         for (int h = 0; h < kDenseHL; ++h) {
             const int y = y0 + h;
@@ -1043,9 +1007,9 @@ __global__ __launch_bounds__(kDenseWaves * 64) void k_field_dense(SceneView one,
         }
         __syncthreads();
         if (y0 < H) {  // uniform across the wave
-            float acc[kDenseHL];
+            double acc[kDenseHL];
 #pragma unroll
-            for (int h = 0; h < kDenseHL; ++h) acc[h] = 0.0f;
+            for (int h = 0; h < kDenseHL; ++h) acc[h] = 0.0;
 #pragma unroll
             for (int r = 0; r < NR; ++r) {
                 const unsigned long long wl = rows[wv * kDenseHL + r][0];
@@ -1062,19 +1026,23 @@ __global__ __launch_bounds__(kDenseWaves * 64) void k_field_dense(SceneView one,
                     win = (wc >> (p - 64)) | (wr << (128 - p));
 #pragma unroll
                 for (int i = 0; i < K; ++i) {  // source column x - R + i
-                    const float bit = (float)(unsigned int)((win >> i) & 1ull);
+                    const double bit = (double)(unsigned int)((win >> i) & 1ull);
 #pragma unroll
                     for (int h = 0; h < kDenseHL; ++h) {
                         const int dy = h + R - r;  // output row y0 + h minus source row
                         if (dy >= -R && dy <= R)
-                            acc[h] = fmaf(bit, phi[2 * R - i][dy + R], acc[h]);
+                            acc[h] = fma(bit, phi[2 * R - i][dy + R], acc[h]);
                     }
                 }
             }
 #pragma unroll
             for (int h = 0; h < kDenseHL; ++h) {
                 const int y = y0 + h;
-                if (x < W && y < H) P[(size_t)y * W + x] = sv[h] + acc[h];
+                if (x < W && y < H) {
+                    const size_t c = (size_t)y * W + x;
+                    if (one.phi) phi_out[c] = acc[h];
+                    P[c] = (float)(sv[h] + acc[h]);
+                }
             }
         }
         __syncthreads();  // the rows are restaged for the next tile
@@ -1476,18 +1444,18 @@ inline unsigned int blocks_for(size_t n, unsigned int bs, unsigned int cap = 655
     return (unsigned int)(b > cap ? cap : b);
 }
 
-template <typename T, int TW, int HL, bool ADD_S>
-hipError_t sup_launch(const SupCfg &c, const unsigned long long *bits, int wpr, const T *tab,
-                      const float *S, T *outT, float *outP, int W, int H, hipStream_t st)
+template <int TW, int HL>
+hipError_t sup_launch(const SupCfg &c, const unsigned long long *bits, int wpr, const double *tab,
+                      double *out, int W, int H, hipStream_t st)
 {
     constexpr int TH = (64 / TW) * HL;
     const int tiles_x = (W + TW - 1) / TW, tiles_y = (H + TH - 1) / TH;
     const int n_tiles = tiles_x * tiles_y;
     const int want = (n_tiles + kSupThreads / 64 - 1) / (kSupThreads / 64);
     const int grid = want < c.grid ? want : c.grid;
-    hipLaunchKernelGGL((k_superpose<T, TW, HL, ADD_S>), dim3(grid > 0 ? grid : 1), dim3(kSupThreads),
+    hipLaunchKernelGGL((k_superpose<TW, HL>), dim3(grid > 0 ? grid : 1), dim3(kSupThreads),
                        c.lds_bytes, st, bits, wpr, tab, c.ncols * c.stride, c.stride, c.padx,
-                       c.pady, c.radius, S, outT, outP, W, H, tiles_x, n_tiles);
+                       c.pady, c.radius, out, W, H, tiles_x, n_tiles);
     return hipGetLastError();
 }
 
@@ -1541,23 +1509,6 @@ hipError_t launch_mask_to_bits(const uint8_t *mask, unsigned long long *bits, in
     return hipGetLastError();
 }
 
-hipError_t launch_phi_table_f32(float *tab, const SupCfg &c, double k, double alpha, hipStream_t st)
-{
-    const int n = c.ncols * c.stride;
-    hipLaunchKernelGGL(k_phi_table<float>, dim3(blocks_for(n, 256)), dim3(256), 0, st, tab, c.ncols,
-                       c.nrows, c.stride, c.padx, c.pady, c.radius, k, alpha);
-    return hipGetLastError();
-}
-
-hipError_t launch_phi_table_f64(double *tab, const SupCfg &c, double k, double alpha,
-                                hipStream_t st)
-{
-    const int n = c.ncols * c.stride;
-    hipLaunchKernelGGL(k_phi_table<double>, dim3(blocks_for(n, 256)), dim3(256), 0, st, tab,
-                       c.ncols, c.nrows, c.stride, c.padx, c.pady, c.radius, k, alpha);
-    return hipGetLastError();
-}
-
 hipError_t launch_bfs_seed(const uint8_t *exitm, int32_t *D, int n, hipStream_t st)
 {
     hipLaunchKernelGGL(k_bfs_seed, dim3(blocks_for(n, 256, kCoverAll)), dim3(256), 0, st, exitm,
@@ -1589,7 +1540,7 @@ hipError_t launch_count_unreachable(const uint8_t *obst, const int32_t *D, int n
 
 hipError_t set_superpose_lds_limit(size_t f64_bytes)
 {
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_superpose<double, 8, 1, false>),
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_superpose<8, 1>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)f64_bytes);
 }
 
@@ -1597,34 +1548,32 @@ hipError_t set_superpose_lds_limit(size_t f64_bytes)
 
 namespace {
 
-// Most lanes of one LDS read of a source's column slice that share a bank:
-// lane l (column l % tw, row group l / tw) reads the hl contiguous dwords at
-// col*stride + rg*hl.  The LDS serves 256 bytes per clock, so 64 / hl lanes
-// form one pass.
-int bank_degree(int tw, int hl, int stride)
+// Most lanes of one 8-byte LDS read of a source's stamp column that share a
+// bank pair: lane l (column l % tw, row group l / tw) reads the double at
+// col*stride + rg (+ a uniform offset).  The LDS serves 256 bytes per clock,
+// so 32 lanes of an 8-byte read form one pass; a pass is conflict-free when
+// their double indices are distinct modulo 32.
+int bank_degree(int tw, int stride)
 {
-    const int lanes = 64 / hl;
     int worst = 0;
-    for (int p = 0; p < 64; p += lanes) {
-        int hits[64] = {0};
-        for (int l = p; l < p + lanes && l < 64; ++l) {
+    for (int p = 0; p < 64; p += 32) {
+        int hits[32] = {0};
+        for (int l = p; l < p + 32; ++l) {
             const int col = l % tw, rg = l / tw;
-            const int a = col * stride + rg * hl;
-            for (int j = 0; j < hl; ++j) ++hits[(a + j) % 64];
+            ++hits[(col * stride + rg) % 32];
         }
-        for (int b = 0; b < 64; ++b) worst = hits[b] > worst ? hits[b] : worst;
+        for (int b = 0; b < 32; ++b) worst = hits[b] > worst ? hits[b] : worst;
     }
     return worst;
 }
 
 }  // namespace
 
-ListCfg make_list_cfg(int radius, int tw, int hl, int vec, int nw, int list_cap)
+ListCfg make_list_cfg(int radius, int tw, int hl, int nw, int list_cap)
 {
     ListCfg c;
     c.tw = tw;
     c.hl = hl;
-    c.vec = vec;
     c.nw = nw;
     c.g = 64 / tw;
     c.th = c.g * hl;
@@ -1634,11 +1583,9 @@ ListCfg make_list_cfg(int radius, int tw, int hl, int vec, int nw, int list_cap)
     c.pady = radius + c.th - 1;
     c.ncols = 2 * c.padx + 1;
     c.nrows = 2 * c.pady + 1;
-    const int min_s = c.nrows + vec - 1;
     int best = -1, best_deg = 1 << 30;
-    for (int s = min_s; s < min_s + 64; ++s) {
-        if (s % vec != 0) continue;  // aligned VEC-wide reads
-        const int d = bank_degree(tw, hl, s);
+    for (int s = c.nrows; s < c.nrows + 64; ++s) {
+        const int d = bank_degree(tw, s);
         if (d < best_deg) {
             best_deg = d;
             best = s;
@@ -1646,27 +1593,26 @@ ListCfg make_list_cfg(int radius, int tw, int hl, int vec, int nw, int list_cap)
         if (d == 1) break;
     }
     c.stride = best;
-    c.copy_elems = (c.ncols * c.stride + 3) & ~3;  // copies start 16-byte aligned
+    c.tab_elems = (c.ncols * c.stride + 1) & ~1;  // loaded as 16-byte vectors
     c.max_row = tw + 2 * radius;
     c.list_cap = list_cap;
     c.halo_rows = c.wt + 2 * radius;
-    c.lds_bytes = (size_t)vec * c.copy_elems * 4 + (size_t)list_cap * 4 +
-                  (size_t)(c.halo_rows + 1) * 4;
+    c.lds_bytes = (size_t)c.tab_elems * 8 + (size_t)list_cap * 4 + (size_t)(c.halo_rows + 1) * 4;
     return c;
 }
 
 ListCfg pick_list_cfg(int radius, size_t max_lds)
 {
-    // one list per workgroup strip, 16-column strips, one aligned 8-byte read
-    // per source and lane (conflict-free banks); two workgroups per CU are
-    // preferred, smaller lists and workgroups if LDS is short
-    const int shapes[][4] = {{16, 2, 2, 8}, {16, 2, 2, 4}};
+    // one list per workgroup strip, 16-column strips, two stamp entries per
+    // 8-byte-pair LDS read and lane (conflict-free banks); two workgroups per
+    // CU are preferred, smaller lists and workgroups if LDS is short
+    const int shapes[][3] = {{16, 2, 8}, {16, 2, 4}};
     ListCfg best;
     for (int i = 0; i < 2; ++i) {
         const int *sh = shapes[i];
         for (int cap = 4096; cap >= 512; cap /= 2) {
-            ListCfg t = make_list_cfg(radius, sh[0], sh[1], sh[2], sh[3], cap);
-            if (cap < 2 * t.max_row || t.halo_rows > 64 * sh[3]) break;
+            ListCfg t = make_list_cfg(radius, sh[0], sh[1], sh[2], cap);
+            if (cap < 2 * t.max_row || t.halo_rows > 64 * sh[2]) break;
             if (t.lds_bytes <= max_lds / 2) return t;
             if (t.lds_bytes <= max_lds && best.lds_bytes == 0) best = t;
         }
@@ -1674,24 +1620,15 @@ ListCfg pick_list_cfg(int radius, size_t max_lds)
     return best;
 }
 
-hipError_t launch_phi_copies(float *tab, const ListCfg &c, double k, double alpha, hipStream_t st)
-{
-    const int n = c.vec * c.copy_elems;
-    hipLaunchKernelGGL(k_phi_copies, dim3(blocks_for(n, 256)), dim3(256), 0, st, tab, c.vec,
-                       c.copy_elems, c.ncols, c.stride, c.padx, c.pady, c.radius, k, alpha);
-    return hipGetLastError();
-}
-
-void set_view_layout(SceneView &v, const ListCfg &c, const float *tab)
+void set_view_layout(SceneView &v, const ListCfg &c, const double *tab)
 {
     v.tiles_x = (v.W + c.tw - 1) / c.tw;
     v.n_strips = v.tiles_x * ((v.H + c.wt - 1) / c.wt);
-    v.copy_elems = c.copy_elems;
     v.stride = c.stride;
     v.padx = c.padx;
     v.pady = c.pady;
     v.max_row = c.max_row;
-    v.tab_elems = c.vec * c.copy_elems;
+    v.tab_elems = c.tab_elems;
     v.tab = tab;
 }
 
@@ -1700,10 +1637,9 @@ FieldLaunch field_launch_for(const ListCfg &c)
     FieldLaunch f;
     f.tw = c.tw;
     f.hl = c.hl;
-    f.vec = c.vec;
     f.nw = c.nw;
     f.list_cap = c.list_cap;
-    f.tab_max = c.vec * c.copy_elems;
+    f.tab_max = c.tab_elems;
     f.halo_max = c.halo_rows;
     f.grid = c.grid;
     f.lds_bytes = field_lds_bytes(f);
@@ -1712,17 +1648,18 @@ FieldLaunch field_launch_for(const ListCfg &c)
 
 size_t field_lds_bytes(const FieldLaunch &f)
 {
-    return (size_t)f.tab_max * 4 + (size_t)f.list_cap * 4 + (size_t)(f.halo_max + 1) * 4;
+    return (size_t)f.tab_max * 8 + (size_t)f.list_cap * 4 + (size_t)(f.halo_max + 1) * 4;
 }
 
+// Compiled shapes (strip width TW, rows per lane HL, waves per workgroup NW).
 #define SF_LIST_SHAPES(X)                                                                     \
-    X(16, 2, 2, 4) X(16, 2, 2, 8) X(16, 4, 2, 4) X(16, 4, 2, 8) X(16, 4, 4, 4) X(16, 4, 4, 8)    \
-    X(32, 2, 2, 4) X(32, 2, 2, 8) X(32, 4, 2, 4) X(32, 4, 4, 4) X(8, 4, 4, 4) X(8, 2, 2, 4)
+    X(16, 2, 4) X(16, 2, 8) X(16, 4, 4) X(16, 4, 8) X(32, 2, 4) X(32, 2, 8) X(32, 4, 4)         \
+    X(8, 2, 4) X(8, 4, 4)
 
-bool list_shape_compiled(int tw, int hl, int vec, int nw)
+bool list_shape_compiled(int tw, int hl, int nw)
 {
-#define SF_KNOWN(a, b, v, n) \
-    if (tw == a && hl == b && vec == v && nw == n) return true;
+#define SF_KNOWN(a, b, n) \
+    if (tw == a && hl == b && nw == n) return true;
     SF_LIST_SHAPES(SF_KNOWN)
 #undef SF_KNOWN
     return false;
@@ -1731,14 +1668,14 @@ bool list_shape_compiled(int tw, int hl, int vec, int nw)
 hipError_t set_field_lds_limit(size_t bytes)
 {
     hipError_t e = hipSuccess;
-#define SF_SET(a, b, v, n)                                                                        \
-    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_field<a, b, v, n, false>),       \
+#define SF_SET(a, b, n)                                                                          \
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_field<a, b, n, false>),         \
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);          \
     if (e != hipSuccess) return e;                                                            \
-    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_field<a, b, v, n, true>),        \
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_field<a, b, n, true>),          \
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);          \
     if (e != hipSuccess) return e;                                                            \
-    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_field<a, b, v, n, false, true>), \
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_field<a, b, n, false, true>),   \
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);          \
     if (e != hipSuccess) return e;
     SF_LIST_SHAPES(SF_SET)
@@ -1752,26 +1689,26 @@ hipError_t launch_field(const FieldLaunch &f, const SceneView *views, const int3
     const int grid = std::max(1, std::min(f.grid, n_items));
     const int4 *it = reinterpret_cast<const int4 *>(items);
     const SceneView none = {};
-#define SF_DISPATCH(a, b, v, n)                                                                   \
-    if (f.tw == a && f.hl == b && f.vec == v && f.nw == n)                                      \
-        return launch(k_field<a, b, v, n, true>, dim3(grid), dim3(n * 64), f.lds_bytes, st, ev,  \
+#define SF_DISPATCH(a, b, n)                                                                      \
+    if (f.tw == a && f.hl == b && f.nw == n)                                                    \
+        return launch(k_field<a, b, n, true>, dim3(grid), dim3(n * 64), f.lds_bytes, st, ev,     \
                       none, views, it, n_items, 0, f.tab_max, f.list_cap);
     SF_LIST_SHAPES(SF_DISPATCH)
 #undef SF_DISPATCH
     return hipErrorInvalidValue;
 }
 
-int field_resident_blocks(int tw, int hl, int vec, int nw, size_t lds_bytes, bool multi)
+int field_resident_blocks(int tw, int hl, int nw, size_t lds_bytes, bool multi)
 {
     int n = 0;
     hipError_t e = hipErrorInvalidValue;
-#define SF_OCC(a, b, v, w)                                                                        \
-    if (tw == a && hl == b && vec == v && nw == w)                                               \
+#define SF_OCC(a, b, w)                                                                           \
+    if (tw == a && hl == b && nw == w)                                                           \
         e = multi ? hipOccupancyMaxActiveBlocksPerMultiprocessor(                                \
-                        &n, reinterpret_cast<const void *>(&k_field<a, b, v, w, true>), w * 64,   \
+                        &n, reinterpret_cast<const void *>(&k_field<a, b, w, true>), w * 64,      \
                         lds_bytes)                                                               \
                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(                                \
-                        &n, reinterpret_cast<const void *>(&k_field<a, b, v, w, false>), w * 64,  \
+                        &n, reinterpret_cast<const void *>(&k_field<a, b, w, false>), w * 64,     \
                         lds_bytes);
     SF_LIST_SHAPES(SF_OCC)
 #undef SF_OCC
@@ -1798,10 +1735,10 @@ hipError_t launch_field_one(const FieldLaunch &f, const SceneView &view, int per
 {
     const int n_items = std::max(1, (view.n_strips + per - 1) / per);
     const int grid = std::max(1, std::min(f.grid, n_items));
-#define SF_DISPATCH(a, b, v, n)                                                                   \
-    if (f.tw == a && f.hl == b && f.vec == v && f.nw == n)                                      \
-        return launch(k_field<a, b, v, n, false>, dim3(grid), dim3(n * 64), f.lds_bytes, st,     \
-                      ev, view, (const SceneView *)nullptr, (const int4 *)nullptr, n_items, per, \
+#define SF_DISPATCH(a, b, n)                                                                      \
+    if (f.tw == a && f.hl == b && f.nw == n)                                                    \
+        return launch(k_field<a, b, n, false>, dim3(grid), dim3(n * 64), f.lds_bytes, st, ev,    \
+                      view, (const SceneView *)nullptr, (const int4 *)nullptr, n_items, per,    \
                       f.tab_max, f.list_cap);
     SF_LIST_SHAPES(SF_DISPATCH)
 #undef SF_DISPATCH
@@ -1813,10 +1750,10 @@ hipError_t launch_field_update(const FieldLaunch &f, const SceneView &view, int 
 {
     const int n_items = std::max(1, (view.n_strips + per - 1) / per);
     const int grid = std::max(1, std::min(f.grid, n_items));
-#define SF_DISPATCH(a, b, v, n)                                                                   \
-    if (f.tw == a && f.hl == b && f.vec == v && f.nw == n)                                      \
-        return launch(k_field<a, b, v, n, false, true>, dim3(grid), dim3(n * 64), f.lds_bytes,  \
-                      st, ev, view, (const SceneView *)nullptr, (const int4 *)nullptr, n_items, \
+#define SF_DISPATCH(a, b, n)                                                                      \
+    if (f.tw == a && f.hl == b && f.nw == n)                                                    \
+        return launch(k_field<a, b, n, false, true>, dim3(grid), dim3(n * 64), f.lds_bytes, st, \
+                      ev, view, (const SceneView *)nullptr, (const int4 *)nullptr, n_items,     \
                       per, f.tab_max, f.list_cap);
     SF_LIST_SHAPES(SF_DISPATCH)
 #undef SF_DISPATCH
@@ -1826,13 +1763,12 @@ hipError_t launch_field_update(const FieldLaunch &f, const SceneView &view, int 
 hipError_t launch_superpose_f64(const SupCfg &c, const unsigned long long *bits, int wpr,
                                 const double *tab, double *out, int W, int H, hipStream_t st)
 {
-    if (c.tw == 8 && c.hl == 1)
-        return sup_launch<double, 8, 1, false>(c, bits, wpr, tab, nullptr, out, nullptr, W, H, st);
+    if (c.tw == 8 && c.hl == 1) return sup_launch<8, 1>(c, bits, wpr, tab, out, W, H, st);
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_static_S(const int32_t *D, const double *O, const uint8_t *obst, double w_dest,
-                           float *S, int n, hipStream_t st)
+                           double *S, int n, hipStream_t st)
 {
     hipLaunchKernelGGL(k_static_S, dim3(blocks_for(n, 256, kCoverAll)), dim3(256), 0, st, D, O,
                        obst, w_dest, S, n);

@@ -35,18 +35,29 @@ import numpy as np
 from . import sf
 
 # Device bytes a resident scene holds (the library's per-scene arrays):
-# per su  S, P, D (4 B each), exit mask (1), claims (8), occupancy bits (1/8);
-# per pedestrian  keys (8), positions, targets, id map (4 each), flags (1);
-# plus counters and the stamp copies (< 1 MiB).
-BYTES_PER_SU = 4 + 4 + 4 + 1 + 8 + 0.125
+# per su  S (FP64, 8 B), P and D (4 B each), exit mask (1), claims (8),
+# occupancy bits (1/8); per pedestrian  keys (8), positions, targets, id map
+# (4 each), flags (1); plus counters, the stamp and the scene's share of a
+# batch's layout (views, workgroup maps, work items, stamp tables): < 1 MiB.
+BYTES_PER_SU = 8 + 4 + 4 + 1 + 8 + 0.125
 BYTES_PER_PED = 8 + 4 + 4 + 4 + 1
 FIXED_BYTES = 1 << 20
+# Temporaries of scene creation, released when the build ends: per su the
+# obstacle mask (1 B), five bitmaps (obstacles, two visited sets, two
+# frontiers: 5/8 B) and the FP64 obstacle field (8 B).
+BUILD_BYTES_PER_SU = 1 + 5 * 0.125 + 8
 
 
 def footprint_bytes(scene) -> int:
+    """Device bytes a resident scene holds."""
     su = int(scene.width) * int(scene.height)
     return int(su * BYTES_PER_SU + int(np.asarray(scene.pos).shape[0]) * BYTES_PER_PED
                + FIXED_BYTES)
+
+
+def build_bytes(scene) -> int:
+    """Device bytes a scene holds on top of its footprint while it is built."""
+    return int(int(scene.width) * int(scene.height) * BUILD_BYTES_PER_SU)
 
 
 @dataclasses.dataclass
@@ -130,11 +141,11 @@ class Server:
             job = jobs.get()
             if job is None:
                 return
-            req, scene, need = job
+            req, scene, need, extra = job
             try:
-                done.put((req, need, sf.GpuScene(scene, stream=stream), None))
+                done.put((req, need, extra, sf.GpuScene(scene, stream=stream), None))
             except BaseException as e:  # reported by the serving loop
-                done.put((req, need, None, e))
+                done.put((req, need, extra, None, e))
 
     def run(self, requests: List[Request], stop_admitting_at: Optional[float] = None,
             drain: bool = True, deadline: Optional[float] = None) -> dict:
@@ -175,8 +186,9 @@ class Server:
 
         def join_built(item):
             nonlocal building, used
-            req, need, g, err = item
+            req, need, extra, g, err = item
             building -= 1
+            used -= extra  # the build's temporaries are released
             if err is not None:
                 used -= need
                 raise err
@@ -212,25 +224,27 @@ class Server:
                     req = queue[0]
                     scene = req.scene()
                     need = footprint_bytes(scene)
-                    if used + need > self.budget:
+                    extra = build_bytes(scene)
+                    if used + need + extra > self.budget:
                         if not resident and not building:
                             raise ValueError(f"request {req.rid} needs {need} B, more than "
                                              f"the whole budget of {self.budget} B")
                         break
                     queue.popleft()
                     req._scene = None  # the device copy is the state from here on
-                    used += need
+                    used += need + extra
                     admitted_n += 1
                     admitted_now += 1
                     max_used = max(max_used, used)
                     if self.background:
                         building += 1
-                        jobs.put((req, scene, need))
+                        jobs.put((req, scene, need, extra))
                         continue
                     if batch is not None:
                         batch.close()
                         batch = None
                     g = sf.GpuScene(scene, stream=self.create_stream)
+                    used -= extra
                     resident.append(_Resident(req, None, g, now(), need))
                     changed = True
                 if not resident and building:
@@ -289,8 +303,8 @@ class Server:
                         item = done_q.get_nowait()
                     except _queue.Empty:
                         break
-                    if item[2] is not None:
-                        item[2].close()
+                    if item[3] is not None:
+                        item[3].close()
             if batch is not None:
                 batch.close()
             for r in resident:

@@ -234,6 +234,10 @@ class GpuScene:
         _check(lib.sf_create_scene(ctypes.byref(desc), _stream_handle(stream), ctypes.byref(h)))
         self._h = h
         del keep
+        import torch
+
+        # the library creates the scene on the device current at the call
+        self.device = torch.cuda.current_device()
 
     @property
     def handle(self):
@@ -264,8 +268,22 @@ class GpuScene:
 
     def field(self, out=None):
         """Host copy (numpy float32 [H*W]) or, with a torch tensor `out`, a
-        device-to-device copy enqueued on the scene stream."""
+        device-to-device copy enqueued on the scene's stream.  `out` must be a
+        contiguous float32 tensor of at least H*W elements on the scene's
+        device; a reader on another stream must wait for the scene's stream
+        (for instance with an event) before it uses `out`."""
         if out is not None:
+            import torch
+
+            n = self.width * self.height
+            if not isinstance(out, torch.Tensor):
+                raise TypeError("out must be a torch tensor")
+            if out.dtype != torch.float32 or not out.is_contiguous() or out.numel() < n:
+                raise ValueError(f"out must be a contiguous float32 tensor of at least {n} "
+                                 f"elements (got {out.dtype}, {tuple(out.shape)}, "
+                                 f"contiguous={out.is_contiguous()})")
+            if out.device.type != "cuda" or out.device.index != self.device:
+                raise ValueError(f"out is on {out.device}, the scene on cuda:{self.device}")
             _check(load().sf_field(self._h, ctypes.c_void_p(out.data_ptr()), 1))
             return out
         a = np.empty(self.width * self.height, dtype=np.float32)
@@ -273,7 +291,8 @@ class GpuScene:
         return a
 
     def static_field(self):
-        S = np.empty(self.width * self.height, dtype=np.float32)
+        """(S float64 [H*W] = w_dest*D + O, +inf on obstacles; D int32 [H*W])."""
+        S = np.empty(self.width * self.height, dtype=np.float64)
         D = np.empty(self.width * self.height, dtype=np.int32)
         _check(load().sf_static_field(self._h, _ptr(S), _ptr(D), 0))
         return S, D

@@ -3,14 +3,18 @@
 Protocol: at each compared tick the oracle takes the GPU's state (positions,
 tick index), computes the FP64 field P_t and the tick's outcome, and the two
 are compared:
-  * field: max |P_gpu - P_oracle| / max(|P_oracle|, 1) over non-obstacle su,
-    bound 1e-5;
+  * field: the GPU's FP32 field must be the oracle's FP64 field rounded to
+    FP32, bit for bit, on every su (both sides sum FP32 strengths exactly in
+    FP64 and round once); the relative error max |P_gpu - P_oracle| /
+    max(|P_oracle|, 1) over non-obstacle su, at most 2^-24, is reported
+    beside it against the 1e-5 bound;
   * per pedestrian: chosen su, election result and new position must match
-    bit for bit, except where the oracle flags a near tie (its two best FP64
-    candidate values within 1e-5 relative) or where the mismatch is caused by
-    one: a near-tied pedestrian whose oracle or GPU target equals this
-    pedestrian's target (either side's) or its position.  Everything else is
-    an "untied" mismatch and must not occur.
+    bit for bit.  Mismatches are classified: "tied" where the oracle flags a
+    near tie (its two best FP64 candidate values within 1e-5 relative) or the
+    mismatch is caused by one (a near-tied pedestrian whose oracle or GPU
+    target equals this pedestrian's target, either side's, or its position),
+    "untied" otherwise.  With a bit-exact field both sides take every FP32
+    decision on the same numbers, so neither kind may occur.
 """
 from __future__ import annotations
 
@@ -19,6 +23,22 @@ import numpy as np
 import oracle
 
 FIELD_RTOL = 1e-5
+# threads of the oracle's field (the same bits as one thread)
+THREADS = min(16, oracle.host_threads())
+
+
+def assert_parity(rep: "Report"):
+    """The bar: a bit-exact field and no mismatched decision of either kind."""
+    assert rep.field_mismatch == 0, rep
+    assert rep.max_field_err <= FIELD_RTOL, rep
+    assert rep.untied == 0, (rep, rep.first_untied)
+    assert rep.tied_mismatch == 0, rep
+
+
+def field_bits_differ(P_gpu: np.ndarray, P_orc: np.ndarray) -> int:
+    """Number of su whose GPU value is not the oracle's FP64 value rounded to
+    FP32 (+inf on obstacles on both sides)."""
+    return int(np.count_nonzero(np.asarray(P_gpu, np.float32) != P_orc.astype(np.float32)))
 
 
 def field_rel_err(P_gpu: np.ndarray, P_orc: np.ndarray, obstacle: np.ndarray) -> float:
@@ -56,6 +76,7 @@ class Report:
     def __init__(self):
         self.steps = 0
         self.max_field_err = 0.0
+        self.field_mismatch = 0
         self.untied = 0
         self.tied_mismatch = 0
         self.tied_flags = 0
@@ -64,6 +85,7 @@ class Report:
 
     def __repr__(self):
         return (f"Report(steps={self.steps}, max_field_err={self.max_field_err:.3g}, "
+                f"field_mismatch={self.field_mismatch}, "
                 f"untied={self.untied}, tied_mismatch={self.tied_mismatch}, "
                 f"tied_flags={self.tied_flags}, decisions={self.decisions})")
 
@@ -72,8 +94,9 @@ def compare_tick(g, st, report: Report, t: int):
     """Compare one tick of GPU scene `g` (about to run tick t) with the oracle."""
     pos = g.positions()
     P_gpu = g.field()
-    r = oracle.step(st, pos, t)
+    r = oracle.step(st, pos, t, threads=THREADS)
     err = field_rel_err(P_gpu, r.P, st.obstacle)
+    report.field_mismatch += field_bits_differ(P_gpu, r.P)
     g.step(1)
     tgt_g, flags_g = g.last_moves()
     pos_g = g.positions()

@@ -15,7 +15,7 @@ from paper_1803_04782_amd import scenes
 
 pytestmark = pytest.mark.gpu
 
-from parity import FIELD_RTOL, lockstep  # noqa: E402
+from parity import assert_parity, lockstep  # noqa: E402
 
 
 @pytest.fixture(scope="module")
@@ -71,8 +71,7 @@ def test_dense_stencil_lockstep(sf, monkeypatch, name, make):
     with sf.GpuScene(sc) as g:
         rep = lockstep(g, st, sc.start_step, 25)
     print(f"[dense] {name}", rep, flush=True)
-    assert rep.max_field_err <= FIELD_RTOL, rep
-    assert rep.untied == 0, (rep, rep.first_untied)
+    assert_parity(rep)
 
 
 def test_dense_stencil_incremental_update(sf, monkeypatch):

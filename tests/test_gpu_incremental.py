@@ -1,11 +1,11 @@
 """GPU tests of the incremental field update (sf_set_field_update).
 
 Between full superpositions, each tick adds the stamps at the su its
-winners entered and subtracts those at the su they left.  Bar: the same as
-the full path (field within 1e-5 relative of the oracle's FP64 field of the
-current positions, no untied mismatch), with the FP32 rounding of the
-updates accumulating for up to K - 1 ticks; bit-for-bit independence of the
-launch shape; batches refuse such scenes.
+winners entered and subtracts those at the su they left, into an exact FP64
+pedestrian field.  Bar: the same as the full path (parity.py: the field bit
+for bit, no mismatched decision) at every tick of a refresh period;
+bit-for-bit independence of the launch shape and of the refresh period;
+batches refuse such scenes.
 """
 import numpy as np
 import pytest
@@ -15,7 +15,7 @@ from paper_1803_04782_amd import scenes
 
 pytestmark = pytest.mark.gpu
 
-from parity import FIELD_RTOL, lockstep  # noqa: E402
+from parity import assert_parity, lockstep  # noqa: E402
 
 
 @pytest.fixture(scope="module")
@@ -50,14 +50,13 @@ def test_incremental_lockstep(sf, name, make, K, ticks, every):
         g.set_field_update(K)
         rep = lockstep(g, st, sc.start_step, ticks, every)
     _say(f"[incremental K={K}] {name}", rep)
-    assert rep.max_field_err <= FIELD_RTOL, rep
-    assert rep.untied == 0, (rep, rep.first_untied)
+    assert_parity(rep)
 
 
 def test_incremental_tile_shape_invariance(sf, monkeypatch):
     sc = scenes.random_scene(130, 90, n_peds=1500, radius=7, seed=33, bernoulli=0.03)
     out = []
-    for shape in ("16x2x2x8", "32x4x4x4", "8x2x2x4"):
+    for shape in ("16x2x2x8", "32x4x2x4", "8x2x2x4"):
         monkeypatch.setenv("SF_TILE", shape)
         with sf.GpuScene(sc) as g:
             g.set_field_update(16)
@@ -89,3 +88,19 @@ def test_incremental_scene_cannot_join_a_batch(sf):
             b.step(2)
             with pytest.raises(sf.SfError):
                 g.set_field_update(8)
+
+
+@pytest.mark.parametrize("K", [2, 16, 1000])
+def test_update_is_the_full_field_bit_for_bit(sf, K):
+    """The pedestrian field is kept exactly, so between refreshes every
+    updated field equals the full superposition of the same positions, bit
+    for bit, however long the refresh period (no drift to bound)."""
+    sc = scenes.random_scene(180, 120, n_peds=3000, radius=9, seed=77, bernoulli=0.04,
+                             exits=("E", "W", "S"), exit_width=8, k=-0.6, k_obs=0.4)
+    with sf.GpuScene(sc) as a, sf.GpuScene(sc) as b:
+        b.set_field_update(K)
+        for t in range(60):
+            a.step(1)
+            b.step(1)
+            assert np.array_equal(a.positions(), b.positions()), t
+            assert np.array_equal(a.field(), b.field()), t

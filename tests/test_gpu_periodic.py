@@ -2,13 +2,13 @@
 with headed flows, section 5), of headings on bounded scenes, and of walk
 periods (pedestrians that act every p-th tick).
 
-Bar: field within 1e-5 relative of the oracle's FP64 field at every compared
-tick, no untied mismatch of target, election or position (lockstep protocol
-of parity.py); launch-shape and batch independence bit for bit.  Sizes cover
+Bar (lockstep protocol of parity.py): the field bit for bit at every compared
+tick and no mismatch of target, election or position; launch-shape and batch
+independence bit for bit.  Sizes cover
 a width of exactly one bitmap word, widths and heights off the word and tile
 sizes, radii from the paper's 7x7 window to 33x33, densities 0.2 to 0.9, and
-the full 1000 x 1000, density 0.5, 8-directional scenario on sampled su and
-pedestrians.
+the full 1000 x 1000, density 0.5, 8-directional scenario on every su and
+every pedestrian.
 """
 import numpy as np
 import pytest
@@ -18,7 +18,7 @@ from paper_1803_04782_amd import scenes
 
 pytestmark = pytest.mark.gpu
 
-from parity import FIELD_RTOL, lockstep, sampled_field_err, sampled_outcomes  # noqa: E402
+from parity import FIELD_RTOL, assert_parity, lockstep  # noqa: E402
 
 
 @pytest.fixture(scope="module")
@@ -50,8 +50,7 @@ def test_periodic_lockstep(sf, name, make, ticks):
         rep = lockstep(g, st, sc.start_step, ticks)
         s = g.stats()
     _say(f"[periodic] {name}", rep)
-    assert rep.max_field_err <= FIELD_RTOL, rep
-    assert rep.untied == 0, (rep, rep.first_untied)
+    assert_parity(rep)
     assert s["live"] == sc.n_peds and s["evacuated"] == 0
 
 
@@ -65,8 +64,7 @@ def test_headings_on_a_bounded_scene(sf):
     with sf.GpuScene(sc) as g:
         rep = lockstep(g, st, sc.start_step, 30)
     _say("[heading bounded]", rep)
-    assert rep.max_field_err <= FIELD_RTOL, rep
-    assert rep.untied == 0, (rep, rep.first_untied)
+    assert_parity(rep)
 
 
 @pytest.mark.parametrize("h", [1, 2, 3, 7, 8])
@@ -87,7 +85,7 @@ def test_lone_walker_wraps_around(sf, h):
 def test_periodic_tile_shape_invariance(sf, monkeypatch):
     sc = scenes.flow_scene(190, 133, 0.4, 8, radius=7, seed=6)
     out = []
-    for shape in ("16x2x2x8", "32x4x4x4", "8x2x2x4", "16x4x2x4"):
+    for shape in ("16x2x2x8", "32x4x2x4", "8x2x2x4", "16x4x2x4"):
         monkeypatch.setenv("SF_TILE", shape)
         with sf.GpuScene(sc) as g:
             g.step(10)
@@ -127,38 +125,20 @@ def test_periodic_incremental_update(sf):
         g.set_field_update(8)
         rep = lockstep(g, st, sc.start_step, 30)
     _say("[periodic incremental K=8]", rep)
-    assert rep.max_field_err <= FIELD_RTOL, rep
-    assert rep.untied == 0, (rep, rep.first_untied)
+    assert_parity(rep)
 
 
-def test_paper_scenario_1000_sampled(sf):
+def test_paper_scenario_1000_full(sf):
     """1000 x 1000 torus, density 0.5 (500,000 pedestrians), 8-directional
-    flow, 7x7 fields: sampled su and pedestrians from the oracle's point
-    route at three ticks, including su on the seams."""
+    flow, 7x7 fields, in lockstep with the oracle's full tick for 26 ticks:
+    every su of the field (seams included) and every pedestrian's outcome."""
     sc = scenes.flow_scene(1000, 1000, 0.5, 8, radius=3, seed=0)
-    st = oracle.statics(sc, with_obstacle_field=False)
-    rng = np.random.default_rng(1)
-    W, H = sc.width, sc.height
-    edge = np.concatenate([np.arange(W), (H - 1) * W + np.arange(W), np.arange(H) * W,
-                           np.arange(H) * W + W - 1])
+    st = oracle.statics(sc)
     with sf.GpuScene(sc) as g:
-        for t in (0, 1, 25):
-            g.step(t - g.stats()["step"])
-            pos = g.positions()
-            P = g.field()
-            cells = np.concatenate([rng.choice(W * H, size=300, replace=False),
-                                    rng.choice(edge, size=100, replace=False)])
-            err = sampled_field_err(st, sc.obstacle, pos, P, cells)
-            assert err <= FIELD_RTOL, (t, err)
-            on_edge = np.flatnonzero(np.isin(pos, edge))
-            ids = np.concatenate([rng.choice(len(pos), size=60, replace=False),
-                                  rng.choice(on_edge, size=40, replace=False)])
-            g.step(1)
-            tgt_g, flags_g = g.last_moves()
-            bad = sampled_outcomes(st, sc.exit, pos, t, ids, tgt_g, flags_g, g.positions())
-            assert not bad, (t, bad[:5])
-            _say(f"[paper 1000^2] t={t} field err {err:.2e} ok")
+        rep = lockstep(g, st, sc.start_step, 26)
         assert g.stats()["live"] == sc.n_peds
+    _say("[paper 1000^2]", rep)
+    assert_parity(rep)
 
 
 WALK_CASES = [
@@ -176,8 +156,7 @@ def test_walk_period_lockstep(sf, name, make):
     with sf.GpuScene(sc) as g:
         rep = lockstep(g, st, sc.start_step, 30)
     _say(f"[walk period] {name}", rep)
-    assert rep.max_field_err <= FIELD_RTOL, rep
-    assert rep.untied == 0, (rep, rep.first_untied)
+    assert_parity(rep)
 
 
 def test_walk_period_on_a_bounded_scene_and_in_a_batch(sf):
@@ -190,8 +169,7 @@ def test_walk_period_on_a_bounded_scene_and_in_a_batch(sf):
     with sf.GpuScene(sc) as g:
         rep = lockstep(g, st, sc.start_step, 25)
     _say("[walk period bounded]", rep)
-    assert rep.max_field_err <= FIELD_RTOL, rep
-    assert rep.untied == 0, (rep, rep.first_untied)
+    assert_parity(rep)
     other = scenes.flow_scene(90, 80, 0.5, 8, radius=3, seed=24, max_walk_period=3)
     alone = []
     for s in (sc, other):

@@ -155,3 +155,21 @@ def test_total_field_composition(orc):
     ref[sc.obstacle.reshape(H, W) == 1] = np.inf
     np.testing.assert_allclose(P.reshape(H, W), ref, rtol=1e-13, atol=1e-12)
     assert np.isinf(P[sc.obstacle == 1]).all()
+
+
+@pytest.mark.parametrize("W,H,R,periodic,threads", [(61, 47, 5, False, 4), (64, 40, 7, True, 8),
+                                                    (33, 9, 12, False, 3), (70, 70, 3, True, 16)])
+def test_threaded_field_is_the_serial_field(orc, W, H, R, periodic, threads):
+    # the row-band threads give the serial scatter's field bit for bit: each
+    # su gets the same terms, and every sum of FP32 strengths is exact
+    rng = np.random.default_rng(W * H + R)
+    src = (rng.random(W * H) < 0.35).astype(np.uint8)
+    for k, alpha in ((1.0, -0.5), (-0.3, -1.0), (0.2, 1.0)):
+        a = orc.source_field(W, H, src, R, k, alpha, periodic)
+        b = orc.source_field(W, H, src, R, k, alpha, periodic, threads=threads)
+        assert np.array_equal(a, b)
+    sc = scenes.random_scene(W + 5, H + 5, n_peds=200, radius=R, seed=7, bernoulli=0.05)
+    st = orc.statics(sc)
+    st4 = orc.statics(sc, threads=threads)
+    assert np.array_equal(st.O, st4.O)
+    assert np.array_equal(orc.total_field(st, sc.pos), orc.total_field(st, sc.pos, threads))
