@@ -121,6 +121,9 @@ typedef struct {
     int64_t moved;     /* sum of pedestrians that won their election and moved    */
     int64_t tied;      /* sum of decisions whose two best FP32 values were within
                           1e-5 relative (near ties)                               */
+    int64_t max_claimants; /* most pedestrians that registered for one su in one
+                          tick, over all ticks run (section 3.1, s-2: at most 8
+                          under v_max = 1)                                        */
 } sf_stats_t;
 
 /* Flags reported per pedestrian by sf_last_moves. */
@@ -153,17 +156,26 @@ int sf_create_scene(const sf_scene_desc *desc, void *hip_stream, sf_scene **out)
 int sf_step(sf_scene *s, int32_t n_steps);
 
 /* Copy the current total field P (float32 [height*width], +inf on obstacle
- * su).  dst_on_device = 1: dst is device memory and the copy is enqueued on
- * the scene's stream; 0: dst is host memory and the call blocks. */
+ * su): the superposed field that k-5 writes back to the paper's shared field
+ * store at the end of a tick (Algorithm 1; sections 2 and 3.1), summed as
+ * Algorithms 2/3 and Eq. 1 sum it (any partition of the terms, the same
+ * total).  dst_on_device = 1: dst is device memory and the copy is enqueued
+ * on the scene's stream; 0: dst is host memory and the call blocks.  The
+ * caller owns dst, which must hold height*width floats.  SF_EINVAL for a NULL
+ * scene or dst; SF_EDEVICE if the copy fails. */
 int sf_field(const sf_scene *s, float *dst, int dst_on_device);
 
-/* Copy positions by pedestrian id (int32 [n_peds], -1 once evacuated) and,
- * if `alive` is not NULL, alive flags (uint8 [n_peds]).  Same dst_on_device
- * convention as sf_field. */
+/* Copy positions by pedestrian id (int32 [n_peds]: the centre su of section
+ * 2's discrete model, -1 once the pedestrian has left through an opening, Fig.
+ * 6 caption task 11) and, if `alive` is not NULL, alive flags (uint8 [n_peds],
+ * host memory only).  Same dst_on_device convention as sf_field; the caller
+ * owns both buffers.  SF_EINVAL for a NULL scene or pos, or alive flags asked
+ * for on the device; SF_EDEVICE if a copy fails. */
 int sf_positions(const sf_scene *s, int32_t *pos, uint8_t *alive, int dst_on_device);
 
-/* Outcome of the last tick by pedestrian id: target su (int32 [n_peds]; own su
- * when staying, -1 when already evacuated before that tick) and SF_FLAG_*
+/* Outcome of the last tick by pedestrian id (Algorithm 1: the su chosen by
+ * k-2, the election of k-3, the move of k-4): target su (int32 [n_peds]; own
+ * su when staying, -1 when already evacuated before that tick) and SF_FLAG_*
  * bits (uint8 [n_peds]).  Either pointer may be NULL.  Same dst_on_device
  * convention as sf_field.  Before the first tick all entries are zero. */
 int sf_last_moves(const sf_scene *s, int32_t *target, uint8_t *flags, int dst_on_device);
@@ -175,16 +187,22 @@ int sf_last_moves(const sf_scene *s, int32_t *target, uint8_t *flags, int dst_on
 int sf_static_field(const sf_scene *s, double *S, int32_t *D, int dst_on_device);
 
 /* Replace the pedestrian state (checkpoint resume): host positions by id
- * (int32 [n_peds], -1 = evacuated; live ones distinct, on free non-exit su)
- * and the index of the next tick.  Counters are reset as at creation with the
- * evacuated count set to the number of -1 entries.  Blocks.  SF_EINVAL on a
- * bad state. */
+ * (int32 [n_peds], -1 = evacuated; live ones distinct, on free non-exit su,
+ * as section 2 requires) and the index of the next tick t of Algorithm 1's
+ * loop.  Counters are reset as at creation with the evacuated count set to
+ * the number of -1 entries.  Blocks.  SF_EINVAL on a bad state. */
 int sf_set_state(sf_scene *s, const int32_t *pos, int64_t step);
 
-/* Copy the running totals (blocks until the scene's queued work is done). */
+/* Copy the running totals of the ticks run (Algorithm 1's loop: registrations
+ * of k-2, elections of k-3 with section 3.1's s-2 bound of 8 registrants per
+ * su, moves of k-4, departures through openings).  Blocks until the scene's
+ * queued work is done.  SF_EINVAL for a NULL argument; SF_EDEVICE if the copy
+ * fails. */
 int sf_stats(const sf_scene *s, sf_stats_t *out);
 
-/* Block until all work enqueued for the scene has finished. */
+/* Block until all work enqueued for the scene has finished (the host side of
+ * the paper's command-queue synchronisation, section 4).  SF_EINVAL for a
+ * NULL scene; SF_EDEVICE if the stream reports an error. */
 int sf_sync(const sf_scene *s);
 
 /* Field update mode.  refresh_ticks <= 1 (default 0): the field is
@@ -192,33 +210,38 @@ int sf_sync(const sf_scene *s);
  * incremental update of Algorithm 1 (k-4 buffers the field changes of the
  * pedestrians that moved, k-5 writes them back): between full superpositions,
  * a tick adds the stamps at the su its winners entered and subtracts those at
- * the su they left, and every K-th tick the field is superposed in full again
- * (FP32 rounding of the updates accumulates between refreshes).  The update
- * is one launch of the superposition kernel with the su entered and the su
- * left as two source sets, each summed in row-major source order, so it is
- * deterministic and independent of the launch shape.  Blocks.
- * SF_EINVAL for a negative value or a scene that belongs to a batch. */
+ * the su they left, into an exact FP64 pedestrian field the scene keeps (8 B
+ * per su), and every K-th tick the field is superposed in full again.  The
+ * sums are exact, so every updated field is the full superposition of the
+ * same positions bit for bit, whatever K.  The update is one launch of the
+ * superposition kernel with the su entered and the su left as two source
+ * sets.  Blocks.  SF_EINVAL for a negative value or a scene that belongs to a
+ * batch; SF_ENOMEM if the FP64 field cannot be allocated. */
 int sf_set_field_update(sf_scene *s, int32_t refresh_ticks);
 
 /* Superpose the field of the current positions again, n_times times (no
- * tick; positions, counters and step index unchanged).  The result is the
- * field sf_step leaves after a tick, bit for bit, so repeated calls change
- * nothing; under the incremental update (sf_set_field_update) it discards the
- * accumulated rounding and starts a new refresh period.  Enqueued on the
+ * tick; positions, counters and step index unchanged): k-5's write-back of
+ * Algorithm 1 alone.  The result is the field sf_step leaves after a tick, bit
+ * for bit, so repeated calls change nothing; under the incremental update
+ * (sf_set_field_update) it starts a new refresh period.  Enqueued on the
  * scene's stream (timed as SF_KERNEL_SUPERPOSE); does not block.  SF_EINVAL
  * for a negative count or a scene that belongs to a batch. */
 int sf_refresh_field(sf_scene *s, int32_t n_times);
 
-/* Per-kernel timing: while enabled, every launch of the kernels listed above
+/* Per-kernel timing of the tick's kernels (the per-job time profile of the
+ * paper's Fig. 7): while enabled, every launch of the kernels listed above
  * records a start/stop HIP event pair as part of its own dispatch (the
- * kernel's execution interval, no extra stream packets).  enable = 1 starts a fresh
- * measurement, 0 stops recording.  sf_kernel_time blocks, then reports the
- * summed duration in milliseconds and the number of launches measured for
- * one SF_KERNEL_* id. */
+ * kernel's execution interval, no extra stream packets).  enable = 1 starts a
+ * fresh measurement, 0 stops recording.  sf_kernel_time blocks, then reports
+ * the summed duration in milliseconds and the number of launches measured for
+ * one SF_KERNEL_* id (SF_EINVAL for a NULL argument or an unknown id). */
 int sf_set_timing(sf_scene *s, int enable);
 int sf_kernel_time(const sf_scene *s, int kernel, double *total_ms, int64_t *launches);
 
-/* Release the scene (NULL is ignored).  Waits for the scene's work first. */
+/* Release the scene and all its device memory (NULL is ignored): the end of
+ * Algorithm 1's simulation period.  Waits for the scene's work first.  A batch
+ * that still holds the scene can no longer step (sf_batch_step then fails
+ * with SF_EINVAL). */
 void sf_destroy_scene(sf_scene *s);
 
 /* ---- batches ---------------------------------------------------------------

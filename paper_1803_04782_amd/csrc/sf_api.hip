@@ -78,6 +78,7 @@ struct sf_scene {
     int32_t *D = nullptr;
     uint8_t *exitm = nullptr;
     unsigned long long *occ = nullptr, *claim = nullptr, *key = nullptr;
+    unsigned int *regs = nullptr;  // registrations per su in the current tick
     int32_t *pos = nullptr, *target = nullptr;
     // Per-pedestrian arrays use internal ids: live pedestrians in row-major
     // order of their positions when the state was set, then the evacuated
@@ -135,7 +136,7 @@ struct BatchLayout {
     int n_groups = 0;
     GroupLayout g[2];
     SceneView *d_all = nullptr;               // every member, batch order (totals)
-    unsigned long long *d_totals = nullptr;   // 8 words per scene (sf_batch_stats)
+    unsigned long long *d_totals = nullptr;   // 16 words per scene (sf_batch_stats)
     std::vector<void *> bufs;
 };
 
@@ -371,6 +372,13 @@ int64_t counter_sum(const unsigned long long *h, int id)
 {
     unsigned long long v = 0;
     for (int k = 0; k < sf::kSlots; ++k) v += h[sf::ctr_index(id, k)];
+    return (int64_t)v;
+}
+
+int64_t counter_max(const unsigned long long *h, int id)
+{
+    unsigned long long v = 0;
+    for (int k = 0; k < sf::kSlots; ++k) v = std::max(v, h[sf::ctr_index(id, k)]);
     return (int64_t)v;
 }
 
@@ -630,6 +638,7 @@ int create(const sf_scene_desc *d, void *hip_stream, sf_scene **out)
         (rc = dalloc(s, &s->tab, (size_t)s->lc.tab_elems, "phi table")) ||
         (rc = dalloc(s, &s->occ, (size_t)s->wpr * s->H, "occupancy")) ||
         (rc = dalloc(s, &s->claim, n, "claims")) || (rc = dalloc(s, &s->key, N, "keys")) ||
+        (rc = dalloc(s, &s->regs, n, "registrations")) ||
         (rc = dalloc(s, &s->pos, N, "positions")) || (rc = dalloc(s, &s->target, N, "targets")) ||
         (rc = dalloc(s, &s->ext, N, "id map")) ||
         (rc = dalloc(s, &s->flags, (N + 3) & ~(size_t)3, "flags")) ||
@@ -640,6 +649,8 @@ int create(const sf_scene_desc *d, void *hip_stream, sf_scene **out)
 
     hipStream_t st = s->stream;
     SF_HIP(sf::launch_fill_u64(s->claim, n, ~0ull, st), "clear claims");
+    SF_HIP(sf::launch_fill_i32(reinterpret_cast<int32_t *>(s->regs), n, 0, st),
+           "clear registrations");
     SF_HIP(sf::launch_fill_i32(s->target, N, 0, st), "clear targets");
     SF_HIP(sf::launch_fill_i32(reinterpret_cast<int32_t *>(s->flags), (N + 3) / 4, 0, st),
            "clear flags");
@@ -684,6 +695,7 @@ int setup_launches(sf_scene *s)
     v.P = s->P;
     v.occ = s->occ;
     v.claim = s->claim;
+    v.regs = s->regs;
     v.key = s->key;
     v.ctr = s->ctr;
     v.pos = s->pos;
@@ -1024,7 +1036,7 @@ int build_layout(sf_batch *b, const sf_batch_tiling *req, BatchLayout *out)
     }
     if (L.n_groups == 1) L.t.group[1] = L.t.group[0];
     if ((rc = balloc(L.bufs, &L.d_all, views.size(), "batch views")) ||
-        (rc = balloc(L.bufs, &L.d_totals, views.size() * 8, "batch totals")))
+        (rc = balloc(L.bufs, &L.d_totals, views.size() * 16, "batch totals")))
         return rc;
     SF_HIP(hipMemcpyAsync(L.d_all, views.data(), views.size() * sizeof(SceneView),
                           hipMemcpyHostToDevice, b->stream),
@@ -1372,6 +1384,8 @@ int sf_set_state(sf_scene *s, const int32_t *pos, int64_t step)
         if ((rc = upload_positions(s, pos))) return rc;
         if ((rc = reset_counters(s, step, gone))) return rc;
         SF_HIP(sf::launch_fill_u64(s->claim, n, ~0ull, st), "clear claims");
+        SF_HIP(sf::launch_fill_i32(reinterpret_cast<int32_t *>(s->regs), n, 0, st),
+               "clear registrations");
         SF_HIP(sf::launch_fill_i32(s->target, (size_t)s->N, 0, st), "clear targets");
         SF_HIP(sf::launch_fill_i32(reinterpret_cast<int32_t *>(s->flags), ((size_t)s->N + 3) / 4,
                                    0, st),
@@ -1399,6 +1413,7 @@ int sf_stats(const sf_scene *s, sf_stats_t *out)
     out->movers = counter_sum(h.data(), sf::kMovers);
     out->moved = counter_sum(h.data(), sf::kMoved);
     out->tied = counter_sum(h.data(), sf::kTied);
+    out->max_claimants = counter_max(h.data(), sf::kMaxClaim);
     return SF_OK;
 }
 
@@ -1519,7 +1534,7 @@ int sf_batch_stats(const sf_batch *b, sf_stats_t *out)
     DeviceGuard g(b->device);
     try {
         const size_t n = b->scenes.size();
-        std::vector<unsigned long long> h(n * 8);
+        std::vector<unsigned long long> h(n * 16);
         SF_HIP(sf::launch_sum_counters(b->cur.d_all, (int)n, b->cur.d_totals, b->stream),
                "batch totals");
         SF_HIP(hipMemcpyAsync(h.data(), b->cur.d_totals, h.size() * 8, hipMemcpyDeviceToHost,
@@ -1527,7 +1542,7 @@ int sf_batch_stats(const sf_batch *b, sf_stats_t *out)
                "batch totals copy");
         SF_HIP(hipStreamSynchronize(b->stream), "batch totals sync");
         for (size_t j = 0; j < n; ++j) {
-            const unsigned long long *w = &h[j * 8];
+            const unsigned long long *w = &h[j * 16];
             out[j].step = (int64_t)w[0];
             out[j].live = (int64_t)w[1 + sf::kLive];
             out[j].evacuated = (int64_t)w[1 + sf::kEvacuated];
@@ -1535,6 +1550,7 @@ int sf_batch_stats(const sf_batch *b, sf_stats_t *out)
             out[j].movers = (int64_t)w[1 + sf::kMovers];
             out[j].moved = (int64_t)w[1 + sf::kMoved];
             out[j].tied = (int64_t)w[1 + sf::kTied];
+            out[j].max_claimants = (int64_t)w[1 + sf::kMaxClaim];
         }
     } catch (const std::bad_alloc &) {
         return fail(SF_ENOMEM, "host allocation failed");

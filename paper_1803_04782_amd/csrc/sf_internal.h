@@ -26,6 +26,7 @@ enum CounterId {
     kMovers,      // registrations
     kMoved,       // election winners
     kTied,        // FP32 near-tie decisions
+    kMaxClaim,    // most registrants of one su in one tick (a running maximum)
     kScratch,     // set-up counts (reachability)
     kNumCounters
 };
@@ -107,6 +108,9 @@ struct SceneView {
     // on (written by full superpositions, updated in place), else NULL
     double *phi;
     unsigned long long *occ, *claim, *key, *ctr;
+    // registrations per su in the current tick (decide adds, the election's
+    // winner clears it in commit)
+    unsigned int *regs;
     // per-pedestrian arrays are indexed by an internal id (pedestrians in
     // row-major order of their positions when the state was set); ext maps
     // it to the caller's id, which keys the election
@@ -215,7 +219,8 @@ hipError_t launch_scatter_i32(const int32_t *src, const int32_t *ext, int32_t *d
                               hipStream_t st);
 hipError_t launch_scatter_u8(const uint8_t *src, const int32_t *ext, uint8_t *dst, int n,
                              hipStream_t st);
-// out[j*8 + 0] = step of scene j, out[j*8 + 1 + id] = running total id.
+// out[j*16 + 0] = step of scene j, out[j*16 + 1 + id] = running total id
+// (kMaxClaim: the maximum over the slots, every other total: their sum).
 hipError_t launch_sum_counters(const SceneView *views, int n_scenes, unsigned long long *out,
                                hipStream_t st);
 

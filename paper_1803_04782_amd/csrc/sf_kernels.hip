@@ -87,6 +87,27 @@ __device__ __forceinline__ void block_sums_add(const int (&v)[NV], Ctr ctr, cons
     __syncthreads();
 }
 
+// Maximum of `v` over the block into copy (block % kSlots) of running total
+// `id` by one atomic maximum (skipped when 0).  Every thread of the block must
+// call it; it synchronises the block.
+template <typename Ctr>
+__device__ __forceinline__ void block_max_into(unsigned int v, Ctr ctr, int id)
+{
+    __shared__ unsigned int part[16];
+    for (int d = 32; d >= 1; d >>= 1) v = max(v, (unsigned int)__shfl_xor(v, d));
+    const int wv = threadIdx.x >> 6;
+    if (lane_id() == 0) part[wv] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long m = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) m = max(m, (unsigned long long)part[w]);
+        if (m)
+            __hip_atomic_fetch_max(&ctr[ctr_index(id, blockIdx.x % kSlots)], m, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+}
+
 // Pointer into LDS (address space 3): 32-bit byte addresses, ds_* instructions.
 template <typename T>
 using lds_ptr = const __attribute__((address_space(3))) T *;
@@ -1115,7 +1136,7 @@ __global__ __launch_bounds__(kDecideThreads) void k_decide_claim(
     }
     const unsigned long long seed = v.seed;
     const float phi_axial = v.phi_axial, phi_diag = v.phi_diag;
-    unsigned int movers = 0, ties = 0;
+    unsigned int movers = 0, ties = 0, regs_seen = 0;
     // the step index and this pedestrian's arrays are requested together and
     // waited for once (the empty asm takes all of them, so no load is moved
     // behind a branch that would wait for it alone)
@@ -1308,6 +1329,11 @@ __global__ __launch_bounds__(kDecideThreads) void k_decide_claim(
                                              (uint32_t)seed, (uint32_t)(seed >> 32));
                 const unsigned long long kk = ((unsigned long long)r << 32) | eid;
                 __hip_atomic_fetch_min(&claim[tgt], kk, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                // registrations at the target so far, this one included (s-2:
+                // at most 8 under v_max = 1)
+                regs_seen = 1u + __hip_atomic_fetch_add(&to_global(v.regs)[tgt], 1u,
+                                                        __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_AGENT);
                 key[i] = kk;
                 mover = true;
             }
@@ -1318,6 +1344,7 @@ __global__ __launch_bounds__(kDecideThreads) void k_decide_claim(
         }
     }
     block_sums_add<2>({(int)movers, (int)ties}, ctr, {kMovers, kTied});
+    block_max_into(regs_seen, ctr, kMaxClaim);
 }
 
 // ---- commit (k-4 moves, exits) -------------------------------------------------------
@@ -1358,6 +1385,7 @@ __global__ __launch_bounds__(commit_threads<MULTI>()) void k_commit(SceneView on
                 if (cw == kk) {
                     won = true;
                     claim[tgt] = ~0ull;
+                    to_global(v.regs)[tgt] = 0u;
                     const int y = p / W, x = p - y * W;
                     const size_t wp = (size_t)y * wpr + (x >> 6);
                     __hip_atomic_fetch_and(&occ[wp], ~(1ull << (x & 63)), __ATOMIC_RELAXED,
@@ -1402,7 +1430,8 @@ __global__ void k_scatter(const T *__restrict__ src, const int32_t *__restrict__
 // ---- batched counter read-out --------------------------------------------------------
 //
 // Workgroup j sums the slot copies of every running total of scene j into
-// out[j * 8 + (0: step, 1 + id: total id)].
+// out[j * 16 + (0: step, 1 + id: total id)]: the slot copies are summed,
+// except those of the running maximum kMaxClaim.
 
 __global__ __launch_bounds__(64) void k_sum_counters(const SceneView *__restrict__ views,
                                                      unsigned long long *__restrict__ out)
@@ -1413,11 +1442,14 @@ __global__ __launch_bounds__(64) void k_sum_counters(const SceneView *__restrict
     unsigned long long mine = 0;
     for (int id = 0; id < kNumCounters; ++id) {
         unsigned long long v = ctr[ctr_index(id, lane)];
-        for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
+        for (int d = 32; d >= 1; d >>= 1) {
+            const unsigned long long o = __shfl_xor(v, d);
+            v = id == kMaxClaim ? max(v, o) : v + o;
+        }
         if (lane == 1 + id) mine = v;
     }
     if (lane == 0) mine = ctr[0];
-    if (lane < 8) out[(size_t)blockIdx.x * 8 + lane] = mine;
+    if (lane < 16) out[(size_t)blockIdx.x * 16 + lane] = mine;
 }
 
 // Plain launch, or a launch whose dispatch records `ev` (kernel timing).
@@ -1823,7 +1855,7 @@ hipError_t launch_scatter_u8(const uint8_t *src, const int32_t *ext, uint8_t *ds
 hipError_t launch_sum_counters(const SceneView *views, int n_scenes, unsigned long long *out,
                                hipStream_t st)
 {
-    static_assert(kSlots == 64 && kNumCounters <= 7, "one lane per slot, eight words per scene");
+    static_assert(kSlots == 64 && kNumCounters <= 15, "one lane per slot, 16 words per scene");
     hipLaunchKernelGGL(k_sum_counters, dim3(n_scenes), dim3(64), 0, st, views, out);
     return hipGetLastError();
 }

@@ -36,10 +36,11 @@ from . import sf
 
 # Device bytes a resident scene holds (the library's per-scene arrays):
 # per su  S (FP64, 8 B), P and D (4 B each), exit mask (1), claims (8),
-# occupancy bits (1/8); per pedestrian  keys (8), positions, targets, id map
-# (4 each), flags (1); plus counters, the stamp and the scene's share of a
-# batch's layout (views, workgroup maps, work items, stamp tables): < 1 MiB.
-BYTES_PER_SU = 8 + 4 + 4 + 1 + 8 + 0.125
+# registration counts (4), occupancy bits (1/8); per pedestrian  keys (8),
+# positions, targets, id map (4 each), flags (1); plus counters, the stamp and
+# the scene's share of a batch's layout (views, workgroup maps, work items,
+# stamp tables): < 1 MiB.
+BYTES_PER_SU = 8 + 4 + 4 + 1 + 8 + 4 + 0.125
 BYTES_PER_PED = 8 + 4 + 4 + 4 + 1
 FIXED_BYTES = 1 << 20
 # Temporaries of scene creation, released when the build ends: per su the

@@ -56,7 +56,8 @@ class SceneDesc(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("step", ctypes.c_int64), ("live", ctypes.c_int64), ("evacuated", ctypes.c_int64),
                 ("ped_steps", ctypes.c_int64), ("movers", ctypes.c_int64),
-                ("moved", ctypes.c_int64), ("tied", ctypes.c_int64)]
+                ("moved", ctypes.c_int64), ("tied", ctypes.c_int64),
+                ("max_claimants", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}

@@ -237,6 +237,7 @@ def test_stats_consistency(sf):
             moved += int(((flags & sf.SF_FLAG_WON) != 0).sum())
             tied += int(((flags & sf.SF_FLAG_TIED) != 0).sum())
         s = g.stats()
+        assert s["max_claimants"] <= 8
         assert s["ped_steps"] == total
         assert s["live"] + s["evacuated"] == sc.n_peds
         assert s["live"] == int((g.positions() >= 0).sum())
@@ -264,3 +265,27 @@ def test_plaza8192_full(sf):
         rep = lockstep(g, st, 0, 2)
         _say(f"[plaza] {rep}, host {time.time() - t0:.1f} s")
     assert_parity(rep)
+
+
+def test_max_claimants_dense_crowd(sf):
+    """sf_stats' max_claimants (section 3.1, s-2: at most 8 registrants per su
+    under v_max = 1) equals the largest number of the oracle's movers that
+    chose one su in one tick, on a crowd dense enough for many-way
+    elections."""
+    sc = scenes.random_scene(120, 90, n_peds=0, radius=2, seed=31, bernoulli=0.02,
+                             exits=("E", "W", "N", "S"), exit_width=10, occupancy=0.55)
+    st = oracle.statics(sc)
+    most = 0
+    with sf.GpuScene(sc) as g:
+        for t in range(15):
+            pos = g.positions()
+            r = oracle.step(st, pos, t, threads=THREADS)
+            movers = (pos >= 0) & (r.target != pos)
+            if movers.any():
+                most = max(most, int(np.bincount(r.target[movers]).max()))
+            g.step(1)
+            assert np.array_equal(g.positions(), r.pos), t
+        s = g.stats()
+    _say(f"[claimants] most registrants of one su: GPU {s['max_claimants']}, oracle {most}")
+    assert s["max_claimants"] == most
+    assert 3 <= most <= 8
