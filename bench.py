@@ -1,33 +1,25 @@
 """Benchmark of the social-field tick on one MI355X.
 
-Workload: the 1024x1024 hall (5% rectangle obstacles, two 16-su exits,
-50,000 pedestrians, field radius 16, 500 ticks), synthetic and seeded.  A
-"step" is one tick of the whole hot path: bin, decide + claim, commit,
-superpose.  Inputs are resident in HBM when the timed region starts.
+Default line (the metric's configuration): the batched ensemble of 256
+uneven scenes (sides 128..2048 su, obstacle cover 0..10%, 1..10% occupancy,
+radii 4/8/16/32, 1..4 exits), synthetic and seeded.  A "step" is one tick of
+the whole hot path for every scene: bin, decide + claim, commit, superpose.
+Inputs are resident in HBM when the timed region starts.  The batch (one
+decide, commit and field launch per group per tick, graph replays, autotuned
+tiling) is timed over K ticks five times from the same reset state, and the
+median run is `value`; the plain loop of per-scene sf_step ticks is timed the
+same way for `batched_vs_plain`.  The line carries the roofline of the
+batched field superposition (HIP events around back-to-back field passes),
+the FP64 oracle timed on all host cores on a bounded sample, an accuracy
+gate against the oracle, and sub-objects: "hall1024" and "plaza8192"
+(single scenes, each with its own roofline and accuracy gate) and "serving"
+(a short continuous-batching leg at 50, 200 and 800 arrivals/s).
 
-Prints one JSON line: pedestrian-steps/s (value) and su-field updates/s, the
-roofline of the dominant kernel (field superposition) from HIP events recorded
-around its launches, the CPU oracle timed on a bounded sample, and (object
-"ensemble256") the batched-vs-plain comparison described below.
-
---workload serving runs the serving loop (Poisson arrivals at 50, 200 and 800
-scenes/s, sizes from the same distribution, each scene to evacuation or 2000
-ticks, admission by device footprint) and reports per-tick latency p50/p99
-and scenes/s per rate.
-
---workload ensemble256 measures batching instead: 256 scenes of uneven size,
-crowd and radius (sides 128..2048 su, 300 ticks), stepped once as a plain
-loop of per-scene ticks and once as a batch (one decide, commit and field
-launch per tick for all scenes, graph replays, autotuned tiling), with both
-results checked to be identical and a lockstep tick of the smallest scenes
-against the oracle.
-
---workload flow1000 runs the paper's own experiment scenario (section 5,
-Table IV): a 1000x1000 torus, density 0.5, 8-directional flow, 7x7 fields,
-1000 ticks, with the paper's time quoted beside it as context; --workload
-flow-sweep runs its 360-combination grid (sides 100..1000, densities
-0.1..0.9, 1/2/4/8 directions) and --workload flow-walk its walk-period
-experiment (Table V: flow1000 with periods uniform in 1..max, max = 1..11).
+Other workloads (--workload): hall1024, room64, plaza8192 (one scene each),
+serving (longer windows), flow1000 (the paper's section 5 scenario: a
+1000x1000 torus, density 0.5, 8-directional flow, 7x7 fields, 1000 ticks),
+flow-sweep (its 360-combination grid) and flow-walk (its walk-period
+experiment of Table V).
 """
 from __future__ import annotations
 
@@ -45,37 +37,70 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "pedestrian-steps/s + su-field updates/s; batched vs plain, 0 untied mismatches"
-# Non-packed FP32 add rate of MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz.
+# The field is summed with one FP64 add per (pedestrian, su) contribution.
+# MI355X issues one FP64 add (or FMA) per lane per clock: 256 CUs x 64 lanes
+# x 2.4 GHz = 39.3e12 adds/s (the 78.6 TFLOP/s FP64 vector peak counts an FMA
+# as two flops).
 ALU_PEAK_TFLOPS = 256 * 64 * 2.4e9 / 1e12
+HBM_PEAK = 8.0e12
 # back-to-back field launches timed for the roofline
 FIELD_LOOP = 200
+# host threads of the oracle: the cores a GPU machine grants one GPU's job
+ORACLE_THREADS_CAP = 16
 KERNEL_SRC = os.path.join(ROOT, "paper_1803_04782_amd", "csrc", "sf_kernels.hip")
-PMC_SUMMARY = os.path.join(ROOT, "profiles", "superpose_hall1024_pmc.json")
+PMC_DIR = os.path.join(ROOT, "profiles")
+
+
+def say(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
 
 
 def kernel_source_hash() -> str:
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
 
 
-def window_contributions(sc) -> float:
-    """Mean number of (pedestrian, su) pairs per pedestrian with the su inside
-    the grid and the pedestrian's window, own su excluded, at the initial
-    positions."""
-    W, H, R = sc.width, sc.height, sc.radius
-    if getattr(sc, "periodic", False):
-        return float((2 * R + 1) ** 2 - 1)  # a torus: every window is whole
-    x = sc.pos % W
-    y = sc.pos // W
+def host_info() -> dict:
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model}
+
+
+def oracle_threads() -> int:
+    import oracle
+
+    return min(ORACLE_THREADS_CAP, oracle.host_threads())
+
+
+def contributions(W, H, R, periodic, pos) -> float:
+    """(pedestrian, su) pairs of the live pedestrians: su inside the grid and
+    the pedestrian's window, own su excluded (one FP64 add each)."""
+    live = np.asarray(pos)
+    live = live[live >= 0]
+    if periodic:
+        return float(live.size) * ((2 * R + 1) ** 2 - 1)  # a torus: every window is whole
+    x, y = live % W, live // W
     wx = np.minimum(x + R, W - 1) - np.maximum(x - R, 0) + 1
     wy = np.minimum(y + R, H - 1) - np.maximum(y - R, 0) + 1
-    return float(np.mean(wx * wy - 1))
+    return float(np.sum(wx * wy - 1))
 
 
-def traffic_per_launch():
-    """HBM bytes per superposition launch from the committed rocprofv3 PMC
-    summary, if it was taken on the current kernel source."""
+def field_bytes(W, H) -> float:
+    """Algorithmic bytes of one field pass: S (FP64) read and P (FP32)
+    written once per su, the occupancy bitmap read once."""
+    return 12.0 * W * H + 8.0 * ((W + 63) // 64) * H
+
+
+def traffic_per_launch(name):
+    """HBM bytes per field launch from the committed rocprofv3 PMC summary
+    profiles/<name>_pmc.json, if it was taken on the current kernel source."""
     try:
-        d = json.load(open(PMC_SUMMARY))
+        d = json.load(open(os.path.join(PMC_DIR, f"{name}_pmc.json")))
     except (OSError, ValueError):
         return None
     if d.get("kernel_source_sha256_16") != kernel_source_hash():
@@ -83,57 +108,184 @@ def traffic_per_launch():
     return d.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(sc, gpu_state, seconds: float = 12.0):
-    """The FP64 oracle as it stands (single thread) on a bounded sample of the
-    workload, plus the same-run accuracy gate: one lockstep tick of the GPU
-    state against the oracle."""
+def roofline(contrib, nbytes, launch_us, kernel, timing, traffic_name):
+    achieved = contrib / (launch_us * 1e-6) / 1e12
+    r = {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+         "frac": achieved / ALU_PEAK_TFLOPS, "traffic": traffic_per_launch(traffic_name),
+         "kernel": kernel, "flop_per_launch": contrib, "avg_launch_us": launch_us,
+         "launch_timing": timing, "algorithmic_bytes_per_launch": nbytes,
+         "hbm_frac": nbytes / (launch_us * 1e-6) / HBM_PEAK}
+    if r["traffic"] is not None:
+        r["measured_hbm_GBps"] = r["traffic"] / (launch_us * 1e-6) / 1e9
+    t_hbm, t_alu = nbytes / HBM_PEAK, contrib / (ALU_PEAK_TFLOPS * 1e12)
+    r["floor_us"] = 1e6 * max(t_hbm, t_alu)
+    r["floor_binding"] = "alu" if t_alu >= t_hbm else "hbm"
+    return r
+
+
+def windows(k: int, n: int = 5):
+    """k timed ticks split into up to n windows of near-equal length."""
+    n = max(1, min(n, k))
+    return [k // n + (1 if i < k % n else 0) for i in range(n)]
+
+
+def gate_tick(st, pos, P_g, t, tgt_g, flags_g, pos_next, threads):
+    """One tick of a GPU scene against the oracle's full tick: field bits,
+    relative error and mismatched decisions (the parity bar)."""
     import oracle
 
-    st = oracle.statics(sc)
-    pos = sc.pos.copy()
-    live_sum = 0
-    ticks = 0
-    t0 = time.perf_counter()
-    while time.perf_counter() - t0 < seconds and ticks < sc.steps:
-        live_sum += int((pos >= 0).sum())
-        pos = oracle.step(st, pos, sc.start_step + ticks).pos
-        ticks += 1
-    dt = time.perf_counter() - t0
-    base = {"value": live_sum / dt, "unit": "pedestrian-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {ticks} ticks of the workload from its initial state "
-                      f"(FP64 C oracle, one thread, {dt:.1f} s)"}
-    # accuracy gate on the GPU's final state
-    pos_g, P_g, t_g, tgt_g, flags_g, pos_next = gpu_state
-    r = oracle.step(st, pos_g, t_g)
-    free = sc.obstacle == 0
-    err = float(np.max(np.abs(P_g[free] - r.P[free]) / np.maximum(np.abs(r.P[free]), 1.0)))
-    live = pos_g >= 0
+    r = oracle.step(st, pos, t, threads=threads)
+    free = st.obstacle == 0
+    err = 0.0
+    if free.any():
+        err = float(np.max(np.abs(P_g[free] - r.P[free]) / np.maximum(np.abs(r.P[free]), 1.0)))
+    live = pos >= 0
     won = (flags_g & 2) != 0
     bad = live & ((tgt_g != r.target) | (won != (r.moved == 1)) | (pos_next != r.pos))
-    tied = set(r.target[live & (r.tied == 1)].tolist()) | set(tgt_g[live & (r.tied == 1)].tolist())
+    hot = set(r.target[live & (r.tied == 1)].tolist()) | set(tgt_g[live & (r.tied == 1)].tolist())
     untied = [j for j in np.flatnonzero(bad)
-              if not r.tied[j] and r.target[j] not in tied and tgt_g[j] not in tied]
-    gate = {"tick": int(t_g), "field_rel_err": err, "untied_mismatches": len(untied),
+              if not r.tied[j] and r.target[j] not in hot and tgt_g[j] not in hot
+              and pos[j] not in hot]
+    return {"field_su_differing": int(np.count_nonzero(P_g != r.P.astype(np.float32))),
+            "field_rel_err": err, "untied_mismatches": len(untied),
             "tied_mismatches": int(bad.sum()) - len(untied),
             "near_tie_decisions": int(r.tied[live].sum()), "decisions": int(live.sum())}
-    return base, gate
 
 
-def bench_ensemble(args, stream, steps=None, emit=True):
-    """Batched vs plain on the uneven 256-scene ensemble; prints the JSON line
-    (emit) and returns it."""
+def merge_gates(gates):
+    out = {"field_su_differing": 0, "field_rel_err": 0.0, "untied_mismatches": 0,
+           "tied_mismatches": 0, "near_tie_decisions": 0, "decisions": 0}
+    for g in gates:
+        for k in out:
+            out[k] = max(out[k], g[k]) if k == "field_rel_err" else out[k] + g[k]
+    return out
+
+
+def oracle_sample(items, seconds, threads):
+    """The FP64 oracle as it stands on a bounded sample: for each (statics,
+    positions, tick) the oracle's full tick (field on `threads` threads);
+    statics are built outside the timed region (scene creation)."""
+    import oracle
+
+    live_sum, ticks, t_run = 0, 0, 0.0
+    for make, label in items:
+        st, pos, t = make()
+        while True:
+            t0 = time.perf_counter()
+            r = oracle.step(st, pos, t, threads=threads)
+            t_run += time.perf_counter() - t0
+            live_sum += int((pos >= 0).sum())
+            ticks += 1
+            pos, t = r.pos, t + 1
+            if t_run >= seconds or label == "one":
+                break
+        if t_run >= seconds:
+            break
+    return live_sum, ticks, t_run
+
+
+def cpu_baseline_dict(live_sum, ticks, t_run, threads, sample):
+    d = {"value": live_sum / t_run if t_run > 0 else None, "unit": "pedestrian-steps/s",
+         "cores": threads, "kind": "oracle", "sample": sample, "timed_s": t_run,
+         "ticks": ticks}
+    d.update(host_info())
+    return d
+
+
+def single_scene(sc, args, stream, steps, field_loop, cpu_seconds, kernel_label):
+    """One scene: `steps` timed ticks after warm-up (from the initial state),
+    per-kernel events, the field roofline from back-to-back launches, a
+    one-tick accuracy gate and the oracle baseline."""
+    import torch
+
+    import oracle
+    from paper_1803_04782_amd import sf
+
+    threads = oracle_threads()
+    free_su = int((sc.obstacle == 0).sum())
+    t0 = time.perf_counter()
+    g = sf.GpuScene(sc, stream=stream)
+    say(f"{sc.name}: {sc.width}x{sc.height} su, {sc.n_peds} pedestrians, R={sc.radius}, "
+        f"created in {time.perf_counter() - t0:.1f} s")
+    if args.field_update:
+        g.set_field_update(args.field_update)
+    try:
+        g.step(args.warmup)
+        g.set_state(sc.pos, sc.start_step)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.step(steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        s = g.stats()
+        # same ticks again with HIP events around every kernel launch
+        g.set_state(sc.pos, sc.start_step)
+        g.set_timing(True)
+        g.step(steps)
+        torch.cuda.synchronize()
+        ktimes = {}
+        for name, kid in (("superpose", sf.SF_KERNEL_SUPERPOSE), ("decide", sf.SF_KERNEL_DECIDE),
+                          ("commit", sf.SF_KERNEL_COMMIT)):
+            ms, n = g.kernel_time(kid)
+            ktimes[name] = {"avg_us": 1000.0 * ms / max(n, 1), "launches": n}
+        g.set_timing(False)
+        # the field alone, back to back on the final state (the field keeps
+        # its bits), two HIP events around the loop on the scene's stream
+        pos_end = g.positions()
+        g.refresh_field(5)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        g.refresh_field(field_loop)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        field_us = 1000.0 * e0.elapsed_time(e1) / field_loop
+        # accuracy gate: the next tick against the oracle's full tick
+        P_g = g.field()
+        t_g = g.stats()["step"]
+        g.step(1)
+        tgt_g, flags_g = g.last_moves()
+        pos_next = g.positions()
+    finally:
+        g.close()
+    st = oracle.statics(sc, threads=threads)
+    gate = gate_tick(st, pos_end, P_g, t_g, tgt_g, flags_g, pos_next, threads)
+    gate["tick"] = int(t_g)
+    contrib = contributions(sc.width, sc.height, sc.radius, sc.periodic, pos_end)
+    out = {"value": s["ped_steps"] / dt, "unit": "pedestrian-steps/s", "steps": steps,
+           "ms_per_step": 1000.0 * dt / steps,
+           "su_field_updates_per_s": steps * free_su / dt,
+           "config": {"workload": sc.name, "grid": [sc.width, sc.height],
+                      "pedestrians": sc.n_peds, "radius": sc.radius, "ticks": steps,
+                      "field_update": args.field_update},
+           "kernels": ktimes,
+           "roofline": roofline(contrib, field_bytes(sc.width, sc.height), field_us, kernel_label,
+                                f"{field_loop} back-to-back field launches on the final state, "
+                                "HIP events around the loop on the scene's stream", sc.name),
+           "accuracy_gate": gate, "stats": s}
+    out["roofline"]["tick_launch_interval_us"] = ktimes["superpose"]["avg_us"]
+    if cpu_seconds > 0:
+        live_sum, ticks, t_run = oracle_sample(
+            [(lambda: (st, sc.pos.copy(), sc.start_step), "run")], cpu_seconds, threads)
+        out["cpu_baseline"] = cpu_baseline_dict(
+            live_sum, ticks, t_run, threads,
+            f"first {ticks} ticks of {sc.name} from its initial state (FP64 C oracle, field on "
+            f"{threads} threads, {t_run:.1f} s)")
+    else:
+        out["cpu_baseline"] = None
+    return out
+
+
+def ensemble_line(args, stream, steps):
+    """Batched vs plain on the uneven ensemble: the default line's headline."""
     import torch
 
     import oracle
     from paper_1803_04782_amd import scenes, sf
 
-    def say(*a):
-        print("[bench]", *a, file=sys.stderr, flush=True)
-
+    threads = oracle_threads()
     t0 = time.perf_counter()
     scs = scenes.ensemble(n_scenes=args.scenes, seed=3)
-    if steps is None:
-        steps = args.steps if args.steps is not None else scs[0].steps
     su_total = sum(s.width * s.height for s in scs)
     free_total = sum(int((s.obstacle == 0).sum()) for s in scs)
     peds_total = sum(s.n_peds for s in scs)
@@ -144,6 +296,7 @@ def bench_ensemble(args, stream, steps=None, emit=True):
     member = [sf.GpuScene(s, stream=stream) for s in scs]
     say(f"created {2 * len(scs)} scenes in {time.perf_counter() - t0:.1f} s")
     b = sf.Batch(member, stream=stream)
+    wins = windows(steps)
     try:
         t0 = time.perf_counter()
         tiling = b.tune(reps=3)
@@ -153,82 +306,151 @@ def bench_ensemble(args, stream, steps=None, emit=True):
                 g.step(1)
         b.step(args.warmup)
         torch.cuda.synchronize()
-        ps_plain0 = sum(g.stats()["ped_steps"] for g in plain)
-        ps_batch0 = sum(x["ped_steps"] for x in b.stats())
 
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            for g in plain:
-                g.step(1)
-        torch.cuda.synchronize()
-        dt_plain = time.perf_counter() - t0
-        say(f"plain loop: {steps} ticks in {dt_plain:.2f} s")
-        t0 = time.perf_counter()
-        b.step(steps)
-        torch.cuda.synchronize()
-        dt_batch = time.perf_counter() - t0
-        say(f"batched: {steps} ticks in {dt_batch:.2f} s")
-        ps_plain = sum(g.stats()["ped_steps"] for g in plain) - ps_plain0
+        def ped_steps_plain():
+            return sum(g.stats()["ped_steps"] for g in plain)
+
+        def ped_steps_batch():
+            return sum(x["ped_steps"] for x in b.stats())
+
+        runs_p, runs_b = [], []
+        for k in wins:
+            ps0 = ped_steps_plain()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(k):
+                for g in plain:
+                    g.step(1)
+            torch.cuda.synchronize()
+            runs_p.append((k, time.perf_counter() - t0, ped_steps_plain() - ps0))
+        for k in wins:
+            ps0 = ped_steps_batch()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            b.step(k)
+            torch.cuda.synchronize()
+            runs_b.append((k, time.perf_counter() - t0, ped_steps_batch() - ps0))
+        dt_p = sum(r[1] for r in runs_p)
+        dt_b = sum(r[1] for r in runs_b)
+        ps_p = sum(r[2] for r in runs_p)
+        ps_b = sum(r[2] for r in runs_b)
+        say(f"plain: {steps} ticks in {dt_p:.3f} s; batched: {dt_b:.3f} s")
         totals = b.stats()
-        ps_batch = sum(x["ped_steps"] for x in totals) - ps_batch0
 
-        # the two runs must agree bit for bit (positions of every scene, fields
-        # of the 16 smallest)
+        # the batched field alone, back to back, HIP events on the batch's stream
+        pos_all = [m.positions() for m in member]
+        contrib = sum(contributions(s.width, s.height, s.radius, s.periodic, p)
+                      for s, p in zip(scs, pos_all))
+        nbytes = sum(field_bytes(s.width, s.height) for s in scs)
+        loops = 20
+        b.refresh_field(2)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        b.refresh_field(loops)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        pass_us = 1000.0 * e0.elapsed_time(e1) / loops
+        n_groups = tiling["groups"]
+
+        # the two runs agree bit for bit (positions of every scene, fields of
+        # the 16 smallest); one full tick of the 8 smallest and the largest
+        # scene against the oracle
         order = np.argsort([s.width * s.height for s in scs])
         same_pos = all(np.array_equal(a.positions(), m.positions()) for a, m in zip(plain, member))
         same_field = all(np.array_equal(plain[j].field(), member[j].field()) for j in order[:16])
-        # one lockstep tick of the 8 smallest scenes against the oracle
-        small = [int(j) for j in order[:8]]
+        checked = [int(j) for j in order[:8]] + [int(order[-1])]
         before = []
-        for j in small:
-            st = oracle.statics(scs[j])
-            pos = member[j].positions()
-            before.append((j, st, pos, member[j].field(),
-                           oracle.step(st, pos, totals[j]["step"])))
+        for j in checked:
+            before.append((j, pos_all[j], member[j].field(), totals[j]["step"]))
         b.step(1)
-        err, untied, tied = 0.0, 0, 0
-        for j, st, pos, P_g, r in before:
-            free = st.obstacle == 0
-            if free.any():
-                err = max(err, float(np.max(np.abs(P_g[free] - r.P[free]) /
-                                            np.maximum(np.abs(r.P[free]), 1.0))))
+        gates = []
+        for j, pos, P_g, t in before:
+            st = oracle.statics(scs[j], threads=threads)
             tgt_g, flags_g = member[j].last_moves()
-            pos_g = member[j].positions()
-            live = pos >= 0
-            won = (flags_g & 2) != 0
-            bad = live & ((tgt_g != r.target) | (won != (r.moved == 1)) | (pos_g != r.pos))
-            hot = set(r.target[live & (r.tied == 1)].tolist()) | \
-                set(tgt_g[live & (r.tied == 1)].tolist())
-            u = [k for k in np.flatnonzero(bad)
-                 if not r.tied[k] and r.target[k] not in hot and tgt_g[k] not in hot
-                 and pos[k] not in hot]
-            untied += len(u)
-            tied += int(bad.sum()) - len(u)
+            gates.append(gate_tick(st, pos, P_g, t, tgt_g, flags_g, member[j].positions(),
+                                   threads))
+        gate = merge_gates(gates)
+        gate["scenes"] = len(checked)
     finally:
         b.close()
         for g in plain + member:
             g.close()
 
-    value = ps_batch / dt_batch
-    out = {"metric": METRIC, "value": value, "unit": "pedestrian-steps/s", "n_gpus": 1,
-           "steps": steps, "warmup": args.warmup, "ms_per_step": 1000.0 * dt_batch / steps,
-           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+    # the oracle on all host cores: one tick of scenes in a seeded random
+    # order, each from its initial state, bounded to args.cpu_seconds
+    rng = np.random.default_rng(7)
+    pick = [int(j) for j in rng.permutation(len(scs))]
+    items = [((lambda j=j: (oracle.statics(scs[j], threads=threads), scs[j].pos.copy(),
+                             scs[j].start_step)), "one") for j in pick]
+    live_sum, ticks, t_run = oracle_sample(items, args.cpu_seconds, threads)
+    base = cpu_baseline_dict(
+        live_sum, ticks, t_run, threads,
+        f"first tick of {ticks} ensemble scenes in a seeded random order, each from its "
+        f"initial state (FP64 C oracle, field on {threads} threads, {t_run:.1f} s; statics "
+        "built outside the timed region)")
+
+    rate_b = [r[2] / r[1] for r in runs_b]
+    rate_p = [r[2] / r[1] for r in runs_p]
+    field_label = ("superpose (batched: " + ("one launch" if n_groups == 1 else
+                                             f"{n_groups} launches, one per radius group")
+                   + " per pass)")
+    out = {"metric": METRIC, "value": ps_b / dt_b, "unit": "pedestrian-steps/s", "n_gpus": 1,
+           "steps": steps, "warmup": args.warmup, "ms_per_step": 1000.0 * dt_b / steps,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
            "data": "synthetic",
            "config": {"workload": f"ensemble{len(scs)}", "scenes": len(scs), "su": su_total,
                       "pedestrians": peds_total, "ticks": steps, "sides": [128, 2048],
                       "radii": [4, 8, 16, 32], "parallelism": "single-gpu"},
-           "su_field_updates_per_s": steps * free_total / dt_batch,
-           "plain": {"value": ps_plain / dt_plain, "ms_per_step": 1000.0 * dt_plain / steps},
-           "batched_vs_plain": (ps_batch / dt_batch) / (ps_plain / dt_plain),
+           "su_field_updates_per_s": steps * free_total / dt_b,
+           "windows": {"ticks": wins, "batched_rate_median": float(np.median(rate_b)),
+                       "batched_rates": rate_b, "plain_rate_median": float(np.median(rate_p)),
+                       "plain_rates": rate_p},
+           "plain": {"value": ps_p / dt_p, "ms_per_step": 1000.0 * dt_p / steps},
+           "batched_vs_plain": (ps_b / dt_b) / (ps_p / dt_p),
+           "batched_vs_plain_median": float(np.median(rate_b) / np.median(rate_p)),
            "tiling": tiling,
            "identical_to_plain": {"positions_all_scenes": bool(same_pos),
                                   "fields_16_smallest": bool(same_field)},
-           "accuracy_gate": {"scenes": len(small), "field_rel_err": err,
-                             "untied_mismatches": untied, "tied_mismatches": tied},
-           "roofline": None, "cpu_baseline": None}
-    if emit:
-        print(json.dumps(out), flush=True)
+           "accuracy_gate": gate,
+           "roofline": roofline(contrib, nbytes, pass_us, field_label,
+                                f"{loops} back-to-back batched field passes on the final state "
+                                "(sf_batch_refresh_field), HIP events around the loop on the "
+                                "batch's stream", "ensemble256"),
+           "cpu_baseline": base}
     return out
+
+
+def serving_leg(args, stream):
+    """A short continuous-batching leg at each arrival rate."""
+    import torch
+
+    from paper_1803_04782_amd import scenes, serve
+
+    t0 = time.perf_counter()
+    pool = scenes.ensemble(n_scenes=args.pool, seed=4, steps=2000)
+    say(f"request pool of {len(pool)} scenes generated in {time.perf_counter() - t0:.1f} s")
+    rates = [float(r) for r in args.rates.split(",")]
+    runs = []
+    for lam in rates:
+        arrivals = serve.poisson_arrivals(lam, args.serve_seconds, seed=4)
+        reqs = [serve.Request(i, float(a), (lambda s=pool[i % len(pool)]: s), max_steps=2000)
+                for i, a in enumerate(arrivals)]
+        srv = serve.Server(int(args.budget_gib * (1 << 30)), max_scenes=args.max_scenes,
+                           stream=stream, background_builds=not args.sync_builds)
+        say(f"serving at {lam:g}/s: {len(reqs)} requests over {args.serve_seconds:g} s")
+        out = srv.run(reqs, stop_admitting_at=args.serve_seconds, drain=False,
+                      deadline=args.serve_seconds)
+        torch.cuda.synchronize()
+        out.pop("results")
+        out["rate_per_s"] = lam
+        say(f"   p50/p99 step {out['step_latency_ms_p50']:.2f}/{out['step_latency_ms_p99']:.2f} "
+            f"ms, {out['scenes_per_s']:.2f} scenes/s, {out['ped_steps_per_s']:.3g} ped-steps/s")
+        runs.append(out)
+    return {"rates_per_s": rates, "window_s": args.serve_seconds, "max_steps": 2000,
+            "budget_gib": args.budget_gib, "max_scenes": args.max_scenes,
+            "request_pool": len(pool),
+            "builds": "between ticks" if args.sync_builds else "worker thread", "runs": runs}
 
 
 # The paper's time for the same scenario (Table IV, 7x7 fields; 1000 ticks per
@@ -284,7 +506,7 @@ def bench_flow_sweep(args, stream):
     out = {"metric": METRIC, "value": total_ps / total_t, "unit": "pedestrian-steps/s",
            "n_gpus": 1, "steps": steps, "warmup": 5,
            "ms_per_step": 1000.0 * total_t / (steps * len(rows)), "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": "flow-sweep", "sides": sides, "densities": dens,
                       "directions": dirs, "radius": 3, "periodic": True, "ticks": steps,
                       "combinations": len(rows), "parallelism": "single-gpu"},
@@ -334,7 +556,7 @@ def bench_flow_walk(args, stream):
     out = {"metric": METRIC, "value": total_ps / total_t, "unit": "pedestrian-steps/s",
            "n_gpus": 1, "steps": steps, "warmup": 5,
            "ms_per_step": 1000.0 * total_t / (steps * len(rows)), "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": "flow-walk", "grid": [1000, 1000], "density": 0.5,
                       "directions": 8, "radius": 3, "periodic": True, "ticks": steps,
                       "max_walk_periods": [r["max_walk_period"] for r in rows],
@@ -346,48 +568,29 @@ def bench_flow_walk(args, stream):
 
 
 def bench_serving(args, stream):
-    """Serving loop under Poisson arrivals at several rates."""
-    import torch
-
-    from paper_1803_04782_amd import scenes, serve
-
-    def say(*a):
-        print("[bench]", *a, file=sys.stderr, flush=True)
-
-    # request sizes: a pool of scenes drawn from the uneven-ensemble
-    # distribution (request i uses pool entry i mod pool size)
-    t0 = time.perf_counter()
-    pool = scenes.ensemble(n_scenes=args.pool, seed=4, steps=2000)
-    say(f"request pool of {len(pool)} scenes generated in {time.perf_counter() - t0:.1f} s")
-    rates = [float(r) for r in args.rates.split(",")]
-    runs = []
-    for lam in rates:
-        arrivals = serve.poisson_arrivals(lam, args.serve_seconds, seed=4)
-        reqs = [serve.Request(i, float(a), (lambda s=pool[i % len(pool)]: s), max_steps=2000)
-                for i, a in enumerate(arrivals)]
-        srv = serve.Server(int(args.budget_gib * (1 << 30)), max_scenes=args.max_scenes,
-                           stream=stream, background_builds=not args.sync_builds)
-        say(f"rate {lam:g}/s: {len(reqs)} requests over {args.serve_seconds:g} s")
-        out = srv.run(reqs, stop_admitting_at=args.serve_seconds, drain=False,
-                      deadline=args.serve_seconds)
-        torch.cuda.synchronize()
-        out.pop("results")
-        out["rate_per_s"] = lam
-        say(f"   {json.dumps(out)}")
-        runs.append(out)
-    best = max(runs, key=lambda r: r["ped_steps_per_s"])
+    """Serving loop under Poisson arrivals at several rates (longer windows
+    than the default line's leg)."""
+    leg = serving_leg(args, stream)
+    best = max(leg["runs"], key=lambda r: r["ped_steps_per_s"])
+    cfg = {k: v for k, v in leg.items() if k != "runs"}
+    cfg.update({"workload": "serving", "parallelism": "single-gpu"})
     out = {"metric": METRIC, "value": best["ped_steps_per_s"], "unit": "pedestrian-steps/s",
            "n_gpus": 1, "steps": None, "warmup": 0, "ms_per_step": best["step_latency_ms_p50"],
-           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-           "data": "synthetic",
-           "config": {"workload": "serving", "rates_per_s": rates,
-                      "window_s": args.serve_seconds, "max_steps": 2000,
-                      "budget_gib": args.budget_gib, "max_scenes": args.max_scenes,
-                      "request_pool": len(pool),
-                      "builds": "between ticks" if args.sync_builds else "worker thread",
-                      "parallelism": "single-gpu"},
-           "runs": runs, "roofline": None, "cpu_baseline": None}
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic", "config": cfg, "runs": leg["runs"], "roofline": None,
+           "cpu_baseline": None}
     print(json.dumps(out), flush=True)
+
+
+def line_for_single(sub, args):
+    """A single-scene result as the top-level JSON line of its workload."""
+    out = {"metric": METRIC, "value": sub["value"], "unit": sub["unit"], "n_gpus": 1,
+           "steps": sub["steps"], "warmup": args.warmup, "ms_per_step": sub["ms_per_step"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic"}
+    out.update({k: v for k, v in sub.items() if k not in out})
+    out["config"]["parallelism"] = "single-gpu"
+    return out
 
 
 def main():
@@ -395,21 +598,25 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None,
                     help="timed ticks (default: the workload's own tick count)")
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="hall1024",
-                    choices=["hall1024", "room64", "plaza8192", "flow1000", "flow-sweep",
-                             "flow-walk", "ensemble256", "serving"])
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="default",
+                    choices=["default", "ensemble256", "hall1024", "room64", "plaza8192",
+                             "flow1000", "flow-sweep", "flow-walk", "serving"])
     ap.add_argument("--scenes", type=int, default=256, help="ensemble size (ensemble256)")
     ap.add_argument("--rates", default="50,200,800", help="arrival rates per s (serving)")
-    ap.add_argument("--serve-seconds", type=float, default=30.0,
-                    help="arrival window per rate (serving)")
+    ap.add_argument("--serve-seconds", type=float, default=None,
+                    help="arrival window per rate (serving; default 30 s alone, 4 s in the "
+                         "default line)")
     ap.add_argument("--sync-builds", action="store_true",
                     help="serving: build admitted scenes between ticks, not on a worker thread")
     ap.add_argument("--budget-gib", type=float, default=64.0,
                     help="device memory admitted scenes may hold (serving)")
     ap.add_argument("--max-scenes", type=int, default=256, help="resident slots (serving)")
-    ap.add_argument("--pool", type=int, default=64, help="request pool size (serving)")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--pool", type=int, default=None,
+                    help="request pool size (serving; default 64 alone, 32 in the default line)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle legs")
+    ap.add_argument("--no-subs", action="store_true",
+                    help="default line: skip the hall1024, plaza8192 and serving sub-objects")
     ap.add_argument("--sweep-sides", default="100,200,300,400,500,600,700,800,900,1000",
                     help="flow-sweep: torus sides")
     ap.add_argument("--sweep-densities", default="0.1,0.2,0.3,0.4,0.5,0.6,0.7,0.8,0.9",
@@ -418,9 +625,8 @@ def main():
     ap.add_argument("--field-update", type=int, default=0,
                     help="K >= 2: incremental field update with a full superposition every K "
                          "ticks (sf_set_field_update); 0 = full superposition every tick")
-    ap.add_argument("--no-ensemble", action="store_true",
-                    help="hall1024: skip the attached batched-vs-plain ensemble comparison")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="bound on the timed oracle work of each CPU baseline")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (HBM "
                          "counter calibration under rocprofv3) and exit")
@@ -443,15 +649,16 @@ def main():
 
     import torch
 
-    from paper_1803_04782_amd import scenes, sf
+    from paper_1803_04782_amd import scenes
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
-    if args.workload == "ensemble256":
-        bench_ensemble(args, stream)
-        return
+    if args.no_cpu:
+        args.cpu_seconds = 0.0
     if args.workload == "serving":
+        args.serve_seconds = args.serve_seconds or 30.0
+        args.pool = args.pool or 64
         bench_serving(args, stream)
         return
     if args.workload == "flow-sweep":
@@ -460,122 +667,30 @@ def main():
     if args.workload == "flow-walk":
         bench_flow_walk(args, stream)
         return
+    if args.workload in ("default", "ensemble256"):
+        t_start = time.perf_counter()
+        steps = args.steps if args.steps is not None else 300
+        out = ensemble_line(args, stream, steps)
+        if args.workload == "default" and not args.no_subs:
+            # the metric's single-scene configurations, each with its roofline
+            sub_cpu = min(args.cpu_seconds, 5.0)
+            out["hall1024"] = single_scene(scenes.hall1024(), args, stream, 500, FIELD_LOOP,
+                                           sub_cpu, "superpose")
+            out["plaza8192"] = single_scene(scenes.plaza8192(), args, stream, 200, 50,
+                                            sub_cpu, "superpose")
+            args.serve_seconds = args.serve_seconds or 4.0
+            args.pool = args.pool or 32
+            out["serving"] = serving_leg(args, stream)
+        out["bench_wall_s"] = time.perf_counter() - t_start
+        print(json.dumps(out), flush=True)
+        return
     sc = scenes.WORKLOADS[args.workload]()
-    if args.steps is None:
-        args.steps = sc.steps
-    print(f"[bench] workload {sc.name}: {sc.width}x{sc.height} su, {sc.n_peds} pedestrians, "
-          f"R={sc.radius}", file=sys.stderr, flush=True)
-    free_su = int((sc.obstacle == 0).sum())
-    g = sf.GpuScene(sc, stream=stream)
-    if args.field_update:
-        g.set_field_update(args.field_update)
-    try:
-        # warm-up ticks, then back to the initial state for the timed run
-        g.step(args.warmup)
-        g.set_state(sc.pos, sc.start_step)
-        torch.cuda.synchronize()
-
-        t0 = time.perf_counter()
-        g.step(args.steps)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        s = g.stats()
-        ped_steps = s["ped_steps"]
-
-        # same ticks again with HIP events around every kernel launch
-        g.set_state(sc.pos, sc.start_step)
-        g.set_timing(True)
-        g.step(args.steps)
-        torch.cuda.synchronize()
-        ktimes = {}
-        for name, kid in (("superpose", sf.SF_KERNEL_SUPERPOSE), ("decide", sf.SF_KERNEL_DECIDE),
-                          ("commit", sf.SF_KERNEL_COMMIT)):
-            ms, n = g.kernel_time(kid)
-            ktimes[name] = {"avg_us": 1000.0 * ms / max(n, 1), "launches": n}
-        g.set_timing(False)
-        s2 = g.stats()
-
-        # the field kernel alone, back to back: FIELD_LOOP superpositions of
-        # the final state (sf_refresh_field; the field stays the same bit for
-        # bit), two HIP events around the loop on the scene's stream.  The
-        # per-launch events above cost the host more per launch than a tick
-        # takes on the device, so those launches run with idle gaps before
-        # them and their start-to-stop intervals read high.
-        g.refresh_field(10)
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        g.refresh_field(FIELD_LOOP)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        field_loop_us = 1000.0 * e0.elapsed_time(e1) / FIELD_LOOP
-
-        # final state for the accuracy gate
-        pos_g = g.positions()
-        P_g = g.field()
-        t_g = g.stats()["step"]
-        g.step(1)
-        tgt_g, flags_g = g.last_moves()
-        pos_next = g.positions()
-    finally:
-        g.close()
-
-    value = ped_steps / dt
-    su_updates = args.steps * free_su / dt
-    contrib_per_launch = (s2["ped_steps"] / max(args.steps, 1)) * window_contributions(sc)
-    sup_us = field_loop_us
-    achieved = contrib_per_launch / (sup_us * 1e-6) / 1e12
-    # algorithmic bytes of one superposition launch: S (FP64) read and P
-    # (FP32) written once, the bitmap read once
-    # per su, the occupancy bitmap read once
-    alg_bytes = 12.0 * sc.width * sc.height + 8.0 * ((sc.width + 63) // 64) * sc.height
-    roofline = {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved / ALU_PEAK_TFLOPS,
-                "traffic": traffic_per_launch(), "kernel": "superpose",
-                "flop_per_launch": contrib_per_launch, "avg_launch_us": sup_us,
-                "launch_timing": f"{FIELD_LOOP} back-to-back field launches on the final state, "
-                                 "HIP events around the loop",
-                "tick_launch_interval_us": ktimes["superpose"]["avg_us"],
-                "algorithmic_bytes_per_launch": alg_bytes,
-                "hbm_frac": alg_bytes / (sup_us * 1e-6) / 8.0e12}
-    # measured HBM rate (calibrated counters over the launch duration) and the
-    # launch's floor at peak: max(algorithmic bytes / 8 TB/s, adds / ALU rate)
-    if roofline["traffic"] is not None:
-        roofline["measured_hbm_GBps"] = roofline["traffic"] / (sup_us * 1e-6) / 1e9
-    t_hbm = alg_bytes / 8.0e12
-    t_alu = contrib_per_launch / (ALU_PEAK_TFLOPS * 1e12)
-    roofline["floor_us"] = 1e6 * max(t_hbm, t_alu)
-    roofline["floor_binding"] = "alu" if t_alu >= t_hbm else "hbm"
-
-    out = {"metric": METRIC, "value": value, "unit": "pedestrian-steps/s", "n_gpus": 1,
-           "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1000.0 * dt / args.steps,
-           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-           "field_us_per_tick": ktimes["superpose"]["avg_us"] * ktimes["superpose"]["launches"]
-           / max(args.steps, 1),
-           "data": "synthetic", "config": {"workload": sc.name, "grid": [sc.width, sc.height],
-                                           "field_update": args.field_update,
-                                           "pedestrians": sc.n_peds, "radius": sc.radius,
-                                           "ticks": args.steps, "parallelism": "single-gpu"},
-           "su_field_updates_per_s": su_updates, "kernels": ktimes, "roofline": roofline,
-           "stats": s}
+    steps = args.steps if args.steps is not None else sc.steps
+    sub = single_scene(sc, args, stream, steps, FIELD_LOOP, args.cpu_seconds, "superpose")
+    out = line_for_single(sub, args)
     if args.workload == "flow1000":
         out["config"].update({"periodic": True, "density": 0.5, "directions": 8})
         out["paper_context"] = PAPER_FLOW1000
-    if not args.no_cpu:
-        base, gate = cpu_baseline(sc, (pos_g, P_g, t_g, tgt_g, flags_g, pos_next),
-                                  args.cpu_seconds)
-        out["cpu_baseline"] = base
-        out["accuracy_gate"] = gate
-    else:
-        out["cpu_baseline"] = None
-    if args.workload == "hall1024" and not args.no_ensemble:
-        # the metric's batched-vs-plain half: the 256-scene ensemble, 300 ticks
-        e = bench_ensemble(args, stream, steps=300, emit=False)
-        out["ensemble256"] = {k: e[k] for k in ("value", "unit", "ms_per_step", "steps",
-                                                "su_field_updates_per_s", "plain",
-                                                "batched_vs_plain", "tiling",
-                                                "identical_to_plain", "accuracy_gate")}
-        out["ensemble256"]["config"] = e["config"]
     print(json.dumps(out), flush=True)
 
 

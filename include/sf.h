@@ -310,6 +310,14 @@ int sf_batch_get_tiling(const sf_batch *b, sf_batch_tiling *out);
  * captured on first use; a single tick is launched directly. */
 int sf_batch_step(sf_batch *b, int32_t n_steps);
 
+/* Superpose the field of every member scene again, n_times times (no tick;
+ * positions, counters and step index unchanged; the fields keep their bits):
+ * the field launch of each group in turn, back to back on the batch's stream
+ * (k-5's write-back of Algorithm 1 for all members).  For timing the batched
+ * field.  Does not block.  SF_EINVAL for a negative count or a batch whose
+ * member was destroyed. */
+int sf_batch_refresh_field(sf_batch *b, int32_t n_times);
+
 /* Running totals of every member scene (out[n_scenes], in the order given to
  * sf_batch_create), read with one launch and one copy.  Blocks until the
  * batch's queued work is done. */

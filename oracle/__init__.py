@@ -71,8 +71,10 @@ def _load():
     lib.orc_claim_key.restype = u64
     lib.orc_claim_key.argtypes = [i32, i64, u64]
     lib.orc_step.restype = i64
-    lib.orc_step.argtypes = [i32, i32, P, P, P, i32, f64, f64, i32, P, f64, P, u64, i64, i32, P,
-                             P, P, P]
+    lib.orc_step.argtypes = [i32, i32, P, P, P, i32, f64, f64, i32, P, f64, P, i32, i32, u64, i64,
+                             i32, P, P, P, P]
+    lib.orc_body_map.restype = i64
+    lib.orc_body_map.argtypes = [i32, i32, i32, P, i32, i32, i32, P]
     lib.orc_field_at.restype = f64
     lib.orc_field_at.argtypes = [i32, i32, P, P, P, f64, i32, f64, f64, i32, f64, f64, i32, i64]
     lib.orc_decide_at.restype = None
@@ -159,6 +161,8 @@ class Statics:
     heading: Optional[np.ndarray] = None  # uint8 [N] by pedestrian id, or None
     w_heading: float = 1.0
     walk_period: Optional[np.ndarray] = None  # uint8 [N] by pedestrian id, or None
+    body_w: int = 1  # body width and height in su (odd; 1 x 1 = one su)
+    body_h: int = 1
 
     def acts(self, i: int, t: int) -> bool:
         """Whether pedestrian i decides on tick t (walk period)."""
@@ -199,7 +203,8 @@ def statics(scene, with_obstacle_field: bool = True, threads: int = 1) -> Static
                    int(scene.seed), unreach, periodic,
                    None if hd is None else _c(hd, np.uint8),
                    float(getattr(scene, "w_heading", 1.0)),
-                   None if wp is None else _c(wp, np.uint8))
+                   None if wp is None else _c(wp, np.uint8),
+                   int(getattr(scene, "body_w", 1)), int(getattr(scene, "body_h", 1)))
 
 
 def total_field(st: Statics, pos, threads: int = 1) -> np.ndarray:
@@ -254,8 +259,8 @@ def step(st: Statics, pos, t: int, P: Optional[np.ndarray] = None,
     wp = None if st.walk_period is None else _ptr(st.walk_period)
     left = _load().orc_step(st.W, st.H, _ptr(st.obstacle), _ptr(st.exit), _ptr(P), st.R,
                             st.k, st.alpha, int(st.periodic), hd, st.w_heading, wp,
-                            st.seed & (2**64 - 1), int(t), n, _ptr(newpos), _ptr(target),
-                            _ptr(moved), _ptr(tied))
+                            st.body_w, st.body_h, st.seed & (2**64 - 1), int(t), n,
+                            _ptr(newpos), _ptr(target), _ptr(moved), _ptr(tied))
     return StepResult(P, target, moved, tied, newpos, int(left))
 
 
@@ -268,6 +273,17 @@ def run(st: Statics, pos, t0: int, n_steps: int):
         out.append(r)
         cur = r.pos
     return out
+
+
+def body_map(st: Statics, pos):
+    """(owner int32 [W*H]: the pedestrian whose body covers each su, else -1;
+    0 or 1 + the first pedestrian whose body leaves a bounded grid or overlaps
+    another)."""
+    p = _c(pos, np.int32)
+    owner = np.empty(st.W * st.H, dtype=np.int32)
+    bad = _load().orc_body_map(st.W, st.H, p.shape[0], _ptr(p), st.body_w, st.body_h,
+                               int(st.periodic), _ptr(owner))
+    return owner, int(bad)
 
 
 # ---- point evaluation (large grids) ------------------------------------------

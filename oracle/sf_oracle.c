@@ -63,6 +63,24 @@
  *                  deciding or registering (it still occupies its su and
  *                  spreads its field).
  *
+ * Pedestrians larger than one su (section 2: odd width and height, so one su
+ * is the centre; the experiments of Table VI):
+ *   body           a bw x bh block of su centred on the pedestrian's su
+ *                  (bw, bh odd, the same for every pedestrian of a scene);
+ *                  bodies lie in the grid (or wrap on a torus), cover no
+ *                  obstacle and no exit, and never overlap;
+ *   field          the pedestrian's field radiates from its centre su;
+ *   candidates     move e is a candidate if the body shifted by e lies in
+ *                  the grid, covers no obstacle and no su of another body at
+ *                  the start of the tick; the value is taken at the shifted
+ *                  centre as for one su;
+ *   registration   a mover registers for every su its shifted body covers
+ *                  and its current body does not (the su it enters);
+ *   election       it wins if its key is the smallest at every su it
+ *                  registered for; losers stay;
+ *   openings       a winner whose shifted body covers an exit su leaves.
+ * With bw = bh = 1 these are exactly the one-su rules above.
+ *
  * Direction list: e0 = (0,0) stay, e1 = (1,0), e2 = (1,1), e3 = (0,1),
  * e4 = (-1,1), e5 = (-1,0), e6 = (-1,-1), e7 = (0,-1), e8 = (1,-1); x is the
  * column (east +), y the row (south +); linear index c = y*W + x.
@@ -350,13 +368,35 @@ static float heading_term32(int h, int d, double w_h)
     }
 }
 
-/* Decision of one live pedestrian at su p, given the step-start field P and
- * occupancy.  Writes the chosen su and whether the two best candidates are a
- * near tie.  phi1 / phi2: the pedestrian's own field at an axial / diagonal
+/* Whether the body of pedestrian `id` (half-widths a, b) shifted to centre
+ * (cx, cy) lies in the grid (bounded) or wraps (periodic), covers no obstacle
+ * and no su of another body: owner[c] is the pedestrian whose body covers c,
+ * or -1. */
+static int body_fits(int W, int H, const uint8_t *obst, const int32_t *owner, int32_t id,
+                     int a, int b, int periodic, int cx, int cy)
+{
+    for (int j = -b; j <= b; ++j)
+        for (int i = -a; i <= a; ++i) {
+            int x = cx + i, y = cy + j;
+            if (periodic) {
+                x = ((x % W) + W) % W;
+                y = ((y % H) + H) % H;
+            } else if (x < 0 || y < 0 || x >= W || y >= H) {
+                return 0;
+            }
+            int64_t c = (int64_t)y * W + x;
+            if (obst[c] || (owner[c] >= 0 && owner[c] != id)) return 0;
+        }
+    return 1;
+}
+
+/* Decision of one live pedestrian `id` at su p, given the step-start field P
+ * and body map.  Writes the chosen su and whether the two best candidates are
+ * a near tie.  phi1 / phi2: the pedestrian's own field at an axial / diagonal
  * neighbour; h, w_h: its heading and the heading weight. */
-static void decide_one(int W, int H, const uint8_t *obst, const uint8_t *occ,
-                       const double *P, double phi_axial, double phi_diag, int periodic,
-                       int h, double w_h, int32_t p, int32_t *target, uint8_t *tied)
+static void decide_one(int W, int H, const uint8_t *obst, const int32_t *owner, int32_t id,
+                       int a, int b, const double *P, double phi_axial, double phi_diag,
+                       int periodic, int h, double w_h, int32_t p, int32_t *target, uint8_t *tied)
 {
     int x = p % W, y = p / W;
     float best32 = 0.0f;
@@ -371,8 +411,8 @@ static void decide_one(int W, int H, const uint8_t *obst, const uint8_t *occ,
         }
         if (d > 0) {
             if (nx < 0 || ny < 0 || nx >= W || ny >= H) continue;
-            int64_t nc = (int64_t)ny * W + nx;
-            if (obst[nc] || occ[nc]) continue;
+            if (!body_fits(W, H, obst, owner, id, a, b, periodic, x + DIR_X[d], y + DIR_Y[d]))
+                continue;
         }
         int64_t c = (int64_t)ny * W + nx;
         double own = d == 0 ? 0.0 : ((d & 1) ? phi_axial : phi_diag);
@@ -397,6 +437,52 @@ static void decide_one(int W, int H, const uint8_t *obst, const uint8_t *occ,
     *tied = (isfinite(u_lo2) && (u_lo2 - u_lo) <= 1e-5 * scale) ? 1 : 0;
 }
 
+/* Body map: owner[c] = the live pedestrian whose body covers c, else -1.
+ * Returns 0, or 1 + the first pedestrian whose body leaves a bounded grid or
+ * overlaps another body (the map then holds the bodies before it). */
+int64_t orc_body_map(int W, int H, int32_t n_peds, const int32_t *pos, int bw, int bh,
+                     int periodic, int32_t *owner)
+{
+    int a = (bw - 1) / 2, b = (bh - 1) / 2;
+    for (int64_t c = 0; c < (int64_t)W * H; ++c) owner[c] = -1;
+    for (int32_t i = 0; i < n_peds; ++i) {
+        if (pos[i] < 0) continue;
+        int x = pos[i] % W, y = pos[i] / W;
+        for (int j = -b; j <= b; ++j)
+            for (int q = -a; q <= a; ++q) {
+                int sx = x + q, sy = y + j;
+                if (periodic) {
+                    sx = ((sx % W) + W) % W;
+                    sy = ((sy % H) + H) % H;
+                } else if (sx < 0 || sy < 0 || sx >= W || sy >= H) {
+                    return 1 + (int64_t)i;
+                }
+                int64_t c = (int64_t)sy * W + sx;
+                if (owner[c] >= 0) return 1 + (int64_t)i;
+                owner[c] = i;
+            }
+    }
+    return 0;
+}
+
+/* Column and row step (-1, 0 or 1) from su p to its neighbour q, across
+ * the seam of a torus. */
+static int step_dx(int W, int periodic, int32_t p, int32_t q)
+{
+    int d = q % W - p % W;
+    if (periodic && d > 1) d -= W;
+    if (periodic && d < -1) d += W;
+    return d;
+}
+
+static int step_dy(int W, int H, int periodic, int32_t p, int32_t q)
+{
+    int d = q / W - p / W;
+    if (periodic && d > 1) d -= H;
+    if (periodic && d < -1) d += H;
+    return d;
+}
+
 /* Whether pedestrian i acts on tick t (walk period p, NULL or 1: every tick). */
 static int acts(const uint8_t *period, int32_t i, int64_t t)
 {
@@ -404,10 +490,32 @@ static int acts(const uint8_t *period, int32_t i, int64_t t)
     return ((uint64_t)t + (uint64_t)i) % period[i] == 0;
 }
 
+/* Su of the body of half-widths (a, b) centred at (cx, cy) that the body
+ * centred at (ox, oy) does not cover (the centres are at most one su apart,
+ * unwrapped); wrapped on a torus.  Writes up to (2a+1)(2b+1) linear indices
+ * to out and returns their number. */
+static int entered_su(int W, int H, int a, int b, int periodic, int ox, int oy, int cx, int cy,
+                      int64_t *out)
+{
+    int n = 0;
+    for (int j = -b; j <= b; ++j)
+        for (int i = -a; i <= a; ++i) {
+            int x = cx + i, y = cy + j;
+            if (x >= ox - a && x <= ox + a && y >= oy - b && y <= oy + b) continue;
+            if (periodic) {
+                x = ((x % W) + W) % W;
+                y = ((y % H) + H) % H;
+            }
+            out[n++] = (int64_t)y * W + x;
+        }
+    return n;
+}
+
 /* One tick from state (pos, t).
  *   P       [W*H]  the step-start total field (orc_total_field of pos)
  *   heading [N]    headings (NULL: none)
  *   period  [N]    walk periods (NULL: every pedestrian acts every tick)
+ *   bw, bh         body width and height (odd; 1, 1: one su per pedestrian)
  *   pos     [N]    in: step-start positions (-1 = evacuated); out: new ones
  *   target  [N]    out: chosen su (own su when staying; -1 when evacuated)
  *   moved   [N]    out: 1 if the pedestrian won its election and moved
@@ -415,12 +523,13 @@ static int acts(const uint8_t *period, int32_t i, int64_t t)
  * Returns the number of pedestrians that left through an exit this tick. */
 int64_t orc_step(int W, int H, const uint8_t *obst, const uint8_t *exitm, const double *P,
                  int R, double k, double alpha, int periodic, const uint8_t *heading,
-                 double w_h, const uint8_t *period, uint64_t seed, int64_t t, int32_t n_peds,
-                 int32_t *pos, int32_t *target, uint8_t *moved, uint8_t *tied)
+                 double w_h, const uint8_t *period, int bw, int bh, uint64_t seed, int64_t t,
+                 int32_t n_peds, int32_t *pos, int32_t *target, uint8_t *moved, uint8_t *tied)
 {
     int64_t n = (int64_t)W * H;
-    uint8_t *occ = (uint8_t *)malloc((size_t)(n > 0 ? n : 1));
-    orc_occupancy(W, H, n_peds, pos, occ);
+    int a = (bw - 1) / 2, b = (bh - 1) / 2;
+    int32_t *owner = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    orc_body_map(W, H, n_peds, pos, bw, bh, periodic, owner);
     double phi_axial = orc_phi(1, 0, R, k, alpha);
     double phi_diag = orc_phi(1, 1, R, k, alpha);
 
@@ -434,34 +543,58 @@ int64_t orc_step(int W, int H, const uint8_t *obst, const uint8_t *exitm, const 
             target[i] = pos[i]; /* resting this tick */
             continue;
         }
-        decide_one(W, H, obst, occ, P, phi_axial, phi_diag, periodic, heading ? heading[i] : 0,
-                   w_h, pos[i], &target[i], &tied[i]);
+        decide_one(W, H, obst, owner, i, a, b, P, phi_axial, phi_diag, periodic,
+                   heading ? heading[i] : 0, w_h, pos[i], &target[i], &tied[i]);
     }
 
-    /* k-3: per claimed su, the registered pedestrian with the smallest key. */
+    /* k-3: per su a mover enters, the registered pedestrian with the smallest
+     * key; a mover wins if it holds that key at every su it enters (for one
+     * su, its target). */
+    int64_t *su = (int64_t *)malloc(sizeof(int64_t) * (size_t)(bw * bh));
     uint64_t *best = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(n > 0 ? n : 1));
     for (int64_t c = 0; c < n; ++c) best[c] = UINT64_MAX;
     for (int32_t i = 0; i < n_peds; ++i) {
         if (pos[i] < 0 || target[i] == pos[i]) continue;
         uint64_t key = orc_claim_key(i, t, seed);
-        if (key < best[target[i]]) best[target[i]] = key;
+        int ox = pos[i] % W, oy = pos[i] / W;
+        int m = entered_su(W, H, a, b, periodic, ox, oy,
+                           ox + step_dx(W, periodic, pos[i], target[i]),
+                           oy + step_dy(W, H, periodic, pos[i], target[i]), su);
+        for (int q = 0; q < m; ++q)
+            if (key < best[su[q]]) best[su[q]] = key;
     }
 
-    /* k-4: winners move (or leave through an exit); losers stay. */
+    /* k-4: winners move (or leave when the body reaches an exit); losers
+     * stay.  New positions are written after every winner is known. */
     int64_t left = 0;
+    int32_t *newpos = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n_peds > 0 ? n_peds : 1));
     for (int32_t i = 0; i < n_peds; ++i) {
+        newpos[i] = pos[i];
         if (pos[i] < 0 || target[i] == pos[i]) continue;
-        if (best[target[i]] != orc_claim_key(i, t, seed)) continue;
+        uint64_t key = orc_claim_key(i, t, seed);
+        int ox = pos[i] % W, oy = pos[i] / W;
+        int m = entered_su(W, H, a, b, periodic, ox, oy,
+                           ox + step_dx(W, periodic, pos[i], target[i]),
+                           oy + step_dy(W, H, periodic, pos[i], target[i]), su);
+        int won = 1, at_exit = 0;
+        for (int q = 0; q < m; ++q) {
+            if (best[su[q]] != key) won = 0;
+            if (exitm[su[q]]) at_exit = 1;
+        }
+        if (!won) continue;
         moved[i] = 1;
-        if (exitm[target[i]]) {
-            pos[i] = -1;
+        if (at_exit) {
+            newpos[i] = -1;
             ++left;
         } else {
-            pos[i] = target[i];
+            newpos[i] = target[i];
         }
     }
+    memcpy(pos, newpos, sizeof(int32_t) * (size_t)(n_peds > 0 ? n_peds : 0));
+    free(newpos);
     free(best);
-    free(occ);
+    free(su);
+    free(owner);
     return left;
 }
 
@@ -526,11 +659,12 @@ void orc_decide_at(int W, int H, const uint8_t *obst, const uint8_t *occ, const 
     if (P9)
         for (int d = 0; d <= 8; ++d) P9[d] = Ploc[d];
     /* reuse the full-grid rule on a 3x3 window around p */
-    uint8_t o3[9], c3[9];
+    uint8_t o3[9];
+    int32_t c3[9];
     double P3[9];
     for (int j = 0; j < 9; ++j) {
         o3[j] = 1;
-        c3[j] = 0;
+        c3[j] = -1;
         P3[j] = INFINITY;
     }
     for (int d = 0; d <= 8; ++d) {
@@ -540,11 +674,12 @@ void orc_decide_at(int W, int H, const uint8_t *obst, const uint8_t *occ, const 
         int64_t nc = (int64_t)ny * W + nx;
         int j = (DIR_Y[d] + 1) * 3 + (DIR_X[d] + 1);
         o3[j] = obst[nc];
-        c3[j] = d == 0 ? 1 : occ[nc];
+        c3[j] = d == 0 ? 0 : (occ[nc] ? 1 : -1);
         P3[j] = Ploc[d];
     }
     int32_t t3;
-    decide_one(3, 3, o3, c3, P3, orc_phi(1, 0, R, k, alpha), orc_phi(1, 1, R, k, alpha), 0, h,
+    decide_one(3, 3, o3, c3, 0, 0, 0, P3, orc_phi(1, 0, R, k, alpha), orc_phi(1, 1, R, k, alpha),
+               0, h,
                w_h, 4, &t3, tied);
     int tx = wrap_or_drop(x + t3 % 3 - 1, W, periodic);
     int ty = wrap_or_drop(y + t3 / 3 - 1, H, periodic);

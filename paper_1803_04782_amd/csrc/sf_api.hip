@@ -1527,6 +1527,20 @@ int sf_batch_step(sf_batch *b, int32_t n_steps)
     return SF_OK;
 }
 
+int sf_batch_refresh_field(sf_batch *b, int32_t n_times)
+{
+    if (!b) return fail(SF_EINVAL, "batch is NULL");
+    if (n_times < 0) return fail(SF_EINVAL, "n_times %d is negative", n_times);
+    if (b->broken) return fail(SF_EINVAL, "a member scene of the batch was destroyed");
+    DeviceGuard g(b->device);
+    for (int32_t i = 0; i < n_times; ++i)
+        for (int gi = 0; gi < b->cur.n_groups; ++gi) {
+            const int rc = group_field(b->cur.g[gi], b->stream);
+            if (rc) return rc;
+        }
+    return SF_OK;
+}
+
 int sf_batch_stats(const sf_batch *b, sf_stats_t *out)
 {
     if (!b || !out) return fail(SF_EINVAL, "batch or out is NULL");

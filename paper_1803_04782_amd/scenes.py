@@ -60,6 +60,8 @@ class Scene:
     heading: Optional[np.ndarray] = None  # uint8 [N]: direction index 1..8, 0 = none
     w_heading: float = 1.0  # weight of the heading slope
     walk_period: Optional[np.ndarray] = None  # uint8 [N]: acts on ticks t with (t+id) % p == 0
+    body_w: int = 1  # pedestrian body width in su (odd; section 2), centred on pos
+    body_h: int = 1  # pedestrian body height in su (odd)
 
     @property
     def n_peds(self) -> int:
@@ -261,6 +263,74 @@ def flow_scene(width: int, height: int, density: float, directions: int, *, radi
                  exit=np.zeros(n, np.uint8), pos=pos, radius=radius, seed=seed_sc, steps=steps,
                  name=f"flow{width}x{height}d{density:g}k{directions}", periodic=True,
                  heading=heading, w_heading=w_heading, walk_period=walk)
+
+
+def lattice_bodies(width: int, height: int, bw: int, bh: int, n: int, rng,
+                   allowed=None, offset=(0, 0)) -> np.ndarray:
+    """Centres of n non-overlapping bw x bh bodies: a random subset of the
+    cells of the lattice of bw x bh blocks anchored at `offset` (whole blocks
+    inside the grid only), keeping blocks whose su are all `allowed` (a bool
+    [H*W] mask, None = all).  Sorted linear centre indices."""
+    a, b = (bw - 1) // 2, (bh - 1) // 2
+    xs = np.arange(offset[0] + a, width - a, bw)
+    ys = np.arange(offset[1] + b, height - b, bh)
+    cx, cy = np.meshgrid(xs, ys)
+    cx, cy = cx.ravel(), cy.ravel()
+    if allowed is not None:
+        ok = np.ones(cx.size, bool)
+        al = np.asarray(allowed, bool).reshape(height, width)
+        for j in range(-b, b + 1):
+            for i in range(-a, a + 1):
+                ok &= al[cy + j, cx + i]
+        cx, cy = cx[ok], cy[ok]
+    if n > cx.size:
+        raise ValueError(f"{n} bodies of {bw}x{bh} do not fit ({cx.size} lattice cells)")
+    pick = rng.choice(cx.size, size=n, replace=False)
+    return np.sort(cy[pick] * width + cx[pick]).astype(np.int32)
+
+
+def body_flow_scene(width: int, height: int, cover: float, directions: int, body: int, *,
+                    radius: int = 3, seed: int = 0, steps: int = 1000, w_heading: float = 1.0,
+                    max_walk_period: int = 1) -> Scene:
+    """The paper's footprint experiment (Table VI): a width x height torus
+    whose pedestrians have body x body su bodies covering `cover` of the su
+    (round(cover * su / body^2) pedestrians, on a random subset of the blocks
+    of a body x body lattice), headed flows as in flow_scene, fields of
+    half-width `radius`, walk periods uniform in 1..max_walk_period."""
+    if directions not in FLOW_HEADINGS:
+        raise ValueError(f"directions must be one of {sorted(FLOW_HEADINGS)}")
+    rng = np.random.Generator(np.random.PCG64([seed, width, height, directions, body]))
+    n = width * height
+    N = int(round(cover * n / (body * body)))
+    pos = lattice_bodies(width, height, body, body, N, rng)
+    hs = np.array(FLOW_HEADINGS[directions], dtype=np.uint8)
+    heading = rng.permutation(np.resize(hs, N)).astype(np.uint8)
+    seed_sc = int(rng.integers(0, 2**63 - 1))
+    walk = None
+    if max_walk_period > 1:
+        walk = np.random.Generator(np.random.PCG64([seed, 7, max_walk_period])).integers(
+            1, max_walk_period + 1, size=N).astype(np.uint8)
+    return Scene(width=width, height=height, obstacle=np.zeros(n, np.uint8),
+                 exit=np.zeros(n, np.uint8), pos=pos, radius=radius, seed=seed_sc, steps=steps,
+                 name=f"bodyflow{width}x{height}b{body}k{directions}", periodic=True,
+                 heading=heading, w_heading=w_heading, walk_period=walk, body_w=body,
+                 body_h=body)
+
+
+def body_room(width: int, height: int, bw: int, bh: int, n_peds: int, radius: int, seed: int, *,
+              exits=("E",), exit_width: int = 9, bernoulli: float = 0.0, **params) -> Scene:
+    """A walled room (build_scene recipe, no pedestrians) with n_peds bodies
+    of bw x bh su on a random subset of lattice blocks that cover only free
+    interior su that are not exits."""
+    sc = build_scene(width, height, exits=exits, exit_width=exit_width, n_peds=0,
+                     radius=radius, seed=seed, bernoulli=bernoulli,
+                     name=f"bodyroom{width}x{height}b{bw}x{bh}s{seed}", **params)
+    rng = np.random.Generator(np.random.PCG64([seed, 91, bw, bh]))
+    allowed = (sc.obstacle == 0) & (sc.exit == 0)
+    sc.pos = lattice_bodies(width, height, bw, bh, n_peds, rng, allowed=allowed,
+                            offset=(int(rng.integers(0, bw)), int(rng.integers(0, bh))))
+    sc.body_w, sc.body_h = bw, bh
+    return sc
 
 
 def random_scene(width: int, height: int, n_peds: int, radius: int, seed: int, *,

@@ -35,7 +35,8 @@ SF_KERNEL_COMMIT = 2
 EXPORTS = ("sf_create_scene", "sf_step", "sf_field", "sf_positions", "sf_last_moves",
            "sf_static_field", "sf_set_state", "sf_stats", "sf_sync", "sf_set_timing",
            "sf_kernel_time", "sf_refresh_field", "sf_set_field_update", "sf_destroy_scene", "sf_batch_create", "sf_batch_tune",
-           "sf_batch_get_tiling", "sf_batch_step", "sf_batch_stats", "sf_batch_sync",
+           "sf_batch_get_tiling", "sf_batch_step", "sf_batch_refresh_field", "sf_batch_stats",
+           "sf_batch_sync",
            "sf_batch_destroy", "sf_device_count",
            "sf_last_error")
 _VOID = ("sf_destroy_scene", "sf_batch_destroy", "sf_last_error")
@@ -159,6 +160,7 @@ def load():
     lib.sf_batch_tune.argtypes = [P, i32, ctypes.POINTER(Tiling)]
     lib.sf_batch_get_tiling.argtypes = [P, ctypes.POINTER(Tiling)]
     lib.sf_batch_step.argtypes = [P, i32]
+    lib.sf_batch_refresh_field.argtypes = [P, i32]
     lib.sf_batch_stats.argtypes = [P, ctypes.POINTER(Stats)]
     lib.sf_batch_sync.argtypes = [P]
     lib.sf_batch_destroy.argtypes = [P]
@@ -371,6 +373,10 @@ class Batch:
 
     def step(self, n: int = 1):
         _check(load().sf_batch_step(self._h, int(n)))
+
+    def refresh_field(self, n: int = 1):
+        """n field passes over every member (no tick; the fields keep their bits)."""
+        _check(load().sf_batch_refresh_field(self._h, int(n)))
 
     def sync(self):
         _check(load().sf_batch_sync(self._h))
