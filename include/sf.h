@@ -70,6 +70,9 @@ extern "C" {
 /* Largest field half-width R (pedestrian and obstacle fields) accepted. */
 #define SF_MAX_RADIUS 48
 
+/* Largest pedestrian body side in su (odd). */
+#define SF_MAX_BODY 15
+
 /* Largest number of pedestrians of one scene (per-pedestrian launches index
  * whole workgroups of 256 with 32-bit ids). */
 #define SF_MAX_PEDS (2147483647 - 1023)
@@ -109,6 +112,18 @@ typedef struct {
                                  only on ticks t with (t + i) mod p_i = 0 and rests
                                  (stays, registers for nothing) on the others.
                                  NULL = every pedestrian acts every tick; copied */
+    /* Pedestrians larger than one su (section 2; Table VI): */
+    int32_t body_w, body_h;   /* body width and height in su, odd, 1..SF_MAX_BODY
+                                 (0 reads as 1): pedestrian i covers the block
+                                 centred on pos[i]; bodies lie in the grid (or
+                                 wrap on a torus), cover no obstacle or exit and
+                                 never overlap.  A move needs the whole shifted
+                                 body free; a mover registers for the su its
+                                 body enters and wins if its key is the
+                                 smallest at all of them; a winner whose body
+                                 reaches an exit leaves; the field radiates
+                                 from the centre.  Scenes with bodies larger
+                                 than 1 x 1 cannot join a batch.             */
 } sf_scene_desc;
 
 /* Running totals of a scene. */

@@ -65,6 +65,7 @@ struct sf_scene {
     double w_heading = 1;
     std::vector<uint8_t> h_heading;  // by caller id; empty: no headings
     std::vector<uint8_t> h_walk;     // walk periods by caller id; empty: none
+    int bw = 1, bh = 1;              // body width and height (odd)
     int device = 0;
     hipStream_t stream = nullptr;
     int ncu = 0;
@@ -103,6 +104,8 @@ struct sf_scene {
     int refresh = 0, since_full = 0;
     unsigned long long *moved_from = nullptr, *moved_to = nullptr;
     double *phi = nullptr;  // exact pedestrian field (FP64) kept for the updates
+    // bodies larger than one su: covered su and (bounded grids) obstacles
+    unsigned long long *bodies = nullptr, *obits = nullptr;
     SceneView view_upd = {};
     FieldLaunch fl;
     // batch membership: while a batch holds the scene, `stream` is the
@@ -266,6 +269,11 @@ int validate(const sf_scene_desc *d)
         for (int i = 0; i < d->n_peds; ++i)
             if (d->walk_period[i] == 0)
                 return fail(SF_EINVAL, "pedestrian %d has walk period 0", i);
+    const int bw = d->body_w ? d->body_w : 1, bh = d->body_h ? d->body_h : 1;
+    if (bw < 1 || bh < 1 || bw > SF_MAX_BODY || bh > SF_MAX_BODY || !(bw & 1) || !(bh & 1))
+        return fail(SF_EINVAL, "body %d x %d: sides must be odd, 1..%d", bw, bh, SF_MAX_BODY);
+    if (bw > d->width || bh > d->height)
+        return fail(SF_EINVAL, "body %d x %d is larger than the grid", bw, bh);
     const int64_t n = (int64_t)d->width * d->height;
     if (d->periodic) {
         // a torus: the halo words of the field kernel wrap at most once
@@ -292,10 +300,12 @@ int validate(const sf_scene_desc *d)
     return SF_OK;
 }
 
-// Pedestrian positions must be in range, on free non-exit su and distinct
-// (evacuated = -1 allowed when `allow_gone`).
+// Pedestrian positions must be in range and their bodies (half-widths a, b;
+// 0, 0 = one su) inside the grid (or wrapped on a torus), on free non-exit su
+// and disjoint (evacuated = -1 allowed when `allow_gone`).
 int validate_positions(int W, int H, const uint8_t *obst, const uint8_t *exitm, int N,
-                       const int32_t *pos, bool allow_gone)
+                       const int32_t *pos, bool allow_gone, int a = 0, int b = 0,
+                       bool periodic = false)
 {
     const int64_t n = (int64_t)W * H;
     std::vector<uint64_t> seen((size_t)(n + 63) / 64, 0);
@@ -303,12 +313,28 @@ int validate_positions(int W, int H, const uint8_t *obst, const uint8_t *exitm, 
         const int32_t p = pos[i];
         if (p == -1 && allow_gone) continue;
         if (p < 0 || p >= n) return fail(SF_EINVAL, "pedestrian %d at su %d is outside the grid", i, p);
-        if (obst[p]) return fail(SF_EINVAL, "pedestrian %d stands on obstacle su %d", i, p);
-        if (exitm[p]) return fail(SF_EINVAL, "pedestrian %d stands on exit su %d", i, p);
-        uint64_t &w = seen[(size_t)p >> 6];
-        const uint64_t bit = 1ull << (p & 63);
-        if (w & bit) return fail(SF_EINVAL, "pedestrian %d shares su %d with another", i, p);
-        w |= bit;
+        const int x = p % W, y = p / W;
+        for (int j = -b; j <= b; ++j)
+            for (int k = -a; k <= a; ++k) {
+                int sx = x + k, sy = y + j;
+                if (periodic) {
+                    sx = (sx % W + W) % W;
+                    sy = (sy % H + H) % H;
+                } else if (sx < 0 || sy < 0 || sx >= W || sy >= H) {
+                    return fail(SF_EINVAL, "the body of pedestrian %d at su %d leaves the grid",
+                                i, p);
+                }
+                const int64_t c = (int64_t)sy * W + sx;
+                if (obst[c]) return fail(SF_EINVAL, "pedestrian %d covers obstacle su %lld", i,
+                                         (long long)c);
+                if (exitm[c]) return fail(SF_EINVAL, "pedestrian %d covers exit su %lld", i,
+                                          (long long)c);
+                uint64_t &w = seen[(size_t)c >> 6];
+                const uint64_t bit = 1ull << (c & 63);
+                if (w & bit) return fail(SF_EINVAL, "pedestrian %d shares su %lld with another",
+                                         i, (long long)c);
+                w |= bit;
+            }
     }
     return SF_OK;
 }
@@ -353,6 +379,10 @@ int rebuild_dynamic(sf_scene *s)
     SF_HIP(sf::launch_fill_u64(s->occ, nwords, 0ull, s->stream), "clear occupancy");
     SF_HIP(sf::launch_occ_init(s->pos, s->N, s->occ, s->wpr, s->W, s->ctr, s->stream),
            "occupancy");
+    if (s->bodies) {
+        SF_HIP(sf::launch_fill_u64(s->bodies, nwords, 0ull, s->stream), "clear bodies");
+        SF_HIP(sf::launch_body_init(s->view, s->stream), "bodies");
+    }
     SF_HIP(scene_field(s, s->view, s->stream), "superpose");
     return SF_OK;
 }
@@ -417,6 +447,10 @@ int build_statics(sf_scene *s, const uint8_t *h_obst, const uint8_t *h_exit)
     SF_HIP(hipMemcpyAsync(obst, h_obst, (size_t)n, hipMemcpyHostToDevice, st), "copy obstacles");
     SF_HIP(hipMemcpyAsync(s->exitm, h_exit, (size_t)n, hipMemcpyHostToDevice, st), "copy exits");
     SF_HIP(sf::launch_mask_to_bits(obst, obits, W, H, s->wpr, st), "obstacle bitmap");
+    if (s->obits)  // kept for the move tests of bodies larger than one su
+        SF_HIP(hipMemcpyAsync(s->obits, obits, nbw * sizeof(unsigned long long),
+                              hipMemcpyDeviceToDevice, st),
+               "keep obstacle bitmap");
 
     // destination field: BFS over free su from the exit set, a batch of
     // launches between looks at whether a frontier is left
@@ -555,8 +589,9 @@ int create(const sf_scene_desc *d, void *hip_stream, sf_scene **out)
 {
     int rc = validate(d);
     if (rc) return rc;
+    const int bw = d->body_w ? d->body_w : 1, bh = d->body_h ? d->body_h : 1;
     if ((rc = validate_positions(d->width, d->height, d->obstacle, d->exit, d->n_peds, d->pos,
-                                 false)))
+                                 false, (bw - 1) / 2, (bh - 1) / 2, d->periodic != 0)))
         return rc;
     sf_scene *s = new (std::nothrow) sf_scene;
     if (!s) return fail(SF_ENOMEM, "host allocation failed");
@@ -582,6 +617,8 @@ int create(const sf_scene_desc *d, void *hip_stream, sf_scene **out)
     s->start_step = d->start_step;
     s->periodic = d->periodic != 0;
     s->w_heading = d->w_heading;
+    s->bw = bw;
+    s->bh = bh;
     if (d->heading && s->N) s->h_heading.assign(d->heading, d->heading + s->N);
     if (d->walk_period && s->N) s->h_walk.assign(d->walk_period, d->walk_period + s->N);
     s->stream = static_cast<hipStream_t>(hip_stream);
@@ -644,6 +681,11 @@ int create(const sf_scene_desc *d, void *hip_stream, sf_scene **out)
         (rc = dalloc(s, &s->flags, (N + 3) & ~(size_t)3, "flags")) ||
         (rc = dalloc(s, &s->ctr, sf::kCtrWords, "counters")))
         return rc;
+    if (s->bw * s->bh > 1) {
+        if ((rc = dalloc(s, &s->bodies, (size_t)s->wpr * s->H, "body bitmap"))) return rc;
+        if (!s->periodic && (rc = dalloc(s, &s->obits, (size_t)s->wpr * s->H, "obstacle bitmap")))
+            return rc;
+    }
     if (!s->h_heading.empty() && (rc = dalloc(s, &s->heading, N, "headings"))) return rc;
     if (!s->h_walk.empty() && (rc = dalloc(s, &s->walk, N, "walk periods"))) return rc;
 
@@ -708,6 +750,10 @@ int setup_launches(sf_scene *s)
     v.walk = s->walk;
     v.hw_axis = (float)s->w_heading;
     v.hw_diag = (float)(s->w_heading / std::sqrt(2.0));
+    v.ba = (s->bw - 1) / 2;
+    v.bb = (s->bh - 1) / 2;
+    v.bodies = s->bodies;
+    v.obits = s->obits;
     sf::set_view_layout(v, s->lc, s->tab);
     s->fl = sf::field_launch_for(s->lc);
     // one strip per item: workgroup b takes strips b, b + grid, ...
@@ -731,9 +777,15 @@ int enqueue_tick(sf_scene *s)
     sf::LaunchEvents ev;
     int rc;
     if ((rc = timing_events(s, SF_KERNEL_DECIDE, &ev))) return rc;
-    SF_HIP(sf::launch_decide_one(s->view, st, &ev), "decide");
+    if (s->bodies)
+        SF_HIP(sf::launch_decide_body(s->view, st, &ev), "decide");
+    else
+        SF_HIP(sf::launch_decide_one(s->view, st, &ev), "decide");
     if ((rc = timing_events(s, SF_KERNEL_COMMIT, &ev))) return rc;
-    SF_HIP(sf::launch_commit_one(s->view, st, &ev), "commit");
+    if (s->bodies)
+        SF_HIP(sf::launch_commit_body(s->view, st, &ev), "commit");
+    else
+        SF_HIP(sf::launch_commit_one(s->view, st, &ev), "commit");
     if ((rc = timing_events(s, SF_KERNEL_SUPERPOSE, &ev))) return rc;
     if (s->refresh > 1 && s->since_full + 1 < s->refresh) {
         // P = (P + stamps at the su entered) - stamps at the su left this tick
@@ -1133,6 +1185,8 @@ int batch_create(sf_scene *const *scenes, int32_t n, const sf_batch_tiling *tili
         if (s->batch) return fail(SF_EINVAL, "scene %d already belongs to a batch", i);
         if (s->refresh)
             return fail(SF_EINVAL, "scene %d uses the incremental field update", i);
+        if (s->bodies)
+            return fail(SF_EINVAL, "scene %d has bodies larger than one su", i);
         if (s->device != dev) return fail(SF_EINVAL, "scene %d is on device %d, not %d", i, s->device, dev);
         for (int32_t j = 0; j < i; ++j)
             if (scenes[j] == s) return fail(SF_EINVAL, "scene %d is listed twice", i);
@@ -1376,7 +1430,8 @@ int sf_set_state(sf_scene *s, const int32_t *pos, int64_t step)
                "copy exits");
         SF_HIP(hipStreamSynchronize(s->stream), "set_state sync");
         for (size_t c = 0; c < n; ++c) obst[c] = std::isinf(S[c]) ? 1 : 0;
-        int rc = validate_positions(s->W, s->H, obst.data(), exitm.data(), s->N, pos, true);
+        int rc = validate_positions(s->W, s->H, obst.data(), exitm.data(), s->N, pos, true,
+                                    (s->bw - 1) / 2, (s->bh - 1) / 2, s->periodic);
         if (rc) return rc;
         int64_t gone = 0;
         for (int i = 0; i < s->N; ++i) gone += pos[i] < 0;

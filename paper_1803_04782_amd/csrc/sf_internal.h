@@ -131,6 +131,12 @@ struct SceneView {
     // bitmaps of the su the tick's winners left and entered, set by commit,
     // read by the field update, cleared by the next tick's decide
     unsigned long long *moved_from, *moved_to;
+    // pedestrian bodies larger than one su: half-widths (0, 0 = one su), the
+    // bitmap of the su the bodies cover and the obstacle bitmap (NULL on a
+    // torus); occ keeps the centres, the field's sources
+    int32_t ba, bb;
+    unsigned long long *bodies;
+    const unsigned long long *obits;
 };
 
 // Field layout fields of `v` for shape `c` (built for the scene's radius).
@@ -178,6 +184,13 @@ hipError_t launch_decide_one(const SceneView &view, hipStream_t st,
                              const LaunchEvents *ev = nullptr);
 hipError_t launch_commit_one(const SceneView &view, hipStream_t st,
                              const LaunchEvents *ev = nullptr);
+// Bodies larger than one su (view.ba, view.bb > 0; single scenes): body bitmap
+// from the positions, and the tick's decide + claim and commit.
+hipError_t launch_body_init(const SceneView &view, hipStream_t st);
+hipError_t launch_decide_body(const SceneView &view, hipStream_t st,
+                              const LaunchEvents *ev = nullptr);
+hipError_t launch_commit_body(const SceneView &view, hipStream_t st,
+                              const LaunchEvents *ev = nullptr);
 
 // Launchers: all enqueue on `st` and return the launch status.
 hipError_t launch_fill_u64(unsigned long long *p, size_t n, unsigned long long v, hipStream_t st);

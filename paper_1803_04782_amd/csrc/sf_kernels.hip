@@ -1417,6 +1417,319 @@ __global__ __launch_bounds__(commit_threads<MULTI>()) void k_commit(SceneView on
                       {kPedSteps, kMoved, kEvacuated, kLive});
 }
 
+// ---- pedestrians larger than one su (section 2; Table VI) -----------------------------
+//
+// A pedestrian covers the (2a+1) x (2b+1) block of su centred on its su.  The
+// bitmap `bodies` holds every covered su; `occ` keeps the centres, the field's
+// sources.  A move e is a candidate when the su the shifted body enters are in
+// the grid (or wrap), off obstacles and off other bodies; a mover registers
+// (claim word, registration count) at each of them and wins if its key is the
+// smallest at all of them; the smallest key's holder at an su clears that su's
+// claim word after it has read all of its own, so a later reader finds either
+// that key or the cleared word, never its own.  A winner whose shifted body
+// covers an exit su leaves.
+
+constexpr int kBodyMaxHalf = 7;  // bodies up to 15 x 15 su
+
+// One step of the body of half-widths (a, b) at (x, y) by (ex, ey): the su it
+// enters (shifted body minus current body), or with `trailing` the su it
+// leaves (current body minus shifted body), as unwrapped coordinates handed to
+// f(sx, sy).  A column of 2b+1 su when ex != 0, a row of 2a+1 su when ey != 0,
+// their shared corner once.
+template <typename F>
+__device__ __forceinline__ void body_edge(int x, int y, int a, int b, int ex, int ey,
+                                          bool trailing, F f)
+{
+    // entered: column x + ex(a+1) over rows y + ey + j; row y + ey(b+1) over
+    // columns x + ex + i.  Leaving: column x - ex a over rows y + j; row
+    // y - ey b over columns x + i.
+    const int cx = trailing ? x - ex * a : x + ex * (a + 1);
+    const int ry = trailing ? y - ey * b : y + ey * (b + 1);
+    const int oy = trailing ? 0 : ey, ox = trailing ? 0 : ex;
+    if (ex != 0)
+        for (int j = -b; j <= b; ++j) f(cx, y + oy + j);
+    if (ey != 0)
+        for (int i = -a; i <= a; ++i) {
+            const int sx = x + ox + i;
+            if (ex != 0 && sx == cx) continue;  // the corner, already listed
+            f(sx, ry);
+        }
+}
+
+// Bits of columns x0 .. x0 + n - 1 (n <= 32, unwrapped) of bitmap row `row`:
+// on a torus taken modulo W (W >= 64), on a bounded grid with the columns
+// outside [0, W) read as set (blocked).
+__device__ __forceinline__ unsigned int row_window(gptr<const unsigned long long> row, int x0,
+                                                   int n, int W, int wpr, bool periodic)
+{
+    const unsigned long long nmask = (1ull << n) - 1ull;
+    if (periodic) {
+        const int w0 = x0 >= 0 ? x0 >> 6 : -((63 - x0) >> 6);
+        const int off = x0 - 64 * w0;
+        unsigned long long v = wrapped_word(row, w0, W, wpr) >> off;
+        if (off + n > 64) v |= wrapped_word(row, w0 + 1, W, wpr) << (64 - off);
+        return (unsigned int)(v & nmask);
+    }
+    const int lo = max(x0, 0), hi = min(x0 + n - 1, W - 1);
+    unsigned long long out = nmask;
+    if (lo <= hi) {
+        const int w = lo >> 6, bo = lo & 63, m = hi - lo + 1;
+        unsigned long long v = row[w] >> bo;
+        if (bo != 0 && w + 1 < wpr) v |= row[w + 1] << (64 - bo);
+        v &= m == 64 ? ~0ull : ((1ull << m) - 1ull);
+        const unsigned long long in = (m == 64 ? ~0ull : ((1ull << m) - 1ull)) << (lo - x0);
+        out = (out & ~in) | (v << (lo - x0));
+    }
+    return (unsigned int)out;
+}
+
+__device__ __forceinline__ int wrap_or_keep(int v, int n, bool periodic)
+{
+    if (!periodic) return v;
+    v %= n;
+    return v < 0 ? v + n : v;
+}
+
+// Body bitmap from the positions: every live pedestrian sets its block.
+__global__ void k_body_init(SceneView v)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (size_t)v.N) return;
+    const int p = v.pos[i];
+    if (p < 0) return;
+    const int W = v.W, H = v.H, x = p % W, y = p / W;
+    const bool per = v.periodic != 0;
+    for (int j = -v.bb; j <= v.bb; ++j)
+        for (int q = -v.ba; q <= v.ba; ++q) {
+            const int sx = wrap_or_keep(x + q, W, per), sy = wrap_or_keep(y + j, H, per);
+            __hip_atomic_fetch_or(&v.bodies[(size_t)sy * v.wpr + (sx >> 6)], 1ull << (sx & 63),
+                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+}
+
+// Decide + claim for bodies: one thread per pedestrian.  The (2a+3) x (2b+3)
+// window around the body (covered and obstacle su, blocked outside a bounded
+// grid) is read row by row; a move is a candidate when the su it enters are
+// all clear.  Values, tie-break, near-tie flag and keys as for one su.
+__global__ __launch_bounds__(kDecideThreads) void k_decide_body(SceneView v)
+{
+    const int W = v.W, H = v.H, wpr = v.wpr, N = v.N;
+    const int i = (int)blockIdx.x * kDecideThreads + (int)threadIdx.x;
+    const bool per = v.periodic != 0;
+    const int a = v.ba, b = v.bb, bw = 2 * a + 1, bh = 2 * b + 1;
+    const gptr<const unsigned long long> bodies =
+        to_global((const unsigned long long *)v.bodies);
+    const gptr<const unsigned long long> obits = to_global(v.obits);
+    const gptr<const float> P = to_global((const float *)v.P);
+    const gptr<unsigned long long> claim = to_global(v.claim), key = to_global(v.key),
+                                   ctr = to_global(v.ctr);
+    const gptr<unsigned int> regs = to_global(v.regs);
+    if (v.moved_from) {
+        const int nb = decide_block_count(N);
+        const size_t nwd = (size_t)wpr * H;
+        for (size_t k = (size_t)blockIdx.x * kDecideThreads + threadIdx.x; k < nwd;
+             k += (size_t)nb * kDecideThreads) {
+            to_global(v.moved_from)[k] = 0ull;
+            to_global(v.moved_to)[k] = 0ull;
+        }
+    }
+    const unsigned long long t = ctr[0], seed = v.seed;
+    unsigned int movers = 0, ties = 0, regs_seen = 0;
+    const int p = i < N ? to_global((const int32_t *)v.pos)[i] : -1;
+    if (p >= 0) {
+        const uint32_t eid = (uint32_t)to_global((const int32_t *)v.ext)[i];
+        const int h = v.heading ? (int)to_global(v.heading)[i] : 0;
+        const unsigned int wp = v.walk ? (unsigned int)to_global(v.walk)[i] : 1u;
+        if (wp > 1u && (t + eid) % wp != 0ull) {
+            to_global(v.target)[i] = p;
+            to_global(v.flags)[i] = 0;
+        } else {
+            const int y = p / W, x = p - y * W;
+            // window rows r = 0 .. bh + 1 (grid row y - b - 1 + r), bit c of a
+            // row = column x - a - 1 + c
+            unsigned int win[2 * kBodyMaxHalf + 3];
+            for (int r = 0; r < bh + 2; ++r) {
+                const int yy = y - b - 1 + r;
+                if (!per && (yy < 0 || yy >= H)) {
+                    win[r] = (1u << (bw + 2)) - 1u;
+                    continue;
+                }
+                const size_t ro = (size_t)wrap_or_keep(yy, H, per) * wpr;
+                unsigned int m = row_window(bodies + ro, x - a - 1, bw + 2, W, wpr, per);
+                if (v.obits) m |= row_window(obits + ro, x - a - 1, bw + 2, W, wpr, per);
+                win[r] = m;
+            }
+            const float phi_axial = v.phi_axial, phi_diag = v.phi_diag;
+            const float hw_axis = v.hw_axis, hw_diag = v.hw_diag;
+            auto heading_term = [&](int d) -> float {
+                if (h == 0) return 0.0f;
+                int turn = h > d ? h - d : d - h;
+                turn = turn > 4 ? 8 - turn : turn;
+                return turn == 0 ? -hw_axis
+                                 : turn == 1 ? -hw_diag
+                                             : turn == 2 ? 0.0f : turn == 3 ? hw_diag : hw_axis;
+            };
+            float lo = P[p], lo2 = INFINITY;
+            int best = 0;
+            for (int d = 1; d <= 8; ++d) {
+                const int ex = kDirX[d], ey = kDirY[d];
+                bool blocked = false;
+                if (ex != 0) {
+                    const int c = ex > 0 ? bw + 1 : 0;
+                    for (int r = 1 + ey; r <= bh + ey; ++r) blocked |= (win[r] >> c) & 1u;
+                }
+                if (ey != 0) {
+                    const unsigned int row = win[ey > 0 ? bh + 1 : 0];
+                    blocked |= ((row >> (1 + ex)) & ((1u << bw) - 1u)) != 0u;
+                }
+                if (blocked) continue;
+                const int nx = wrap_or_keep(x + ex, W, per), ny = wrap_or_keep(y + ey, H, per);
+                const float pc = P[(size_t)ny * W + nx];
+                if (!(pc < INFINITY)) continue;
+                const float u = (pc - ((d & 1) ? phi_axial : phi_diag)) + heading_term(d);
+                if (u < lo) {
+                    lo2 = lo;
+                    lo = u;
+                    best = d;
+                } else if (u < lo2) {
+                    lo2 = u;
+                }
+            }
+            const float scale = fmaxf(fmaxf(fabsf(lo), fabsf(lo2)), 1.0f);
+            const bool tied = lo2 < INFINITY && (lo2 - lo) <= 1e-5f * scale;
+            int tgt = p;
+            if (best != 0) {
+                const int ex = kDirX[best], ey = kDirY[best];
+                tgt = wrap_or_keep(y + ey, H, per) * W + wrap_or_keep(x + ex, W, per);
+                const uint32_t r = philox_w0(eid, (uint32_t)t, (uint32_t)(t >> 32), 0u,
+                                             (uint32_t)seed, (uint32_t)(seed >> 32));
+                const unsigned long long kk = ((unsigned long long)r << 32) | eid;
+                body_edge(x, y, a, b, ex, ey, false, [&](int sx, int sy) {
+                    const size_t q = (size_t)wrap_or_keep(sy, H, per) * W + wrap_or_keep(sx, W, per);
+                    __hip_atomic_fetch_min(&claim[q], kk, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                    regs_seen = max(regs_seen, 1u + __hip_atomic_fetch_add(
+                                                        &regs[q], 1u, __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_AGENT));
+                });
+                key[i] = kk;
+                ++movers;
+            }
+            to_global(v.target)[i] = tgt;
+            to_global(v.flags)[i] =
+                (uint8_t)((best != 0 ? kFlagMover : 0u) | (tied ? kFlagTied : 0u));
+            ties += tied;
+        }
+    }
+    block_sums_add<2>({(int)movers, (int)ties}, ctr, {kMovers, kTied});
+    block_max_into(regs_seen, ctr, kMaxClaim);
+}
+
+// Commit for bodies: a mover reads the claim words of every su it entered; it
+// won if all hold its key.  It then clears the words it holds (with their
+// registration counts).  A winner clears the su it leaves and sets the su it
+// enters in the body bitmap and moves its centre bit, or, when its shifted
+// body covers an exit su, clears its whole body and leaves.
+__global__ __launch_bounds__(256) void k_commit_body(SceneView v)
+{
+    const int i = (int)blockIdx.x * 256 + (int)threadIdx.x;
+    const int W = v.W, H = v.H, wpr = v.wpr;
+    const bool per = v.periodic != 0;
+    const int a = v.ba, b = v.bb;
+    const gptr<int32_t> pos = to_global(v.pos), target = to_global(v.target);
+    const gptr<uint8_t> flags = to_global(v.flags);
+    const gptr<const uint8_t> exitm = to_global(v.exitm);
+    const gptr<unsigned long long> claim = to_global(v.claim), occ = to_global(v.occ),
+                                   bodies = to_global(v.bodies), ctr = to_global(v.ctr);
+    const gptr<unsigned int> regs = to_global(v.regs);
+    bool was_live = false, won = false, left = false;
+    auto su_of = [&](int sx, int sy) {
+        return (size_t)wrap_or_keep(sy, H, per) * W + wrap_or_keep(sx, W, per);
+    };
+    auto bit_and = [&](size_t q, bool set) {
+        const int qy = (int)(q / W), qx = (int)(q - (size_t)qy * W);
+        const size_t wd = (size_t)qy * wpr + (qx >> 6);
+        const unsigned long long m = 1ull << (qx & 63);
+        if (set)
+            __hip_atomic_fetch_or(&bodies[wd], m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        else
+            __hip_atomic_fetch_and(&bodies[wd], ~m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    };
+    if (i < v.N) {
+        const int p = pos[i];
+        const uint8_t f = flags[i];
+        const int tgt = target[i];
+        if (p < 0) {
+            target[i] = -1;
+            flags[i] = 0;
+        } else {
+            was_live = true;
+            if (f & kFlagMover) {
+                const unsigned long long kk = to_global((const unsigned long long *)v.key)[i];
+                const int y = p / W, x = p - y * W, ty = tgt / W, tx = tgt - ty * W;
+                int ex = tx - x, ey = ty - y;
+                if (per) {
+                    ex = ex > 1 ? ex - W : (ex < -1 ? ex + W : ex);
+                    ey = ey > 1 ? ey - H : (ey < -1 ? ey + H : ey);
+                }
+                // read every claim word first, then clear the ones this mover holds
+                bool all_mine = true, at_exit = false;
+                unsigned int held = 0u;
+                int k = 0;
+                body_edge(x, y, a, b, ex, ey, false, [&](int sx, int sy) {
+                    const size_t q = su_of(sx, sy);
+                    const bool mine = claim[q] == kk;
+                    all_mine &= mine;
+                    held |= (mine ? 1u : 0u) << k;
+                    at_exit |= exitm[q] != 0;
+                    ++k;
+                });
+                k = 0;
+                body_edge(x, y, a, b, ex, ey, false, [&](int sx, int sy) {
+                    if ((held >> k) & 1u) {
+                        const size_t q = su_of(sx, sy);
+                        claim[q] = ~0ull;
+                        regs[q] = 0u;
+                    }
+                    ++k;
+                });
+                if (all_mine) {
+                    won = true;
+                    const size_t wp = (size_t)y * wpr + (x >> 6);
+                    __hip_atomic_fetch_and(&occ[wp], ~(1ull << (x & 63)), __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                    if (v.moved_from)
+                        __hip_atomic_fetch_or(&to_global(v.moved_from)[wp], 1ull << (x & 63),
+                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (at_exit) {
+                        left = true;
+                        for (int j = -b; j <= b; ++j)
+                            for (int q = -a; q <= a; ++q) bit_and(su_of(x + q, y + j), false);
+                        pos[i] = -1;
+                    } else {
+                        body_edge(x, y, a, b, ex, ey, true,
+                                  [&](int sx, int sy) { bit_and(su_of(sx, sy), false); });
+                        body_edge(x, y, a, b, ex, ey, false,
+                                  [&](int sx, int sy) { bit_and(su_of(sx, sy), true); });
+                        const size_t wt = (size_t)ty * wpr + (tx >> 6);
+                        __hip_atomic_fetch_or(&occ[wt], 1ull << (tx & 63), __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+                        if (v.moved_to)
+                            __hip_atomic_fetch_or(&to_global(v.moved_to)[wt], 1ull << (tx & 63),
+                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        pos[i] = tgt;
+                    }
+                    flags[i] = f | kFlagWon;
+                }
+            }
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        __hip_atomic_fetch_add(&ctr[0], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    block_sums_add<4>({was_live ? 1 : 0, won ? 1 : 0, left ? 1 : 0, left ? -1 : 0}, ctr,
+                      {kPedSteps, kMoved, kEvacuated, kLive});
+}
+
 // ---- caller-order output ---------------------------------------------------------------
 
 template <typename T>
@@ -1866,6 +2179,25 @@ hipError_t launch_commit(const SceneView *views, const int32_t *block_scene, int
     const SceneView none = {};
     return launch(k_commit<true>, dim3(n_blocks), dim3(commit_threads<true>()), 0, st, ev, none,
                   views, block_scene);
+}
+
+hipError_t launch_body_init(const SceneView &view, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_body_init, dim3(blocks_for((size_t)view.N, 256, kCoverAll)), dim3(256), 0,
+                       st, view);
+    return hipGetLastError();
+}
+
+hipError_t launch_decide_body(const SceneView &view, hipStream_t st, const LaunchEvents *ev)
+{
+    return launch(k_decide_body, dim3(decide_blocks(view.N)), dim3(kDecideThreads), 0, st, ev,
+                  view);
+}
+
+hipError_t launch_commit_body(const SceneView &view, hipStream_t st, const LaunchEvents *ev)
+{
+    return launch(k_commit_body, dim3(blocks_for((size_t)view.N, 256, 1u << 30)), dim3(256), 0,
+                  st, ev, view);
 }
 
 hipError_t launch_commit_one(const SceneView &view, hipStream_t st, const LaunchEvents *ev)

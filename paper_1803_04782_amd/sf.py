@@ -51,7 +51,8 @@ class SceneDesc(ctypes.Structure):
                 ("radius_obs", ctypes.c_int32), ("w_dest", ctypes.c_double),
                 ("seed", ctypes.c_uint64), ("start_step", ctypes.c_int64),
                 ("periodic", ctypes.c_int32), ("heading", ctypes.c_void_p),
-                ("w_heading", ctypes.c_double), ("walk_period", ctypes.c_void_p)]
+                ("w_heading", ctypes.c_double), ("walk_period", ctypes.c_void_p),
+                ("body_w", ctypes.c_int32), ("body_h", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -213,7 +214,8 @@ def make_desc(scene, start_step: Optional[int] = None):
                   periodic=int(bool(getattr(scene, "periodic", False))),
                   heading=_ptr(hd).value if hd is not None and hd.size else None,
                   w_heading=float(getattr(scene, "w_heading", 1.0)),
-                  walk_period=_ptr(wk).value if wk is not None and wk.size else None)
+                  walk_period=_ptr(wk).value if wk is not None and wk.size else None,
+                  body_w=int(getattr(scene, "body_w", 1)), body_h=int(getattr(scene, "body_h", 1)))
     return d, (ob, ex, pos, hd, wk)
 
 
