@@ -18,9 +18,12 @@
  *     exits; static obstacle field O = the same law summed over obstacle su;
  *   - total field P = fl32(S + Phi) with S = w_dest*D + O in FP64 and Phi the
  *     sum of the pedestrians' strengths formed in FP64, +inf on obstacle su.
- *     For the laws used here (nonzero strengths within a factor 2^16 of one
- *     another, windows up to (2*48+1)^2) every such sum is exact, so P is the
- *     FP64 field rounded once to FP32 whatever the order of the terms;
+ *     Every term of a window is a multiple of q = 2^(e - 23), e the exponent
+ *     of its smallest nonzero |strength|; sf_create_scene accepts a law (of
+ *     the pedestrians, and of the obstacles) only if 4 * sum|strength| over
+ *     its window is below 2^53 * q (strengths spread over up to about 2^15),
+ *     so that every such sum is an FP64 number and P is the FP64 field
+ *     rounded once to FP32 whatever the order of the terms;
  *   - a pedestrian at x chooses, among x and its free in-grid non-obstacle
  *     Moore neighbours y, the minimum of u(y) = P(y) - phi(y - x), lowest
  *     direction index on exact ties; direction order stay, (1,0), (1,1),

@@ -238,6 +238,41 @@ int upload_table(double *dst, const std::vector<double> &t, hipStream_t st)
     return SF_OK;
 }
 
+// The superposition adds FP32 strengths in FP64.  Every term of a window is
+// an integer multiple of q = 2^(e_min - 23), e_min the exponent of the
+// smallest nonzero |strength|, and every partial sum of one su's terms (each
+// window offset at most once, or up to twice for the incremental update's
+// previous field plus the entered sources) is bounded by 2*sum|strength|.
+// When 4*sum|strength| < 2^53 * q every such sum is an FP64 number, so the
+// field does not depend on the order of its terms.  Laws outside that range
+// (strengths spread over more than about 2^15 within one window) are refused.
+int check_law(int R, double k, double alpha, const char *what)
+{
+    double sum = 0.0, tmin = 0.0;
+    for (int dy = -R; dy <= R; ++dy)
+        for (int dx = -R; dx <= R; ++dx) {
+            if (dx == 0 && dy == 0) continue;
+            const double dist = std::sqrt((double)dx * dx + (double)dy * dy);
+            const float t = (float)(k * std::pow(dist, alpha));
+            if (!std::isfinite(t))
+                return fail(SF_EINVAL, "%s law k = %g, alpha = %g: strength at (%d, %d) is not "
+                            "a finite FP32 number", what, k, alpha, dx, dy);
+            const double a = std::fabs((double)t);
+            if (a == 0.0) continue;
+            sum += a;
+            tmin = tmin == 0.0 || a < tmin ? a : tmin;
+        }
+    if (sum == 0.0) return SF_OK;
+    int e;
+    (void)std::frexp(tmin, &e);  // tmin = f * 2^e, f in [0.5, 1): exponent e - 1
+    const double q = std::ldexp(1.0, std::max(e - 1 - 23, -149));
+    if (4.0 * sum >= std::ldexp(q, 53))
+        return fail(SF_EINVAL, "%s law k = %g, alpha = %g, radius %d: strengths from %g to a "
+                    "window sum of %g are too far apart for exact FP64 sums", what, k, alpha, R,
+                    tmin, sum);
+    return SF_OK;
+}
+
 int validate(const sf_scene_desc *d)
 {
     if (!d) return fail(SF_EINVAL, "descriptor is NULL");
@@ -259,6 +294,14 @@ int validate(const sf_scene_desc *d)
         if (!std::isfinite(v)) return fail(SF_EINVAL, "field parameters must be finite");
     if (d->start_step < 0) return fail(SF_EINVAL, "start_step %lld is negative",
                                        (long long)d->start_step);
+    {
+        int rc = check_law(d->radius, d->k, d->alpha, "pedestrian");
+        if (rc) return rc;
+        if (!d->periodic &&
+            (rc = check_law(d->radius_obs < 0 ? d->radius : d->radius_obs, d->k_obs,
+                            d->alpha_obs, "obstacle")))
+            return rc;
+    }
     if (d->periodic != 0 && d->periodic != 1)
         return fail(SF_EINVAL, "periodic = %d is neither 0 nor 1", d->periodic);
     if (d->heading)

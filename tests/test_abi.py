@@ -73,6 +73,10 @@ def test_validation_errors(sf):
         "nan k": _mut(k=math.nan),
         "inf w_dest": _mut(w_dest=math.inf),
         "negative start": _mut(start_step=-3),
+        # strengths spread too far for exact FP64 sums (1 down to about 1e-11)
+        "steep law": _mut(alpha=-6.0, radius=48),
+        "steep obstacle law": _mut(alpha_obs=-6.0, radius_obs=40),
+        "strength overflows FP32": _mut(k=1e39),
     }
     p = base.pos.copy()
     p[0] = obst
