@@ -1,6 +1,9 @@
 """GPU test of the serving loop: requests arrive while others run, are admitted
 as memory and slots free up, and share batched ticks; every result must be
-the same as the scene run alone with sf_step for the same number of ticks."""
+the same as the scene run alone with sf_step for the same number of ticks, and
+the same as the FP64 oracle's free run of that scene."""
+import functools
+
 import numpy as np
 import pytest
 
@@ -27,6 +30,21 @@ def _request_scene(i):
     return scenes.build_scene(W, H, exits=walls, exit_width=6, n_peds=0, radius=R,
                               seed=int(rng.integers(0, 2**31 - 1)), bernoulli=0.03,
                               occupancy=occ, name=f"req{i}")
+
+
+@functools.lru_cache(maxsize=None)
+def _oracle_run(rid, steps):
+    """Final positions and evacuations of the oracle's free run of request rid."""
+    import oracle
+
+    sc = _request_scene(rid)
+    st = oracle.statics(sc)
+    pos = sc.pos.copy()
+    left = 0
+    for t in range(sc.start_step, sc.start_step + steps):
+        r = oracle.step(st, pos, t)
+        pos, left = r.pos, left + r.left
+    return pos, left
 
 
 @pytest.mark.parametrize("background", [True, False], ids=["background-builds", "sync-builds"])
@@ -56,3 +74,9 @@ def test_serving_results_match_scenes_alone(sf, background):
         for k in ("step", "live", "evacuated", "ped_steps", "movers", "moved", "tied"):
             assert alone[k] == f.stats[k], (f.rid, k, alone[k], f.stats[k])
         assert f.stats["live"] == 0 or f.steps == 120
+        # the field is the oracle's rounded once and both sides decide on the
+        # same FP32 numbers, so a served run follows the oracle's free run
+        # tick for tick: same positions, same evacuations
+        opos, oleft = _oracle_run(f.rid, f.steps)
+        assert np.array_equal(opos, f.positions), (f.rid, "served run differs from the oracle")
+        assert oleft == f.stats["evacuated"], (f.rid, oleft, f.stats["evacuated"])
