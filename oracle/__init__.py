@@ -80,6 +80,12 @@ def _load():
     lib.orc_decide_at.restype = None
     lib.orc_decide_at.argtypes = [i32, i32, P, P, P, f64, i32, f64, f64, i32, f64, f64, i32, i32,
                                   f64, i32, P, P, P]
+    lib.orc_sect.restype = i32
+    lib.orc_sect.argtypes = [i32, i32]
+    lib.orc_fan_out.restype = i32
+    lib.orc_fan_out.argtypes = [i32, i32]
+    lib.orc_sect_field.restype = i32
+    lib.orc_sect_field.argtypes = [i32, i32, P, P, i32, f64, f64, i32, i32, P, P]
     _lib = lib
     return lib
 
@@ -128,6 +134,52 @@ def source_field(W: int, H: int, src_mask, R: int, k: float, alpha: float,
         _load().orc_source_field(W, H, _ptr(src), int(R), float(k), float(alpha),
                                  int(periodic), _ptr(out))
     return out
+
+
+# ---- the paper's own field path: sects, fan-out, K slots (Algorithm 3) --------
+
+SECT_KS = (2, 4, 8, 16)
+
+
+def sect_of(dx: int, dy: int) -> int:
+    """Sect (0..7) of a nonzero offset: floor(angle / 45 deg), the angle of d
+    from +x toward +y in [0, 360)."""
+    return int(_load().orc_sect(int(dx), int(dy)))
+
+
+def fan_out(wd: int, ht: int) -> int:
+    """Strength fan-out of a wd x ht geometry: most window offsets in one sect."""
+    return int(_load().orc_fan_out(int(wd), int(ht)))
+
+
+def sect_field(W: int, H: int, src_mask, R: int, k: float, alpha: float, K: int,
+               periodic: bool = False, image: bool = False):
+    """Algorithm 3's FP32 field of the sources with K slots: (phi float32
+    [H*W], image float32 [8, H*W] or None)."""
+    src = _c(src_mask, np.uint8)
+    phi = np.empty(W * H, dtype=np.float32)
+    img = np.empty((8, W * H), dtype=np.float32) if image else None
+    n = _load().orc_sect_field(W, H, _ptr(src), None, int(R), float(k), float(alpha),
+                               int(periodic), int(K), _ptr(phi),
+                               None if img is None else _ptr(img))
+    if n < 0:
+        raise ValueError(f"K = {K} is not one of {SECT_KS}")
+    return phi, img
+
+
+def sect_update(W: int, H: int, entered, left, R: int, k: float, alpha: float, K: int,
+                phi, image=None, periodic: bool = False):
+    """The incremental form: phi (float32 [H*W]) and image (float32 [8, H*W]
+    or None) add Algorithm 3's FP32 sums of +strength at the su entered and
+    -strength at the su left.  Returns new arrays."""
+    phi = np.array(phi, dtype=np.float32, copy=True)
+    img = None if image is None else np.array(image, dtype=np.float32, copy=True)
+    n = _load().orc_sect_field(W, H, _ptr(_c(entered, np.uint8)), _ptr(_c(left, np.uint8)),
+                               int(R), float(k), float(alpha), int(periodic), int(K), _ptr(phi),
+                               None if img is None else _ptr(img))
+    if n < 0:
+        raise ValueError(f"K = {K} is not one of {SECT_KS}")
+    return phi, img
 
 
 def host_threads() -> int:

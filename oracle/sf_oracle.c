@@ -685,3 +685,154 @@ void orc_decide_at(int W, int H, const uint8_t *obst, const uint8_t *occ, const 
     int ty = wrap_or_drop(y + t3 / 3 - 1, H, periodic);
     *target = (int32_t)((int64_t)ty * W + tx);
 }
+
+/* ---- the paper's own field path: 8 sects, strength fan-out, K slots -------- */
+/*
+ * Section 3.1, s-1: each su keeps its field strengths in 8 sects (the shared
+ * "3-D image"), and the strength a source puts at su c goes to the sect of
+ * the offset d = c - o from the source's su o to c.  For one sect of one su,
+ * the set of offsets of the window that land there has the same size wherever
+ * the source is: the strength fan-out SF.  Algorithm 2 caches the 8*SF
+ * possible strengths of an su and sums them in one pass; Algorithm 3 (with
+ * Eq. 1) bounds the cache to K slots: the 8*SF terms, padded with zero
+ * strengths to a multiple of K, are split into K blocks of m = 8*SF/K
+ * consecutive terms, each block summed into its slot, then the K slots are
+ * summed.  The caches are floats, so every sum here is an FP32 sum taken in
+ * the stated order.
+ *
+ * Readings (the sect rule is in figures that are not available):
+ *   sect rule      sect(d) = floor(theta / 45 degrees), theta in [0, 360) the
+ *                  angle of d from +x (east) toward +y (south); each sect is
+ *                  half-open on its far edge.  For a (2R+1)^2 window every
+ *                  sect holds R(R+1)/2 offsets, so SF = R(R+1)/2 (the 7x7 field
+ *                  of the paper's example has SF = 6).
+ *   term order     sect by sect (0..7); within a sect, offsets in row-major
+ *                  order (dy ascending, then dx ascending); zero strengths are
+ *                  appended at the end to reach a multiple of K.
+ *   blocks         block j holds terms j*m .. j*m + m - 1 (Eq. 1 read with the
+ *                  block index j*m + i); s[j] is their sequential FP32 sum from
+ *                  +0, and the field is ((s[0] + s[1]) + s[2]) + ... in FP32.
+ *   image          sect s of su c holds the sequential FP32 sum of that sect's
+ *                  terms (for K = 8 the blocks are the sects).
+ *   write-back     P = fl32(S + Phi) with Phi the FP32 field, S in FP64.
+ *   update         the incremental form of k-4/k-5: the terms are the
+ *                  strengths of the su entered (+) and left (-) this tick, and
+ *                  the field and image add their block sums: Phi += sum,
+ *                  sect += sect sum (FP32).
+ */
+
+/* Sect of a nonzero offset: rotate by -90 degrees, (dx, dy) -> (dy, -dx),
+ * until it lies in [0, 90) (dx > 0, dy >= 0); two sects per quarter turn. */
+int orc_sect(int dx, int dy)
+{
+    int q = 0;
+    while (!(dx > 0 && dy >= 0)) {
+        int t = dx;
+        dx = dy;
+        dy = -t;
+        ++q;
+    }
+    return 2 * q + (dy < dx ? 0 : 1);
+}
+
+/* Strength fan-out of a wd x ht field geometry (wd, ht odd): the largest
+ * number of window offsets that share one sect (Tables I and II). */
+int orc_fan_out(int wd, int ht)
+{
+    int a = (wd - 1) / 2, b = (ht - 1) / 2, cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0}, best = 0;
+    for (int dy = -b; dy <= b; ++dy)
+        for (int dx = -a; dx <= a; ++dx)
+            if (dx != 0 || dy != 0) ++cnt[orc_sect(dx, dy)];
+    for (int s = 0; s < 8; ++s) best = cnt[s] > best ? cnt[s] : best;
+    return best;
+}
+
+/* The term list of an (2R+1)^2 window in the order above, padded with zero
+ * terms to a multiple of K: offsets, strengths, sects (-1 for padding).
+ * Returns the padded length n; the arrays hold (2R+1)^2 - 1 + K entries. */
+static int sect_terms(int R, double k, double alpha, int K, int *tdx, int *tdy, float *tphi,
+                      int *tsect)
+{
+    int n = 0;
+    for (int s = 0; s < 8; ++s)
+        for (int dy = -R; dy <= R; ++dy)
+            for (int dx = -R; dx <= R; ++dx) {
+                if ((dx == 0 && dy == 0) || orc_sect(dx, dy) != s) continue;
+                tdx[n] = dx;
+                tdy[n] = dy;
+                tphi[n] = (float)orc_phi(dx, dy, R, k, alpha);
+                tsect[n] = s;
+                ++n;
+            }
+    while (n % K != 0) {
+        tdx[n] = tdy[n] = 0;
+        tphi[n] = 0.0f;
+        tsect[n] = -1;
+        ++n;
+    }
+    return n;
+}
+
+/* Source bit of su (x, y) - d: 1 if that su is a source (bounded grids have
+ * no sources beyond the edge; a torus wraps). */
+static int source_at(int W, int H, const uint8_t *src, int periodic, int x, int y)
+{
+    if (periodic) {
+        x = ((x % W) + W) % W;
+        y = ((y % H) + H) % H;
+    } else if (x < 0 || y < 0 || x >= W || y >= H) {
+        return 0;
+    }
+    return src[(size_t)y * W + x] != 0;
+}
+
+/* Algorithm 3 with K slots over every su.  With `minus` == NULL the terms are
+ * the strengths of the sources in `plus` (a full field: phi and image are
+ * written); otherwise the terms are +strength for `plus` and -strength for
+ * `minus` and the block and sect sums are added to phi and image (the
+ * update).  image (8 planes of W*H floats) may be NULL.  Returns the padded
+ * number of terms, or -1 if K is not one of 2, 4, 8, 16. */
+int orc_sect_field(int W, int H, const uint8_t *plus, const uint8_t *minus, int R, double k,
+                   double alpha, int periodic, int K, float *phi, float *image)
+{
+    if (K != 2 && K != 4 && K != 8 && K != 16) return -1;
+    const int cap = (2 * R + 1) * (2 * R + 1) - 1 + K;
+    int *tdx = malloc(sizeof(int) * cap), *tdy = malloc(sizeof(int) * cap);
+    int *tsect = malloc(sizeof(int) * cap);
+    float *tphi = malloc(sizeof(float) * cap);
+    const int n = sect_terms(R, k, alpha, K, tdx, tdy, tphi, tsect);
+    const int m = n / K;
+    const size_t plane = (size_t)W * H;
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) {
+            float slot[16], sect[8];
+            for (int j = 0; j < K; ++j) slot[j] = 0.0f;
+            for (int s = 0; s < 8; ++s) sect[s] = 0.0f;
+            for (int i = 0; i < n; ++i) {
+                if (tsect[i] < 0) continue; /* appended zero strength: adds +0 */
+                const int sx = x - tdx[i], sy = y - tdy[i];
+                float a = 0.0f;
+                if (source_at(W, H, plus, periodic, sx, sy)) a = tphi[i];
+                if (minus && source_at(W, H, minus, periodic, sx, sy)) a = -tphi[i];
+                slot[i / m] = slot[i / m] + a;
+                sect[tsect[i]] = sect[tsect[i]] + a;
+            }
+            float sum = 0.0f;
+            for (int j = 0; j < K; ++j) sum = sum + slot[j];
+            const size_t c = (size_t)y * W + x;
+            if (minus) {
+                phi[c] = phi[c] + sum;
+                if (image)
+                    for (int s = 0; s < 8; ++s) image[s * plane + c] = image[s * plane + c] + sect[s];
+            } else {
+                phi[c] = sum;
+                if (image)
+                    for (int s = 0; s < 8; ++s) image[s * plane + c] = sect[s];
+            }
+        }
+    free(tdx);
+    free(tdy);
+    free(tsect);
+    free(tphi);
+    return n;
+}
