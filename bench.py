@@ -18,8 +18,9 @@ gate against the oracle, and sub-objects: "hall1024" and "plaza8192"
 Other workloads (--workload): hall1024, room64, plaza8192 (one scene each),
 serving (longer windows), flow1000 (the paper's section 5 scenario: a
 1000x1000 torus, density 0.5, 8-directional flow, 7x7 fields, 1000 ticks),
-flow-sweep (its 360-combination grid) and flow-walk (its walk-period
-experiment of Table V).
+flow-sweep (its 360-combination grid), flow-walk (its walk-period
+experiment of Table V) and sect-compare (the paper's own 8-sect, K-slot FP32
+field path against the exact gather: speed and error).
 """
 from __future__ import annotations
 
@@ -567,6 +568,82 @@ def bench_flow_walk(args, stream):
     print(json.dumps(out), flush=True)
 
 
+def bench_sect_compare(args, stream):
+    """The paper's own field path (8 sects, fan-out terms, Algorithm 3's K
+    FP32 slots; sf_set_field_sect) against the exact gather on flow1000 (7x7
+    fields) and hall1024 (R = 16): field launch time (back-to-back launches,
+    HIP events), tick time, the FP32 field's error against the exact field and
+    the decisions of one tick that differ from the exact path's."""
+    import torch
+
+    from paper_1803_04782_amd import scenes, sf
+
+    steps = args.steps if args.steps is not None else 100
+    loops = 50
+    rows = []
+    for sc in (scenes.flow1000(), scenes.hall1024()):
+        for K in (0, 2, 4, 8, 16):
+            for refresh in (0, 8):
+                g = sf.GpuScene(sc, stream=stream)
+                ref = sf.GpuScene(sc, stream=stream)
+                try:
+                    if refresh:
+                        g.set_field_update(refresh)
+                    if K:
+                        g.set_field_sect(K)
+                    g.step(args.warmup)
+                    g.set_state(sc.pos, sc.start_step)
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    g.step(steps)
+                    torch.cuda.synchronize()
+                    dt = time.perf_counter() - t0
+                    ps = g.stats()["ped_steps"]
+                    # field launches back to back on the final state
+                    g.refresh_field(3)
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    e0.record(stream)
+                    g.refresh_field(loops)
+                    e1.record(stream)
+                    torch.cuda.synchronize()
+                    field_us = 1000.0 * e0.elapsed_time(e1) / loops
+                    # error and decisions against the exact path from the same state
+                    pos = g.positions()
+                    t_now = g.stats()["step"]
+                    ref.set_state(pos, t_now)
+                    P, Pe = g.field(), ref.field()
+                    free = np.isfinite(Pe)
+                    rel = np.abs(P[free].astype(np.float64) - Pe[free]) / np.maximum(
+                        np.abs(Pe[free].astype(np.float64)), 1.0)
+                    g.step(1)
+                    ref.step(1)
+                    tg, _ = g.last_moves()
+                    te, _ = ref.last_moves()
+                    live = pos >= 0
+                finally:
+                    g.close()
+                    ref.close()
+                row = {"workload": sc.name, "K": K, "path": "sect" if K else "gather",
+                       "refresh": refresh, "ms_per_tick": 1000.0 * dt / steps,
+                       "pedestrian_steps_per_s": ps / dt, "field_launch_us": field_us,
+                       "field_max_rel_err": float(rel.max()) if rel.size else 0.0,
+                       "field_su_differing": int(np.count_nonzero(P[free] != Pe[free])),
+                       "decisions_differing": int(np.count_nonzero(live & (tg != te))),
+                       "decisions": int(live.sum())}
+                rows.append(row)
+                say(f"{sc.name} {row['path']} K={K} refresh={refresh}: tick "
+                    f"{row['ms_per_tick'] * 1000:.1f} us, field {field_us:.1f} us, max rel err "
+                    f"{row['field_max_rel_err']:.2e}, {row['decisions_differing']} decisions "
+                    "differ")
+    out = {"metric": METRIC, "value": None, "unit": "pedestrian-steps/s", "n_gpus": 1,
+           "steps": steps, "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32 (sect path) / f64 (gather)", "data": "synthetic",
+           "config": {"workload": "sect-compare", "parallelism": "single-gpu"},
+           "runs": rows, "roofline": None, "cpu_baseline": None}
+    print(json.dumps(out), flush=True)
+
+
 def bench_serving(args, stream):
     """Serving loop under Poisson arrivals at several rates (longer windows
     than the default line's leg)."""
@@ -601,7 +678,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="default",
                     choices=["default", "ensemble256", "hall1024", "room64", "plaza8192",
-                             "flow1000", "flow-sweep", "flow-walk", "serving"])
+                             "flow1000", "flow-sweep", "flow-walk", "serving",
+                             "sect-compare"])
     ap.add_argument("--scenes", type=int, default=256, help="ensemble size (ensemble256)")
     ap.add_argument("--rates", default="50,200,800", help="arrival rates per s (serving)")
     ap.add_argument("--serve-seconds", type=float, default=None,
@@ -666,6 +744,9 @@ def main():
         return
     if args.workload == "flow-walk":
         bench_flow_walk(args, stream)
+        return
+    if args.workload == "sect-compare":
+        bench_sect_compare(args, stream)
         return
     if args.workload in ("default", "ensemble256"):
         t_start = time.perf_counter()

@@ -237,6 +237,32 @@ int sf_sync(const sf_scene *s);
  * batch; SF_ENOMEM if the FP64 field cannot be allocated. */
 int sf_set_field_update(sf_scene *s, int32_t refresh_ticks);
 
+/* The paper's own field path instead of the exact gather (section 3.1, s-1:
+ * each su keeps its strengths in 8 sects, the "3-D image", and the strength a
+ * source at o puts at su c lands in the sect of the offset c - o; the number
+ * of window offsets per sect is the strength fan-out SF; Algorithm 3 with
+ * Eq. 1: an su's 8*SF fan-out terms, zero padded to a multiple of K, are
+ * summed in K blocks of m consecutive terms, each into one FP32 slot, and the
+ * K slots are summed).  Readings: sect = floor(angle(c - o) / 45 degrees),
+ * the angle from +x toward +y in [0, 360) (SF = R(R+1)/2; the paper's 7x7
+ * field has 6); terms sect by sect, row-major within a sect; block j = terms
+ * j*m .. j*m + m - 1; all sums FP32 in that order; P = fl32(S + Phi32).
+ * K = 2, 4, 8 or 16 selects the path; K = 0 returns to the exact gather.
+ * keep_image = 1 also keeps the 8 sect planes (sf_sect_image; 32 B per su).
+ * With sf_set_field_update(K' >= 2) the ticks between full fields add the
+ * FP32 sums of the strengths at the su entered (+) and left (-) to the kept
+ * FP32 field and image: the incremental k-4/k-5 of Algorithm 1, whose FP32
+ * rounding drifts until the next full field.  The field is recomputed at
+ * once; blocks.  SF_EINVAL for another K or a scene in a batch (batches keep
+ * the gather); SF_ENOMEM if the FP32 field or image cannot be allocated. */
+int sf_set_field_sect(sf_scene *s, int32_t K, int32_t keep_image);
+
+/* The 8 sect planes of the sect path (8 x height x width floats, plane s =
+ * sect s of every su; the FP32 sums of that sect's terms), as kept by
+ * sf_set_field_sect with keep_image = 1; copy semantics as sf_field.
+ * SF_EINVAL when the scene keeps no image. */
+int sf_sect_image(const sf_scene *s, float *dst, int dst_on_device);
+
 /* Superpose the field of the current positions again, n_times times (no
  * tick; positions, counters and step index unchanged): k-5's write-back of
  * Algorithm 1 alone.  The result is the field sf_step leaves after a tick, bit
@@ -245,6 +271,35 @@ int sf_set_field_update(sf_scene *s, int32_t refresh_ticks);
  * scene's stream (timed as SF_KERNEL_SUPERPOSE); does not block.  SF_EINVAL
  * for a negative count or a scene that belongs to a batch. */
 int sf_refresh_field(sf_scene *s, int32_t n_times);
+
+/* Superposition without a scene: k-5's field write-back of Algorithm 1 for a
+ * caller's set of pedestrians (Algorithms 2 and 3 with Eq. 1: the field of an
+ * su is the sum of the strengths that the sources in its window put there,
+ * in any order).  For every su c of a width x height grid
+ *     P[c] = fl32(S[c] + sum over j < n with 0 <= pos[j] < width*height of
+ *                 phi(c - pos[j])),
+ * phi(d) = fl32(k*|d|_2^alpha) for 0 < |d|_inf <= radius, 0 elsewhere (on a
+ * torus, periodic = 1, the nearest image of each source), the sum formed
+ * exactly in FP64 (the law must pass the check of sf_create_scene) and
+ * rounded once.
+ *   S    device, double[width*height]: the static field (+inf on obstacle su
+ *        gives P = +inf there); read only.
+ *   pos  device, int32[n]: linear su indices; entries outside
+ *        0..width*height-1 (-1 for an absent pedestrian) are skipped, and a
+ *        repeated su counts once (the sources are the set of occupied su).
+ *   P    device, float[width*height]: written.
+ * The pointers belong to the caller and to the device current at the call.
+ * The work is enqueued on hip_stream (NULL = the null stream) and the call
+ * returns before it completes; its scratch (an occupancy bitmap of width*height
+ * bits and the stamp table, at most 160 KiB) is allocated and freed in stream
+ * order (hipMallocAsync / hipFreeAsync).  The same grid limits as a scene:
+ * SF_EINVAL for sizes, radius (0..SF_MAX_RADIUS; a torus needs width >= 64
+ * and 2*radius+1 <= both sides), a law refused by the exactness check,
+ * periodic not 0/1, n < 0, or a NULL S, P (or pos with n > 0); SF_ENOMEM when
+ * the scratch cannot be allocated; SF_EDEVICE for a HIP error. */
+int sf_superpose(int32_t width, int32_t height, int32_t periodic, int32_t radius, double k,
+                 double alpha, const double *S, const int32_t *pos, int32_t n, float *P,
+                 void *hip_stream);
 
 /* Per-kernel timing of the tick's kernels (the per-job time profile of the
  * paper's Fig. 7): while enabled, every launch of the kernels listed above

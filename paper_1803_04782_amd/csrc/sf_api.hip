@@ -106,6 +106,13 @@ struct sf_scene {
     double *phi = nullptr;  // exact pedestrian field (FP64) kept for the updates
     // bodies larger than one su: covered su and (bounded grids) obstacles
     unsigned long long *bodies = nullptr, *obits = nullptr;
+    // the paper's own field path (sf_set_field_sect): K slots (0 = off), the
+    // term list, the kept FP32 field and the optional 8-plane sect image
+    int sect_K = 0;
+    bool sect_image = false;
+    int2 *sect_terms = nullptr;
+    float *phi32 = nullptr, *image = nullptr;
+    sf::SectView sect_view = {};
     SceneView view_upd = {};
     FieldLaunch fl;
     // batch membership: while a batch holds the scene, `stream` is the
@@ -273,6 +280,18 @@ int check_law(int R, double k, double alpha, const char *what)
     return SF_OK;
 }
 
+// Persistent workgroups per compute unit of a single-scene field launch: as
+// many as a compute unit holds at once (LDS, registers, 32 waves); more would
+// run as a partial second round.
+int field_blocks_per_cu(const ListCfg &lc)
+{
+    int per_cu = (int)std::max<size_t>(1, (size_t)(160 * 1024) / lc.lds_bytes);
+    per_cu = std::min(per_cu, std::max(1, 32 / lc.nw));
+    const int resident = sf::field_resident_blocks(lc.tw, lc.hl, lc.nw, lc.lds_bytes, false);
+    if (resident > 0) per_cu = std::min(per_cu, resident);
+    return per_cu;
+}
+
 int validate(const sf_scene_desc *d)
 {
     if (!d) return fail(SF_EINVAL, "descriptor is NULL");
@@ -404,6 +423,8 @@ int timing_events(sf_scene *s, int k, sf::LaunchEvents *ev)
 hipError_t scene_field(const sf_scene *s, const SceneView &v, hipStream_t st,
                        const sf::LaunchEvents *ev = nullptr)
 {
+    if (s->sect_K)
+        return sf::launch_field_sect(s->sect_view, s->ncu * 8, false, s->sect_image, st, ev);
     if (s->dense) return sf::launch_field_dense(v, s->ncu * 8, st, ev);
     return sf::launch_field_one(s->fl, v, s->strips_per_block, st, ev);
 }
@@ -696,11 +717,7 @@ int create(const sf_scene_desc *d, void *hip_stream, sf_scene **out)
     {
         // as many persistent workgroups as a compute unit holds at once: more
         // would run as a partial second round
-        int per_cu = (int)std::max<size_t>(1, (size_t)(160 * 1024) / s->lc.lds_bytes);
-        per_cu = std::min(per_cu, std::max(1, 32 / (s->lc.nw)));
-        const int resident =
-            sf::field_resident_blocks(s->lc.tw, s->lc.hl, s->lc.nw, s->lc.lds_bytes, false);
-        if (resident > 0) per_cu = std::min(per_cu, resident);
+        int per_cu = field_blocks_per_cu(s->lc);
         if (const char *e = std::getenv("SF_FIELD_BLOCKS_PER_CU")) {
             // override of the field kernel's persistent workgroups per CU (speed only)
             const int b = std::atoi(e);
@@ -832,8 +849,15 @@ int enqueue_tick(sf_scene *s)
     if ((rc = timing_events(s, SF_KERNEL_SUPERPOSE, &ev))) return rc;
     if (s->refresh > 1 && s->since_full + 1 < s->refresh) {
         // P = (P + stamps at the su entered) - stamps at the su left this tick
-        SF_HIP(sf::launch_field_update(s->fl, s->view_upd, s->strips_per_block, st, &ev),
-               "update");
+        if (s->sect_K) {
+            sf::SectView u = s->sect_view;
+            u.src = s->moved_to;
+            u.src2 = s->moved_from;
+            SF_HIP(sf::launch_field_sect(u, s->ncu * 8, true, s->sect_image, st, &ev), "update");
+        } else {
+            SF_HIP(sf::launch_field_update(s->fl, s->view_upd, s->strips_per_block, st, &ev),
+                   "update");
+        }
         ++s->since_full;
     } else {
         SF_HIP(scene_field(s, s->view, st, &ev), "superpose");
@@ -870,6 +894,82 @@ int set_field_update(sf_scene *s, int32_t refresh)
     // the next tick starts a new refresh period from a full field
     s->since_full = s->refresh;
     SF_HIP(hipStreamSynchronize(s->stream), "field update sync");
+    return SF_OK;
+}
+
+// Sect of a nonzero offset d: floor(angle / 45 degrees), the angle of d from
+// +x (east) toward +y (south) in [0, 360), each sector half-open at its far
+// edge; two sects per quadrant.
+int offset_sect(int dx, int dy)
+{
+    if (dx > 0 && dy >= 0) return dy < dx ? 0 : 1;
+    if (dx <= 0 && dy > 0) return -dx < dy ? 2 : 3;
+    if (dx < 0 && dy <= 0) return -dy < -dx ? 4 : 5;
+    return dx < -dy ? 6 : 7;  // dx >= 0, dy < 0
+}
+
+// Switches the scene's field to the paper's own path with K slots (K = 0:
+// back to the exact gather) and recomputes the field.
+int set_field_sect(sf_scene *s, int K, bool keep_image)
+{
+    const size_t n = (size_t)s->W * s->H;
+    int rc;
+    if (K != 0) {
+        if (s->R > sf::kSectMaxRadius)
+            return fail(SF_EINVAL, "radius %d is above %d for the sect path", s->R,
+                        sf::kSectMaxRadius);
+        // fan-out terms: sect by sect, row-major within a sect, strengths
+        // fl32(k |d|^alpha) as in the gather's stamp
+        std::vector<int2> terms;
+        const int R = s->R;
+        for (int sc = 0; sc < 8; ++sc) {
+            const size_t first = terms.size();
+            for (int dy = -R; dy <= R; ++dy)
+                for (int dx = -R; dx <= R; ++dx) {
+                    if ((dx == 0 && dy == 0) || offset_sect(dx, dy) != sc) continue;
+                    const double dist = std::sqrt((double)dx * dx + (double)dy * dy);
+                    const float ph = (float)(s->k * std::pow(dist, s->alpha));
+                    int2 t;
+                    t.x = (dx + 128) | ((dy + 128) << 8) | (sc << 16);
+                    std::memcpy(&t.y, &ph, sizeof ph);
+                    terms.push_back(t);
+                }
+            if (terms.size() > first) terms.back().x |= 1 << 20;  // last term of the sect
+        }
+        const int n_real = (int)terms.size();
+        if (!s->sect_terms && (rc = dalloc(s, &s->sect_terms, (size_t)std::max(n_real, 1),
+                                           "sect terms")))
+            return rc;
+        if (!s->phi32 && (rc = dalloc(s, &s->phi32, n, "FP32 field"))) return rc;
+        if (keep_image && !s->image && (rc = dalloc(s, &s->image, 8 * n, "sect image")))
+            return rc;
+        if (n_real)
+            SF_HIP(hipMemcpyAsync(s->sect_terms, terms.data(), terms.size() * sizeof(int2),
+                                  hipMemcpyHostToDevice, s->stream),
+                   "copy sect terms");
+        sf::SectView &v = s->sect_view;
+        v = sf::SectView{};
+        v.W = s->W;
+        v.H = s->H;
+        v.wpr = s->wpr;
+        v.R = R;
+        v.periodic = s->periodic ? 1 : 0;
+        v.K = K;
+        v.m = (n_real + K - 1) / K;  // zero terms pad the list to m*K
+        v.n_real = n_real;
+        v.terms = s->sect_terms;
+        v.src = v.src2 = s->occ;
+        v.S = s->S;
+        v.P = s->P;
+        v.phi32 = s->phi32;
+        v.image = keep_image ? s->image : nullptr;
+    }
+    s->sect_K = K;
+    s->sect_image = K != 0 && keep_image;
+    // the next tick of an incremental update starts from a full field
+    s->since_full = s->refresh;
+    SF_HIP(scene_field(s, s->view, s->stream), "superpose");
+    SF_HIP(hipStreamSynchronize(s->stream), "field path sync");
     return SF_OK;
 }
 
@@ -1230,6 +1330,8 @@ int batch_create(sf_scene *const *scenes, int32_t n, const sf_batch_tiling *tili
             return fail(SF_EINVAL, "scene %d uses the incremental field update", i);
         if (s->bodies)
             return fail(SF_EINVAL, "scene %d has bodies larger than one su", i);
+        if (s->sect_K)
+            return fail(SF_EINVAL, "scene %d uses the sect field path", i);
         if (s->device != dev) return fail(SF_EINVAL, "scene %d is on device %d, not %d", i, s->device, dev);
         for (int32_t j = 0; j < i; ++j)
             if (scenes[j] == s) return fail(SF_EINVAL, "scene %d is listed twice", i);
@@ -1352,6 +1454,108 @@ int batch_tune(sf_batch *b, int32_t reps, sf_batch_tiling *chosen)
     free_layout(b->cur);
     b->cur = L;
     if (chosen) *chosen = b->cur.t;
+    return SF_OK;
+}
+
+// ---- stateless superposition (sf_superpose) -------------------------------------------
+
+// Arguments of a stateless superposition after validation, with its launch
+// shape and the scratch it needs: the occupancy bitmap (wpr*H words) and the
+// stamp table (lc.tab_elems doubles).
+struct SuperposeCall {
+    int W = 0, H = 0, R = 0, periodic = 0, n = 0, wpr = 0;
+    double k = 1, alpha = -0.5;
+    const double *S = nullptr;
+    const int32_t *pos = nullptr;
+    float *P = nullptr;
+    hipStream_t stream = nullptr;
+    ListCfg lc;
+    size_t lds_limit = 0;
+    size_t bitmap_words = 0, tab_doubles = 0;
+};
+
+int superpose_prepare(int32_t W, int32_t H, int32_t periodic, int32_t R, double k, double alpha,
+                      const double *S, const int32_t *pos, int32_t n, float *P, void *hip_stream,
+                      SuperposeCall *c)
+{
+    if (W <= 0 || H <= 0)
+        return fail(SF_EINVAL, "grid %d x %d: both sides must be positive", W, H);
+    if ((int64_t)W * H >= (int64_t)1 << 31)
+        return fail(SF_EINVAL, "grid %d x %d has 2^31 su or more", W, H);
+    if (R < 0 || R > SF_MAX_RADIUS) return fail(SF_EINVAL, "radius %d outside 0..%d", R,
+                                                SF_MAX_RADIUS);
+    if (periodic != 0 && periodic != 1)
+        return fail(SF_EINVAL, "periodic = %d is neither 0 nor 1", periodic);
+    if (periodic && W < 64) return fail(SF_EINVAL, "periodic grid width %d is below 64", W);
+    if (periodic && 2 * R + 1 > std::min(W, H))
+        return fail(SF_EINVAL, "periodic grid %d x %d is narrower than the %d-su window", W, H,
+                    2 * R + 1);
+    if (!std::isfinite(k) || !std::isfinite(alpha))
+        return fail(SF_EINVAL, "field parameters must be finite");
+    if (n < 0) return fail(SF_EINVAL, "n = %d is negative", n);
+    if (n > 0 && !pos) return fail(SF_EINVAL, "pos is NULL with n = %d", n);
+    if (!S || !P) return fail(SF_EINVAL, "S and P are required");
+    int rc = check_law(R, k, alpha, "pedestrian");
+    if (rc) return rc;
+    int dev = 0, max_lds = 0;
+    SF_HIP(hipGetDevice(&dev), "hipGetDevice");
+    SF_HIP(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev),
+           "LDS size");
+    c->lc = sf::pick_list_cfg(R, (size_t)max_lds - 1024);
+    if (c->lc.lds_bytes == 0 || c->lc.lds_bytes > (size_t)max_lds - 1024 ||
+        c->lc.list_cap < 2 * c->lc.max_row)
+        return fail(SF_EINVAL, "field of radius %d does not fit %d B of LDS", R, max_lds);
+    int ncu = 0;
+    SF_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev), "CU count");
+    c->lc.grid = ncu * field_blocks_per_cu(c->lc);
+    c->lds_limit = (size_t)max_lds - 1024;  // the same limit as the scenes' launches
+    c->W = W;
+    c->H = H;
+    c->R = R;
+    c->periodic = periodic;
+    c->n = n;
+    c->k = k;
+    c->alpha = alpha;
+    c->S = S;
+    c->pos = pos;
+    c->P = P;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    c->wpr = (W + 63) / 64;
+    c->bitmap_words = (size_t)c->wpr * H;
+    c->tab_doubles = (size_t)c->lc.tab_elems;
+    return SF_OK;
+}
+
+// Enqueues the superposition of `c` on its stream with the given scratch:
+// clear the bitmap, mark the positions, fill the stamp, gather.
+int superpose_enqueue(const SuperposeCall &c, unsigned long long *bits, double *tab)
+{
+    const int R = c.R;
+    float oct[(SF_MAX_RADIUS + 1) * (SF_MAX_RADIUS + 2) / 2];
+    for (int i = 0; i <= R; ++i)
+        for (int j = 0; j <= i; ++j) {
+            // the same strength as the scene's stamp: fl32(k |d|^alpha)
+            const double dist = std::sqrt((double)i * i + (double)j * j);
+            oct[i * (i + 1) / 2 + j] =
+                (i == 0) ? 0.f : (float)(c.k * std::pow(dist, c.alpha));
+        }
+    SF_HIP(sf::set_field_lds_limit(c.lds_limit), "LDS limit");
+    SF_HIP(sf::launch_fill_u64(bits, c.bitmap_words, 0ull, c.stream), "clear bitmap");
+    SF_HIP(sf::launch_occ_mark(c.pos, c.n, bits, c.wpr, c.W, c.W * c.H, c.stream), "mark");
+    SF_HIP(sf::launch_stamp_fill(tab, c.lc.tab_elems, c.lc.ncols, c.lc.stride, c.lc.padx,
+                                 c.lc.pady, R, oct, c.stream),
+           "stamp");
+    SceneView v{};
+    v.W = c.W;
+    v.H = c.H;
+    v.wpr = c.wpr;
+    v.R = R;
+    v.S = c.S;
+    v.P = c.P;
+    v.occ = bits;
+    v.periodic = c.periodic;
+    sf::set_view_layout(v, c.lc, tab);
+    SF_HIP(sf::launch_field_one(sf::field_launch_for(c.lc), v, 1, c.stream), "superpose");
     return SF_OK;
 }
 
@@ -1537,6 +1741,28 @@ int sf_set_field_update(sf_scene *s, int32_t refresh_ticks)
     }
 }
 
+int sf_set_field_sect(sf_scene *s, int32_t K, int32_t keep_image)
+{
+    if (!s) return fail(SF_EINVAL, "scene is NULL");
+    if (K != 0 && K != 2 && K != 4 && K != 8 && K != 16)
+        return fail(SF_EINVAL, "K = %d is not 0, 2, 4, 8 or 16", K);
+    if (s->batch) return fail(SF_EINVAL, "the scene belongs to a batch");
+    DeviceGuard g(s->device);
+    try {
+        return set_field_sect(s, K, keep_image != 0);
+    } catch (const std::bad_alloc &) {
+        return fail(SF_ENOMEM, "host allocation failed");
+    }
+}
+
+int sf_sect_image(const sf_scene *s, float *dst, int dst_on_device)
+{
+    if (!s || !dst) return fail(SF_EINVAL, "scene or dst is NULL");
+    if (!s->sect_image) return fail(SF_EINVAL, "the scene keeps no sect image");
+    DeviceGuard g(s->device);
+    return copy_out(s, dst, s->image, 8 * (size_t)s->W * s->H * sizeof(float), dst_on_device);
+}
+
 int sf_set_timing(sf_scene *s, int enable)
 {
     if (!s) return fail(SF_EINVAL, "scene is NULL");
@@ -1692,6 +1918,32 @@ void sf_batch_destroy(sf_batch *b)
     free_layout(b->cur);
     destroy_batch_streams(b);
     delete b;
+}
+
+int sf_superpose(int32_t width, int32_t height, int32_t periodic, int32_t radius, double k,
+                 double alpha, const double *S, const int32_t *pos, int32_t n, float *P,
+                 void *hip_stream)
+{
+    g_last_error.clear();
+    SuperposeCall c;
+    int rc = superpose_prepare(width, height, periodic, radius, k, alpha, S, pos, n, P,
+                               hip_stream, &c);
+    if (rc) return rc;
+    void *bits = nullptr, *tab = nullptr;
+    SF_HIP(hipMallocAsync(&bits, c.bitmap_words * 8, c.stream), "bitmap");
+    hipError_t e = hipMallocAsync(&tab, c.tab_doubles * 8, c.stream);
+    if (e != hipSuccess) {
+        (void)hipFreeAsync(bits, c.stream);
+        return hip_fail(e, "stamp table");
+    }
+    rc = superpose_enqueue(c, static_cast<unsigned long long *>(bits), static_cast<double *>(tab));
+    // freed in stream order, after the launches that use them
+    const hipError_t e1 = hipFreeAsync(tab, c.stream);
+    const hipError_t e2 = hipFreeAsync(bits, c.stream);
+    if (rc) return rc;
+    SF_HIP(e1, "free stamp table");
+    SF_HIP(e2, "free bitmap");
+    return SF_OK;
 }
 
 int sf_device_count(void)

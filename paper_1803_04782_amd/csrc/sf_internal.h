@@ -192,6 +192,25 @@ hipError_t launch_decide_body(const SceneView &view, hipStream_t st,
 hipError_t launch_commit_body(const SceneView &view, hipStream_t st,
                               const LaunchEvents *ev = nullptr);
 
+// The paper's own field path (8 sects, fan-out terms, Algorithm 3's K FP32
+// slots) of one scene.  terms[i] (i < n_real; the padded count is m*K):
+// x = (dx + 128) | (dy + 128) << 8 | sect << 16 | (last term of its sect) << 20,
+// y = the FP32 strength's bits; sect by sect, row-major within a sect.
+struct SectView {
+    int32_t W, H, wpr, R, periodic;
+    int32_t K, m, n_real;
+    const int2 *terms;
+    const unsigned long long *src;   // sources (full field) or the su entered (update)
+    const unsigned long long *src2;  // the su left (update), else = src
+    const double *S;
+    float *P;
+    float *phi32;  // the FP32 field, written (full) or updated in place
+    float *image;  // 8 planes of W*H sect sums, or NULL
+};
+constexpr int kSectMaxRadius = 48;
+hipError_t launch_field_sect(const SectView &v, int grid, bool update, bool image,
+                             hipStream_t st, const LaunchEvents *ev = nullptr);
+
 // Launchers: all enqueue on `st` and return the launch status.
 hipError_t launch_fill_u64(unsigned long long *p, size_t n, unsigned long long v, hipStream_t st);
 hipError_t launch_fill_i32(int32_t *p, size_t n, int32_t v, hipStream_t st);
@@ -220,6 +239,14 @@ hipError_t launch_static_S(const int32_t *D, const double *O, const uint8_t *obs
                            double w_dest, double *S, int n, hipStream_t st);
 hipError_t launch_occ_init(const int32_t *pos, int N, unsigned long long *occ, int wpr, int W,
                            unsigned long long *ctr, hipStream_t st);
+// Stateless superposition: bitmap bits of the entries 0 <= pos[i] < nsu (the
+// bitmap must be cleared first), and the gather's stamp table (n doubles of
+// the layout of a ListCfg) from the law's strengths over one octant of the
+// window, oct[i(i+1)/2 + j] for 0 <= j <= i <= R.
+hipError_t launch_occ_mark(const int32_t *pos, int n, unsigned long long *occ, int wpr, int W,
+                           int nsu, hipStream_t st);
+hipError_t launch_stamp_fill(double *tab, int n, int ncols, int stride, int padx, int pady, int R,
+                             const float *oct, hipStream_t st);
 // Decide + claim over `n_blocks` workgroups, decide_blocks(N) per scene.
 // `block_scene[b]` names the scene of workgroup b (NULL: every workgroup
 // belongs to views[0]).

@@ -962,6 +962,51 @@ __global__ void k_occ_init(const int32_t *__restrict__ pos, int N, unsigned long
     block_sum_add(p >= 0 ? 1u : 0u, ctr, kLive);
 }
 
+// Occupancy bitmap of a caller's position list (the stateless superposition):
+// the bit of su p is set for every entry 0 <= p < nsu; other entries (-1 for
+// an absent pedestrian, or out of range) set nothing.
+__global__ void k_occ_mark(const int32_t *__restrict__ pos, int n, unsigned long long *occ,
+                           int wpr, int W, int nsu)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (size_t)n) return;
+    const int p = pos[i];
+    if (p < 0 || p >= nsu) return;
+    const int y = p / W, x = p - y * W;
+    atomicOr(&occ[(size_t)y * wpr + (x >> 6)], 1ull << (x & 63));
+}
+
+// The law's strengths over one octant of the window, (i, j) with
+// 0 <= j <= i <= R at index i(i+1)/2 + j, travel as kernel arguments in
+// chunks (no host buffer outlives the call that launches them).
+constexpr int kOctChunk = 960;
+struct OctChunk {
+    int first, count;
+    float v[kOctChunk];
+};
+
+// Stamp table of the gather (column-major, zero padded, FP32 strengths held
+// as doubles) from octant strengths: entry (dx, dy) takes the strength of
+// (max(|dx|,|dy|), min(|dx|,|dy|)) for 0 < |d|_inf <= R and 0 elsewhere.
+// A launch writes the entries whose octant index is in its chunk; the launch
+// of the first chunk also writes the zeros.
+__global__ void k_stamp_fill(double *__restrict__ tab, int n, int ncols, int stride, int padx,
+                             int pady, int R, OctChunk c)
+{
+    for (int e = (int)(blockIdx.x * blockDim.x + threadIdx.x); e < n;
+         e += (int)(gridDim.x * blockDim.x)) {
+        const int ci = e / stride, ri = e - ci * stride;
+        const int ax = abs(ci - padx), ay = abs(ri - pady);
+        const int i = max(ax, ay), j = min(ax, ay);
+        if (ci >= ncols || i == 0 || i > R) {
+            if (c.first == 0) tab[e] = 0.0;
+            continue;
+        }
+        const int idx = i * (i + 1) / 2 + j - c.first;
+        if (idx >= 0 && idx < c.count) tab[e] = (double)c.v[idx];
+    }
+}
+
 // ---- small-radius field: dense stencil over the occupancy bits -------------------
 //
 // With a small window and a dense crowd most of the gather's adds are the zero
@@ -1067,6 +1112,175 @@ __global__ __launch_bounds__(kDenseWaves * 64) void k_field_dense(SceneView one,
             }
         }
         __syncthreads();  // the rows are restaged for the next tile
+    }
+}
+
+// ---- the paper's own field path: 8 sects, fan-out terms, K slots -----------------------
+//
+// Section 3.1 (s-1) keeps an su's strengths in 8 sects and Algorithm 3 (Eq. 1)
+// sums its 8*SF fan-out terms in K blocks of m consecutive terms, each block
+// into one FP32 slot, then the slots.  Here every su walks the scene's term
+// list (offset, strength, sect) in that order: a term adds its strength when
+// the su at the offset's source holds a pedestrian.  Lane l owns column X0 + l
+// of a 64-column tile and kSectHL rows; the term is uniform across the wave
+// (a scalar load), and the lane takes the source bits of its kSectHL rows
+// from a column word of the source column: the workgroup stages the window's
+// bitmap rows in LDS, each wave transposes them into one 128-bit word per
+// column (bit j = row Y0w - R + j), and a term reads the column x - dx at bit
+// R - dy.  The FP32 adds follow the term order exactly, so the field is the
+// one the FP32 sums of Algorithm 3 give, bit for bit.  UPDATE: the sources are
+// the su entered (+) and left (-) this tick and the sums are added to the kept
+// FP32 field and image.  IMAGE: sect s of each su (its terms' FP32 sum) is
+// written to plane s.
+
+constexpr int kSectHL = 8;     // rows per lane
+constexpr int kSectWaves = 4;  // waves per workgroup (tile: 64 x 32 su)
+constexpr int kSectMaxR = 48;  // column words hold kSectHL + 2R <= 128 rows
+
+template <bool UPDATE, bool IMAGE, bool SECTACC>
+__global__ __launch_bounds__(kSectWaves * 64) void k_field_sect(SectView v, int n_tiles)
+{
+    constexpr int TH = kSectWaves * kSectHL;
+    constexpr int NSRC = UPDATE ? 2 : 1;
+    constexpr int MAXR = TH + 2 * kSectMaxR;   // staged rows
+    constexpr int MAXC = 64 + 2 * kSectMaxR;   // columns of a wave's window
+    __shared__ unsigned long long rows[NSRC][MAXR][4];
+    // one spare column: a term at bit 96 reads the word after its column's last
+    __shared__ uint4 cols[NSRC][kSectWaves][MAXC + 1];
+    const int W = v.W, H = v.H, wpr = v.wpr, R = v.R;
+    const int tid = (int)threadIdx.x, lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int tiles_x = (W + 63) >> 6;
+    const int TR = TH + 2 * R, NC = 64 + 2 * R;
+    const gptr<const double> S = to_global(v.S);
+    const gptr<float> P = to_global(v.P);
+    const gptr<float> F = to_global(v.phi32);
+    const gptr<float> img = to_global(v.image);
+    const size_t plane = (size_t)W * H;
+    for (int t = (int)blockIdx.x; t < n_tiles; t += (int)gridDim.x) {
+        const int ty = t / tiles_x, tx = t - ty * tiles_x;
+        const int X0 = tx * 64, Y0 = ty * TH, y0 = Y0 + wv * kSectHL, x = X0 + lane;
+        const int wa = (X0 - R) >> 6;  // first staged word (floor)
+        // 1. stage the bitmap rows Y0 - R .. Y0 + TH + R - 1, words wa .. wa + 3
+        for (int k = tid; k < NSRC * TR * 4; k += kSectWaves * 64) {
+            const int src = k / (TR * 4), rk = k - src * TR * 4;
+            const int r = rk >> 2, c = rk & 3;
+            const gptr<const unsigned long long> bits = to_global(src ? v.src2 : v.src);
+            int sy = Y0 - R + r;
+            const int w = wa + c;
+            unsigned long long wd = 0ull;
+            if (v.periodic) {
+                sy = ((sy % H) + H) % H;
+                wd = wrapped_word(bits + (size_t)sy * wpr, w, W, wpr);
+            } else if (sy >= 0 && sy < H && w >= 0 && w < wpr) {
+                wd = bits[(size_t)sy * wpr + w];
+            }
+            rows[src][r][c] = wd;
+        }
+        __syncthreads();
+        // 2. this wave's column words: column X0 - R + j (j < NC), bit i = row
+        // y0 - R + i (i < kSectHL + 2R)
+        for (int j = lane; j < NC; j += 64) {
+            const int cx = X0 - R + j, wi = (cx >> 6) - wa, b = cx & 63;
+#pragma unroll
+            for (int src = 0; src < NSRC; ++src) {
+                unsigned int cw[4] = {0u, 0u, 0u, 0u};
+                for (int i = 0; i < kSectHL + 2 * R; ++i) {
+                    const unsigned int bit =
+                        (unsigned int)(rows[src][wv * kSectHL + i][wi] >> b) & 1u;
+                    cw[i >> 5] |= bit << (i & 31);
+                }
+                cols[src][wv][j] = make_uint4(cw[0], cw[1], cw[2], cw[3]);
+            }
+        }
+        __syncthreads();
+        // S (and, for an update, the kept field) of this lane's su
+        double sv[kSectHL];
+        float fv[kSectHL];
+#pragma unroll
+        for (int h = 0; h < kSectHL; ++h) {
+            const size_t c = (size_t)min(y0 + h, H - 1) * W + min(x, W - 1);
+            sv[h] = S[c];
+            fv[h] = UPDATE ? F[c] : 0.0f;
+        }
+        // 3. the terms in order, block by block
+        float tot[kSectHL], sec[kSectHL];
+#pragma unroll
+        for (int h = 0; h < kSectHL; ++h) tot[h] = sec[h] = 0.0f;
+        const uint32_t cbase = (uint32_t)(uintptr_t)(lds_ptr<uint4>)&cols[0][wv][0];
+        const uint32_t cbase2 = (uint32_t)(uintptr_t)(lds_ptr<uint4>)&cols[NSRC - 1][wv][0];
+        const bool store = x < W && y0 < H;
+        for (int j = 0; j < v.K; ++j) {
+            float blk[kSectHL];
+#pragma unroll
+            for (int h = 0; h < kSectHL; ++h) blk[h] = 0.0f;
+            const int i1 = min(j * v.m + v.m, v.n_real);
+            for (int i = j * v.m; i < i1; ++i) {
+                const int2 term = v.terms[i];
+                const int info = __builtin_amdgcn_readfirstlane(term.x);
+                const float ph = __int_as_float(__builtin_amdgcn_readfirstlane(term.y));
+                const int dx = (info & 0xFF) - 128, dy = ((info >> 8) & 0xFF) - 128;
+                // bits R - dy .. R - dy + 7 of column x - dx
+                const int sh = R - dy, q = sh >> 5, rr = sh & 31;
+                const uint32_t off = (uint32_t)((lane + R - dx) * 16 + q * 4);
+                typedef const __attribute__((address_space(3))) unsigned int *lds_u;
+                const lds_u a = reinterpret_cast<lds_u>(cbase + off);
+                unsigned int bits = __builtin_amdgcn_alignbit(a[1], a[0], rr);
+                unsigned int bits2 = 0u;
+                if constexpr (UPDATE) {
+                    const lds_u a2 = reinterpret_cast<lds_u>(cbase2 + off);
+                    bits2 = __builtin_amdgcn_alignbit(a2[1], a2[0], rr);
+                }
+#pragma unroll
+                for (int h = 0; h < kSectHL; ++h) {
+                    float d = (float)((bits >> h) & 1u);
+                    if constexpr (UPDATE) d -= (float)((bits2 >> h) & 1u);
+                    blk[h] = fmaf(d, ph, blk[h]);
+                    if constexpr (SECTACC) sec[h] = fmaf(d, ph, sec[h]);
+                }
+                if constexpr (IMAGE && SECTACC) {
+                    if (info & (1 << 20)) {  // the last term of its sect
+                        const int s = (info >> 16) & 7;
+#pragma unroll
+                        for (int h = 0; h < kSectHL; ++h) {
+                            const size_t c = (size_t)(y0 + h) * W + x;
+                            if (store && y0 + h < H)
+                                img[s * plane + c] = UPDATE ? img[s * plane + c] + sec[h] : sec[h];
+                            sec[h] = 0.0f;
+                        }
+                    }
+                }
+            }
+            if constexpr (IMAGE && !SECTACC) {  // K = 8: block j is sect j
+#pragma unroll
+                for (int h = 0; h < kSectHL; ++h) {
+                    const size_t c = (size_t)(y0 + h) * W + x;
+                    if (store && y0 + h < H)
+                        img[j * plane + c] = UPDATE ? img[j * plane + c] + blk[h] : blk[h];
+                }
+            }
+#pragma unroll
+            for (int h = 0; h < kSectHL; ++h) tot[h] = tot[h] + blk[h];
+        }
+        if constexpr (IMAGE) {
+            if (v.n_real == 0 && !UPDATE) {  // R = 0: no terms, every sect is 0
+                for (int s = 0; s < 8; ++s)
+#pragma unroll
+                    for (int h = 0; h < kSectHL; ++h)
+                        if (store && y0 + h < H) img[s * plane + (size_t)(y0 + h) * W + x] = 0.0f;
+            }
+        }
+        // 4. the FP32 field (an update adds its sum to the kept field) and P
+#pragma unroll
+        for (int h = 0; h < kSectHL; ++h) {
+            if (store && y0 + h < H) {
+                const size_t c = (size_t)(y0 + h) * W + x;
+                const float f = UPDATE ? fv[h] + tot[h] : tot[h];
+                F[c] = f;
+                P[c] = (float)(sv[h] + (double)f);
+            }
+        }
+        __syncthreads();  // rows and columns are restaged for the next tile
     }
 }
 
@@ -1844,6 +2058,50 @@ hipError_t launch_fill_i32(int32_t *p, size_t n, int32_t v, hipStream_t st)
 {
     hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(n, 256, 8192)), dim3(256), 0, st, p, n, v);
     return hipGetLastError();
+}
+
+hipError_t launch_field_sect(const SectView &v, int grid, bool update, bool image,
+                             hipStream_t st, const LaunchEvents *ev)
+{
+    if (v.R > kSectMaxR) return hipErrorInvalidValue;
+    const int tiles = ((v.W + 63) / 64) * ((v.H + kSectWaves * kSectHL - 1) / (kSectWaves * kSectHL));
+    const dim3 g((unsigned)std::max(1, std::min(grid, tiles))), b(kSectWaves * 64);
+    const bool sectacc = image && v.K != 8;
+    if (update) {
+        if (!image) return launch(k_field_sect<true, false, false>, g, b, 0, st, ev, v, tiles);
+        if (sectacc) return launch(k_field_sect<true, true, true>, g, b, 0, st, ev, v, tiles);
+        return launch(k_field_sect<true, true, false>, g, b, 0, st, ev, v, tiles);
+    }
+    if (!image) return launch(k_field_sect<false, false, false>, g, b, 0, st, ev, v, tiles);
+    if (sectacc) return launch(k_field_sect<false, true, true>, g, b, 0, st, ev, v, tiles);
+    return launch(k_field_sect<false, true, false>, g, b, 0, st, ev, v, tiles);
+}
+
+hipError_t launch_occ_mark(const int32_t *pos, int n, unsigned long long *occ, int wpr, int W,
+                           int nsu, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_occ_mark, dim3(blocks_for((size_t)n, 256, kCoverAll)), dim3(256), 0, st,
+                       pos, n, occ, wpr, W, nsu);
+    return hipGetLastError();
+}
+
+hipError_t launch_stamp_fill(double *tab, int n, int ncols, int stride, int padx, int pady, int R,
+                             const float *oct, hipStream_t st)
+{
+    const int total = (R + 1) * (R + 2) / 2;
+    for (int first = 0; first < total; first += kOctChunk) {
+        OctChunk c;
+        c.first = first;
+        c.count = std::min(kOctChunk, total - first);
+        for (int i = 0; i < c.count; ++i) c.v[i] = oct[first + i];
+        for (int i = c.count; i < kOctChunk; ++i) c.v[i] = 0.f;
+        hipLaunchKernelGGL(k_stamp_fill, dim3(blocks_for((size_t)n, 256, 1024)), dim3(256), 0, st,
+                           tab, n, ncols, stride, padx, pady, R, c);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_mask_to_bits(const uint8_t *mask, unsigned long long *bits, int W, int H, int wpr,

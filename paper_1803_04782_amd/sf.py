@@ -34,10 +34,11 @@ SF_KERNEL_COMMIT = 2
 # every symbol include/sf.h declares
 EXPORTS = ("sf_create_scene", "sf_step", "sf_field", "sf_positions", "sf_last_moves",
            "sf_static_field", "sf_set_state", "sf_stats", "sf_sync", "sf_set_timing",
-           "sf_kernel_time", "sf_refresh_field", "sf_set_field_update", "sf_destroy_scene", "sf_batch_create", "sf_batch_tune",
+           "sf_kernel_time", "sf_refresh_field", "sf_set_field_update", "sf_set_field_sect",
+           "sf_sect_image", "sf_destroy_scene", "sf_batch_create", "sf_batch_tune",
            "sf_batch_get_tiling", "sf_batch_step", "sf_batch_refresh_field", "sf_batch_stats",
            "sf_batch_sync",
-           "sf_batch_destroy", "sf_device_count",
+           "sf_batch_destroy", "sf_superpose", "sf_device_count",
            "sf_last_error")
 _VOID = ("sf_destroy_scene", "sf_batch_destroy", "sf_last_error")
 
@@ -154,6 +155,8 @@ def load():
                                    ctypes.POINTER(i64)]
     lib.sf_set_field_update.argtypes = [P, i32]
     lib.sf_refresh_field.argtypes = [P, i32]
+    lib.sf_set_field_sect.argtypes = [P, i32, i32]
+    lib.sf_sect_image.argtypes = [P, P, ctypes.c_int]
     lib.sf_destroy_scene.argtypes = [P]
     lib.sf_destroy_scene.restype = None
     lib.sf_batch_create.argtypes = [ctypes.POINTER(P), i32, ctypes.POINTER(Tiling), P,
@@ -166,6 +169,8 @@ def load():
     lib.sf_batch_sync.argtypes = [P]
     lib.sf_batch_destroy.argtypes = [P]
     lib.sf_batch_destroy.restype = None
+    lib.sf_superpose.argtypes = [i32, i32, i32, i32, ctypes.c_double, ctypes.c_double, P, P, i32,
+                                 P, P]
     lib.sf_last_error.restype = ctypes.c_char_p
     lib.sf_last_error.argtypes = []
     lib.sf_device_count.argtypes = []
@@ -179,6 +184,46 @@ def load():
 def device_count() -> int:
     """HIP devices the library sees (0 without one)."""
     return int(load().sf_device_count())
+
+
+def _device_tensor(t, dtype, numel: int, what: str):
+    """Pointer of a contiguous CUDA tensor of `dtype` with at least `numel` elements."""
+    import torch
+
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{what} must be a CUDA tensor")
+    if t.dtype != dtype or not t.is_contiguous() or t.numel() < numel:
+        raise ValueError(f"{what} must be a contiguous {dtype} tensor of at least {numel} "
+                         f"elements (got {t.dtype}, {tuple(t.shape)}, contiguous="
+                         f"{t.is_contiguous()})")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def superpose(S, pos, width: int, height: int, radius: int, k: float = 1.0,
+              alpha: float = -0.5, periodic: bool = False, out=None, stream=None):
+    """sf_superpose: P = fl32(S + sum of the strengths of the sources at `pos`)
+    for device tensors S (float64, width*height) and pos (int32; entries
+    outside the grid are skipped).  Returns `out` (float32, width*height, made
+    on S's device when None).  Enqueued on `stream` (default: torch's current
+    stream of S's device); does not block."""
+    import torch
+
+    n_su = width * height
+    if out is None:
+        out = torch.empty(n_su, dtype=torch.float32, device=S.device)
+    s_ptr = _device_tensor(S, torch.float64, n_su, "S")
+    p_ptr = _device_tensor(out, torch.float32, n_su, "out")
+    n = int(pos.numel())
+    pos_ptr = _device_tensor(pos, torch.int32, n, "pos") if n else None
+    for t in (pos, out):
+        if t.device != S.device:
+            raise ValueError("S, pos and out must be on one device")
+    with torch.cuda.device(S.device):
+        st = stream if stream is not None else torch.cuda.current_stream(S.device)
+        _check(load().sf_superpose(width, height, int(bool(periodic)), radius, float(k),
+                                   float(alpha), s_ptr, pos_ptr, n, p_ptr,
+                                   ctypes.c_void_p(st.cuda_stream)))
+    return out
 
 
 def _check(rc: int):
@@ -326,6 +371,17 @@ class GpuScene:
         """0/1: full superposition every tick; K >= 2: incremental update with
         a full superposition every K ticks."""
         _check(load().sf_set_field_update(self._h, int(refresh_ticks)))
+
+    def set_field_sect(self, K: int, image: bool = False):
+        """The paper's sect path with K in {2, 4, 8, 16} FP32 slots (0: the
+        exact gather); image: keep the 8 sect planes."""
+        _check(load().sf_set_field_sect(self._h, int(K), 1 if image else 0))
+
+    def sect_image(self):
+        """The 8 sect planes (float32 [8, H*W]) of the sect path."""
+        a = np.empty((8, self.width * self.height), dtype=np.float32)
+        _check(load().sf_sect_image(self._h, _ptr(a), 0))
+        return a
 
     def refresh_field(self, n_times: int = 1):
         """Superpose the field of the current positions again, n_times times

@@ -129,7 +129,8 @@ def test_room_beyond_2_28_su(sf):
     alone = np.array([not np.any((np.abs(qx - x) <= R) & (np.abs(qy - y) <= R))
                       for x, y in zip(xs, ys)])
     assert alone.sum() > 5000
-    assert np.array_equal(P[idx[alone]], S[idx[alone]])
+    # no pedestrian within R: Phi = 0 and P is S (FP64) rounded once
+    assert np.array_equal(P[idx[alone]], S[idx[alone]].astype(np.float32))
     assert D[W - 1 + (y0 + 3) * W] == 0 and D[(H - 1) * W + W // 2] == -1
     live = after[after >= 0]
     assert np.all(after >= -1) and np.all(live < W * H) and np.unique(live).size == live.size
