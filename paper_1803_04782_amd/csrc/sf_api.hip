@@ -73,8 +73,13 @@ struct sf_scene {
     int wpr = 0;          // 64-bit words per bitmap row
     ListCfg lc;           // pedestrian field launch shape
     float phi_axial = 0.f, phi_diag = 0.f;
-    // device state: S = w_dest*D + O (FP64), P = fl32(S + Phi), the stamp
+    // device state: S = w_dest*D + O (FP64), P = fl32(S + Phi), the stamp as
+    // doubles and (laws that allow 32-bit sums, see law_units) as integers in
+    // units of q
     double *S = nullptr, *tab = nullptr;
+    int32_t *tabi = nullptr;
+    double q_unit = 1.0;
+    bool int_ok = false;
     float *P = nullptr;
     int32_t *D = nullptr;
     uint8_t *exitm = nullptr;
@@ -245,6 +250,45 @@ int upload_table(double *dst, const std::vector<double> &t, hipStream_t st)
     return SF_OK;
 }
 
+// The gather's integer form of a law (sf::ListCfg elem = 4): every FP32
+// strength of the window is an integer multiple of q = 2^(e_min - 23), e_min
+// the exponent of the smallest nonzero |strength| (the same q as check_law),
+// and the kernel sums 8 of them in a 32-bit integer before moving the sum into
+// FP64, which needs 8 * max|strength| / q < 2^31.
+struct LawUnits {
+    double q = 1.0;
+    bool int_ok = true;
+};
+
+LawUnits law_units(int R, double k, double alpha)
+{
+    double tmin = 0.0, tmax = 0.0;
+    for (int dy = -R; dy <= R; ++dy)
+        for (int dx = -R; dx <= R; ++dx) {
+            if (dx == 0 && dy == 0) continue;
+            const double dist = std::sqrt((double)dx * dx + (double)dy * dy);
+            const double a = std::fabs((double)(float)(k * std::pow(dist, alpha)));
+            if (a == 0.0) continue;
+            tmin = tmin == 0.0 || a < tmin ? a : tmin;
+            tmax = a > tmax ? a : tmax;
+        }
+    LawUnits u;
+    if (tmax == 0.0) return u;
+    int e;
+    (void)std::frexp(tmin, &e);
+    u.q = std::ldexp(1.0, std::max(e - 1 - 23, -149));
+    u.int_ok = 8.0 * (tmax / u.q) < 2147483648.0;
+    return u;
+}
+
+// The stamp of stamp_table in units of q (exact integers).
+std::vector<int32_t> stamp_table_int(const std::vector<double> &t, double q)
+{
+    std::vector<int32_t> r(t.size());
+    for (size_t i = 0; i < t.size(); ++i) r[i] = (int32_t)(t[i] / q);
+    return r;
+}
+
 // The superposition adds FP32 strengths in FP64.  Every term of a window is
 // an integer multiple of q = 2^(e_min - 23), e_min the exponent of the
 // smallest nonzero |strength|, and every partial sum of one su's terms (each
@@ -287,7 +331,8 @@ int field_blocks_per_cu(const ListCfg &lc)
 {
     int per_cu = (int)std::max<size_t>(1, (size_t)(160 * 1024) / lc.lds_bytes);
     per_cu = std::min(per_cu, std::max(1, 32 / lc.nw));
-    const int resident = sf::field_resident_blocks(lc.tw, lc.hl, lc.nw, lc.lds_bytes, false);
+    const int resident =
+        sf::field_resident_blocks(lc.tw, lc.hl, lc.nw, lc.lds_bytes, false, lc.elem);
     if (resident > 0) per_cu = std::min(per_cu, resident);
     return per_cu;
 }
@@ -695,7 +740,15 @@ int create(const sf_scene_desc *d, void *hip_stream, sf_scene **out)
     int max_lds = 0;
     SF_HIP(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, s->device),
            "LDS size");
-    s->lc = sf::pick_list_cfg(s->R, (size_t)max_lds - 1024);
+    {
+        const LawUnits u = law_units(s->R, s->k, s->alpha);
+        s->q_unit = u.q;
+        s->int_ok = u.int_ok;
+        if (const char *e = std::getenv("SF_FIELD_INT"))
+            if (std::atoi(e) == 0) s->int_ok = false;  // speed only: the same field
+    }
+    const int elem = s->int_ok ? 4 : 8;
+    s->lc = sf::pick_list_cfg(s->R, (size_t)max_lds - 1024, elem);
     if (const char *e = std::getenv("SF_TILE")) {
         // launch-shape override "TWxHLxVECxNW[xCAP]"; the field does not
         // depend on it bit for bit, the speed does
@@ -705,7 +758,7 @@ int create(const sf_scene_desc *d, void *hip_stream, sf_scene **out)
             return fail(SF_EINVAL, "SF_TILE=%s is not of the form TWxHLxVECxNW[xCAP]", e);
         if (v != 2 || !sf::list_shape_compiled(a, b, w) || cap < 1 || cap > (1 << 16))
             return fail(SF_EINVAL, "SF_TILE=%s is not a compiled shape", e);
-        s->lc = sf::make_list_cfg(s->R, a, b, w, cap);
+        s->lc = sf::make_list_cfg(s->R, a, b, w, cap, elem);
         if (s->lc.halo_rows > 64 * w)
             return fail(SF_EINVAL, "SF_TILE=%s does not fit radius %d", e, s->R);
     }
@@ -733,6 +786,7 @@ int create(const sf_scene_desc *d, void *hip_stream, sf_scene **out)
     if ((rc = dalloc(s, &s->S, n, "S")) || (rc = dalloc(s, &s->P, n, "P")) ||
         (rc = dalloc(s, &s->D, n, "D")) || (rc = dalloc(s, &s->exitm, n, "exit mask")) ||
         (rc = dalloc(s, &s->tab, (size_t)s->lc.tab_elems, "phi table")) ||
+        (s->int_ok && (rc = dalloc(s, &s->tabi, (size_t)s->lc.tab_elems, "phi table"))) ||
         (rc = dalloc(s, &s->occ, (size_t)s->wpr * s->H, "occupancy")) ||
         (rc = dalloc(s, &s->claim, n, "claims")) || (rc = dalloc(s, &s->key, N, "keys")) ||
         (rc = dalloc(s, &s->regs, n, "registrations")) ||
@@ -761,6 +815,13 @@ int create(const sf_scene_desc *d, void *hip_stream, sf_scene **out)
         const std::vector<double> t = stamp_table(s->R, s->k, s->alpha, c.ncols, c.nrows,
                                                   c.stride, c.padx, c.pady, (size_t)c.tab_elems);
         if ((rc = upload_table(s->tab, t, st))) return rc;
+        if (s->tabi) {
+            const std::vector<int32_t> ti = stamp_table_int(t, s->q_unit);
+            SF_HIP(hipMemcpyAsync(s->tabi, ti.data(), ti.size() * sizeof(int32_t),
+                                  hipMemcpyHostToDevice, st),
+                   "copy stamp");
+            SF_HIP(hipStreamSynchronize(st), "stamp sync");
+        }
         // own-field values at axial and diagonal neighbours (FP32 numbers)
         const size_t ia = (size_t)(c.padx + 1) * c.stride + c.pady;
         s->phi_axial = (float)t[ia];
@@ -814,7 +875,7 @@ int setup_launches(sf_scene *s)
     v.bb = (s->bh - 1) / 2;
     v.bodies = s->bodies;
     v.obits = s->obits;
-    sf::set_view_layout(v, s->lc, s->tab);
+    sf::set_view_layout(v, s->lc, s->tab, s->tabi, s->q_unit);
     s->fl = sf::field_launch_for(s->lc);
     // one strip per item: workgroup b takes strips b, b + grid, ...
     s->strips_per_block = 1;
@@ -1046,11 +1107,11 @@ int split_members(const sf_batch *b, sf_batch_tiling *t, std::vector<int> (&memb
 
 // Fill in the defaults of group tiling `t` and check it against the group's
 // largest radius R; `lc` receives the launch shape at that radius.
-int resolve_group_tiling(const sf_batch *b, int R, sf_group_tiling *t, ListCfg *lc)
+int resolve_group_tiling(const sf_batch *b, int R, int elem, sf_group_tiling *t, ListCfg *lc)
 {
     const size_t lds_cap = b->max_lds - 1024;
     if (t->tw == 0 && t->hl == 0 && t->vec == 0 && t->nw == 0) {
-        const ListCfg d = sf::pick_list_cfg(R, lds_cap);
+        const ListCfg d = sf::pick_list_cfg(R, lds_cap, elem);
         t->tw = d.tw;
         t->hl = d.hl;
         t->nw = d.nw;
@@ -1062,7 +1123,7 @@ int resolve_group_tiling(const sf_batch *b, int R, sf_group_tiling *t, ListCfg *
                     t->nw);
     if (t->list_cap == 0) {
         for (int cap = 4096; cap >= 512; cap /= 2) {
-            const ListCfg c = sf::make_list_cfg(R, t->tw, t->hl, t->nw, cap);
+            const ListCfg c = sf::make_list_cfg(R, t->tw, t->hl, t->nw, cap, elem);
             if (c.lds_bytes <= lds_cap) {
                 t->list_cap = cap;
                 break;
@@ -1071,12 +1132,13 @@ int resolve_group_tiling(const sf_batch *b, int R, sf_group_tiling *t, ListCfg *
     }
     if (t->list_cap < 0 || t->list_cap > (1 << 16))
         return fail(SF_EINVAL, "list_cap %d outside 0..65536", t->list_cap);
-    const ListCfg c = sf::make_list_cfg(R, t->tw, t->hl, t->nw, t->list_cap);
+    const ListCfg c = sf::make_list_cfg(R, t->tw, t->hl, t->nw, t->list_cap, elem);
     if (c.list_cap < 2 * c.max_row || c.halo_rows > 64 * t->nw || c.lds_bytes > lds_cap)
         return fail(SF_EINVAL, "tiling %dx%dx%dx%d with list_cap %d does not fit radius %d",
                     t->tw, t->hl, t->vec, t->nw, t->list_cap, R);
     int bpc_max = std::max(1, std::min((int)((160 * 1024) / c.lds_bytes), 32 / t->nw));
-    const int resident = sf::field_resident_blocks(t->tw, t->hl, t->nw, c.lds_bytes, true);
+    const int resident =
+        sf::field_resident_blocks(t->tw, t->hl, t->nw, c.lds_bytes, true, elem);
     if (resident > 0) bpc_max = std::min(bpc_max, resident);  // no partial second round
     if (t->blocks_per_cu == 0) t->blocks_per_cu = bpc_max;
     if (t->blocks_per_cu < 1 || t->blocks_per_cu > 64)
@@ -1102,11 +1164,16 @@ int build_group(sf_batch *b, const std::vector<int> &members, const sf_group_til
         }
     } guard{&G};
     int R = 0;
-    for (int j : members) R = std::max(R, b->scenes[(size_t)j]->R);
+    bool int_ok = true;  // one launch: integer sums only if every member's law allows them
+    for (int j : members) {
+        R = std::max(R, b->scenes[(size_t)j]->R);
+        int_ok = int_ok && b->scenes[(size_t)j]->int_ok;
+    }
+    const int elem = int_ok ? 4 : 8;
     G.t = req;
     G.members = members;
     ListCfg lmax;
-    int rc = resolve_group_tiling(b, R, &G.t, &lmax);
+    int rc = resolve_group_tiling(b, R, elem, &G.t, &lmax);
     if (rc) return rc;
     const sf_group_tiling &t = G.t;
     G.fl = sf::field_launch_for(lmax);
@@ -1116,24 +1183,40 @@ int build_group(sf_batch *b, const std::vector<int> &members, const sf_group_til
     const int n = (int)members.size();
     std::vector<SceneView> gv((size_t)n);
     std::vector<double> strip_cost((size_t)n);
-    std::map<std::tuple<int, double, double>, double *> tables;
+    std::map<std::tuple<int, double, double>, void *> tables;
     int64_t dec_total = 0, com_total = 0;
     for (int q = 0; q < n; ++q) {
         const sf_scene *s = b->scenes[(size_t)members[(size_t)q]];
-        const ListCfg lc = sf::make_list_cfg(s->R, t.tw, t.hl, t.nw, t.list_cap);
+        const ListCfg lc = sf::make_list_cfg(s->R, t.tw, t.hl, t.nw, t.list_cap, elem);
         const auto key = std::make_tuple(s->R, s->k, s->alpha);
-        double *&tab = tables[key];
+        void *&tab = tables[key];
         if (!tab) {
-            if ((rc = balloc(G.bufs, &tab, (size_t)lc.tab_elems, "batch phi table"))) return rc;
-            if ((rc = upload_table(tab,
-                                   stamp_table(s->R, s->k, s->alpha, lc.ncols, lc.nrows,
-                                               lc.stride, lc.padx, lc.pady,
-                                               (size_t)lc.tab_elems),
-                                   st)))
-                return rc;
+            const std::vector<double> td = stamp_table(s->R, s->k, s->alpha, lc.ncols, lc.nrows,
+                                                       lc.stride, lc.padx, lc.pady,
+                                                       (size_t)lc.tab_elems);
+            if (elem == 4) {
+                int32_t *ti = nullptr;
+                if ((rc = balloc(G.bufs, &ti, (size_t)lc.tab_elems, "batch phi table")))
+                    return rc;
+                const std::vector<int32_t> h = stamp_table_int(td, s->q_unit);
+                SF_HIP(hipMemcpyAsync(ti, h.data(), h.size() * sizeof(int32_t),
+                                      hipMemcpyHostToDevice, st),
+                       "copy stamp");
+                SF_HIP(hipStreamSynchronize(st), "stamp sync");
+                tab = ti;
+            } else {
+                double *t64 = nullptr;
+                if ((rc = balloc(G.bufs, &t64, (size_t)lc.tab_elems, "batch phi table")))
+                    return rc;
+                if ((rc = upload_table(t64, td, st))) return rc;
+                tab = t64;
+            }
         }
         SceneView v = s->view;
-        sf::set_view_layout(v, lc, tab);
+        if (elem == 4)
+            sf::set_view_layout(v, lc, nullptr, static_cast<const int32_t *>(tab), s->q_unit);
+        else
+            sf::set_view_layout(v, lc, static_cast<const double *>(tab), nullptr, 1.0);
         v.dec_block0 = (int32_t)dec_total;
         v.com_block0 = (int32_t)com_total;
         dec_total += sf::decide_blocks(s->N);
@@ -1471,7 +1554,8 @@ struct SuperposeCall {
     hipStream_t stream = nullptr;
     ListCfg lc;
     size_t lds_limit = 0;
-    size_t bitmap_words = 0, tab_doubles = 0;
+    size_t bitmap_words = 0, tab_bytes = 0;
+    double q = 1.0;  // unit of an integer stamp (lc.elem == 4)
 };
 
 int superpose_prepare(int32_t W, int32_t H, int32_t periodic, int32_t R, double k, double alpha,
@@ -1501,7 +1585,9 @@ int superpose_prepare(int32_t W, int32_t H, int32_t periodic, int32_t R, double 
     SF_HIP(hipGetDevice(&dev), "hipGetDevice");
     SF_HIP(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev),
            "LDS size");
-    c->lc = sf::pick_list_cfg(R, (size_t)max_lds - 1024);
+    const LawUnits u = law_units(R, k, alpha);
+    c->q = u.q;
+    c->lc = sf::pick_list_cfg(R, (size_t)max_lds - 1024, u.int_ok ? 4 : 8);
     if (c->lc.lds_bytes == 0 || c->lc.lds_bytes > (size_t)max_lds - 1024 ||
         c->lc.list_cap < 2 * c->lc.max_row)
         return fail(SF_EINVAL, "field of radius %d does not fit %d B of LDS", R, max_lds);
@@ -1522,13 +1608,13 @@ int superpose_prepare(int32_t W, int32_t H, int32_t periodic, int32_t R, double 
     c->stream = static_cast<hipStream_t>(hip_stream);
     c->wpr = (W + 63) / 64;
     c->bitmap_words = (size_t)c->wpr * H;
-    c->tab_doubles = (size_t)c->lc.tab_elems;
+    c->tab_bytes = (size_t)c->lc.tab_elems * c->lc.elem;
     return SF_OK;
 }
 
 // Enqueues the superposition of `c` on its stream with the given scratch:
 // clear the bitmap, mark the positions, fill the stamp, gather.
-int superpose_enqueue(const SuperposeCall &c, unsigned long long *bits, double *tab)
+int superpose_enqueue(const SuperposeCall &c, unsigned long long *bits, void *tab)
 {
     const int R = c.R;
     float oct[(SF_MAX_RADIUS + 1) * (SF_MAX_RADIUS + 2) / 2];
@@ -1542,8 +1628,8 @@ int superpose_enqueue(const SuperposeCall &c, unsigned long long *bits, double *
     SF_HIP(sf::set_field_lds_limit(c.lds_limit), "LDS limit");
     SF_HIP(sf::launch_fill_u64(bits, c.bitmap_words, 0ull, c.stream), "clear bitmap");
     SF_HIP(sf::launch_occ_mark(c.pos, c.n, bits, c.wpr, c.W, c.W * c.H, c.stream), "mark");
-    SF_HIP(sf::launch_stamp_fill(tab, c.lc.tab_elems, c.lc.ncols, c.lc.stride, c.lc.padx,
-                                 c.lc.pady, R, oct, c.stream),
+    SF_HIP(sf::launch_stamp_fill(tab, c.lc.elem, c.q, c.lc.tab_elems, c.lc.ncols, c.lc.stride,
+                                 c.lc.padx, c.lc.pady, R, oct, c.stream),
            "stamp");
     SceneView v{};
     v.W = c.W;
@@ -1554,7 +1640,10 @@ int superpose_enqueue(const SuperposeCall &c, unsigned long long *bits, double *
     v.P = c.P;
     v.occ = bits;
     v.periodic = c.periodic;
-    sf::set_view_layout(v, c.lc, tab);
+    if (c.lc.elem == 4)
+        sf::set_view_layout(v, c.lc, nullptr, static_cast<const int32_t *>(tab), c.q);
+    else
+        sf::set_view_layout(v, c.lc, static_cast<const double *>(tab), nullptr, 1.0);
     SF_HIP(sf::launch_field_one(sf::field_launch_for(c.lc), v, 1, c.stream), "superpose");
     return SF_OK;
 }
@@ -1931,12 +2020,12 @@ int sf_superpose(int32_t width, int32_t height, int32_t periodic, int32_t radius
     if (rc) return rc;
     void *bits = nullptr, *tab = nullptr;
     SF_HIP(hipMallocAsync(&bits, c.bitmap_words * 8, c.stream), "bitmap");
-    hipError_t e = hipMallocAsync(&tab, c.tab_doubles * 8, c.stream);
+    hipError_t e = hipMallocAsync(&tab, c.tab_bytes, c.stream);
     if (e != hipSuccess) {
         (void)hipFreeAsync(bits, c.stream);
         return hip_fail(e, "stamp table");
     }
-    rc = superpose_enqueue(c, static_cast<unsigned long long *>(bits), static_cast<double *>(tab));
+    rc = superpose_enqueue(c, static_cast<unsigned long long *>(bits), tab);
     // freed in stream order, after the launches that use them
     const hipError_t e1 = hipFreeAsync(tab, c.stream);
     const hipError_t e2 = hipFreeAsync(bits, c.stream);

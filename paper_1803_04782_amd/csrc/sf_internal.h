@@ -63,11 +63,15 @@ SupCfg make_sup_cfg(int radius, int tw, int hl, size_t elem);
 // rows [w*TH, (w+1)*TH).  Lane l owns column l % TW and, with rg = l / TW and
 // G = 64 / TW, the HL rows rg + G*r (r < HL), so its entries of a source's
 // stamp column are G apart and each pair is one 8-byte-aligned LDS read.
-// The stamp is held once, column-major, as doubles (FP32 strengths):
+// The stamp is held once, column-major: as integers in units of the law's
+// q = 2^(e_min - 23) (elem = 4 bytes; the FP32 strengths are integer
+// multiples of q) or as doubles (elem = 8, laws whose strengths span too many
+// binades for 32-bit sums of 8 of them):
 //   entry (dx, dy) at (dx + padx)*stride + dy + pady,
 //   padx = R + TW (one zero column beyond the halo), pady = R + TH - 1,
-//   stride >= 2*pady + 1, chosen so that the 32 lanes of each half-wave read
-//   32 distinct bank pairs.
+//   stride >= 2*pady + 1, chosen so that each pass of a read hits distinct
+//   banks (16 lanes and index mod 16 for doubles, 32 lanes and mod 32 for
+//   integers).
 // The strip's halo sources are listed in LDS in row-major order; the list
 // holds `list_cap` entries and longer halos are processed in several passes.
 struct ListCfg {
@@ -75,16 +79,17 @@ struct ListCfg {
     int g = 0, th = 0, wt = 0;
     int radius = 0;
     int padx = 0, pady = 0, ncols = 0, nrows = 0, stride = 0;
-    int tab_elems = 0;   // ncols * stride rounded up to an even count of doubles
+    int elem = 8;        // bytes per stamp entry: 4 (integers) or 8 (doubles)
+    int tab_elems = 0;   // ncols * stride rounded up to whole 16-byte vectors
     int list_cap = 0;
     int max_row = 0;     // most sources one halo row can hold
     int halo_rows = 0;   // most halo rows of one strip
     size_t lds_bytes = 0;
     int grid = 0;
 };
-ListCfg make_list_cfg(int radius, int tw, int hl, int nw, int list_cap);
+ListCfg make_list_cfg(int radius, int tw, int hl, int nw, int list_cap, int elem);
 // Picks the launch shape for radius R that fits `max_lds` bytes of LDS.
-ListCfg pick_list_cfg(int radius, size_t max_lds);
+ListCfg pick_list_cfg(int radius, size_t max_lds, int elem);
 bool list_shape_compiled(int tw, int hl, int nw);
 // Dynamic LDS limit of the field kernels.
 hipError_t set_field_lds_limit(size_t bytes);
@@ -101,7 +106,9 @@ struct SceneView {
     int32_t padx, pady, max_row, tab_elems;
     float phi_axial, phi_diag;  // own-field values at axial / diagonal neighbours
     unsigned long long seed;
-    const double *tab;          // tab_elems doubles: the stamp (FP32 strengths)
+    const double *tab;          // the stamp as doubles (FP32 strengths), or NULL
+    const int32_t *tabi;        // the stamp as integers in units of q, or NULL
+    double q;                   // the unit of tabi
     const double *S;            // static field w_dest*D + O (FP64, +inf on obstacles)
     float *P;                   // total field fl32(S + Phi)
     // exact pedestrian field Phi (FP64), kept while the incremental update is
@@ -139,8 +146,10 @@ struct SceneView {
     const unsigned long long *obits;
 };
 
-// Field layout fields of `v` for shape `c` (built for the scene's radius).
-void set_view_layout(SceneView &v, const ListCfg &c, const double *tab);
+// Field layout fields of `v` for shape `c` (built for the scene's radius):
+// the gather reads tabi (unit q) when c.elem == 4, else tab.
+void set_view_layout(SceneView &v, const ListCfg &c, const double *tab, const int32_t *tabi,
+                     double q);
 
 // Workgroups of a scene in the decide launches and in a batch's commit launch.
 int decide_blocks(int N);
@@ -153,6 +162,7 @@ int commit_blocks(int N);
 // the largest halo row count; both size the dynamic LDS.
 struct FieldLaunch {
     int tw = 0, hl = 0, nw = 0;
+    int elem = 8;  // stamp entry bytes: 4 = integer sums, 8 = FP64 sums
     int list_cap = 0, tab_max = 0, halo_max = 0;
     int grid = 0;
     size_t lds_bytes = 0;
@@ -160,7 +170,7 @@ struct FieldLaunch {
 FieldLaunch field_launch_for(const ListCfg &c);  // tab_max/halo_max of c, grid = c.grid
 // Workgroups of the field kernel of this shape that one compute unit holds at
 // once with `lds_bytes` of dynamic LDS (registers and LDS; 0 if unknown).
-int field_resident_blocks(int tw, int hl, int nw, size_t lds_bytes, bool multi);
+int field_resident_blocks(int tw, int hl, int nw, size_t lds_bytes, bool multi, int elem);
 size_t field_lds_bytes(const FieldLaunch &f);
 hipError_t launch_field(const FieldLaunch &f, const SceneView *views, const int32_t *items,
                         int n_items, hipStream_t st, const LaunchEvents *ev = nullptr);
@@ -240,13 +250,14 @@ hipError_t launch_static_S(const int32_t *D, const double *O, const uint8_t *obs
 hipError_t launch_occ_init(const int32_t *pos, int N, unsigned long long *occ, int wpr, int W,
                            unsigned long long *ctr, hipStream_t st);
 // Stateless superposition: bitmap bits of the entries 0 <= pos[i] < nsu (the
-// bitmap must be cleared first), and the gather's stamp table (n doubles of
-// the layout of a ListCfg) from the law's strengths over one octant of the
-// window, oct[i(i+1)/2 + j] for 0 <= j <= i <= R.
+// bitmap must be cleared first), and the gather's stamp table (n entries of
+// the layout of a ListCfg: doubles, elem = 8, or integers in units of q,
+// elem = 4) from the law's strengths over one octant of the window,
+// oct[i(i+1)/2 + j] for 0 <= j <= i <= R.
 hipError_t launch_occ_mark(const int32_t *pos, int n, unsigned long long *occ, int wpr, int W,
                            int nsu, hipStream_t st);
-hipError_t launch_stamp_fill(double *tab, int n, int ncols, int stride, int padx, int pady, int R,
-                             const float *oct, hipStream_t st);
+hipError_t launch_stamp_fill(void *tab, int elem, double q, int n, int ncols, int stride,
+                             int padx, int pady, int R, const float *oct, hipStream_t st);
 // Decide + claim over `n_blocks` workgroups, decide_blocks(N) per scene.
 // `block_scene[b]` names the scene of workgroup b (NULL: every workgroup
 // belongs to views[0]).

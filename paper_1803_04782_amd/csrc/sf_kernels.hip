@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <cmath>
 #include <cstdint>
 
@@ -499,12 +500,12 @@ __device__ __forceinline__ int lower_bound_lds(const int *a, int n, int v)
 
 // The HL stamp entries of one source for this lane (LDS byte address a, rows
 // G apart) added to acc.
-template <int HL, int G>
-__device__ __forceinline__ void gather_one(double *acc, uint32_t a)
+template <int HL, int G, typename T>
+__device__ __forceinline__ void gather_one(T *acc, uint32_t a)
 {
-    typedef const __attribute__((address_space(3))) double *ptr;
+    typedef const __attribute__((address_space(3))) T *ptr;
     const ptr s = reinterpret_cast<ptr>(a);
-    double v[HL];
+    T v[HL];
 #pragma unroll
     for (int r = 0; r < HL; ++r) v[r] = s[G * r];
 #pragma unroll
@@ -514,8 +515,10 @@ __device__ __forceinline__ void gather_one(double *acc, uint32_t a)
 // The part of a scene's view that the field kernel reads, kept in scalar
 // registers (a whole SceneView copy would be placed in private memory).
 struct FieldScene {
-    int W, H, wpr, R, tiles_x, stride, padx, pady, max_row, tab_elems, periodic;
-    gptr<const f64x2> tab;  // tab_elems (even) doubles, loaded as 16-byte vectors
+    int W, H, wpr, R, tiles_x, stride, padx, pady, max_row, tab_vecs, periodic;
+    // the stamp (doubles, or integers in units of q), tab_vecs 16-byte vectors
+    gptr<const f64x2> tab;
+    double q;
     gptr<const double> S;
     gptr<float> P;
     gptr<double> phi;       // exact pedestrian field, kept for the update path (or NULL)
@@ -523,6 +526,7 @@ struct FieldScene {
     gptr<const unsigned long long> occ2;  // second source bitmap (update launches)
 };
 
+template <bool INT>
 __device__ __forceinline__ FieldScene field_scene(const SceneView &v)
 {
     FieldScene f;
@@ -535,9 +539,11 @@ __device__ __forceinline__ FieldScene field_scene(const SceneView &v)
     f.padx = v.padx;
     f.pady = v.pady;
     f.max_row = v.max_row;
-    f.tab_elems = v.tab_elems;
+    f.tab_vecs = INT ? v.tab_elems / 4 : v.tab_elems / 2;
     f.periodic = v.periodic;
-    f.tab = to_global(reinterpret_cast<const f64x2 *>(v.tab));
+    f.tab = to_global(INT ? reinterpret_cast<const f64x2 *>(v.tabi)
+                          : reinterpret_cast<const f64x2 *>(v.tab));
+    f.q = v.q;
     f.S = to_global(v.S);
     f.P = to_global(v.P);
     f.phi = to_global(v.phi);
@@ -574,7 +580,7 @@ __device__ __forceinline__ unsigned long long wrapped_word(gptr<const unsigned l
 // Work items of a field launch.  MULTI: items[i] from the table and the
 // scene views from `views`; otherwise the single scene `one` (a kernel
 // argument, no dependent load) and item i = strips [i*per, (i+1)*per).
-template <bool MULTI>
+template <bool MULTI, bool INT>
 struct FieldWork {
     const SceneView &one;
     const SceneView *__restrict__ views;
@@ -587,8 +593,8 @@ struct FieldWork {
     }
     __device__ __forceinline__ FieldScene scene(int j) const
     {
-        if constexpr (MULTI) return field_scene(views[j]);
-        return field_scene(one);
+        if constexpr (MULTI) return field_scene<INT>(views[j]);
+        return field_scene<INT>(one);
     }
 };
 
@@ -596,7 +602,13 @@ struct FieldWork {
 // su entered this tick, occ2 = the su left; Phi := (Phi + Phi(occ)) -
 // Phi(occ2) in place (exact), P = fl32(S + Phi).  Each bitmap gets its own
 // scan, list and gather into its own accumulators.
-template <int TW, int HL, int NW, bool MULTI, bool DUAL = false>
+// INT: the stamp holds each strength as an integer multiple of the law's
+// q = 2^(e_min - 23) (4 bytes, half the LDS traffic of a double), summed in
+// 32-bit integers that are moved into FP64 accumulators every 8 sources
+// (8 * max|strength| / q < 2^31 for such laws, so no partial sum overflows);
+// Phi = q * sum, the same exact value, rounded once.  Otherwise the stamp
+// holds doubles summed in FP64.
+template <int TW, int HL, int NW, bool MULTI, bool DUAL = false, bool INT = false>
 __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
                                                    const SceneView *__restrict__ views,
                                                    const int4 *__restrict__ items, int n_items,
@@ -604,18 +616,20 @@ __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
 {
     static_assert(!(DUAL && MULTI), "the update launch covers one scene");
     constexpr int NSRC = DUAL ? 2 : 1;
-    const FieldWork<MULTI> work{one, views, items, per};
+    using T = std::conditional_t<INT, int, double>;  // a stamp entry
+    constexpr uint32_t ES = sizeof(T);
+    const FieldWork<MULTI, INT> work{one, views, items, per};
     constexpr int G = 64 / TW, TH = G * HL, WT = NW * TH, NT = NW * 64;
     extern __shared__ __align__(16) unsigned char lds_raw[];
     __shared__ int wave_tot[NW];
-    double *tab = reinterpret_cast<double *>(lds_raw);
+    T *tab = reinterpret_cast<T *>(lds_raw);
     int *list = reinterpret_cast<int *>(tab + tab_max);
     int *row_excl = list + list_cap;
 
     const int tid = (int)threadIdx.x, lane = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int col = lane % TW, rg = lane / TW;
-    const uint32_t tbase = (uint32_t)(uintptr_t)((lds_ptr<double>)tab);
+    const uint32_t tbase = (uint32_t)(uintptr_t)((lds_ptr<T>)tab);
 
     // Work items of one scene by XCD: workgroup b runs on XCD b mod 8 (each
     // XCD has its own L2).  XCD x owns a contiguous share of the strips, in
@@ -642,12 +656,12 @@ __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
     // a wait.
     f64x2 *const tab2 = reinterpret_cast<f64x2 *>(tab);
     auto table_load = [&](const FieldScene &s, int i0, f64x2(&r)[8]) {
-        const int n2 = s.tab_elems / 2;
+        const int n2 = s.tab_vecs;
 #pragma unroll
         for (int u = 0; u < 8; ++u) r[u] = s.tab[min(i0 + u * NT + tid, n2 - 1)];
     };
     auto table_store = [&](const FieldScene &s, int i0, const f64x2(&r)[8]) {
-        const int n2 = s.tab_elems / 2;
+        const int n2 = s.tab_vecs;
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const int i = i0 + u * NT + tid;
@@ -655,7 +669,7 @@ __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
         }
     };
     auto load_table = [&](const FieldScene &s) {
-        for (int i0 = 0; i0 < s.tab_elems / 2; i0 += 8 * NT) {
+        for (int i0 = 0; i0 < s.tab_vecs; i0 += 8 * NT) {
             f64x2 r[8];
             table_load(s, i0, r);
             table_store(s, i0, r);
@@ -726,7 +740,7 @@ __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
         fetch_rows(v, t);
         table_load(v, 0, r);
         table_store(v, 0, r);
-        for (int i0 = 8 * NT; i0 < v.tab_elems / 2; i0 += 8 * NT) {
+        for (int i0 = 8 * NT; i0 < v.tab_vecs; i0 += 8 * NT) {
             table_load(v, i0, r);
             table_store(v, i0, r);
         }
@@ -799,16 +813,30 @@ __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
         const int ra = max(y0w - R, ya) - ya;
         const int rb = min(y0w + TH - 1 + R, yb) - ya;
         const uint32_t lb = (uint32_t)opaque_lane(
-            (int)(tbase + (uint32_t)((X0 + col + padx) * stride + (y0w + rg + pady)) * 8u));
-        double accs[NSRC][HL];
+            (int)(tbase + (uint32_t)((X0 + col + padx) * stride + (y0w + rg + pady)) * ES));
+        // accs: the running sums (INT: 32-bit, moved into sums64 by flush())
+        T accs[NSRC][HL];
+        double sums64[NSRC][HL];
 #pragma unroll
         for (int src = 0; src < NSRC; ++src)
 #pragma unroll
-            for (int r = 0; r < HL; ++r) accs[src][r] = 0.0;
+            for (int r = 0; r < HL; ++r) {
+                accs[src][r] = 0;
+                sums64[src][r] = 0.0;
+            }
+        auto flush = [&](int src) {
+            if constexpr (INT) {
+#pragma unroll
+                for (int r = 0; r < HL; ++r) {
+                    sums64[src][r] += (double)accs[src][r];
+                    accs[src][r] = 0;
+                }
+            }
+        };
 
 #pragma unroll
         for (int src = 0; src < NSRC; ++src) {
-            double *acc = accs[src];
+            T *acc = accs[src];
             const int cnt = cnts[src];
             const unsigned long long m0 = mw[src][0], m1 = mw[src][1], m2 = mw[src][2];
             // 2. block exclusive scan of the row counts (ballots within a wave);
@@ -850,7 +878,7 @@ __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
                             const int b = __builtin_ctzll(mj);
                             mj &= mj - 1ull;
                             const uint32_t px = (uint32_t)(xw + b);
-                            list[o++] = (int)(0u - (px * (uint32_t)stride + py) * 8u);
+                            list[o++] = (int)(0u - (px * (uint32_t)stride + py) * ES);
                         }
                     }
                 }
@@ -862,8 +890,9 @@ __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
                     const int hi = __builtin_amdgcn_readfirstlane(min(row_excl[rb + 1], end) - start);
                     int i = lo;
                     for (; i < hi && (i & 3); ++i) gather_one<HL, G>(acc, lb + (uint32_t)list[i]);
+                    flush(src);
                     const int4 *list4 = reinterpret_cast<const int4 *>(list);
-                    typedef const __attribute__((address_space(3))) double *lds_d;
+                    typedef const __attribute__((address_space(3))) T *lds_d;
                     // eight sources per round: eight table reads are in flight
                     // before the adds, and the next round's entries are read
                     // behind them (reading up to eight entries past the pass stays
@@ -878,7 +907,7 @@ __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
                             // the compiler keeps this order: next entries, table
                             // reads, adds (no wait is implied by the barriers)
                             asm volatile("" ::: "memory");
-                            double u8[8][HL];
+                            T u8[8][HL];
 #pragma unroll
                             for (int u = 0; u < 8; ++u) {
                                 const lds_d sp = reinterpret_cast<lds_d>(lb + (uint32_t)a[u]);
@@ -891,12 +920,13 @@ __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
 #pragma unroll
                                 for (int r = 0; r < HL; ++r) acc[r] += u8[u][r];
                             }
+                            flush(src);
                         }
                     }
                     if (i + 4 <= hi) {
                         const int4 ea = list4[i >> 2];
                         const int a[4] = {ea.x, ea.y, ea.z, ea.w};
-                        double u4[4][HL];
+                        T u4[4][HL];
 #pragma unroll
                         for (int u = 0; u < 4; ++u) {
                             const lds_d sp = reinterpret_cast<lds_d>(lb + (uint32_t)a[u]);
@@ -911,6 +941,7 @@ __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
                         i += 4;
                     }
                     for (; i < hi; ++i) gather_one<HL, G>(acc, lb + (uint32_t)list[i]);
+                    flush(src);
                 }
                 __syncthreads();
             }
@@ -922,8 +953,11 @@ __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
 #pragma unroll
             for (int r = 0; r < HL; ++r) {
                 const int y = y0w + rg + G * r;
-                double f = accs[0][r];
-                if constexpr (DUAL) f = (pv[r] + accs[0][r]) - accs[NSRC - 1][r];
+                // the exact sums: integers times q (a power of two), or the FP64 sums
+                const double a0 = INT ? sums64[0][r] * v.q : (double)accs[0][r];
+                const double a1 = INT ? sums64[NSRC - 1][r] * v.q : (double)accs[NSRC - 1][r];
+                double f = a0;
+                if constexpr (DUAL) f = (pv[r] + a0) - a1;
                 if (y < H) {
                     const size_t c = (size_t)y * W + x;
                     if (v.phi) v.phi[c] = f;
@@ -985,25 +1019,38 @@ struct OctChunk {
     float v[kOctChunk];
 };
 
-// Stamp table of the gather (column-major, zero padded, FP32 strengths held
-// as doubles) from octant strengths: entry (dx, dy) takes the strength of
-// (max(|dx|,|dy|), min(|dx|,|dy|)) for 0 < |d|_inf <= R and 0 elsewhere.
-// A launch writes the entries whose octant index is in its chunk; the launch
-// of the first chunk also writes the zeros.
-__global__ void k_stamp_fill(double *__restrict__ tab, int n, int ncols, int stride, int padx,
-                             int pady, int R, OctChunk c)
+// Stamp table of the gather (column-major, zero padded; FP32 strengths held
+// as doubles, elem = 8, or as integers in units of q, elem = 4) from octant
+// strengths: entry (dx, dy) takes the strength of (max(|dx|,|dy|),
+// min(|dx|,|dy|)) for 0 < |d|_inf <= R and 0 elsewhere.  A launch writes the
+// entries whose octant index is in its chunk; the launch of the first chunk
+// also writes the zeros.
+__global__ void k_stamp_fill(void *__restrict__ tabv, int elem, double q, int n, int ncols,
+                             int stride, int padx, int pady, int R, OctChunk c)
 {
+    double *tab = static_cast<double *>(tabv);
+    int *tabi = static_cast<int *>(tabv);
     for (int e = (int)(blockIdx.x * blockDim.x + threadIdx.x); e < n;
          e += (int)(gridDim.x * blockDim.x)) {
         const int ci = e / stride, ri = e - ci * stride;
         const int ax = abs(ci - padx), ay = abs(ri - pady);
         const int i = max(ax, ay), j = min(ax, ay);
         if (ci >= ncols || i == 0 || i > R) {
-            if (c.first == 0) tab[e] = 0.0;
+            if (c.first == 0) {
+                if (elem == 4)
+                    tabi[e] = 0;
+                else
+                    tab[e] = 0.0;
+            }
             continue;
         }
         const int idx = i * (i + 1) / 2 + j - c.first;
-        if (idx >= 0 && idx < c.count) tab[e] = (double)c.v[idx];
+        if (idx >= 0 && idx < c.count) {
+            if (elem == 4)
+                tabi[e] = (int)((double)c.v[idx] / q);  // an exact integer
+            else
+                tab[e] = (double)c.v[idx];
+        }
     }
 }
 
@@ -2086,8 +2133,8 @@ hipError_t launch_occ_mark(const int32_t *pos, int n, unsigned long long *occ, i
     return hipGetLastError();
 }
 
-hipError_t launch_stamp_fill(double *tab, int n, int ncols, int stride, int padx, int pady, int R,
-                             const float *oct, hipStream_t st)
+hipError_t launch_stamp_fill(void *tab, int elem, double q, int n, int ncols, int stride,
+                             int padx, int pady, int R, const float *oct, hipStream_t st)
 {
     const int total = (R + 1) * (R + 2) / 2;
     for (int first = 0; first < total; first += kOctChunk) {
@@ -2097,7 +2144,7 @@ hipError_t launch_stamp_fill(double *tab, int n, int ncols, int stride, int padx
         for (int i = 0; i < c.count; ++i) c.v[i] = oct[first + i];
         for (int i = c.count; i < kOctChunk; ++i) c.v[i] = 0.f;
         hipLaunchKernelGGL(k_stamp_fill, dim3(blocks_for((size_t)n, 256, 1024)), dim3(256), 0, st,
-                           tab, n, ncols, stride, padx, pady, R, c);
+                           tab, elem, q, n, ncols, stride, padx, pady, R, c);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -2151,30 +2198,36 @@ hipError_t set_superpose_lds_limit(size_t f64_bytes)
 
 namespace {
 
-// Most lanes of one 8-byte LDS read of a source's stamp column that share a
-// bank pair: lane l (column l % tw, row group l / tw) reads the double at
-// col*stride + rg (+ a uniform offset).  The LDS serves 256 bytes per clock,
-// so 32 lanes of an 8-byte read form one pass; a pass is conflict-free when
-// their double indices are distinct modulo 32.
-int bank_degree(int tw, int stride)
+// Most lanes of one LDS read of a source's stamp column that share a bank:
+// lane l (column l % tw, row group l / tw) reads the entry at col*stride + rg
+// (+ a uniform offset).  Measured on gfx950 with a probe: ds_read2_b64 (8-byte
+// entries) serves a wave in passes of 16 consecutive lanes, conflict-free when
+// their entry indices are distinct modulo 16; ds_read2_b32 (4-byte entries) in
+// passes of 32 lanes, conflict-free when distinct modulo 32.  An n-way
+// conflict costs up to n times a conflict-free pass (16-column tiles of
+// doubles: an odd stride runs at the rate of a broadcast read, a stride of
+// 2 mod 4 takes 1.6-1.75x as long, 4 mod 8 about 2.8x, 8 mod 16 about 5.6x).
+int bank_degree(int tw, int stride, int elem)
 {
+    const int lanes = elem == 8 ? 16 : 32;
     int worst = 0;
-    for (int p = 0; p < 64; p += 32) {
+    for (int p = 0; p < 64; p += lanes) {
         int hits[32] = {0};
-        for (int l = p; l < p + 32; ++l) {
+        for (int l = p; l < p + lanes; ++l) {
             const int col = l % tw, rg = l / tw;
-            ++hits[(col * stride + rg) % 32];
+            ++hits[(col * stride + rg) % lanes];
         }
-        for (int b = 0; b < 32; ++b) worst = hits[b] > worst ? hits[b] : worst;
+        for (int b = 0; b < lanes; ++b) worst = hits[b] > worst ? hits[b] : worst;
     }
     return worst;
 }
 
 }  // namespace
 
-ListCfg make_list_cfg(int radius, int tw, int hl, int nw, int list_cap)
+ListCfg make_list_cfg(int radius, int tw, int hl, int nw, int list_cap, int elem)
 {
     ListCfg c;
+    c.elem = elem;
     c.tw = tw;
     c.hl = hl;
     c.nw = nw;
@@ -2188,7 +2241,7 @@ ListCfg make_list_cfg(int radius, int tw, int hl, int nw, int list_cap)
     c.nrows = 2 * c.pady + 1;
     int best = -1, best_deg = 1 << 30;
     for (int s = c.nrows; s < c.nrows + 64; ++s) {
-        const int d = bank_degree(tw, s);
+        const int d = bank_degree(tw, s, elem);
         if (d < best_deg) {
             best_deg = d;
             best = s;
@@ -2196,15 +2249,18 @@ ListCfg make_list_cfg(int radius, int tw, int hl, int nw, int list_cap)
         if (d == 1) break;
     }
     c.stride = best;
-    c.tab_elems = (c.ncols * c.stride + 1) & ~1;  // loaded as 16-byte vectors
+    // loaded as 16-byte vectors: 2 doubles or 4 integers each
+    const int per_vec = 16 / elem;
+    c.tab_elems = (c.ncols * c.stride + per_vec - 1) / per_vec * per_vec;
     c.max_row = tw + 2 * radius;
     c.list_cap = list_cap;
     c.halo_rows = c.wt + 2 * radius;
-    c.lds_bytes = (size_t)c.tab_elems * 8 + (size_t)list_cap * 4 + (size_t)(c.halo_rows + 1) * 4;
+    c.lds_bytes = (size_t)c.tab_elems * elem + (size_t)list_cap * 4 +
+                  (size_t)(c.halo_rows + 1) * 4;
     return c;
 }
 
-ListCfg pick_list_cfg(int radius, size_t max_lds)
+ListCfg pick_list_cfg(int radius, size_t max_lds, int elem)
 {
     // one list per workgroup strip, 16-column strips, two stamp entries per
     // 8-byte-pair LDS read and lane (conflict-free banks); two workgroups per
@@ -2214,7 +2270,7 @@ ListCfg pick_list_cfg(int radius, size_t max_lds)
     for (int i = 0; i < 2; ++i) {
         const int *sh = shapes[i];
         for (int cap = 4096; cap >= 512; cap /= 2) {
-            ListCfg t = make_list_cfg(radius, sh[0], sh[1], sh[2], cap);
+            ListCfg t = make_list_cfg(radius, sh[0], sh[1], sh[2], cap, elem);
             if (cap < 2 * t.max_row || t.halo_rows > 64 * sh[2]) break;
             if (t.lds_bytes <= max_lds / 2) return t;
             if (t.lds_bytes <= max_lds && best.lds_bytes == 0) best = t;
@@ -2223,7 +2279,8 @@ ListCfg pick_list_cfg(int radius, size_t max_lds)
     return best;
 }
 
-void set_view_layout(SceneView &v, const ListCfg &c, const double *tab)
+void set_view_layout(SceneView &v, const ListCfg &c, const double *tab, const int32_t *tabi,
+                     double q)
 {
     v.tiles_x = (v.W + c.tw - 1) / c.tw;
     v.n_strips = v.tiles_x * ((v.H + c.wt - 1) / c.wt);
@@ -2233,6 +2290,8 @@ void set_view_layout(SceneView &v, const ListCfg &c, const double *tab)
     v.max_row = c.max_row;
     v.tab_elems = c.tab_elems;
     v.tab = tab;
+    v.tabi = tabi;
+    v.q = q;
 }
 
 FieldLaunch field_launch_for(const ListCfg &c)
@@ -2245,13 +2304,14 @@ FieldLaunch field_launch_for(const ListCfg &c)
     f.tab_max = c.tab_elems;
     f.halo_max = c.halo_rows;
     f.grid = c.grid;
+    f.elem = c.elem;
     f.lds_bytes = field_lds_bytes(f);
     return f;
 }
 
 size_t field_lds_bytes(const FieldLaunch &f)
 {
-    return (size_t)f.tab_max * 8 + (size_t)f.list_cap * 4 + (size_t)(f.halo_max + 1) * 4;
+    return (size_t)f.tab_max * f.elem + (size_t)f.list_cap * 4 + (size_t)(f.halo_max + 1) * 4;
 }
 
 // Compiled shapes (strip width TW, rows per lane HL, waves per workgroup NW).
@@ -2271,18 +2331,17 @@ bool list_shape_compiled(int tw, int hl, int nw)
 hipError_t set_field_lds_limit(size_t bytes)
 {
     hipError_t e = hipSuccess;
-#define SF_SET(a, b, n)                                                                          \
-    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_field<a, b, n, false>),         \
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);          \
-    if (e != hipSuccess) return e;                                                            \
-    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_field<a, b, n, true>),          \
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);          \
-    if (e != hipSuccess) return e;                                                            \
-    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_field<a, b, n, false, true>),   \
+#define SF_SET1(...)                                                                          \
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_field<__VA_ARGS__>),             \
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);          \
     if (e != hipSuccess) return e;
+#define SF_SET(a, b, n)                                                                          \
+    SF_SET1(a, b, n, false, false, false) SF_SET1(a, b, n, true, false, false)                 \
+    SF_SET1(a, b, n, false, true, false) SF_SET1(a, b, n, false, false, true)                  \
+    SF_SET1(a, b, n, true, false, true) SF_SET1(a, b, n, false, true, true)
     SF_LIST_SHAPES(SF_SET)
 #undef SF_SET
+#undef SF_SET1
     return hipSuccess;
 }
 
@@ -2294,25 +2353,33 @@ hipError_t launch_field(const FieldLaunch &f, const SceneView *views, const int3
     const SceneView none = {};
 #define SF_DISPATCH(a, b, n)                                                                      \
     if (f.tw == a && f.hl == b && f.nw == n)                                                    \
-        return launch(k_field<a, b, n, true>, dim3(grid), dim3(n * 64), f.lds_bytes, st, ev,     \
-                      none, views, it, n_items, 0, f.tab_max, f.list_cap);
+        return f.elem == 4                                                                      \
+                   ? launch(k_field<a, b, n, true, false, true>, dim3(grid), dim3(n * 64),      \
+                            f.lds_bytes, st, ev, none, views, it, n_items, 0, f.tab_max,        \
+                            f.list_cap)                                                         \
+                   : launch(k_field<a, b, n, true, false, false>, dim3(grid), dim3(n * 64),     \
+                            f.lds_bytes, st, ev, none, views, it, n_items, 0, f.tab_max,        \
+                            f.list_cap);
     SF_LIST_SHAPES(SF_DISPATCH)
 #undef SF_DISPATCH
     return hipErrorInvalidValue;
 }
 
-int field_resident_blocks(int tw, int hl, int nw, size_t lds_bytes, bool multi)
+int field_resident_blocks(int tw, int hl, int nw, size_t lds_bytes, bool multi, int elem)
 {
     int n = 0;
     hipError_t e = hipErrorInvalidValue;
+    const void *fn = nullptr;
 #define SF_OCC(a, b, w)                                                                           \
-    if (tw == a && hl == b && nw == w)                                                           \
-        e = multi ? hipOccupancyMaxActiveBlocksPerMultiprocessor(                                \
-                        &n, reinterpret_cast<const void *>(&k_field<a, b, w, true>), w * 64,      \
-                        lds_bytes)                                                               \
-                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(                                \
-                        &n, reinterpret_cast<const void *>(&k_field<a, b, w, false>), w * 64,     \
-                        lds_bytes);
+    if (tw == a && hl == b && nw == w) {                                                         \
+        if (elem == 4)                                                                           \
+            fn = multi ? reinterpret_cast<const void *>(&k_field<a, b, w, true, false, true>)     \
+                       : reinterpret_cast<const void *>(&k_field<a, b, w, false, false, true>);   \
+        else                                                                                     \
+            fn = multi ? reinterpret_cast<const void *>(&k_field<a, b, w, true, false, false>)    \
+                       : reinterpret_cast<const void *>(&k_field<a, b, w, false, false, false>);  \
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, w * 64, lds_bytes);             \
+    }
     SF_LIST_SHAPES(SF_OCC)
 #undef SF_OCC
     return e == hipSuccess ? n : 0;
@@ -2340,9 +2407,13 @@ hipError_t launch_field_one(const FieldLaunch &f, const SceneView &view, int per
     const int grid = std::max(1, std::min(f.grid, n_items));
 #define SF_DISPATCH(a, b, n)                                                                      \
     if (f.tw == a && f.hl == b && f.nw == n)                                                    \
-        return launch(k_field<a, b, n, false>, dim3(grid), dim3(n * 64), f.lds_bytes, st, ev,    \
-                      view, (const SceneView *)nullptr, (const int4 *)nullptr, n_items, per,    \
-                      f.tab_max, f.list_cap);
+        return f.elem == 4                                                                      \
+                   ? launch(k_field<a, b, n, false, false, true>, dim3(grid), dim3(n * 64),     \
+                            f.lds_bytes, st, ev, view, (const SceneView *)nullptr,              \
+                            (const int4 *)nullptr, n_items, per, f.tab_max, f.list_cap)         \
+                   : launch(k_field<a, b, n, false, false, false>, dim3(grid), dim3(n * 64),    \
+                            f.lds_bytes, st, ev, view, (const SceneView *)nullptr,              \
+                            (const int4 *)nullptr, n_items, per, f.tab_max, f.list_cap);
     SF_LIST_SHAPES(SF_DISPATCH)
 #undef SF_DISPATCH
     return hipErrorInvalidValue;
@@ -2355,9 +2426,13 @@ hipError_t launch_field_update(const FieldLaunch &f, const SceneView &view, int 
     const int grid = std::max(1, std::min(f.grid, n_items));
 #define SF_DISPATCH(a, b, n)                                                                      \
     if (f.tw == a && f.hl == b && f.nw == n)                                                    \
-        return launch(k_field<a, b, n, false, true>, dim3(grid), dim3(n * 64), f.lds_bytes, st, \
-                      ev, view, (const SceneView *)nullptr, (const int4 *)nullptr, n_items,     \
-                      per, f.tab_max, f.list_cap);
+        return f.elem == 4                                                                      \
+                   ? launch(k_field<a, b, n, false, true, true>, dim3(grid), dim3(n * 64),      \
+                            f.lds_bytes, st, ev, view, (const SceneView *)nullptr,              \
+                            (const int4 *)nullptr, n_items, per, f.tab_max, f.list_cap)         \
+                   : launch(k_field<a, b, n, false, true, false>, dim3(grid), dim3(n * 64),     \
+                            f.lds_bytes, st, ev, view, (const SceneView *)nullptr,              \
+                            (const int4 *)nullptr, n_items, per, f.tab_max, f.list_cap);
     SF_LIST_SHAPES(SF_DISPATCH)
 #undef SF_DISPATCH
     return hipErrorInvalidValue;

@@ -202,6 +202,38 @@ def test_tile_shape_invariance(sf, monkeypatch):
         assert np.array_equal(p, fields[0][1])
 
 
+@pytest.mark.parametrize("periodic", [False, True], ids=["bounded", "torus"])
+def test_integer_and_fp64_stamps_identical(sf, monkeypatch, periodic):
+    """The gather sums the law's strengths as integers in units of q (laws
+    whose 8 largest strengths fit 32 bits) or as doubles (SF_FIELD_INT=0, and
+    laws spanning more binades): both are the exact sum, so the fields and
+    the runs are the same bit for bit, for a scene and for a batch; and a law
+    that needs the FP64 form matches the oracle."""
+    if periodic:
+        sc = scenes.flow_scene(192, 128, 0.3, 8, radius=11, seed=5)
+    else:
+        sc = scenes.random_scene(170, 110, n_peds=2500, radius=13, seed=44, bernoulli=0.03,
+                                 exits=("E", "S"), exit_width=8)
+    runs = []
+    for flag in ("1", "0"):
+        monkeypatch.setenv("SF_FIELD_INT", flag)
+        with sf.GpuScene(sc) as g, sf.GpuScene(sc) as m:
+            with sf.Batch([m]) as b:
+                g.step(6)
+                b.step(6)
+                runs.append((g.field(), g.positions(), m.field(), m.positions()))
+    for a, b in zip(runs[0], runs[1]):
+        assert np.array_equal(a, b)
+    assert np.array_equal(runs[0][0], runs[0][2])
+    # strengths from 1 down to (13 sqrt 2)^-2: too wide a span for 32-bit sums
+    wide = sc.with_params(alpha=-2.0)
+    st = oracle.statics(wide)
+    with sf.GpuScene(wide) as g:
+        rep = lockstep(g, st, wide.start_step, 3, 1)
+    _say("[fp64 stamp]", rep)
+    assert_parity(rep)
+
+
 def test_refresh_field(sf):
     """sf_refresh_field superposes the current positions again: on the full
     path the field keeps its bits and nothing else changes; under the
