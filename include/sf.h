@@ -301,6 +301,22 @@ int sf_superpose(int32_t width, int32_t height, int32_t periodic, int32_t radius
                  double alpha, const double *S, const int32_t *pos, int32_t n, float *P,
                  void *hip_stream);
 
+/* sf_superpose for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same arguments, the same kernels and the same result bit for bit, with no
+ * hipMalloc, hipFree or other allocating call.  Its scratch (bitmap and stamp)
+ * is a static device array of 8.25 MiB that each device the library runs on
+ * holds until the process ends; grids whose bitmap needs more than 2^20 words
+ * (ceil(width/64)*height; 8192 x 8192 is the largest square) are refused
+ * with SF_EINVAL.  Every
+ * call on one device shares that array and leaves its last contents there
+ * (the call clears what it needs): calls that overlap on one device, on
+ * different streams or threads, race and give undefined fields; calls on one
+ * stream are ordered.  Errors as for sf_superpose, without SF_ENOMEM. */
+int sf_superpose_noalloc(int32_t width, int32_t height, int32_t periodic, int32_t radius,
+                         double k, double alpha, const double *S, const int32_t *pos, int32_t n,
+                         float *P, void *hip_stream);
+
 /* Per-kernel timing of the tick's kernels (the per-job time profile of the
  * paper's Fig. 7): while enabled, every launch of the kernels listed above
  * records a start/stop HIP event pair as part of its own dispatch (the

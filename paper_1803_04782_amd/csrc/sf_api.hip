@@ -9,6 +9,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <tuple>
@@ -1648,6 +1649,45 @@ int superpose_enqueue(const SuperposeCall &c, unsigned long long *bits, void *ta
     return SF_OK;
 }
 
+// ---- the superposition without allocation (sf_superpose_noalloc) -----------------
+
+// Its scratch lives in a static device array instead: the stamp table (any
+// radius's table fits, the LDS bounds it to 160 KiB), then the occupancy
+// bitmap of grids of up to 2^20 bitmap words (2^26 su when the width is a
+// multiple of 64).  Each device holds its own copy until the process ends.
+constexpr size_t kScratchTabDoubles = (size_t)1 << 15;  // 256 KiB
+constexpr size_t kScratchBitmapWords = (size_t)1 << 20; // 8 MiB
+constexpr int kScratchMaxDevices = 64;
+
+}  // namespace
+
+static __device__ __align__(256) unsigned long long
+    scratch[kScratchTabDoubles + kScratchBitmapWords];
+
+namespace {
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kScratchMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per
+// device (the host-side name of the array is not a device address).
+int scratch_address(void **out)
+{
+    int dev = 0;
+    SF_HIP(hipGetDevice(&dev), "hipGetDevice");
+    if (dev < 0 || dev >= kScratchMaxDevices)
+        return fail(SF_EINVAL, "device %d is beyond the %d devices the static scratch serves",
+                    dev, kScratchMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        SF_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "scratch address");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return SF_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -2033,6 +2073,28 @@ int sf_superpose(int32_t width, int32_t height, int32_t periodic, int32_t radius
     SF_HIP(e1, "free stamp table");
     SF_HIP(e2, "free bitmap");
     return SF_OK;
+}
+
+int sf_superpose_noalloc(int32_t width, int32_t height, int32_t periodic, int32_t radius,
+                         double k, double alpha, const double *S, const int32_t *pos, int32_t n,
+                         float *P, void *hip_stream)
+{
+    g_last_error.clear();
+    SuperposeCall c;
+    int rc = superpose_prepare(width, height, periodic, radius, k, alpha, S, pos, n, P,
+                               hip_stream, &c);
+    if (rc) return rc;
+    if (c.bitmap_words > kScratchBitmapWords)
+        return fail(SF_EINVAL, "grid %d x %d needs %zu bitmap words; the static scratch holds %zu",
+                    width, height, c.bitmap_words, kScratchBitmapWords);
+    if (c.tab_bytes > kScratchTabDoubles * 8)
+        return fail(SF_EINVAL, "the stamp of radius %d needs %zu bytes; the static scratch "
+                    "holds %zu", radius, c.tab_bytes, kScratchTabDoubles * 8);
+    void *base = nullptr;
+    if ((rc = scratch_address(&base))) return rc;
+    void *tab = base;
+    unsigned long long *bits = static_cast<unsigned long long *>(base) + kScratchTabDoubles;
+    return superpose_enqueue(c, bits, tab);
 }
 
 int sf_device_count(void)

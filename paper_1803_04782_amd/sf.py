@@ -38,7 +38,8 @@ EXPORTS = ("sf_create_scene", "sf_step", "sf_field", "sf_positions", "sf_last_mo
            "sf_sect_image", "sf_destroy_scene", "sf_batch_create", "sf_batch_tune",
            "sf_batch_get_tiling", "sf_batch_step", "sf_batch_refresh_field", "sf_batch_stats",
            "sf_batch_sync",
-           "sf_batch_destroy", "sf_superpose", "sf_device_count",
+           "sf_batch_destroy", "sf_superpose", "sf_superpose_noalloc",
+           "sf_device_count",
            "sf_last_error")
 _VOID = ("sf_destroy_scene", "sf_batch_destroy", "sf_last_error")
 
@@ -171,6 +172,7 @@ def load():
     lib.sf_batch_destroy.restype = None
     lib.sf_superpose.argtypes = [i32, i32, i32, i32, ctypes.c_double, ctypes.c_double, P, P, i32,
                                  P, P]
+    lib.sf_superpose_noalloc.argtypes = lib.sf_superpose.argtypes
     lib.sf_last_error.restype = ctypes.c_char_p
     lib.sf_last_error.argtypes = []
     lib.sf_device_count.argtypes = []
@@ -200,12 +202,15 @@ def _device_tensor(t, dtype, numel: int, what: str):
 
 
 def superpose(S, pos, width: int, height: int, radius: int, k: float = 1.0,
-              alpha: float = -0.5, periodic: bool = False, out=None, stream=None):
+              alpha: float = -0.5, periodic: bool = False, out=None, stream=None,
+              noalloc: bool = False):
     """sf_superpose: P = fl32(S + sum of the strengths of the sources at `pos`)
     for device tensors S (float64, width*height) and pos (int32; entries
     outside the grid are skipped).  Returns `out` (float32, width*height, made
     on S's device when None).  Enqueued on `stream` (default: torch's current
-    stream of S's device); does not block."""
+    stream of S's device); does not block.  noalloc: sf_superpose_noalloc (no
+    device allocation; scratch in a static device array shared by every call on
+    the device)."""
     import torch
 
     n_su = width * height
@@ -220,9 +225,9 @@ def superpose(S, pos, width: int, height: int, radius: int, k: float = 1.0,
             raise ValueError("S, pos and out must be on one device")
     with torch.cuda.device(S.device):
         st = stream if stream is not None else torch.cuda.current_stream(S.device)
-        _check(load().sf_superpose(width, height, int(bool(periodic)), radius, float(k),
-                                   float(alpha), s_ptr, pos_ptr, n, p_ptr,
-                                   ctypes.c_void_p(st.cuda_stream)))
+        fn = load().sf_superpose_noalloc if noalloc else load().sf_superpose
+        _check(fn(width, height, int(bool(periodic)), radius, float(k), float(alpha), s_ptr,
+                  pos_ptr, n, p_ptr, ctypes.c_void_p(st.cuda_stream)))
     return out
 
 
