@@ -99,9 +99,9 @@ def field_bytes(W, H) -> float:
 
 def traffic_per_launch(name):
     """HBM bytes per field launch from the committed rocprofv3 PMC summary
-    profiles/<name>_pmc.json, if it was taken on the current kernel source."""
+    profiles/superpose_<name>_pmc.json, if it was taken on the current kernel source."""
     try:
-        d = json.load(open(os.path.join(PMC_DIR, f"{name}_pmc.json")))
+        d = json.load(open(os.path.join(PMC_DIR, f"superpose_{name}_pmc.json")))
     except (OSError, ValueError):
         return None
     if d.get("kernel_source_sha256_16") != kernel_source_hash():
@@ -440,15 +440,18 @@ def serving_leg(args, stream):
         srv = serve.Server(int(args.budget_gib * (1 << 30)), max_scenes=args.max_scenes,
                            stream=stream, background_builds=not args.sync_builds)
         say(f"serving at {lam:g}/s: {len(reqs)} requests over {args.serve_seconds:g} s")
-        out = srv.run(reqs, stop_admitting_at=args.serve_seconds, drain=False,
-                      deadline=args.serve_seconds)
+        # arrivals for serve_seconds, then the resident scenes keep running
+        # (up to serve_seconds + drain_seconds) so that finished scenes count
+        out = srv.run(reqs, stop_admitting_at=args.serve_seconds, drain=args.drain_seconds > 0,
+                      deadline=args.serve_seconds + args.drain_seconds)
         torch.cuda.synchronize()
         out.pop("results")
         out["rate_per_s"] = lam
         say(f"   p50/p99 step {out['step_latency_ms_p50']:.2f}/{out['step_latency_ms_p99']:.2f} "
             f"ms, {out['scenes_per_s']:.2f} scenes/s, {out['ped_steps_per_s']:.3g} ped-steps/s")
         runs.append(out)
-    return {"rates_per_s": rates, "window_s": args.serve_seconds, "max_steps": 2000,
+    return {"rates_per_s": rates, "window_s": args.serve_seconds,
+            "drain_s": args.drain_seconds, "max_steps": 2000,
             "budget_gib": args.budget_gib, "max_scenes": args.max_scenes,
             "request_pool": len(pool),
             "builds": "between ticks" if args.sync_builds else "worker thread", "runs": runs}
@@ -685,6 +688,9 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=None,
                     help="arrival window per rate (serving; default 30 s alone, 4 s in the "
                          "default line)")
+    ap.add_argument("--drain-seconds", type=float, default=None,
+                    help="serving: after the arrival window, keep ticking the resident scenes "
+                         "for up to this long (default 0 alone, 6 s in the default line)")
     ap.add_argument("--sync-builds", action="store_true",
                     help="serving: build admitted scenes between ticks, not on a worker thread")
     ap.add_argument("--budget-gib", type=float, default=64.0,
@@ -736,6 +742,7 @@ def main():
         args.cpu_seconds = 0.0
     if args.workload == "serving":
         args.serve_seconds = args.serve_seconds or 30.0
+        args.drain_seconds = args.drain_seconds or 0.0
         args.pool = args.pool or 64
         bench_serving(args, stream)
         return
@@ -760,6 +767,7 @@ def main():
             out["plaza8192"] = single_scene(scenes.plaza8192(), args, stream, 200, 50,
                                             sub_cpu, "superpose")
             args.serve_seconds = args.serve_seconds or 4.0
+            args.drain_seconds = 6.0 if args.drain_seconds is None else args.drain_seconds
             args.pool = args.pool or 32
             out["serving"] = serving_leg(args, stream)
         out["bench_wall_s"] = time.perf_counter() - t_start

@@ -109,6 +109,18 @@ __device__ __forceinline__ void block_max_into(unsigned int v, Ctr ctr, int id)
     __syncthreads();
 }
 
+// Maximum of `v` over the wave into copy (workgroup % kSlots) of running total
+// `id` by one atomic maximum from lane 0 (skipped when 0); no barrier, so it
+// may sit in divergent code only if the whole wave reaches it.
+template <typename Ctr>
+__device__ __forceinline__ void wave_max_into(unsigned int v, Ctr ctr, int id)
+{
+    for (int d = 32; d >= 1; d >>= 1) v = max(v, (unsigned int)__shfl_xor(v, d));
+    if (lane_id() == 0 && v)
+        __hip_atomic_fetch_max(&ctr[ctr_index(id, blockIdx.x % kSlots)], (unsigned long long)v,
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Pointer into LDS (address space 3): 32-bit byte addresses, ds_* instructions.
 template <typename T>
 using lds_ptr = const __attribute__((address_space(3))) T *;
@@ -1397,7 +1409,7 @@ __global__ __launch_bounds__(kDecideThreads) void k_decide_claim(
     }
     const unsigned long long seed = v.seed;
     const float phi_axial = v.phi_axial, phi_diag = v.phi_diag;
-    unsigned int movers = 0, ties = 0, regs_seen = 0;
+    unsigned int movers = 0, ties = 0;
     // the step index and this pedestrian's arrays are requested together and
     // waited for once (the empty asm takes all of them, so no load is moved
     // behind a branch that would wait for it alone)
@@ -1590,11 +1602,11 @@ __global__ __launch_bounds__(kDecideThreads) void k_decide_claim(
                                              (uint32_t)seed, (uint32_t)(seed >> 32));
                 const unsigned long long kk = ((unsigned long long)r << 32) | eid;
                 __hip_atomic_fetch_min(&claim[tgt], kk, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                // registrations at the target so far, this one included (s-2:
-                // at most 8 under v_max = 1)
-                regs_seen = 1u + __hip_atomic_fetch_add(&to_global(v.regs)[tgt], 1u,
-                                                        __ATOMIC_RELAXED,
-                                                        __HIP_MEMORY_SCOPE_AGENT);
+                // one more registration at the target (s-2: at most 8 under
+                // v_max = 1); the count is read by the election's winner in
+                // commit, so this atomic returns nothing and nothing waits
+                __hip_atomic_fetch_add(&to_global(v.regs)[tgt], 1u, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
                 key[i] = kk;
                 mover = true;
             }
@@ -1605,7 +1617,6 @@ __global__ __launch_bounds__(kDecideThreads) void k_decide_claim(
         }
     }
     block_sums_add<2>({(int)movers, (int)ties}, ctr, {kMovers, kTied});
-    block_max_into(regs_seen, ctr, kMaxClaim);
 }
 
 // ---- commit (k-4 moves, exits) -------------------------------------------------------
@@ -1626,9 +1637,11 @@ __global__ __launch_bounds__(commit_threads<MULTI>()) void k_commit(SceneView on
     const gptr<unsigned long long> claim = to_global(v.claim), occ = to_global(v.occ),
                                    ctr = to_global(v.ctr);
     bool was_live = false, won = false, left = false;
+    unsigned int regs_seen = 0;  // registrants of the su this thread won
     if (i < v.N) {
         // independent loads first (one round trip), then, for movers, the
-        // claim word, the exit flag and the mover's own key together
+        // claim word, the exit flag, the registration count and the mover's
+        // own key together
         const int p = pos[i];
         const uint8_t f = flags[i];
         const int tgt = target[i];
@@ -1642,9 +1655,14 @@ __global__ __launch_bounds__(commit_threads<MULTI>()) void k_commit(SceneView on
                 // also resets the word, which losers then read as "not mine"
                 const unsigned long long cw = claim[tgt];
                 const bool to_exit = exitm[tgt] != 0;
+                const unsigned int nreg = to_global(v.regs)[tgt];
                 const unsigned long long kk = key[i];
                 if (cw == kk) {
+                    // every registration of this tick is counted by now (decide
+                    // has finished); each claimed su has one winner, which reads
+                    // the count before it clears it
                     won = true;
+                    regs_seen = nreg;
                     claim[tgt] = ~0ull;
                     to_global(v.regs)[tgt] = 0u;
                     const int y = p / W, x = p - y * W;
@@ -1674,6 +1692,7 @@ __global__ __launch_bounds__(commit_threads<MULTI>()) void k_commit(SceneView on
     }
     if (lb == 0 && threadIdx.x == 0)
         __hip_atomic_fetch_add(&ctr[0], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    wave_max_into(regs_seen, ctr, kMaxClaim);
     block_sums_add<4>({was_live ? 1 : 0, won ? 1 : 0, left ? 1 : 0, left ? -1 : 0}, ctr,
                       {kPedSteps, kMoved, kEvacuated, kLive});
 }
