@@ -744,12 +744,29 @@ __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
             }
         }
     };
+    // S (and, for an update, the previous Phi) of this lane's su in a strip:
+    // requested one strip ahead, like the halo rows, so that a strip whose
+    // gather is short (small radius, sparse crowd) does not wait for them
+    double sv_n[HL], pv_n[HL];
+    auto fetch_sp = [&](const FieldScene &s, int ts) {
+        const int ty = ts / s.tiles_x, tx = ts - ty * s.tiles_x;
+        const int x = tx * TW + col, y0 = ty * WT + wv * TH;
+#pragma unroll
+        for (int r = 0; r < HL; ++r) {
+            const int y = y0 + rg + G * r;
+            const size_t c = (size_t)min(y, s.H - 1) * s.W + min(x, s.W - 1);
+            sv_n[r] = s.S[c];
+            pv_n[r] = 0.0;
+            if constexpr (DUAL) pv_n[r] = s.phi[c];
+        }
+    };
     {
         // the first batch of the stamp (all of it unless it exceeds 8 vectors
-        // per thread) and the first strip's halo rows are requested together,
-        // in straight-line code, so that their round trips overlap
+        // per thread), the first strip's halo rows and its S are requested
+        // together, in straight-line code, so that their round trips overlap
         f64x2 r[8];
         fetch_rows(v, t);
+        fetch_sp(v, t);
         table_load(v, 0, r);
         table_store(v, 0, r);
         for (int i0 = 8 * NT; i0 < v.tab_vecs; i0 += 8 * NT) {
@@ -806,20 +823,20 @@ __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
         // keep the loads below after the use of the prefetched words, so that
         // the wait for those does not also wait for the new requests
         asm volatile("" ::"v"(cnts[0]), "v"(cnts[NSRC - 1]) : "memory");
-        // S (and, for an update, the previous Phi) of this lane's su and the
-        // next strip's halo rows are requested now and arrive while this
+        // this strip's S (and previous Phi), requested a strip ago; the next
+        // strip's halo rows and S are requested now and arrive while this
         // strip is gathered
         const int x = X0 + col;
         double sv[HL], pv[HL];
 #pragma unroll
         for (int r = 0; r < HL; ++r) {
-            const int y = y0w + rg + G * r;
-            const size_t c = (size_t)min(y, H - 1) * W + min(x, W - 1);
-            sv[r] = v.S[c];
-            pv[r] = 0.0;
-            if constexpr (DUAL) pv[r] = v.phi[c];
+            sv[r] = sv_n[r];
+            pv[r] = pv_n[r];
         }
-        if (more) fetch_rows(nv, nt);
+        if (more) {
+            fetch_rows(nv, nt);
+            fetch_sp(nv, nt);
+        }
 
         // this wave's halo rows (relative to ya) and per-lane base address
         const int ra = max(y0w - R, ya) - ya;
