@@ -20,7 +20,8 @@ serving (longer windows), flow1000 (the paper's section 5 scenario: a
 1000x1000 torus, density 0.5, 8-directional flow, 7x7 fields, 1000 ticks),
 flow-sweep (its 360-combination grid), flow-walk (its walk-period
 experiment of Table V) and sect-compare (the paper's own 8-sect, K-slot FP32
-field path against the exact gather: speed and error).
+field path against the exact gather: speed and error) and ensemble-classes
+(the ensemble's batched field pass by radius class).
 """
 from __future__ import annotations
 
@@ -647,6 +648,65 @@ def bench_sect_compare(args, stream):
     print(json.dumps(out), flush=True)
 
 
+def bench_ensemble_classes(args, stream):
+    """The ensemble's field pass by radius class: the scenes of each radius as
+    a one-group batch (tuned), back-to-back field passes timed with HIP
+    events; beside each, the class's contributions and its HBM and ALU
+    floors, and the default two-group batch of all 256 scenes."""
+    import torch
+
+    from paper_1803_04782_amd import scenes, sf
+
+    scs = scenes.ensemble(n_scenes=args.scenes, seed=3)
+    loops = 10
+
+    def timed(b):
+        b.refresh_field(2)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        b.refresh_field(loops)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return 1000.0 * e0.elapsed_time(e1) / loops
+
+    rows = []
+    for R in sorted({s.radius for s in scs}):
+        sub = [s for s in scs if s.radius == R]
+        gs = [sf.GpuScene(s, stream=stream) for s in sub]
+        try:
+            with sf.Batch(gs, tiling={"groups": 1}, stream=stream) as b:
+                tiling = b.tune(reps=2)
+                us = timed(b)
+        finally:
+            for g in gs:
+                g.close()
+        su = sum(s.width * s.height for s in sub)
+        contrib = sum(contributions(s.width, s.height, s.radius, s.periodic, s.pos) for s in sub)
+        nbytes = sum(field_bytes(s.width, s.height) for s in sub)
+        rows.append({"radius": R, "scenes": len(sub), "su": su, "contributions": contrib,
+                     "pass_us": us, "hbm_floor_us": 1e6 * nbytes / HBM_PEAK,
+                     "alu_floor_us": 1e6 * contrib / (ALU_PEAK_TFLOPS * 1e12),
+                     "tiling": tiling["group"][0]})
+        say(f"R={R}: {len(sub)} scenes, field pass {us:.1f} us")
+    gs = [sf.GpuScene(s, stream=stream) for s in scs]
+    try:
+        with sf.Batch(gs, stream=stream) as b:
+            tiling = b.tune(reps=2)
+            all_us = timed(b)
+    finally:
+        for g in gs:
+            g.close()
+    out = {"metric": METRIC, "value": None, "unit": "us per field pass", "n_gpus": 1,
+           "steps": None, "warmup": 2, "higher_is_better": False, "scaling": "weak",
+           "vs_baseline": None, "dtype": "i32 sums (exact)", "data": "synthetic",
+           "config": {"workload": "ensemble-classes", "scenes": len(scs),
+                      "parallelism": "single-gpu"},
+           "classes": rows, "two_groups": {"pass_us": all_us, "tiling": tiling},
+           "roofline": None, "cpu_baseline": None}
+    print(json.dumps(out), flush=True)
+
+
 def bench_serving(args, stream):
     """Serving loop under Poisson arrivals at several rates (longer windows
     than the default line's leg)."""
@@ -682,7 +742,7 @@ def main():
     ap.add_argument("--workload", default="default",
                     choices=["default", "ensemble256", "hall1024", "room64", "plaza8192",
                              "flow1000", "flow-sweep", "flow-walk", "serving",
-                             "sect-compare"])
+                             "sect-compare", "ensemble-classes"])
     ap.add_argument("--scenes", type=int, default=256, help="ensemble size (ensemble256)")
     ap.add_argument("--rates", default="50,200,800", help="arrival rates per s (serving)")
     ap.add_argument("--serve-seconds", type=float, default=None,
@@ -754,6 +814,9 @@ def main():
         return
     if args.workload == "sect-compare":
         bench_sect_compare(args, stream)
+        return
+    if args.workload == "ensemble-classes":
+        bench_ensemble_classes(args, stream)
         return
     if args.workload in ("default", "ensemble256"):
         t_start = time.perf_counter()
