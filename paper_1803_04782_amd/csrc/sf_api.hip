@@ -81,6 +81,7 @@ struct sf_scene {
     int32_t *tabi = nullptr;
     double q_unit = 1.0;
     bool int_ok = false;
+    int int_rounds = 1;  // rounds of 8 integer terms summed in 32 bits (see law_units)
     float *P = nullptr;
     int32_t *D = nullptr;
     uint8_t *exitm = nullptr;
@@ -227,15 +228,17 @@ struct DeviceGuard {
 // Stamp of the law phi(d) = k*|d|_2^alpha on the window |d|_inf <= R (zero at
 // d = 0 and outside it), each strength rounded once to FP32 and held as a
 // double: entry (dx, dy) at (dx + padx)*stride + dy + pady of a column-major
-// table of n doubles with ncols columns of nrows used rows, zero elsewhere.
+// table of n doubles with ncols columns of nrows rows around row pady, zero
+// elsewhere (the nonzero band |dy| <= R lies inside each column's stride).
 std::vector<double> stamp_table(int R, double k, double alpha, int ncols, int nrows, int stride,
                                 int padx, int pady, size_t n)
 {
     std::vector<double> t(n, 0.0);
     for (int ci = 0; ci < ncols; ++ci)
-        for (int ri = 0; ri < nrows; ++ri) {
+        for (int ri = std::max(0, pady - R); ri < nrows && ri <= pady + R; ++ri) {
             const int dx = ci - padx, dy = ri - pady;
             if (std::abs(dx) > R || std::abs(dy) > R || (dx == 0 && dy == 0)) continue;
+            if (ri >= stride || (size_t)ci * stride + ri >= n) continue;  // not reached
             const double dist = std::sqrt((double)dx * dx + (double)dy * dy);
             t[(size_t)ci * stride + ri] = (double)(float)(k * std::pow(dist, alpha));
         }
@@ -256,9 +259,12 @@ int upload_table(double *dst, const std::vector<double> &t, hipStream_t st)
 // the exponent of the smallest nonzero |strength| (the same q as check_law),
 // and the kernel sums 8 of them in a 32-bit integer before moving the sum into
 // FP64, which needs 8 * max|strength| / q < 2^31.
+// The gather may sum `rounds` rounds of 8 terms in 32 bits when
+// 8 * rounds * max|strength| / q < 2^31 (at most 64 rounds).
 struct LawUnits {
     double q = 1.0;
     bool int_ok = true;
+    int rounds = 1;
 };
 
 LawUnits law_units(int R, double k, double alpha)
@@ -279,6 +285,8 @@ LawUnits law_units(int R, double k, double alpha)
     (void)std::frexp(tmin, &e);
     u.q = std::ldexp(1.0, std::max(e - 1 - 23, -149));
     u.int_ok = 8.0 * (tmax / u.q) < 2147483648.0;
+    if (u.int_ok)
+        u.rounds = (int)std::min(64.0, std::floor(2147483647.0 / (8.0 * (tmax / u.q))));
     return u;
 }
 
@@ -333,7 +341,7 @@ int field_blocks_per_cu(const ListCfg &lc)
     int per_cu = (int)std::max<size_t>(1, (size_t)(160 * 1024) / lc.lds_bytes);
     per_cu = std::min(per_cu, std::max(1, 32 / lc.nw));
     const int resident =
-        sf::field_resident_blocks(lc.tw, lc.hl, lc.nw, lc.lds_bytes, false, lc.elem);
+        sf::field_resident_blocks(lc.tw, lc.hl, lc.nw, lc.lds_bytes, false, lc.elem, lc.vec);
     if (resident > 0) per_cu = std::min(per_cu, resident);
     return per_cu;
 }
@@ -745,6 +753,7 @@ int create(const sf_scene_desc *d, void *hip_stream, sf_scene **out)
         const LawUnits u = law_units(s->R, s->k, s->alpha);
         s->q_unit = u.q;
         s->int_ok = u.int_ok;
+        s->int_rounds = u.rounds;
         if (const char *e = std::getenv("SF_FIELD_INT"))
             if (std::atoi(e) == 0) s->int_ok = false;  // speed only: the same field
     }
@@ -757,9 +766,9 @@ int create(const sf_scene_desc *d, void *hip_stream, sf_scene **out)
         const int got = std::sscanf(e, "%dx%dx%dx%dx%d", &a, &b, &v, &w, &cap);
         if (got != 4 && got != 5)
             return fail(SF_EINVAL, "SF_TILE=%s is not of the form TWxHLxVECxNW[xCAP]", e);
-        if (v != 2 || !sf::list_shape_compiled(a, b, w) || cap < 1 || cap > (1 << 16))
+        if (!sf::list_shape_compiled(a, b, w, v, elem) || cap < 1 || cap > (1 << 16))
             return fail(SF_EINVAL, "SF_TILE=%s is not a compiled shape", e);
-        s->lc = sf::make_list_cfg(s->R, a, b, w, cap, elem);
+        s->lc = sf::make_list_cfg(s->R, a, b, w, cap, elem, v);
         if (s->lc.halo_rows > 64 * w)
             return fail(SF_EINVAL, "SF_TILE=%s does not fit radius %d", e, s->R);
     }
@@ -876,7 +885,7 @@ int setup_launches(sf_scene *s)
     v.bb = (s->bh - 1) / 2;
     v.bodies = s->bodies;
     v.obits = s->obits;
-    sf::set_view_layout(v, s->lc, s->tab, s->tabi, s->q_unit);
+    sf::set_view_layout(v, s->lc, s->tab, s->tabi, s->q_unit, s->int_rounds);
     s->fl = sf::field_launch_for(s->lc);
     // one strip per item: workgroup b takes strips b, b + grid, ...
     s->strips_per_block = 1;
@@ -1115,16 +1124,17 @@ int resolve_group_tiling(const sf_batch *b, int R, int elem, sf_group_tiling *t,
         const ListCfg d = sf::pick_list_cfg(R, lds_cap, elem);
         t->tw = d.tw;
         t->hl = d.hl;
+        t->vec = d.vec;
         t->nw = d.nw;
         if (t->list_cap == 0) t->list_cap = d.list_cap;
     }
     if (t->vec == 0) t->vec = 2;
-    if (t->vec != 2 || !sf::list_shape_compiled(t->tw, t->hl, t->nw))
-        return fail(SF_EINVAL, "tiling %dx%dx%dx%d is not a compiled shape", t->tw, t->hl, t->vec,
-                    t->nw);
+    if (!sf::list_shape_compiled(t->tw, t->hl, t->nw, t->vec, elem))
+        return fail(SF_EINVAL, "tiling %dx%dx%dx%d is not a compiled shape%s", t->tw, t->hl,
+                    t->vec, t->nw, t->vec == 4 ? " (vec 4 needs integer stamps)" : "");
     if (t->list_cap == 0) {
         for (int cap = 4096; cap >= 512; cap /= 2) {
-            const ListCfg c = sf::make_list_cfg(R, t->tw, t->hl, t->nw, cap, elem);
+            const ListCfg c = sf::make_list_cfg(R, t->tw, t->hl, t->nw, cap, elem, t->vec);
             if (c.lds_bytes <= lds_cap) {
                 t->list_cap = cap;
                 break;
@@ -1133,13 +1143,13 @@ int resolve_group_tiling(const sf_batch *b, int R, int elem, sf_group_tiling *t,
     }
     if (t->list_cap < 0 || t->list_cap > (1 << 16))
         return fail(SF_EINVAL, "list_cap %d outside 0..65536", t->list_cap);
-    const ListCfg c = sf::make_list_cfg(R, t->tw, t->hl, t->nw, t->list_cap, elem);
+    const ListCfg c = sf::make_list_cfg(R, t->tw, t->hl, t->nw, t->list_cap, elem, t->vec);
     if (c.list_cap < 2 * c.max_row || c.halo_rows > 64 * t->nw || c.lds_bytes > lds_cap)
         return fail(SF_EINVAL, "tiling %dx%dx%dx%d with list_cap %d does not fit radius %d",
                     t->tw, t->hl, t->vec, t->nw, t->list_cap, R);
     int bpc_max = std::max(1, std::min((int)((160 * 1024) / c.lds_bytes), 32 / t->nw));
     const int resident =
-        sf::field_resident_blocks(t->tw, t->hl, t->nw, c.lds_bytes, true, elem);
+        sf::field_resident_blocks(t->tw, t->hl, t->nw, c.lds_bytes, true, elem, t->vec);
     if (resident > 0) bpc_max = std::min(bpc_max, resident);  // no partial second round
     if (t->blocks_per_cu == 0) t->blocks_per_cu = bpc_max;
     if (t->blocks_per_cu < 1 || t->blocks_per_cu > 64)
@@ -1188,7 +1198,7 @@ int build_group(sf_batch *b, const std::vector<int> &members, const sf_group_til
     int64_t dec_total = 0, com_total = 0;
     for (int q = 0; q < n; ++q) {
         const sf_scene *s = b->scenes[(size_t)members[(size_t)q]];
-        const ListCfg lc = sf::make_list_cfg(s->R, t.tw, t.hl, t.nw, t.list_cap, elem);
+        const ListCfg lc = sf::make_list_cfg(s->R, t.tw, t.hl, t.nw, t.list_cap, elem, t.vec);
         const auto key = std::make_tuple(s->R, s->k, s->alpha);
         void *&tab = tables[key];
         if (!tab) {
@@ -1215,7 +1225,8 @@ int build_group(sf_batch *b, const std::vector<int> &members, const sf_group_til
         }
         SceneView v = s->view;
         if (elem == 4)
-            sf::set_view_layout(v, lc, nullptr, static_cast<const int32_t *>(tab), s->q_unit);
+            sf::set_view_layout(v, lc, nullptr, static_cast<const int32_t *>(tab), s->q_unit,
+                                s->int_rounds);
         else
             sf::set_view_layout(v, lc, static_cast<const double *>(tab), nullptr, 1.0);
         v.dec_block0 = (int32_t)dec_total;
@@ -1493,8 +1504,11 @@ int batch_tune(sf_batch *b, int32_t reps, sf_batch_tiling *chosen)
     } ev_guard{&ep};
     if (eb != hipSuccess) return hip_fail(eb, "hipEventCreate");
 
-    static const int shapes[][3] = {{16, 2, 4}, {16, 2, 8}, {16, 4, 4}, {16, 4, 8}, {32, 2, 4},
-                                    {32, 2, 8}, {32, 4, 4}, {8, 2, 4},  {8, 4, 4}};
+    // tw, hl, nw, vec (vec 4 shapes are skipped for groups without integer stamps)
+    static const int shapes[][4] = {{16, 2, 4, 2}, {16, 2, 8, 2}, {16, 4, 4, 2}, {16, 4, 8, 2},
+                                    {32, 2, 4, 2}, {32, 2, 8, 2}, {32, 4, 4, 2}, {8, 2, 4, 2},
+                                    {8, 4, 4, 2},  {16, 4, 4, 4}, {16, 4, 8, 4}, {32, 4, 4, 4},
+                                    {8, 4, 4, 4}};
     const int caps[] = {1024, 2048, 4096};
     const int ipbs[] = {2, 8};
     sf_batch_tiling best = b->cur.t;
@@ -1508,7 +1522,7 @@ int batch_tune(sf_batch *b, int32_t reps, sf_batch_tiling *chosen)
                     sf_group_tiling t = b->cur.g[gi].t;
                     t.tw = sh[0];
                     t.hl = sh[1];
-                    t.vec = 2;
+                    t.vec = sh[3];
                     t.nw = sh[2];
                     t.list_cap = cap;
                     t.blocks_per_cu = 0;
@@ -1557,6 +1571,7 @@ struct SuperposeCall {
     size_t lds_limit = 0;
     size_t bitmap_words = 0, tab_bytes = 0;
     double q = 1.0;  // unit of an integer stamp (lc.elem == 4)
+    int rounds = 1;  // rounds of 8 integer terms per 32-bit sum
 };
 
 int superpose_prepare(int32_t W, int32_t H, int32_t periodic, int32_t R, double k, double alpha,
@@ -1588,6 +1603,7 @@ int superpose_prepare(int32_t W, int32_t H, int32_t periodic, int32_t R, double 
            "LDS size");
     const LawUnits u = law_units(R, k, alpha);
     c->q = u.q;
+    c->rounds = u.rounds;
     c->lc = sf::pick_list_cfg(R, (size_t)max_lds - 1024, u.int_ok ? 4 : 8);
     if (c->lc.lds_bytes == 0 || c->lc.lds_bytes > (size_t)max_lds - 1024 ||
         c->lc.list_cap < 2 * c->lc.max_row)
@@ -1642,7 +1658,7 @@ int superpose_enqueue(const SuperposeCall &c, unsigned long long *bits, void *ta
     v.occ = bits;
     v.periodic = c.periodic;
     if (c.lc.elem == 4)
-        sf::set_view_layout(v, c.lc, nullptr, static_cast<const int32_t *>(tab), c.q);
+        sf::set_view_layout(v, c.lc, nullptr, static_cast<const int32_t *>(tab), c.q, c.rounds);
     else
         sf::set_view_layout(v, c.lc, static_cast<const double *>(tab), nullptr, 1.0);
     SF_HIP(sf::launch_field_one(sf::field_launch_for(c.lc), v, 1, c.stream), "superpose");

@@ -62,16 +62,20 @@ SupCfg make_sup_cfg(int radius, int tw, int hl, size_t elem);
 // A workgroup of NW waves covers a TW-column strip of NW*TH rows; wave w owns
 // rows [w*TH, (w+1)*TH).  Lane l owns column l % TW and, with rg = l / TW and
 // G = 64 / TW, the HL rows rg + G*r (r < HL), so its entries of a source's
-// stamp column are G apart and each pair is one 8-byte-aligned LDS read.
+// stamp column are G apart and each pair is one paired LDS read (vec = 2);
+// or (vec = 4: integer stamps, HL = 4) the rows 4*rg + r, read as one 16-byte
+// load from one of four copies of the stamp, copy c shifted by c entries.
 // The stamp is held once, column-major: as integers in units of the law's
 // q = 2^(e_min - 23) (elem = 4 bytes; the FP32 strengths are integer
 // multiples of q) or as doubles (elem = 8, laws whose strengths span too many
 // binades for 32-bit sums of 8 of them):
 //   entry (dx, dy) at (dx + padx)*stride + dy + pady,
 //   padx = R + TW (one zero column beyond the halo), pady = R + TH - 1,
-//   stride >= 2*pady + 1, chosen so that each pass of a read hits distinct
+//   stride >= 2R + TH (a read past the band |dy| <= R lands on zero rows of
+//   its own or the neighbouring column; one zero column more at the end),
+//   chosen so that each pass of a read hits distinct
 //   banks (16 lanes and index mod 16 for doubles, 32 lanes and mod 32 for
-//   integers).
+//   integers; vec = 4: a multiple of 4, 32 lanes and 16-byte unit mod 32).
 // The strip's halo sources are listed in LDS in row-major order; the list
 // holds `list_cap` entries and longer halos are processed in several passes.
 struct ListCfg {
@@ -80,17 +84,19 @@ struct ListCfg {
     int radius = 0;
     int padx = 0, pady = 0, ncols = 0, nrows = 0, stride = 0;
     int elem = 8;        // bytes per stamp entry: 4 (integers) or 8 (doubles)
-    int tab_elems = 0;   // ncols * stride rounded up to whole 16-byte vectors
+    int vec = 2;         // stamp entries per LDS load and lane: 2 or 4
+    int tab_elems = 0;   // (ncols + 1) * stride rounded up to whole 16-byte vectors
+    int lds_tab = 0;     // stamp entries in LDS: tab_elems, or (vec 4) 4*tab_elems + 4
     int list_cap = 0;
     int max_row = 0;     // most sources one halo row can hold
     int halo_rows = 0;   // most halo rows of one strip
     size_t lds_bytes = 0;
     int grid = 0;
 };
-ListCfg make_list_cfg(int radius, int tw, int hl, int nw, int list_cap, int elem);
+ListCfg make_list_cfg(int radius, int tw, int hl, int nw, int list_cap, int elem, int vec = 2);
 // Picks the launch shape for radius R that fits `max_lds` bytes of LDS.
 ListCfg pick_list_cfg(int radius, size_t max_lds, int elem);
-bool list_shape_compiled(int tw, int hl, int nw);
+bool list_shape_compiled(int tw, int hl, int nw, int vec = 2, int elem = 4);
 // Dynamic LDS limit of the field kernels.
 hipError_t set_field_lds_limit(size_t bytes);
 
@@ -104,6 +110,9 @@ struct SceneView {
     // field gather layout of this scene's radius under the launch's tile shape
     int32_t tiles_x, n_strips, stride;
     int32_t padx, pady, max_row, tab_elems;
+    // integer stamps: rounds of 8 sources the gather sums in 32 bits before it
+    // moves the sums into FP64 (8 * int_rounds * max|entry| < 2^31)
+    int32_t int_rounds;
     float phi_axial, phi_diag;  // own-field values at axial / diagonal neighbours
     unsigned long long seed;
     const double *tab;          // the stamp as doubles (FP32 strengths), or NULL
@@ -149,7 +158,7 @@ struct SceneView {
 // Field layout fields of `v` for shape `c` (built for the scene's radius):
 // the gather reads tabi (unit q) when c.elem == 4, else tab.
 void set_view_layout(SceneView &v, const ListCfg &c, const double *tab, const int32_t *tabi,
-                     double q);
+                     double q, int int_rounds = 1);
 
 // Workgroups of a scene in the decide launches and in a batch's commit launch.
 int decide_blocks(int N);
@@ -158,11 +167,12 @@ int commit_blocks(int N);
 // One field launch over `n_items` work items (int4: scene, first strip,
 // end strip, unused).  The workgroups on each XCD share a contiguous run of
 // the items (in proportion to their number) round robin.
-// `tab_max` is the largest tab_elems of the launch's scenes and `halo_max`
+// `tab_max` is the largest lds_tab of the launch's scenes and `halo_max`
 // the largest halo row count; both size the dynamic LDS.
 struct FieldLaunch {
     int tw = 0, hl = 0, nw = 0;
     int elem = 8;  // stamp entry bytes: 4 = integer sums, 8 = FP64 sums
+    int vec = 2;   // stamp entries per LDS load and lane (4: 16-byte loads)
     int list_cap = 0, tab_max = 0, halo_max = 0;
     int grid = 0;
     size_t lds_bytes = 0;
@@ -170,7 +180,8 @@ struct FieldLaunch {
 FieldLaunch field_launch_for(const ListCfg &c);  // tab_max/halo_max of c, grid = c.grid
 // Workgroups of the field kernel of this shape that one compute unit holds at
 // once with `lds_bytes` of dynamic LDS (registers and LDS; 0 if unknown).
-int field_resident_blocks(int tw, int hl, int nw, size_t lds_bytes, bool multi, int elem);
+int field_resident_blocks(int tw, int hl, int nw, size_t lds_bytes, bool multi, int elem,
+                          int vec = 2);
 size_t field_lds_bytes(const FieldLaunch &f);
 hipError_t launch_field(const FieldLaunch &f, const SceneView *views, const int32_t *items,
                         int n_items, hipStream_t st, const LaunchEvents *ev = nullptr);

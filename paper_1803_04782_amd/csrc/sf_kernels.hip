@@ -466,11 +466,19 @@ __global__ __launch_bounds__(kSupThreads) void k_superpose(
 //     turns a lane's base address into the address of table entry
 //     (lane su - source);
 //  4. each wave walks the contiguous part of the list that lies within R rows
-//     of its own rows: per source one address add, HL/2 paired 8-byte LDS
-//     loads and HL FP64 adds per lane.
-// Lane l owns column l % TW and rows rg + G*r (rg = l / TW, G = 64 / TW,
-// r < HL) of its wave's TW x TH tile, so its HL entries of a source are G
-// apart in the column-major stamp and two of them make one ds_read2_b64.
+//     of its own rows: per source one address add, HL/2 paired LDS loads (or
+//     one 16-byte load, VEC = 4) and HL adds per lane.
+// Lane l owns column l % TW and, with rg = l / TW and G = 64 / TW, HL rows of
+// its wave's TW x TH tile: rows rg + G*r (r < HL), so that its entries of a
+// source are G apart in the column-major stamp and two of them make one
+// paired load; or (VEC = 4, integer stamps, HL = 4) rows 4*rg + r, so that
+// its four entries of a source are adjacent and one 16-byte load reads them.
+// A 16-byte LDS load must be 16-byte aligned, and the start of a lane's four
+// entries moves with the source's row: the stamp is held four times in LDS,
+// copy c shifted by c entries, and a source in row py reads the copy with
+// c = (py - pady) mod 4, which puts every lane's four entries on a 16-byte
+// boundary (lane rows start at multiples of 4 and the stride is a multiple of
+// 4).  The copy is folded into the source's list entry.
 // A halo with more than list_cap - max_row sources is processed in several
 // passes over consecutive row ranges.  The bitmap rows of the next strip
 // (possibly of the next item and scene) are requested before the current
@@ -478,6 +486,7 @@ __global__ __launch_bounds__(kSupThreads) void k_superpose(
 // belong to scenes with different tables.
 
 typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef int i32x4 __attribute__((ext_vector_type(4)));
 
 // Exclusive prefix sum over the lanes of a wave of counts in [0, 255], and the
 // wave total, from eight ballots.
@@ -511,15 +520,24 @@ __device__ __forceinline__ int lower_bound_lds(const int *a, int n, int v)
 }
 
 // The HL stamp entries of one source for this lane (LDS byte address a, rows
-// G apart) added to acc.
-template <int HL, int G, typename T>
+// G apart, or with V4 four adjacent integers at a 16-byte aligned address)
+// added to acc.
+template <int HL, int G, bool V4, typename T>
 __device__ __forceinline__ void gather_one(T *acc, uint32_t a)
 {
-    typedef const __attribute__((address_space(3))) T *ptr;
-    const ptr s = reinterpret_cast<ptr>(a);
     T v[HL];
+    if constexpr (V4) {
+        static_assert(HL == 4 && sizeof(T) == 4, "16-byte loads of four integers");
+        typedef const __attribute__((address_space(3))) i32x4 *ptr4;
+        const i32x4 w = *reinterpret_cast<ptr4>(a);
 #pragma unroll
-    for (int r = 0; r < HL; ++r) v[r] = s[G * r];
+        for (int r = 0; r < 4; ++r) v[r] = w[r];
+    } else {
+        typedef const __attribute__((address_space(3))) T *ptr;
+        const ptr s = reinterpret_cast<ptr>(a);
+#pragma unroll
+        for (int r = 0; r < HL; ++r) v[r] = s[G * r];
+    }
 #pragma unroll
     for (int r = 0; r < HL; ++r) acc[r] += v[r];
 }
@@ -528,6 +546,7 @@ __device__ __forceinline__ void gather_one(T *acc, uint32_t a)
 // registers (a whole SceneView copy would be placed in private memory).
 struct FieldScene {
     int W, H, wpr, R, tiles_x, stride, padx, pady, max_row, tab_vecs, periodic;
+    int rounds;  // integer stamps: rounds of 8 sources summed in 32 bits before a flush
     // the stamp (doubles, or integers in units of q), tab_vecs 16-byte vectors
     gptr<const f64x2> tab;
     double q;
@@ -553,6 +572,7 @@ __device__ __forceinline__ FieldScene field_scene(const SceneView &v)
     f.max_row = v.max_row;
     f.tab_vecs = INT ? v.tab_elems / 4 : v.tab_elems / 2;
     f.periodic = v.periodic;
+    f.rounds = v.int_rounds;
     f.tab = to_global(INT ? reinterpret_cast<const f64x2 *>(v.tabi)
                           : reinterpret_cast<const f64x2 *>(v.tab));
     f.q = v.q;
@@ -618,15 +638,21 @@ struct FieldWork {
 // q = 2^(e_min - 23) (4 bytes, half the LDS traffic of a double), summed in
 // 32-bit integers that are moved into FP64 accumulators every 8 sources
 // (8 * max|strength| / q < 2^31 for such laws, so no partial sum overflows);
-// Phi = q * sum, the same exact value, rounded once.  Otherwise the stamp
-// holds doubles summed in FP64.
-template <int TW, int HL, int NW, bool MULTI, bool DUAL = false, bool INT = false>
+// Phi = q * sum, the same exact value, rounded once.  A law whose strengths
+// allow it sums several rounds of 8 before moving the sums (the scene's
+// int_rounds, with 8 * int_rounds * max|strength| / q < 2^31).  Otherwise the
+// stamp holds doubles summed in FP64.
+// VEC: stamp entries per LDS load and lane, 2 (paired loads) or 4 (one
+// 16-byte load; integer stamps, HL = 4, the stamp held four times).
+template <int TW, int HL, int NW, bool MULTI, bool DUAL = false, bool INT = false, int VEC = 2>
 __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
                                                    const SceneView *__restrict__ views,
                                                    const int4 *__restrict__ items, int n_items,
                                                    int per, int tab_max, int list_cap)
 {
     static_assert(!(DUAL && MULTI), "the update launch covers one scene");
+    static_assert(VEC == 2 || (VEC == 4 && INT && HL == 4), "16-byte loads: integers, HL = 4");
+    constexpr bool V4 = VEC == 4;
     constexpr int NSRC = DUAL ? 2 : 1;
     using T = std::conditional_t<INT, int, double>;  // a stamp entry
     constexpr uint32_t ES = sizeof(T);
@@ -641,6 +667,8 @@ __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
     const int tid = (int)threadIdx.x, lane = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int col = lane % TW, rg = lane / TW;
+    // row of this lane's r-th su within its wave's tile
+    auto lrow = [&](int r) { return V4 ? HL * rg + r : rg + G * r; };
     const uint32_t tbase = (uint32_t)(uintptr_t)((lds_ptr<T>)tab);
 
     // Work items of one scene by XCD: workgroup b runs on XCD b mod 8 (each
@@ -677,7 +705,24 @@ __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const int i = i0 + u * NT + tid;
-            if (i < n2) tab2[i] = r[u];
+            if (i < n2) {
+                if constexpr (V4) {
+                    // copy c at integer c * (4 * n2 + 1): shifted by c entries
+                    const i32x4 w = __builtin_bit_cast(i32x4, r[u]);
+                    int *const ti = reinterpret_cast<int *>(tab);
+                    reinterpret_cast<i32x4 *>(ti)[i] = w;
+#pragma unroll
+                    for (int c = 1; c < 4; ++c) {
+                        int *const d = ti + c * (4 * n2 + 1) + 4 * i;
+                        d[0] = w[0];
+                        d[1] = w[1];
+                        d[2] = w[2];
+                        d[3] = w[3];
+                    }
+                } else {
+                    tab2[i] = r[u];
+                }
+            }
         }
     };
     auto load_table = [&](const FieldScene &s) {
@@ -753,7 +798,7 @@ __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
         const int x = tx * TW + col, y0 = ty * WT + wv * TH;
 #pragma unroll
         for (int r = 0; r < HL; ++r) {
-            const int y = y0 + rg + G * r;
+            const int y = y0 + lrow(r);
             const size_t c = (size_t)min(y, s.H - 1) * s.W + min(x, s.W - 1);
             sv_n[r] = s.S[c];
             pv_n[r] = 0.0;
@@ -842,7 +887,10 @@ __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
         const int ra = max(y0w - R, ya) - ya;
         const int rb = min(y0w + TH - 1 + R, yb) - ya;
         const uint32_t lb = (uint32_t)opaque_lane(
-            (int)(tbase + (uint32_t)((X0 + col + padx) * stride + (y0w + rg + pady)) * ES));
+            (int)(tbase + (uint32_t)((X0 + col + padx) * stride + (y0w + lrow(0) + pady)) * ES));
+        // V4: bytes from one stamp copy to the next (each copy is 4 * tab_vecs
+        // integers plus one of shift)
+        const uint32_t copy_step = (uint32_t)v.tab_vecs * 16u + 4u;
         // accs: the running sums (INT: 32-bit, moved into sums64 by flush())
         T accs[NSRC][HL];
         double sums64[NSRC][HL];
@@ -898,6 +946,9 @@ __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
                 // the source (px, py) in the column-major stamp, modulo 2^32
                 if (tid < nr && cnt > 0 && excl >= start && excl < end) {
                     const uint32_t py = (uint32_t)(ya + tid);
+                    // V4: the copy whose shift aligns this row's sources
+                    const uint32_t coff =
+                        V4 ? (uint32_t)((ya + tid - pady) & 3) * copy_step : 0u;
                     int o = excl - start;
 #pragma unroll
                     for (int j = 0; j < 3; ++j) {
@@ -907,7 +958,7 @@ __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
                             const int b = __builtin_ctzll(mj);
                             mj &= mj - 1ull;
                             const uint32_t px = (uint32_t)(xw + b);
-                            list[o++] = (int)(0u - (px * (uint32_t)stride + py) * ES);
+                            list[o++] = (int)(coff - (px * (uint32_t)stride + py) * ES);
                         }
                     }
                 }
@@ -918,19 +969,42 @@ __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
                     const int lo = __builtin_amdgcn_readfirstlane(max(row_excl[ra], start) - start);
                     const int hi = __builtin_amdgcn_readfirstlane(min(row_excl[rb + 1], end) - start);
                     int i = lo;
-                    for (; i < hi && (i & 3); ++i) gather_one<HL, G>(acc, lb + (uint32_t)list[i]);
+                    for (; i < hi && (i & 3); ++i)
+                        gather_one<HL, G, V4>(acc, lb + (uint32_t)list[i]);
                     flush(src);
                     const int4 *list4 = reinterpret_cast<const int4 *>(list);
                     typedef const __attribute__((address_space(3))) T *lds_d;
+                    typedef const __attribute__((address_space(3))) i32x4 *lds_4;
+                    // the HL entries of a source at LDS byte address ad
+                    auto read_at = [&](uint32_t ad, T(&u)[HL]) {
+                        if constexpr (V4) {
+                            const i32x4 w = *reinterpret_cast<lds_4>(ad);
+#pragma unroll
+                            for (int r = 0; r < HL; ++r) u[r] = w[r];
+                        } else {
+                            const lds_d sp = reinterpret_cast<lds_d>(ad);
+#pragma unroll
+                            for (int r = 0; r < HL; ++r) u[r] = sp[G * r];
+                        }
+                    };
                     // eight sources per round: eight table reads are in flight
                     // before the adds, and the next round's entries are read
                     // behind them (reading up to eight entries past the pass stays
-                    // inside the allocation: row_excl follows the list)
+                    // inside the allocation: row_excl follows the list).  Integer
+                    // sums are moved into FP64 every v.rounds rounds.
                     if (i + 8 <= hi) {
                         int4 ea = list4[i >> 2];
                         int4 eb = list4[(i >> 2) + 1];
+                        int rounds = 0;
                         for (; i + 8 <= hi; i += 8) {
+                            // the round's addresses are formed before the next
+                            // entries are requested into the same registers
                             const int a[8] = {ea.x, ea.y, ea.z, ea.w, eb.x, eb.y, eb.z, eb.w};
+                            uint32_t ad[8];
+#pragma unroll
+                            for (int u = 0; u < 8; ++u) ad[u] = lb + (uint32_t)a[u];
+                            asm volatile("" : "+v"(ad[0]), "+v"(ad[1]), "+v"(ad[2]), "+v"(ad[3]),
+                                         "+v"(ad[4]), "+v"(ad[5]), "+v"(ad[6]), "+v"(ad[7]));
                             ea = list4[(i >> 2) + 2];
                             eb = list4[(i >> 2) + 3];
                             // the compiler keeps this order: next entries, table
@@ -938,30 +1012,26 @@ __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
                             asm volatile("" ::: "memory");
                             T u8[8][HL];
 #pragma unroll
-                            for (int u = 0; u < 8; ++u) {
-                                const lds_d sp = reinterpret_cast<lds_d>(lb + (uint32_t)a[u]);
-#pragma unroll
-                                for (int r = 0; r < HL; ++r) u8[u][r] = sp[G * r];
-                            }
+                            for (int u = 0; u < 8; ++u) read_at(ad[u], u8[u]);
                             asm volatile("" ::: "memory");
 #pragma unroll
                             for (int u = 0; u < 8; ++u) {
 #pragma unroll
                                 for (int r = 0; r < HL; ++r) acc[r] += u8[u][r];
                             }
-                            flush(src);
+                            if (++rounds >= v.rounds) {
+                                flush(src);
+                                rounds = 0;
+                            }
                         }
+                        flush(src);
                     }
                     if (i + 4 <= hi) {
                         const int4 ea = list4[i >> 2];
                         const int a[4] = {ea.x, ea.y, ea.z, ea.w};
                         T u4[4][HL];
 #pragma unroll
-                        for (int u = 0; u < 4; ++u) {
-                            const lds_d sp = reinterpret_cast<lds_d>(lb + (uint32_t)a[u]);
-#pragma unroll
-                            for (int r = 0; r < HL; ++r) u4[u][r] = sp[G * r];
-                        }
+                        for (int u = 0; u < 4; ++u) read_at(lb + (uint32_t)a[u], u4[u]);
 #pragma unroll
                         for (int u = 0; u < 4; ++u) {
 #pragma unroll
@@ -969,7 +1039,7 @@ __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
                         }
                         i += 4;
                     }
-                    for (; i < hi; ++i) gather_one<HL, G>(acc, lb + (uint32_t)list[i]);
+                    for (; i < hi; ++i) gather_one<HL, G, V4>(acc, lb + (uint32_t)list[i]);
                     flush(src);
                 }
                 __syncthreads();
@@ -981,7 +1051,7 @@ __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
         if (x < W) {
 #pragma unroll
             for (int r = 0; r < HL; ++r) {
-                const int y = y0w + rg + G * r;
+                const int y = y0w + lrow(r);
                 // the exact sums: integers times q (a power of two), or the FP64 sums
                 const double a0 = INT ? sums64[0][r] * v.q : (double)accs[0][r];
                 const double a1 = INT ? sums64[NSRC - 1][r] * v.q : (double)accs[NSRC - 1][r];
@@ -2243,8 +2313,25 @@ namespace {
 // conflict costs up to n times a conflict-free pass (16-column tiles of
 // doubles: an odd stride runs at the rate of a broadcast read, a stride of
 // 2 mod 4 takes 1.6-1.75x as long, 4 mod 8 about 2.8x, 8 mod 16 about 5.6x).
-int bank_degree(int tw, int stride, int elem)
+// 16-byte loads (ds_read_b128; lane l reads the four integers from
+// col*stride + 4*rg, stride a multiple of 4) run in passes of 32 lanes,
+// conflict-free when their 16-byte units are distinct modulo 32 (probe: a
+// conflict-free pass moves about 280 bytes per clock, against about 130 for
+// the paired 4-byte loads; a 2-way conflict about 170).
+int bank_degree(int tw, int stride, int elem, int vec = 2)
 {
+    if (vec == 4) {
+        int worst = 0;
+        for (int p = 0; p < 64; p += 32) {
+            int hits[32] = {0};
+            for (int l = p; l < p + 32; ++l) {
+                const int col = l % tw, rg = l / tw;
+                ++hits[(col * (stride / 4) + rg) % 32];
+            }
+            for (int b = 0; b < 32; ++b) worst = hits[b] > worst ? hits[b] : worst;
+        }
+        return worst;
+    }
     const int lanes = elem == 8 ? 16 : 32;
     int worst = 0;
     for (int p = 0; p < 64; p += lanes) {
@@ -2260,10 +2347,11 @@ int bank_degree(int tw, int stride, int elem)
 
 }  // namespace
 
-ListCfg make_list_cfg(int radius, int tw, int hl, int nw, int list_cap, int elem)
+ListCfg make_list_cfg(int radius, int tw, int hl, int nw, int list_cap, int elem, int vec)
 {
     ListCfg c;
     c.elem = elem;
+    c.vec = vec;
     c.tw = tw;
     c.hl = hl;
     c.nw = nw;
@@ -2275,9 +2363,17 @@ ListCfg make_list_cfg(int radius, int tw, int hl, int nw, int list_cap, int elem
     c.pady = radius + c.th - 1;
     c.ncols = 2 * c.padx + 1;
     c.nrows = 2 * c.pady + 1;
+    // A column holds the band |dy| <= R at rows pady - R .. pady + R; a read
+    // reaches up to TH - 1 rows past the band on either side.  With stride >=
+    // 2R + TH those reads land on zero rows of the same column or of the
+    // neighbouring column (the next column's band starts TH - 1 rows into
+    // it), so the columns need not hold all nrows rows; one zero column more
+    // at the end takes the last column's overrun.
+    const int smin = 2 * radius + c.th;
     int best = -1, best_deg = 1 << 30;
-    for (int s = c.nrows; s < c.nrows + 64; ++s) {
-        const int d = bank_degree(tw, s, elem);
+    for (int s = smin; s < smin + 64; ++s) {
+        if (vec == 4 && s % 4 != 0) continue;  // lane rows 16-byte aligned in every column
+        const int d = bank_degree(tw, s, elem, vec);
         if (d < best_deg) {
             best_deg = d;
             best = s;
@@ -2287,11 +2383,12 @@ ListCfg make_list_cfg(int radius, int tw, int hl, int nw, int list_cap, int elem
     c.stride = best;
     // loaded as 16-byte vectors: 2 doubles or 4 integers each
     const int per_vec = 16 / elem;
-    c.tab_elems = (c.ncols * c.stride + per_vec - 1) / per_vec * per_vec;
+    c.tab_elems = ((c.ncols + 1) * c.stride + per_vec - 1) / per_vec * per_vec;
+    c.lds_tab = vec == 4 ? 4 * c.tab_elems + 4 : c.tab_elems;
     c.max_row = tw + 2 * radius;
     c.list_cap = list_cap;
     c.halo_rows = c.wt + 2 * radius;
-    c.lds_bytes = (size_t)c.tab_elems * elem + (size_t)list_cap * 4 +
+    c.lds_bytes = (size_t)c.lds_tab * elem + (size_t)list_cap * 4 +
                   (size_t)(c.halo_rows + 1) * 4;
     return c;
 }
@@ -2316,8 +2413,9 @@ ListCfg pick_list_cfg(int radius, size_t max_lds, int elem)
 }
 
 void set_view_layout(SceneView &v, const ListCfg &c, const double *tab, const int32_t *tabi,
-                     double q)
+                     double q, int int_rounds)
 {
+    v.int_rounds = int_rounds;
     v.tiles_x = (v.W + c.tw - 1) / c.tw;
     v.n_strips = v.tiles_x * ((v.H + c.wt - 1) / c.wt);
     v.stride = c.stride;
@@ -2337,10 +2435,11 @@ FieldLaunch field_launch_for(const ListCfg &c)
     f.hl = c.hl;
     f.nw = c.nw;
     f.list_cap = c.list_cap;
-    f.tab_max = c.tab_elems;
+    f.tab_max = c.lds_tab;
     f.halo_max = c.halo_rows;
     f.grid = c.grid;
     f.elem = c.elem;
+    f.vec = c.vec;
     f.lds_bytes = field_lds_bytes(f);
     return f;
 }
@@ -2350,16 +2449,22 @@ size_t field_lds_bytes(const FieldLaunch &f)
     return (size_t)f.tab_max * f.elem + (size_t)f.list_cap * 4 + (size_t)(f.halo_max + 1) * 4;
 }
 
-// Compiled shapes (strip width TW, rows per lane HL, waves per workgroup NW).
+// Compiled shapes (strip width TW, rows per lane HL, waves per workgroup NW);
+// the 16-byte-load shapes (VEC = 4) are compiled for integer stamps only.
 #define SF_LIST_SHAPES(X)                                                                     \
     X(16, 2, 4) X(16, 2, 8) X(16, 4, 4) X(16, 4, 8) X(32, 2, 4) X(32, 2, 8) X(32, 4, 4)         \
     X(8, 2, 4) X(8, 4, 4)
+#define SF_V4_SHAPES(X) X(16, 4, 4) X(16, 4, 8) X(32, 4, 4) X(8, 4, 4)
 
-bool list_shape_compiled(int tw, int hl, int nw)
+bool list_shape_compiled(int tw, int hl, int nw, int vec, int elem)
 {
 #define SF_KNOWN(a, b, n) \
     if (tw == a && hl == b && nw == n) return true;
-    SF_LIST_SHAPES(SF_KNOWN)
+    if (vec == 2) {
+        SF_LIST_SHAPES(SF_KNOWN)
+    } else if (vec == 4 && elem == 4) {
+        SF_V4_SHAPES(SF_KNOWN)
+    }
 #undef SF_KNOWN
     return false;
 }
@@ -2375,7 +2480,12 @@ hipError_t set_field_lds_limit(size_t bytes)
     SF_SET1(a, b, n, false, false, false) SF_SET1(a, b, n, true, false, false)                 \
     SF_SET1(a, b, n, false, true, false) SF_SET1(a, b, n, false, false, true)                  \
     SF_SET1(a, b, n, true, false, true) SF_SET1(a, b, n, false, true, true)
+#define SF_SET4(a, b, n)                                                                         \
+    SF_SET1(a, b, n, false, false, true, 4) SF_SET1(a, b, n, true, false, true, 4)             \
+    SF_SET1(a, b, n, false, true, true, 4)
     SF_LIST_SHAPES(SF_SET)
+    SF_V4_SHAPES(SF_SET4)
+#undef SF_SET4
 #undef SF_SET
 #undef SF_SET1
     return hipSuccess;
@@ -2387,6 +2497,16 @@ hipError_t launch_field(const FieldLaunch &f, const SceneView *views, const int3
     const int grid = std::max(1, std::min(f.grid, n_items));
     const int4 *it = reinterpret_cast<const int4 *>(items);
     const SceneView none = {};
+#define SF_DISPATCH4(a, b, n)                                                                     \
+    if (f.tw == a && f.hl == b && f.nw == n)                                                    \
+        return launch(k_field<a, b, n, true, false, true, 4>, dim3(grid), dim3(n * 64),          \
+                      f.lds_bytes, st, ev, none, views, it, n_items, 0, f.tab_max, f.list_cap);
+    if (f.vec == 4) {
+        if (f.elem != 4) return hipErrorInvalidValue;
+        SF_V4_SHAPES(SF_DISPATCH4)
+        return hipErrorInvalidValue;
+    }
+#undef SF_DISPATCH4
 #define SF_DISPATCH(a, b, n)                                                                      \
     if (f.tw == a && f.hl == b && f.nw == n)                                                    \
         return f.elem == 4                                                                      \
@@ -2401,11 +2521,23 @@ hipError_t launch_field(const FieldLaunch &f, const SceneView *views, const int3
     return hipErrorInvalidValue;
 }
 
-int field_resident_blocks(int tw, int hl, int nw, size_t lds_bytes, bool multi, int elem)
+int field_resident_blocks(int tw, int hl, int nw, size_t lds_bytes, bool multi, int elem, int vec)
 {
     int n = 0;
     hipError_t e = hipErrorInvalidValue;
     const void *fn = nullptr;
+    if (vec == 4) {
+        if (elem != 4) return 0;
+#define SF_OCC4(a, b, w)                                                                          \
+    if (tw == a && hl == b && nw == w) {                                                         \
+        fn = multi ? reinterpret_cast<const void *>(&k_field<a, b, w, true, false, true, 4>)      \
+                   : reinterpret_cast<const void *>(&k_field<a, b, w, false, false, true, 4>);    \
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, w * 64, lds_bytes);             \
+    }
+        SF_V4_SHAPES(SF_OCC4)
+#undef SF_OCC4
+        return e == hipSuccess ? n : 0;
+    }
 #define SF_OCC(a, b, w)                                                                           \
     if (tw == a && hl == b && nw == w) {                                                         \
         if (elem == 4)                                                                           \
@@ -2441,6 +2573,17 @@ hipError_t launch_field_one(const FieldLaunch &f, const SceneView &view, int per
 {
     const int n_items = std::max(1, (view.n_strips + per - 1) / per);
     const int grid = std::max(1, std::min(f.grid, n_items));
+#define SF_DISPATCH4(a, b, n)                                                                     \
+    if (f.tw == a && f.hl == b && f.nw == n)                                                    \
+        return launch(k_field<a, b, n, false, false, true, 4>, dim3(grid), dim3(n * 64),         \
+                      f.lds_bytes, st, ev, view, (const SceneView *)nullptr,                    \
+                      (const int4 *)nullptr, n_items, per, f.tab_max, f.list_cap);
+    if (f.vec == 4) {
+        if (f.elem != 4) return hipErrorInvalidValue;
+        SF_V4_SHAPES(SF_DISPATCH4)
+        return hipErrorInvalidValue;
+    }
+#undef SF_DISPATCH4
 #define SF_DISPATCH(a, b, n)                                                                      \
     if (f.tw == a && f.hl == b && f.nw == n)                                                    \
         return f.elem == 4                                                                      \
@@ -2460,6 +2603,17 @@ hipError_t launch_field_update(const FieldLaunch &f, const SceneView &view, int 
 {
     const int n_items = std::max(1, (view.n_strips + per - 1) / per);
     const int grid = std::max(1, std::min(f.grid, n_items));
+#define SF_DISPATCH4(a, b, n)                                                                     \
+    if (f.tw == a && f.hl == b && f.nw == n)                                                    \
+        return launch(k_field<a, b, n, false, true, true, 4>, dim3(grid), dim3(n * 64),          \
+                      f.lds_bytes, st, ev, view, (const SceneView *)nullptr,                    \
+                      (const int4 *)nullptr, n_items, per, f.tab_max, f.list_cap);
+    if (f.vec == 4) {
+        if (f.elem != 4) return hipErrorInvalidValue;
+        SF_V4_SHAPES(SF_DISPATCH4)
+        return hipErrorInvalidValue;
+    }
+#undef SF_DISPATCH4
 #define SF_DISPATCH(a, b, n)                                                                      \
     if (f.tw == a && f.hl == b && f.nw == n)                                                    \
         return f.elem == 4                                                                      \

@@ -91,9 +91,14 @@ def test_batch_members_match_scenes_alone(sf):
     dict(tw=32, hl=4, vec=2, nw=4, items_per_block=1),
     dict(tw=8, hl=2, vec=2, nw=4, list_cap=4096, items_per_block=64),
     dict(tw=16, hl=4, vec=2, nw=8, blocks_per_cu=1),
+    dict(tw=16, hl=4, vec=4, nw=4),
+    dict(tw=32, hl=4, vec=4, nw=4, items_per_block=1),
+    dict(tw=8, hl=4, vec=4, nw=4, list_cap=1024, items_per_block=64),
     dict(groups=1),
     dict(groups=2, split_radius=16,
          group=[dict(tw=32, hl=4, vec=2, nw=4), dict(tw=16, hl=2, vec=2, nw=8)]),
+    dict(groups=2, split_radius=8,
+         group=[dict(tw=16, hl=4, vec=4, nw=8), dict(tw=16, hl=4, vec=4, nw=4)]),
 ])
 def test_batch_tilings_identical(sf, tiling):
     scs = _mixed_scenes()[:5]
@@ -216,6 +221,8 @@ def test_batch_membership_rules(sf):
         sf.Batch([])
     with pytest.raises(sf.SfError):
         sf.Batch([gs[2]], tiling=dict(tw=12, hl=2, vec=2, nw=4))  # not a compiled shape
+    with pytest.raises(sf.SfError):
+        sf.Batch([gs[2]], tiling=dict(tw=16, hl=2, vec=4, nw=4))  # 16-byte loads need HL 4
     b.step(2)
     b.close()
     gs[0].step(1)  # back on its own

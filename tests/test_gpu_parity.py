@@ -115,6 +115,27 @@ def test_dense_crowd_multipass_lockstep(sf):
     _run_lockstep(sf, sc, 12)
 
 
+# 16-byte-load shapes (TWxHLx4xNW[xCAP]) against the oracle: ragged sizes over
+# several strips, a torus (halo rows of negative index pick their stamp copy
+# modulo 4), an attractive law, and a small list that forces several passes
+VEC4_CASES = [
+    ("16x4x4x4", lambda: scenes.random_scene(150, 77, n_peds=2200, radius=9, seed=61,
+                                             bernoulli=0.03, exits=("E", "N"), exit_width=6)),
+    ("8x4x4x4", lambda: scenes.flow_scene(131, 97, 0.35, 8, radius=6, seed=62)),
+    ("32x4x4x4", lambda: scenes.random_scene(173, 101, n_peds=1800, radius=13, seed=63,
+                                             exits=("W",), exit_width=8, k=-0.6)),
+    ("16x4x4x8x400", lambda: scenes.random_scene(120, 110, n_peds=0, radius=16, seed=64,
+                                                 bernoulli=0.02, exits=("S",), exit_width=6,
+                                                 occupancy=0.5)),
+]
+
+
+@pytest.mark.parametrize("shape,make", VEC4_CASES, ids=[c[0] for c in VEC4_CASES])
+def test_vec4_shapes_lockstep(sf, monkeypatch, shape, make):
+    monkeypatch.setenv("SF_TILE", shape)
+    _run_lockstep(sf, make(), 8)
+
+
 def test_hall1024_lockstep_sampled(sf):
     # the benchmark workload at full size, same launch configuration
     sc = scenes.hall1024()
@@ -182,8 +203,10 @@ def test_deterministic_and_resume(sf):
         assert np.array_equal(a.field(), b.field())
 
 
+# TWxHLxVECxNW: VEC 4 reads a lane's four entries of a source with one
+# 16-byte load from one of four shifted copies of the stamp
 SHAPES = ("16x2x2x4", "16x2x2x8", "16x4x2x4", "16x4x2x8", "32x2x2x4", "32x2x2x8",
-          "32x4x2x4", "8x2x2x4", "8x4x2x4")
+          "32x4x2x4", "8x2x2x4", "8x4x2x4", "16x4x4x4", "16x4x4x8", "32x4x4x4", "8x4x4x4")
 
 
 def test_tile_shape_invariance(sf, monkeypatch):
