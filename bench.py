@@ -652,7 +652,7 @@ def bench_ensemble_classes(args, stream):
     """The ensemble's field pass by radius class: the scenes of each radius as
     a one-group batch (tuned), back-to-back field passes timed with HIP
     events; beside each, the class's contributions and its HBM and ALU
-    floors, and the default two-group batch of all 256 scenes."""
+    floors, and the default grouping of all 256 scenes."""
     import torch
 
     from paper_1803_04782_amd import scenes, sf
@@ -702,7 +702,7 @@ def bench_ensemble_classes(args, stream):
            "vs_baseline": None, "dtype": "i32 sums (exact)", "data": "synthetic",
            "config": {"workload": "ensemble-classes", "scenes": len(scs),
                       "parallelism": "single-gpu"},
-           "classes": rows, "two_groups": {"pass_us": all_us, "tiling": tiling},
+           "classes": rows, "default_groups": {"pass_us": all_us, "tiling": tiling},
            "roofline": None, "cpu_baseline": None}
     print(json.dumps(out), flush=True)
 

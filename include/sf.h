@@ -340,8 +340,8 @@ void sf_destroy_scene(sf_scene *s);
  * scene, and runs of ticks are replayed from captured HIP graphs.  Every
  * member evolves exactly as under sf_step alone: the kernels are the same,
  * per scene, and the field's summation order does not depend on the launch.
- * (Scenes are split into at most two groups, each with its own three launches
- * per tick; see sf_batch_tiling.)
+ * (Scenes are split into at most SF_MAX_GROUPS groups by radius, each with its
+ * own three launches per tick; see sf_batch_tiling.)
  *
  * While a scene belongs to a batch its work runs on the batch's stream:
  * sf_field, sf_positions, sf_last_moves, sf_static_field, sf_stats and sf_sync
@@ -355,25 +355,35 @@ typedef struct sf_batch sf_batch; /* opaque, library-owned */
  * default). */
 typedef struct {
     int32_t tw, hl, vec, nw;   /* field kernel: strip width in su, rows per lane,
-                                  stamp entries per LDS read (2), waves per
-                                  workgroup; one of the compiled shapes, or all
-                                  four zero (vec 0 reads as 2)                 */
+                                  stamp entries per LDS read (2: paired loads;
+                                  4: one 16-byte load, integer stamps and hl 4
+                                  only), waves per workgroup; one of the
+                                  compiled shapes, or all four zero (vec 0
+                                  reads as 2)                                  */
     int32_t list_cap;          /* field kernel: source-list entries in LDS      */
     int32_t blocks_per_cu;     /* field kernel: workgroups per compute unit     */
     int32_t items_per_block;   /* field kernel: work items (runs of strips of
                                   one scene) dealt to each workgroup per tick  */
 } sf_group_tiling;
 
-/* A batch splits its scenes into up to two groups by field radius: group 0
- * holds the scenes with radius <= split_radius, group 1 the others.  Each
+/* A batch splits its scenes into up to SF_MAX_GROUPS groups by field radius:
+ * group g holds the scenes with split_radius[g-1] < radius <= split_radius[g]
+ * (group 0 from radius 0, the last group up to the largest radius).  Each
  * group has its own launches and tiling (small and large stamps favour
- * different tile shapes and LDS budgets), and the two groups' ticks run as
- * independent streams of work. */
+ * different tile shapes and LDS budgets), and the groups' ticks run as
+ * independent streams of work that the GPU overlaps. */
+#define SF_MAX_GROUPS 4
 typedef struct {
-    int32_t groups;            /* 0 = two groups when both are non-empty, 1 = one
-                                  group (group[0]), 2 = two groups              */
-    int32_t split_radius;      /* 0 = default (8)                               */
-    sf_group_tiling group[2];
+    int32_t groups;            /* 0 = default: one group per distinct radius when
+                                  there are at most SF_MAX_GROUPS of them, else
+                                  SF_MAX_GROUPS groups of about equal estimated
+                                  field work; 1..SF_MAX_GROUPS = that many
+                                  (each must be non-empty)                      */
+    int32_t split_radius[SF_MAX_GROUPS - 1];
+                               /* upper radius of groups 0..groups-2, strictly
+                                  increasing; all zero = chosen as for the
+                                  default (two groups: split at radius 8)       */
+    sf_group_tiling group[SF_MAX_GROUPS];
 } sf_batch_tiling;
 
 /* Group n_scenes (>= 1, distinct, none in another batch, all on the current

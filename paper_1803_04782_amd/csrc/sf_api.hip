@@ -85,8 +85,8 @@ struct sf_scene {
     float *P = nullptr;
     int32_t *D = nullptr;
     uint8_t *exitm = nullptr;
-    unsigned long long *occ = nullptr, *claim = nullptr, *key = nullptr;
-    unsigned int *regs = nullptr;  // registrations per su in the current tick
+    unsigned long long *occ = nullptr, *key = nullptr;
+    sf::ClaimRec *claims = nullptr;  // per su: election word and registration count
     int32_t *pos = nullptr, *target = nullptr;
     // Per-pedestrian arrays use internal ids: live pedestrians in row-major
     // order of their positions when the state was set, then the evacuated
@@ -151,7 +151,7 @@ struct GroupLayout {
 struct BatchLayout {
     sf_batch_tiling t = {};
     int n_groups = 0;
-    GroupLayout g[2];
+    GroupLayout g[SF_MAX_GROUPS];
     SceneView *d_all = nullptr;               // every member, batch order (totals)
     unsigned long long *d_totals = nullptr;   // 16 words per scene (sf_batch_stats)
     std::vector<void *> bufs;
@@ -162,10 +162,11 @@ struct BatchLayout {
 struct sf_batch {
     int device = 0;
     hipStream_t stream = nullptr;   // where ticks run (caller's stream)
-    hipStream_t aux = nullptr;      // second group's ticks (joined back to `stream`)
+    // ticks of groups 1.. (forked from and joined back to `stream`)
+    hipStream_t aux[SF_MAX_GROUPS - 1] = {};
     hipStream_t capture = nullptr;  // private streams on which graphs are captured
-    hipStream_t capture_aux = nullptr;
-    hipEvent_t fork = nullptr, join = nullptr;
+    hipStream_t capture_aux[SF_MAX_GROUPS - 1] = {};
+    hipEvent_t fork = nullptr, join[SF_MAX_GROUPS - 1] = {};
     int ncu = 0;
     size_t max_lds = 0;
     std::vector<sf_scene *> scenes;
@@ -798,8 +799,7 @@ int create(const sf_scene_desc *d, void *hip_stream, sf_scene **out)
         (rc = dalloc(s, &s->tab, (size_t)s->lc.tab_elems, "phi table")) ||
         (s->int_ok && (rc = dalloc(s, &s->tabi, (size_t)s->lc.tab_elems, "phi table"))) ||
         (rc = dalloc(s, &s->occ, (size_t)s->wpr * s->H, "occupancy")) ||
-        (rc = dalloc(s, &s->claim, n, "claims")) || (rc = dalloc(s, &s->key, N, "keys")) ||
-        (rc = dalloc(s, &s->regs, n, "registrations")) ||
+        (rc = dalloc(s, &s->claims, n, "claims")) || (rc = dalloc(s, &s->key, N, "keys")) ||
         (rc = dalloc(s, &s->pos, N, "positions")) || (rc = dalloc(s, &s->target, N, "targets")) ||
         (rc = dalloc(s, &s->ext, N, "id map")) ||
         (rc = dalloc(s, &s->flags, (N + 3) & ~(size_t)3, "flags")) ||
@@ -814,9 +814,7 @@ int create(const sf_scene_desc *d, void *hip_stream, sf_scene **out)
     if (!s->h_walk.empty() && (rc = dalloc(s, &s->walk, N, "walk periods"))) return rc;
 
     hipStream_t st = s->stream;
-    SF_HIP(sf::launch_fill_u64(s->claim, n, ~0ull, st), "clear claims");
-    SF_HIP(sf::launch_fill_i32(reinterpret_cast<int32_t *>(s->regs), n, 0, st),
-           "clear registrations");
+    SF_HIP(sf::launch_clear_claims(s->claims, n, st), "clear claims");
     SF_HIP(sf::launch_fill_i32(s->target, N, 0, st), "clear targets");
     SF_HIP(sf::launch_fill_i32(reinterpret_cast<int32_t *>(s->flags), (N + 3) / 4, 0, st),
            "clear flags");
@@ -867,8 +865,7 @@ int setup_launches(sf_scene *s)
     v.S = s->S;
     v.P = s->P;
     v.occ = s->occ;
-    v.claim = s->claim;
-    v.regs = s->regs;
+    v.claims = s->claims;
     v.key = s->key;
     v.ctr = s->ctr;
     v.pos = s->pos;
@@ -1093,25 +1090,69 @@ void drop_graphs(sf_batch *b)
 
 constexpr int kDefaultSplitRadius = 8;
 
-// Member indices of each group for tiling `t` (groups and split filled in).
-int split_members(const sf_batch *b, sf_batch_tiling *t, std::vector<int> (&members)[2])
+// Member indices of each group for tiling `t` (groups and splits filled in).
+int split_members(const sf_batch *b, sf_batch_tiling *t,
+                  std::vector<int> (&members)[SF_MAX_GROUPS])
 {
-    if (t->groups < 0 || t->groups > 2) return fail(SF_EINVAL, "groups %d outside 0..2", t->groups);
-    if (t->split_radius < 0 || t->split_radius > SF_MAX_RADIUS)
-        return fail(SF_EINVAL, "split_radius %d outside 0..%d", t->split_radius, SF_MAX_RADIUS);
-    if (t->split_radius == 0) t->split_radius = kDefaultSplitRadius;
-    members[0].clear();
-    members[1].clear();
-    for (int j = 0; j < (int)b->scenes.size(); ++j)
-        members[b->scenes[(size_t)j]->R <= t->split_radius ? 0 : 1].push_back(j);
-    if (t->groups == 0) t->groups = (!members[0].empty() && !members[1].empty()) ? 2 : 1;
-    if (t->groups == 1) {
-        for (int j : members[1]) members[0].push_back(j);
-        std::sort(members[0].begin(), members[0].end());
-        members[1].clear();
-    } else if (members[0].empty() || members[1].empty()) {
-        return fail(SF_EINVAL, "split at radius %d leaves a group empty", t->split_radius);
+    if (t->groups < 0 || t->groups > SF_MAX_GROUPS)
+        return fail(SF_EINVAL, "groups %d outside 0..%d", t->groups, SF_MAX_GROUPS);
+    for (int g = 0; g < SF_MAX_GROUPS - 1; ++g)
+        if (t->split_radius[g] < 0 || t->split_radius[g] > SF_MAX_RADIUS)
+            return fail(SF_EINVAL, "split_radius[%d] = %d outside 0..%d", g, t->split_radius[g],
+                        SF_MAX_RADIUS);
+    bool given = false;
+    for (int g = 0; g < SF_MAX_GROUPS - 1; ++g) given = given || t->split_radius[g] != 0;
+    if (!given) {
+        // distinct radii with an estimate of their field work: per su a fixed
+        // part (S, P, a strip's bookkeeping) plus the sources of a wave's halo
+        std::map<int, double> work;
+        for (const sf_scene *s : b->scenes) {
+            const double su = (double)s->W * s->H, rho = (double)s->N / su;
+            work[s->R] += su * (40.0 + rho * (2.0 * s->R + 16) * (2.0 * s->R + 16) / 4.0);
+        }
+        std::vector<std::pair<int, double>> r(work.begin(), work.end());  // by radius
+        int want = t->groups;
+        if (want == 0) want = std::min<int>((int)r.size(), SF_MAX_GROUPS);
+        if (want == 2 && t->groups == 2) {
+            t->split_radius[0] = kDefaultSplitRadius;
+        } else if (want > 1) {
+            if ((int)r.size() < want)
+                return fail(SF_EINVAL, "%d groups for %d distinct radii", want, (int)r.size());
+            // merge the neighbouring pair of smallest joint work until `want` remain
+            while ((int)r.size() > want) {
+                size_t best = 0;
+                for (size_t i = 1; i + 1 < r.size(); ++i)
+                    if (r[i].second + r[i + 1].second < r[best].second + r[best + 1].second)
+                        best = i;
+                r[best].first = r[best + 1].first;
+                r[best].second += r[best + 1].second;
+                r.erase(r.begin() + (long)best + 1);
+            }
+            for (int g = 0; g + 1 < want; ++g) t->split_radius[g] = r[(size_t)g].first;
+        }
+        t->groups = want;
+    } else if (t->groups == 0) {
+        int n = 1;
+        while (n < SF_MAX_GROUPS && t->split_radius[n - 1] != 0) ++n;
+        t->groups = n;
     }
+    if (t->groups == 0) t->groups = 1;
+    for (int g = t->groups - 1; g < SF_MAX_GROUPS - 1; ++g) t->split_radius[g] = 0;
+    for (int g = 1; g + 1 < t->groups; ++g)
+        if (t->split_radius[g] <= t->split_radius[g - 1])
+            return fail(SF_EINVAL, "split radii must increase (%d after %d)", t->split_radius[g],
+                        t->split_radius[g - 1]);
+    for (auto &m : members) m.clear();
+    for (int j = 0; j < (int)b->scenes.size(); ++j) {
+        const int R = b->scenes[(size_t)j]->R;
+        int g = 0;
+        while (g + 1 < t->groups && R > t->split_radius[g]) ++g;
+        members[g].push_back(j);
+    }
+    for (int g = 0; g < t->groups; ++g)
+        if (members[g].empty())
+            return fail(SF_EINVAL, "the split at radii %d/%d/%d leaves group %d empty",
+                        t->split_radius[0], t->split_radius[1], t->split_radius[2], g);
     return SF_OK;
 }
 
@@ -1315,7 +1356,7 @@ int build_layout(sf_batch *b, const sf_batch_tiling *req, BatchLayout *out)
         }
     } guard{&L};
     L.t = req ? *req : sf_batch_tiling{};
-    std::vector<int> members[2];
+    std::vector<int> members[SF_MAX_GROUPS];
     int rc = split_members(b, &L.t, members);
     if (rc) return rc;
     L.n_groups = L.t.groups;
@@ -1324,7 +1365,7 @@ int build_layout(sf_batch *b, const sf_batch_tiling *req, BatchLayout *out)
         if ((rc = build_group(b, members[gi], L.t.group[gi], &L.g[gi], views))) return rc;
         L.t.group[gi] = L.g[gi].t;
     }
-    if (L.n_groups == 1) L.t.group[1] = L.t.group[0];
+    for (int gi = L.n_groups; gi < SF_MAX_GROUPS; ++gi) L.t.group[gi] = sf_group_tiling{};
     if ((rc = balloc(L.bufs, &L.d_all, views.size(), "batch views")) ||
         (rc = balloc(L.bufs, &L.d_totals, views.size() * 16, "batch totals")))
         return rc;
@@ -1351,23 +1392,25 @@ int group_tick(const GroupLayout &G, hipStream_t st)
     return group_field(G, st);
 }
 
-// `k` ticks of every group: group 0 on `main`, group 1 on `aux`, forked
-// from and joined back into `main` (the groups share no scene).
-int batch_ticks(const sf_batch *b, int k, hipStream_t main, hipStream_t aux)
+// `k` ticks of every group: group 0 on `main`, group g > 0 on aux[g - 1],
+// forked from and joined back into `main` (the groups share no scene).
+int batch_ticks(const sf_batch *b, int k, hipStream_t main, const hipStream_t *aux)
 {
     const BatchLayout &L = b->cur;
     int rc;
-    if (L.n_groups == 2) {
+    if (L.n_groups > 1) {
         SF_HIP(hipEventRecord(b->fork, main), "fork");
-        SF_HIP(hipStreamWaitEvent(aux, b->fork, 0), "fork wait");
+        for (int g = 1; g < L.n_groups; ++g)
+            SF_HIP(hipStreamWaitEvent(aux[g - 1], b->fork, 0), "fork wait");
     }
-    for (int i = 0; i < k; ++i)
-        if ((rc = group_tick(L.g[0], main))) return rc;
-    if (L.n_groups == 2) {
+    for (int g = 0; g < L.n_groups; ++g) {
+        hipStream_t st = g == 0 ? main : aux[g - 1];
         for (int i = 0; i < k; ++i)
-            if ((rc = group_tick(L.g[1], aux))) return rc;
-        SF_HIP(hipEventRecord(b->join, aux), "join");
-        SF_HIP(hipStreamWaitEvent(main, b->join, 0), "join wait");
+            if ((rc = group_tick(L.g[g], st))) return rc;
+    }
+    for (int g = 1; g < L.n_groups; ++g) {
+        SF_HIP(hipEventRecord(b->join[g - 1], aux[g - 1]), "join");
+        SF_HIP(hipStreamWaitEvent(main, b->join[g - 1], 0), "join wait");
     }
     return SF_OK;
 }
@@ -1404,11 +1447,13 @@ constexpr int kGraphTicks = 8;
 
 void destroy_batch_streams(sf_batch *b)
 {
-    if (b->aux) (void)hipStreamDestroy(b->aux);
+    for (int g = 0; g < SF_MAX_GROUPS - 1; ++g) {
+        if (b->aux[g]) (void)hipStreamDestroy(b->aux[g]);
+        if (b->capture_aux[g]) (void)hipStreamDestroy(b->capture_aux[g]);
+        if (b->join[g]) (void)hipEventDestroy(b->join[g]);
+    }
     if (b->capture) (void)hipStreamDestroy(b->capture);
-    if (b->capture_aux) (void)hipStreamDestroy(b->capture_aux);
     if (b->fork) (void)hipEventDestroy(b->fork);
-    if (b->join) (void)hipEventDestroy(b->join);
 }
 
 int batch_create(sf_scene *const *scenes, int32_t n, const sf_batch_tiling *tiling,
@@ -1453,11 +1498,14 @@ int batch_create(sf_scene *const *scenes, int32_t n, const sf_batch_tiling *tili
            "LDS size");
     b->max_lds = (size_t)max_lds;
     SF_HIP(sf::set_field_lds_limit(b->max_lds - 1024), "LDS limit");
-    SF_HIP(hipStreamCreateWithFlags(&b->aux, hipStreamNonBlocking), "batch stream");
+    for (int g = 0; g < SF_MAX_GROUPS - 1; ++g) {
+        SF_HIP(hipStreamCreateWithFlags(&b->aux[g], hipStreamNonBlocking), "batch stream");
+        SF_HIP(hipStreamCreateWithFlags(&b->capture_aux[g], hipStreamNonBlocking),
+               "capture stream");
+        SF_HIP(hipEventCreateWithFlags(&b->join[g], hipEventDisableTiming), "join event");
+    }
     SF_HIP(hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking), "capture stream");
-    SF_HIP(hipStreamCreateWithFlags(&b->capture_aux, hipStreamNonBlocking), "capture stream");
     SF_HIP(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming), "fork event");
-    SF_HIP(hipEventCreateWithFlags(&b->join, hipEventDisableTiming), "join event");
     for (sf_scene *s : b->scenes) SF_HIP(hipStreamSynchronize(s->stream), "scene sync");
     int rc = build_layout(b, tiling, &b->cur);
     if (rc) return rc;
@@ -1508,7 +1556,7 @@ int batch_tune(sf_batch *b, int32_t reps, sf_batch_tiling *chosen)
     static const int shapes[][4] = {{16, 2, 4, 2}, {16, 2, 8, 2}, {16, 4, 4, 2}, {16, 4, 8, 2},
                                     {32, 2, 4, 2}, {32, 2, 8, 2}, {32, 4, 4, 2}, {8, 2, 4, 2},
                                     {8, 4, 4, 2},  {16, 4, 4, 4}, {16, 4, 8, 4}, {32, 4, 4, 4},
-                                    {8, 4, 4, 4}};
+                                    {8, 4, 4, 4},  {16, 4, 16, 4}};
     const int caps[] = {1024, 2048, 4096};
     const int ipbs[] = {2, 8};
     sf_batch_tiling best = b->cur.t;
@@ -1543,7 +1591,6 @@ int batch_tune(sf_batch *b, int32_t reps, sf_batch_tiling *chosen)
             }
         }
     }
-    if (b->cur.n_groups == 1) best.group[1] = best.group[0];
     g_last_error.clear();
     BatchLayout L;
     int rc = build_layout(b, &best, &L);
@@ -1830,9 +1877,7 @@ int sf_set_state(sf_scene *s, const int32_t *pos, int64_t step)
         hipStream_t st = s->stream;
         if ((rc = upload_positions(s, pos))) return rc;
         if ((rc = reset_counters(s, step, gone))) return rc;
-        SF_HIP(sf::launch_fill_u64(s->claim, n, ~0ull, st), "clear claims");
-        SF_HIP(sf::launch_fill_i32(reinterpret_cast<int32_t *>(s->regs), n, 0, st),
-               "clear registrations");
+        SF_HIP(sf::launch_clear_claims(s->claims, n, st), "clear claims");
         SF_HIP(sf::launch_fill_i32(s->target, (size_t)s->N, 0, st), "clear targets");
         SF_HIP(sf::launch_fill_i32(reinterpret_cast<int32_t *>(s->flags), ((size_t)s->N + 3) / 4,
                                    0, st),
@@ -2058,7 +2103,8 @@ void sf_batch_destroy(sf_batch *b)
         s->batch = nullptr;
         s->stream = s->own_stream;
     }
-    (void)hipStreamSynchronize(b->aux);
+    for (hipStream_t a : b->aux)
+        if (a) (void)hipStreamSynchronize(a);
     drop_graphs(b);
     free_layout(b->cur);
     destroy_batch_streams(b);

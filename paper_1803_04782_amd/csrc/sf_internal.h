@@ -100,6 +100,17 @@ bool list_shape_compiled(int tw, int hl, int nw, int vec = 2, int elem = 4);
 // Dynamic LDS limit of the field kernels.
 hipError_t set_field_lds_limit(size_t bytes);
 
+// Claim record of one su, 16 bytes: the election word (the smallest key of
+// the tick's registrants, ~0 when there is none) and the number of
+// registrations, which decide adds and the election's winner reads and clears
+// in commit.  Held together, a registrant's two atomics and the winner's reads
+// and resets touch one cache line instead of two.
+struct ClaimRec {
+    unsigned long long word;
+    unsigned int regs, pad;
+};
+hipError_t launch_clear_claims(ClaimRec *c, size_t n, hipStream_t st);
+
 // What the per-tick kernels read of one scene.  A launch covers one or more
 // scenes; every scene of a launch has its own view.
 struct SceneView {
@@ -123,10 +134,9 @@ struct SceneView {
     // exact pedestrian field Phi (FP64), kept while the incremental update is
     // on (written by full superpositions, updated in place), else NULL
     double *phi;
-    unsigned long long *occ, *claim, *key, *ctr;
-    // registrations per su in the current tick (decide adds, the election's
-    // winner clears it in commit)
-    unsigned int *regs;
+    unsigned long long *occ, *key, *ctr;
+    // claim record per su (the election word and the tick's registration count)
+    ClaimRec *claims;
     // per-pedestrian arrays are indexed by an internal id (pedestrians in
     // row-major order of their positions when the state was set); ext maps
     // it to the caller's id, which keys the election

@@ -180,6 +180,18 @@ __global__ void k_fill_u64(unsigned long long *p, size_t n, unsigned long long v
         p[i] = v;
 }
 
+__global__ void k_clear_claims(ClaimRec *c, size_t n)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        ClaimRec r;
+        r.word = ~0ull;
+        r.regs = 0u;
+        r.pad = 0u;
+        c[i] = r;
+    }
+}
+
 __global__ void k_fill_i32(int32_t *p, size_t n, int32_t v)
 {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
@@ -1480,8 +1492,8 @@ __global__ __launch_bounds__(kDecideThreads) void k_decide_claim(
     const int i = lb * kDecideThreads + (int)threadIdx.x;
     const gptr<const unsigned long long> occ = to_global((const unsigned long long *)v.occ);
     const gptr<const float> P = to_global((const float *)v.P);
-    const gptr<unsigned long long> claim = to_global(v.claim), key = to_global(v.key),
-                                   ctr = to_global(v.ctr);
+    const gptr<ClaimRec> claims = to_global(v.claims);
+    const gptr<unsigned long long> key = to_global(v.key), ctr = to_global(v.ctr);
     const gptr<int32_t> target = to_global(v.target);
     const gptr<uint8_t> flags = to_global(v.flags);
     if (v.moved_from) {
@@ -1688,11 +1700,12 @@ __global__ __launch_bounds__(kDecideThreads) void k_decide_claim(
                 const uint32_t r = philox_w0(eid, (uint32_t)t, (uint32_t)(t >> 32), 0u,
                                              (uint32_t)seed, (uint32_t)(seed >> 32));
                 const unsigned long long kk = ((unsigned long long)r << 32) | eid;
-                __hip_atomic_fetch_min(&claim[tgt], kk, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_min(&claims[tgt].word, kk, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
                 // one more registration at the target (s-2: at most 8 under
                 // v_max = 1); the count is read by the election's winner in
                 // commit, so this atomic returns nothing and nothing waits
-                __hip_atomic_fetch_add(&to_global(v.regs)[tgt], 1u, __ATOMIC_RELAXED,
+                __hip_atomic_fetch_add(&claims[tgt].regs, 1u, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
                 key[i] = kk;
                 mover = true;
@@ -1721,8 +1734,8 @@ __global__ __launch_bounds__(commit_threads<MULTI>()) void k_commit(SceneView on
     const gptr<uint8_t> flags = to_global(v.flags);
     const gptr<const uint8_t> exitm = to_global(v.exitm);
     const gptr<const unsigned long long> key = to_global((const unsigned long long *)v.key);
-    const gptr<unsigned long long> claim = to_global(v.claim), occ = to_global(v.occ),
-                                   ctr = to_global(v.ctr);
+    const gptr<ClaimRec> claims = to_global(v.claims);
+    const gptr<unsigned long long> occ = to_global(v.occ), ctr = to_global(v.ctr);
     bool was_live = false, won = false, left = false;
     unsigned int regs_seen = 0;  // registrants of the su this thread won
     if (i < v.N) {
@@ -1740,9 +1753,9 @@ __global__ __launch_bounds__(commit_threads<MULTI>()) void k_commit(SceneView on
             if (f & kFlagMover) {
                 // the winner is the only registrant that finds its own key; it
                 // also resets the word, which losers then read as "not mine"
-                const unsigned long long cw = claim[tgt];
+                const unsigned long long cw = claims[tgt].word;
                 const bool to_exit = exitm[tgt] != 0;
-                const unsigned int nreg = to_global(v.regs)[tgt];
+                const unsigned int nreg = claims[tgt].regs;
                 const unsigned long long kk = key[i];
                 if (cw == kk) {
                     // every registration of this tick is counted by now (decide
@@ -1750,8 +1763,8 @@ __global__ __launch_bounds__(commit_threads<MULTI>()) void k_commit(SceneView on
                     // the count before it clears it
                     won = true;
                     regs_seen = nreg;
-                    claim[tgt] = ~0ull;
-                    to_global(v.regs)[tgt] = 0u;
+                    claims[tgt].word = ~0ull;
+                    claims[tgt].regs = 0u;
                     const int y = p / W, x = p - y * W;
                     const size_t wp = (size_t)y * wpr + (x >> 6);
                     __hip_atomic_fetch_and(&occ[wp], ~(1ull << (x & 63)), __ATOMIC_RELAXED,
@@ -1888,9 +1901,8 @@ __global__ __launch_bounds__(kDecideThreads) void k_decide_body(SceneView v)
         to_global((const unsigned long long *)v.bodies);
     const gptr<const unsigned long long> obits = to_global(v.obits);
     const gptr<const float> P = to_global((const float *)v.P);
-    const gptr<unsigned long long> claim = to_global(v.claim), key = to_global(v.key),
-                                   ctr = to_global(v.ctr);
-    const gptr<unsigned int> regs = to_global(v.regs);
+    const gptr<ClaimRec> claims = to_global(v.claims);
+    const gptr<unsigned long long> key = to_global(v.key), ctr = to_global(v.ctr);
     if (v.moved_from) {
         const int nb = decide_block_count(N);
         const size_t nwd = (size_t)wpr * H;
@@ -1973,10 +1985,10 @@ __global__ __launch_bounds__(kDecideThreads) void k_decide_body(SceneView v)
                 const unsigned long long kk = ((unsigned long long)r << 32) | eid;
                 body_edge(x, y, a, b, ex, ey, false, [&](int sx, int sy) {
                     const size_t q = (size_t)wrap_or_keep(sy, H, per) * W + wrap_or_keep(sx, W, per);
-                    __hip_atomic_fetch_min(&claim[q], kk, __ATOMIC_RELAXED,
+                    __hip_atomic_fetch_min(&claims[q].word, kk, __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_AGENT);
                     regs_seen = max(regs_seen, 1u + __hip_atomic_fetch_add(
-                                                        &regs[q], 1u, __ATOMIC_RELAXED,
+                                                        &claims[q].regs, 1u, __ATOMIC_RELAXED,
                                                         __HIP_MEMORY_SCOPE_AGENT));
                 });
                 key[i] = kk;
@@ -2006,9 +2018,9 @@ __global__ __launch_bounds__(256) void k_commit_body(SceneView v)
     const gptr<int32_t> pos = to_global(v.pos), target = to_global(v.target);
     const gptr<uint8_t> flags = to_global(v.flags);
     const gptr<const uint8_t> exitm = to_global(v.exitm);
-    const gptr<unsigned long long> claim = to_global(v.claim), occ = to_global(v.occ),
-                                   bodies = to_global(v.bodies), ctr = to_global(v.ctr);
-    const gptr<unsigned int> regs = to_global(v.regs);
+    const gptr<ClaimRec> claims = to_global(v.claims);
+    const gptr<unsigned long long> occ = to_global(v.occ), bodies = to_global(v.bodies),
+                                   ctr = to_global(v.ctr);
     bool was_live = false, won = false, left = false;
     auto su_of = [&](int sx, int sy) {
         return (size_t)wrap_or_keep(sy, H, per) * W + wrap_or_keep(sx, W, per);
@@ -2045,7 +2057,7 @@ __global__ __launch_bounds__(256) void k_commit_body(SceneView v)
                 int k = 0;
                 body_edge(x, y, a, b, ex, ey, false, [&](int sx, int sy) {
                     const size_t q = su_of(sx, sy);
-                    const bool mine = claim[q] == kk;
+                    const bool mine = claims[q].word == kk;
                     all_mine &= mine;
                     held |= (mine ? 1u : 0u) << k;
                     at_exit |= exitm[q] != 0;
@@ -2055,8 +2067,8 @@ __global__ __launch_bounds__(256) void k_commit_body(SceneView v)
                 body_edge(x, y, a, b, ex, ey, false, [&](int sx, int sy) {
                     if ((held >> k) & 1u) {
                         const size_t q = su_of(sx, sy);
-                        claim[q] = ~0ull;
-                        regs[q] = 0u;
+                        claims[q].word = ~0ull;
+                        claims[q].regs = 0u;
                     }
                     ++k;
                 });
@@ -2395,9 +2407,22 @@ ListCfg make_list_cfg(int radius, int tw, int hl, int nw, int list_cap, int elem
 
 ListCfg pick_list_cfg(int radius, size_t max_lds, int elem)
 {
-    // one list per workgroup strip, 16-column strips, two stamp entries per
-    // 8-byte-pair LDS read and lane (conflict-free banks); two workgroups per
-    // CU are preferred, smaller lists and workgroups if LDS is short
+    // Integer stamps: 16-byte loads (four stamp copies) with two workgroups of
+    // 8 or 4 waves per CU when LDS allows, else one workgroup of 16 waves
+    // (large radii).  Otherwise, and for FP64 stamps: 16-column strips, two
+    // entries per paired LDS read, two workgroups per CU preferred, smaller
+    // lists and workgroups if LDS is short.
+    if (elem == 4) {
+        const int v4[][3] = {{16, 4, 8}, {16, 4, 4}, {16, 4, 16}};
+        for (int i = 0; i < 3; ++i) {
+            const int *sh = v4[i];
+            for (int cap = 4096; cap >= 1024; cap /= 2) {
+                ListCfg t = make_list_cfg(radius, sh[0], sh[1], sh[2], cap, elem, 4);
+                if (cap < 2 * t.max_row || t.halo_rows > 64 * sh[2]) break;
+                if (t.lds_bytes <= (sh[2] == 16 ? max_lds : max_lds / 2)) return t;
+            }
+        }
+    }
     const int shapes[][3] = {{16, 2, 8}, {16, 2, 4}};
     ListCfg best;
     for (int i = 0; i < 2; ++i) {
@@ -2455,6 +2480,8 @@ size_t field_lds_bytes(const FieldLaunch &f)
     X(16, 2, 4) X(16, 2, 8) X(16, 4, 4) X(16, 4, 8) X(32, 2, 4) X(32, 2, 8) X(32, 4, 4)         \
     X(8, 2, 4) X(8, 4, 4)
 #define SF_V4_SHAPES(X) X(16, 4, 4) X(16, 4, 8) X(32, 4, 4) X(8, 4, 4)
+// 16 waves: for stamps large enough that one workgroup fills a CU's LDS
+#define SF_V4_WIDE(X) X(16, 4, 16)
 
 bool list_shape_compiled(int tw, int hl, int nw, int vec, int elem)
 {
@@ -2464,6 +2491,7 @@ bool list_shape_compiled(int tw, int hl, int nw, int vec, int elem)
         SF_LIST_SHAPES(SF_KNOWN)
     } else if (vec == 4 && elem == 4) {
         SF_V4_SHAPES(SF_KNOWN)
+        SF_V4_WIDE(SF_KNOWN)
     }
 #undef SF_KNOWN
     return false;
@@ -2485,6 +2513,7 @@ hipError_t set_field_lds_limit(size_t bytes)
     SF_SET1(a, b, n, false, true, true, 4)
     SF_LIST_SHAPES(SF_SET)
     SF_V4_SHAPES(SF_SET4)
+    SF_V4_WIDE(SF_SET4)
 #undef SF_SET4
 #undef SF_SET
 #undef SF_SET1
@@ -2504,6 +2533,7 @@ hipError_t launch_field(const FieldLaunch &f, const SceneView *views, const int3
     if (f.vec == 4) {
         if (f.elem != 4) return hipErrorInvalidValue;
         SF_V4_SHAPES(SF_DISPATCH4)
+        SF_V4_WIDE(SF_DISPATCH4)
         return hipErrorInvalidValue;
     }
 #undef SF_DISPATCH4
@@ -2535,6 +2565,7 @@ int field_resident_blocks(int tw, int hl, int nw, size_t lds_bytes, bool multi, 
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, w * 64, lds_bytes);             \
     }
         SF_V4_SHAPES(SF_OCC4)
+        SF_V4_WIDE(SF_OCC4)
 #undef SF_OCC4
         return e == hipSuccess ? n : 0;
     }
@@ -2581,6 +2612,7 @@ hipError_t launch_field_one(const FieldLaunch &f, const SceneView &view, int per
     if (f.vec == 4) {
         if (f.elem != 4) return hipErrorInvalidValue;
         SF_V4_SHAPES(SF_DISPATCH4)
+        SF_V4_WIDE(SF_DISPATCH4)
         return hipErrorInvalidValue;
     }
 #undef SF_DISPATCH4
@@ -2611,6 +2643,7 @@ hipError_t launch_field_update(const FieldLaunch &f, const SceneView &view, int 
     if (f.vec == 4) {
         if (f.elem != 4) return hipErrorInvalidValue;
         SF_V4_SHAPES(SF_DISPATCH4)
+        SF_V4_WIDE(SF_DISPATCH4)
         return hipErrorInvalidValue;
     }
 #undef SF_DISPATCH4
@@ -2670,6 +2703,12 @@ hipError_t launch_decide_one(const SceneView &view, hipStream_t st, const Launch
 {
     return launch(k_decide_claim<false>, dim3(decide_blocks(view.N)), dim3(kDecideThreads), 0, st,
                   ev, view, (const SceneView *)nullptr, (const int32_t *)nullptr);
+}
+
+hipError_t launch_clear_claims(ClaimRec *c, size_t n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_clear_claims, dim3(blocks_for(n, 256, kCoverAll)), dim3(256), 0, st, c, n);
+    return hipGetLastError();
 }
 
 hipError_t launch_scatter_i32(const int32_t *src, const int32_t *ext, int32_t *dst, int n,

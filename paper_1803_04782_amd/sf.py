@@ -77,32 +77,45 @@ class GroupTiling(ctypes.Structure):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
+MAX_GROUPS = 4  # SF_MAX_GROUPS
+
+
 class Tiling(ctypes.Structure):
-    """sf_batch_tiling: split of a batch into groups and each group's tiling
-    (zero fields = library defaults)."""
-    _fields_ = [("groups", ctypes.c_int32), ("split_radius", ctypes.c_int32),
-                ("group", GroupTiling * 2)]
+    """sf_batch_tiling: split of a batch into groups by radius and each
+    group's tiling (zero fields = library defaults)."""
+    _fields_ = [("groups", ctypes.c_int32), ("split_radius", ctypes.c_int32 * (MAX_GROUPS - 1)),
+                ("group", GroupTiling * MAX_GROUPS)]
 
     @classmethod
     def from_dict(cls, d: dict) -> "Tiling":
-        """{"groups", "split_radius", "group": [dict, dict]} or a flat dict of
-        group fields applied to both groups."""
+        """{"groups", "split_radius": int or list, "group": [dict, ...]} or a
+        flat dict of group fields applied to every group."""
         t = cls()
         group_keys = {k for k, _ in GroupTiling._fields_}
         flat = {k: v for k, v in d.items() if k in group_keys}
-        for gi in range(2):
+        per_group = list(d.get("group", []))
+        if len(per_group) > MAX_GROUPS:
+            raise ValueError(f"at most {MAX_GROUPS} groups")
+        for gi in range(MAX_GROUPS):
             g = dict(flat)
-            if "group" in d:
-                g.update(d["group"][gi])
+            if gi < len(per_group):
+                g.update(per_group[gi])
             for k, v in g.items():
                 setattr(t.group[gi], k, int(v))
         t.groups = int(d.get("groups", 0))
-        t.split_radius = int(d.get("split_radius", 0))
+        split = d.get("split_radius", 0)
+        split = [split] if isinstance(split, int) else list(split)
+        if len(split) > MAX_GROUPS - 1:
+            raise ValueError(f"at most {MAX_GROUPS - 1} split radii")
+        for gi, r in enumerate(split):
+            t.split_radius[gi] = int(r)
         return t
 
     def as_dict(self):
-        return {"groups": int(self.groups), "split_radius": int(self.split_radius),
-                "group": [self.group[0].as_dict(), self.group[1].as_dict()]}
+        n = max(1, int(self.groups))
+        return {"groups": int(self.groups),
+                "split_radius": [int(r) for r in self.split_radius][: max(0, n - 1)],
+                "group": [self.group[gi].as_dict() for gi in range(n)]}
 
 
 class SfError(RuntimeError):

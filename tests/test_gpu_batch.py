@@ -94,11 +94,16 @@ def test_batch_members_match_scenes_alone(sf):
     dict(tw=16, hl=4, vec=4, nw=4),
     dict(tw=32, hl=4, vec=4, nw=4, items_per_block=1),
     dict(tw=8, hl=4, vec=4, nw=4, list_cap=1024, items_per_block=64),
+    dict(tw=16, hl=4, vec=4, nw=16, blocks_per_cu=1),
     dict(groups=1),
     dict(groups=2, split_radius=16,
          group=[dict(tw=32, hl=4, vec=2, nw=4), dict(tw=16, hl=2, vec=2, nw=8)]),
     dict(groups=2, split_radius=8,
          group=[dict(tw=16, hl=4, vec=4, nw=8), dict(tw=16, hl=4, vec=4, nw=4)]),
+    dict(groups=3),
+    dict(groups=4, split_radius=[4, 8, 16],
+         group=[dict(tw=32, hl=4, vec=4, nw=4), dict(tw=16, hl=4, vec=4, nw=4),
+                dict(tw=16, hl=2, vec=2, nw=8), dict(tw=16, hl=4, vec=4, nw=16)]),
 ])
 def test_batch_tilings_identical(sf, tiling):
     scs = _mixed_scenes()[:5]
@@ -223,6 +228,10 @@ def test_batch_membership_rules(sf):
         sf.Batch([gs[2]], tiling=dict(tw=12, hl=2, vec=2, nw=4))  # not a compiled shape
     with pytest.raises(sf.SfError):
         sf.Batch([gs[2]], tiling=dict(tw=16, hl=2, vec=4, nw=4))  # 16-byte loads need HL 4
+    with pytest.raises(sf.SfError):
+        sf.Batch([gs[2]], tiling=dict(groups=2))  # one radius: the second group is empty
+    with pytest.raises(sf.SfError):
+        sf.Batch([gs[2]], tiling=dict(groups=5))
     b.step(2)
     b.close()
     gs[0].step(1)  # back on its own

@@ -56,7 +56,7 @@ def test_incremental_lockstep(sf, name, make, K, ticks, every):
 def test_incremental_tile_shape_invariance(sf, monkeypatch):
     sc = scenes.random_scene(130, 90, n_peds=1500, radius=7, seed=33, bernoulli=0.03)
     out = []
-    for shape in ("16x2x2x8", "32x4x2x4", "8x2x2x4", "16x4x4x8", "8x4x4x4"):
+    for shape in ("16x2x2x8", "32x4x2x4", "8x2x2x4", "16x4x4x8", "8x4x4x4", "16x4x4x16"):
         monkeypatch.setenv("SF_TILE", shape)
         with sf.GpuScene(sc) as g:
             g.set_field_update(16)

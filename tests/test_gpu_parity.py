@@ -206,7 +206,8 @@ def test_deterministic_and_resume(sf):
 # TWxHLxVECxNW: VEC 4 reads a lane's four entries of a source with one
 # 16-byte load from one of four shifted copies of the stamp
 SHAPES = ("16x2x2x4", "16x2x2x8", "16x4x2x4", "16x4x2x8", "32x2x2x4", "32x2x2x8",
-          "32x4x2x4", "8x2x2x4", "8x4x2x4", "16x4x4x4", "16x4x4x8", "32x4x4x4", "8x4x4x4")
+          "32x4x2x4", "8x2x2x4", "8x4x2x4", "16x4x4x4", "16x4x4x8", "32x4x4x4", "8x4x4x4",
+          "16x4x4x16")
 
 
 def test_tile_shape_invariance(sf, monkeypatch):
