@@ -356,8 +356,8 @@ typedef struct sf_batch sf_batch; /* opaque, library-owned */
 typedef struct {
     int32_t tw, hl, vec, nw;   /* field kernel: strip width in su, rows per lane,
                                   stamp entries per LDS read (2: paired loads;
-                                  4: one 16-byte load, integer stamps and hl 4
-                                  only), waves per workgroup; one of the
+                                  4: 16-byte loads, integer stamps and hl 4
+                                  or 8 only), waves per workgroup; one of the
                                   compiled shapes, or all four zero (vec 0
                                   reads as 2)                                  */
     int32_t list_cap;          /* field kernel: source-list entries in LDS      */

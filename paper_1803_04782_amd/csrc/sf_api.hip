@@ -1556,7 +1556,7 @@ int batch_tune(sf_batch *b, int32_t reps, sf_batch_tiling *chosen)
     static const int shapes[][4] = {{16, 2, 4, 2}, {16, 2, 8, 2}, {16, 4, 4, 2}, {16, 4, 8, 2},
                                     {32, 2, 4, 2}, {32, 2, 8, 2}, {32, 4, 4, 2}, {8, 2, 4, 2},
                                     {8, 4, 4, 2},  {16, 4, 4, 4}, {16, 4, 8, 4}, {32, 4, 4, 4},
-                                    {8, 4, 4, 4},  {16, 4, 16, 4}};
+                                    {8, 4, 4, 4},  {16, 4, 16, 4}, {32, 8, 4, 4}, {16, 8, 4, 4}};
     const int caps[] = {1024, 2048, 4096};
     const int ipbs[] = {2, 8};
     sf_batch_tiling best = b->cur.t;

@@ -63,8 +63,9 @@ SupCfg make_sup_cfg(int radius, int tw, int hl, size_t elem);
 // rows [w*TH, (w+1)*TH).  Lane l owns column l % TW and, with rg = l / TW and
 // G = 64 / TW, the HL rows rg + G*r (r < HL), so its entries of a source's
 // stamp column are G apart and each pair is one paired LDS read (vec = 2);
-// or (vec = 4: integer stamps, HL = 4) the rows 4*rg + r, read as one 16-byte
-// load from one of four copies of the stamp, copy c shifted by c entries.
+// or (vec = 4: integer stamps, HL = 4 or 8) the rows HL*rg + r, read four at
+// a time by 16-byte loads from one of four copies of the stamp, copy c
+// shifted by c entries.
 // The stamp is held once, column-major: as integers in units of the law's
 // q = 2^(e_min - 23) (elem = 4 bytes; the FP32 strengths are integer
 // multiples of q) or as doubles (elem = 8, laws whose strengths span too many

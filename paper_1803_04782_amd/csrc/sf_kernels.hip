@@ -479,18 +479,18 @@ __global__ __launch_bounds__(kSupThreads) void k_superpose(
 //     (lane su - source);
 //  4. each wave walks the contiguous part of the list that lies within R rows
 //     of its own rows: per source one address add, HL/2 paired LDS loads (or
-//     one 16-byte load, VEC = 4) and HL adds per lane.
+//     HL/4 16-byte loads, VEC = 4) and HL adds per lane.
 // Lane l owns column l % TW and, with rg = l / TW and G = 64 / TW, HL rows of
 // its wave's TW x TH tile: rows rg + G*r (r < HL), so that its entries of a
 // source are G apart in the column-major stamp and two of them make one
-// paired load; or (VEC = 4, integer stamps, HL = 4) rows 4*rg + r, so that
-// its four entries of a source are adjacent and one 16-byte load reads them.
-// A 16-byte LDS load must be 16-byte aligned, and the start of a lane's four
-// entries moves with the source's row: the stamp is held four times in LDS,
-// copy c shifted by c entries, and a source in row py reads the copy with
-// c = (py - pady) mod 4, which puts every lane's four entries on a 16-byte
-// boundary (lane rows start at multiples of 4 and the stride is a multiple of
-// 4).  The copy is folded into the source's list entry.
+// paired load; or (VEC = 4, integer stamps, HL = 4 or 8) rows HL*rg + r, so
+// that its entries of a source are adjacent and 16-byte loads read them four
+// at a time.  A 16-byte LDS load must be 16-byte aligned, and the start of a
+// lane's entries moves with the source's row: the stamp is held four times in
+// LDS, copy c shifted by c entries, and a source in row py reads the copy with
+// c = (py - pady) mod 4, which puts every lane's entries on a 16-byte boundary
+// (lane rows start at multiples of 4 and the stride is a multiple of 4).  The
+// copy is folded into the source's list entry.
 // A halo with more than list_cap - max_row sources is processed in several
 // passes over consecutive row ranges.  The bitmap rows of the next strip
 // (possibly of the next item and scene) are requested before the current
@@ -539,11 +539,14 @@ __device__ __forceinline__ void gather_one(T *acc, uint32_t a)
 {
     T v[HL];
     if constexpr (V4) {
-        static_assert(HL == 4 && sizeof(T) == 4, "16-byte loads of four integers");
+        static_assert(HL % 4 == 0 && sizeof(T) == 4, "16-byte loads of four integers");
         typedef const __attribute__((address_space(3))) i32x4 *ptr4;
-        const i32x4 w = *reinterpret_cast<ptr4>(a);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) v[r] = w[r];
+        for (int h = 0; h < HL / 4; ++h) {
+            const i32x4 w = *reinterpret_cast<ptr4>(a + 16u * h);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) v[4 * h + r] = w[r];
+        }
     } else {
         typedef const __attribute__((address_space(3))) T *ptr;
         const ptr s = reinterpret_cast<ptr>(a);
@@ -654,8 +657,8 @@ struct FieldWork {
 // allow it sums several rounds of 8 before moving the sums (the scene's
 // int_rounds, with 8 * int_rounds * max|strength| / q < 2^31).  Otherwise the
 // stamp holds doubles summed in FP64.
-// VEC: stamp entries per LDS load and lane, 2 (paired loads) or 4 (one
-// 16-byte load; integer stamps, HL = 4, the stamp held four times).
+// VEC: stamp entries per LDS load and lane, 2 (paired loads) or 4 (16-byte
+// loads; integer stamps, HL a multiple of 4, the stamp held four times).
 template <int TW, int HL, int NW, bool MULTI, bool DUAL = false, bool INT = false, int VEC = 2>
 __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
                                                    const SceneView *__restrict__ views,
@@ -663,7 +666,8 @@ __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
                                                    int per, int tab_max, int list_cap)
 {
     static_assert(!(DUAL && MULTI), "the update launch covers one scene");
-    static_assert(VEC == 2 || (VEC == 4 && INT && HL == 4), "16-byte loads: integers, HL = 4");
+    static_assert(VEC == 2 || (VEC == 4 && INT && HL % 4 == 0),
+                  "16-byte loads: integers, HL a multiple of 4");
     constexpr bool V4 = VEC == 4;
     constexpr int NSRC = DUAL ? 2 : 1;
     using T = std::conditional_t<INT, int, double>;  // a stamp entry
@@ -990,9 +994,12 @@ __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
                     // the HL entries of a source at LDS byte address ad
                     auto read_at = [&](uint32_t ad, T(&u)[HL]) {
                         if constexpr (V4) {
-                            const i32x4 w = *reinterpret_cast<lds_4>(ad);
 #pragma unroll
-                            for (int r = 0; r < HL; ++r) u[r] = w[r];
+                            for (int h = 0; h < HL / 4; ++h) {
+                                const i32x4 w = *reinterpret_cast<lds_4>(ad + 16u * h);
+#pragma unroll
+                                for (int r = 0; r < 4; ++r) u[4 * h + r] = w[r];
+                            }
                         } else {
                             const lds_d sp = reinterpret_cast<lds_d>(ad);
 #pragma unroll
@@ -2330,15 +2337,17 @@ namespace {
 // conflict-free when their 16-byte units are distinct modulo 32 (probe: a
 // conflict-free pass moves about 280 bytes per clock, against about 130 for
 // the paired 4-byte loads; a 2-way conflict about 170).
-int bank_degree(int tw, int stride, int elem, int vec = 2)
+int bank_degree(int tw, int stride, int elem, int vec = 2, int hl = 4)
 {
     if (vec == 4) {
+        // lane l's first load: integer col*stride + hl*rg, 16-byte unit
+        // col*stride/4 + (hl/4)*rg (later loads of an hl = 8 lane: the next unit)
         int worst = 0;
         for (int p = 0; p < 64; p += 32) {
             int hits[32] = {0};
             for (int l = p; l < p + 32; ++l) {
                 const int col = l % tw, rg = l / tw;
-                ++hits[(col * (stride / 4) + rg) % 32];
+                ++hits[(col * (stride / 4) + (hl / 4) * rg) % 32];
             }
             for (int b = 0; b < 32; ++b) worst = hits[b] > worst ? hits[b] : worst;
         }
@@ -2385,7 +2394,7 @@ ListCfg make_list_cfg(int radius, int tw, int hl, int nw, int list_cap, int elem
     int best = -1, best_deg = 1 << 30;
     for (int s = smin; s < smin + 64; ++s) {
         if (vec == 4 && s % 4 != 0) continue;  // lane rows 16-byte aligned in every column
-        const int d = bank_degree(tw, s, elem, vec);
+        const int d = bank_degree(tw, s, elem, vec, hl);
         if (d < best_deg) {
             best_deg = d;
             best = s;
@@ -2479,7 +2488,7 @@ size_t field_lds_bytes(const FieldLaunch &f)
 #define SF_LIST_SHAPES(X)                                                                     \
     X(16, 2, 4) X(16, 2, 8) X(16, 4, 4) X(16, 4, 8) X(32, 2, 4) X(32, 2, 8) X(32, 4, 4)         \
     X(8, 2, 4) X(8, 4, 4)
-#define SF_V4_SHAPES(X) X(16, 4, 4) X(16, 4, 8) X(32, 4, 4) X(8, 4, 4)
+#define SF_V4_SHAPES(X) X(16, 4, 4) X(16, 4, 8) X(32, 4, 4) X(8, 4, 4) X(32, 8, 4) X(16, 8, 4)
 // 16 waves: for stamps large enough that one workgroup fills a CU's LDS
 #define SF_V4_WIDE(X) X(16, 4, 16)
 

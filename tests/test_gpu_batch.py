@@ -95,6 +95,8 @@ def test_batch_members_match_scenes_alone(sf):
     dict(tw=32, hl=4, vec=4, nw=4, items_per_block=1),
     dict(tw=8, hl=4, vec=4, nw=4, list_cap=1024, items_per_block=64),
     dict(tw=16, hl=4, vec=4, nw=16, blocks_per_cu=1),
+    dict(groups=2, split_radius=8,
+         group=[dict(tw=32, hl=8, vec=4, nw=4), dict(tw=16, hl=8, vec=4, nw=4, list_cap=1024)]),
     dict(groups=1),
     dict(groups=2, split_radius=16,
          group=[dict(tw=32, hl=4, vec=2, nw=4), dict(tw=16, hl=2, vec=2, nw=8)]),

@@ -127,6 +127,9 @@ VEC4_CASES = [
     ("16x4x4x8x400", lambda: scenes.random_scene(120, 110, n_peds=0, radius=16, seed=64,
                                                  bernoulli=0.02, exits=("S",), exit_width=6,
                                                  occupancy=0.5)),
+    ("32x8x4x4", lambda: scenes.random_scene(141, 93, n_peds=1500, radius=5, seed=65,
+                                             bernoulli=0.04, exits=("E",), exit_width=6)),
+    ("16x8x4x4x300", lambda: scenes.flow_scene(97, 83, 0.3, 4, radius=8, seed=66)),
 ]
 
 
@@ -207,7 +210,7 @@ def test_deterministic_and_resume(sf):
 # 16-byte load from one of four shifted copies of the stamp
 SHAPES = ("16x2x2x4", "16x2x2x8", "16x4x2x4", "16x4x2x8", "32x2x2x4", "32x2x2x8",
           "32x4x2x4", "8x2x2x4", "8x4x2x4", "16x4x4x4", "16x4x4x8", "32x4x4x4", "8x4x4x4",
-          "16x4x4x16")
+          "16x4x4x16", "32x8x4x4", "16x8x4x4")
 
 
 def test_tile_shape_invariance(sf, monkeypatch):

@@ -85,7 +85,8 @@ def test_lone_walker_wraps_around(sf, h):
 def test_periodic_tile_shape_invariance(sf, monkeypatch):
     sc = scenes.flow_scene(190, 133, 0.4, 8, radius=7, seed=6)
     out = []
-    for shape in ("16x2x2x8", "32x4x2x4", "8x2x2x4", "16x4x2x4", "16x4x4x4", "32x4x4x4"):
+    for shape in ("16x2x2x8", "32x4x2x4", "8x2x2x4", "16x4x2x4", "16x4x4x4", "32x4x4x4",
+                  "16x8x4x4"):
         monkeypatch.setenv("SF_TILE", shape)
         with sf.GpuScene(sc) as g:
             g.step(10)
