@@ -297,12 +297,17 @@ def ensemble_line(args, stream, steps):
     plain = [sf.GpuScene(s, stream=stream) for s in scs]
     member = [sf.GpuScene(s, stream=stream) for s in scs]
     say(f"created {2 * len(scs)} scenes in {time.perf_counter() - t0:.1f} s")
-    b = sf.Batch(member, stream=stream)
+    fixed = json.loads(args.tiling) if args.tiling else None
+    b = sf.Batch(member, tiling=fixed, stream=stream)
     wins = windows(steps)
     try:
         t0 = time.perf_counter()
-        tiling = b.tune(reps=3)
-        say(f"autotuned tiling {tiling} in {time.perf_counter() - t0:.1f} s")
+        if fixed is None:
+            tiling = b.tune(reps=3)
+            say(f"autotuned tiling {tiling} in {time.perf_counter() - t0:.1f} s")
+        else:
+            tiling = b.tiling()
+            say(f"tiling as given: {tiling}")
         for _ in range(args.warmup):
             for g in plain:
                 g.step(1)
@@ -744,6 +749,9 @@ def main():
                              "flow1000", "flow-sweep", "flow-walk", "serving",
                              "sect-compare", "ensemble-classes"])
     ap.add_argument("--scenes", type=int, default=256, help="ensemble size (ensemble256)")
+    ap.add_argument("--tiling", default=None,
+                    help="ensemble256: batch tiling as JSON instead of the autotuner's "
+                         "(for counter runs whose kernels must all be the timed ones)")
     ap.add_argument("--rates", default="50,200,800", help="arrival rates per s (serving)")
     ap.add_argument("--serve-seconds", type=float, default=None,
                     help="arrival window per rate (serving; default 30 s alone, 4 s in the "

@@ -705,6 +705,8 @@ __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
     int4 it = work.item(item);
     FieldScene v = work.scene(it.x);
     int t = it.y;
+    // this strip's tile column and row (a division per work item, not per strip)
+    int ty = t / v.tiles_x, tx = t - ty * v.tiles_x;
     // stamp into LDS, 8 vectors of 16 bytes per thread and batch: each
     // thread's loads are all issued before the stores, so a batch costs one
     // memory round trip.  The loads are unconditional (indices past the end
@@ -756,9 +758,9 @@ __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
     struct Strip {
         int X0, Y0, ya, nr, xa, xb, wa, nwd;
     };
-    auto strip = [&](const FieldScene &s, int ts) {
+    // strip (tx, ty): strip index ty * tiles_x + tx
+    auto strip = [&](const FieldScene &s, int tx, int ty) {
         Strip g;
-        const int ty = ts / s.tiles_x, tx = ts - ty * s.tiles_x;
         g.X0 = tx * TW;
         g.Y0 = ty * WT;
         if (s.periodic) {
@@ -779,10 +781,10 @@ __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
     // bitmap words of this thread's halo row of a strip (issued early: the
     // loads stay in flight across the previous strip's work)
     unsigned long long nw_[NSRC][3];
-    auto fetch_rows = [&](const FieldScene &s, int ts) {
+    auto fetch_rows = [&](const FieldScene &s, int tx, int ty) {
 #pragma unroll
         for (int src = 0; src < NSRC; ++src) nw_[src][0] = nw_[src][1] = nw_[src][2] = 0;
-        const Strip g = strip(s, ts);
+        const Strip g = strip(s, tx, ty);
         if (tid < g.nr) {
 #pragma unroll
             for (int src = 0; src < NSRC; ++src) {
@@ -809,8 +811,7 @@ __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
     // requested one strip ahead, like the halo rows, so that a strip whose
     // gather is short (small radius, sparse crowd) does not wait for them
     double sv_n[HL], pv_n[HL];
-    auto fetch_sp = [&](const FieldScene &s, int ts) {
-        const int ty = ts / s.tiles_x, tx = ts - ty * s.tiles_x;
+    auto fetch_sp = [&](const FieldScene &s, int tx, int ty) {
         const int x = tx * TW + col, y0 = ty * WT + wv * TH;
 #pragma unroll
         for (int r = 0; r < HL; ++r) {
@@ -826,8 +827,8 @@ __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
         // per thread), the first strip's halo rows and its S are requested
         // together, in straight-line code, so that their round trips overlap
         f64x2 r[8];
-        fetch_rows(v, t);
-        fetch_sp(v, t);
+        fetch_rows(v, tx, ty);
+        fetch_sp(v, tx, ty);
         table_load(v, 0, r);
         table_store(v, 0, r);
         for (int i0 = 8 * NT; i0 < v.tab_vecs; i0 += 8 * NT) {
@@ -840,7 +841,11 @@ __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
     for (;;) {
         // the strip after this one: the next of this item, else the first of
         // this workgroup's next item
-        int nitem = item, nt = t + 1;
+        int nitem = item, nt = t + 1, ntx = tx + 1, nty = ty;
+        if (ntx == v.tiles_x) {
+            ntx = 0;
+            ++nty;
+        }
         int4 nit = it;
         FieldScene nv = v;
         if (nt >= it.z) {
@@ -849,11 +854,13 @@ __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
                 nit = work.item(nitem);
                 nt = nit.y;
                 if (nit.x != it.x) nv = work.scene(nit.x);
+                nty = nt / nv.tiles_x;
+                ntx = nt - nty * nv.tiles_x;
             }
         }
         const bool more = nitem < item_end;
 
-        const Strip g = strip(v, t);
+        const Strip g = strip(v, tx, ty);
         const int W = v.W, H = v.H, R = v.R, stride = v.stride, padx = v.padx, pady = v.pady;
         const int X0 = g.X0, Y0 = g.Y0, y0w = Y0 + wv * TH;
         const int ya = g.ya, nr = g.nr, xa = g.xa, xb = g.xb, wa = g.wa, nwd = g.nwd;
@@ -895,8 +902,8 @@ __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
             pv[r] = pv_n[r];
         }
         if (more) {
-            fetch_rows(nv, nt);
-            fetch_sp(nv, nt);
+            fetch_rows(nv, ntx, nty);
+            fetch_sp(nv, ntx, nty);
         }
 
         // this wave's halo rows (relative to ya) and per-lane base address
@@ -951,7 +958,7 @@ __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
             __syncthreads();
 
             const int cap = list_cap - v.max_row;
-            const int npass = (total + cap - 1) / cap;
+            const int npass = total <= cap ? 1 : (total + cap - 1) / cap;
             for (int k = 0; k < npass; ++k) {
                 int start = 0, end = total;
                 if (npass > 1) {
@@ -1097,6 +1104,8 @@ __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
         }
         v = nv;
         t = nt;
+        tx = ntx;
+        ty = nty;
     }
 }
 
