@@ -145,6 +145,7 @@ struct GroupLayout {
     int n_items = 0, dec_blocks = 0, com_blocks = 0;
     SceneView *d_views = nullptr;
     int32_t *d_dec_scene = nullptr, *d_com_scene = nullptr, *d_items = nullptr;
+    unsigned int *d_queue = nullptr;  // the field launch's work-queue counters (zero between launches)
     std::vector<void *> bufs;
 };
 
@@ -1326,8 +1327,10 @@ int build_group(sf_batch *b, const std::vector<int> &members, const sf_group_til
     if ((rc = balloc(G.bufs, &G.d_views, gv.size(), "batch views")) ||
         (rc = balloc(G.bufs, &G.d_dec_scene, dec_scene.size(), "batch decide map")) ||
         (rc = balloc(G.bufs, &G.d_com_scene, com_scene.size(), "batch commit map")) ||
-        (rc = balloc(G.bufs, &G.d_items, items.size(), "batch items")))
+        (rc = balloc(G.bufs, &G.d_items, items.size(), "batch items")) ||
+        (rc = balloc(G.bufs, &G.d_queue, 2, "batch work queue")))
         return rc;
+    SF_HIP(sf::launch_fill_i32(reinterpret_cast<int32_t *>(G.d_queue), 2, 0, st), "clear queue");
     SF_HIP(hipMemcpyAsync(G.d_views, gv.data(), gv.size() * sizeof(SceneView),
                           hipMemcpyHostToDevice, st),
            "batch views");
@@ -1380,7 +1383,8 @@ int build_layout(sf_batch *b, const sf_batch_tiling *req, BatchLayout *out)
 
 int group_field(const GroupLayout &G, hipStream_t st, const sf::LaunchEvents *ev = nullptr)
 {
-    SF_HIP(sf::launch_field(G.fl, G.d_views, G.d_items, G.n_items, st, ev), "batch field");
+    SF_HIP(sf::launch_field(G.fl, G.d_views, G.d_items, G.n_items, G.d_queue, st, ev),
+           "batch field");
     return SF_OK;
 }
 

@@ -176,8 +176,9 @@ int decide_blocks(int N);
 int commit_blocks(int N);
 
 // One field launch over `n_items` work items (int4: scene, first strip,
-// end strip, unused).  The workgroups on each XCD share a contiguous run of
-// the items (in proportion to their number) round robin.
+// end strip, unused), taken by the workgroups from a work queue in the order
+// they ask (a single scene's launch: the workgroups on each XCD share a
+// contiguous run of the items, in proportion to their number, round robin).
 // `tab_max` is the largest lds_tab of the launch's scenes and `halo_max`
 // the largest halo row count; both size the dynamic LDS.
 struct FieldLaunch {
@@ -194,8 +195,11 @@ FieldLaunch field_launch_for(const ListCfg &c);  // tab_max/halo_max of c, grid 
 int field_resident_blocks(int tw, int hl, int nw, size_t lds_bytes, bool multi, int elem,
                           int vec = 2);
 size_t field_lds_bytes(const FieldLaunch &f);
+// `queue`: two zeroed counters of the launch's work queue (items go to
+// workgroups in the order they ask; the launch leaves the counters zeroed).
 hipError_t launch_field(const FieldLaunch &f, const SceneView *views, const int32_t *items,
-                        int n_items, hipStream_t st, const LaunchEvents *ev = nullptr);
+                        int n_items, unsigned int *queue, hipStream_t st,
+                        const LaunchEvents *ev = nullptr);
 // Single-scene forms: the view is passed by value.  Field item i is strips
 // [i*per, (i+1)*per), dealt as above (grid = min(f.grid, items)); decide and
 // commit launch the scene's own blocks.

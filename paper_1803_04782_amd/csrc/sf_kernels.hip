@@ -663,7 +663,8 @@ template <int TW, int HL, int NW, bool MULTI, bool DUAL = false, bool INT = fals
 __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
                                                    const SceneView *__restrict__ views,
                                                    const int4 *__restrict__ items, int n_items,
-                                                   int per, int tab_max, int list_cap)
+                                                   int per, int tab_max, int list_cap,
+                                                   unsigned int *__restrict__ queue)
 {
     static_assert(!(DUAL && MULTI), "the update launch covers one scene");
     static_assert(VEC == 2 || (VEC == 4 && INT && HL % 4 == 0),
@@ -691,17 +692,49 @@ __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
     // XCD has its own L2).  XCD x owns a contiguous share of the strips, in
     // proportion to its workgroups, and deals it round robin to them, so that
     // neighbouring strips (which share the cache lines of S, P and the bitmap
-    // rows) are worked on under one L2.  A batch's items are ordered for load
-    // balance instead and are dealt round robin over the whole grid.
+    // rows) are worked on under one L2.  A batch's items (ordered for load
+    // balance) go to workgroups in the order they ask for them, from the
+    // counter queue[0]: a batch's groups run concurrently, and a workgroup that
+    // starts late behind another group's launch then takes fewer items instead
+    // of holding back the end of its own launch.  Every workgroup counts itself
+    // out in queue[1] after its last request; the last one resets both
+    // counters for the next launch (no other workgroup touches them again).
+    __shared__ int next_item;
+    auto grab = [&]() -> int {
+        if (tid == 0)
+            next_item = (int)__hip_atomic_fetch_add(&queue[0], 1u, __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+        // the value is read before the next request: every item spans at
+        // least one strip, and a strip has barriers
+        __syncthreads();
+        return next_item;
+    };
+    auto finish = [&]() {
+        if constexpr (MULTI) {
+            if (tid == 0) {
+                const unsigned int d = __hip_atomic_fetch_add(&queue[1], 1u, __ATOMIC_ACQ_REL,
+                                                              __HIP_MEMORY_SCOPE_AGENT);
+                if (d == gridDim.x - 1) {
+                    __hip_atomic_store(&queue[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store(&queue[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+            }
+        }
+    };
     const int NG = (int)gridDim.x, xb = (int)blockIdx.x & 7, kb = (int)blockIdx.x >> 3;
     int gx = NG, item = (int)blockIdx.x, item_end = n_items;
-    if constexpr (!MULTI) {
+    if constexpr (MULTI) {
+        item = grab();
+    } else {
         gx = (NG >> 3) + (xb < (NG & 7) ? 1 : 0);           // workgroups on this XCD
         const int sx = xb * (NG >> 3) + min(xb, NG & 7);    // their first logical index
         item_end = (int)((long long)(sx + gx) * n_items / NG);
         item = (int)((long long)sx * n_items / NG) + kb;
     }
-    if (item >= item_end) return;
+    if (item >= item_end) {
+        finish();
+        return;
+    }
     int4 it = work.item(item);
     FieldScene v = work.scene(it.x);
     int t = it.y;
@@ -849,7 +882,10 @@ __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
         int4 nit = it;
         FieldScene nv = v;
         if (nt >= it.z) {
-            nitem = item + gx;
+            if constexpr (MULTI)
+                nitem = grab();
+            else
+                nitem = item + gx;
             if (nitem < item_end) {
                 nit = work.item(nitem);
                 nt = nit.y;
@@ -1107,6 +1143,7 @@ __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
         tx = ntx;
         ty = nty;
     }
+    finish();
 }
 
 // ---- occupancy ----------------------------------------------------------------------
@@ -2539,7 +2576,7 @@ hipError_t set_field_lds_limit(size_t bytes)
 }
 
 hipError_t launch_field(const FieldLaunch &f, const SceneView *views, const int32_t *items,
-                        int n_items, hipStream_t st, const LaunchEvents *ev)
+                        int n_items, unsigned int *queue, hipStream_t st, const LaunchEvents *ev)
 {
     const int grid = std::max(1, std::min(f.grid, n_items));
     const int4 *it = reinterpret_cast<const int4 *>(items);
@@ -2547,7 +2584,8 @@ hipError_t launch_field(const FieldLaunch &f, const SceneView *views, const int3
 #define SF_DISPATCH4(a, b, n)                                                                     \
     if (f.tw == a && f.hl == b && f.nw == n)                                                    \
         return launch(k_field<a, b, n, true, false, true, 4>, dim3(grid), dim3(n * 64),          \
-                      f.lds_bytes, st, ev, none, views, it, n_items, 0, f.tab_max, f.list_cap);
+                      f.lds_bytes, st, ev, none, views, it, n_items, 0, f.tab_max, f.list_cap,    \
+                      queue);
     if (f.vec == 4) {
         if (f.elem != 4) return hipErrorInvalidValue;
         SF_V4_SHAPES(SF_DISPATCH4)
@@ -2560,10 +2598,10 @@ hipError_t launch_field(const FieldLaunch &f, const SceneView *views, const int3
         return f.elem == 4                                                                      \
                    ? launch(k_field<a, b, n, true, false, true>, dim3(grid), dim3(n * 64),      \
                             f.lds_bytes, st, ev, none, views, it, n_items, 0, f.tab_max,        \
-                            f.list_cap)                                                         \
+                            f.list_cap, queue)                                                  \
                    : launch(k_field<a, b, n, true, false, false>, dim3(grid), dim3(n * 64),     \
                             f.lds_bytes, st, ev, none, views, it, n_items, 0, f.tab_max,        \
-                            f.list_cap);
+                            f.list_cap, queue);
     SF_LIST_SHAPES(SF_DISPATCH)
 #undef SF_DISPATCH
     return hipErrorInvalidValue;
@@ -2626,7 +2664,8 @@ hipError_t launch_field_one(const FieldLaunch &f, const SceneView &view, int per
     if (f.tw == a && f.hl == b && f.nw == n)                                                    \
         return launch(k_field<a, b, n, false, false, true, 4>, dim3(grid), dim3(n * 64),         \
                       f.lds_bytes, st, ev, view, (const SceneView *)nullptr,                    \
-                      (const int4 *)nullptr, n_items, per, f.tab_max, f.list_cap);
+                      (const int4 *)nullptr, n_items, per, f.tab_max, f.list_cap,       \
+                      (unsigned int *)nullptr);
     if (f.vec == 4) {
         if (f.elem != 4) return hipErrorInvalidValue;
         SF_V4_SHAPES(SF_DISPATCH4)
@@ -2639,10 +2678,12 @@ hipError_t launch_field_one(const FieldLaunch &f, const SceneView &view, int per
         return f.elem == 4                                                                      \
                    ? launch(k_field<a, b, n, false, false, true>, dim3(grid), dim3(n * 64),     \
                             f.lds_bytes, st, ev, view, (const SceneView *)nullptr,              \
-                            (const int4 *)nullptr, n_items, per, f.tab_max, f.list_cap)         \
+                            (const int4 *)nullptr, n_items, per, f.tab_max, f.list_cap,       \
+                      (unsigned int *)nullptr)         \
                    : launch(k_field<a, b, n, false, false, false>, dim3(grid), dim3(n * 64),    \
                             f.lds_bytes, st, ev, view, (const SceneView *)nullptr,              \
-                            (const int4 *)nullptr, n_items, per, f.tab_max, f.list_cap);
+                            (const int4 *)nullptr, n_items, per, f.tab_max, f.list_cap,       \
+                      (unsigned int *)nullptr);
     SF_LIST_SHAPES(SF_DISPATCH)
 #undef SF_DISPATCH
     return hipErrorInvalidValue;
@@ -2657,7 +2698,8 @@ hipError_t launch_field_update(const FieldLaunch &f, const SceneView &view, int 
     if (f.tw == a && f.hl == b && f.nw == n)                                                    \
         return launch(k_field<a, b, n, false, true, true, 4>, dim3(grid), dim3(n * 64),          \
                       f.lds_bytes, st, ev, view, (const SceneView *)nullptr,                    \
-                      (const int4 *)nullptr, n_items, per, f.tab_max, f.list_cap);
+                      (const int4 *)nullptr, n_items, per, f.tab_max, f.list_cap,       \
+                      (unsigned int *)nullptr);
     if (f.vec == 4) {
         if (f.elem != 4) return hipErrorInvalidValue;
         SF_V4_SHAPES(SF_DISPATCH4)
@@ -2670,10 +2712,12 @@ hipError_t launch_field_update(const FieldLaunch &f, const SceneView &view, int 
         return f.elem == 4                                                                      \
                    ? launch(k_field<a, b, n, false, true, true>, dim3(grid), dim3(n * 64),      \
                             f.lds_bytes, st, ev, view, (const SceneView *)nullptr,              \
-                            (const int4 *)nullptr, n_items, per, f.tab_max, f.list_cap)         \
+                            (const int4 *)nullptr, n_items, per, f.tab_max, f.list_cap,       \
+                      (unsigned int *)nullptr)         \
                    : launch(k_field<a, b, n, false, true, false>, dim3(grid), dim3(n * 64),     \
                             f.lds_bytes, st, ev, view, (const SceneView *)nullptr,              \
-                            (const int4 *)nullptr, n_items, per, f.tab_max, f.list_cap);
+                            (const int4 *)nullptr, n_items, per, f.tab_max, f.list_cap,       \
+                      (unsigned int *)nullptr);
     SF_LIST_SHAPES(SF_DISPATCH)
 #undef SF_DISPATCH
     return hipErrorInvalidValue;
