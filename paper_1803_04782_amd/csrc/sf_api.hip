@@ -1562,7 +1562,7 @@ int batch_tune(sf_batch *b, int32_t reps, sf_batch_tiling *chosen)
                                     {8, 4, 4, 2},  {16, 4, 4, 4}, {16, 4, 8, 4}, {32, 4, 4, 4},
                                     {8, 4, 4, 4},  {16, 4, 16, 4}, {32, 8, 4, 4}, {16, 8, 4, 4}};
     const int caps[] = {1024, 2048, 4096};
-    const int ipbs[] = {2, 8};
+    const int ipbs[] = {2, 8, 32};
     sf_batch_tiling best = b->cur.t;
     std::vector<SceneView> scratch_views(b->scenes.size());
     for (int gi = 0; gi < b->cur.n_groups; ++gi) {
