@@ -1688,22 +1688,25 @@ __global__ __launch_bounds__(kDecideThreads) void k_decide_claim(
                 // every load is issued unconditionally at a clamped (in-grid)
                 // su and all are waited for once; the values outside the grid
                 // or beside the word are then replaced
-                unsigned long long wm[3], wl[3], wr[3];
+                // per row the word of column x and the word on the side of x's
+                // nearer word edge (the only neighbour word a column x - 1 or
+                // x + 1 can fall into)
+                unsigned long long wm[3], we[3];
                 float pr[3][3];
+                const int wn = min(max(b < 32 ? w - 1 : w + 1, 0), wpr - 1);
 #pragma unroll
                 for (int r = 0; r < 3; ++r) {
                     const int yc = min(max(y - 1 + r, 0), H - 1);
                     const size_t rw = (size_t)yc * wpr;
                     wm[r] = occ[rw + w];
-                    wl[r] = occ[rw + max(w - 1, 0)];
-                    wr[r] = occ[rw + min(w + 1, wpr - 1)];
+                    we[r] = occ[rw + wn];
 #pragma unroll
                     for (int c = 0; c < 3; ++c)
                         pr[r][c] = P[(size_t)yc * W + min(max(x - 1 + c, 0), W - 1)];
                 }
 #pragma unroll
                 for (int r = 0; r < 3; ++r) {
-                    asm volatile("" : "+v"(wm[r]), "+v"(wl[r]), "+v"(wr[r]));
+                    asm volatile("" : "+v"(wm[r]), "+v"(we[r]));
                     asm volatile("" : "+v"(pr[r][0]), "+v"(pr[r][1]), "+v"(pr[r][2]));
                 }
 #pragma unroll
@@ -1712,8 +1715,8 @@ __global__ __launch_bounds__(kDecideThreads) void k_decide_claim(
                     row[r] = yy;
                     const bool row_in = yy >= 0 && yy < H;
                     const unsigned long long mid = row_in ? wm[r] : 0ull;
-                    const unsigned long long lft = row_in && b == 0 && w > 0 ? wl[r] : 0ull;
-                    const unsigned long long rgt = row_in && b == 63 && w + 1 < wpr ? wr[r] : 0ull;
+                    const unsigned long long lft = row_in && b == 0 && w > 0 ? we[r] : 0ull;
+                    const unsigned long long rgt = row_in && b == 63 && w + 1 < wpr ? we[r] : 0ull;
                     const unsigned int cl = b > 0 ? (unsigned int)(mid >> (b - 1)) & 1u
                                                   : (unsigned int)(lft >> 63);
                     const unsigned int cc = (unsigned int)(mid >> b) & 1u;
@@ -1816,9 +1819,13 @@ __global__ __launch_bounds__(commit_threads<MULTI>()) void k_commit(SceneView on
             if (f & kFlagMover) {
                 // the winner is the only registrant that finds its own key; it
                 // also resets the word, which losers then read as "not mine"
-                const unsigned long long cw = claims[tgt].word;
+                // the claim record in one 16-byte load: word, registrations
+                typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+                const u32x4 rec =
+                    *reinterpret_cast<const __attribute__((address_space(1))) u32x4 *>(&claims[tgt]);
+                const unsigned long long cw = ((unsigned long long)rec[1] << 32) | rec[0];
                 const bool to_exit = exitm[tgt] != 0;
-                const unsigned int nreg = claims[tgt].regs;
+                const unsigned int nreg = rec[2];
                 const unsigned long long kk = key[i];
                 if (cw == kk) {
                     // every registration of this tick is counted by now (decide
