@@ -59,6 +59,7 @@ struct EventPair {
 struct sf_scene {
     // description
     int W = 0, H = 0, N = 0, R = 0, R_obs = 0;
+    int fp = 0;  // row pitch of S, P, phi and phi32 (sf::field_pitch(W))
     double k = 1, alpha = -0.5, k_obs = 1, alpha_obs = -0.5, w_dest = 1;
     unsigned long long seed = 0;
     int64_t start_step = 0;
@@ -539,8 +540,8 @@ int build_statics(sf_scene *s, const uint8_t *h_obst, const uint8_t *h_exit)
     if (s->periodic) {
         // a torus without obstacles or openings: no static field
         SF_HIP(sf::launch_fill_i32(s->D, (size_t)n, 0, st), "destination field");
-        SF_HIP(sf::launch_fill_u64(reinterpret_cast<unsigned long long *>(s->S), (size_t)n, 0ull,
-                                   st),
+        SF_HIP(sf::launch_fill_u64(reinterpret_cast<unsigned long long *>(s->S),
+                                   (size_t)s->fp * H, 0ull, st),
                "static field");
         SF_HIP(hipMemcpyAsync(s->exitm, h_exit, (size_t)n, hipMemcpyHostToDevice, st),
                "copy exits");
@@ -629,7 +630,11 @@ int build_statics(sf_scene *s, const uint8_t *h_obst, const uint8_t *h_exit)
                            st)))
         return rc;
     SF_HIP(sf::launch_superpose_f64(ocg, obits, s->wpr, tab64, O, W, H, st), "obstacle field");
-    SF_HIP(sf::launch_static_S(s->D, O, obst, s->w_dest, s->S, n, st), "static field");
+    // the padding columns of S are never read; they are cleared all the same
+    SF_HIP(sf::launch_fill_u64(reinterpret_cast<unsigned long long *>(s->S), (size_t)s->fp * H,
+                               0ull, st),
+           "static field");
+    SF_HIP(sf::launch_static_S(s->D, O, obst, s->w_dest, s->S, W, H, s->fp, st), "static field");
     SF_HIP(hipStreamSynchronize(st), "statics sync");
     for (size_t i = first_tmp; i < s->owned.size(); ++i) (void)hipFree(s->owned[i]);
     s->owned.resize(first_tmp);
@@ -795,7 +800,9 @@ int create(const sf_scene_desc *d, void *hip_stream, sf_scene **out)
 
     const size_t n = (size_t)s->W * s->H;
     const size_t N = (size_t)s->N;
-    if ((rc = dalloc(s, &s->S, n, "S")) || (rc = dalloc(s, &s->P, n, "P")) ||
+    s->fp = sf::field_pitch(s->W);
+    const size_t nf = (size_t)s->fp * s->H;
+    if ((rc = dalloc(s, &s->S, nf, "S")) || (rc = dalloc(s, &s->P, nf, "P")) ||
         (rc = dalloc(s, &s->D, n, "D")) || (rc = dalloc(s, &s->exitm, n, "exit mask")) ||
         (rc = dalloc(s, &s->tab, (size_t)s->lc.tab_elems, "phi table")) ||
         (s->int_ok && (rc = dalloc(s, &s->tabi, (size_t)s->lc.tab_elems, "phi table"))) ||
@@ -855,6 +862,7 @@ int setup_launches(sf_scene *s)
     v = SceneView{};
     v.W = s->W;
     v.H = s->H;
+    v.fp = s->fp;
     v.wpr = s->wpr;
     v.N = s->N;
     v.R = s->R;
@@ -944,7 +952,7 @@ int set_field_update(sf_scene *s, int32_t refresh)
         int rc;
         if ((rc = dalloc(s, &s->moved_from, nwords, "moved bitmap")) ||
             (rc = dalloc(s, &s->moved_to, nwords, "moved bitmap")) ||
-            (rc = dalloc(s, &s->phi, (size_t)s->W * s->H, "pedestrian field")))
+            (rc = dalloc(s, &s->phi, (size_t)s->fp * s->H, "pedestrian field")))
             return rc;
         SF_HIP(sf::launch_fill_u64(s->moved_from, nwords, 0ull, s->stream), "clear moves");
         SF_HIP(sf::launch_fill_u64(s->moved_to, nwords, 0ull, s->stream), "clear moves");
@@ -1009,7 +1017,8 @@ int set_field_sect(sf_scene *s, int K, bool keep_image)
         if (!s->sect_terms && (rc = dalloc(s, &s->sect_terms, (size_t)std::max(n_real, 1),
                                            "sect terms")))
             return rc;
-        if (!s->phi32 && (rc = dalloc(s, &s->phi32, n, "FP32 field"))) return rc;
+        if (!s->phi32 && (rc = dalloc(s, &s->phi32, (size_t)s->fp * s->H, "FP32 field")))
+            return rc;
         if (keep_image && !s->image && (rc = dalloc(s, &s->image, 8 * n, "sect image")))
             return rc;
         if (n_real)
@@ -1020,6 +1029,7 @@ int set_field_sect(sf_scene *s, int K, bool keep_image)
         v = sf::SectView{};
         v.W = s->W;
         v.H = s->H;
+        v.fp = s->fp;
         v.wpr = s->wpr;
         v.R = R;
         v.periodic = s->periodic ? 1 : 0;
@@ -1039,6 +1049,20 @@ int set_field_sect(sf_scene *s, int K, bool keep_image)
     s->since_full = s->refresh;
     SF_HIP(scene_field(s, s->view, s->stream), "superpose");
     SF_HIP(hipStreamSynchronize(s->stream), "field path sync");
+    return SF_OK;
+}
+
+// rows of `row_bytes` each, `src_pitch` bytes apart on the device, to a
+// dense destination
+int copy_out_rows(const sf_scene *s, void *dst, const void *src, size_t row_bytes,
+                  size_t src_pitch, size_t rows, int on_device)
+{
+    if (!dst) return SF_OK;
+    SF_HIP(hipMemcpy2DAsync(dst, row_bytes, src, src_pitch, row_bytes, rows,
+                            on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                            s->stream),
+           "copy out");
+    if (!on_device) SF_HIP(hipStreamSynchronize(s->stream), "copy out sync");
     return SF_OK;
 }
 
@@ -1702,6 +1726,7 @@ int superpose_enqueue(const SuperposeCall &c, unsigned long long *bits, void *ta
     SceneView v{};
     v.W = c.W;
     v.H = c.H;
+    v.fp = c.W;  // the caller's S and P are dense rows
     v.wpr = c.wpr;
     v.R = R;
     v.S = c.S;
@@ -1814,7 +1839,8 @@ int sf_field(const sf_scene *s, float *dst, int dst_on_device)
 {
     if (!s || !dst) return fail(SF_EINVAL, "scene or dst is NULL");
     DeviceGuard g(s->device);
-    return copy_out(s, dst, s->P, (size_t)s->W * s->H * sizeof(float), dst_on_device);
+    return copy_out_rows(s, dst, s->P, (size_t)s->W * sizeof(float), (size_t)s->fp * sizeof(float),
+                         (size_t)s->H, dst_on_device);
 }
 
 int sf_positions(const sf_scene *s, int32_t *pos, uint8_t *alive, int dst_on_device)
@@ -1851,7 +1877,8 @@ int sf_static_field(const sf_scene *s, double *S, int32_t *D, int dst_on_device)
     if (!s) return fail(SF_EINVAL, "scene is NULL");
     DeviceGuard g(s->device);
     const size_t n = (size_t)s->W * s->H;
-    int rc = copy_out(s, S, s->S, n * sizeof(double), dst_on_device);
+    int rc = copy_out_rows(s, S, s->S, (size_t)s->W * sizeof(double),
+                           (size_t)s->fp * sizeof(double), (size_t)s->H, dst_on_device);
     if (rc) return rc;
     return copy_out(s, D, s->D, n * sizeof(int32_t), dst_on_device);
 }
@@ -1867,7 +1894,9 @@ int sf_set_state(sf_scene *s, const int32_t *pos, int64_t step)
         const size_t n = (size_t)s->W * s->H;
         std::vector<uint8_t> obst(n), exitm(n);
         std::vector<double> S(n);
-        SF_HIP(hipMemcpyAsync(S.data(), s->S, n * sizeof(double), hipMemcpyDeviceToHost, s->stream),
+        SF_HIP(hipMemcpy2DAsync(S.data(), (size_t)s->W * sizeof(double), s->S,
+                                (size_t)s->fp * sizeof(double), (size_t)s->W * sizeof(double),
+                                (size_t)s->H, hipMemcpyDeviceToHost, s->stream),
                "copy S");
         SF_HIP(hipMemcpyAsync(exitm.data(), s->exitm, n, hipMemcpyDeviceToHost, s->stream),
                "copy exits");

@@ -116,6 +116,10 @@ hipError_t launch_clear_claims(ClaimRec *c, size_t n, hipStream_t st);
 // scenes; every scene of a launch has its own view.
 struct SceneView {
     int32_t W, H, wpr, N;
+    // row pitch (elements) of the su-indexed field arrays S, P and phi; su
+    // (x, y) is element y * fp + x of them, while positions and every other
+    // su array keep pitch W (see field_pitch)
+    int32_t fp;
     int32_t R;
     int32_t dec_block0;  // first workgroup of this scene in the decide launch
     int32_t com_block0;  // first workgroup of this scene in the commit launch
@@ -165,6 +169,13 @@ struct SceneView {
     unsigned long long *bodies;
     const unsigned long long *obits;
 };
+
+// Row pitch of a scene's field arrays: W rounded up to a multiple of 32, so
+// that every row of P starts on a 128-byte boundary and every row of S on a
+// 256-byte one.  A strip's rows are then read and written in whole cache
+// lines (a tile of 16 or 32 columns starts at a multiple of 16 columns), not
+// in pieces that straddle two lines.
+inline int field_pitch(int W) { return (W + 31) & ~31; }
 
 // Field layout fields of `v` for shape `c` (built for the scene's radius):
 // the gather reads tabi (unit q) when c.elem == 4, else tab.
@@ -234,6 +245,7 @@ hipError_t launch_commit_body(const SceneView &view, hipStream_t st,
 // y = the FP32 strength's bits; sect by sect, row-major within a sect.
 struct SectView {
     int32_t W, H, wpr, R, periodic;
+    int32_t fp;  // row pitch of S, P and phi32 (the image planes keep pitch W)
     int32_t K, m, n_real;
     const int2 *terms;
     const unsigned long long *src;   // sources (full field) or the su entered (update)
@@ -271,8 +283,9 @@ hipError_t launch_count_unreachable(const uint8_t *obst, const int32_t *D, int n
 hipError_t launch_superpose_f64(const SupCfg &c, const unsigned long long *bits, int wpr,
                                 const double *tab, double *out, int W, int H, hipStream_t st);
 hipError_t set_superpose_lds_limit(size_t f64_bytes);
+// S (row pitch fp) from D, O and the obstacle mask (row pitch W)
 hipError_t launch_static_S(const int32_t *D, const double *O, const uint8_t *obst,
-                           double w_dest, double *S, int n, hipStream_t st);
+                           double w_dest, double *S, int W, int H, int fp, hipStream_t st);
 hipError_t launch_occ_init(const int32_t *pos, int N, unsigned long long *occ, int wpr, int W,
                            unsigned long long *ctr, hipStream_t st);
 // Stateless superposition: bitmap bits of the entries 0 <= pos[i] < nsu (the

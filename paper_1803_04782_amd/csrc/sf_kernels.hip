@@ -350,14 +350,17 @@ __global__ void k_count_unreachable(const uint8_t *__restrict__ obst, const int3
 }
 
 // S = fl64(fl64(w_dest*D) + O), +inf on obstacles: the product is rounded
-// before the sum (no fused multiply-add).
+// before the sum (no fused multiply-add).  D, O and obst have row pitch W, S
+// has row pitch fp (its padding columns are left as they are).
 __global__ void k_static_S(const int32_t *__restrict__ D, const double *__restrict__ O,
                            const uint8_t *__restrict__ obst, double w_dest, double *__restrict__ S,
-                           int n)
+                           int W, int H, int fp)
 {
     const size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= (size_t)n) return;
-    S[c] = obst[c] ? (double)INFINITY : __dadd_rn(__dmul_rn(w_dest, (double)D[c]), O[c]);
+    if (c >= (size_t)W * H) return;
+    const size_t y = c / (size_t)W, x = c - y * (size_t)W;
+    S[y * (size_t)fp + x] =
+        obst[c] ? (double)INFINITY : __dadd_rn(__dmul_rn(w_dest, (double)D[c]), O[c]);
 }
 
 // ---- field superposition --------------------------------------------------------
@@ -560,7 +563,7 @@ __device__ __forceinline__ void gather_one(T *acc, uint32_t a)
 // The part of a scene's view that the field kernel reads, kept in scalar
 // registers (a whole SceneView copy would be placed in private memory).
 struct FieldScene {
-    int W, H, wpr, R, tiles_x, stride, padx, pady, max_row, tab_vecs, periodic;
+    int W, H, fp, wpr, R, tiles_x, stride, padx, pady, max_row, tab_vecs, periodic;
     int rounds;  // integer stamps: rounds of 8 sources summed in 32 bits before a flush
     // the stamp (doubles, or integers in units of q), tab_vecs 16-byte vectors
     gptr<const f64x2> tab;
@@ -578,6 +581,7 @@ __device__ __forceinline__ FieldScene field_scene(const SceneView &v)
     FieldScene f;
     f.W = v.W;
     f.H = v.H;
+    f.fp = v.fp;
     f.wpr = v.wpr;
     f.R = v.R;
     f.tiles_x = v.tiles_x;
@@ -853,7 +857,7 @@ __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
 #pragma unroll
         for (int r = 0; r < HL; ++r) {
             const int y = y0 + lrow(r);
-            const size_t c = (size_t)min(y, s.H - 1) * s.W + min(x, s.W - 1);
+            const size_t c = (size_t)min(y, s.H - 1) * s.fp + min(x, s.W - 1);
             sv_n[r] = s.S[c];
             pv_n[r] = 0.0;
             if constexpr (DUAL) pv_n[r] = s.phi[c];
@@ -1130,7 +1134,7 @@ __global__ __launch_bounds__(NW * 64) void k_field(SceneView one,
                 double f = a0;
                 if constexpr (DUAL) f = (pv[r] + a0) - a1;
                 if (y < H) {
-                    const size_t c = (size_t)y * W + x;
+                    const size_t c = (size_t)y * v.fp + x;
                     if (v.phi) v.phi[c] = f;
                     v.P[c] = (float)(sv[r] + f);
                 }
@@ -1247,7 +1251,7 @@ template <int R>
 __global__ __launch_bounds__(kDenseWaves * 64) void k_field_dense(SceneView one, int n_tiles)
 {
     constexpr int K = 2 * R + 1, NR = kDenseHL + 2 * R;
-    const int W = one.W, H = one.H, wpr = one.wpr;
+    const int W = one.W, H = one.H, wpr = one.wpr, fp = one.fp;
     const gptr<const unsigned long long> occ = to_global((const unsigned long long *)one.occ);
     const gptr<const double> S = to_global(one.S);
     const gptr<float> P = to_global(one.P);
@@ -1278,7 +1282,7 @@ __global__ __launch_bounds__(kDenseWaves * 64) void k_field_dense(SceneView one,
 #pragma unroll
         for (int h = 0; h < kDenseHL; ++h) {
             const int y = y0 + h;
-            sv[h] = S[(size_t)min(y, H - 1) * W + min(x, W - 1)];
+            sv[h] = S[(size_t)min(y, H - 1) * fp + min(x, W - 1)];
         }
         for (int k = tid; k < TR * 3; k += kDenseWaves * 64) {
             const int r = k / 3, c = k - r * 3;
@@ -1326,7 +1330,7 @@ __global__ __launch_bounds__(kDenseWaves * 64) void k_field_dense(SceneView one,
             for (int h = 0; h < kDenseHL; ++h) {
                 const int y = y0 + h;
                 if (x < W && y < H) {
-                    const size_t c = (size_t)y * W + x;
+                    const size_t c = (size_t)y * fp + x;
                     if (one.phi) phi_out[c] = acc[h];
                     P[c] = (float)(sv[h] + acc[h]);
                 }
@@ -1420,7 +1424,7 @@ __global__ __launch_bounds__(kSectWaves * 64) void k_field_sect(SectView v, int 
         float fv[kSectHL];
 #pragma unroll
         for (int h = 0; h < kSectHL; ++h) {
-            const size_t c = (size_t)min(y0 + h, H - 1) * W + min(x, W - 1);
+            const size_t c = (size_t)min(y0 + h, H - 1) * v.fp + min(x, W - 1);
             sv[h] = S[c];
             fv[h] = UPDATE ? F[c] : 0.0f;
         }
@@ -1495,7 +1499,7 @@ __global__ __launch_bounds__(kSectWaves * 64) void k_field_sect(SectView v, int 
 #pragma unroll
         for (int h = 0; h < kSectHL; ++h) {
             if (store && y0 + h < H) {
-                const size_t c = (size_t)(y0 + h) * W + x;
+                const size_t c = (size_t)(y0 + h) * v.fp + x;
                 const float f = UPDATE ? fv[h] + tot[h] : tot[h];
                 F[c] = f;
                 P[c] = (float)(sv[h] + (double)f);
@@ -1625,7 +1629,7 @@ __global__ __launch_bounds__(kDecideThreads) void k_decide_claim(
                     q0[r] = occ[rw + wp0];
                     q1[r] = occ[rw + wp0 + 1];
                     qs[r] = occ[rw + ws];
-                    const size_t rp = (size_t)yy * W;
+                    const size_t rp = (size_t)yy * v.fp;
                     t0[r] = P[rp + xb0];
                     t1[r] = P[rp + xb0 + 1];
                     t2[r] = P[rp + xb0 + 2];
@@ -1676,7 +1680,7 @@ __global__ __launch_bounds__(kDecideThreads) void k_decide_claim(
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
                         m |= (unsigned int)(occ[rw + (col[c] >> 6)] >> (col[c] & 63) & 1ull) << c;
-                        pv[r][c] = P[(size_t)yy * W + col[c]];
+                        pv[r][c] = P[(size_t)yy * v.fp + col[c]];
                     }
                     nb3[r] = m;
                 }
@@ -1702,7 +1706,7 @@ __global__ __launch_bounds__(kDecideThreads) void k_decide_claim(
                     we[r] = occ[rw + wn];
 #pragma unroll
                     for (int c = 0; c < 3; ++c)
-                        pr[r][c] = P[(size_t)yc * W + min(max(x - 1 + c, 0), W - 1)];
+                        pr[r][c] = P[(size_t)yc * v.fp + min(max(x - 1 + c, 0), W - 1)];
                 }
 #pragma unroll
                 for (int r = 0; r < 3; ++r) {
@@ -2018,7 +2022,7 @@ __global__ __launch_bounds__(kDecideThreads) void k_decide_body(SceneView v)
                                  : turn == 1 ? -hw_diag
                                              : turn == 2 ? 0.0f : turn == 3 ? hw_diag : hw_axis;
             };
-            float lo = P[p], lo2 = INFINITY;
+            float lo = P[(size_t)y * v.fp + x], lo2 = INFINITY;
             int best = 0;
             for (int d = 1; d <= 8; ++d) {
                 const int ex = kDirX[d], ey = kDirY[d];
@@ -2033,7 +2037,7 @@ __global__ __launch_bounds__(kDecideThreads) void k_decide_body(SceneView v)
                 }
                 if (blocked) continue;
                 const int nx = wrap_or_keep(x + ex, W, per), ny = wrap_or_keep(y + ey, H, per);
-                const float pc = P[(size_t)ny * W + nx];
+                const float pc = P[(size_t)ny * v.fp + nx];
                 if (!(pc < INFINITY)) continue;
                 const float u = (pc - ((d & 1) ? phi_axial : phi_diag)) + heading_term(d);
                 if (u < lo) {
@@ -2748,10 +2752,11 @@ hipError_t launch_superpose_f64(const SupCfg &c, const unsigned long long *bits,
 }
 
 hipError_t launch_static_S(const int32_t *D, const double *O, const uint8_t *obst, double w_dest,
-                           double *S, int n, hipStream_t st)
+                           double *S, int W, int H, int fp, hipStream_t st)
 {
+    const int n = W * H;
     hipLaunchKernelGGL(k_static_S, dim3(blocks_for(n, 256, kCoverAll)), dim3(256), 0, st, D, O,
-                       obst, w_dest, S, n);
+                       obst, w_dest, S, W, H, fp);
     return hipGetLastError();
 }
 

@@ -35,12 +35,14 @@ import numpy as np
 from . import sf
 
 # Device bytes a resident scene holds (the library's per-scene arrays):
-# per su  S (FP64, 8 B), P and D (4 B each), exit mask (1), claims (8),
-# registration counts (4), occupancy bits (1/8); per pedestrian  keys (8),
+# per su  D (4 B), exit mask (1), the claim record (claim word, registration
+# count, padding: 16), occupancy bits (1/8), and S (FP64, 8 B) and P (4 B) per su of rows padded to
+# a multiple of 32 columns; per pedestrian  keys (8),
 # positions, targets, id map (4 each), flags (1); plus counters, the stamp and
 # the scene's share of a batch's layout (views, workgroup maps, work items,
 # stamp tables): < 1 MiB.
-BYTES_PER_SU = 8 + 4 + 4 + 1 + 8 + 4 + 0.125
+BYTES_PER_SU = 4 + 1 + 16 + 0.125
+BYTES_PER_PADDED_SU = 8 + 4
 BYTES_PER_PED = 8 + 4 + 4 + 4 + 1
 FIXED_BYTES = 1 << 20
 # Temporaries of scene creation, released when the build ends: per su the
@@ -52,8 +54,9 @@ BUILD_BYTES_PER_SU = 1 + 5 * 0.125 + 8
 def footprint_bytes(scene) -> int:
     """Device bytes a resident scene holds."""
     su = int(scene.width) * int(scene.height)
-    return int(su * BYTES_PER_SU + int(np.asarray(scene.pos).shape[0]) * BYTES_PER_PED
-               + FIXED_BYTES)
+    padded = (int(scene.width) + 31) // 32 * 32 * int(scene.height)
+    return int(su * BYTES_PER_SU + padded * BYTES_PER_PADDED_SU
+               + int(np.asarray(scene.pos).shape[0]) * BYTES_PER_PED + FIXED_BYTES)
 
 
 def build_bytes(scene) -> int:
