@@ -1841,19 +1841,32 @@ __global__ __launch_bounds__(commit_threads<MULTI>()) void k_commit(SceneView on
                     claims[tgt].regs = 0u;
                     const int y = p / W, x = p - y * W;
                     const size_t wp = (size_t)y * wpr + (x >> 6);
-                    __hip_atomic_fetch_and(&occ[wp], ~(1ull << (x & 63)), __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
+                    const unsigned long long bp = 1ull << (x & 63);
                     if (v.moved_from)
-                        __hip_atomic_fetch_or(&to_global(v.moved_from)[wp], 1ull << (x & 63),
-                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        __hip_atomic_fetch_or(&to_global(v.moved_from)[wp], bp, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
                     if (to_exit) {
+                        __hip_atomic_fetch_and(&occ[wp], ~bp, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
                         left = true;
                         pos[i] = -1;
                     } else {
                         const int ty = tgt / W, tx = tgt - ty * W;
                         const size_t wt = (size_t)ty * wpr + (tx >> 6);
-                        __hip_atomic_fetch_or(&occ[wt], 1ull << (tx & 63), __ATOMIC_RELAXED,
-                                              __HIP_MEMORY_SCOPE_AGENT);
+                        const unsigned long long bt = 1ull << (tx & 63);
+                        if (wt == wp) {
+                            // one word: the bit of p is set and the bit of the
+                            // target clear (it was a free candidate, and this
+                            // winner is the only one to enter it), so one
+                            // exclusive or moves the pedestrian
+                            __hip_atomic_fetch_xor(&occ[wp], bp | bt, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+                        } else {
+                            __hip_atomic_fetch_and(&occ[wp], ~bp, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+                            __hip_atomic_fetch_or(&occ[wt], bt, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
+                        }
                         if (v.moved_to)
                             __hip_atomic_fetch_or(&to_global(v.moved_to)[wt], 1ull << (tx & 63),
                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
