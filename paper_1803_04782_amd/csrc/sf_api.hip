@@ -1052,17 +1052,26 @@ int set_field_sect(sf_scene *s, int K, bool keep_image)
     return SF_OK;
 }
 
-// rows of `row_bytes` each, `src_pitch` bytes apart on the device, to a
-// dense destination
-int copy_out_rows(const sf_scene *s, void *dst, const void *src, size_t row_bytes,
-                  size_t src_pitch, size_t rows, int on_device)
+// A field array of the scene (rows of pitch fp, elements of `elem` bytes) to
+// dense rows of W elements: on the device by a copy kernel, to the host as
+// one contiguous copy of the pitched rows, packed on the host.  (A strided
+// runtime copy into pageable host memory read back wrong values under a
+// kernel-tracing profiler; these two forms do not depend on it.)
+int copy_out_rows(const sf_scene *s, void *dst, const void *src, size_t elem, int on_device)
 {
     if (!dst) return SF_OK;
-    SF_HIP(hipMemcpy2DAsync(dst, row_bytes, src, src_pitch, row_bytes, rows,
-                            on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
-                            s->stream),
+    const size_t W = (size_t)s->W, H = (size_t)s->H, fp = (size_t)s->fp;
+    if (on_device) {
+        SF_HIP(sf::launch_copy_rows(src, s->fp, dst, s->W, s->H, (int)elem, s->stream),
+               "copy rows");
+        return SF_OK;
+    }
+    std::vector<unsigned char> tmp(fp * H * elem);
+    SF_HIP(hipMemcpyAsync(tmp.data(), src, tmp.size(), hipMemcpyDeviceToHost, s->stream),
            "copy out");
-    if (!on_device) SF_HIP(hipStreamSynchronize(s->stream), "copy out sync");
+    SF_HIP(hipStreamSynchronize(s->stream), "copy out sync");
+    unsigned char *d = static_cast<unsigned char *>(dst);
+    for (size_t y = 0; y < H; ++y) std::memcpy(d + y * W * elem, &tmp[y * fp * elem], W * elem);
     return SF_OK;
 }
 
@@ -1839,8 +1848,11 @@ int sf_field(const sf_scene *s, float *dst, int dst_on_device)
 {
     if (!s || !dst) return fail(SF_EINVAL, "scene or dst is NULL");
     DeviceGuard g(s->device);
-    return copy_out_rows(s, dst, s->P, (size_t)s->W * sizeof(float), (size_t)s->fp * sizeof(float),
-                         (size_t)s->H, dst_on_device);
+    try {
+        return copy_out_rows(s, dst, s->P, sizeof(float), dst_on_device);
+    } catch (const std::bad_alloc &) {
+        return fail(SF_ENOMEM, "host allocation failed");
+    }
 }
 
 int sf_positions(const sf_scene *s, int32_t *pos, uint8_t *alive, int dst_on_device)
@@ -1877,8 +1889,12 @@ int sf_static_field(const sf_scene *s, double *S, int32_t *D, int dst_on_device)
     if (!s) return fail(SF_EINVAL, "scene is NULL");
     DeviceGuard g(s->device);
     const size_t n = (size_t)s->W * s->H;
-    int rc = copy_out_rows(s, S, s->S, (size_t)s->W * sizeof(double),
-                           (size_t)s->fp * sizeof(double), (size_t)s->H, dst_on_device);
+    int rc;
+    try {
+        rc = copy_out_rows(s, S, s->S, sizeof(double), dst_on_device);
+    } catch (const std::bad_alloc &) {
+        return fail(SF_ENOMEM, "host allocation failed");
+    }
     if (rc) return rc;
     return copy_out(s, D, s->D, n * sizeof(int32_t), dst_on_device);
 }
@@ -1894,10 +1910,8 @@ int sf_set_state(sf_scene *s, const int32_t *pos, int64_t step)
         const size_t n = (size_t)s->W * s->H;
         std::vector<uint8_t> obst(n), exitm(n);
         std::vector<double> S(n);
-        SF_HIP(hipMemcpy2DAsync(S.data(), (size_t)s->W * sizeof(double), s->S,
-                                (size_t)s->fp * sizeof(double), (size_t)s->W * sizeof(double),
-                                (size_t)s->H, hipMemcpyDeviceToHost, s->stream),
-               "copy S");
+        int rc0 = copy_out_rows(s, S.data(), s->S, sizeof(double), 0);
+        if (rc0) return rc0;
         SF_HIP(hipMemcpyAsync(exitm.data(), s->exitm, n, hipMemcpyDeviceToHost, s->stream),
                "copy exits");
         SF_HIP(hipStreamSynchronize(s->stream), "set_state sync");

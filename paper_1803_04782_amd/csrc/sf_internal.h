@@ -304,6 +304,10 @@ hipError_t launch_decide_claim(const SceneView *views, const int32_t *block_scen
                                hipStream_t st, const LaunchEvents *ev = nullptr);
 hipError_t launch_commit(const SceneView *views, const int32_t *block_scene, int n_blocks,
                          hipStream_t st, const LaunchEvents *ev = nullptr);
+// Dense rows from a pitched field array: dst[y * W + x] = src[y * fp + x]
+// (elements of `elem` = 4 or 8 bytes; both pointers on the device).
+hipError_t launch_copy_rows(const void *src, int fp, void *dst, int W, int H, int elem,
+                            hipStream_t st);
 // dst[ext[i]] = src[i] for i < n (internal to caller order).
 hipError_t launch_scatter_i32(const int32_t *src, const int32_t *ext, int32_t *dst, int n,
                               hipStream_t st);

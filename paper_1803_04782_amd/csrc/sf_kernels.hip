@@ -2206,6 +2206,16 @@ __global__ void k_scatter(const T *__restrict__ src, const int32_t *__restrict__
     if (i < (size_t)n) dst[ext[i]] = src[i];
 }
 
+// Rows of a pitched field array into dense rows: dst[y * W + x] = src[y * fp + x].
+template <typename T>
+__global__ void k_copy_rows(const T *__restrict__ src, int fp, T *__restrict__ dst, int W, int H)
+{
+    const size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= (size_t)W * H) return;
+    const size_t y = c / (size_t)W, x = c - y * (size_t)W;
+    dst[c] = src[y * (size_t)fp + x];
+}
+
 // ---- batched counter read-out --------------------------------------------------------
 //
 // Workgroup j sums the slot copies of every running total of scene j into
@@ -2821,6 +2831,24 @@ hipError_t launch_scatter_u8(const uint8_t *src, const int32_t *ext, uint8_t *ds
 {
     hipLaunchKernelGGL(k_scatter<uint8_t>, dim3(blocks_for((size_t)n, 256, kCoverAll)), dim3(256),
                        0, st, src, ext, dst, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_rows(const void *src, int fp, void *dst, int W, int H, int elem,
+                            hipStream_t st)
+{
+    const size_t n = (size_t)W * H;
+    if (n == 0) return hipSuccess;
+    if (elem == 4)
+        hipLaunchKernelGGL(k_copy_rows<uint32_t>, dim3(blocks_for(n, 256, kCoverAll)), dim3(256),
+                           0, st, static_cast<const uint32_t *>(src), fp,
+                           static_cast<uint32_t *>(dst), W, H);
+    else if (elem == 8)
+        hipLaunchKernelGGL(k_copy_rows<unsigned long long>, dim3(blocks_for(n, 256, kCoverAll)),
+                           dim3(256), 0, st, static_cast<const unsigned long long *>(src), fp,
+                           static_cast<unsigned long long *>(dst), W, H);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

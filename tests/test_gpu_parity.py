@@ -283,6 +283,29 @@ def test_refresh_field(sf):
         assert np.array_equal(g.field(), P_ref)
 
 
+@pytest.mark.parametrize("W", [100, 128, 161])
+def test_field_exports_of_padded_rows(sf, W):
+    """The field arrays hold rows padded to a multiple of 32 columns: the host
+    copy, the device copy and the oracle's field agree su for su, and so do
+    the host and device copies of the static field (widths below, at and
+    above a multiple of 32)."""
+    import torch
+
+    sc = scenes.random_scene(W, 77, n_peds=400, radius=5, seed=W, bernoulli=0.05)
+    st = oracle.statics(sc)
+    with sf.GpuScene(sc) as g:
+        g.step(3)
+        P = g.field()
+        dev = torch.empty(W * 77, dtype=torch.float32, device="cuda:0")
+        g.field(out=dev)
+        torch.cuda.synchronize()
+        assert np.array_equal(P.view(np.uint32), dev.cpu().numpy().view(np.uint32))
+        want = oracle.total_field(st, g.positions()).astype(np.float32)
+        assert not field_bits_differ(P, want)
+        S, D = g.static_field()
+        assert np.array_equal(S, st.S) and np.array_equal(D, st.D)
+
+
 def test_stats_consistency(sf):
     sc = scenes.random_scene(90, 70, n_peds=700, radius=4, seed=5, bernoulli=0.02,
                              exits=("E", "W", "N"), exit_width=8)
