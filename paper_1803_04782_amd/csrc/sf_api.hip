@@ -687,7 +687,8 @@ int upload_positions(sf_scene *s, const int32_t *pos)
 
 // Copy a per-pedestrian array to caller order: dst[ext[i]] = src[i].
 template <typename T>
-int copy_by_caller_id(const sf_scene *s, T *dst, const T *src, int dst_on_device)
+int copy_by_caller_id(const sf_scene *s, T *dst, const T *src, int dst_on_device,
+                      T mask = (T)-1)
 {
     const int N = s->N;
     if (!dst || N == 0) return SF_OK;
@@ -698,7 +699,8 @@ int copy_by_caller_id(const sf_scene *s, T *dst, const T *src, int dst_on_device
                                        reinterpret_cast<int32_t *>(dst), N, s->stream);
         else
             e = sf::launch_scatter_u8(reinterpret_cast<const uint8_t *>(src), s->ext,
-                                      reinterpret_cast<uint8_t *>(dst), N, s->stream);
+                                      reinterpret_cast<uint8_t *>(dst), N, (uint8_t)mask,
+                                      s->stream);
         SF_HIP(e, "scatter by id");
         return SF_OK;
     }
@@ -706,7 +708,7 @@ int copy_by_caller_id(const sf_scene *s, T *dst, const T *src, int dst_on_device
     SF_HIP(hipMemcpyAsync(tmp.data(), src, (size_t)N * sizeof(T), hipMemcpyDeviceToHost, s->stream),
            "copy out");
     SF_HIP(hipStreamSynchronize(s->stream), "copy out sync");
-    for (int i = 0; i < N; ++i) dst[s->h_ext[(size_t)i]] = tmp[(size_t)i];
+    for (int i = 0; i < N; ++i) dst[s->h_ext[(size_t)i]] = (T)(tmp[(size_t)i] & mask);
     return SF_OK;
 }
 
@@ -1878,7 +1880,8 @@ int sf_last_moves(const sf_scene *s, int32_t *target, uint8_t *flags, int dst_on
     try {
         int rc = copy_by_caller_id(s, target, (const int32_t *)s->target, dst_on_device);
         if (rc) return rc;
-        return copy_by_caller_id(s, flags, (const uint8_t *)s->flags, dst_on_device);
+        return copy_by_caller_id(s, flags, (const uint8_t *)s->flags, dst_on_device,
+                                 sf::kPublicFlagBits);
     } catch (const std::bad_alloc &) {
         return fail(SF_ENOMEM, "host allocation failed");
     }

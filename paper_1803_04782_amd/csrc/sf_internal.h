@@ -311,8 +311,12 @@ hipError_t launch_copy_rows(const void *src, int fp, void *dst, int W, int H, in
 // dst[ext[i]] = src[i] for i < n (internal to caller order).
 hipError_t launch_scatter_i32(const int32_t *src, const int32_t *ext, int32_t *dst, int n,
                               hipStream_t st);
+// dst[ext[i]] = src[i] & mask for i < n.
 hipError_t launch_scatter_u8(const uint8_t *src, const int32_t *ext, uint8_t *dst, int n,
-                             hipStream_t st);
+                             uint8_t mask, hipStream_t st);
+// the flag bits a caller sees (SF_FLAG_MOVER | SF_FLAG_WON | SF_FLAG_TIED); the
+// kernels keep internal bits above them
+constexpr uint8_t kPublicFlagBits = 7u;
 // out[j*16 + 0] = step of scene j, out[j*16 + 1 + id] = running total id
 // (kMaxClaim: the maximum over the slots, every other total: their sum).
 hipError_t launch_sum_counters(const SceneView *views, int n_scenes, unsigned long long *out,

@@ -33,6 +33,11 @@ constexpr int kDirY[9] = {0, 0, 1, 1, 1, 0, -1, -1, -1};
 // per-pedestrian flag bits of the last tick (SF_FLAG_* of the public header);
 // distinct from the running-total ids kMovers, kMoved, kTied
 constexpr uint8_t kFlagMover = 1u, kFlagWon = 2u, kFlagTied = 4u;
+// internal: a mover that no other pedestrian can contest (no pedestrian on
+// the su around its target but itself) wins without registering
+constexpr uint8_t kFlagSolo = 8u;
+static_assert((kFlagMover | kFlagWon | kFlagTied) == kPublicFlagBits && !(kFlagSolo & kPublicFlagBits),
+              "public flag bits");
 
 // ---- small helpers ------------------------------------------------------------
 
@@ -1603,6 +1608,15 @@ __global__ __launch_bounds__(kDecideThreads) void k_decide_claim(
             // col[] (periodic: wrapped across the edges)
             unsigned int nb3[3];
             float pv[3][3];
+            // bounded grids of a single scene: the 5 x 5 block of centres
+            // around the pedestrian (solo_ok once it is loaded).  Tori and
+            // batches register every move: in a batch, decide runs beside the
+            // other radius groups' field launches, and the lighter decide and
+            // commit measured slower there (256-scene tick 3.39 -> 3.48 ms:
+            // the concurrent schedule of the groups shifted against the field
+            // of the largest stamps)
+            unsigned int win25 = 0u;
+            bool solo_ok = false;
             int col[3], row[3];
             if (v.periodic && W >= 3 && wpr >= 2) {
                 col[0] = x == 0 ? W - 1 : x - 1;
@@ -1695,32 +1709,65 @@ __global__ __launch_bounds__(kDecideThreads) void k_decide_claim(
                 // per row the word of column x and the word on the side of x's
                 // nearer word edge (the only neighbour word a column x - 1 or
                 // x + 1 can fall into)
-                unsigned long long wm[3], we[3];
+                // (one scene: rows y - 2 and y + 2 too, the 5 x 5 block of
+                // centres that tells whether anyone else can register at the
+                // chosen target)
+                constexpr bool SOLO = !MULTI;
+                unsigned long long wm[5] = {}, we[5] = {};
                 float pr[3][3];
                 const int wn = min(max(b < 32 ? w - 1 : w + 1, 0), wpr - 1);
 #pragma unroll
-                for (int r = 0; r < 3; ++r) {
-                    const int yc = min(max(y - 1 + r, 0), H - 1);
+                for (int r = 0; r < 5; ++r) {
+                    if (!SOLO && (r == 0 || r == 4)) continue;
+                    const int yc = min(max(y - 2 + r, 0), H - 1);
                     const size_t rw = (size_t)yc * wpr;
                     wm[r] = occ[rw + w];
                     we[r] = occ[rw + wn];
+                    if (r >= 1 && r <= 3) {
 #pragma unroll
-                    for (int c = 0; c < 3; ++c)
-                        pr[r][c] = P[(size_t)yc * v.fp + min(max(x - 1 + c, 0), W - 1)];
+                        for (int c = 0; c < 3; ++c)
+                            pr[r - 1][c] = P[(size_t)yc * v.fp + min(max(x - 1 + c, 0), W - 1)];
+                    }
                 }
 #pragma unroll
-                for (int r = 0; r < 3; ++r) {
-                    asm volatile("" : "+v"(wm[r]), "+v"(we[r]));
+                for (int r = 0; r < 5; ++r)
+                    if (SOLO || (r >= 1 && r <= 3)) asm volatile("" : "+v"(wm[r]), "+v"(we[r]));
+#pragma unroll
+                for (int r = 0; r < 3; ++r)
                     asm volatile("" : "+v"(pr[r][0]), "+v"(pr[r][1]), "+v"(pr[r][2]));
+                // centres in columns x - 2 .. x + 2 of rows y - 2 .. y + 2: bit
+                // 5r + c of win25 is column x - 2 + c of row y - 2 + r (0 outside
+                // the grid; the word beside x's nearer word edge holds every such
+                // column off word w)
+#pragma unroll
+                for (int r = 0; r < 5 && SOLO; ++r) {
+                    const int yy = y - 2 + r;
+                    unsigned long long lo, hi;
+                    int at;
+                    if (b < 32) {
+                        lo = w > 0 ? we[r] : 0ull;
+                        hi = wm[r];
+                        at = 62 + b;
+                    } else {
+                        lo = wm[r];
+                        hi = w + 1 < wpr ? we[r] : 0ull;
+                        at = b - 2;
+                    }
+                    const unsigned long long bits =
+                        at >= 64 ? hi >> (at - 64) : (lo >> at) | (hi << (64 - at));
+                    if (yy >= 0 && yy < H) win25 |= ((unsigned int)bits & 31u) << (5 * r);
                 }
+                solo_ok = SOLO;
 #pragma unroll
                 for (int r = 0; r < 3; ++r) {
                     const int yy = y - 1 + r;
                     row[r] = yy;
                     const bool row_in = yy >= 0 && yy < H;
-                    const unsigned long long mid = row_in ? wm[r] : 0ull;
-                    const unsigned long long lft = row_in && b == 0 && w > 0 ? we[r] : 0ull;
-                    const unsigned long long rgt = row_in && b == 63 && w + 1 < wpr ? we[r] : 0ull;
+                    const unsigned long long mid = row_in ? wm[r + 1] : 0ull;
+                    const unsigned long long lft =
+                        row_in && b == 0 && w > 0 ? we[r + 1] : 0ull;
+                    const unsigned long long rgt =
+                        row_in && b == 63 && w + 1 < wpr ? we[r + 1] : 0ull;
                     const unsigned int cl = b > 0 ? (unsigned int)(mid >> (b - 1)) & 1u
                                                   : (unsigned int)(lft >> 63);
                     const unsigned int cc = (unsigned int)(mid >> b) & 1u;
@@ -1764,24 +1811,37 @@ __global__ __launch_bounds__(kDecideThreads) void k_decide_claim(
             const float scale = fmaxf(fmaxf(fabsf(lo), fabsf(lo2)), 1.0f);
             const bool tied = lo2 < INFINITY && (lo2 - lo) <= 1e-5f * scale;
             int tgt = p;
-            bool mover = false;
+            bool mover = false, solo = false;
             if (best != 0) {
                 tgt = row[1 + kDirY[best]] * W + col[1 + kDirX[best]];
                 const uint32_t r = philox_w0(eid, (uint32_t)t, (uint32_t)(t >> 32), 0u,
                                              (uint32_t)seed, (uint32_t)(seed >> 32));
                 const unsigned long long kk = ((unsigned long long)r << 32) | eid;
-                __hip_atomic_fetch_min(&claims[tgt].word, kk, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-                // one more registration at the target (s-2: at most 8 under
-                // v_max = 1); the count is read by the election's winner in
-                // commit, so this atomic returns nothing and nothing waits
-                __hip_atomic_fetch_add(&claims[tgt].regs, 1u, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
+                // Only a pedestrian on one of the 8 su around the target can
+                // register there (moves reach the 8 neighbours).  With none
+                // but this one, it is the election's only registrant and wins
+                // (the smallest key of one): no claim is needed.
+                if (solo_ok) {
+                    const int dx = kDirX[best], dy = kDirY[best];
+                    const unsigned int m = 7u << (dx + 1);
+                    const unsigned int around = (m | (m << 5) | (m << 10)) << (5 * (dy + 1));
+                    solo = (win25 & around & ~(1u << 12)) == 0u;  // bit 12: this pedestrian
+                }
+                if (!solo) {
+                    __hip_atomic_fetch_min(&claims[tgt].word, kk, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                    // one more registration at the target (s-2: at most 8 under
+                    // v_max = 1); the count is read by the election's winner in
+                    // commit, so this atomic returns nothing and nothing waits
+                    __hip_atomic_fetch_add(&claims[tgt].regs, 1u, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                }
                 key[i] = kk;
                 mover = true;
             }
             target[i] = tgt;
-            flags[i] = (uint8_t)((mover ? kFlagMover : 0u) | (tied ? kFlagTied : 0u));
+            flags[i] = (uint8_t)((mover ? kFlagMover : 0u) | (tied ? kFlagTied : 0u) |
+                                 (solo ? kFlagSolo : 0u));
             movers += mover;
             ties += tied;
         }
@@ -1821,24 +1881,38 @@ __global__ __launch_bounds__(commit_threads<MULTI>()) void k_commit(SceneView on
         } else {
             was_live = true;
             if (f & kFlagMover) {
-                // the winner is the only registrant that finds its own key; it
-                // also resets the word, which losers then read as "not mine"
-                // the claim record in one 16-byte load: word, registrations
-                typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-                const u32x4 rec =
-                    *reinterpret_cast<const __attribute__((address_space(1))) u32x4 *>(&claims[tgt]);
-                const unsigned long long cw = ((unsigned long long)rec[1] << 32) | rec[0];
-                const bool to_exit = exitm[tgt] != 0;
-                const unsigned int nreg = rec[2];
-                const unsigned long long kk = key[i];
-                if (cw == kk) {
-                    // every registration of this tick is counted by now (decide
-                    // has finished); each claimed su has one winner, which reads
-                    // the count before it clears it
+                bool win;
+                bool to_exit;
+                if (f & kFlagSolo) {
+                    // the target's only possible registrant (decide saw no
+                    // other pedestrian around it) wins without a claim
+                    win = true;
+                    regs_seen = 1u;
+                    to_exit = exitm[tgt] != 0;
+                } else {
+                    // the winner is the only registrant that finds its own key;
+                    // it also resets the word, which losers then read as "not
+                    // mine"; the claim record in one 16-byte load: word,
+                    // registrations
+                    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+                    const u32x4 rec = *reinterpret_cast<const __attribute__((address_space(1)))
+                                                            u32x4 *>(&claims[tgt]);
+                    const unsigned long long cw = ((unsigned long long)rec[1] << 32) | rec[0];
+                    to_exit = exitm[tgt] != 0;
+                    const unsigned int nreg = rec[2];
+                    const unsigned long long kk = key[i];
+                    win = cw == kk;
+                    if (win) {
+                        // every registration of this tick is counted by now
+                        // (decide has finished); each claimed su has one
+                        // winner, which reads the count before it clears it
+                        regs_seen = nreg;
+                        claims[tgt].word = ~0ull;
+                        claims[tgt].regs = 0u;
+                    }
+                }
+                if (win) {
                     won = true;
-                    regs_seen = nreg;
-                    claims[tgt].word = ~0ull;
-                    claims[tgt].regs = 0u;
                     const int y = p / W, x = p - y * W;
                     const size_t wp = (size_t)y * wpr + (x >> 6);
                     const unsigned long long bp = 1ull << (x & 63);
@@ -2200,10 +2274,10 @@ __global__ __launch_bounds__(256) void k_commit_body(SceneView v)
 
 template <typename T>
 __global__ void k_scatter(const T *__restrict__ src, const int32_t *__restrict__ ext,
-                          T *__restrict__ dst, int n)
+                          T *__restrict__ dst, int n, T mask)
 {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < (size_t)n) dst[ext[i]] = src[i];
+    if (i < (size_t)n) dst[ext[i]] = src[i] & mask;
 }
 
 // Rows of a pitched field array into dense rows: dst[y * W + x] = src[y * fp + x].
@@ -2822,15 +2896,15 @@ hipError_t launch_scatter_i32(const int32_t *src, const int32_t *ext, int32_t *d
                               hipStream_t st)
 {
     hipLaunchKernelGGL(k_scatter<int32_t>, dim3(blocks_for((size_t)n, 256, kCoverAll)), dim3(256),
-                       0, st, src, ext, dst, n);
+                       0, st, src, ext, dst, n, (int32_t)-1);
     return hipGetLastError();
 }
 
 hipError_t launch_scatter_u8(const uint8_t *src, const int32_t *ext, uint8_t *dst, int n,
-                             hipStream_t st)
+                             uint8_t mask, hipStream_t st)
 {
     hipLaunchKernelGGL(k_scatter<uint8_t>, dim3(blocks_for((size_t)n, 256, kCoverAll)), dim3(256),
-                       0, st, src, ext, dst, n);
+                       0, st, src, ext, dst, n, mask);
     return hipGetLastError();
 }
 
